@@ -1,0 +1,550 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Nothing here compares the oracle with itself: each check is a printed value of
+the paper (tests/golden/, each file citing its passage), a closed form, an
+invariant, brute force on tiny inputs, or an independent library (sympy, Python
+big integers, numpy float64 at sizes where it is exact).
+"""
+import json
+import math
+import os
+from decimal import Decimal, getcontext
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import sympy
+
+import oracle as O
+from paper_2207_04620_amd import inputs as I
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    # N = 16, a few 20/24-bit primes: brute force is cheap here
+    return O.Ctx(4, [24, 20, 20], [24, 24], 1, 12.0, 11)
+
+
+@pytest.fixture(scope="module")
+def small():
+    return O.Ctx.from_params(I.small(log_n=10, n_q=5, alpha=2))
+
+
+# ---------------------------------------------------------------- integers
+def test_mulmod_matches_python_ints():
+    rng = np.random.default_rng(0)
+    for _ in range(2000):
+        q = int(rng.integers(3, 2 ** 62)) | 1
+        a, b = int(rng.integers(0, q)), int(rng.integers(0, q))
+        assert O.mulmod(a, b, q) == a * b % q
+
+
+def test_is_prime_brute_force_and_sympy():
+    small_primes = {n for n in range(2, 20000) if all(n % d for d in range(2, int(n ** 0.5) + 1))}
+    for n in range(20000):
+        assert O.is_prime(n) == (n in small_primes)
+    rng = np.random.default_rng(1)
+    for _ in range(300):
+        n = int(rng.integers(2 ** 40, 2 ** 62)) | 1
+        assert O.is_prime(n) == sympy.isprime(n)
+
+
+@pytest.mark.parametrize("prm", [I.C1, I.C1P, I.C2, I.C3, I.C4], ids=lambda p: p.name)
+def test_prime_chain(prm):
+    """largest unused primes below 2^bits with q = 1 mod 2N, Q list then P list"""
+    c = O.Ctx.from_params(prm, threads=2)
+    m2n = 2 * prm.n
+    used = []
+    for q, bits in zip(c.moduli, prm.q_bits + prm.p_bits):
+        assert sympy.isprime(q) and q % m2n == 1 and q < 2 ** bits and q > 2 ** (bits - 1)
+        # no larger admissible prime of that size was skipped
+        cand = (2 ** bits - 1) // m2n * m2n + 1
+        while cand > q:
+            assert cand in used or not sympy.isprime(cand)
+            cand -= m2n
+        used.append(q)
+    assert len(set(c.moduli)) == len(c.moduli)
+
+
+def test_psi_is_smallest_primitive_root(tiny):
+    for i, q in enumerate(tiny.moduli):
+        psi = tiny.psi(i)
+        n = tiny.n
+        assert pow(psi, n, q) == q - 1
+        roots = [x for x in range(1, q) if pow(x, n, q) == q - 1]
+        assert psi == min(roots)
+
+
+# ---------------------------------------------------------------- NTT
+def naive_negacyclic(a, b, q):
+    n = len(a)
+    out = [0] * n
+    for i in range(n):
+        for j in range(n):
+            k = i + j
+            if k < n:
+                out[k] = (out[k] + a[i] * b[j]) % q
+            else:
+                out[k - n] = (out[k - n] - a[i] * b[j]) % q
+    return out
+
+
+@pytest.mark.parametrize("log_n", [3, 4, 5, 6])
+def test_poly_mul_is_negacyclic_convolution(log_n):
+    c = O.Ctx(log_n, [40, 30], [45], 1, 20.0, 5)
+    rng = np.random.default_rng(log_n)
+    for mi, q in enumerate(c.moduli):
+        a = rng.integers(0, q, size=c.n, dtype=np.uint64)
+        b = rng.integers(0, q, size=c.n, dtype=np.uint64)
+        got = c.poly_mul(mi, a, b)
+        want = naive_negacyclic([int(x) for x in a], [int(x) for x in b], q)
+        assert [int(x) for x in got] == want
+
+
+def test_eval_bitrev_is_evaluation_at_odd_powers(tiny):
+    rng = np.random.default_rng(3)
+    L = tiny.log_n
+    for mi, q in enumerate(tiny.moduli):
+        a = [int(x) for x in rng.integers(0, q, size=tiny.n)]
+        got = tiny.eval_bitrev(mi, np.array(a, np.uint64))
+        psi = tiny.psi(mi)
+        for j in range(tiny.n):
+            br = int(format(j, f"0{L}b")[::-1], 2)
+            x = pow(psi, 2 * br + 1, q)
+            assert int(got[j]) == sum(ai * pow(x, i, q) for i, ai in enumerate(a)) % q
+
+
+# ---------------------------------------------------------------- ChaCha20 and samplers
+def test_chacha20_rfc8439_block():
+    g = gold("chacha20_rfc8439.json")
+    out = O.chacha20_block(g["key_words"], g["counter"], g["nonce_words"])
+    assert [format(x, "08x") for x in out] == g["out_words_hex"]
+
+
+def test_stream_word_layout():
+    # word w of (seed, purpose, index) = words 2(w%8), 2(w%8)+1 of block w/8
+    seed, purpose, index = 0x1234_5678_9ABC_DEF0, 4, (7 << 16) | 3
+    key = [seed & 0xFFFFFFFF, seed >> 32, 0, 0, 0, 0, 0, 0]
+    nonce = [purpose, index & 0xFFFFFFFF, index >> 32]
+    for w in (0, 1, 7, 8, 13, 1000):
+        blk = O.chacha20_block(key, w // 8, nonce)
+        assert O.word(seed, purpose, index, w) == blk[2 * (w % 8)] | (blk[2 * (w % 8) + 1] << 32)
+
+
+def test_gauss_table_matches_decimal():
+    getcontext().prec = 60
+    sigma = Decimal("3.2")
+    rho = [(-(Decimal(x * x)) / (2 * sigma * sigma)).exp() for x in range(20)]
+    tot = rho[0] + 2 * sum(rho[1:])
+    cum = rho[0]
+    want = []
+    for k in range(19):
+        if k:
+            cum += 2 * rho[k]
+        want.append(int((cum / tot * (Decimal(2) ** 63)).to_integral_value(rounding="ROUND_FLOOR")))
+    assert [int(x) for x in O.gauss_table()] == want
+
+
+def test_sampler_distributions():
+    n = 1 << 18
+    t = O.sample_ternary(9, 1, 0, n)
+    assert set(np.unique(t)) <= {-1, 0, 1}
+    frac = [np.mean(t == v) for v in (-1, 0, 1)]
+    assert max(abs(f - 1 / 3) for f in frac) < 0.01
+    e = O.sample_gauss(9, 3, 0, n)
+    assert np.abs(e).max() <= 19
+    assert abs(e.mean()) < 0.03 and abs(e.std() - 3.2) < 0.03
+    # chi-square against the discrete Gaussian on [-19, 19]
+    xs = np.arange(-12, 13)
+    p = np.exp(-(xs ** 2) / (2 * 3.2 ** 2))
+    p /= np.exp(-(np.arange(-19, 20) ** 2) / (2 * 3.2 ** 2)).sum()
+    obs = np.array([(e == x).sum() for x in xs])
+    chi2 = ((obs - n * p) ** 2 / (n * p)).sum()
+    assert chi2 < 60  # 25 bins; the 0.9999 quantile is about 58
+    q = (1 << 45) + 12345
+    u = O.sample_uniform(9, 2, 0, q, n)
+    assert int(u.max()) < q and abs(u.astype(np.float64).mean() / q - 0.5) < 0.005
+
+
+# ---------------------------------------------------------------- base conversion
+def test_base_conversion_is_crt_lift_within_alpha_half(small):
+    rng = np.random.default_rng(5)
+    src = [1, 2]
+    D = small.moduli[1] * small.moduli[2]
+    for dst in (0, 3, len(small.q)):
+        t = small.moduli[dst]
+        x_int = [int(v) for v in rng.integers(0, D, size=small.n, dtype=np.uint64)] if D < 2 ** 63 else \
+            [int.from_bytes(rng.bytes(16), "little") % D for _ in range(small.n)]
+        res = np.array([[v % small.moduli[s] for v in x_int] for s in src], np.uint64)
+        got = small.base_conv(src, dst, res)
+        for v, g in zip(x_int[:512], got[:512]):
+            # the lift is x + u D for an integer |u| <= len(src)/2
+            ok = any((v + u * D - int(g)) % t == 0 for u in range(-1, 2))
+            assert ok
+
+
+def test_base_conversion_exact_for_small_centered_values(small):
+    rng = np.random.default_rng(6)
+    src = [1, 2, 3]
+    D = math.prod(small.moduli[s] for s in src)
+    vals = [int(v) for v in rng.integers(-(2 ** 40), 2 ** 40, size=small.n)]
+    res = np.array([[v % small.moduli[s] for v in vals] for s in src], np.uint64)
+    got = small.base_conv(src, 0, res)
+    q0 = small.moduli[0]
+    # |x| << D / (2 n_src): the centered lift sum y_s D/q_s equals x + u D with u in {-1,0,1};
+    # the oracle's result must be one of these residues.
+    for v, g in zip(vals, got):
+        assert any((v + u * D) % q0 == int(g) for u in (-1, 0, 1))
+
+
+# ---------------------------------------------------------------- encoding
+def test_encode_constant_is_constant_polynomial(small):
+    m, _ = small.encode(np.full(7, 0.25), scale=2.0 ** 30)
+    assert m[0] == 2 ** 28 and not np.any(m[1:])
+
+
+def test_encode_matches_direct_formula_float64(tiny):
+    # N = 16: m_i = (2/N) sum_j z_j cos(pi * (5^j i mod 2N) / N), exact enough in float64
+    rng = np.random.default_rng(8)
+    z = rng.uniform(-1, 1, size=tiny.n // 2)
+    scale = 2.0 ** 20
+    m, tie = tiny.encode(z, scale)
+    N = tiny.n
+    want = []
+    for i in range(N):
+        s = sum(z[j] * math.cos(math.pi * ((pow(5, j, 2 * N) * i) % (2 * N)) / N) for j in range(N // 2))
+        want.append(2.0 / N * s * scale)
+    assert tie > 1e-6
+    assert list(m) == [int(round(w)) for w in want]
+
+
+def test_encode_rotation_is_automorphism(small):
+    """Ecd(R(z, r)) = sigma_{5^r}(Ecd(z)): pins slot j <-> zeta^(5^j) and the left rotation"""
+    rng = np.random.default_rng(9)
+    z = rng.uniform(-1, 1, size=small.n // 2)
+    m, tie = small.encode(z)
+    assert tie > 1e-9
+    N = small.n
+    for r in (1, 3, 17):
+        mr, _ = small.encode(np.roll(z, -r))
+        g = pow(5, r, 2 * N)
+        perm = np.zeros(N, np.int64)
+        for i in range(N):
+            e = i * g % (2 * N)
+            if e < N:
+                perm[e] = m[i]
+            else:
+                perm[e - N] = -m[i]
+        assert np.array_equal(mr, perm)
+
+
+def test_decode_inverts_encode(small):
+    rng = np.random.default_rng(10)
+    z = rng.uniform(-1, 1, size=small.n // 2)
+    m, _ = small.encode(z)
+    back = small.decode(m.astype(np.float64), small.scale)
+    assert np.abs(back - z).max() < 1e-6
+
+
+def test_slotwise_product_of_polynomial_product(small):
+    """the canonical embedding turns negacyclic products into slot products"""
+    rng = np.random.default_rng(11)
+    a, b = rng.uniform(-1, 1, size=small.n // 2), rng.uniform(-1, 1, size=small.n // 2)
+    ma, _ = small.encode(a, 2.0 ** 20)
+    mb, _ = small.encode(b, 2.0 ** 20)
+    prod = naive_negacyclic_int([int(x) for x in ma], [int(x) for x in mb])
+    back = small.decode(np.array(prod, np.float64), 2.0 ** 40)
+    assert np.abs(back - a * b).max() < 1e-4
+
+
+def naive_negacyclic_int(a, b):
+    n = len(a)
+    aa, bb = np.array(a, dtype=object), np.array(b, dtype=object)
+    out = [0] * n
+    for i in range(n):
+        if aa[i] == 0:
+            continue
+        for j in range(n):
+            k = i + j
+            if k < n:
+                out[k] += aa[i] * bb[j]
+            else:
+                out[k - n] -= aa[i] * bb[j]
+    return out
+
+
+# ---------------------------------------------------------------- encryption and Fig. 1 operations
+def test_encrypt_decrypt_roundtrip_noise_bound(small):
+    rng = np.random.default_rng(12)
+    m = rng.integers(-(2 ** 30), 2 ** 30, size=small.n)
+    for level in (small.max_level, 2):
+        ct = small.encrypt_coeffs(m, level, small.scale, nonce=3)
+        got = small.decrypt_coeffs(ct)
+        noise = got - m
+        # |v e_pk + e0 + e1 s| <= 19 (N + 1 + N) for ternary v, s
+        assert np.abs(noise).max() <= 19 * (2 * small.n + 1)
+        assert np.abs(noise).max() > 0
+
+
+def test_rotation_matches_slot_rotation(small):
+    rng = np.random.default_rng(13)
+    z = rng.uniform(-1, 1, size=small.n // 2)
+    ct = small.encrypt(z, nonce=4)
+    for k in (1, 5, -3, 64, small.n // 2 - 1):
+        got = small.decrypt(small.rotate(ct, k))
+        assert np.abs(got - np.roll(z, -k)).max() < 1e-3
+
+
+def test_hoisted_rotation_is_bit_identical(small):
+    rng = np.random.default_rng(14)
+    ct = small.encrypt(rng.uniform(-1, 1, size=64), nonce=5)
+    ks = [1, 2, 7, -8, 40]
+    for k, r in zip(ks, small.rotate_hoisted(ct, ks)):
+        assert np.array_equal(r.export(), small.rotate(ct, k).export())
+
+
+def test_mul_relin_rescale(small):
+    rng = np.random.default_rng(15)
+    a, b = rng.uniform(-1, 1, size=small.n // 2), rng.uniform(-1, 1, size=small.n // 2)
+    ca, cb = small.encrypt(a, nonce=6), small.encrypt(b, nonce=7)
+    t = small.tensor(ca, cb)
+    assert t.degree == 2
+    assert np.abs(small.decrypt(t) - a * b).max() < 1e-3  # degree-2 decryption with s^2
+    r = small.rescale(small.relin(t))
+    assert r.level == ca.level - 1
+    assert abs(r.scale - ca.scale * cb.scale / small.q[ca.level]) < 1e-6 * r.scale
+    assert np.abs(small.decrypt(r) - a * b).max() < 1e-3
+
+
+def test_add_level_min_scale_max(small):
+    z = np.linspace(-1, 1, 32)
+    a = small.encrypt(z, nonce=8)
+    b = small.drop(small.encrypt(z, nonce=9), 2)
+    s = small.add(a, b)
+    assert s.level == 2 and s.scale == max(a.scale, b.scale)
+    assert np.abs(small.decrypt(s, 32) - 2 * z).max() < 1e-3
+
+
+# ---------------------------------------------------------------- Sec. 3: masks and permutations
+def perm_from_rows(rows, vec):
+    return np.array([vec[c] for c in rows])
+
+
+def test_fig2_masks_and_permutations():
+    g = gold("fig2_3x3.json")
+    h = g["h"]
+    for k, v in g["u_mu"].items():
+        assert list(O.mask_slots(0, h, int(k))) == v
+    for k, v in g["u_zeta"].items():
+        assert list(O.mask_slots(1, h, int(k) // h)) == v
+    for k, v in g["v"].items():
+        k = int(k)
+        kind, kk = (2, k) if k > 0 else (3, k + h)
+        assert list(O.mask_slots(kind, h, kk)) == v
+    a = np.arange(9)
+    # Eq. 1: U a = sum_k u_k . R(a, k) with R(m,k)[t] = m[t+k]
+    ua = sum(O.mask_slots(0, h, k) * np.roll(a, -k) for k in range(-h + 1, h))
+    assert list(ua.astype(int)) == g["U_mu_a"] == g["perm_rows"]["U_mu"]
+    zb = sum(O.mask_slots(1, h, k) * np.roll(a, -h * k) for k in range(h))
+    assert list(zb.astype(int)) == g["U_zeta_b"] == g["perm_rows"]["U_zeta"]
+    mu = np.array(g["U_mu_a"])
+    zt = np.array(g["U_zeta_b"])
+    for k in (1, 2):
+        vk = O.mask_slots(2, h, k) * np.roll(mu, -k) + O.mask_slots(3, h, k) * np.roll(mu, -(k - h))
+        assert vk.astype(int).reshape(h, h).tolist() == g[f"phi{k}_mu_A"]
+        assert list(vk.astype(int)) == list(perm_from_rows(g["perm_rows"][f"V{k}"], mu))
+        pk = np.roll(zt, -h * k)
+        assert pk.reshape(h, h).tolist() == g[f"pi{k}_zeta_B"]
+        assert list(pk) == list(perm_from_rows(g["perm_rows"][f"P{k}"], zt))
+
+
+@pytest.mark.parametrize("h", [2, 4, 8, 16])
+def test_eq2_with_oracle_masks(h):
+    """masks reproduce mu, zeta, phi^k, pi^k (Sec. 3.3 definitions) and Eq. 2 gives A B"""
+    rng = np.random.default_rng(h)
+    A, B = rng.uniform(-1, 1, (h, h)), rng.uniform(-1, 1, (h, h))
+    a, b = A.ravel(), B.ravel()
+    mu_def = np.array([[A[i, (i + j) % h] for j in range(h)] for i in range(h)])
+    zeta_def = np.array([[B[(i + j) % h, j] for j in range(h)] for i in range(h)])
+    mu = sum(O.mask_slots(0, h, k) * np.roll(a, -k) for k in range(-h + 1, h))
+    zt = sum(O.mask_slots(1, h, k) * np.roll(b, -h * k) for k in range(h))
+    assert np.array_equal(mu, mu_def.ravel()) and np.array_equal(zt, zeta_def.ravel())
+    total = mu * zt
+    for k in range(1, h):
+        phi = O.mask_slots(2, h, k) * np.roll(mu, -k) + O.mask_slots(3, h, k) * np.roll(mu, -(k - h))
+        pi = np.roll(zt, -h * k)
+        phi_def = np.array([[mu_def[i, (j + k) % h] for j in range(h)] for i in range(h)])
+        pi_def = np.array([[zeta_def[(i + k) % h, j] for j in range(h)] for i in range(h)])
+        assert np.array_equal(phi, phi_def.ravel()) and np.array_equal(pi, pi_def.ravel())
+        total = total + phi * pi
+    assert np.abs(total.reshape(h, h) - A @ B).max() < 1e-12
+    assert np.array_equal(O.mask_slots(2, h, 0), np.ones(h * h))
+
+
+# ---------------------------------------------------------------- Alg. 3 end to end
+def expected_rotations(h):
+    b = 1 << ((int(math.log2(h)) + 1) // 2)
+    giant1 = len([i for i in range(-((h - 1 + b - 1) // b), (h + b - 1) // b) if i != 0])
+    giant2 = len([i for i in range(1, (h + b - 1) // b)])
+    return (b - 1) + giant1 + (b - 1) + giant2 + 3 * (h - 1)
+
+
+def test_rotation_count_h64_vs_table1():
+    g = gold("gd_coefficients.json")
+    h = 64
+    # Table I: 3h + 5 sqrt(h) = 232 rotations; the corrected BSGS index range uses 225
+    assert 3 * h + 5 * int(math.isqrt(h)) == g["rotations_h64"]
+    assert expected_rotations(64) == 225 <= g["rotations_h64"]
+
+
+@pytest.mark.parametrize("h,keys", [(8, 22), (16, 46), (32, 94), (64, 190)])
+def test_distinct_rotation_keys(h, keys):
+    c = O.Ctx(14, [40, 40], [50], 1, 30.0, 1)
+    assert len(c.matmul_rotations(h)) == keys
+
+
+@pytest.mark.parametrize("h", [4, 8, 16])
+def test_matmul_decrypts_to_product_and_counts(small, h):
+    A, B = I.matrix_pair(100 + h, h)
+    ca, cb = small.encrypt(A.ravel(), nonce=20), small.encrypt(B.ravel(), nonce=21)
+    small.reset_counters()
+    cm = small.matmul(ca, cb, h)
+    cnt = small.counters()
+    assert cm.level == ca.level - 3
+    got = small.decrypt(cm, h * h).reshape(h, h)
+    assert np.abs(got - A @ B).max() < 1e-3
+    # replicas in the other slots hold the same product (tiled layout)
+    full = small.decrypt(cm)
+    for r in range(small.n // 2 // (h * h)):
+        assert np.abs(full[r * h * h:(r + 1) * h * h].reshape(h, h) - A @ B).max() < 1e-3
+    assert cnt["rot"] == expected_rotations(h)
+    assert cnt["mul_ct"] == h
+    assert cnt["mul_pt"] == (2 * h - 1) + h + (2 * (h - 1) + 1)
+    assert cnt["keyswitch"] == expected_rotations(h) + h
+    assert cnt["rescale"] == 2 + h + 1  # Step 1-1, Step 1-2, each A^(k), the final sum
+
+
+def test_matmul_c1plus_bound():
+    """the stated accuracy: max abs error <= 1e-3 at scale 2^30 (C1+ ring, h = 8)"""
+    c = O.Ctx.from_params(I.C1P)
+    A, B = I.matrix_pair(1, 8)
+    cm = c.matmul(c.encrypt(A.ravel(), nonce=1), c.encrypt(B.ravel(), nonce=2), 8)
+    assert np.abs(c.decrypt(cm, 64).reshape(8, 8) - A @ B).max() < 1e-3
+
+
+def test_matmul_relin_once(small):
+    h = 8
+    A, B = I.matrix_pair(7, h)
+    ca, cb = small.encrypt(A.ravel(), nonce=30), small.encrypt(B.ravel(), nonce=31)
+    small.reset_counters()
+    once = small.matmul(ca, cb, h, O.RELIN_ONCE)
+    assert small.counters()["keyswitch"] == expected_rotations(h) + 1
+    each = small.matmul(ca, cb, h, O.RELIN_EACH)
+    assert np.abs(small.decrypt(once, 64).reshape(h, h) - A @ B).max() < 1e-3
+    assert not np.array_equal(once.export(), each.export())
+
+
+def test_matmul_rejects_bad_shapes(small):
+    ct = small.encrypt(np.zeros(4), nonce=1)
+    with pytest.raises(ValueError):
+        small.matmul(ct, ct, 6)             # not a power of two
+    with pytest.raises(ValueError):
+        small.matmul(ct, ct, 32)            # h^2 > N/2
+    with pytest.raises(ValueError):
+        small.matmul(small.drop(ct, 2), ct, 4)  # level below depth 3
+
+
+# ---------------------------------------------------------------- Sec. 4: g_d
+def gd_from_definition(d):
+    m = sympy.symbols("m")
+    g = sum(Fraction(math.comb(2 * i, i), 4 ** i) * m * (1 - m ** 2) ** i for i in range(d + 1))
+    return sympy.Poly(sympy.expand(g), m), m
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_gd_printed_coefficients_and_properties(d):
+    g = gold("gd_coefficients.json")["g"][str(d)]
+    poly, m = gd_from_definition(d)
+    coeffs = {int(k): sympy.Rational(v[0], v[1]) for k, v in g.items()}
+    got = {mon[0]: c for mon, c in zip(poly.monoms(), poly.coeffs())}
+    assert got == coeffs
+    # each coefficient is n / 2^(2d-1) with n an integer (Sec. 4.2)
+    assert all((c * 2 ** (2 * d - 1)).q == 1 for c in coeffs.values())
+    expr = poly.as_expr()
+    assert expr.subs(m, 1) == 1 and expr.subs(m, -1) == -1                    # Prop. II
+    assert sympy.expand(expr.subs(m, -m) + expr) == 0                         # Prop. I
+    p_d = sympy.Rational(2 * d + 1, 4 ** d) * math.comb(2 * d, d)             # Lemma 4.1
+    assert coeffs[1] == p_d == sum(sympy.Rational(math.comb(2 * i, i), 4 ** i) for i in range(d + 1))
+    assert sympy.expand(sympy.diff(expr, m) - p_d * (1 - m ** 2) ** d) == 0   # Prop. III
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_lemmas_4_2_4_3(d):
+    poly, m = gd_from_definition(d)
+    f = sympy.lambdify(m, poly.as_expr(), "numpy")
+    p_d = (2 * d + 1) / 4 ** d * math.comb(2 * d, d)
+    x = np.linspace(0, 1, 20001)
+    one_minus = 1 - f(x)
+    assert np.all(one_minus >= -1e-15)
+    assert np.all(one_minus <= (1 - x) ** p_d + 1e-12)
+    assert np.all(one_minus <= 2 ** d * (1 - x) ** (d + 1) + 1e-12)
+
+
+def min_k(d, sigma, delta):
+    poly, m = gd_from_definition(d)
+    f = sympy.lambdify(m, poly.as_expr(), "numpy")
+    x = np.concatenate([np.geomspace(delta, 1, 200001)])
+    for k in range(1, 60):
+        x = f(x)
+        if np.max(1 - x) <= 2.0 ** -sigma:
+            return k
+    return None
+
+
+def test_theorem_3_5_k_table():
+    """the minimal k with g_d^(k) (sigma, delta)-close, against the theorem's leading terms"""
+    k = min_k(4, 20, 2.0 ** -20)
+    p4 = 315 / 128
+    lead = math.log2(2 ** 20) / math.log2(p4) + math.log2(19) / math.log2(5)
+    assert k == 17 and abs(k - lead) < 2
+    assert min_k(3, 8, 2.0 ** -8) == 9
+
+
+def gd_eval(d, x):
+    g = gold("gd_coefficients.json")["g"][str(d)]
+    return sum(v[0] / v[1] * x ** int(p) for p, v in g.items())
+
+
+@pytest.mark.parametrize("d,k", [(1, 1), (2, 1), (3, 1), (1, 2)])
+def test_sign_decrypts_to_composite_polynomial(d, k):
+    c = O.Ctx.from_params(I.small(log_n=10, n_q=8, alpha=2, q_bits=40, log_scale=40.0))
+    X = I.sign_inputs(5, 1, 16)[0].ravel()
+    x = c.encrypt(X, nonce=40)
+    y = c.sign(x, d, k)
+    want = X.copy()
+    for _ in range(k):
+        want = gd_eval(d, want)
+    nb = int(math.floor(math.log2(d))) + 1
+    assert y.level == x.level - k * (nb + 1)
+    assert np.abs(c.decrypt(y, 256) - want).max() < 1e-3
+
+
+def test_relu_decrypts(small):
+    c = O.Ctx.from_params(I.small(log_n=10, n_q=6, alpha=2, q_bits=40, log_scale=40.0))
+    X = I.sign_inputs(6, 1, 16)[0].ravel()
+    y = c.sign(c.encrypt(X, nonce=41), 3, 1, relu=True)
+    g = gd_eval(3, X)
+    assert np.abs(c.decrypt(y, 256) - (X + X * g) / 2).max() < 1e-3
+
+
+def test_sign_rejects_shallow_level(small):
+    x = small.drop(small.encrypt(np.zeros(4), nonce=1), 2)
+    with pytest.raises(ValueError):
+        small.sign(x, 3, 1)
