@@ -1,0 +1,181 @@
+/*
+ * he.h -- C ABI of libhe: packed ciphertext x ciphertext matrix products over
+ * RNS-CKKS on one MI355X (gfx950), after Hercules (arXiv 2207.04620).
+ *
+ * Plain pointers and sizes only.  Every call returns an he_status; out-parameters
+ * are written only on HE_OK.  A context is used by one host thread at a time.
+ * Ciphertexts live in device memory, in the evaluation (NTT) domain, as one block
+ * u64[deg+1][level+1][N]; the caller owns every he_ct* it receives and releases it
+ * with he_ct_free before destroying the context.  Work is issued on the context's
+ * HIP stream and is asynchronous unless a call says it synchronizes.
+ *
+ * Conventions fixed where the paper is silent (readings):
+ *  - ring Z_Q[X]/(X^N + 1), Q = q_0 ... q_L (Sec. 2.2), special modulus P for
+ *    hybrid key switching with digits of 'alpha' Q-limbs;
+ *  - primes: for each requested bit size, Q list then P list, the largest unused
+ *    prime below 2^bits that is 1 mod 2N;
+ *  - slot j of a plaintext is its value at zeta^(5^j), zeta = exp(i pi / N);
+ *    a vector shorter than N/2 slots is replicated to fill them (the packed
+ *    product treats rotation as cyclic modulo h^2, Sec. 3.2 and 3.4);
+ *  - Rot(c, k) is the left rotation R(m, k)[t] = m[t + k] of Sec. 3.2;
+ *  - randomness: ChaCha20 (RFC 8439) keyed by the 64-bit seed; stream purposes
+ *    1 secret, 2 public-key a, 3 public-key e, 4 switching-key a, 5 switching-key e,
+ *    6/7/8 encryption v/e0/e1; ternary secret, Gaussian sigma 3.2 on [-19, 19].
+ */
+#ifndef HE_H
+#define HE_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct he_ctx he_ctx;
+typedef struct he_ct he_ct;
+
+typedef enum {
+    HE_OK = 0,
+    HE_EINVAL = 1,      /* bad argument (null pointer, size mismatch, bad parameter set) */
+    HE_ENOMEM = 2,      /* device or host allocation failed, or admission budget exceeded */
+    HE_ELEVEL = 3,      /* ciphertext level below the depth of the operation */
+    HE_ESCALE = 4,      /* scale out of range */
+    HE_EKEY = 5,        /* rotation key not generated */
+    HE_ESHAPE = 6,      /* h not a power of two, or h^2 > N/2 */
+    HE_EMISMATCH = 7,   /* handles from different contexts, or degrees that do not fit */
+    HE_EDEVICE = 8,     /* HIP runtime error */
+    HE_EUNSUPPORTED = 9
+} he_status;
+
+/* Device hooks.  stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream),
+ * or NULL for a stream the context creates.  alloc/free: optional device allocator
+ * (NULL: hipMalloc/hipFree behind a size-bucketed cache owned by the context). */
+typedef struct {
+    void *stream;
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+} he_device;
+
+#define HE_SCHED_RELIN_EACH 0u /* relinearise every Step-3 product (Mul_ct of Fig. 1) */
+#define HE_SCHED_RELIN_ONCE 1u /* accumulate degree-2 products, relinearise once */
+
+typedef struct {
+    uint32_t log_n;          /* ring degree N = 2^log_n, 8 <= log_n <= 17 */
+    uint32_t n_q;            /* Q limbs (top level L = n_q - 1) */
+    const uint32_t *q_bits;  /* bit size of each Q prime, q_0 first (<= 60) */
+    uint32_t n_p;            /* special primes K */
+    const uint32_t *p_bits;  /* bit size of each special prime (<= 60) */
+    uint32_t alpha;          /* Q limbs per key-switching digit; dnum = ceil(n_q/alpha) */
+    double log_scale;        /* scale Delta = 2^log_scale of fresh ciphertexts and masks */
+    uint64_t seed;           /* ChaCha20 key */
+    uint32_t n_h;            /* matrix sides whose rotation keys and masks are made at creation */
+    const uint32_t *h_list;
+    uint32_t schedule;       /* HE_SCHED_RELIN_EACH or HE_SCHED_RELIN_ONCE */
+} he_params;
+
+/* Context: primes, twiddles, secret/public/relinearisation keys, rotation keys and
+ * diagonal masks for every h in h_list (Sec. 3.5-3.6 and App. B).  Synchronizes. */
+he_status he_ctx_create(const he_params *params, const he_device *dev, he_ctx **out);
+void he_ctx_destroy(he_ctx *ctx);
+/* primes (Q then P) into out[0 .. n_q+n_p) */
+he_status he_ctx_moduli(const he_ctx *ctx, uint64_t *out, size_t n);
+/* blocks the host until all queued work on the context stream is done */
+he_status he_sync(he_ctx *ctx);
+/* op counters: rotations, key switches, Mul_pt, Mul_ct, Add, RS */
+he_status he_counters(const he_ctx *ctx, int64_t out[6], int reset);
+/* device bytes held by keys + masks, and by the allocation cache */
+he_status he_memory(const he_ctx *ctx, uint64_t *keys_bytes, uint64_t *pool_bytes);
+
+/* Ecd + Enc (Fig. 1 items 3 and 5): n_vals values (n_vals divides N/2) replicated to
+ * N/2 slots, encoded at Delta (exact rounding, computed in 113-bit floating point),
+ * encrypted with the public key at 'level' (<= L) using stream index 'nonce'. */
+he_status he_encrypt(he_ctx *ctx, const double *vals, size_t n_vals, uint32_t level, uint64_t nonce,
+                     he_ct **out);
+/* Enc of an already-encoded plaintext: N signed integer coefficients at 'scale' */
+he_status he_encrypt_coeffs(he_ctx *ctx, const int64_t *coeffs, uint32_t level, double scale, uint64_t nonce,
+                            he_ct **out);
+/* single-key Dec + Dcd (Fig. 1 items 4 and 6): first n_out slot values (real parts).
+ * The plaintext must be below q_0 q_1 / 2 in magnitude.  Synchronizes. */
+he_status he_decrypt(he_ctx *ctx, const he_ct *ct, double *out, size_t n_out);
+/* Dec only: the N centered plaintext coefficients (unscaled).  Synchronizes. */
+he_status he_decrypt_coeffs(he_ctx *ctx, const he_ct *ct, double *out, size_t n);
+/* Ecd only: N integer coefficients of the encoding at 'scale' */
+he_status he_encode(he_ctx *ctx, const double *vals, size_t n_vals, double scale, int64_t *out);
+
+void he_ct_free(he_ct *ct);
+he_status he_ct_info(const he_ct *ct, uint32_t *level, uint32_t *degree, double *scale);
+/* coefficient-domain residues, u64[deg+1][level+1][N] with values in [0, q_i). Synchronizes. */
+he_status he_ct_export(he_ctx *ctx, const he_ct *ct, uint64_t *buf, size_t n);
+he_status he_ct_import(he_ctx *ctx, const uint64_t *buf, size_t n, uint32_t level, uint32_t degree, double scale,
+                       he_ct **out);
+
+/* Fig. 1 operations.  Add/Sub: level min, scale max.  Mul_pt: coeffs are an encoded
+ * plaintext at pt_scale.  Mul: tensor + relinearisation.  RS: divide by the last prime.
+ * Rot: left rotation by k (Sec. 3.2), needs the key for 5^k mod 2N (HE_EKEY). */
+he_status he_add(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out);
+he_status he_sub(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out);
+he_status he_drop(he_ctx *ctx, const he_ct *a, uint32_t level, he_ct **out);
+he_status he_mul_plain(he_ctx *ctx, const he_ct *a, const int64_t *coeffs, double pt_scale, he_ct **out);
+he_status he_mul_int(he_ctx *ctx, const he_ct *a, int64_t k, he_ct **out);
+he_status he_tensor(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out);
+he_status he_relin(he_ctx *ctx, const he_ct *a, he_ct **out);
+he_status he_mul(he_ctx *ctx, const he_ct *a, const he_ct *b, he_ct **out);
+he_status he_rescale(he_ctx *ctx, const he_ct *a, he_ct **out);
+he_status he_rotate(he_ctx *ctx, const he_ct *a, int64_t k, he_ct **out);
+/* rotation key for amount k (made on demand; no-op when it exists) */
+he_status he_gen_rotation_key(he_ctx *ctx, int64_t k);
+
+/* HE-MatMult (Alg. 3 with the baby-step/giant-step Steps 1-1/1-2 of App. B): A and B
+ * encrypt row-major h x h matrices (Sec. 3.4) replicated over the slots; the result
+ * encrypts A B three levels below min(level A, level B).  HE_ESHAPE if h is not a
+ * power of two or h^2 > N/2; HE_ELEVEL if the level is below 3. */
+he_status he_matmul(he_ctx *ctx, const he_ct *a, const he_ct *b, uint32_t h, he_ct **out);
+/* n independent products C[i] = A[i] B[i] of sides h[i] (mixed h and levels allowed),
+ * scheduled together so that each switching key is streamed once per rotation round
+ * for all members.  Results are bit-identical to he_matmul on each pair. */
+he_status he_matmul_batch(he_ctx *ctx, size_t n, const he_ct *const *a, const he_ct *const *b,
+                          const uint32_t *h, he_ct **out);
+
+/* Composite sign approximation g_d^(k) (Sec. 4.2; Alg. 5 for ReLU):
+ * mode 0: g_d applied k times; mode 1: ReLU(x) = (x + x g_d^(k)(x)) / 2.
+ * Depth per composition 1 + floor(log2 d) + 1; HE_ELEVEL if the level is too low. */
+he_status he_sign_approx(he_ctx *ctx, const he_ct *x, uint32_t d, uint32_t k, uint32_t mode, he_ct **out);
+
+/* Limb-batched negacyclic NTT on device memory: n_limbs limbs of N u64 each at
+ * 'dev_ptr' (device pointer), limb i reduced modulo prime index mod_idx[i] (host array).
+ * Forward output order: position j holds a(psi^(2 bitrev(j) + 1)), psi the smallest
+ * primitive 2N-th root of unity mod q.  inverse = 1 undoes it. */
+he_status he_ntt(he_ctx *ctx, uint64_t *dev_ptr, uint32_t n_limbs, const uint32_t *mod_idx, int inverse);
+
+/* Serving: a host thread admits requests by device-memory footprint and runs them
+ * with continuous batching; each request's result is the same as running it alone. */
+typedef struct he_server he_server;
+typedef struct {
+    uint64_t mem_budget_bytes; /* admission budget for in-flight requests (0: no limit) */
+    uint32_t max_batch;        /* requests merged into one round (0: 32) */
+} he_serve_config;
+#define HE_REQ_MATMUL 0u
+#define HE_REQ_SIGN 1u
+typedef struct {
+    uint32_t op;      /* HE_REQ_MATMUL or HE_REQ_SIGN */
+    uint32_t h;       /* matmul side */
+    uint32_t d, k;    /* sign degree parameter and compositions */
+    uint32_t mode;    /* sign mode */
+    const he_ct *a;   /* inputs (borrowed until the request completes) */
+    const he_ct *b;
+} he_request;
+he_status he_serve_start(he_ctx *ctx, const he_serve_config *cfg, he_server **out);
+/* HE_ENOMEM when the request alone exceeds the budget */
+he_status he_serve_submit(he_server *s, const he_request *req, uint64_t *ticket);
+/* done = 1 and *result set when finished (caller owns it); status of the request in *req_status */
+he_status he_serve_poll(he_server *s, uint64_t ticket, int *done, he_ct **result, he_status *req_status,
+                        double *latency_s);
+he_status he_serve_stop(he_server *s);
+
+const char *he_status_string(he_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

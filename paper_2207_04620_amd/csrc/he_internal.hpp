@@ -1,0 +1,154 @@
+// Internal types of the libhe runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <set>
+#include <memory>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/he.h"
+#include "host_math.hpp"
+#include "kernels.hpp"
+
+struct HeError {
+    he_status s;
+    explicit HeError(he_status v) : s(v) {}
+};
+void hip_check(hipError_t e, const char* what);
+
+// ChaCha20 stream purposes
+enum { P_SK = 1, P_PK_A = 2, P_PK_E = 3, P_SWK_A = 4, P_SWK_E = 5, P_ENC_V = 6, P_ENC_E0 = 7, P_ENC_E1 = 8 };
+// op counters
+enum { C_ROT = 0, C_KS = 1, C_MULPT = 2, C_MULCT = 3, C_ADD = 4, C_RS = 5 };
+
+// Size-bucketed cache over hipMalloc; all work is ordered on one stream, so a block
+// released here may be handed out again at once.
+struct Pool {
+    std::unordered_map<size_t, std::vector<void*>> free_;
+    size_t held = 0, cached = 0;
+    void* (*dev_alloc)(size_t, void*) = nullptr;
+    void (*dev_free)(void*, void*) = nullptr;
+    void* user = nullptr;
+    void* alloc(size_t bytes);
+    void release(void* p, size_t bytes);
+    void trim();
+};
+
+struct Ctx;
+struct DBuf {
+    Ctx* ctx;
+    u64* p = nullptr;
+    size_t n;
+    DBuf(Ctx* c, size_t n_u64);
+    ~DBuf();
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+};
+
+struct CtData {
+    int level = 0, deg = 1;
+    double scale = 1.0;
+    std::unique_ptr<DBuf> buf;  // u64[deg+1][level+1][N], evaluation form
+};
+typedef std::shared_ptr<CtData> CtPtr;
+
+struct ModUpInfo {
+    int lo = 0, hi = 0;
+    size_t off = 0;  // into the ModUp table
+    u64 hinv[HE_MAXSRC] = {0}, hinv_sh[HE_MAXSRC] = {0};
+};
+
+struct MaskKey {
+    int kind, h, k;
+    int64_t rot;
+    bool operator<(const MaskKey& o) const {
+        if (kind != o.kind) return kind < o.kind;
+        if (h != o.h) return h < o.h;
+        if (k != o.k) return k < o.k;
+        return rot < o.rot;
+    }
+    bool operator==(const MaskKey& o) const { return kind == o.kind && h == o.h && k == o.k && rot == o.rot; }
+};
+
+struct Ctx {
+    int log_n = 0;
+    int64_t N = 0;
+    int n_q = 0, n_p = 0, alpha = 1;
+    double scale = 1.0;
+    u64 seed = 0;
+    uint32_t schedule = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    Pool pool;
+    hm::Encoder enc;
+    std::vector<u64> mods, roots, pmod;
+    std::vector<ModP> host_mods;
+    DevTables T{};
+    u64 cdt[19];
+    // device tables
+    std::unique_ptr<DBuf> d_mods, d_psi, d_psi_sh, d_ipsi, d_ipsi_sh, d_rs, d_md_tab, d_pinv, d_mu_tab;
+    std::vector<u64> md_hinv, md_hinv_sh;
+    std::vector<std::vector<ModUpInfo>> mu;  // [level][digit]
+    // keys
+    std::unique_ptr<DBuf> s_eval, s2_eval, pk, rlk;
+    std::map<u64, std::unique_ptr<DBuf>> rot_keys;
+    std::map<MaskKey, std::unique_ptr<DBuf>> masks;
+    size_t keys_bytes = 0;
+    std::set<int> prepared_h;
+    int64_t cnt[6] = {0, 0, 0, 0, 0, 0};
+
+    int ext_mod(int level, int i) const;
+    void build_tables();
+    void ntt(u64* base, int npoly, int64_t pstride_limbs, int nl, bool inverse, int level_for_ext);
+    void sample_into(u64* dst, int count, const int* modidx, int kind, uint32_t purpose, u64 index, const u64* uidx);
+    void keygen_base();
+    std::unique_ptr<DBuf> make_swk(u64 key_id, const u64* sp);
+    const u64* relin_key();
+    u64 galois(int64_t k) const;
+    const u64* rot_key(u64 g, bool create);
+
+    CtPtr new_ct(int level, int deg, double scale);
+    CtPtr encrypt_coeffs(const int64_t* m, int level, double scale, u64 nonce);
+    void decrypt_coeffs(const CtData& c, double* out);
+    CtPtr drop(const CtData& a, int level);
+    CtPtr add_sub(const CtData& a, const CtData& b, bool sub);
+    CtPtr tensor(const CtData& a, const CtData& b);
+    std::unique_ptr<DBuf> ks_lift(const u64* d, int level);
+    void ks_apply(const u64* lift, int level, const u64* key, u64 g, const u64* add0, const u64* add1, u64* out0,
+                  u64* out1);
+    CtPtr relin(const CtData& a);
+    CtPtr rescale(const CtData& a);
+    CtPtr rotate_from_lift(const CtData& a, const u64* lift, int64_t k);
+    CtPtr rotate(const CtData& a, int64_t k);
+    CtPtr mul_int(const CtData& a, int64_t k);
+    std::unique_ptr<DBuf> plaintext_mont(const int64_t* coeffs);
+    CtPtr mask_sum(const std::vector<std::pair<const CtData*, const u64*>>& terms, double mask_scale);
+
+    const u64* mask(int kind, int h, int k, int64_t rot);
+    void prepare_masks(const std::vector<MaskKey>& keys);
+    int bsgs(int h) const;
+    std::vector<MaskKey> matmul_masks(int h) const;
+    std::vector<int64_t> matmul_rotations(int h) const;
+    void prepare_h(int h);
+    CtPtr matmul(const CtData& A, const CtData& B, int h);
+    std::vector<CtPtr> matmul_batch(const std::vector<const CtData*>& A, const std::vector<const CtData*>& B,
+                                    const std::vector<int>& h);
+
+    CtPtr mul_rs(const CtData& x, const CtData& y);
+    CtPtr eval_gd(const CtData& x, int d);
+    CtPtr sign(const CtData& x, int d, int k, int mode);
+
+    void release_all() {
+        masks.clear();
+        rot_keys.clear();
+        rlk.reset();
+        pk.reset();
+        s2_eval.reset();
+        s_eval.reset();
+        d_mods.reset(); d_psi.reset(); d_psi_sh.reset(); d_ipsi.reset(); d_ipsi_sh.reset();
+        d_rs.reset(); d_md_tab.reset(); d_pinv.reset(); d_mu_tab.reset();
+        pool.trim();
+    }
+};

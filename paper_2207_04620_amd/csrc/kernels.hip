@@ -1,0 +1,582 @@
+// HIP kernels for gfx950: limb-batched negacyclic NTT staged in LDS, centered fast
+// base conversion, key-switch inner product with fused automorphism, rescale,
+// tensor product, mask multiply-accumulate and the ChaCha20 samplers.
+//
+// The ring is Z_q[X]/(X^N+1) (Sec. 2.2 of the paper); the transforms and the
+// RNS-CKKS internals are not described by the paper and follow the published
+// constructions named at each kernel.
+#include "kernels.hpp"
+
+#define TPB 256
+#define NTT_E 2048  // elements held in LDS by one NTT block (16 KiB)
+
+static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------------ NTT
+// Forward transform: Cooley-Tukey with the psi twist merged into the twiddles
+// (Longa-Naehrig 2016), bit-reversed output: stage m (1..N/2), butterfly group i
+// uses psi^(bitrev(m+i)).  N = N1 * N2: the first log N1 stages pair elements a
+// multiple of N2 apart (column pass), the last log N2 stages stay inside contiguous
+// rows of N2 elements (row pass).  Each block stages NTT_E elements in LDS.
+__global__ __launch_bounds__(TPB) void k_ntt_fwd_cols(DevTables T, Jobs J) {
+    __shared__ u64 s[NTT_E];
+    const int N = 1 << T.log_n, L1 = T.n1_log, N2 = N >> L1;
+    const int logC = 11 - L1, C = 1 << logC;
+    const int job = blockIdx.y, c = job / J.n, k = job % J.n;
+    u64* a = J.base + c * J.cstride + (int64_t)J.off[k] * N;
+    const int mi = J.mod[k];
+    const u64 q = T.mods[mi].q;
+    const u64* W = T.psi + (int64_t)mi * N;
+    const u64* Ws = T.psi_sh + (int64_t)mi * N;
+    const int c0 = blockIdx.x * C;
+    for (int e = threadIdx.x; e < NTT_E; e += TPB) s[e] = a[(int64_t)(e >> logC) * N2 + c0 + (e & (C - 1))];
+    __syncthreads();
+    for (int st = 0; st < L1; st++) {
+        const int m = 1 << st, ltk = L1 - st - 1, tk = 1 << ltk;
+        for (int b = threadIdx.x; b < NTT_E / 2; b += TPB) {
+            const int cc = b & (C - 1), bb = b >> logC;
+            const int i = bb >> ltk, j = bb & (tk - 1);
+            const int k1 = (i << (ltk + 1)) + j, k2 = k1 + tk;
+            const u64 U = s[(k1 << logC) + cc];
+            const u64 V = mul_shoup(s[(k2 << logC) + cc], W[m + i], Ws[m + i], q);
+            s[(k1 << logC) + cc] = add_mod(U, V, q);
+            s[(k2 << logC) + cc] = sub_mod(U, V, q);
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < NTT_E; e += TPB) a[(int64_t)(e >> logC) * N2 + c0 + (e & (C - 1))] = s[e];
+}
+
+__global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J) {
+    __shared__ u64 s[NTT_E];
+    const int N = 1 << T.log_n, L1 = T.n1_log, L2 = T.n2_log, N1 = 1 << L1, N2 = 1 << L2;
+    const int job = blockIdx.y, c = job / J.n, k = job % J.n;
+    const int r = blockIdx.x;
+    u64* a = J.base + c * J.cstride + (int64_t)J.off[k] * N + (int64_t)r * N2;
+    const int mi = J.mod[k];
+    const u64 q = T.mods[mi].q;
+    const u64* W = T.psi + (int64_t)mi * N;
+    const u64* Ws = T.psi_sh + (int64_t)mi * N;
+    for (int e = threadIdx.x; e < N2; e += TPB) s[e] = a[e];
+    __syncthreads();
+    for (int st = 0; st < L2; st++) {
+        const int mp = 1 << st, lt = L2 - st - 1, t = 1 << lt;
+        for (int b = threadIdx.x; b < N2 / 2; b += TPB) {
+            const int i = b >> lt, j = b & (t - 1);
+            const int j1 = (i << (lt + 1)) + j;
+            const int idx = mp * (N1 + r) + i;
+            const u64 U = s[j1];
+            const u64 V = mul_shoup(s[j1 + t], W[idx], Ws[idx], q);
+            s[j1] = add_mod(U, V, q);
+            s[j1 + t] = sub_mod(U, V, q);
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < N2; e += TPB) a[e] = s[e];
+}
+
+// Inverse transform: Gentleman-Sande, bit-reversed input, natural output, then N^-1.
+__global__ __launch_bounds__(TPB) void k_ntt_inv_rows(DevTables T, Jobs J) {
+    __shared__ u64 s[NTT_E];
+    const int N = 1 << T.log_n, L1 = T.n1_log, L2 = T.n2_log, N1 = 1 << L1, N2 = 1 << L2;
+    const int job = blockIdx.y, c = job / J.n, k = job % J.n;
+    const int r = blockIdx.x;
+    u64* a = J.base + c * J.cstride + (int64_t)J.off[k] * N + (int64_t)r * N2;
+    const int mi = J.mod[k];
+    const ModP mp_ = T.mods[mi];
+    const u64 q = mp_.q;
+    const u64* W = T.ipsi + (int64_t)mi * N;
+    const u64* Ws = T.ipsi_sh + (int64_t)mi * N;
+    for (int e = threadIdx.x; e < N2; e += TPB) s[e] = a[e];
+    __syncthreads();
+    for (int st = L2 - 1; st >= 0; st--) {
+        const int mp = 1 << st, lt = L2 - st - 1, t = 1 << lt;
+        for (int b = threadIdx.x; b < N2 / 2; b += TPB) {
+            const int i = b >> lt, j = b & (t - 1);
+            const int j1 = (i << (lt + 1)) + j;
+            const int idx = mp * (N1 + r) + i;
+            const u64 U = s[j1], V = s[j1 + t];
+            s[j1] = add_mod(U, V, q);
+            s[j1 + t] = mul_shoup(sub_mod(U, V, q), W[idx], Ws[idx], q);
+        }
+        __syncthreads();
+    }
+    if (L1 == 0) {
+        for (int e = threadIdx.x; e < N2; e += TPB) a[e] = mul_shoup(s[e], mp_.ninv, mp_.ninv_sh, q);
+    } else {
+        for (int e = threadIdx.x; e < N2; e += TPB) a[e] = s[e];
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_ntt_inv_cols(DevTables T, Jobs J) {
+    __shared__ u64 s[NTT_E];
+    const int N = 1 << T.log_n, L1 = T.n1_log, N2 = N >> L1;
+    const int logC = 11 - L1, C = 1 << logC;
+    const int job = blockIdx.y, c = job / J.n, k = job % J.n;
+    u64* a = J.base + c * J.cstride + (int64_t)J.off[k] * N;
+    const int mi = J.mod[k];
+    const ModP mp_ = T.mods[mi];
+    const u64 q = mp_.q;
+    const u64* W = T.ipsi + (int64_t)mi * N;
+    const u64* Ws = T.ipsi_sh + (int64_t)mi * N;
+    const int c0 = blockIdx.x * C;
+    for (int e = threadIdx.x; e < NTT_E; e += TPB) s[e] = a[(int64_t)(e >> logC) * N2 + c0 + (e & (C - 1))];
+    __syncthreads();
+    for (int st = L1 - 1; st >= 0; st--) {
+        const int m = 1 << st, ltk = L1 - st - 1, tk = 1 << ltk;
+        for (int b = threadIdx.x; b < NTT_E / 2; b += TPB) {
+            const int cc = b & (C - 1), bb = b >> logC;
+            const int i = bb >> ltk, j = bb & (tk - 1);
+            const int k1 = (i << (ltk + 1)) + j, k2 = k1 + tk;
+            const u64 U = s[(k1 << logC) + cc], V = s[(k2 << logC) + cc];
+            s[(k1 << logC) + cc] = add_mod(U, V, q);
+            s[(k2 << logC) + cc] = mul_shoup(sub_mod(U, V, q), W[m + i], Ws[m + i], q);
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < NTT_E; e += TPB)
+        a[(int64_t)(e >> logC) * N2 + c0 + (e & (C - 1))] = mul_shoup(s[e], mp_.ninv, mp_.ninv_sh, q);
+}
+
+void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st) {
+    if (J.n == 0 || J.nct == 0) return;
+    const int N = 1 << T.log_n, N1 = 1 << T.n1_log;
+    dim3 grid_rows(N1, J.n * J.nct), grid_cols(N / NTT_E, J.n * J.nct);
+    if (!inverse) {
+        if (T.n1_log > 0) hipLaunchKernelGGL(k_ntt_fwd_cols, grid_cols, dim3(TPB), 0, st, T, J);
+        hipLaunchKernelGGL(k_ntt_fwd_rows, grid_rows, dim3(TPB), 0, st, T, J);
+    } else {
+        hipLaunchKernelGGL(k_ntt_inv_rows, grid_rows, dim3(TPB), 0, st, T, J);
+        if (T.n1_log > 0) hipLaunchKernelGGL(k_ntt_inv_cols, grid_cols, dim3(TPB), 0, st, T, J);
+    }
+}
+
+// ------------------------------------------------------------------ base conversion
+// Centered fast base conversion (Bajard et al. 2016 / Halevi-Polyakov-Shoup 2019 in
+// its centered form): y_s = centered([x_s (D/q_s)^-1]_{q_s}),
+// out_t = sum_s y_s (D/q_s) mod q_t, accumulated in 128 bits and reduced once (REDC).
+__global__ __launch_bounds__(TPB) void k_baseconv(DevTables T, ConvDesc D) {
+    const int N = 1 << T.log_n;
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int p = blockIdx.z;
+    const int t0 = blockIdx.y * 8, t1 = min(D.nt, t0 + 8);
+    if (i >= N) return;
+    u64 y[HE_MAXSRC];
+    bool neg[HE_MAXSRC];
+    const u64* src = D.src + p * D.src_pstride;
+    for (int s = 0; s < D.ns; s++) {
+        const ModP m = T.mods[D.smod[s]];
+        const u64 v = mul_shoup(src[(int64_t)s * N + i], D.hinv[s], D.hinv_sh[s], m.q);
+        y[s] = v;
+        neg[s] = v > m.half;
+    }
+    u64* dst = D.dst + p * D.dst_pstride;
+    for (int t = t0; t < t1; t++) {
+        const ModP m = T.mods[D.dmod[t]];
+        Acc128 acc = {0, 0};
+        for (int s = 0; s < D.ns; s++) {
+            const u64* e = D.tab + ((int64_t)s * D.tab_ld + D.tcol[t]) * 2;
+            mac128(acc, y[s], e[0]);
+            if (neg[s]) add128(acc, e[1]);
+        }
+        dst[(int64_t)D.doff[t] * N + i] = redc(acc.lo, acc.hi, m.q, m.qninv);
+    }
+}
+
+void launch_baseconv(const DevTables& T, const ConvDesc& D, hipStream_t st) {
+    const int N = 1 << T.log_n;
+    dim3 grid(ceil_div(N, TPB), ceil_div(D.nt, 8), D.npoly);
+    hipLaunchKernelGGL(k_baseconv, grid, dim3(TPB), 0, st, T, D);
+}
+
+// ------------------------------------------------------------------ ChaCha20 samplers
+__device__ __forceinline__ u32 rotl(u32 v, int c) { return (v << c) | (v >> (32 - c)); }
+#define CQR(a, b, c, d)                    \
+    a += b; d ^= a; d = rotl(d, 16);       \
+    c += d; b ^= c; b = rotl(b, 12);       \
+    a += b; d ^= a; d = rotl(d, 8);        \
+    c += d; b ^= c; b = rotl(b, 7);
+
+// RFC 8439 section 2.3 block function; key = seed (little-endian) zero-extended,
+// nonce = (purpose, index lo, index hi).
+__device__ void chacha_block(u64 seed, u32 purpose, u64 index, u32 counter, u32 out[16]) {
+    const u32 st[16] = {0x61707865u, 0x3320646eu, 0x79622d32u, 0x6b206574u, (u32)seed, (u32)(seed >> 32), 0, 0,
+                        0, 0, 0, 0, counter, purpose, (u32)index, (u32)(index >> 32)};
+    u32 x[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) x[i] = st[i];
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        CQR(x[0], x[4], x[8], x[12]);
+        CQR(x[1], x[5], x[9], x[13]);
+        CQR(x[2], x[6], x[10], x[14]);
+        CQR(x[3], x[7], x[11], x[15]);
+        CQR(x[0], x[5], x[10], x[15]);
+        CQR(x[1], x[6], x[11], x[12]);
+        CQR(x[2], x[7], x[8], x[13]);
+        CQR(x[3], x[4], x[9], x[14]);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; i++) out[i] = x[i] + st[i];
+}
+
+__device__ __forceinline__ u64 signed_to_res(int64_t v, u64 q) { return v >= 0 ? (u64)v : q - (u64)(-v); }
+
+// ternary / Gaussian: one 64-bit word per coefficient, word w = block w/8, words 2(w%8)+{0,1}
+__global__ __launch_bounds__(TPB) void k_sample_small(DevTables T, Jobs J, SampleArgs A) {
+    const int N = 1 << T.log_n;
+    const int blk = blockIdx.x * TPB + threadIdx.x;
+    if (blk * 8 >= N) return;
+    u32 o[16];
+    chacha_block(A.seed, A.purpose, A.index, (u32)blk, o);
+    for (int w = 0; w < 8; w++) {
+        const u64 word = (u64)o[2 * w] | ((u64)o[2 * w + 1] << 32);
+        int64_t v;
+        if (A.kind == 0) {
+            v = (int64_t)(word % 3) - 1;
+        } else {
+            const u64 u = word >> 1;
+            int mag = 0;
+            for (int k = 0; k < 19; k++) mag += (u >= A.cdt[k]) ? 1 : 0;
+            v = (word & 1) ? -mag : mag;
+        }
+        const int x = blk * 8 + w;
+        for (int k = 0; k < J.n; k++) {
+            const u64 q = T.mods[J.mod[k]].q;
+            J.base[(int64_t)J.off[k] * N + x] = signed_to_res(v, q);
+        }
+    }
+}
+
+// uniform mod q: two words per coefficient, value = (w[2x+1] 2^64 + w[2x]) mod q
+__global__ __launch_bounds__(TPB) void k_sample_uniform(DevTables T, Jobs J, SampleArgs A) {
+    const int N = 1 << T.log_n;
+    const int blk = blockIdx.x * TPB + threadIdx.x;
+    const int k = blockIdx.y;
+    if (blk * 4 >= N) return;
+    u32 o[16];
+    chacha_block(A.seed, A.purpose, A.uidx[k], (u32)blk, o);
+    const ModP m = T.mods[J.mod[k]];
+    for (int w = 0; w < 4; w++) {
+        const u64 lo = (u64)o[4 * w] | ((u64)o[4 * w + 1] << 32);
+        const u64 hi = (u64)o[4 * w + 2] | ((u64)o[4 * w + 3] << 32);
+        // (hi 2^64 + lo) mod q = REDC(hi' 2^64 + lo) * R mod q with hi' = hi mod q
+        const u64 t = redc(lo, reduce64(hi, m), m.q, m.qninv);
+        J.base[(int64_t)J.off[k] * N + blk * 4 + w] = redc(t * m.r2, __umul64hi(t, m.r2), m.q, m.qninv);
+    }
+}
+
+void launch_sample(const DevTables& T, const Jobs& J, const SampleArgs& A, hipStream_t st) {
+    const int N = 1 << T.log_n;
+    if (A.kind == 2) {
+        dim3 grid(ceil_div(N / 4, TPB), J.n);
+        hipLaunchKernelGGL(k_sample_uniform, grid, dim3(TPB), 0, st, T, J, A);
+    } else {
+        dim3 grid(ceil_div(N / 8, TPB));
+        hipLaunchKernelGGL(k_sample_small, grid, dim3(TPB), 0, st, T, J, A);
+    }
+}
+
+// ------------------------------------------------------------------ element-wise
+__global__ __launch_bounds__(TPB) void k_ew(DevTables T, ModMap mm, int nl, u64* out, int64_t out_ps,
+                                            const u64* a, int64_t a_ps, const u64* b, int64_t b_ps, int op) {
+    const int N = 1 << T.log_n;
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int l = blockIdx.y, p = blockIdx.z;
+    const ModP m = T.mods[mm(l)];
+    const int64_t o = (int64_t)l * N + i;
+    const u64 x = a[p * a_ps + o], y = b[p * b_ps + o];
+    u64 r;
+    switch (op) {
+        case EW_ADD: r = add_mod(x, y, m.q); break;
+        case EW_SUB: r = sub_mod(x, y, m.q); break;
+        case EW_MUL_MONT: r = mul_mont(x, y, m.q, m.qninv); break;
+        default: r = mul_plain(x, y, m); break;
+    }
+    out[p * out_ps + o] = r;
+}
+
+void launch_ew(const DevTables& T, ModMap mm, int nl, int npoly, u64* out, int64_t out_ps, const u64* a,
+               int64_t a_ps, const u64* b, int64_t b_ps, int op, hipStream_t st) {
+    const int N = 1 << T.log_n;
+    dim3 grid(ceil_div(N, TPB), nl, npoly);
+    hipLaunchKernelGGL(k_ew, grid, dim3(TPB), 0, st, T, mm, nl, out, out_ps, a, a_ps, b, b_ps, op);
+}
+
+__global__ __launch_bounds__(TPB) void k_mul_const(DevTables T, ModMap mm, u64* out, int64_t out_ps,
+                                                   const u64* a, int64_t a_ps, const u64* c, const u64* c_sh) {
+    const int N = 1 << T.log_n;
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int l = blockIdx.y, p = blockIdx.z;
+    const u64 q = T.mods[mm(l)].q;
+    const int64_t o = (int64_t)l * N + i;
+    out[p * out_ps + o] = mul_shoup(a[p * a_ps + o], c[l], c_sh[l], q);
+}
+
+void launch_mul_const(const DevTables& T, ModMap mm, int nl, int npoly, u64* out, int64_t out_ps, const u64* a,
+                      int64_t a_ps, const u64* c, const u64* c_sh, hipStream_t st) {
+    const int N = 1 << T.log_n;
+    dim3 grid(ceil_div(N, TPB), nl, npoly);
+    hipLaunchKernelGGL(k_mul_const, grid, dim3(TPB), 0, st, T, mm, out, out_ps, a, a_ps, c, c_sh);
+}
+
+// position j of the bit-reversed evaluation layout holds a(psi^(2 brev(j) + 1)); sigma_g
+// evaluates there as a(psi^(g (2 brev(j) + 1)))
+__device__ __forceinline__ int perm_g(int j, u64 g, int log_n) {
+    const u32 two_n_mask = (2u << log_n) - 1;
+    const u32 e = 2 * brev_bits((u32)j, log_n) + 1;
+    const u32 e2 = (u32)(((u64)e * g) & two_n_mask);
+    return (int)brev_bits((e2 - 1) >> 1, log_n);
+}
+
+__global__ __launch_bounds__(TPB) void k_automorph(DevTables T, u64* out, int64_t out_ps, const u64* in,
+                                                   int64_t in_ps, u64 g) {
+    const int N = 1 << T.log_n;
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int l = blockIdx.y, p = blockIdx.z;
+    out[p * out_ps + (int64_t)l * N + i] = in[p * in_ps + (int64_t)l * N + perm_g(i, g, T.log_n)];
+}
+
+void launch_automorph(const DevTables& T, int nl, int npoly, u64* out, int64_t out_ps, const u64* in,
+                      int64_t in_ps, u64 g, hipStream_t st) {
+    const int N = 1 << T.log_n;
+    dim3 grid(ceil_div(N, TPB), nl, npoly);
+    hipLaunchKernelGGL(k_automorph, grid, dim3(TPB), 0, st, T, out, out_ps, in, in_ps, g);
+}
+
+__global__ __launch_bounds__(TPB) void k_to_mont(DevTables T, ModMap mm, u64* x, int64_t ps) {
+    const int N = 1 << T.log_n;
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int l = blockIdx.y, p = blockIdx.z;
+    const ModP m = T.mods[mm(l)];
+    u64* v = x + p * ps + (int64_t)l * N + i;
+    *v = to_mont(*v, m);
+}
+
+void launch_to_mont(const DevTables& T, ModMap mm, int nl, int npoly, u64* x, int64_t ps, hipStream_t st) {
+    const int N = 1 << T.log_n;
+    dim3 grid(ceil_div(N, TPB), nl, npoly);
+    hipLaunchKernelGGL(k_to_mont, grid, dim3(TPB), 0, st, T, mm, x, ps);
+}
+
+__global__ __launch_bounds__(TPB) void k_swk_finish(DevTables T, u64* b, const u64* a, const u64* e,
+                                                    const u64* s, const u64* sp, const u64* pmod,
+                                                    const uint8_t* in_digit) {
+    const int N = 1 << T.log_n;
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int l = blockIdx.y;
+    const ModP m = T.mods[l];
+    const int64_t o = (int64_t)l * N + i;
+    u64 v = sub_mod(e[o], mul_plain(a[o], s[o], m), m.q);
+    if (in_digit[l]) v = add_mod(v, mul_plain(pmod[l], sp[o], m), m.q);
+    b[o] = v;
+}
+
+void launch_swk_finish(const DevTables& T, int M, u64* b, const u64* a, const u64* e, const u64* s, const u64* sp,
+                       const u64* pmod, const uint8_t* in_digit, hipStream_t st) {
+    const int N = 1 << T.log_n;
+    dim3 grid(ceil_div(N, TPB), M);
+    hipLaunchKernelGGL(k_swk_finish, grid, dim3(TPB), 0, st, T, b, a, e, s, sp, pmod, in_digit);
+}
+
+// ------------------------------------------------------------------ key switching
+// Hybrid key switching (Han-Ki 2020): inner product of the lifted digits with the
+// switching key over Q_l and P.  The automorphism of a rotation is fused as a
+// gather: the digits of sigma_g(c1) are the permuted digits of c1 (hoisting).
+__global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
+    const int N = 1 << T.log_n;
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int t = blockIdx.y;
+    const int mi = D.mod[t];
+    const ModP m = T.mods[mi];
+    const int src = D.g == 1 ? i : perm_g(i, D.g, T.log_n);
+    Acc128 a0 = {0, 0}, a1 = {0, 0};
+    for (int j = 0; j < D.beta; j++) {
+        const u64 x = D.lift[((int64_t)j * D.ne + t) * N + src];
+        const u64* kb = D.key + (((int64_t)j * 2 + 0) * D.M + mi) * N;
+        const u64* ka = D.key + (((int64_t)j * 2 + 1) * D.M + mi) * N;
+        mac128(a0, x, kb[i]);
+        mac128(a1, x, ka[i]);
+    }
+    D.u[(int64_t)t * N + i] = redc(a0.lo, a0.hi, m.q, m.qninv);
+    D.u[((int64_t)D.ne + t) * N + i] = redc(a1.lo, a1.hi, m.q, m.qninv);
+}
+
+void launch_inner_product(const DevTables& T, const IpDesc& D, hipStream_t st) {
+    const int N = 1 << T.log_n;
+    dim3 grid(ceil_div(N, TPB), D.ne);
+    hipLaunchKernelGGL(k_inner_product, grid, dim3(TPB), 0, st, T, D);
+}
+
+__global__ __launch_bounds__(TPB) void k_moddown_combine(DevTables T, const u64* u, int64_t u_ps, const u64* conv,
+                                                         int64_t conv_ps, const u64* pinv, const u64* pinv_sh,
+                                                         const u64* add, int64_t add_ps, u64* out,
+                                                         int64_t out_ps) {
+    const int N = 1 << T.log_n;
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int l = blockIdx.y, p = blockIdx.z;
+    const u64 q = T.mods[l].q;
+    const int64_t o = (int64_t)l * N + i;
+    u64 v = mul_shoup(sub_mod(u[p * u_ps + o], conv[p * conv_ps + o], q), pinv[l], pinv_sh[l], q);
+    if (add) v = add_mod(v, add[p * add_ps + o], q);
+    out[p * out_ps + o] = v;
+}
+
+void launch_moddown_combine(const DevTables& T, int nl, int npoly, const u64* u, int64_t u_ps, const u64* conv,
+                            int64_t conv_ps, const u64* pinv, const u64* pinv_sh, const u64* add, int64_t add_ps,
+                            u64* out, int64_t out_ps, hipStream_t st) {
+    const int N = 1 << T.log_n;
+    dim3 grid(ceil_div(N, TPB), nl, npoly);
+    hipLaunchKernelGGL(k_moddown_combine, grid, dim3(TPB), 0, st, T, u, u_ps, conv, conv_ps, pinv, pinv_sh, add,
+                       add_ps, out, out_ps);
+}
+
+// ------------------------------------------------------------------ rescale
+__global__ __launch_bounds__(TPB) void k_rescale_spread(DevTables T, const u64* last, int64_t last_ps, int last_mod,
+                                                        u64* tmp, int64_t tmp_ps) {
+    const int N = 1 << T.log_n;
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int l = blockIdx.y, p = blockIdx.z;
+    const ModP ml = T.mods[last_mod], m = T.mods[l];
+    const u64 r = last[p * last_ps + i];
+    u64 v = reduce64(r, m);
+    if (r > ml.half) v = sub_mod(v, reduce64(ml.q, m), m.q);
+    tmp[p * tmp_ps + (int64_t)l * N + i] = v;
+}
+
+void launch_rescale_spread(const DevTables& T, int nl_out, int npoly, const u64* last, int64_t last_ps,
+                           int last_mod, u64* tmp, int64_t tmp_ps, hipStream_t st) {
+    const int N = 1 << T.log_n;
+    dim3 grid(ceil_div(N, TPB), nl_out, npoly);
+    hipLaunchKernelGGL(k_rescale_spread, grid, dim3(TPB), 0, st, T, last, last_ps, last_mod, tmp, tmp_ps);
+}
+
+__global__ __launch_bounds__(TPB) void k_rescale_combine(DevTables T, const u64* c, int64_t c_ps, const u64* tmp,
+                                                         int64_t tmp_ps, const u64* qinv, const u64* qinv_sh,
+                                                         u64* out, int64_t out_ps) {
+    const int N = 1 << T.log_n;
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int l = blockIdx.y, p = blockIdx.z;
+    const u64 q = T.mods[l].q;
+    const int64_t o = (int64_t)l * N + i;
+    out[p * out_ps + o] = mul_shoup(sub_mod(c[p * c_ps + o], tmp[p * tmp_ps + o], q), qinv[l], qinv_sh[l], q);
+}
+
+void launch_rescale_combine(const DevTables& T, int nl_out, int npoly, const u64* c, int64_t c_ps, const u64* tmp,
+                            int64_t tmp_ps, const u64* qinv, const u64* qinv_sh, u64* out, int64_t out_ps,
+                            hipStream_t st) {
+    const int N = 1 << T.log_n;
+    dim3 grid(ceil_div(N, TPB), nl_out, npoly);
+    hipLaunchKernelGGL(k_rescale_combine, grid, dim3(TPB), 0, st, T, c, c_ps, tmp, tmp_ps, qinv, qinv_sh, out,
+                       out_ps);
+}
+
+// ------------------------------------------------------------------ products
+__global__ __launch_bounds__(TPB) void k_tensor(DevTables T, const u64* a, int64_t a_ps, const u64* b,
+                                                int64_t b_ps, u64* d, int64_t d_ps, int acc) {
+    const int N = 1 << T.log_n;
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int l = blockIdx.y;
+    const ModP m = T.mods[l];
+    const int64_t o = (int64_t)l * N + i;
+    const u64 a0 = a[o], a1 = a[a_ps + o];
+    const u64 b0 = to_mont(b[o], m), b1 = to_mont(b[b_ps + o], m);
+    const u64 d0 = mul_mont(a0, b0, m.q, m.qninv);
+    Acc128 t = {0, 0};
+    mac128(t, a0, b1);
+    mac128(t, a1, b0);
+    const u64 d1 = redc(t.lo, t.hi, m.q, m.qninv);
+    const u64 d2 = mul_mont(a1, b1, m.q, m.qninv);
+    if (acc) {
+        d[o] = add_mod(d[o], d0, m.q);
+        d[d_ps + o] = add_mod(d[d_ps + o], d1, m.q);
+        d[2 * d_ps + o] = add_mod(d[2 * d_ps + o], d2, m.q);
+    } else {
+        d[o] = d0;
+        d[d_ps + o] = d1;
+        d[2 * d_ps + o] = d2;
+    }
+}
+
+void launch_tensor(const DevTables& T, int nl, const u64* a, int64_t a_ps, const u64* b, int64_t b_ps, u64* d,
+                   int64_t d_ps, int acc, hipStream_t st) {
+    const int N = 1 << T.log_n;
+    dim3 grid(ceil_div(N, TPB), nl);
+    hipLaunchKernelGGL(k_tensor, grid, dim3(TPB), 0, st, T, a, a_ps, b, b_ps, d, d_ps, acc);
+}
+
+// sum of up to 16 (ciphertext limb x mask) products, one REDC per output
+__global__ __launch_bounds__(TPB) void k_mask_mac(DevTables T, MacDesc D, u64* out, int64_t out_ps, int acc) {
+    const int N = 1 << T.log_n;
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int l = blockIdx.y, p = blockIdx.z;
+    const ModP m = T.mods[l];
+    const int64_t o = (int64_t)l * N + i;
+    Acc128 s = {0, 0};
+    for (int r = 0; r < D.nterm; r++) mac128(s, D.in[r][p * D.in_ps[r] + o], D.mask[r][o]);
+    // D.nterm * q^2 < q 2^64 for nterm <= 16 and q < 2^60
+    u64 v = redc(s.lo, s.hi, m.q, m.qninv);
+    if (acc) v = add_mod(v, out[p * out_ps + o], m.q);
+    out[p * out_ps + o] = v;
+}
+
+void launch_mask_mac(const DevTables& T, int nl, int npoly, const MacDesc& D, u64* out, int64_t out_ps, int acc,
+                     hipStream_t st) {
+    const int N = 1 << T.log_n;
+    dim3 grid(ceil_div(N, TPB), nl, npoly);
+    hipLaunchKernelGGL(k_mask_mac, grid, dim3(TPB), 0, st, T, D, out, out_ps, acc);
+}
+
+// ------------------------------------------------------------------ encrypt / decrypt
+__global__ __launch_bounds__(TPB) void k_dec_dot(DevTables T, int deg, const u64* c, int64_t c_ps, const u64* s,
+                                                 const u64* s2, u64* mo) {
+    const int N = 1 << T.log_n;
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int l = blockIdx.y;
+    const ModP m = T.mods[l];
+    const int64_t o = (int64_t)l * N + i;
+    u64 v = add_mod(c[o], mul_plain(c[c_ps + o], s[o], m), m.q);
+    if (deg == 2) v = add_mod(v, mul_plain(c[2 * c_ps + o], s2[o], m), m.q);
+    mo[o] = v;
+}
+
+void launch_dec_dot(const DevTables& T, int nl, int deg, const u64* c, int64_t c_ps, const u64* s, const u64* s2,
+                    u64* m, hipStream_t st) {
+    const int N = 1 << T.log_n;
+    dim3 grid(ceil_div(N, TPB), nl);
+    hipLaunchKernelGGL(k_dec_dot, grid, dim3(TPB), 0, st, T, deg, c, c_ps, s, s2, m);
+}
+
+__global__ __launch_bounds__(TPB) void k_enc_combine(DevTables T, const u64* v, const u64* pk0, const u64* pk1,
+                                                     const u64* x0, const u64* x1, u64* c0, u64* c1) {
+    const int N = 1 << T.log_n;
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int l = blockIdx.y;
+    const ModP m = T.mods[l];
+    const int64_t o = (int64_t)l * N + i;
+    c0[o] = add_mod(mul_mont(v[o], pk0[o], m.q, m.qninv), x0[o], m.q);
+    c1[o] = add_mod(mul_mont(v[o], pk1[o], m.q, m.qninv), x1[o], m.q);
+}
+
+void launch_enc_combine(const DevTables& T, int nl, const u64* v, const u64* pk0, const u64* pk1, const u64* x0,
+                        const u64* x1, u64* c0, u64* c1, hipStream_t st) {
+    const int N = 1 << T.log_n;
+    dim3 grid(ceil_div(N, TPB), nl);
+    hipLaunchKernelGGL(k_enc_combine, grid, dim3(TPB), 0, st, T, v, pk0, pk1, x0, x1, c0, c1);
+}
+
+__global__ __launch_bounds__(TPB) void k_add_signed(DevTables T, u64* x, const int64_t* msg) {
+    const int N = 1 << T.log_n;
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int l = blockIdx.y;
+    const ModP m = T.mods[l];
+    const int64_t v = msg[i];
+    const u64 r = v >= 0 ? reduce64((u64)v, m) : neg_mod(reduce64((u64)(-v), m), m.q);
+    x[(int64_t)l * N + i] = add_mod(x[(int64_t)l * N + i], r, m.q);
+}
+
+void launch_add_signed(const DevTables& T, int nl, u64* x, const int64_t* m, hipStream_t st) {
+    const int N = 1 << T.log_n;
+    dim3 grid(ceil_div(N, TPB), nl);
+    hipLaunchKernelGGL(k_add_signed, grid, dim3(TPB), 0, st, T, x, m);
+}

@@ -1,0 +1,140 @@
+// Kernel descriptors and launchers shared by the host runtime (he_host.hip)
+// and the kernels (kernels.hip).
+//
+// Memory layout: a ciphertext of degree d at level l is one compact device block
+// u64[d+1][l+1][N]; every limb is in the evaluation (NTT, bit-reversed) domain.
+// An "extended" polynomial over Q_l and P has l+1+K limbs: Q limbs 0..l (prime
+// index = limb index) followed by the K special primes (prime index n_q + k).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "modarith.hpp"
+
+#define HE_MAXJ 192   // limbs in one job list
+#define HE_MAXSRC 8   // source limbs of one base conversion (digit width / K)
+#define HE_MAXT 64    // target limbs of one base conversion / ext limbs
+
+// A list of limbs: limb k of copy c lives at base + c * cstride + off[k] * N and is
+// reduced modulo the prime with index mod[k].
+struct Jobs {
+    u64* base;
+    int64_t cstride;
+    int n;
+    int nct;
+    uint16_t off[HE_MAXJ];
+    uint8_t mod[HE_MAXJ];
+};
+
+// limb i of an (extended) polynomial -> prime index
+struct ModMap {
+    int nq_l;  // limbs below this are Q limbs with prime index i
+    int n_q;   // limbs at or above nq_l map to n_q + (i - nq_l)
+    __device__ __forceinline__ int operator()(int i) const { return i < nq_l ? i : n_q + (i - nq_l); }
+};
+
+// Device-resident tables of one context.
+struct DevTables {
+    const ModP* mods;    // [M]
+    const u64* psi;      // [M][N]  psi^(bitrev k)
+    const u64* psi_sh;   // [M][N]
+    const u64* ipsi;     // [M][N]  psi^-(bitrev k)
+    const u64* ipsi_sh;  // [M][N]
+    int log_n;
+    int n1_log;  // column-pass stages
+    int n2_log;  // row-pass stages
+};
+
+// Centered fast base conversion from ns source limbs to nt target limbs, for npoly
+// polynomials.  Source limb s of poly p at src + p * src_pstride + s * N (coefficient
+// form, prime smod[s]); target t of poly p at dst + p * dst_pstride + doff[t] * N.
+// tab[(s * tab_ld + tcol[t]) * 2 + 0] = (D/q_s mod q_t) R mod q_t,
+// tab[(s * tab_ld + tcol[t]) * 2 + 1] = (-q_s (D/q_s) mod q_t) R mod q_t.
+struct ConvDesc {
+    const u64* src;
+    int64_t src_pstride;
+    u64* dst;
+    int64_t dst_pstride;
+    const u64* tab;
+    int tab_ld;  // table row length: entry (s, col) at tab[(s * tab_ld + col) * 2]
+    int ns, nt, npoly;
+    int smod[HE_MAXSRC];
+    u64 hinv[HE_MAXSRC], hinv_sh[HE_MAXSRC];
+    uint16_t doff[HE_MAXT];
+    uint16_t tcol[HE_MAXT];  // table column of target t
+    uint8_t dmod[HE_MAXT];
+};
+
+struct SampleArgs {
+    u64 seed;
+    uint32_t purpose;
+    u64 index;
+    int kind;          // 0 ternary, 1 Gaussian, 2 uniform mod the limb's prime
+    u64 uidx[HE_MAXJ]; // uniform: stream index of limb k
+    u64 cdt[19];
+};
+
+// Key switch inner product: for ext limb t (prime mod[t]) and coefficient i,
+//  u0[t][i] = sum_j lift[j][t][perm_g(i)] kb[j][mod[t]][i], u1 likewise with ka.
+struct IpDesc {
+    const u64* lift;  // [beta][ne][N]
+    const u64* key;   // [beta_top][2][M][N] Montgomery form
+    u64* u;           // [2][ne][N]
+    int ne, beta, M;
+    u64 g;            // Galois element (1 = identity)
+    uint8_t mod[HE_MAXT];
+};
+
+struct MacDesc {
+    const u64* in[16];
+    const u64* mask[16];
+    int64_t in_ps[16];
+    int nterm;
+};
+
+enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_MUL_MONT = 2, EW_MUL_PLAIN = 3 };
+
+// ------------------------------------------------------------------ launchers
+void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st);
+void launch_baseconv(const DevTables& T, const ConvDesc& D, hipStream_t st);
+void launch_sample(const DevTables& T, const Jobs& J, const SampleArgs& A, hipStream_t st);
+// out[p][i] = a[p][i] (op) b[p][i] over nl limbs (prime map mm) and npoly polys;
+// b_ps = 0 broadcasts one b polynomial to every poly
+void launch_ew(const DevTables& T, ModMap mm, int nl, int npoly, u64* out, int64_t out_ps, const u64* a,
+               int64_t a_ps, const u64* b, int64_t b_ps, int op, hipStream_t st);
+// out[p][i] = a[p][i] * c_i (Shoup constants in device arrays c, c_sh indexed by limb)
+void launch_mul_const(const DevTables& T, ModMap mm, int nl, int npoly, u64* out, int64_t out_ps, const u64* a,
+                      int64_t a_ps, const u64* c, const u64* c_sh, hipStream_t st);
+// evaluation-domain automorphism: out[p][i][j] = in[p][i][perm_g(j)]
+void launch_automorph(const DevTables& T, int nl, int npoly, u64* out, int64_t out_ps, const u64* in,
+                      int64_t in_ps, u64 g, hipStream_t st);
+void launch_to_mont(const DevTables& T, ModMap mm, int nl, int npoly, u64* x, int64_t ps, hipStream_t st);
+// b = e - a s (+ pmod_i s' on flagged limbs), all limbs of the full chain [M][N]
+void launch_swk_finish(const DevTables& T, int M, u64* b, const u64* a, const u64* e, const u64* s,
+                       const u64* sp, const u64* pmod, const uint8_t* in_digit, hipStream_t st);
+void launch_inner_product(const DevTables& T, const IpDesc& D, hipStream_t st);
+// out[p][t] = (u[p][t] - conv[p][t]) * Pinv_t (+ add[p][t])
+void launch_moddown_combine(const DevTables& T, int nl, int npoly, const u64* u, int64_t u_ps, const u64* conv,
+                            int64_t conv_ps, const u64* pinv, const u64* pinv_sh, const u64* add, int64_t add_ps,
+                            u64* out, int64_t out_ps, hipStream_t st);
+// tmp[p][i] = centered(last[p]) mod q_i (coefficient form)
+void launch_rescale_spread(const DevTables& T, int nl_out, int npoly, const u64* last, int64_t last_ps,
+                           int last_mod, u64* tmp, int64_t tmp_ps, hipStream_t st);
+// out[p][i] = (c[p][i] - tmp[p][i]) * qinv_i
+void launch_rescale_combine(const DevTables& T, int nl_out, int npoly, const u64* c, int64_t c_ps, const u64* tmp,
+                            int64_t tmp_ps, const u64* qinv, const u64* qinv_sh, u64* out, int64_t out_ps,
+                            hipStream_t st);
+// d0 (+)= a0 b0, d1 (+)= a0 b1 + a1 b0, d2 (+)= a1 b1
+void launch_tensor(const DevTables& T, int nl, const u64* a, int64_t a_ps, const u64* b, int64_t b_ps, u64* d,
+                   int64_t d_ps, int acc, hipStream_t st);
+// out[p][i] (+)= sum_r in_r[p][i] mask_r[i]  (masks in Montgomery form, compact [nl_top][N])
+void launch_mask_mac(const DevTables& T, int nl, int npoly, const MacDesc& D, u64* out, int64_t out_ps, int acc,
+                     hipStream_t st);
+// m = c0 + c1 s (+ c2 s^2); s, s2 plain evaluation form [M][N]
+void launch_dec_dot(const DevTables& T, int nl, int deg, const u64* c, int64_t c_ps, const u64* s, const u64* s2,
+                    u64* m, hipStream_t st);
+// c0 = v pk0 + x0, c1 = v pk1 + x1 (pk in Montgomery form)
+void launch_enc_combine(const DevTables& T, int nl, const u64* v, const u64* pk0, const u64* pk1, const u64* x0,
+                        const u64* x1, u64* c0, u64* c1, hipStream_t st);
+// x[i][j] += m[j] mod q_i (signed 64-bit message)
+void launch_add_signed(const DevTables& T, int nl, u64* x, const int64_t* m, hipStream_t st);

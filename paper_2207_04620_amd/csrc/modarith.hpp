@@ -1,0 +1,86 @@
+// Device modular arithmetic over word-size primes q < 2^61 (gfx950, 64-wide waves).
+//
+// Two reductions are used, both exact:
+//  - Shoup/Harvey products a*w mod q with a precomputed companion
+//    w' = floor(w 2^64 / q) for fixed operands (twiddles, per-limb constants);
+//  - Montgomery REDC with R = 2^64 for products with keys and masks stored as
+//    x R mod q, and for 128-bit multiply-accumulate chains (sum < q 2^64).
+// gfx950 has no 64-bit multiplier: the compiler lowers the 64x64 products to
+// v_mad_u64_u32 / v_mul_hi_u32 chains.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+
+struct ModP {
+    u64 q;      // the prime
+    u64 qninv;  // -q^-1 mod 2^64
+    u64 r2;     // 2^128 mod q  (to enter Montgomery form)
+    u64 bar;    // floor((2^64 - 1) / q)
+    u64 ninv;   // N^-1 mod q
+    u64 ninv_sh;
+    u64 half;   // (q - 1) / 2
+    u64 pad;
+};
+
+__device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) {
+    u64 s = a + b;
+    return s >= q ? s - q : s;
+}
+__device__ __forceinline__ u64 sub_mod(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
+__device__ __forceinline__ u64 neg_mod(u64 a, u64 q) { return a ? q - a : 0; }
+
+// a * w mod q, w < q, w_sh = floor(w 2^64 / q); any a < 2^64
+__device__ __forceinline__ u64 mul_shoup(u64 a, u64 w, u64 w_sh, u64 q) {
+    u64 qh = __umul64hi(a, w_sh);
+    u64 r = a * w - qh * q;
+    return r >= q ? r - q : r;
+}
+// lazy form: result in [0, 2q)
+__device__ __forceinline__ u64 mul_shoup_lazy(u64 a, u64 w, u64 w_sh, u64 q) {
+    u64 qh = __umul64hi(a, w_sh);
+    return a * w - qh * q;
+}
+
+// (hi 2^64 + lo) R^-1 mod q for hi 2^64 + lo < q 2^64
+__device__ __forceinline__ u64 redc(u64 lo, u64 hi, u64 q, u64 qninv) {
+    u64 m = lo * qninv;
+    u64 mh = __umul64hi(m, q);
+    u64 r = hi + mh + (lo != 0 ? 1 : 0);
+    return r >= q ? r - q : r;
+}
+// a * (b R) R^-1 = a b mod q
+__device__ __forceinline__ u64 mul_mont(u64 a, u64 bR, u64 q, u64 qninv) {
+    return redc(a * bR, __umul64hi(a, bR), q, qninv);
+}
+// a b mod q for two plain residues: a b R^-1, then times R^2 R^-1
+__device__ __forceinline__ u64 mul_plain(u64 a, u64 b, const ModP& m) {
+    u64 t = redc(a * b, __umul64hi(a, b), m.q, m.qninv);
+    return redc(t * m.r2, __umul64hi(t, m.r2), m.q, m.qninv);
+}
+// to Montgomery form
+__device__ __forceinline__ u64 to_mont(u64 a, const ModP& m) { return redc(a * m.r2, __umul64hi(a, m.r2), m.q, m.qninv); }
+
+struct Acc128 {
+    u64 lo, hi;
+};
+__device__ __forceinline__ void mac128(Acc128& acc, u64 a, u64 b) {
+    u64 lo = a * b, hi = __umul64hi(a, b);
+    acc.lo += lo;
+    acc.hi += hi + (acc.lo < lo ? 1 : 0);
+}
+__device__ __forceinline__ void add128(Acc128& acc, u64 a) {
+    acc.lo += a;
+    acc.hi += (acc.lo < a ? 1 : 0);
+}
+
+// x mod q for any 64-bit x
+__device__ __forceinline__ u64 reduce64(u64 x, const ModP& m) {
+    u64 qh = __umul64hi(x, m.bar);
+    u64 r = x - qh * m.q;
+    return r >= m.q ? r - m.q : r;
+}
+
+__device__ __forceinline__ u32 brev_bits(u32 x, int bits) { return __builtin_bitreverse32(x) >> (32 - bits); }

@@ -1,0 +1,277 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integer results (every ciphertext residue, exported in the coefficient domain)
+must be bit-identical; decrypted values must be within the stated bound of the
+FP64 product.  Both sides receive the same seeded inputs from
+paper_2207_04620_amd.inputs and derive everything else from the seed.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2207_04620_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def he():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2207_04620_amd import he as H
+    H.lib()
+    return H
+
+
+class Pair:
+    def __init__(self, H, prm, h_list=None, schedule=0):
+        _log(f"[parity] context {prm.name} N=2^{prm.log_n} h={h_list if h_list is not None else prm.h_list}")
+        self.prm = prm
+        self.g = H.Context(prm, schedule=schedule, h_list=h_list)
+        self.o = O.Ctx.from_params(prm)
+
+    def same(self, gct, oct_):
+        g = self.g.export(gct)
+        o = oct_.export()
+        assert g.shape == o.shape, (g.shape, o.shape)
+        bad = np.argwhere(g != o)
+        assert bad.size == 0, f"{len(bad)} residues differ, first at {bad[:3].tolist()}"
+        lv, dg, sc = gct.info()
+        assert lv == oct_.level and dg == oct_.degree
+        assert sc == pytest.approx(oct_.scale, rel=1e-12)
+
+
+@pytest.fixture(scope="module")
+def small(he):
+    return Pair(he, I.small(log_n=12, n_q=6, alpha=2, q_bits=40, p_bits=50), h_list=[4, 8, 16])
+
+
+@pytest.fixture(scope="module")
+def c1p(he):
+    return Pair(he, I.C1P)
+
+
+def test_moduli_match(small):
+    assert small.g.moduli == small.o.moduli
+
+
+@pytest.mark.parametrize("log_n", [11, 12, 14, 15, 16])
+def test_ntt_matches_oracle_evaluation_order(he, log_n):
+    import torch
+    prm = I.Params(f"ntt{log_n}", log_n, [60, 45, 40], [50], 1, 40.0, 3, [])
+    _log(f"[parity] ntt log_n={log_n}")
+    g = he.Context(prm, h_list=[])
+    o = O.Ctx.from_params(prm)
+    x = I.residues(log_n, (len(g.moduli), g.n), g.moduli)
+    t = torch.from_numpy(x.view(np.int64)).cuda()
+    g.ntt(t, list(range(len(g.moduli))))
+    torch.cuda.synchronize()
+    got = t.cpu().numpy().view(np.uint64)
+    for mi in range(len(g.moduli)):
+        assert np.array_equal(got[mi], o.eval_bitrev(mi, x[mi])), f"limb {mi}"
+    g.ntt(t, list(range(len(g.moduli))), inverse=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(t.cpu().numpy().view(np.uint64), x)
+
+
+def test_encode_matches_oracle(small):
+    z = I.matrix(3, 16).ravel()
+    a = small.g.encode(z)
+    b, tie = small.o.encode(z)
+    assert tie > 1e-9 and np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("level", [5, 2, 0])
+def test_encrypt_coeffs_parity(small, level):
+    m = I.plaintext_poly(level, small.g.n, 2 ** 35)
+    gct = small.g.encrypt_coeffs(m, level, 2.0 ** 40, nonce=11 + level)
+    oct_ = small.o.encrypt_coeffs(m, level, 2.0 ** 40, nonce=11 + level)
+    small.same(gct, oct_)
+    assert np.array_equal(small.g.decrypt_coeffs(gct), small.o.decrypt_coeffs(oct_))
+
+
+def test_encrypt_values_parity_and_roundtrip(small):
+    z = I.matrix(4, 16).ravel()
+    gct, oct_ = small.g.encrypt(z, nonce=3), small.o.encrypt(z, nonce=3)
+    small.same(gct, oct_)
+    assert np.abs(small.g.decrypt(gct, 256) - z).max() < 1e-6
+
+
+def test_add_sub_drop_rescale_parity(small):
+    a, b = I.matrix_pair(5, 16)
+    ga, gb = small.g.encrypt(a.ravel(), nonce=1), small.g.encrypt(b.ravel(), level=4, nonce=2)
+    oa, ob = small.o.encrypt(a.ravel(), nonce=1), small.o.encrypt(b.ravel(), level=4, nonce=2)
+    small.same(small.g.add(ga, gb), small.o.add(oa, ob))
+    small.same(small.g.sub(ga, gb), small.o.sub(oa, ob))
+    small.same(small.g.drop(ga, 3), small.o.drop(oa, 3))
+    small.same(small.g.rescale(ga), small.o.rescale(oa))
+
+
+def test_mul_relin_rescale_parity(small):
+    a, b = I.matrix_pair(6, 16)
+    ga, gb = small.g.encrypt(a.ravel(), nonce=4), small.g.encrypt(b.ravel(), nonce=5)
+    oa, ob = small.o.encrypt(a.ravel(), nonce=4), small.o.encrypt(b.ravel(), nonce=5)
+    gt, ot = small.g.tensor(ga, gb), small.o.tensor(oa, ob)
+    small.same(gt, ot)
+    gr, orr = small.g.relin(gt), small.o.relin(ot)
+    small.same(gr, orr)
+    gs, os_ = small.g.rescale(gr), small.o.rescale(orr)
+    small.same(gs, os_)
+    assert np.abs(small.g.decrypt(gs, 256) - (a * b).ravel()).max() < 1e-3
+
+
+def test_mul_plain_and_int_parity(small):
+    a = I.matrix(7, 16).ravel()
+    ga, oa = small.g.encrypt(a, nonce=6), small.o.encrypt(a, nonce=6)
+    pt = I.plaintext_poly(7, small.g.n, 2 ** 20)
+    small.same(small.g.mul_plain(ga, pt, 2.0 ** 20), small.o.mul_plain(oa, pt, 2.0 ** 20))
+    for k in (3, -5, 2 ** 44 + 1, -(2 ** 50)):
+        small.same(small.g.mul_int(ga, k), small.o.mul_int(oa, k))
+
+
+@pytest.mark.parametrize("k", [1, 3, -1, -7, 16, 100, 1023, 2047])
+def test_rotate_parity(small, k):
+    a = I.matrix(8, 16).ravel()
+    ga, oa = small.g.encrypt(a, nonce=7), small.o.encrypt(a, nonce=7)
+    small.g.gen_rotation_key(k)
+    gr, orr = small.g.rotate(ga, k), small.o.rotate(oa, k)
+    small.same(gr, orr)
+    assert np.abs(small.g.decrypt(gr, 256) - np.roll(a, -k)).max() < 1e-6
+
+
+def test_rotate_lower_level_parity(small):
+    a = I.matrix(9, 16).ravel()
+    ga, oa = small.g.drop(small.g.encrypt(a, nonce=8), 1), small.o.drop(small.o.encrypt(a, nonce=8), 1)
+    small.g.gen_rotation_key(5)
+    small.same(small.g.rotate(ga, 5), small.o.rotate(oa, 5))
+
+
+def test_missing_key_is_reported(small, he):
+    ga = small.g.encrypt(np.zeros(4), nonce=1)
+    with pytest.raises(he.HEError) as e:
+        small.g.rotate(ga, 777)
+    assert e.value.name == "HE_EKEY"
+
+
+@pytest.mark.parametrize("h", [4, 8, 16])
+def test_matmul_parity_small(small, h):
+    A, B = I.matrix_pair(20 + h, h)
+    _log(f"[parity] matmul small h={h}")
+    ga, gb = small.g.encrypt(A.ravel(), nonce=30), small.g.encrypt(B.ravel(), nonce=31)
+    oa, ob = small.o.encrypt(A.ravel(), nonce=30), small.o.encrypt(B.ravel(), nonce=31)
+    small.g.counters(reset=True)
+    small.o.reset_counters()
+    gm = small.g.matmul(ga, gb, h)
+    om = small.o.matmul(oa, ob, h)
+    small.same(gm, om)
+    gc, oc = small.g.counters(), small.o.counters()
+    for key in ("rot", "keyswitch", "mul_pt", "mul_ct", "rescale"):
+        assert gc[key] == oc[key], key
+    assert np.abs(small.g.decrypt(gm, h * h).reshape(h, h) - A @ B).max() < 1e-3
+
+
+def test_matmul_relin_once_parity(he):
+    prm = I.small(log_n=12, n_q=6, alpha=2, q_bits=40, p_bits=50)
+    p = Pair(he, prm, h_list=[8], schedule=1)
+    A, B = I.matrix_pair(77, 8)
+    gm = p.g.matmul(p.g.encrypt(A.ravel(), nonce=1), p.g.encrypt(B.ravel(), nonce=2), 8)
+    om = p.o.matmul(p.o.encrypt(A.ravel(), nonce=1), p.o.encrypt(B.ravel(), nonce=2), 8, O.RELIN_ONCE)
+    p.same(gm, om)
+
+
+def test_matmul_c1plus_parity_and_bound(c1p):
+    """the h=8 product on the 2^12 ring at scale 2^30: bit-exact, and within 1e-3 of FP64"""
+    A, B = I.matrix_pair(1, 8)
+    gm = c1p.g.matmul(c1p.g.encrypt(A.ravel(), nonce=1), c1p.g.encrypt(B.ravel(), nonce=2), 8)
+    om = c1p.o.matmul(c1p.o.encrypt(A.ravel(), nonce=1), c1p.o.encrypt(B.ravel(), nonce=2), 8)
+    c1p.same(gm, om)
+    err = np.abs(c1p.g.decrypt(gm, 64).reshape(8, 8) - A @ B).max()
+    _log(f"[parity] C1+ h=8 max abs error {err:.3e}")
+    assert err < 1e-3
+
+
+def test_matmul_shape_and_level_errors(small, he):
+    ga = small.g.encrypt(np.zeros(16), nonce=1)
+    with pytest.raises(he.HEError) as e:
+        small.g.matmul(ga, ga, 6)
+    assert e.value.name == "HE_ESHAPE"
+    with pytest.raises(he.HEError) as e:
+        small.g.matmul(ga, ga, 64)
+    assert e.value.name == "HE_ESHAPE"
+    with pytest.raises(he.HEError) as e:
+        small.g.matmul(small.g.drop(ga, 2), ga, 4)
+    assert e.value.name == "HE_ELEVEL"
+
+
+def test_matmul_batch_equals_single(small):
+    pairs = [(4, 5), (8, 5), (16, 4), (8, 3)]
+    As, Bs, hs, singles = [], [], [], []
+    for i, (h, lvl) in enumerate(pairs):
+        A, B = I.matrix_pair(200 + i, h)
+        a = small.g.encrypt(A.ravel(), level=lvl, nonce=100 + 2 * i)
+        b = small.g.encrypt(B.ravel(), level=lvl, nonce=101 + 2 * i)
+        As.append(a), Bs.append(b), hs.append(h)
+        singles.append(small.g.export(small.g.matmul(a, b, h)))
+    res = small.g.matmul_batch(As, Bs, hs)
+    for r, s in zip(res, singles):
+        assert np.array_equal(small.g.export(r), s)
+
+
+@pytest.mark.parametrize("d,k,mode", [(3, 1, 0), (1, 2, 0), (2, 1, 0), (3, 1, 1)])
+def test_sign_parity(he, d, k, mode):
+    prm = I.small(log_n=12, n_q=8, alpha=3, q_bits=40, p_bits=50)
+    p = Pair(he, prm, h_list=[])
+    X = I.sign_inputs(5, 1, 16)[0].ravel()
+    gx, ox = p.g.encrypt(X, nonce=9), p.o.encrypt(X, nonce=9)
+    gy, oy = p.g.sign_approx(gx, d, k, mode), p.o.sign(ox, d, k, relu=bool(mode))
+    p.same(gy, oy)
+    y = X.copy()
+    coef = {1: [1.5, -0.5], 2: [15 / 8, -10 / 8, 3 / 8], 3: [35 / 16, -35 / 16, 21 / 16, -5 / 16]}[d]
+    for _ in range(k):
+        y = sum(c * y ** (2 * i + 1) for i, c in enumerate(coef))
+    want = (X + X * y) / 2 if mode else y
+    assert np.abs(p.g.decrypt(gy, 256) - want).max() < 1e-3
+
+
+# ---------------------------------------------------------------- full-size configurations
+def test_c2_h64_matmul_parity(he):
+    """N=2^14, 7 x 40-bit Q + 60-bit P, scale 2^40: the whole h=64 product, every residue"""
+    p = Pair(he, I.C2)
+    A, B = I.matrix_pair(2, 64)
+    ga, gb = p.g.encrypt(A.ravel(), nonce=1), p.g.encrypt(B.ravel(), nonce=2)
+    oa, ob = p.o.encrypt(A.ravel(), nonce=1), p.o.encrypt(B.ravel(), nonce=2)
+    p.same(ga, oa)
+    _log("[parity] C2 h=64 GPU matmul")
+    gm = p.g.matmul(ga, gb, 64)
+    _log("[parity] C2 h=64 oracle matmul")
+    om = p.o.matmul(oa, ob, 64)
+    p.same(gm, om)
+    err = np.abs(p.g.decrypt(gm, 4096).reshape(64, 64) - A @ B).max()
+    _log(f"[parity] C2 h=64 max abs error {err:.3e}")
+    assert err < 1e-3
+
+
+def test_c3_rotations_and_h16_matmul_parity(he):
+    """N=2^15, Q = 60 + 13 x 45, P = 3 x 60 + 56, alpha 5 (dnum 3), scale 2^45"""
+    p = Pair(he, I.C3, h_list=[16])
+    A, B = I.matrix_pair(3, 16)
+    for lvl in (13, 7, 3):
+        ga, oa = p.g.encrypt(A.ravel(), level=lvl, nonce=lvl), p.o.encrypt(A.ravel(), level=lvl, nonce=lvl)
+        for k in (1, 16, -15):
+            p.same(p.g.rotate(ga, k), p.o.rotate(oa, k))
+    ga, gb = p.g.encrypt(A.ravel(), level=9, nonce=40), p.g.encrypt(B.ravel(), level=9, nonce=41)
+    oa, ob = p.o.encrypt(A.ravel(), level=9, nonce=40), p.o.encrypt(B.ravel(), level=9, nonce=41)
+    _log("[parity] C3 h=16 matmul")
+    gm = p.g.matmul(ga, gb, 16)
+    om = p.o.matmul(oa, ob, 16)
+    p.same(gm, om)
+    assert np.abs(p.g.decrypt(gm, 256).reshape(16, 16) - A @ B).max() < 1e-6
