@@ -1,0 +1,156 @@
+"""Benchmark: packed ct x ct h=64 matrix products per second at N = 2^15 on one MI355X.
+
+Workload (one "step"): a batch of B independent h=64 products HE-MatMult (Alg. 3 with
+the App. B baby-step/giant-step split) on the N=2^15 ring with Q = 60 + 13 x 45 bits,
+P = 3 x 60 + 56 bits, dnum 3, scale 2^45; inputs are fresh encryptions at the top
+level (13) of matrices with entries uniform in [-1, 1], resident in HBM before the
+timed region.  The plain path (one he_matmul at a time) is timed beside it.
+
+Prints one JSON line (see the design doc for the roofline and traffic derivations).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "ct×ct h=64 HE-matmuls/s at N=2^15 vs plain path; p50/p99 serve latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(prm, seconds_hint=30.0):
+    """The oracle (plain scalar C, OpenMP over limbs) on the host: one h=16 product on the
+    same N=2^15 ring and chain, extrapolated to h=64 by the key-switch + Mul_pt count."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import oracle as O
+    from paper_2207_04620_amd import inputs as I
+
+    threads = os.cpu_count() or 1
+    o = O.Ctx.from_params(prm, threads=threads)
+    A, B = I.matrix_pair(3, 16)
+    a, b = o.encrypt(A.ravel(), nonce=1), o.encrypt(B.ravel(), nonce=2)
+    o.matmul(a, b, 16)  # keys and masks for h=16 (not timed)
+    o.reset_counters()
+    t0 = time.perf_counter()
+    o.matmul(a, b, 16)
+    dt = time.perf_counter() - t0
+    c = o.counters()
+    work16 = c["keyswitch"] + c["mul_pt"]
+    work64 = (225 + 64) + (127 + 64 + 127)  # key switches + Mul_pt of one h=64 product
+    t64 = dt * work64 / work16
+    return {"value": 1.0 / t64, "unit": "HE-matmuls/s", "cores": threads, "kind": "oracle",
+            "sample": f"one h=16 product at N=2^15 from level 13 ({dt:.2f} s, {c['keyswitch']} key switches, "
+                      f"{c['mul_pt']} Mul_pt), extrapolated to h=64 by the op-count ratio {work64}/{work16}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--plain-iters", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the packed product is sharded by "
+              "request across GPUs with no exchange step, so N GPUs give N independent copies of this number.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2207_04620_amd import he, inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    prm = I.C3
+    h = 64
+    log("context C3 (keys + masks for h=64)")
+    t0 = time.perf_counter()
+    ctx = he.Context(prm, h_list=[h], stream=stream.cuda_stream)
+    log(f"context ready in {time.perf_counter() - t0:.1f} s")
+    level = prm.max_level
+    As, Bs = [], []
+    for i in range(args.batch):
+        A, B = I.matrix_pair(1000 + i, h)
+        As.append(ctx.encrypt(A.ravel(), level=level, nonce=2 * i))
+        Bs.append(ctx.encrypt(B.ravel(), level=level, nonce=2 * i + 1))
+    ctx.sync()
+
+    # plain path: one product at a time
+    log("plain path")
+    ctx.matmul(As[0], Bs[0], h)
+    ctx.sync()
+    t0 = time.perf_counter()
+    for i in range(args.plain_iters):
+        ctx.matmul(As[i % args.batch], Bs[i % args.batch], h)
+    ctx.sync()
+    plain_s = (time.perf_counter() - t0) / args.plain_iters
+    log(f"plain {plain_s * 1e3:.1f} ms per product")
+
+    # batched path
+    log("batched path: warmup")
+    for _ in range(args.warmup):
+        ctx.matmul_batch(As, Bs, [h] * args.batch)
+    ctx.sync()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    out = None
+    for s in range(args.steps):
+        out = ctx.matmul_batch(As, Bs, [h] * args.batch)
+        log(f"step {s + 1}/{args.steps} issued")
+    ctx.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.profile(False)
+    prof = ctx.profile_report()
+    step_ms = elapsed / args.steps * 1e3
+    value = args.batch * args.steps / elapsed
+    err = float(np.abs(ctx.decrypt(out[0], h * h).reshape(h, h) - np.dot(*I.matrix_pair(1000, h))).max())
+    log(f"batched {value:.3f} products/s ({step_ms:.1f} ms per step of {args.batch}); max abs error {err:.2e}")
+
+    # dominant kernel by summed duration
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    avg_ms = d["ms"] / max(1, d["launches"])
+    bytes_per_launch = d["bytes"] / max(1, d["launches"])
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "avg_launch_us": round(avg_ms * 1e3, 2), "launches": d["launches"],
+                "share_of_gpu_time": round(d["ms"] / sum(v["ms"] for v in prof.values()), 3)}
+
+    result = {
+        "metric": METRIC, "value": round(value, 4), "unit": "HE-matmuls/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(step_ms, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "C3: batch of packed ct x ct h=64 products (Alg. 3 + App. B), N=2^15, "
+                               "Q=60+13x45 bits, P=3x60+56 bits, dnum=3, scale 2^45, inputs at level 13",
+                   "batch": args.batch, "h": h, "log_n": 15,
+                   "plain_matmuls_per_s": round(1.0 / plain_s, 4), "plain_ms": round(plain_s * 1e3, 2),
+                   "batched_over_plain": round(value * plain_s, 3), "max_abs_error": err},
+        "roofline": roofline,
+        "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in prof.items()},
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline(prm)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

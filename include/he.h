@@ -173,6 +173,13 @@ he_status he_serve_poll(he_server *s, uint64_t ticket, int *done, he_ct **result
                         double *latency_s);
 he_status he_serve_stop(he_server *s);
 
+/* Launch timing: with profiling on, every kernel launch is bracketed by HIP events on
+ * its stream.  The report (JSON text, NUL-terminated, truncated to n bytes) gives per
+ * kernel kind the launch count, summed duration in ms and algorithmic bytes (operands
+ * read once, results written once); reading it synchronizes and clears the records. */
+he_status he_profile_enable(he_ctx *ctx, int on);
+he_status he_profile_report(he_ctx *ctx, char *buf, size_t n);
+
 const char *he_status_string(he_status s);
 
 #ifdef __cplusplus

@@ -1322,6 +1322,20 @@ he_status he_sign_approx(he_ctx* ctx, const he_ct* x, uint32_t d, uint32_t k, ui
     if (mode > 1) return HE_EINVAL;
     return guard([&]() { *out = wrap(ctx->c.get(), ctx->c->sign(*x->c, (int)d, (int)k, (int)mode)); });
 }
+he_status he_profile_enable(he_ctx* ctx, int on) {
+    if (!ctx) return HE_EINVAL;
+    prof_enable(on != 0);
+    return HE_OK;
+}
+he_status he_profile_report(he_ctx* ctx, char* buf, size_t n) {
+    if (!ctx || !buf || n == 0) return HE_EINVAL;
+    return guard([&]() {
+        const std::string r = prof_report();
+        const size_t m = std::min(n - 1, r.size());
+        memcpy(buf, r.data(), m);
+        buf[m] = 0;
+    });
+}
 he_status he_ntt(he_ctx* ctx, uint64_t* dev_ptr, uint32_t n_limbs, const uint32_t* mod_idx, int inverse) {
     if (!ctx || !dev_ptr || !mod_idx || n_limbs == 0) return HE_EINVAL;
     Ctx* c = ctx->c.get();

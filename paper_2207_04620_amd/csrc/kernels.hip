@@ -7,10 +7,88 @@
 // constructions named at each kernel.
 #include "kernels.hpp"
 
+#include <cstdio>
+#include <string>
+#include <vector>
+
 #define TPB 256
 #define NTT_E 2048  // elements held in LDS by one NTT block (16 KiB)
 
 static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------------ launch timing
+// Optional HIP-event timing of every launch (he_profile_enable): a pair of events on
+// the launch stream brackets each kernel; durations are read back on report.  The
+// byte count attached to a launch is its algorithmic traffic: each operand read once
+// and each result written once (tables of constants excluded).
+static const char* const kProfNames[PK_COUNT] = {
+    "ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "baseconv", "inner_product",
+    "moddown_combine", "rescale_spread", "rescale_combine", "tensor", "mask_mac", "automorph", "elementwise"};
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+    double bytes;
+};
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof;
+static std::vector<hipEvent_t> g_ev_free;
+
+static hipEvent_t ev_get() {
+    if (!g_ev_free.empty()) {
+        hipEvent_t e = g_ev_free.back();
+        g_ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+struct ProfScope {
+    int kind;
+    double bytes;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    ProfScope(int k, double b, hipStream_t s) : kind(k), bytes(b), st(s) {
+        if (g_prof_on) {
+            a = ev_get();
+            (void)hipEventRecord(a, st);
+        }
+    }
+    ~ProfScope() {
+        if (g_prof_on && a) {
+            hipEvent_t b = ev_get();
+            (void)hipEventRecord(b, st);
+            g_prof.push_back({kind, a, b, bytes});
+        }
+    }
+};
+
+void prof_enable(bool on) { g_prof_on = on; }
+
+std::string prof_report() {
+    double ms[PK_COUNT] = {0}, by[PK_COUNT] = {0};
+    long cnt[PK_COUNT] = {0};
+    for (auto& r : g_prof) {
+        (void)hipEventSynchronize(r.b);
+        float t = 0;
+        (void)hipEventElapsedTime(&t, r.a, r.b);
+        ms[r.kind] += t;
+        by[r.kind] += r.bytes;
+        cnt[r.kind]++;
+        g_ev_free.push_back(r.a);
+        g_ev_free.push_back(r.b);
+    }
+    g_prof.clear();
+    std::string out = "{";
+    for (int k = 0; k < PK_COUNT; ++k) {
+        char buf[256];
+        snprintf(buf, sizeof buf, "%s\"%s\": {\"launches\": %ld, \"ms\": %.6f, \"bytes\": %.0f}", k ? ", " : "",
+                 kProfNames[k], cnt[k], ms[k], by[k]);
+        out += buf;
+    }
+    return out + "}";
+}
 
 // ------------------------------------------------------------------ NTT
 // Forward transform: Cooley-Tukey with the psi twist merged into the twiddles
@@ -142,12 +220,23 @@ void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st)
     if (J.n == 0 || J.nct == 0) return;
     const int N = 1 << T.log_n, N1 = 1 << T.n1_log;
     dim3 grid_rows(N1, J.n * J.nct), grid_cols(N / NTT_E, J.n * J.nct);
+    const double bytes = 16.0 * J.n * J.nct * N;
     if (!inverse) {
-        if (T.n1_log > 0) hipLaunchKernelGGL(k_ntt_fwd_cols, grid_cols, dim3(TPB), 0, st, T, J);
+        if (T.n1_log > 0) {
+            ProfScope p(PK_NTT_FWD_COLS, bytes, st);
+            hipLaunchKernelGGL(k_ntt_fwd_cols, grid_cols, dim3(TPB), 0, st, T, J);
+        }
+        ProfScope p(PK_NTT_FWD_ROWS, bytes, st);
         hipLaunchKernelGGL(k_ntt_fwd_rows, grid_rows, dim3(TPB), 0, st, T, J);
     } else {
-        hipLaunchKernelGGL(k_ntt_inv_rows, grid_rows, dim3(TPB), 0, st, T, J);
-        if (T.n1_log > 0) hipLaunchKernelGGL(k_ntt_inv_cols, grid_cols, dim3(TPB), 0, st, T, J);
+        {
+            ProfScope p(PK_NTT_INV_ROWS, bytes, st);
+            hipLaunchKernelGGL(k_ntt_inv_rows, grid_rows, dim3(TPB), 0, st, T, J);
+        }
+        if (T.n1_log > 0) {
+            ProfScope p(PK_NTT_INV_COLS, bytes, st);
+            hipLaunchKernelGGL(k_ntt_inv_cols, grid_cols, dim3(TPB), 0, st, T, J);
+        }
     }
 }
 
@@ -184,6 +273,7 @@ __global__ __launch_bounds__(TPB) void k_baseconv(DevTables T, ConvDesc D) {
 }
 
 void launch_baseconv(const DevTables& T, const ConvDesc& D, hipStream_t st) {
+    ProfScope prof_(PK_BASECONV, (double)(D.ns + D.nt) * D.npoly * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), ceil_div(D.nt, 8), D.npoly);
     hipLaunchKernelGGL(k_baseconv, grid, dim3(TPB), 0, st, T, D);
@@ -267,6 +357,7 @@ __global__ __launch_bounds__(TPB) void k_sample_uniform(DevTables T, Jobs J, Sam
 }
 
 void launch_sample(const DevTables& T, const Jobs& J, const SampleArgs& A, hipStream_t st) {
+    ProfScope prof_(PK_EW, 1.0 * J.n * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     if (A.kind == 2) {
         dim3 grid(ceil_div(N / 4, TPB), J.n);
@@ -298,6 +389,7 @@ __global__ __launch_bounds__(TPB) void k_ew(DevTables T, ModMap mm, int nl, u64*
 
 void launch_ew(const DevTables& T, ModMap mm, int nl, int npoly, u64* out, int64_t out_ps, const u64* a,
                int64_t a_ps, const u64* b, int64_t b_ps, int op, hipStream_t st) {
+    ProfScope prof_(PK_EW, 3.0 * nl * npoly * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl, npoly);
     hipLaunchKernelGGL(k_ew, grid, dim3(TPB), 0, st, T, mm, nl, out, out_ps, a, a_ps, b, b_ps, op);
@@ -315,6 +407,7 @@ __global__ __launch_bounds__(TPB) void k_mul_const(DevTables T, ModMap mm, u64* 
 
 void launch_mul_const(const DevTables& T, ModMap mm, int nl, int npoly, u64* out, int64_t out_ps, const u64* a,
                       int64_t a_ps, const u64* c, const u64* c_sh, hipStream_t st) {
+    ProfScope prof_(PK_EW, 2.0 * nl * npoly * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl, npoly);
     hipLaunchKernelGGL(k_mul_const, grid, dim3(TPB), 0, st, T, mm, out, out_ps, a, a_ps, c, c_sh);
@@ -339,6 +432,7 @@ __global__ __launch_bounds__(TPB) void k_automorph(DevTables T, u64* out, int64_
 
 void launch_automorph(const DevTables& T, int nl, int npoly, u64* out, int64_t out_ps, const u64* in,
                       int64_t in_ps, u64 g, hipStream_t st) {
+    ProfScope prof_(PK_AUTOMORPH, 2.0 * nl * npoly * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl, npoly);
     hipLaunchKernelGGL(k_automorph, grid, dim3(TPB), 0, st, T, out, out_ps, in, in_ps, g);
@@ -354,6 +448,7 @@ __global__ __launch_bounds__(TPB) void k_to_mont(DevTables T, ModMap mm, u64* x,
 }
 
 void launch_to_mont(const DevTables& T, ModMap mm, int nl, int npoly, u64* x, int64_t ps, hipStream_t st) {
+    ProfScope prof_(PK_EW, 2.0 * nl * npoly * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl, npoly);
     hipLaunchKernelGGL(k_to_mont, grid, dim3(TPB), 0, st, T, mm, x, ps);
@@ -374,6 +469,7 @@ __global__ __launch_bounds__(TPB) void k_swk_finish(DevTables T, u64* b, const u
 
 void launch_swk_finish(const DevTables& T, int M, u64* b, const u64* a, const u64* e, const u64* s, const u64* sp,
                        const u64* pmod, const uint8_t* in_digit, hipStream_t st) {
+    ProfScope prof_(PK_EW, 6.0 * M * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), M);
     hipLaunchKernelGGL(k_swk_finish, grid, dim3(TPB), 0, st, T, b, a, e, s, sp, pmod, in_digit);
@@ -403,6 +499,7 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
 }
 
 void launch_inner_product(const DevTables& T, const IpDesc& D, hipStream_t st) {
+    ProfScope prof_(PK_INNER, (double)D.ne * (3.0 * D.beta + 2.0) * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), D.ne);
     hipLaunchKernelGGL(k_inner_product, grid, dim3(TPB), 0, st, T, D);
@@ -425,6 +522,7 @@ __global__ __launch_bounds__(TPB) void k_moddown_combine(DevTables T, const u64*
 void launch_moddown_combine(const DevTables& T, int nl, int npoly, const u64* u, int64_t u_ps, const u64* conv,
                             int64_t conv_ps, const u64* pinv, const u64* pinv_sh, const u64* add, int64_t add_ps,
                             u64* out, int64_t out_ps, hipStream_t st) {
+    ProfScope prof_(PK_MODDOWN, (add ? 4.0 : 3.0) * nl * npoly * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl, npoly);
     hipLaunchKernelGGL(k_moddown_combine, grid, dim3(TPB), 0, st, T, u, u_ps, conv, conv_ps, pinv, pinv_sh, add,
@@ -446,6 +544,7 @@ __global__ __launch_bounds__(TPB) void k_rescale_spread(DevTables T, const u64* 
 
 void launch_rescale_spread(const DevTables& T, int nl_out, int npoly, const u64* last, int64_t last_ps,
                            int last_mod, u64* tmp, int64_t tmp_ps, hipStream_t st) {
+    ProfScope prof_(PK_RS_SPREAD, (1.0 + nl_out) * npoly * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl_out, npoly);
     hipLaunchKernelGGL(k_rescale_spread, grid, dim3(TPB), 0, st, T, last, last_ps, last_mod, tmp, tmp_ps);
@@ -465,6 +564,7 @@ __global__ __launch_bounds__(TPB) void k_rescale_combine(DevTables T, const u64*
 void launch_rescale_combine(const DevTables& T, int nl_out, int npoly, const u64* c, int64_t c_ps, const u64* tmp,
                             int64_t tmp_ps, const u64* qinv, const u64* qinv_sh, u64* out, int64_t out_ps,
                             hipStream_t st) {
+    ProfScope prof_(PK_RS_COMBINE, 3.0 * nl_out * npoly * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl_out, npoly);
     hipLaunchKernelGGL(k_rescale_combine, grid, dim3(TPB), 0, st, T, c, c_ps, tmp, tmp_ps, qinv, qinv_sh, out,
@@ -500,6 +600,7 @@ __global__ __launch_bounds__(TPB) void k_tensor(DevTables T, const u64* a, int64
 
 void launch_tensor(const DevTables& T, int nl, const u64* a, int64_t a_ps, const u64* b, int64_t b_ps, u64* d,
                    int64_t d_ps, int acc, hipStream_t st) {
+    ProfScope prof_(PK_TENSOR, (acc ? 10.0 : 7.0) * nl * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl);
     hipLaunchKernelGGL(k_tensor, grid, dim3(TPB), 0, st, T, a, a_ps, b, b_ps, d, d_ps, acc);
@@ -522,6 +623,7 @@ __global__ __launch_bounds__(TPB) void k_mask_mac(DevTables T, MacDesc D, u64* o
 
 void launch_mask_mac(const DevTables& T, int nl, int npoly, const MacDesc& D, u64* out, int64_t out_ps, int acc,
                      hipStream_t st) {
+    ProfScope prof_(PK_MASKMAC, ((2.0 * D.nterm + 1.0 + acc) * nl * npoly) * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl, npoly);
     hipLaunchKernelGGL(k_mask_mac, grid, dim3(TPB), 0, st, T, D, out, out_ps, acc);
@@ -542,6 +644,7 @@ __global__ __launch_bounds__(TPB) void k_dec_dot(DevTables T, int deg, const u64
 
 void launch_dec_dot(const DevTables& T, int nl, int deg, const u64* c, int64_t c_ps, const u64* s, const u64* s2,
                     u64* m, hipStream_t st) {
+    ProfScope prof_(PK_EW, (2.0 + 2.0 * deg) * nl * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl);
     hipLaunchKernelGGL(k_dec_dot, grid, dim3(TPB), 0, st, T, deg, c, c_ps, s, s2, m);
@@ -560,6 +663,7 @@ __global__ __launch_bounds__(TPB) void k_enc_combine(DevTables T, const u64* v, 
 
 void launch_enc_combine(const DevTables& T, int nl, const u64* v, const u64* pk0, const u64* pk1, const u64* x0,
                         const u64* x1, u64* c0, u64* c1, hipStream_t st) {
+    ProfScope prof_(PK_EW, 7.0 * nl * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl);
     hipLaunchKernelGGL(k_enc_combine, grid, dim3(TPB), 0, st, T, v, pk0, pk1, x0, x1, c0, c1);
@@ -576,6 +680,7 @@ __global__ __launch_bounds__(TPB) void k_add_signed(DevTables T, u64* x, const i
 }
 
 void launch_add_signed(const DevTables& T, int nl, u64* x, const int64_t* m, hipStream_t st) {
+    ProfScope prof_(PK_EW, 3.0 * nl * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl);
     hipLaunchKernelGGL(k_add_signed, grid, dim3(TPB), 0, st, T, x, m);

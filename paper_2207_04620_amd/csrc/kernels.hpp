@@ -94,6 +94,15 @@ struct MacDesc {
 
 enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_MUL_MONT = 2, EW_MUL_PLAIN = 3 };
 
+// ------------------------------------------------------------------ launch timing
+enum ProfKind {
+    PK_NTT_FWD_COLS = 0, PK_NTT_FWD_ROWS, PK_NTT_INV_ROWS, PK_NTT_INV_COLS, PK_BASECONV, PK_INNER, PK_MODDOWN,
+    PK_RS_SPREAD, PK_RS_COMBINE, PK_TENSOR, PK_MASKMAC, PK_AUTOMORPH, PK_EW, PK_COUNT
+};
+#include <string>
+void prof_enable(bool on);
+std::string prof_report();  // JSON: per kernel kind {launches, ms, bytes}; clears the records
+
 // ------------------------------------------------------------------ launchers
 void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st);
 void launch_baseconv(const DevTables& T, const ConvDesc& D, hipStream_t st);

@@ -95,6 +95,8 @@ SIGNATURES = {
     "he_serve_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_void_p),
                                 C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "he_serve_stop": (C.c_int, [C.c_void_p]),
+    "he_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "he_profile_report": (C.c_int, [C.c_void_p, C.c_char_p, C.c_size_t]),
     "he_status_string": (C.c_char_p, [C.c_int]),
 }
 
@@ -211,6 +213,15 @@ class Context:
         k, p = C.c_uint64(), C.c_uint64()
         _chk(lib().he_memory(self.ptr, C.byref(k), C.byref(p)), "he_memory")
         return k.value, p.value
+
+    def profile(self, on: bool):
+        _chk(lib().he_profile_enable(self.ptr, int(on)), "he_profile_enable")
+
+    def profile_report(self):
+        import json
+        buf = C.create_string_buffer(1 << 16)
+        _chk(lib().he_profile_report(self.ptr, buf, len(buf)), "he_profile_report")
+        return json.loads(buf.value.decode())
 
     # -- encode / encrypt / decrypt
     def encode(self, vals, scale=None):
