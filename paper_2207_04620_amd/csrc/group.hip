@@ -1,0 +1,475 @@
+// Lockstep execution of HE-MatMult (Alg. 3 + App. B) over a group of ciphertext pairs
+// with the same matrix side h and level.  Every operation of the product runs once
+// per group: each launch covers all members, and the kernels that read a shared
+// operand (a switching key in the key-switch inner product, a diagonal mask in the
+// mask multiply-accumulate) load it once and reuse it for every member, so a key
+// crosses HBM once per rotation round of the whole group.  The operation DAG is the
+// one of the single product, so every member's result is bit-identical to running
+// it alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+
+#include "he_internal.hpp"
+
+static void copy2d(Ctx* c, u64* dst, int64_t dpitch, const u64* src, int64_t spitch, int64_t width, int64_t height) {
+    if (height <= 0 || width <= 0) return;
+    hip_check(hipMemcpy2DAsync(dst, (size_t)dpitch * 8, src, (size_t)spitch * 8, (size_t)width * 8, (size_t)height,
+                               hipMemcpyDeviceToDevice, c->stream),
+              "copy2d");
+}
+
+Grp Ctx::g_new(int B, int level, int deg, const std::vector<double>& sc) {
+    Grp g;
+    g.B = B;
+    g.level = level;
+    g.deg = deg;
+    g.scale = sc;
+    g.ps = (int64_t)(level + 1) * N;
+    g.cs = (int64_t)(deg + 1) * g.ps;
+    g.buf = std::make_shared<DBuf>(this, (size_t)B * g.cs);
+    g.p = g.buf->p;
+    return g;
+}
+
+Grp Ctx::g_gather(const std::vector<const CtData*>& v, int level) {
+    std::vector<double> sc;
+    for (auto* c : v) {
+        if (c->deg != 1 || c->level < level) throw HeError(HE_EMISMATCH);
+        sc.push_back(c->scale);
+    }
+    Grp g = g_new((int)v.size(), level, 1, sc);
+    for (size_t i = 0; i < v.size(); ++i)
+        copy2d(this, g.p + i * g.cs, g.ps, v[i]->buf->p, (int64_t)(v[i]->level + 1) * N, g.ps, 2);
+    return g;
+}
+
+std::vector<CtPtr> Ctx::g_scatter(const Grp& g) {
+    std::vector<CtPtr> out;
+    for (int i = 0; i < g.B; ++i) {
+        CtPtr c = new_ct(g.level, g.deg, g.scale[i]);
+        hip_check(hipMemcpyAsync(c->buf->p, g.p + i * g.cs, (size_t)g.cs * 8, hipMemcpyDeviceToDevice, stream),
+                  "scatter");
+        out.push_back(c);
+    }
+    return out;
+}
+
+Grp Ctx::g_drop(const Grp& a, int level) {
+    if (level > a.level) throw HeError(HE_ELEVEL);
+    Grp g = g_new(a.B, level, a.deg, a.scale);
+    copy2d(this, g.p, g.ps, a.p, a.ps, g.ps, (int64_t)a.B * (a.deg + 1));
+    return g;
+}
+
+void Ctx::g_add_into(Grp& acc, const Grp& t) {
+    if (acc.B != t.B || acc.deg != t.deg || acc.level != t.level) throw HeError(HE_EMISMATCH);
+    launch_ew(T, ModMap{1 << 20, n_q}, acc.level + 1, acc.deg + 1, acc.p, acc.ps, acc.p, acc.ps, t.p, t.ps, EW_ADD,
+              stream, acc.B, acc.cs, acc.cs, t.cs);
+    for (int i = 0; i < acc.B; ++i) acc.scale[i] = std::max(acc.scale[i], t.scale[i]);
+    cnt[C_ADD] += acc.B;
+}
+
+// digits of poly 'poly' of every member, lifted to Q_l and P: [B][beta][ne][N]
+std::shared_ptr<DBuf> Ctx::g_lift(const Grp& a, int poly) {
+    const int level = a.level, nl = level + 1, ne = nl + n_p, B = a.B;
+    const auto& infos = mu[level];
+    const int beta = (int)infos.size();
+    const int64_t lcs = (int64_t)beta * ne * N;
+    auto lift = std::make_shared<DBuf>(this, (size_t)B * lcs);
+    DBuf coef(this, (size_t)B * nl * N);
+    copy2d(this, coef.p, (int64_t)nl * N, a.p + poly * a.ps, a.cs, (int64_t)nl * N, B);
+    {
+        Jobs J;
+        J.base = coef.p;
+        J.cstride = (int64_t)nl * N;
+        J.nct = B;
+        J.n = nl;
+        for (int i = 0; i < nl; ++i) {
+            J.off[i] = (uint16_t)i;
+            J.mod[i] = (uint8_t)i;
+        }
+        launch_ntt(T, J, true, stream);
+    }
+    Jobs J;
+    J.base = lift->p;
+    J.cstride = lcs;
+    J.nct = B;
+    J.n = 0;
+    for (int j = 0; j < beta; ++j) {
+        const ModUpInfo& inf = infos[j];
+        ConvDesc D;
+        memset(&D, 0, sizeof D);
+        D.src = coef.p + (size_t)inf.lo * N;
+        D.src_cstride = (int64_t)nl * N;
+        D.dst = lift->p + (size_t)j * ne * N;
+        D.dst_cstride = lcs;
+        D.nct = B;
+        D.npoly = 1;
+        D.tab = d_mu_tab->p + inf.off;
+        D.tab_ld = ne;
+        D.ns = inf.hi - inf.lo;
+        int nt = 0;
+        for (int t = 0; t < ne; ++t) {
+            if (t >= inf.lo && t < inf.hi) continue;
+            D.doff[nt] = (uint16_t)t;
+            D.dmod[nt] = (uint8_t)ext_mod(level, t);
+            D.tcol[nt] = (uint16_t)t;
+            ++nt;
+            if (J.n >= HE_MAXJ) throw HeError(HE_EUNSUPPORTED);
+            J.off[J.n] = (uint16_t)(j * ne + t);
+            J.mod[J.n] = (uint8_t)ext_mod(level, t);
+            ++J.n;
+        }
+        D.nt = nt;
+        for (int s = 0; s < D.ns; ++s) {
+            D.smod[s] = inf.lo + s;
+            D.hinv[s] = inf.hinv[s];
+            D.hinv_sh[s] = inf.hinv_sh[s];
+        }
+        launch_baseconv(T, D, stream);
+        copy2d(this, lift->p + ((size_t)j * ne + inf.lo) * N, lcs, a.p + poly * a.ps + (size_t)inf.lo * N, a.cs,
+               (int64_t)(inf.hi - inf.lo) * N, B);
+    }
+    launch_ntt(T, J, false, stream);
+    return lift;
+}
+
+// ModDown(<lift o sigma_g, key>) (+ add) into out, for every member
+void Ctx::g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, const u64* add0, const u64* add1,
+                     int64_t add_cs, u64* out0, u64* out1, int64_t out_cs) {
+    const int nl = level + 1, ne = nl + n_p;
+    const int beta = (int)mu[level].size();
+    const int64_t ucs = 2 * (int64_t)ne * N, ccs = 2 * (int64_t)nl * N;
+    DBuf u(this, (size_t)B * ucs);
+    IpDesc D;
+    memset(&D, 0, sizeof D);
+    D.lift = lift;
+    D.key = key;
+    D.u = u.p;
+    D.lift_cs = (int64_t)beta * ne * N;
+    D.u_cs = ucs;
+    D.nct = B;
+    D.ne = ne;
+    D.beta = beta;
+    D.M = n_q + n_p;
+    D.g = g;
+    for (int t = 0; t < ne; ++t) D.mod[t] = (uint8_t)ext_mod(level, t);
+    launch_inner_product(T, D, stream);
+    {
+        Jobs J;
+        J.base = u.p;
+        J.cstride = ucs;
+        J.nct = B;
+        J.n = 0;
+        for (int p = 0; p < 2; ++p)
+            for (int k = 0; k < n_p; ++k) {
+                J.off[J.n] = (uint16_t)(p * ne + nl + k);
+                J.mod[J.n] = (uint8_t)(n_q + k);
+                ++J.n;
+            }
+        launch_ntt(T, J, true, stream);
+    }
+    DBuf conv(this, (size_t)B * ccs);
+    ConvDesc C;
+    memset(&C, 0, sizeof C);
+    C.src = u.p + (size_t)nl * N;
+    C.src_pstride = (int64_t)ne * N;
+    C.src_cstride = ucs;
+    C.dst = conv.p;
+    C.dst_pstride = (int64_t)nl * N;
+    C.dst_cstride = ccs;
+    C.nct = B;
+    C.tab = d_md_tab->p;
+    C.tab_ld = n_q;
+    C.ns = n_p;
+    C.nt = nl;
+    C.npoly = 2;
+    for (int s = 0; s < n_p; ++s) {
+        C.smod[s] = n_q + s;
+        C.hinv[s] = md_hinv[s];
+        C.hinv_sh[s] = md_hinv_sh[s];
+    }
+    for (int t = 0; t < nl; ++t) {
+        C.doff[t] = (uint16_t)t;
+        C.dmod[t] = (uint8_t)t;
+        C.tcol[t] = (uint16_t)t;
+    }
+    launch_baseconv(T, C, stream);
+    {
+        Jobs J;
+        J.base = conv.p;
+        J.cstride = ccs;
+        J.nct = B;
+        J.n = 2 * nl;
+        for (int p = 0; p < 2; ++p)
+            for (int t = 0; t < nl; ++t) {
+                J.off[p * nl + t] = (uint16_t)(p * nl + t);
+                J.mod[p * nl + t] = (uint8_t)t;
+            }
+        launch_ntt(T, J, false, stream);
+    }
+    const u64* pinv = d_pinv->p;
+    launch_moddown_combine(T, nl, 1, u.p, 0, conv.p, 0, pinv, pinv + n_q, add0, 0, out0, 0, stream, B, ucs, ccs,
+                           add_cs, out_cs);
+    launch_moddown_combine(T, nl, 1, u.p + (size_t)ne * N, 0, conv.p + (size_t)nl * N, 0, pinv, pinv + n_q, add1, 0,
+                           out1, 0, stream, B, ucs, ccs, add_cs, out_cs);
+    cnt[C_KS] += B;
+}
+
+Grp Ctx::g_rotate_from_lift(const Grp& a, const u64* lift, int64_t k) {
+    const u64 g = galois(k);
+    if (g == 1) return g_drop(a, a.level);
+    const u64* key = rot_key(g, false);
+    Grp out = g_new(a.B, a.level, 1, a.scale);
+    launch_automorph(T, a.level + 1, 1, out.p, 0, a.p, 0, g, stream, a.B, out.cs, a.cs);
+    g_ks_apply(lift, a.B, a.level, key, g, out.p, nullptr, out.cs, out.p, out.p + out.ps, out.cs);
+    cnt[C_ROT] += a.B;
+    return out;
+}
+
+Grp Ctx::g_rotate(const Grp& a, int64_t k) {
+    if (galois(k) == 1) return g_drop(a, a.level);
+    rot_key(galois(k), false);
+    auto lift = g_lift(a, 1);
+    return g_rotate_from_lift(a, lift->p, k);
+}
+
+Grp Ctx::g_mask_sum(const std::vector<std::pair<const Grp*, const u64*>>& terms, double mask_scale) {
+    const Grp& a0 = *terms[0].first;
+    std::vector<double> sc(a0.scale);
+    for (auto& s : sc) s *= mask_scale;
+    Grp out = g_new(a0.B, a0.level, 1, sc);
+    for (size_t base = 0; base < terms.size(); base += 16) {
+        MacDesc D;
+        memset(&D, 0, sizeof D);
+        D.nct = a0.B;
+        D.nterm = (int)std::min<size_t>(16, terms.size() - base);
+        for (int t = 0; t < D.nterm; ++t) {
+            const Grp* g = terms[base + t].first;
+            if (g->level != a0.level || g->deg != 1 || g->B != a0.B) throw HeError(HE_EMISMATCH);
+            D.in[t] = g->p;
+            D.in_ps[t] = g->ps;
+            D.in_cs[t] = g->cs;
+            D.mask[t] = terms[base + t].second;
+        }
+        launch_mask_mac(T, a0.level + 1, 2, D, out.p, out.ps, base > 0, stream, out.cs);
+    }
+    cnt[C_MULPT] += (int64_t)terms.size() * a0.B;
+    cnt[C_ADD] += ((int64_t)terms.size() - 1) * a0.B;
+    return out;
+}
+
+Grp Ctx::g_rescale(const Grp& a) {
+    if (a.level < 1) throw HeError(HE_ELEVEL);
+    const int l = a.level, np = a.deg + 1, B = a.B;
+    DBuf last(this, (size_t)B * np * N);
+    copy2d(this, last.p, N, a.p + (size_t)l * N, a.ps, N, (int64_t)B * np);
+    {
+        Jobs J;
+        J.base = last.p;
+        J.cstride = N;
+        J.nct = B * np;
+        J.n = 1;
+        J.off[0] = 0;
+        J.mod[0] = (uint8_t)l;
+        launch_ntt(T, J, true, stream);
+    }
+    DBuf tmp(this, (size_t)B * np * l * N);
+    launch_rescale_spread(T, l, B * np, last.p, N, l, tmp.p, (int64_t)l * N, stream);
+    {
+        Jobs J;
+        J.base = tmp.p;
+        J.cstride = (int64_t)l * N;
+        J.nct = B * np;
+        J.n = l;
+        for (int i = 0; i < l; ++i) {
+            J.off[i] = (uint16_t)i;
+            J.mod[i] = (uint8_t)i;
+        }
+        launch_ntt(T, J, false, stream);
+    }
+    std::vector<double> sc(a.scale);
+    for (auto& s : sc) s /= (double)mods[l];
+    Grp out = g_new(B, l - 1, a.deg, sc);
+    const u64* qi = d_rs->p + (size_t)l * n_q;
+    const u64* qis = d_rs->p + (size_t)n_q * n_q + (size_t)l * n_q;
+    launch_rescale_combine(T, l, np, a.p, a.ps, tmp.p, (int64_t)l * N, qi, qis, out.p, out.ps, stream, B, a.cs,
+                           (int64_t)np * l * N, out.cs);
+    cnt[C_RS] += B;
+    return out;
+}
+
+Grp Ctx::g_tensor(const Grp& a, const Grp& b) {
+    if (a.deg != 1 || b.deg != 1 || a.B != b.B || a.level != b.level) throw HeError(HE_EMISMATCH);
+    std::vector<double> sc(a.B);
+    for (int i = 0; i < a.B; ++i) sc[i] = a.scale[i] * b.scale[i];
+    Grp out = g_new(a.B, a.level, 2, sc);
+    launch_tensor(T, a.level + 1, a.p, a.ps, b.p, b.ps, out.p, out.ps, 0, stream, a.B, a.cs, b.cs, out.cs);
+    cnt[C_MULCT] += a.B;
+    return out;
+}
+
+void Ctx::g_tensor_acc(Grp& acc, const Grp& a, const Grp& b) {
+    if (a.deg != 1 || b.deg != 1 || acc.deg != 2 || a.level != acc.level || b.level != acc.level)
+        throw HeError(HE_EMISMATCH);
+    launch_tensor(T, a.level + 1, a.p, a.ps, b.p, b.ps, acc.p, acc.ps, 1, stream, a.B, a.cs, b.cs, acc.cs);
+    cnt[C_MULCT] += a.B;
+    cnt[C_ADD] += a.B;
+}
+
+Grp Ctx::g_relin(const Grp& a) {
+    if (a.deg != 2) throw HeError(HE_EMISMATCH);
+    const u64* key = relin_key();
+    auto lift = g_lift(a, 2);
+    Grp out = g_new(a.B, a.level, 1, a.scale);
+    g_ks_apply(lift->p, a.B, a.level, key, 1, a.p, a.p + a.ps, a.cs, out.p, out.p + out.ps, out.cs);
+    return out;
+}
+
+// ------------------------------------------------------------------ the product
+static int floordiv_g(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+std::vector<CtPtr> Ctx::matmul_group(const std::vector<const CtData*>& A, const std::vector<const CtData*>& Bv,
+                                     int h, int lvl) {
+    const int b = bsgs(h);
+    const double ms = scale;
+    Grp a = g_gather(A, lvl), bb = g_gather(Bv, lvl);
+
+    // Step 1-1: A0 = sum_i Rot(sum_j R(u_{bi+j}, -bi) . Rot(A, j), b i), then RS
+    Grp A0;
+    {
+        std::vector<Grp> baby(b);
+        baby[0] = a;
+        {
+            auto lift = g_lift(a, 1);
+            for (int j = 1; j < b; ++j) baby[j] = g_rotate_from_lift(a, lift->p, j);
+        }
+        Grp acc;
+        bool have = false;
+        for (int i = floordiv_g(1 - h, b); i <= floordiv_g(h - 1, b); ++i) {
+            std::vector<std::pair<const Grp*, const u64*>> terms;
+            for (int j = 0; j < b; ++j) {
+                const int k = b * i + j;
+                if (k <= -h || k >= h) continue;
+                terms.push_back({&baby[j], mask(0, h, k, -(int64_t)b * i)});
+            }
+            if (terms.empty()) continue;
+            Grp inner = g_mask_sum(terms, ms);
+            if (i) inner = g_rotate(inner, (int64_t)b * i);
+            if (!have) {
+                acc = inner;
+                have = true;
+            } else {
+                g_add_into(acc, inner);
+            }
+        }
+        A0 = g_rescale(acc);
+    }
+    // Step 1-2: B0 = sum_i Rot(sum_j R(u_{h(bi+j)}, -h b i) . Rot(B, h j), h b i), then RS
+    Grp B0;
+    {
+        std::vector<Grp> baby(b);
+        baby[0] = bb;
+        {
+            auto lift = g_lift(bb, 1);
+            for (int j = 1; j < b; ++j) baby[j] = g_rotate_from_lift(bb, lift->p, (int64_t)h * j);
+        }
+        Grp acc;
+        bool have = false;
+        for (int i = 0; i * b < h; ++i) {
+            std::vector<std::pair<const Grp*, const u64*>> terms;
+            for (int j = 0; j < b && b * i + j < h; ++j)
+                terms.push_back({&baby[j], mask(1, h, b * i + j, -(int64_t)h * b * i)});
+            Grp inner = g_mask_sum(terms, ms);
+            if (i) inner = g_rotate(inner, (int64_t)h * b * i);
+            if (!have) {
+                acc = inner;
+                have = true;
+            } else {
+                g_add_into(acc, inner);
+            }
+        }
+        B0 = g_rescale(acc);
+        B0 = g_drop(B0, B0.level - 1);  // brought to the Step-3 level before its rotations
+    }
+    // Steps 2 and 3
+    auto liftA = g_lift(A0, 1);
+    auto liftB = g_lift(B0, 1);
+    Grp acc;
+    bool have = false;
+    for (int k = 0; k < h; ++k) {
+        Grp Ak;
+        if (k == 0) {
+            Ak = g_mask_sum({{&A0, mask(2, h, 0, 0)}}, ms);
+        } else {
+            Grp r1 = g_rotate_from_lift(A0, liftA->p, k);
+            Grp r2 = g_rotate_from_lift(A0, liftA->p, k - h);
+            Ak = g_mask_sum({{&r1, mask(2, h, k, 0)}, {&r2, mask(3, h, k, 0)}}, ms);
+        }
+        Ak = g_rescale(Ak);
+        Grp Bk = k ? g_rotate_from_lift(B0, liftB->p, (int64_t)h * k) : B0;
+        if (schedule == HE_SCHED_RELIN_EACH) {
+            Grp prod = g_relin(g_tensor(Ak, Bk));
+            if (!have) {
+                acc = prod;
+                have = true;
+            } else {
+                g_add_into(acc, prod);
+            }
+        } else {
+            if (!have) {
+                acc = g_tensor(Ak, Bk);
+                have = true;
+            } else {
+                g_tensor_acc(acc, Ak, Bk);
+            }
+        }
+    }
+    if (schedule == HE_SCHED_RELIN_ONCE) acc = g_relin(acc);
+    return g_scatter(g_rescale(acc));
+}
+
+CtPtr Ctx::matmul(const CtData& A, const CtData& B, int h) {
+    if ((h & (h - 1)) || h < 1 || (int64_t)h * h > N / 2) throw HeError(HE_ESHAPE);
+    if (A.deg != 1 || B.deg != 1) throw HeError(HE_EMISMATCH);
+    const int lvl = std::min(A.level, B.level);
+    if (lvl < 3) throw HeError(HE_ELEVEL);
+    prepare_h(h);
+    return matmul_group({&A}, {&B}, h, lvl)[0];
+}
+
+// Members are grouped by (h, level); each group runs in lockstep.  Group size is
+// capped so the working set (about 12 ciphertext-sized blocks per member plus two
+// lifted-digit blocks) stays well inside HBM.
+std::vector<CtPtr> Ctx::matmul_batch(const std::vector<const CtData*>& A, const std::vector<const CtData*>& B,
+                                     const std::vector<int>& h) {
+    const size_t n = A.size();
+    std::vector<CtPtr> out(n);
+    std::map<std::pair<int, int>, std::vector<size_t>> groups;
+    for (size_t i = 0; i < n; ++i) {
+        const int hh = h[i];
+        if ((hh & (hh - 1)) || hh < 1 || (int64_t)hh * hh > N / 2) throw HeError(HE_ESHAPE);
+        if (A[i]->deg != 1 || B[i]->deg != 1) throw HeError(HE_EMISMATCH);
+        const int lvl = std::min(A[i]->level, B[i]->level);
+        if (lvl < 3) throw HeError(HE_ELEVEL);
+        groups[{hh, lvl}].push_back(i);
+    }
+    for (auto& kv : groups) prepare_h(kv.first.first);
+    const size_t cap = (size_t)std::max(1, max_group);
+    for (auto& kv : groups) {
+        const auto& idx = kv.second;
+        for (size_t s = 0; s < idx.size(); s += cap) {
+            std::vector<const CtData*> a, b;
+            for (size_t t = s; t < std::min(idx.size(), s + cap); ++t) {
+                a.push_back(A[idx[t]]);
+                b.push_back(B[idx[t]]);
+            }
+            auto r = matmul_group(a, b, kv.first.first, kv.first.second);
+            for (size_t t = 0; t < r.size(); ++t) out[idx[s + t]] = r[t];
+        }
+    }
+    return out;
+}

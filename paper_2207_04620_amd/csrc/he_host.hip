@@ -563,6 +563,7 @@ std::unique_ptr<DBuf> Ctx::ks_lift(const u64* d, int level) {
         const ModUpInfo& inf = infos[j];
         ConvDesc D;
         memset(&D, 0, sizeof D);
+        D.nct = 1;
         D.src = coef.p + (size_t)inf.lo * N;
         D.src_pstride = 0;
         D.dst = lift->p + (size_t)j * ne * N;
@@ -615,6 +616,9 @@ void Ctx::ks_apply(const u64* lift, int level, const u64* key, u64 g, const u64*
     D.beta = beta;
     D.M = n_q + n_p;
     D.g = g;
+    D.nct = 1;
+    D.lift_cs = 0;
+    D.u_cs = 0;
     for (int t = 0; t < ne; ++t) D.mod[t] = (uint8_t)ext_mod(level, t);
     launch_inner_product(T, D, stream);
     // ModDown
@@ -633,6 +637,7 @@ void Ctx::ks_apply(const u64* lift, int level, const u64* key, u64 g, const u64*
     DBuf conv(this, 2 * (size_t)nl * N);
     ConvDesc C;
     memset(&C, 0, sizeof C);
+    C.nct = 1;
     C.src = u.p + (size_t)nl * N;
     C.src_pstride = (int64_t)ne * N;
     C.dst = conv.p;
@@ -766,6 +771,7 @@ CtPtr Ctx::mask_sum(const std::vector<std::pair<const CtData*, const u64*>>& ter
     for (size_t base = 0; base < terms.size(); base += 16) {
         MacDesc D;
         memset(&D, 0, sizeof D);
+        D.nct = 1;
         D.nterm = (int)std::min<size_t>(16, terms.size() - base);
         for (int t = 0; t < D.nterm; ++t) {
             const CtData* c = terms[base + t].first;
@@ -883,99 +889,6 @@ void Ctx::prepare_h(int h) {
     prepare_masks(matmul_masks(h));
     hip_check(hipStreamSynchronize(stream), "prepare_h");
     prepared_h.insert(h);
-}
-
-// ====================================================================== HE-MatMult
-// Alg. 3: Step 1-1 A0 = U^mu . a, Step 1-2 B0 = U^zeta . b (both in the baby-step /
-// giant-step form of App. B with pre-rotated diagonals R(u_{bi+j}, -bi)), Step 2
-// A^(k) = v_k . Rot(A0, k) + v_{k-h} . Rot(A0, k-h) and B^(k) = Rot(B0, h k), Step 3
-// sum_k Mul_ct(A^(k), B^(k)); one RS per multiplicative level.  The rotations of one
-// ciphertext share its lifted digits (hoisting); the result is bit-identical to the
-// unhoisted evaluation because the centered lift commutes with automorphisms.
-CtPtr Ctx::matmul(const CtData& A, const CtData& B, int h) {
-    if ((h & (h - 1)) || h < 1 || (int64_t)h * h > N / 2) throw HeError(HE_ESHAPE);
-    if (A.deg != 1 || B.deg != 1) throw HeError(HE_EMISMATCH);
-    const int lvl = std::min(A.level, B.level);
-    if (lvl < 3) throw HeError(HE_ELEVEL);
-    prepare_h(h);  // keys and masks are made once per h
-    CtPtr a = drop(A, lvl), bb = drop(B, lvl);
-    const int b = bsgs(h);
-    const double ms = scale;
-    const int64_t psl = (int64_t)(lvl + 1) * N;
-
-    // Step 1-1
-    CtPtr A0;
-    {
-        auto lift = ks_lift(a->buf->p + psl, lvl);
-        std::vector<CtPtr> baby(b);
-        baby[0] = a;
-        for (int j = 1; j < b; ++j) baby[j] = rotate_from_lift(*a, lift->p, j);
-        lift.reset();
-        CtPtr acc;
-        for (int i = floordiv(1 - h, b); i <= floordiv(h - 1, b); ++i) {
-            std::vector<std::pair<const CtData*, const u64*>> terms;
-            for (int j = 0; j < b; ++j) {
-                const int k = b * i + j;
-                if (k <= -h || k >= h) continue;
-                terms.push_back({baby[j].get(), mask(0, h, k, -(int64_t)b * i)});
-            }
-            if (terms.empty()) continue;
-            CtPtr inner = mask_sum(terms, ms);
-            if (i) inner = rotate(*inner, (int64_t)b * i);
-            acc = acc ? add_sub(*acc, *inner, false) : inner;
-        }
-        A0 = rescale(*acc);
-    }
-    // Step 1-2
-    CtPtr B0;
-    {
-        auto lift = ks_lift(bb->buf->p + psl, lvl);
-        std::vector<CtPtr> baby(b);
-        baby[0] = bb;
-        for (int j = 1; j < b; ++j) baby[j] = rotate_from_lift(*bb, lift->p, (int64_t)h * j);
-        lift.reset();
-        CtPtr acc;
-        for (int i = 0; i * b < h; ++i) {
-            std::vector<std::pair<const CtData*, const u64*>> terms;
-            for (int j = 0; j < b && b * i + j < h; ++j)
-                terms.push_back({baby[j].get(), mask(1, h, b * i + j, -(int64_t)h * b * i)});
-            CtPtr inner = mask_sum(terms, ms);
-            if (i) inner = rotate(*inner, (int64_t)h * b * i);
-            acc = acc ? add_sub(*acc, *inner, false) : inner;
-        }
-        B0 = rescale(*acc);
-        B0 = drop(*B0, B0->level - 1);  // brought to the Step-3 level before its rotations
-    }
-    // Steps 2 and 3
-    const int64_t psA0 = (int64_t)(A0->level + 1) * N, psB0 = (int64_t)(B0->level + 1) * N;
-    auto liftA = ks_lift(A0->buf->p + psA0, A0->level);
-    auto liftB = ks_lift(B0->buf->p + psB0, B0->level);
-    CtPtr acc;
-    for (int k = 0; k < h; ++k) {
-        CtPtr Ak;
-        if (k == 0) {
-            Ak = mask_sum({{A0.get(), mask(2, h, 0, 0)}}, ms);
-        } else {
-            CtPtr r1 = rotate_from_lift(*A0, liftA->p, k);
-            CtPtr r2 = rotate_from_lift(*A0, liftA->p, k - h);
-            Ak = mask_sum({{r1.get(), mask(2, h, k, 0)}, {r2.get(), mask(3, h, k, 0)}}, ms);
-        }
-        Ak = rescale(*Ak);
-        CtPtr Bk = k ? rotate_from_lift(*B0, liftB->p, (int64_t)h * k) : B0;
-        CtPtr prod = tensor(*Ak, *Bk);
-        if (schedule == HE_SCHED_RELIN_EACH) prod = relin(*prod);
-        acc = acc ? add_sub(*acc, *prod, false) : prod;
-    }
-    if (schedule == HE_SCHED_RELIN_ONCE) acc = relin(*acc);
-    return rescale(*acc);
-}
-
-// ====================================================================== batched products
-std::vector<CtPtr> Ctx::matmul_batch(const std::vector<const CtData*>& A, const std::vector<const CtData*>& B,
-                                     const std::vector<int>& h) {
-    std::vector<CtPtr> out;
-    for (size_t i = 0; i < A.size(); ++i) out.push_back(matmul(*A[i], *B[i], h[i]));
-    return out;
 }
 
 // ====================================================================== sign (Sec. 4.2)

@@ -54,6 +54,15 @@ struct CtData {
 };
 typedef std::shared_ptr<CtData> CtPtr;
 
+// B ciphertexts of one level and degree in one block [B][deg+1][level+1][N]
+struct Grp {
+    int B = 0, level = 0, deg = 1;
+    std::vector<double> scale;
+    std::shared_ptr<DBuf> buf;
+    u64* p = nullptr;
+    int64_t ps = 0, cs = 0;  // poly and ciphertext strides (elements)
+};
+
 struct ModUpInfo {
     int lo = 0, hi = 0;
     size_t off = 0;  // into the ModUp table
@@ -135,6 +144,26 @@ struct Ctx {
     CtPtr matmul(const CtData& A, const CtData& B, int h);
     std::vector<CtPtr> matmul_batch(const std::vector<const CtData*>& A, const std::vector<const CtData*>& B,
                                     const std::vector<int>& h);
+    int max_group = 32;
+
+    // lockstep group operations (group.hip)
+    Grp g_new(int B, int level, int deg, const std::vector<double>& sc);
+    Grp g_gather(const std::vector<const CtData*>& v, int level);
+    std::vector<CtPtr> g_scatter(const Grp& g);
+    Grp g_drop(const Grp& a, int level);
+    void g_add_into(Grp& acc, const Grp& t);
+    std::shared_ptr<DBuf> g_lift(const Grp& a, int poly);
+    void g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, const u64* add0, const u64* add1,
+                    int64_t add_cs, u64* out0, u64* out1, int64_t out_cs);
+    Grp g_rotate_from_lift(const Grp& a, const u64* lift, int64_t k);
+    Grp g_rotate(const Grp& a, int64_t k);
+    Grp g_mask_sum(const std::vector<std::pair<const Grp*, const u64*>>& terms, double mask_scale);
+    Grp g_rescale(const Grp& a);
+    Grp g_tensor(const Grp& a, const Grp& b);
+    void g_tensor_acc(Grp& acc, const Grp& a, const Grp& b);
+    Grp g_relin(const Grp& a);
+    std::vector<CtPtr> matmul_group(const std::vector<const CtData*>& A, const std::vector<const CtData*>& B, int h,
+                                    int lvl);
 
     CtPtr mul_rs(const CtData& x, const CtData& y);
     CtPtr eval_gd(const CtData& x, int d);

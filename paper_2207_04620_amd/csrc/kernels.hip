@@ -92,10 +92,121 @@ std::string prof_report() {
 
 // ------------------------------------------------------------------ NTT
 // Forward transform: Cooley-Tukey with the psi twist merged into the twiddles
-// (Longa-Naehrig 2016), bit-reversed output: stage m (1..N/2), butterfly group i
-// uses psi^(bitrev(m+i)).  N = N1 * N2: the first log N1 stages pair elements a
-// multiple of N2 apart (column pass), the last log N2 stages stay inside contiguous
-// rows of N2 elements (row pass).  Each block stages NTT_E elements in LDS.
+// (Longa-Naehrig 2016), bit-reversed output: stage s (m = 2^s butterfly groups),
+// group i uses psi^(bitrev(m+i)).  N = N1 * N2: the first log N1 stages pair elements
+// a multiple of N2 apart (column pass), the last log N2 stages stay inside contiguous
+// rows of N2 elements (row pass).  A block holds NTT_E = 2048 elements: one row, or
+// NTT_E/N1 columns.  Each thread keeps 8 elements in registers and runs up to three
+// stages on them (a radix-8 round) between LDS exchanges; butterflies use Harvey's
+// lazy reduction (values in [0, 4q) forward, [0, 2q) inverse; q < 2^61).
+//
+// Element (transform u, position j) of a block lives at LDS address j * T + u where
+// T is the number of transforms in the block (1 for rows, NTT_E / N1 for columns);
+// the twiddle index of stage s at position j is (X << s) + (j >> (L - s)) with X = 1
+// for the column pass and X = N1 + row for the row pass.
+
+__device__ __forceinline__ u64 red4(u64 x, u64 q2) { return x >= q2 ? x - q2 : x; }
+
+// stages s0 .. s0+R-1 of a length-2^L forward transform; each thread owns 8/2^R groups
+template <int R>
+__device__ __forceinline__ void fwd_round(u64* s, int L, int s0, int logT, u64 X, const u64* __restrict__ W,
+                                          const u64* __restrict__ Ws, u64 q) {
+    constexpr int G = 1 << R, NG = 8 / G;
+    const int ld = L - s0 - R, d = 1 << ld, T = 1 << logT;
+    const u64 q2 = 2 * q;
+#pragma unroll
+    for (int gg = 0; gg < NG; ++gg) {
+        const int g = gg * TPB + threadIdx.x;
+        const int u = g & (T - 1), gi = g >> logT;
+        const int base = ((gi >> ld) << (ld + R)) + (gi & (d - 1));
+        u64 x[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) x[k] = s[((base + k * d) << logT) + u];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int st = s0 + r, half = G >> (r + 1);
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                if (k & half) continue;
+                const int j = base + k * d;
+                const int idx = (int)(X << st) + (j >> (L - st));
+                const u64 U = red4(x[k], q2);
+                const u64 V = mul_shoup_lazy(x[k + half], W[idx], Ws[idx], q);
+                x[k] = U + V;
+                x[k + half] = U - V + q2;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) s[((base + k * d) << logT) + u] = x[k];
+    }
+}
+
+// stages s0 .. s0-R+1 (descending) of a length-2^L inverse transform
+template <int R>
+__device__ __forceinline__ void inv_round(u64* s, int L, int s0, int logT, u64 X, const u64* __restrict__ W,
+                                          const u64* __restrict__ Ws, u64 q) {
+    constexpr int G = 1 << R, NG = 8 / G;
+    // the round covers stages s0-R+1 .. s0; its smallest distance belongs to stage s0
+    const int ld = L - s0 - 1, d = 1 << ld, T = 1 << logT;
+    const u64 q2 = 2 * q;
+#pragma unroll
+    for (int gg = 0; gg < NG; ++gg) {
+        const int g = gg * TPB + threadIdx.x;
+        const int u = g & (T - 1), gi = g >> logT;
+        const int base = ((gi >> ld) << (ld + R)) + (gi & (d - 1));
+        u64 x[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) x[k] = s[((base + k * d) << logT) + u];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int st = s0 - r, half = 1 << r;
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                if (k & half) continue;
+                const int j = base + k * d;
+                const int idx = (int)(X << st) + (j >> (L - st));
+                const u64 U = x[k], V = x[k + half];
+                x[k] = red4(U + V, q2);
+                x[k + half] = mul_shoup_lazy(U - V + q2, W[idx], Ws[idx], q);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) s[((base + k * d) << logT) + u] = x[k];
+    }
+}
+
+__device__ __forceinline__ void fwd_all(u64* s, int L, int logT, u64 X, const u64* W, const u64* Ws, u64 q) {
+    int st = 0;
+    while (L - st >= 3) {
+        fwd_round<3>(s, L, st, logT, X, W, Ws, q);
+        __syncthreads();
+        st += 3;
+    }
+    if (L - st == 2) {
+        fwd_round<2>(s, L, st, logT, X, W, Ws, q);
+        __syncthreads();
+    } else if (L - st == 1) {
+        fwd_round<1>(s, L, st, logT, X, W, Ws, q);
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void inv_all(u64* s, int L, int logT, u64 X, const u64* W, const u64* Ws, u64 q) {
+    int st = L - 1;  // highest stage first
+    while (st + 1 >= 3) {
+        inv_round<3>(s, L, st, logT, X, W, Ws, q);
+        __syncthreads();
+        st -= 3;
+    }
+    if (st + 1 == 2) {
+        inv_round<2>(s, L, st, logT, X, W, Ws, q);
+        __syncthreads();
+    } else if (st + 1 == 1) {
+        inv_round<1>(s, L, st, logT, X, W, Ws, q);
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(TPB) void k_ntt_fwd_cols(DevTables T, Jobs J) {
     __shared__ u64 s[NTT_E];
     const int N = 1 << T.log_n, L1 = T.n1_log, N2 = N >> L1;
@@ -109,19 +220,8 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_cols(DevTables T, Jobs J) {
     const int c0 = blockIdx.x * C;
     for (int e = threadIdx.x; e < NTT_E; e += TPB) s[e] = a[(int64_t)(e >> logC) * N2 + c0 + (e & (C - 1))];
     __syncthreads();
-    for (int st = 0; st < L1; st++) {
-        const int m = 1 << st, ltk = L1 - st - 1, tk = 1 << ltk;
-        for (int b = threadIdx.x; b < NTT_E / 2; b += TPB) {
-            const int cc = b & (C - 1), bb = b >> logC;
-            const int i = bb >> ltk, j = bb & (tk - 1);
-            const int k1 = (i << (ltk + 1)) + j, k2 = k1 + tk;
-            const u64 U = s[(k1 << logC) + cc];
-            const u64 V = mul_shoup(s[(k2 << logC) + cc], W[m + i], Ws[m + i], q);
-            s[(k1 << logC) + cc] = add_mod(U, V, q);
-            s[(k2 << logC) + cc] = sub_mod(U, V, q);
-        }
-        __syncthreads();
-    }
+    fwd_all(s, L1, logC, 1, W, Ws, q);
+    // output stays lazy in [0, 4q) for the row pass
     for (int e = threadIdx.x; e < NTT_E; e += TPB) a[(int64_t)(e >> logC) * N2 + c0 + (e & (C - 1))] = s[e];
 }
 
@@ -132,25 +232,32 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J) {
     const int r = blockIdx.x;
     u64* a = J.base + c * J.cstride + (int64_t)J.off[k] * N + (int64_t)r * N2;
     const int mi = J.mod[k];
-    const u64 q = T.mods[mi].q;
+    const u64 q = T.mods[mi].q, q2 = 2 * q;
     const u64* W = T.psi + (int64_t)mi * N;
     const u64* Ws = T.psi_sh + (int64_t)mi * N;
     for (int e = threadIdx.x; e < N2; e += TPB) s[e] = a[e];
     __syncthreads();
-    for (int st = 0; st < L2; st++) {
-        const int mp = 1 << st, lt = L2 - st - 1, t = 1 << lt;
-        for (int b = threadIdx.x; b < N2 / 2; b += TPB) {
-            const int i = b >> lt, j = b & (t - 1);
-            const int j1 = (i << (lt + 1)) + j;
-            const int idx = mp * (N1 + r) + i;
-            const u64 U = s[j1];
-            const u64 V = mul_shoup(s[j1 + t], W[idx], Ws[idx], q);
-            s[j1] = add_mod(U, V, q);
-            s[j1 + t] = sub_mod(U, V, q);
+    if (N2 == NTT_E) {
+        fwd_all(s, L2, 0, (u64)(N1 + r), W, Ws, q);
+    } else {  // small rings: plain radix-2 stages (N2 < 2048 only when N < 2048)
+        for (int st = 0; st < L2; st++) {
+            const int lt = L2 - st - 1, t = 1 << lt;
+            for (int b = threadIdx.x; b < N2 / 2; b += TPB) {
+                const int i = b >> lt, j = b & (t - 1);
+                const int j1 = (i << (lt + 1)) + j;
+                const int idx = (1 << st) * (N1 + r) + i;
+                const u64 U = red4(s[j1], q2);
+                const u64 V = mul_shoup_lazy(s[j1 + t], W[idx], Ws[idx], q);
+                s[j1] = U + V;
+                s[j1 + t] = U - V + q2;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
-    for (int e = threadIdx.x; e < N2; e += TPB) a[e] = s[e];
+    for (int e = threadIdx.x; e < N2; e += TPB) {
+        u64 v = red4(s[e], q2);
+        a[e] = v >= q ? v - q : v;
+    }
 }
 
 // Inverse transform: Gentleman-Sande, bit-reversed input, natural output, then N^-1.
@@ -162,27 +269,31 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_rows(DevTables T, Jobs J) {
     u64* a = J.base + c * J.cstride + (int64_t)J.off[k] * N + (int64_t)r * N2;
     const int mi = J.mod[k];
     const ModP mp_ = T.mods[mi];
-    const u64 q = mp_.q;
+    const u64 q = mp_.q, q2 = 2 * q;
     const u64* W = T.ipsi + (int64_t)mi * N;
     const u64* Ws = T.ipsi_sh + (int64_t)mi * N;
     for (int e = threadIdx.x; e < N2; e += TPB) s[e] = a[e];
     __syncthreads();
-    for (int st = L2 - 1; st >= 0; st--) {
-        const int mp = 1 << st, lt = L2 - st - 1, t = 1 << lt;
-        for (int b = threadIdx.x; b < N2 / 2; b += TPB) {
-            const int i = b >> lt, j = b & (t - 1);
-            const int j1 = (i << (lt + 1)) + j;
-            const int idx = mp * (N1 + r) + i;
-            const u64 U = s[j1], V = s[j1 + t];
-            s[j1] = add_mod(U, V, q);
-            s[j1 + t] = mul_shoup(sub_mod(U, V, q), W[idx], Ws[idx], q);
+    if (N2 == NTT_E) {
+        inv_all(s, L2, 0, (u64)(N1 + r), W, Ws, q);
+    } else {
+        for (int st = L2 - 1; st >= 0; st--) {
+            const int lt = L2 - st - 1, t = 1 << lt;
+            for (int b = threadIdx.x; b < N2 / 2; b += TPB) {
+                const int i = b >> lt, j = b & (t - 1);
+                const int j1 = (i << (lt + 1)) + j;
+                const int idx = (1 << st) * (N1 + r) + i;
+                const u64 U = s[j1], V = s[j1 + t];
+                s[j1] = red4(U + V, q2);
+                s[j1 + t] = mul_shoup_lazy(U - V + q2, W[idx], Ws[idx], q);
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     if (L1 == 0) {
         for (int e = threadIdx.x; e < N2; e += TPB) a[e] = mul_shoup(s[e], mp_.ninv, mp_.ninv_sh, q);
     } else {
-        for (int e = threadIdx.x; e < N2; e += TPB) a[e] = s[e];
+        for (int e = threadIdx.x; e < N2; e += TPB) a[e] = s[e];  // lazy in [0, 2q)
     }
 }
 
@@ -200,18 +311,7 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_cols(DevTables T, Jobs J) {
     const int c0 = blockIdx.x * C;
     for (int e = threadIdx.x; e < NTT_E; e += TPB) s[e] = a[(int64_t)(e >> logC) * N2 + c0 + (e & (C - 1))];
     __syncthreads();
-    for (int st = L1 - 1; st >= 0; st--) {
-        const int m = 1 << st, ltk = L1 - st - 1, tk = 1 << ltk;
-        for (int b = threadIdx.x; b < NTT_E / 2; b += TPB) {
-            const int cc = b & (C - 1), bb = b >> logC;
-            const int i = bb >> ltk, j = bb & (tk - 1);
-            const int k1 = (i << (ltk + 1)) + j, k2 = k1 + tk;
-            const u64 U = s[(k1 << logC) + cc], V = s[(k2 << logC) + cc];
-            s[(k1 << logC) + cc] = add_mod(U, V, q);
-            s[(k2 << logC) + cc] = mul_shoup(sub_mod(U, V, q), W[m + i], Ws[m + i], q);
-        }
-        __syncthreads();
-    }
+    inv_all(s, L1, logC, 1, W, Ws, q);
     for (int e = threadIdx.x; e < NTT_E; e += TPB)
         a[(int64_t)(e >> logC) * N2 + c0 + (e & (C - 1))] = mul_shoup(s[e], mp_.ninv, mp_.ninv_sh, q);
 }
@@ -244,39 +344,52 @@ void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st)
 // Centered fast base conversion (Bajard et al. 2016 / Halevi-Polyakov-Shoup 2019 in
 // its centered form): y_s = centered([x_s (D/q_s)^-1]_{q_s}),
 // out_t = sum_s y_s (D/q_s) mod q_t, accumulated in 128 bits and reduced once (REDC).
+template <int NS>
 __global__ __launch_bounds__(TPB) void k_baseconv(DevTables T, ConvDesc D) {
     const int N = 1 << T.log_n;
     const int i = blockIdx.x * TPB + threadIdx.x;
-    const int p = blockIdx.z;
+    const int p = blockIdx.z % D.npoly, c = blockIdx.z / D.npoly;
     const int t0 = blockIdx.y * 8, t1 = min(D.nt, t0 + 8);
     if (i >= N) return;
-    u64 y[HE_MAXSRC];
-    bool neg[HE_MAXSRC];
-    const u64* src = D.src + p * D.src_pstride;
-    for (int s = 0; s < D.ns; s++) {
+    u64 y[NS];
+    bool neg[NS];
+    const u64* src = D.src + c * D.src_cstride + p * D.src_pstride;
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
         const ModP m = T.mods[D.smod[s]];
         const u64 v = mul_shoup(src[(int64_t)s * N + i], D.hinv[s], D.hinv_sh[s], m.q);
         y[s] = v;
         neg[s] = v > m.half;
     }
-    u64* dst = D.dst + p * D.dst_pstride;
+    u64* dst = D.dst + c * D.dst_cstride + p * D.dst_pstride;
     for (int t = t0; t < t1; t++) {
         const ModP m = T.mods[D.dmod[t]];
+        const u64* e = D.tab + (int64_t)D.tcol[t] * 2;
         Acc128 acc = {0, 0};
-        for (int s = 0; s < D.ns; s++) {
-            const u64* e = D.tab + ((int64_t)s * D.tab_ld + D.tcol[t]) * 2;
-            mac128(acc, y[s], e[0]);
-            if (neg[s]) add128(acc, e[1]);
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            const u64* es = e + (int64_t)s * D.tab_ld * 2;
+            mac128(acc, y[s], es[0]);
+            if (neg[s]) add128(acc, es[1]);
         }
         dst[(int64_t)D.doff[t] * N + i] = redc(acc.lo, acc.hi, m.q, m.qninv);
     }
 }
 
 void launch_baseconv(const DevTables& T, const ConvDesc& D, hipStream_t st) {
-    ProfScope prof_(PK_BASECONV, (double)(D.ns + D.nt) * D.npoly * 8.0 * (1 << T.log_n), st);
+    ProfScope prof_(PK_BASECONV, (double)(D.ns + D.nt) * D.npoly * D.nct * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
-    dim3 grid(ceil_div(N, TPB), ceil_div(D.nt, 8), D.npoly);
-    hipLaunchKernelGGL(k_baseconv, grid, dim3(TPB), 0, st, T, D);
+    dim3 grid(ceil_div(N, TPB), ceil_div(D.nt, 8), D.npoly * D.nct);
+    switch (D.ns) {
+        case 1: hipLaunchKernelGGL(k_baseconv<1>, grid, dim3(TPB), 0, st, T, D); break;
+        case 2: hipLaunchKernelGGL(k_baseconv<2>, grid, dim3(TPB), 0, st, T, D); break;
+        case 3: hipLaunchKernelGGL(k_baseconv<3>, grid, dim3(TPB), 0, st, T, D); break;
+        case 4: hipLaunchKernelGGL(k_baseconv<4>, grid, dim3(TPB), 0, st, T, D); break;
+        case 5: hipLaunchKernelGGL(k_baseconv<5>, grid, dim3(TPB), 0, st, T, D); break;
+        case 6: hipLaunchKernelGGL(k_baseconv<6>, grid, dim3(TPB), 0, st, T, D); break;
+        case 7: hipLaunchKernelGGL(k_baseconv<7>, grid, dim3(TPB), 0, st, T, D); break;
+        default: hipLaunchKernelGGL(k_baseconv<8>, grid, dim3(TPB), 0, st, T, D); break;
+    }
 }
 
 // ------------------------------------------------------------------ ChaCha20 samplers
@@ -369,13 +482,17 @@ void launch_sample(const DevTables& T, const Jobs& J, const SampleArgs& A, hipSt
 }
 
 // ------------------------------------------------------------------ element-wise
-__global__ __launch_bounds__(TPB) void k_ew(DevTables T, ModMap mm, int nl, u64* out, int64_t out_ps,
-                                            const u64* a, int64_t a_ps, const u64* b, int64_t b_ps, int op) {
+__global__ __launch_bounds__(TPB) void k_ew(DevTables T, ModMap mm, int npoly, u64* out, int64_t out_ps,
+                                            const u64* a, int64_t a_ps, const u64* b, int64_t b_ps, int op,
+                                            int64_t out_cs, int64_t a_cs, int64_t b_cs) {
     const int N = 1 << T.log_n;
     const int i = blockIdx.x * TPB + threadIdx.x;
-    const int l = blockIdx.y, p = blockIdx.z;
+    const int l = blockIdx.y, p = blockIdx.z % npoly, c = blockIdx.z / npoly;
     const ModP m = T.mods[mm(l)];
     const int64_t o = (int64_t)l * N + i;
+    out += c * out_cs;
+    a += c * a_cs;
+    b += c * b_cs;
     const u64 x = a[p * a_ps + o], y = b[p * b_ps + o];
     u64 r;
     switch (op) {
@@ -388,11 +505,13 @@ __global__ __launch_bounds__(TPB) void k_ew(DevTables T, ModMap mm, int nl, u64*
 }
 
 void launch_ew(const DevTables& T, ModMap mm, int nl, int npoly, u64* out, int64_t out_ps, const u64* a,
-               int64_t a_ps, const u64* b, int64_t b_ps, int op, hipStream_t st) {
-    ProfScope prof_(PK_EW, 3.0 * nl * npoly * 8.0 * (1 << T.log_n), st);
+               int64_t a_ps, const u64* b, int64_t b_ps, int op, hipStream_t st, int nct, int64_t out_cs,
+               int64_t a_cs, int64_t b_cs) {
+    ProfScope prof_(PK_EW, 3.0 * nl * npoly * nct * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
-    dim3 grid(ceil_div(N, TPB), nl, npoly);
-    hipLaunchKernelGGL(k_ew, grid, dim3(TPB), 0, st, T, mm, nl, out, out_ps, a, a_ps, b, b_ps, op);
+    dim3 grid(ceil_div(N, TPB), nl, npoly * nct);
+    hipLaunchKernelGGL(k_ew, grid, dim3(TPB), 0, st, T, mm, npoly, out, out_ps, a, a_ps, b, b_ps, op, out_cs, a_cs,
+                       b_cs);
 }
 
 __global__ __launch_bounds__(TPB) void k_mul_const(DevTables T, ModMap mm, u64* out, int64_t out_ps,
@@ -422,20 +541,20 @@ __device__ __forceinline__ int perm_g(int j, u64 g, int log_n) {
     return (int)brev_bits((e2 - 1) >> 1, log_n);
 }
 
-__global__ __launch_bounds__(TPB) void k_automorph(DevTables T, u64* out, int64_t out_ps, const u64* in,
-                                                   int64_t in_ps, u64 g) {
+__global__ __launch_bounds__(TPB) void k_automorph(DevTables T, int npoly, u64* out, int64_t out_ps, const u64* in,
+                                                   int64_t in_ps, u64 g, int64_t out_cs, int64_t in_cs) {
     const int N = 1 << T.log_n;
     const int i = blockIdx.x * TPB + threadIdx.x;
-    const int l = blockIdx.y, p = blockIdx.z;
-    out[p * out_ps + (int64_t)l * N + i] = in[p * in_ps + (int64_t)l * N + perm_g(i, g, T.log_n)];
+    const int l = blockIdx.y, p = blockIdx.z % npoly, c = blockIdx.z / npoly;
+    out[c * out_cs + p * out_ps + (int64_t)l * N + i] = in[c * in_cs + p * in_ps + (int64_t)l * N + perm_g(i, g, T.log_n)];
 }
 
 void launch_automorph(const DevTables& T, int nl, int npoly, u64* out, int64_t out_ps, const u64* in,
-                      int64_t in_ps, u64 g, hipStream_t st) {
-    ProfScope prof_(PK_AUTOMORPH, 2.0 * nl * npoly * 8.0 * (1 << T.log_n), st);
+                      int64_t in_ps, u64 g, hipStream_t st, int nct, int64_t out_cs, int64_t in_cs) {
+    ProfScope prof_(PK_AUTOMORPH, 2.0 * nl * npoly * nct * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
-    dim3 grid(ceil_div(N, TPB), nl, npoly);
-    hipLaunchKernelGGL(k_automorph, grid, dim3(TPB), 0, st, T, out, out_ps, in, in_ps, g);
+    dim3 grid(ceil_div(N, TPB), nl, npoly * nct);
+    hipLaunchKernelGGL(k_automorph, grid, dim3(TPB), 0, st, T, npoly, out, out_ps, in, in_ps, g, out_cs, in_cs);
 }
 
 __global__ __launch_bounds__(TPB) void k_to_mont(DevTables T, ModMap mm, u64* x, int64_t ps) {
@@ -479,6 +598,8 @@ void launch_swk_finish(const DevTables& T, int M, u64* b, const u64* a, const u6
 // Hybrid key switching (Han-Ki 2020): inner product of the lifted digits with the
 // switching key over Q_l and P.  The automorphism of a rotation is fused as a
 // gather: the digits of sigma_g(c1) are the permuted digits of c1 (hoisting).
+// The key values of one (limb, coefficient) are loaded once and reused for every
+// ciphertext of the group: a switching key crosses HBM once per launch.
 __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
     const int N = 1 << T.log_n;
     const int i = blockIdx.x * TPB + threadIdx.x;
@@ -486,32 +607,44 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
     const int mi = D.mod[t];
     const ModP m = T.mods[mi];
     const int src = D.g == 1 ? i : perm_g(i, D.g, T.log_n);
-    Acc128 a0 = {0, 0}, a1 = {0, 0};
+    u64 kb[HE_MAXSRC], ka[HE_MAXSRC];
     for (int j = 0; j < D.beta; j++) {
-        const u64 x = D.lift[((int64_t)j * D.ne + t) * N + src];
-        const u64* kb = D.key + (((int64_t)j * 2 + 0) * D.M + mi) * N;
-        const u64* ka = D.key + (((int64_t)j * 2 + 1) * D.M + mi) * N;
-        mac128(a0, x, kb[i]);
-        mac128(a1, x, ka[i]);
+        kb[j] = D.key[(((int64_t)j * 2 + 0) * D.M + mi) * N + i];
+        ka[j] = D.key[(((int64_t)j * 2 + 1) * D.M + mi) * N + i];
     }
-    D.u[(int64_t)t * N + i] = redc(a0.lo, a0.hi, m.q, m.qninv);
-    D.u[((int64_t)D.ne + t) * N + i] = redc(a1.lo, a1.hi, m.q, m.qninv);
+    for (int c = 0; c < D.nct; c++) {
+        const u64* lift = D.lift + c * D.lift_cs;
+        Acc128 a0 = {0, 0}, a1 = {0, 0};
+        for (int j = 0; j < D.beta; j++) {
+            const u64 x = lift[((int64_t)j * D.ne + t) * N + src];
+            mac128(a0, x, kb[j]);
+            mac128(a1, x, ka[j]);
+        }
+        u64* u = D.u + c * D.u_cs;
+        u[(int64_t)t * N + i] = redc(a0.lo, a0.hi, m.q, m.qninv);
+        u[((int64_t)D.ne + t) * N + i] = redc(a1.lo, a1.hi, m.q, m.qninv);
+    }
 }
 
 void launch_inner_product(const DevTables& T, const IpDesc& D, hipStream_t st) {
-    ProfScope prof_(PK_INNER, (double)D.ne * (3.0 * D.beta + 2.0) * 8.0 * (1 << T.log_n), st);
+    ProfScope prof_(PK_INNER, (double)D.ne * (2.0 * D.beta + D.nct * (D.beta + 2.0)) * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), D.ne);
     hipLaunchKernelGGL(k_inner_product, grid, dim3(TPB), 0, st, T, D);
 }
 
-__global__ __launch_bounds__(TPB) void k_moddown_combine(DevTables T, const u64* u, int64_t u_ps, const u64* conv,
-                                                         int64_t conv_ps, const u64* pinv, const u64* pinv_sh,
-                                                         const u64* add, int64_t add_ps, u64* out,
-                                                         int64_t out_ps) {
+__global__ __launch_bounds__(TPB) void k_moddown_combine(DevTables T, int npoly, const u64* u, int64_t u_ps,
+                                                         const u64* conv, int64_t conv_ps, const u64* pinv,
+                                                         const u64* pinv_sh, const u64* add, int64_t add_ps,
+                                                         u64* out, int64_t out_ps, int64_t u_cs, int64_t conv_cs,
+                                                         int64_t add_cs, int64_t out_cs) {
     const int N = 1 << T.log_n;
     const int i = blockIdx.x * TPB + threadIdx.x;
-    const int l = blockIdx.y, p = blockIdx.z;
+    const int l = blockIdx.y, p = blockIdx.z % npoly, c = blockIdx.z / npoly;
+    u += c * u_cs;
+    conv += c * conv_cs;
+    if (add) add += c * add_cs;
+    out += c * out_cs;
     const u64 q = T.mods[l].q;
     const int64_t o = (int64_t)l * N + i;
     u64 v = mul_shoup(sub_mod(u[p * u_ps + o], conv[p * conv_ps + o], q), pinv[l], pinv_sh[l], q);
@@ -521,12 +654,13 @@ __global__ __launch_bounds__(TPB) void k_moddown_combine(DevTables T, const u64*
 
 void launch_moddown_combine(const DevTables& T, int nl, int npoly, const u64* u, int64_t u_ps, const u64* conv,
                             int64_t conv_ps, const u64* pinv, const u64* pinv_sh, const u64* add, int64_t add_ps,
-                            u64* out, int64_t out_ps, hipStream_t st) {
-    ProfScope prof_(PK_MODDOWN, (add ? 4.0 : 3.0) * nl * npoly * 8.0 * (1 << T.log_n), st);
+                            u64* out, int64_t out_ps, hipStream_t st, int nct, int64_t u_cs, int64_t conv_cs,
+                            int64_t add_cs, int64_t out_cs) {
+    ProfScope prof_(PK_MODDOWN, (add ? 4.0 : 3.0) * nl * npoly * nct * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
-    dim3 grid(ceil_div(N, TPB), nl, npoly);
-    hipLaunchKernelGGL(k_moddown_combine, grid, dim3(TPB), 0, st, T, u, u_ps, conv, conv_ps, pinv, pinv_sh, add,
-                       add_ps, out, out_ps);
+    dim3 grid(ceil_div(N, TPB), nl, npoly * nct);
+    hipLaunchKernelGGL(k_moddown_combine, grid, dim3(TPB), 0, st, T, npoly, u, u_ps, conv, conv_ps, pinv, pinv_sh,
+                       add, add_ps, out, out_ps, u_cs, conv_cs, add_cs, out_cs);
 }
 
 // ------------------------------------------------------------------ rescale
@@ -534,7 +668,7 @@ __global__ __launch_bounds__(TPB) void k_rescale_spread(DevTables T, const u64* 
                                                         u64* tmp, int64_t tmp_ps) {
     const int N = 1 << T.log_n;
     const int i = blockIdx.x * TPB + threadIdx.x;
-    const int l = blockIdx.y, p = blockIdx.z;
+    const int l = blockIdx.y, p = blockIdx.z;  // p runs over (ciphertext, poly) pairs
     const ModP ml = T.mods[last_mod], m = T.mods[l];
     const u64 r = last[p * last_ps + i];
     u64 v = reduce64(r, m);
@@ -550,33 +684,39 @@ void launch_rescale_spread(const DevTables& T, int nl_out, int npoly, const u64*
     hipLaunchKernelGGL(k_rescale_spread, grid, dim3(TPB), 0, st, T, last, last_ps, last_mod, tmp, tmp_ps);
 }
 
-__global__ __launch_bounds__(TPB) void k_rescale_combine(DevTables T, const u64* c, int64_t c_ps, const u64* tmp,
-                                                         int64_t tmp_ps, const u64* qinv, const u64* qinv_sh,
-                                                         u64* out, int64_t out_ps) {
+__global__ __launch_bounds__(TPB) void k_rescale_combine(DevTables T, int npoly, const u64* c, int64_t c_ps,
+                                                         const u64* tmp, int64_t tmp_ps, const u64* qinv,
+                                                         const u64* qinv_sh, u64* out, int64_t out_ps, int64_t c_cs,
+                                                         int64_t tmp_cs, int64_t out_cs) {
     const int N = 1 << T.log_n;
     const int i = blockIdx.x * TPB + threadIdx.x;
-    const int l = blockIdx.y, p = blockIdx.z;
+    const int l = blockIdx.y, p = blockIdx.z % npoly, ct = blockIdx.z / npoly;
     const u64 q = T.mods[l].q;
     const int64_t o = (int64_t)l * N + i;
-    out[p * out_ps + o] = mul_shoup(sub_mod(c[p * c_ps + o], tmp[p * tmp_ps + o], q), qinv[l], qinv_sh[l], q);
+    out[ct * out_cs + p * out_ps + o] =
+        mul_shoup(sub_mod(c[ct * c_cs + p * c_ps + o], tmp[ct * tmp_cs + p * tmp_ps + o], q), qinv[l], qinv_sh[l], q);
 }
 
 void launch_rescale_combine(const DevTables& T, int nl_out, int npoly, const u64* c, int64_t c_ps, const u64* tmp,
                             int64_t tmp_ps, const u64* qinv, const u64* qinv_sh, u64* out, int64_t out_ps,
-                            hipStream_t st) {
-    ProfScope prof_(PK_RS_COMBINE, 3.0 * nl_out * npoly * 8.0 * (1 << T.log_n), st);
+                            hipStream_t st, int nct, int64_t c_cs, int64_t tmp_cs, int64_t out_cs) {
+    ProfScope prof_(PK_RS_COMBINE, 3.0 * nl_out * npoly * nct * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
-    dim3 grid(ceil_div(N, TPB), nl_out, npoly);
-    hipLaunchKernelGGL(k_rescale_combine, grid, dim3(TPB), 0, st, T, c, c_ps, tmp, tmp_ps, qinv, qinv_sh, out,
-                       out_ps);
+    dim3 grid(ceil_div(N, TPB), nl_out, npoly * nct);
+    hipLaunchKernelGGL(k_rescale_combine, grid, dim3(TPB), 0, st, T, npoly, c, c_ps, tmp, tmp_ps, qinv, qinv_sh, out,
+                       out_ps, c_cs, tmp_cs, out_cs);
 }
 
 // ------------------------------------------------------------------ products
 __global__ __launch_bounds__(TPB) void k_tensor(DevTables T, const u64* a, int64_t a_ps, const u64* b,
-                                                int64_t b_ps, u64* d, int64_t d_ps, int acc) {
+                                                int64_t b_ps, u64* d, int64_t d_ps, int acc, int64_t a_cs,
+                                                int64_t b_cs, int64_t d_cs) {
     const int N = 1 << T.log_n;
     const int i = blockIdx.x * TPB + threadIdx.x;
-    const int l = blockIdx.y;
+    const int l = blockIdx.y, c = blockIdx.z;
+    a += c * a_cs;
+    b += c * b_cs;
+    d += c * d_cs;
     const ModP m = T.mods[l];
     const int64_t o = (int64_t)l * N + i;
     const u64 a0 = a[o], a1 = a[a_ps + o];
@@ -599,34 +739,41 @@ __global__ __launch_bounds__(TPB) void k_tensor(DevTables T, const u64* a, int64
 }
 
 void launch_tensor(const DevTables& T, int nl, const u64* a, int64_t a_ps, const u64* b, int64_t b_ps, u64* d,
-                   int64_t d_ps, int acc, hipStream_t st) {
-    ProfScope prof_(PK_TENSOR, (acc ? 10.0 : 7.0) * nl * 8.0 * (1 << T.log_n), st);
+                   int64_t d_ps, int acc, hipStream_t st, int nct, int64_t a_cs, int64_t b_cs, int64_t d_cs) {
+    ProfScope prof_(PK_TENSOR, (acc ? 10.0 : 7.0) * nl * nct * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
-    dim3 grid(ceil_div(N, TPB), nl);
-    hipLaunchKernelGGL(k_tensor, grid, dim3(TPB), 0, st, T, a, a_ps, b, b_ps, d, d_ps, acc);
+    dim3 grid(ceil_div(N, TPB), nl, nct);
+    hipLaunchKernelGGL(k_tensor, grid, dim3(TPB), 0, st, T, a, a_ps, b, b_ps, d, d_ps, acc, a_cs, b_cs, d_cs);
 }
 
 // sum of up to 16 (ciphertext limb x mask) products, one REDC per output
-__global__ __launch_bounds__(TPB) void k_mask_mac(DevTables T, MacDesc D, u64* out, int64_t out_ps, int acc) {
+// masks are shared by every ciphertext of the group: loaded once, reused per member
+__global__ __launch_bounds__(TPB) void k_mask_mac(DevTables T, MacDesc D, u64* out, int64_t out_ps, int acc,
+                                                  int64_t out_cs) {
     const int N = 1 << T.log_n;
     const int i = blockIdx.x * TPB + threadIdx.x;
     const int l = blockIdx.y, p = blockIdx.z;
     const ModP m = T.mods[l];
     const int64_t o = (int64_t)l * N + i;
-    Acc128 s = {0, 0};
-    for (int r = 0; r < D.nterm; r++) mac128(s, D.in[r][p * D.in_ps[r] + o], D.mask[r][o]);
-    // D.nterm * q^2 < q 2^64 for nterm <= 16 and q < 2^60
-    u64 v = redc(s.lo, s.hi, m.q, m.qninv);
-    if (acc) v = add_mod(v, out[p * out_ps + o], m.q);
-    out[p * out_ps + o] = v;
+    u64 mk[16];
+    for (int r = 0; r < D.nterm; r++) mk[r] = D.mask[r][o];
+    for (int c = 0; c < D.nct; c++) {
+        Acc128 s = {0, 0};
+        for (int r = 0; r < D.nterm; r++) mac128(s, D.in[r][c * D.in_cs[r] + p * D.in_ps[r] + o], mk[r]);
+        // nterm * q^2 < q 2^64 for nterm <= 16 and q < 2^60
+        u64 v = redc(s.lo, s.hi, m.q, m.qninv);
+        u64* dst = out + c * out_cs + p * out_ps + o;
+        if (acc) v = add_mod(v, *dst, m.q);
+        *dst = v;
+    }
 }
 
 void launch_mask_mac(const DevTables& T, int nl, int npoly, const MacDesc& D, u64* out, int64_t out_ps, int acc,
-                     hipStream_t st) {
-    ProfScope prof_(PK_MASKMAC, ((2.0 * D.nterm + 1.0 + acc) * nl * npoly) * 8.0 * (1 << T.log_n), st);
+                     hipStream_t st, int64_t out_cs) {
+    ProfScope prof_(PK_MASKMAC, (D.nterm + D.nct * npoly * (D.nterm + 1.0 + acc)) * nl * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl, npoly);
-    hipLaunchKernelGGL(k_mask_mac, grid, dim3(TPB), 0, st, T, D, out, out_ps, acc);
+    hipLaunchKernelGGL(k_mask_mac, grid, dim3(TPB), 0, st, T, D, out, out_ps, acc, out_cs);
 }
 
 // ------------------------------------------------------------------ encrypt / decrypt

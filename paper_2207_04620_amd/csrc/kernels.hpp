@@ -55,6 +55,8 @@ struct ConvDesc {
     int64_t src_pstride;
     u64* dst;
     int64_t dst_pstride;
+    int64_t src_cstride = 0, dst_cstride = 0;  // ciphertext strides
+    int nct = 1;
     const u64* tab;
     int tab_ld;  // table row length: entry (s, col) at tab[(s * tab_ld + col) * 2]
     int ns, nt, npoly;
@@ -77,9 +79,11 @@ struct SampleArgs {
 // Key switch inner product: for ext limb t (prime mod[t]) and coefficient i,
 //  u0[t][i] = sum_j lift[j][t][perm_g(i)] kb[j][mod[t]][i], u1 likewise with ka.
 struct IpDesc {
-    const u64* lift;  // [beta][ne][N]
+    const u64* lift;  // [nct][beta][ne][N] (ciphertext stride lift_cs)
     const u64* key;   // [beta_top][2][M][N] Montgomery form
-    u64* u;           // [2][ne][N]
+    u64* u;           // [nct][2][ne][N] (ciphertext stride u_cs)
+    int64_t lift_cs, u_cs;
+    int nct;
     int ne, beta, M;
     u64 g;            // Galois element (1 = identity)
     uint8_t mod[HE_MAXT];
@@ -89,7 +93,9 @@ struct MacDesc {
     const u64* in[16];
     const u64* mask[16];
     int64_t in_ps[16];
+    int64_t in_cs[16];
     int nterm;
+    int nct;
 };
 
 enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_MUL_MONT = 2, EW_MUL_PLAIN = 3 };
@@ -110,13 +116,14 @@ void launch_sample(const DevTables& T, const Jobs& J, const SampleArgs& A, hipSt
 // out[p][i] = a[p][i] (op) b[p][i] over nl limbs (prime map mm) and npoly polys;
 // b_ps = 0 broadcasts one b polynomial to every poly
 void launch_ew(const DevTables& T, ModMap mm, int nl, int npoly, u64* out, int64_t out_ps, const u64* a,
-               int64_t a_ps, const u64* b, int64_t b_ps, int op, hipStream_t st);
+               int64_t a_ps, const u64* b, int64_t b_ps, int op, hipStream_t st, int nct = 1, int64_t out_cs = 0,
+               int64_t a_cs = 0, int64_t b_cs = 0);
 // out[p][i] = a[p][i] * c_i (Shoup constants in device arrays c, c_sh indexed by limb)
 void launch_mul_const(const DevTables& T, ModMap mm, int nl, int npoly, u64* out, int64_t out_ps, const u64* a,
                       int64_t a_ps, const u64* c, const u64* c_sh, hipStream_t st);
 // evaluation-domain automorphism: out[p][i][j] = in[p][i][perm_g(j)]
 void launch_automorph(const DevTables& T, int nl, int npoly, u64* out, int64_t out_ps, const u64* in,
-                      int64_t in_ps, u64 g, hipStream_t st);
+                      int64_t in_ps, u64 g, hipStream_t st, int nct = 1, int64_t out_cs = 0, int64_t in_cs = 0);
 void launch_to_mont(const DevTables& T, ModMap mm, int nl, int npoly, u64* x, int64_t ps, hipStream_t st);
 // b = e - a s (+ pmod_i s' on flagged limbs), all limbs of the full chain [M][N]
 void launch_swk_finish(const DevTables& T, int M, u64* b, const u64* a, const u64* e, const u64* s,
@@ -125,20 +132,22 @@ void launch_inner_product(const DevTables& T, const IpDesc& D, hipStream_t st);
 // out[p][t] = (u[p][t] - conv[p][t]) * Pinv_t (+ add[p][t])
 void launch_moddown_combine(const DevTables& T, int nl, int npoly, const u64* u, int64_t u_ps, const u64* conv,
                             int64_t conv_ps, const u64* pinv, const u64* pinv_sh, const u64* add, int64_t add_ps,
-                            u64* out, int64_t out_ps, hipStream_t st);
+                            u64* out, int64_t out_ps, hipStream_t st, int nct = 1, int64_t u_cs = 0,
+                            int64_t conv_cs = 0, int64_t add_cs = 0, int64_t out_cs = 0);
 // tmp[p][i] = centered(last[p]) mod q_i (coefficient form)
 void launch_rescale_spread(const DevTables& T, int nl_out, int npoly, const u64* last, int64_t last_ps,
                            int last_mod, u64* tmp, int64_t tmp_ps, hipStream_t st);
 // out[p][i] = (c[p][i] - tmp[p][i]) * qinv_i
 void launch_rescale_combine(const DevTables& T, int nl_out, int npoly, const u64* c, int64_t c_ps, const u64* tmp,
                             int64_t tmp_ps, const u64* qinv, const u64* qinv_sh, u64* out, int64_t out_ps,
-                            hipStream_t st);
+                            hipStream_t st, int nct = 1, int64_t c_cs = 0, int64_t tmp_cs = 0, int64_t out_cs = 0);
 // d0 (+)= a0 b0, d1 (+)= a0 b1 + a1 b0, d2 (+)= a1 b1
 void launch_tensor(const DevTables& T, int nl, const u64* a, int64_t a_ps, const u64* b, int64_t b_ps, u64* d,
-                   int64_t d_ps, int acc, hipStream_t st);
+                   int64_t d_ps, int acc, hipStream_t st, int nct = 1, int64_t a_cs = 0, int64_t b_cs = 0,
+                   int64_t d_cs = 0);
 // out[p][i] (+)= sum_r in_r[p][i] mask_r[i]  (masks in Montgomery form, compact [nl_top][N])
 void launch_mask_mac(const DevTables& T, int nl, int npoly, const MacDesc& D, u64* out, int64_t out_ps, int acc,
-                     hipStream_t st);
+                     hipStream_t st, int64_t out_cs = 0);
 // m = c0 + c1 s (+ c2 s^2); s, s2 plain evaluation form [M][N]
 void launch_dec_dot(const DevTables& T, int nl, int deg, const u64* c, int64_t c_ps, const u64* s, const u64* s2,
                     u64* m, hipStream_t st);
