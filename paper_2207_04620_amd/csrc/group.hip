@@ -139,7 +139,7 @@ std::shared_ptr<DBuf> Ctx::g_lift(const Grp& a, int poly) {
 
 // ModDown(<lift o sigma_g, key>) (+ add) into out, for every member
 void Ctx::g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, const u64* add0, const u64* add1,
-                     int64_t add_cs, u64* out0, u64* out1, int64_t out_cs) {
+                     int64_t add_cs, u64* out0, u64* out1, int64_t out_cs, u64 add_g) {
     const int nl = level + 1, ne = nl + n_p;
     const int beta = (int)mu[level].size();
     const int64_t ucs = 2 * (int64_t)ne * N, ccs = 2 * (int64_t)nl * N;
@@ -198,24 +198,33 @@ void Ctx::g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, c
         C.tcol[t] = (uint16_t)t;
     }
     launch_baseconv(T, C, stream);
-    {
-        Jobs J;
-        J.base = conv.p;
-        J.cstride = ccs;
-        J.nct = B;
-        J.n = 2 * nl;
-        for (int p = 0; p < 2; ++p)
-            for (int t = 0; t < nl; ++t) {
-                J.off[p * nl + t] = (uint16_t)(p * nl + t);
-                J.mod[p * nl + t] = (uint8_t)t;
-            }
-        launch_ntt(T, J, false, stream);
-    }
-    const u64* pinv = d_pinv->p;
-    launch_moddown_combine(T, nl, 1, u.p, 0, conv.p, 0, pinv, pinv + n_q, add0, 0, out0, 0, stream, B, ucs, ccs,
-                           add_cs, out_cs);
-    launch_moddown_combine(T, nl, 1, u.p + (size_t)ne * N, 0, conv.p + (size_t)nl * N, 0, pinv, pinv + n_q, add1, 0,
-                           out1, 0, stream, B, ucs, ccs, add_cs, out_cs);
+    Jobs J;
+    J.base = conv.p;
+    J.cstride = ccs;
+    J.nct = B;
+    J.n = 2 * nl;
+    for (int p = 0; p < 2; ++p)
+        for (int t = 0; t < nl; ++t) {
+            J.off[p * nl + t] = (uint16_t)(p * nl + t);
+            J.mod[p * nl + t] = (uint8_t)t;
+        }
+    Epi E;
+    memset(&E, 0, sizeof E);
+    E.on = 1;
+    E.nl = nl;
+    E.u = u.p;
+    E.u_cs = ucs;
+    E.u_ps = (int64_t)ne * N;
+    E.add[0] = add0;
+    E.add[1] = add1;
+    E.add_cs = add_cs;
+    E.out[0] = out0;
+    E.out[1] = out1;
+    E.out_cs = out_cs;
+    E.pinv = d_pinv->p;
+    E.pinv_sh = d_pinv->p + n_q;
+    E.g = add_g;
+    launch_ntt_moddown(T, J, E, stream);
     cnt[C_KS] += B;
 }
 
@@ -224,8 +233,8 @@ Grp Ctx::g_rotate_from_lift(const Grp& a, const u64* lift, int64_t k) {
     if (g == 1) return g_drop(a, a.level);
     const u64* key = rot_key(g, false);
     Grp out = g_new(a.B, a.level, 1, a.scale);
-    launch_automorph(T, a.level + 1, 1, out.p, 0, a.p, 0, g, stream, a.B, out.cs, a.cs);
-    g_ks_apply(lift, a.B, a.level, key, g, out.p, nullptr, out.cs, out.p, out.p + out.ps, out.cs);
+    // out0 = ModDown(.) + sigma_g(c0): the automorphism of c0 is a gather in the epilogue
+    g_ks_apply(lift, a.B, a.level, key, g, a.p, nullptr, a.cs, out.p, out.p + out.ps, out.cs, g);
     cnt[C_ROT] += a.B;
     return out;
 }
@@ -325,7 +334,7 @@ Grp Ctx::g_relin(const Grp& a) {
     const u64* key = relin_key();
     auto lift = g_lift(a, 2);
     Grp out = g_new(a.B, a.level, 1, a.scale);
-    g_ks_apply(lift->p, a.B, a.level, key, 1, a.p, a.p + a.ps, a.cs, out.p, out.p + out.ps, out.cs);
+    g_ks_apply(lift->p, a.B, a.level, key, 1, a.p, a.p + a.ps, a.cs, out.p, out.p + out.ps, out.cs, 1);
     return out;
 }
 

@@ -27,7 +27,7 @@ static const char* const kProfNames[PK_COUNT] = {
 struct ProfRec {
     int kind;
     hipEvent_t a, b;
-    double bytes;
+    double bytes, ops;
 };
 static bool g_prof_on = false;
 static std::vector<ProfRec> g_prof;
@@ -46,10 +46,10 @@ static hipEvent_t ev_get() {
 
 struct ProfScope {
     int kind;
-    double bytes;
+    double bytes, ops;
     hipStream_t st;
     hipEvent_t a = nullptr;
-    ProfScope(int k, double b, hipStream_t s) : kind(k), bytes(b), st(s) {
+    ProfScope(int k, double b, hipStream_t s, double o = 0) : kind(k), bytes(b), ops(o), st(s) {
         if (g_prof_on) {
             a = ev_get();
             (void)hipEventRecord(a, st);
@@ -59,7 +59,7 @@ struct ProfScope {
         if (g_prof_on && a) {
             hipEvent_t b = ev_get();
             (void)hipEventRecord(b, st);
-            g_prof.push_back({kind, a, b, bytes});
+            g_prof.push_back({kind, a, b, bytes, ops});
         }
     }
 };
@@ -67,7 +67,7 @@ struct ProfScope {
 void prof_enable(bool on) { g_prof_on = on; }
 
 std::string prof_report() {
-    double ms[PK_COUNT] = {0}, by[PK_COUNT] = {0};
+    double ms[PK_COUNT] = {0}, by[PK_COUNT] = {0}, op[PK_COUNT] = {0};
     long cnt[PK_COUNT] = {0};
     for (auto& r : g_prof) {
         (void)hipEventSynchronize(r.b);
@@ -75,6 +75,7 @@ std::string prof_report() {
         (void)hipEventElapsedTime(&t, r.a, r.b);
         ms[r.kind] += t;
         by[r.kind] += r.bytes;
+        op[r.kind] += r.ops;
         cnt[r.kind]++;
         g_ev_free.push_back(r.a);
         g_ev_free.push_back(r.b);
@@ -83,8 +84,8 @@ std::string prof_report() {
     std::string out = "{";
     for (int k = 0; k < PK_COUNT; ++k) {
         char buf[256];
-        snprintf(buf, sizeof buf, "%s\"%s\": {\"launches\": %ld, \"ms\": %.6f, \"bytes\": %.0f}", k ? ", " : "",
-                 kProfNames[k], cnt[k], ms[k], by[k]);
+        snprintf(buf, sizeof buf, "%s\"%s\": {\"launches\": %ld, \"ms\": %.6f, \"bytes\": %.0f, \"ops\": %.0f}",
+                 k ? ", " : "", kProfNames[k], cnt[k], ms[k], by[k], op[k]);
         out += buf;
     }
     return out + "}";
@@ -225,7 +226,9 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_cols(DevTables T, Jobs J) {
     for (int e = threadIdx.x; e < NTT_E; e += TPB) a[(int64_t)(e >> logC) * N2 + c0 + (e & (C - 1))] = s[e];
 }
 
-__global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J) {
+__device__ __forceinline__ int perm_g(int j, u64 g, int log_n);
+
+__global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E) {
     __shared__ u64 s[NTT_E];
     const int N = 1 << T.log_n, L1 = T.n1_log, L2 = T.n2_log, N1 = 1 << L1, N2 = 1 << L2;
     const int job = blockIdx.y, c = job / J.n, k = job % J.n;
@@ -254,9 +257,25 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J) {
             __syncthreads();
         }
     }
+    if (!E.on) {
+        for (int e = threadIdx.x; e < N2; e += TPB) {
+            u64 v = red4(s[e], q2);
+            a[e] = v >= q ? v - q : v;
+        }
+        return;
+    }
+    const int p = J.off[k] / E.nl, t = J.off[k] % E.nl;
+    const u64* u = E.u + c * E.u_cs + p * E.u_ps + (int64_t)t * N;
+    const u64* add = E.add[p] ? E.add[p] + c * E.add_cs + (int64_t)t * N : nullptr;
+    u64* out = E.out[p] + c * E.out_cs + (int64_t)t * N;
+    const u64 pi = E.pinv[t], pis = E.pinv_sh[t];
     for (int e = threadIdx.x; e < N2; e += TPB) {
         u64 v = red4(s[e], q2);
-        a[e] = v >= q ? v - q : v;
+        v = v >= q ? v - q : v;
+        const int i = r * N2 + e;
+        u64 w = mul_shoup(sub_mod(u[i], v, q), pi, pis, q);
+        if (add) w = add_mod(w, add[E.g == 1 ? i : perm_g(i, E.g, T.log_n)], q);
+        out[i] = w;
     }
 }
 
@@ -316,25 +335,42 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_cols(DevTables T, Jobs J) {
         a[(int64_t)(e >> logC) * N2 + c0 + (e & (C - 1))] = mul_shoup(s[e], mp_.ninv, mp_.ninv_sh, q);
 }
 
-void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st) {
+void launch_ntt_moddown(const DevTables& T, const Jobs& J, const Epi& E, hipStream_t st) {
     if (J.n == 0 || J.nct == 0) return;
     const int N = 1 << T.log_n, N1 = 1 << T.n1_log;
     dim3 grid_rows(N1, J.n * J.nct), grid_cols(N / NTT_E, J.n * J.nct);
-    const double bytes = 16.0 * J.n * J.nct * N;
+    const double limbs = (double)J.n * J.nct;
+    if (T.n1_log > 0) {
+        ProfScope p(PK_NTT_FWD_COLS, 16.0 * limbs * N, st, limbs * (N / 2) * T.n1_log);
+        hipLaunchKernelGGL(k_ntt_fwd_cols, grid_cols, dim3(TPB), 0, st, T, J);
+    }
+    // reads the converted limb, u and the gathered add operand; writes the output
+    ProfScope p(PK_NTT_FWD_ROWS, 8.0 * (3 + (E.add[0] ? 1 : 0)) * limbs * N, st, limbs * (N / 2) * T.n2_log);
+    hipLaunchKernelGGL(k_ntt_fwd_rows, grid_rows, dim3(TPB), 0, st, T, J, E);
+}
+
+void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st) {
+    if (J.n == 0 || J.nct == 0) return;
+    Epi E;
+    E.on = 0;
+    const int N = 1 << T.log_n, N1 = 1 << T.n1_log;
+    dim3 grid_rows(N1, J.n * J.nct), grid_cols(N / NTT_E, J.n * J.nct);
+    const double limbs = (double)J.n * J.nct;
+    const double bytes = 16.0 * limbs * N, b1 = limbs * (N / 2) * T.n1_log, b2 = limbs * (N / 2) * T.n2_log;
     if (!inverse) {
         if (T.n1_log > 0) {
-            ProfScope p(PK_NTT_FWD_COLS, bytes, st);
+            ProfScope p(PK_NTT_FWD_COLS, bytes, st, b1);
             hipLaunchKernelGGL(k_ntt_fwd_cols, grid_cols, dim3(TPB), 0, st, T, J);
         }
-        ProfScope p(PK_NTT_FWD_ROWS, bytes, st);
-        hipLaunchKernelGGL(k_ntt_fwd_rows, grid_rows, dim3(TPB), 0, st, T, J);
+        ProfScope p(PK_NTT_FWD_ROWS, bytes, st, b2);
+        hipLaunchKernelGGL(k_ntt_fwd_rows, grid_rows, dim3(TPB), 0, st, T, J, E);
     } else {
         {
-            ProfScope p(PK_NTT_INV_ROWS, bytes, st);
+            ProfScope p(PK_NTT_INV_ROWS, bytes, st, b2);
             hipLaunchKernelGGL(k_ntt_inv_rows, grid_rows, dim3(TPB), 0, st, T, J);
         }
         if (T.n1_log > 0) {
-            ProfScope p(PK_NTT_INV_COLS, bytes, st);
+            ProfScope p(PK_NTT_INV_COLS, bytes, st, b1);
             hipLaunchKernelGGL(k_ntt_inv_cols, grid_cols, dim3(TPB), 0, st, T, J);
         }
     }

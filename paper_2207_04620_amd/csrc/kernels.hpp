@@ -100,6 +100,23 @@ struct MacDesc {
 
 enum EwOp { EW_ADD = 0, EW_SUB = 1, EW_MUL_MONT = 2, EW_MUL_PLAIN = 3 };
 
+// ModDown epilogue fused into a forward NTT over the converted P-part: for job k of
+// ciphertext c (limb t = k % nl of poly p = k / nl) the transformed value v is not
+// stored; instead out_p[c][t][i] = (u[c][p][t][i] - v) * P^-1 + add_p[c][t][perm_g(i)]
+// (add_p may be null; g = 1 is the identity gather).
+struct Epi {
+    int on;
+    int nl;
+    const u64* u;
+    int64_t u_cs, u_ps;
+    const u64* add[2];
+    u64* out[2];
+    int64_t add_cs, out_cs;
+    const u64* pinv;
+    const u64* pinv_sh;
+    u64 g;
+};
+
 // ------------------------------------------------------------------ launch timing
 enum ProfKind {
     PK_NTT_FWD_COLS = 0, PK_NTT_FWD_ROWS, PK_NTT_INV_ROWS, PK_NTT_INV_COLS, PK_BASECONV, PK_INNER, PK_MODDOWN,
@@ -111,6 +128,7 @@ std::string prof_report();  // JSON: per kernel kind {launches, ms, bytes}; clea
 
 // ------------------------------------------------------------------ launchers
 void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st);
+void launch_ntt_moddown(const DevTables& T, const Jobs& J, const Epi& E, hipStream_t st);
 void launch_baseconv(const DevTables& T, const ConvDesc& D, hipStream_t st);
 void launch_sample(const DevTables& T, const Jobs& J, const SampleArgs& A, hipStream_t st);
 // out[p][i] = a[p][i] (op) b[p][i] over nl limbs (prime map mm) and npoly polys;
