@@ -72,6 +72,11 @@ def main():
                     help="Step 3: relinearise the accumulated sum once, or every product")
     ap.add_argument("--plain-iters", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-other", action="store_true", help="skip the other Step-3 schedule")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / batched capacity")
+    ap.add_argument("--serve-min-batch", type=int, default=8)
+    ap.add_argument("--serve-max-wait-ms", type=float, default=60.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the packed product is sharded by "
@@ -133,22 +138,59 @@ def main():
     err = float(np.abs(ctx.decrypt(out[0], h * h).reshape(h, h) - np.dot(*I.matrix_pair(1000, h))).max())
     log(f"batched {value:.3f} products/s ({step_ms:.1f} ms per step of {args.batch}); max abs error {err:.2e}")
 
+    # serving: Poisson arrivals of h=64 products at a fraction of the batched capacity
+    serve = None
+    if args.serve_requests > 0:
+        rate = args.serve_load * value
+        arrivals = I.poisson_arrivals(5, rate, args.serve_requests)
+        log(f"serving {args.serve_requests} requests at {rate:.1f}/s")
+        srv = he.Server(ctx, max_batch=args.batch, min_batch=args.serve_min_batch,
+                        max_wait_us=int(args.serve_max_wait_ms * 1e3))
+        tickets, late = [], {}
+        t_start = time.perf_counter()
+        for i, ta in enumerate(arrivals):
+            while time.perf_counter() - t_start < ta:
+                time.sleep(0.0005)
+            tk = srv.submit(he.REQ_MATMUL, As[i % args.batch], Bs[i % args.batch], h=h)
+            late[tk] = (time.perf_counter() - t_start) - ta  # submit delay counts as queueing
+            tickets.append(tk)
+        lat, t_last = {}, None
+        while len(lat) < len(tickets):
+            for tk in tickets:
+                if tk not in lat:
+                    r = srv.poll(tk)
+                    if r is not None:
+                        lat[tk] = r[1] + late[tk]  # scheduled arrival -> result on the host
+                        t_last = time.perf_counter()
+            time.sleep(0.0005)
+        srv.stop()
+        lats = np.array(list(lat.values()))
+        serve = {"requests": len(tickets), "arrival_rate_per_s": round(rate, 2),
+                 "served_per_s": round(len(tickets) / (t_last - t_start), 3),
+                 "p50_ms": round(float(np.percentile(lats, 50)) * 1e3, 1),
+                 "p99_ms": round(float(np.percentile(lats, 99)) * 1e3, 1),
+                 "max_batch": args.batch, "min_batch": args.serve_min_batch,
+                 "max_wait_ms": args.serve_max_wait_ms}
+        log(f"serve p50 {serve['p50_ms']} ms p99 {serve['p99_ms']} ms, {serve['served_per_s']} /s")
+
     # the other Step-3 schedule, timed without launch events
     other = "each" if args.schedule == "once" else "once"
-    ctx2 = he.Context(prm, h_list=[h], stream=stream.cuda_stream,
-                      schedule=he.SCHED_RELIN_EACH if other == "each" else he.SCHED_RELIN_ONCE)
-    As2 = [ctx2.encrypt(I.matrix_pair(1000 + i, h)[0].ravel(), level=level, nonce=2 * i) for i in range(args.batch)]
-    Bs2 = [ctx2.encrypt(I.matrix_pair(1000 + i, h)[1].ravel(), level=level, nonce=2 * i + 1)
-           for i in range(args.batch)]
-    ctx2.matmul_batch(As2, Bs2, [h] * args.batch)
-    ctx2.sync()
-    t0 = time.perf_counter()
-    ctx2.matmul_batch(As2, Bs2, [h] * args.batch)
-    ctx2.sync()
-    other_value = args.batch / (time.perf_counter() - t0)
-    log(f"schedule '{other}': {other_value:.3f} products/s")
-    del As2, Bs2
-    ctx2.close()
+    other_value = None
+    if not args.no_other:
+        ctx2 = he.Context(prm, h_list=[h], stream=stream.cuda_stream,
+                          schedule=he.SCHED_RELIN_EACH if other == "each" else he.SCHED_RELIN_ONCE)
+        pairs = [I.matrix_pair(1000 + i, h) for i in range(args.batch)]
+        As2 = [ctx2.encrypt(p[0].ravel(), level=level, nonce=2 * i) for i, p in enumerate(pairs)]
+        Bs2 = [ctx2.encrypt(p[1].ravel(), level=level, nonce=2 * i + 1) for i, p in enumerate(pairs)]
+        ctx2.matmul_batch(As2, Bs2, [h] * args.batch)
+        ctx2.sync()
+        t0 = time.perf_counter()
+        ctx2.matmul_batch(As2, Bs2, [h] * args.batch)
+        ctx2.sync()
+        other_value = args.batch / (time.perf_counter() - t0)
+        log(f"schedule '{other}': {other_value:.3f} products/s")
+        del As2, Bs2
+        ctx2.close()
 
     # dominant kernel by summed duration; NTT passes are ALU-bound (butterflies), the
     # other kernels are measured against HBM bandwidth
@@ -183,8 +225,9 @@ def main():
                    "schedule": "relinearise once per product" if args.schedule == "once" else
                                "relinearise every Step-3 product",
                    "plain_matmuls_per_s": round(1.0 / plain_s, 4), "plain_ms": round(plain_s * 1e3, 2),
-                   f"batched_matmuls_per_s_relin_{other}": round(other_value, 4),
+                   f"batched_matmuls_per_s_relin_{other}": None if other_value is None else round(other_value, 4),
                    "batched_over_plain": round(value * plain_s, 3), "max_abs_error": err},
+        "serve": serve,
         "roofline": roofline,
         "ntt_all_passes": {"achieved": round(ntt_rate, 1), "peak": round(NTT_PEAK_GBFLY, 1), "unit": "Gbutterfly/s",
                            "frac": round(ntt_rate / NTT_PEAK_GBFLY, 4), "share_of_gpu_time": round(ntt_ms / total_ms, 3)},

@@ -141,6 +141,10 @@ he_status he_matmul_batch(he_ctx *ctx, size_t n, const he_ct *const *a, const he
  * mode 0: g_d applied k times; mode 1: ReLU(x) = (x + x g_d^(k)(x)) / 2.
  * Depth per composition 1 + floor(log2 d) + 1; HE_ELEVEL if the level is too low. */
 he_status he_sign_approx(he_ctx *ctx, const he_ct *x, uint32_t d, uint32_t k, uint32_t mode, he_ct **out);
+/* n independent sign/ReLU evaluations run in lockstep groups of equal level; each
+ * result is bit-identical to he_sign_approx on that input. */
+he_status he_sign_approx_batch(he_ctx *ctx, size_t n, const he_ct *const *x, uint32_t d, uint32_t k, uint32_t mode,
+                               he_ct **out);
 
 /* Limb-batched negacyclic NTT on device memory: n_limbs limbs of N u64 each at
  * 'dev_ptr' (device pointer), limb i reduced modulo prime index mod_idx[i] (host array).
@@ -153,7 +157,9 @@ he_status he_ntt(he_ctx *ctx, uint64_t *dev_ptr, uint32_t n_limbs, const uint32_
 typedef struct he_server he_server;
 typedef struct {
     uint64_t mem_budget_bytes; /* admission budget for in-flight requests (0: no limit) */
-    uint32_t max_batch;        /* requests merged into one round (0: 32) */
+    uint32_t max_batch;        /* requests merged into one lockstep cohort (0: 32) */
+    uint32_t min_batch;        /* a new cohort waits for this many compatible requests ... */
+    uint32_t max_wait_us;      /* ... or until its oldest request has waited this long (0: no wait) */
 } he_serve_config;
 #define HE_REQ_MATMUL 0u
 #define HE_REQ_SIGN 1u

@@ -341,104 +341,260 @@ Grp Ctx::g_relin(const Grp& a) {
 // ------------------------------------------------------------------ the product
 static int floordiv_g(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
+// Phase 0: Step 1-1 and Step 1-2 and the lifts of A0, B0.  Phases 1..: k_chunk rounds
+// of Steps 2-3 each.  Last phase: relinearisation (relin-once schedule) and the final
+// RS.  The phases follow the order of the unphased evaluation exactly.
+bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
+    const int h = J.h, b = bsgs(h);
+    const double ms = scale;
+    if (J.phase == 0) {
+        Grp a = g_gather(J.A, J.lvl), bb = g_gather(J.B, J.lvl);
+        // Step 1-1: A0 = sum_i Rot(sum_j R(u_{bi+j}, -bi) . Rot(A, j), b i), then RS
+        {
+            std::vector<Grp> baby(b);
+            baby[0] = a;
+            {
+                auto lift = g_lift(a, 1);
+                for (int j = 1; j < b; ++j) baby[j] = g_rotate_from_lift(a, lift->p, j);
+            }
+            Grp acc;
+            bool have = false;
+            for (int i = floordiv_g(1 - h, b); i <= floordiv_g(h - 1, b); ++i) {
+                std::vector<std::pair<const Grp*, const u64*>> terms;
+                for (int j = 0; j < b; ++j) {
+                    const int k = b * i + j;
+                    if (k <= -h || k >= h) continue;
+                    terms.push_back({&baby[j], mask(0, h, k, -(int64_t)b * i)});
+                }
+                if (terms.empty()) continue;
+                Grp inner = g_mask_sum(terms, ms);
+                if (i) inner = g_rotate(inner, (int64_t)b * i);
+                if (!have) {
+                    acc = inner;
+                    have = true;
+                } else {
+                    g_add_into(acc, inner);
+                }
+            }
+            J.A0 = g_rescale(acc);
+        }
+        // Step 1-2: B0 = sum_i Rot(sum_j R(u_{h(bi+j)}, -h b i) . Rot(B, h j), h b i), then RS
+        {
+            std::vector<Grp> baby(b);
+            baby[0] = bb;
+            {
+                auto lift = g_lift(bb, 1);
+                for (int j = 1; j < b; ++j) baby[j] = g_rotate_from_lift(bb, lift->p, (int64_t)h * j);
+            }
+            Grp acc;
+            bool have = false;
+            for (int i = 0; i * b < h; ++i) {
+                std::vector<std::pair<const Grp*, const u64*>> terms;
+                for (int j = 0; j < b && b * i + j < h; ++j)
+                    terms.push_back({&baby[j], mask(1, h, b * i + j, -(int64_t)h * b * i)});
+                Grp inner = g_mask_sum(terms, ms);
+                if (i) inner = g_rotate(inner, (int64_t)h * b * i);
+                if (!have) {
+                    acc = inner;
+                    have = true;
+                } else {
+                    g_add_into(acc, inner);
+                }
+            }
+            J.B0 = g_rescale(acc);
+            J.B0 = g_drop(J.B0, J.B0.level - 1);  // brought to the Step-3 level before its rotations
+        }
+        J.liftA = g_lift(J.A0, 1);
+        J.liftB = g_lift(J.B0, 1);
+        J.k = 0;
+        J.phase = 1;
+        return false;
+    }
+    if (J.phase == 1) {
+        // Steps 2 and 3: A^(k) = RS(v_k . Rot(A0, k) + v_{k-h} . Rot(A0, k-h)), B^(k) = Rot(B0, h k)
+        const int kend = std::min(h, J.k + std::max(1, k_chunk));
+        for (int k = J.k; k < kend; ++k) {
+            Grp Ak;
+            if (k == 0) {
+                Ak = g_mask_sum({{&J.A0, mask(2, h, 0, 0)}}, ms);
+            } else {
+                Grp r1 = g_rotate_from_lift(J.A0, J.liftA->p, k);
+                Grp r2 = g_rotate_from_lift(J.A0, J.liftA->p, k - h);
+                Ak = g_mask_sum({{&r1, mask(2, h, k, 0)}, {&r2, mask(3, h, k, 0)}}, ms);
+            }
+            Ak = g_rescale(Ak);
+            Grp Bk = k ? g_rotate_from_lift(J.B0, J.liftB->p, (int64_t)h * k) : J.B0;
+            if (schedule == HE_SCHED_RELIN_EACH) {
+                Grp prod = g_relin(g_tensor(Ak, Bk));
+                if (!J.have) {
+                    J.acc = prod;
+                    J.have = true;
+                } else {
+                    g_add_into(J.acc, prod);
+                }
+            } else {
+                if (!J.have) {
+                    J.acc = g_tensor(Ak, Bk);
+                    J.have = true;
+                } else {
+                    g_tensor_acc(J.acc, Ak, Bk);
+                }
+            }
+        }
+        J.k = kend;
+        if (J.k == h) {
+            J.liftA.reset();
+            J.liftB.reset();
+            J.A0 = Grp();
+            J.B0 = Grp();
+            J.phase = 2;
+        }
+        return false;
+    }
+    if (schedule == HE_SCHED_RELIN_ONCE) J.acc = g_relin(J.acc);
+    J.result = g_scatter(g_rescale(J.acc));
+    J.acc = Grp();
+    J.phase = 3;
+    return true;
+}
+
 std::vector<CtPtr> Ctx::matmul_group(const std::vector<const CtData*>& A, const std::vector<const CtData*>& Bv,
                                      int h, int lvl) {
-    const int b = bsgs(h);
-    const double ms = scale;
-    Grp a = g_gather(A, lvl), bb = g_gather(Bv, lvl);
+    MatmulJob J;
+    J.A = A;
+    J.B = Bv;
+    J.h = h;
+    J.lvl = lvl;
+    while (!matmul_step(J, h)) {
+    }
+    return J.result;
+}
 
-    // Step 1-1: A0 = sum_i Rot(sum_j R(u_{bi+j}, -bi) . Rot(A, j), b i), then RS
-    Grp A0;
-    {
-        std::vector<Grp> baby(b);
-        baby[0] = a;
-        {
-            auto lift = g_lift(a, 1);
-            for (int j = 1; j < b; ++j) baby[j] = g_rotate_from_lift(a, lift->p, j);
+// ------------------------------------------------------------------ sign (Sec. 4.2), lockstep
+// numerators of the m^(2i+1) coefficients of g_d over 2^(2d-1)
+static std::vector<int64_t> gd_numerators(int d) {
+    auto binom = [](int n, int r) {
+        int64_t v = 1;
+        for (int i = 1; i <= r; ++i) v = v * (n - r + i) / i;
+        return v;
+    };
+    std::vector<int64_t> num(d + 1, 0);
+    for (int j = 0; j <= d; ++j)  // 4^-j C(2j, j) m (1 - m^2)^j, scaled by 4^d
+        for (int i = 0; i <= j; ++i) {
+            const int64_t t = binom(2 * j, j) * binom(j, i) * ((int64_t)1 << (2 * (d - j)));
+            num[i] += (i & 1) ? -t : t;
         }
-        Grp acc;
-        bool have = false;
-        for (int i = floordiv_g(1 - h, b); i <= floordiv_g(h - 1, b); ++i) {
-            std::vector<std::pair<const Grp*, const u64*>> terms;
-            for (int j = 0; j < b; ++j) {
-                const int k = b * i + j;
-                if (k <= -h || k >= h) continue;
-                terms.push_back({&baby[j], mask(0, h, k, -(int64_t)b * i)});
-            }
-            if (terms.empty()) continue;
-            Grp inner = g_mask_sum(terms, ms);
-            if (i) inner = g_rotate(inner, (int64_t)b * i);
-            if (!have) {
-                acc = inner;
-                have = true;
-            } else {
-                g_add_into(acc, inner);
-            }
-        }
-        A0 = g_rescale(acc);
+    for (auto& v : num) v /= 2;
+    return num;
+}
+
+// round(num q / 2^e), half away from zero
+static int64_t round_num_q(int64_t num, u64 q, int e) {
+    const __int128 v = (__int128)num * q, den = (__int128)1 << e;
+    const __int128 a = v < 0 ? -v : v;
+    const __int128 r = (2 * a + den) / (2 * den);
+    return (int64_t)(v < 0 ? -r : r);
+}
+
+Grp Ctx::g_mul_int(const Grp& a, int64_t k) {
+    const int nl = a.level + 1;
+    std::vector<u64> c(2 * nl);
+    for (int i = 0; i < nl; ++i) {
+        const u64 q = mods[i];
+        const u64 r = k >= 0 ? (u64)k % q : (q - (u64)(-(k + 1)) % q - 1) % q;
+        c[i] = r;
+        c[nl + i] = hm::shoup(r, q);
     }
-    // Step 1-2: B0 = sum_i Rot(sum_j R(u_{h(bi+j)}, -h b i) . Rot(B, h j), h b i), then RS
-    Grp B0;
-    {
-        std::vector<Grp> baby(b);
-        baby[0] = bb;
-        {
-            auto lift = g_lift(bb, 1);
-            for (int j = 1; j < b; ++j) baby[j] = g_rotate_from_lift(bb, lift->p, (int64_t)h * j);
-        }
-        Grp acc;
-        bool have = false;
-        for (int i = 0; i * b < h; ++i) {
-            std::vector<std::pair<const Grp*, const u64*>> terms;
-            for (int j = 0; j < b && b * i + j < h; ++j)
-                terms.push_back({&baby[j], mask(1, h, b * i + j, -(int64_t)h * b * i)});
-            Grp inner = g_mask_sum(terms, ms);
-            if (i) inner = g_rotate(inner, (int64_t)h * b * i);
-            if (!have) {
-                acc = inner;
-                have = true;
-            } else {
-                g_add_into(acc, inner);
-            }
-        }
-        B0 = g_rescale(acc);
-        B0 = g_drop(B0, B0.level - 1);  // brought to the Step-3 level before its rotations
-    }
-    // Steps 2 and 3
-    auto liftA = g_lift(A0, 1);
-    auto liftB = g_lift(B0, 1);
-    Grp acc;
+    DBuf dc(this, 2 * (size_t)nl);
+    hip_check(hipMemcpyAsync(dc.p, c.data(), c.size() * 8, hipMemcpyHostToDevice, stream), "mul_int consts");
+    hip_check(hipStreamSynchronize(stream), "mul_int consts");
+    Grp r = g_new(a.B, a.level, a.deg, a.scale);
+    // the group is (B * (deg+1)) polynomials with a uniform poly stride
+    launch_mul_const(T, ModMap{1 << 20, n_q}, nl, a.B * (a.deg + 1), r.p, r.ps, a.p, a.ps, dc.p, dc.p + nl, stream);
+    return r;
+}
+
+Grp Ctx::g_mul_rs(const Grp& x, const Grp& y) {
+    const int l = std::min(x.level, y.level);
+    Grp a = x.level == l ? x : g_drop(x, l);
+    Grp b = y.level == l ? y : g_drop(y, l);
+    return g_rescale(g_relin(g_tensor(a, b)));
+}
+
+// g_d(x) = sum_i c_{2i+1} x^(2i+1): x_c = RS(x * round(c q_l)) lands at the scale of x;
+// x^(2i) comes from the powers x^2, x^4, ... multiplied in along the set bits of i.
+Grp Ctx::g_eval_gd(const Grp& x, int d) {
+    const auto num = gd_numerators(d);
+    const int e = 2 * d - 1;
+    int nb = 0;
+    while ((1 << nb) <= d) ++nb;
+    std::vector<Grp> pw(nb);
+    for (int b = 0; b < nb; ++b) pw[b] = b ? g_mul_rs(pw[b - 1], pw[b - 1]) : g_mul_rs(x, x);
+    const u64 ql = mods[x.level];
+    Grp y;
     bool have = false;
-    for (int k = 0; k < h; ++k) {
-        Grp Ak;
-        if (k == 0) {
-            Ak = g_mask_sum({{&A0, mask(2, h, 0, 0)}}, ms);
+    for (int i = 0; i <= d; ++i) {
+        Grp term = g_rescale(g_mul_int(x, round_num_q(num[i], ql, e)));
+        term.scale = x.scale;  // the constant rides at scale q_l, removed exactly by RS
+        for (int b = 0; b < nb; ++b)
+            if ((i >> b) & 1) term = g_mul_rs(term, pw[b]);
+        if (!have) {
+            y = term;
+            have = true;
         } else {
-            Grp r1 = g_rotate_from_lift(A0, liftA->p, k);
-            Grp r2 = g_rotate_from_lift(A0, liftA->p, k - h);
-            Ak = g_mask_sum({{&r1, mask(2, h, k, 0)}, {&r2, mask(3, h, k, 0)}}, ms);
-        }
-        Ak = g_rescale(Ak);
-        Grp Bk = k ? g_rotate_from_lift(B0, liftB->p, (int64_t)h * k) : B0;
-        if (schedule == HE_SCHED_RELIN_EACH) {
-            Grp prod = g_relin(g_tensor(Ak, Bk));
-            if (!have) {
-                acc = prod;
-                have = true;
-            } else {
-                g_add_into(acc, prod);
-            }
-        } else {
-            if (!have) {
-                acc = g_tensor(Ak, Bk);
-                have = true;
-            } else {
-                g_tensor_acc(acc, Ak, Bk);
-            }
+            // Add: level min, scale max (Fig. 1)
+            const int l = std::min(y.level, term.level);
+            if (y.level != l) y = g_drop(y, l);
+            if (term.level != l) term = g_drop(term, l);
+            g_add_into(y, term);
         }
     }
-    if (schedule == HE_SCHED_RELIN_ONCE) acc = g_relin(acc);
-    return g_scatter(g_rescale(acc));
+    return y;
+}
+
+bool Ctx::sign_step(SignJob& J) {
+    if (J.it == 0 && !J.started) {
+        J.x = g_gather(J.X, J.lvl);
+        J.cur = J.x;
+        J.started = true;
+    }
+    if (J.it < J.k) {
+        J.cur = g_eval_gd(J.cur, J.d);
+        ++J.it;
+        if (J.it < J.k || J.mode) return false;
+    }
+    if (J.mode) {  // ReLU(x) = (x + x g) / 2, the halving kept in the scale
+        Grp r = g_mul_rs(J.x, J.cur);
+        Grp xd = g_drop(J.x, r.level);
+        g_add_into(r, xd);
+        for (auto& s : r.scale) s *= 2.0;
+        J.cur = r;
+    }
+    J.result = g_scatter(J.cur);
+    J.x = Grp();
+    J.cur = Grp();
+    return true;
+}
+
+std::vector<CtPtr> Ctx::sign_group(const std::vector<const CtData*>& X, int d, int k, int mode) {
+    if (d < 1 || d > 7 || k < 0) throw HeError(HE_EINVAL);
+    int nb = 0;
+    while ((1 << nb) <= d) ++nb;
+    int lvl = 1 << 30;
+    for (auto* x : X) {
+        if (x->deg != 1) throw HeError(HE_EMISMATCH);
+        lvl = std::min(lvl, x->level);
+    }
+    if (lvl < k * (nb + 1) + (mode ? 1 : 0)) throw HeError(HE_ELEVEL);
+    SignJob J;
+    J.X = X;
+    J.lvl = lvl;
+    J.d = d;
+    J.k = k;
+    J.mode = mode;
+    while (!sign_step(J)) {
+    }
+    return J.result;
 }
 
 CtPtr Ctx::matmul(const CtData& A, const CtData& B, int h) {

@@ -44,6 +44,7 @@ void hip_check(hipError_t e, const char* what) {
 
 // ====================================================================== device pool
 void* Pool::alloc(size_t bytes) {
+    std::lock_guard<std::mutex> lk(m);
     bytes = (bytes + 255) & ~(size_t)255;
     auto it = free_.find(bytes);
     if (it != free_.end() && !it->second.empty()) {
@@ -57,7 +58,7 @@ void* Pool::alloc(size_t bytes) {
         p = dev_alloc(bytes, user);
     } else if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
-        trim();
+        trim_locked();
         if (hipMalloc(&p, bytes) != hipSuccess) {
             (void)hipGetLastError();
             p = nullptr;
@@ -69,11 +70,16 @@ void* Pool::alloc(size_t bytes) {
 }
 void Pool::release(void* p, size_t bytes) {
     if (!p) return;
+    std::lock_guard<std::mutex> lk(m);
     bytes = (bytes + 255) & ~(size_t)255;
     free_[bytes].push_back(p);
     cached += bytes;
 }
 void Pool::trim() {
+    std::lock_guard<std::mutex> lk(m);
+    trim_locked();
+}
+void Pool::trim_locked() {
     for (auto& kv : free_)
         for (void* p : kv.second) {
             if (dev_free) dev_free(p, user);
@@ -889,85 +895,21 @@ void Ctx::prepare_h(int h) {
     prepare_masks(matmul_masks(h));
     hip_check(hipStreamSynchronize(stream), "prepare_h");
     prepared_h.insert(h);
-}
-
-// ====================================================================== sign (Sec. 4.2)
-// numerators of the m^(2i+1) coefficients of g_d over 2^(2d-1)
-static std::vector<int64_t> gd_num(int d) {
-    auto binom = [](int n, int r) {
-        int64_t v = 1;
-        for (int i = 1; i <= r; ++i) v = v * (n - r + i) / i;
-        return v;
-    };
-    std::vector<int64_t> num(d + 1, 0);
-    for (int j = 0; j <= d; ++j)  // 4^-j C(2j, j) m (1 - m^2)^j, scaled by 4^d
-        for (int i = 0; i <= j; ++i) {
-            const int64_t t = binom(2 * j, j) * binom(j, i) * ((int64_t)1 << (2 * (d - j)));
-            num[i] += (i & 1) ? -t : t;
-        }
-    for (auto& v : num) v /= 2;
-    return num;
-}
-
-// round(num q / 2^e), half away from zero
-static int64_t round_q(int64_t num, u64 q, int e) {
-    const __int128 v = (__int128)num * q, den = (__int128)1 << e;
-    const __int128 a = v < 0 ? -v : v;
-    const __int128 r = (2 * a + den) / (2 * den);
-    return (int64_t)(v < 0 ? -r : r);
-}
-
-CtPtr Ctx::mul_rs(const CtData& x, const CtData& y) {
-    const int l = std::min(x.level, y.level);
-    CtPtr a = x.level == l ? nullptr : drop(x, l);
-    CtPtr b = y.level == l ? nullptr : drop(y, l);
-    CtPtr p = relin(*tensor(a ? *a : x, b ? *b : y));
-    return rescale(*p);
-}
-
-CtPtr Ctx::eval_gd(const CtData& x, int d) {
-    const auto num = gd_num(d);
-    const int e = 2 * d - 1;
-    int nb = 0;
-    while ((1 << nb) <= d) ++nb;
-    std::vector<CtPtr> pw(nb);
-    for (int b = 0; b < nb; ++b) pw[b] = b ? mul_rs(*pw[b - 1], *pw[b - 1]) : mul_rs(x, x);
-    const u64 ql = mods[x.level];
-    CtPtr y;
-    for (int i = 0; i <= d; ++i) {
-        CtPtr term = rescale(*mul_int(x, round_q(num[i], ql, e)));
-        term->scale = x.scale;  // the constant rides at scale q_l, removed exactly by RS
-        for (int b = 0; b < nb; ++b)
-            if ((i >> b) & 1) term = mul_rs(*term, *pw[b]);
-        y = y ? add_sub(*y, *term, false) : term;
-    }
-    return y;
-}
-
-CtPtr Ctx::sign(const CtData& x, int d, int k, int mode) {
-    if (d < 1 || d > 7 || k < 0 || x.deg != 1) throw HeError(HE_EINVAL);
-    int nb = 0;
-    while ((1 << nb) <= d) ++nb;
-    if (x.level < k * (nb + 1) + (mode ? 1 : 0)) throw HeError(HE_ELEVEL);
-    CtPtr cur = drop(x, x.level);
-    for (int it = 0; it < k; ++it) cur = eval_gd(*cur, d);
-    if (!mode) return cur;
-    CtPtr r = mul_rs(x, *cur);
-    CtPtr xd = drop(x, r->level);
-    CtPtr y = add_sub(*r, *xd, false);
-    y->scale *= 2.0;  // (x + x g) / 2
-    return y;
+    int lg = 0;
+    while ((1 << lg) < h) ++lg;
+    prepared_mask.fetch_or(1u << lg);
 }
 
 // ====================================================================== C ABI
-struct he_ct {
-    Ctx* ctx;
-    CtPtr c;
-};
-struct he_ctx {
-    std::unique_ptr<Ctx> c;
-};
 
+
+template <class F>
+static he_status guard(F&& f);
+template <class F>
+static he_status guardc(he_ctx* ctx, F&& f) {
+    std::lock_guard<std::recursive_mutex> lk(ctx->c->api_mu);
+    return guard(std::forward<F>(f));
+}
 template <class F>
 static he_status guard(F&& f) {
     try {
@@ -982,7 +924,7 @@ static he_status guard(F&& f) {
     }
 }
 
-static he_ct* wrap(Ctx* c, CtPtr p) { return new he_ct{c, std::move(p)}; }
+he_ct* wrap(Ctx* c, CtPtr p) { return new he_ct{c, std::move(p)}; }
 
 extern "C" {
 
@@ -1047,7 +989,7 @@ he_status he_ctx_moduli(const he_ctx* ctx, uint64_t* out, size_t n) {
 
 he_status he_sync(he_ctx* ctx) {
     if (!ctx) return HE_EINVAL;
-    return guard([&]() { hip_check(hipStreamSynchronize(ctx->c->stream), "sync"); });
+    return guardc(ctx, [&]() { hip_check(hipStreamSynchronize(ctx->c->stream), "sync"); });
 }
 
 he_status he_counters(const he_ctx* ctx, int64_t out[6], int reset) {
@@ -1067,13 +1009,14 @@ he_status he_memory(const he_ctx* ctx, uint64_t* keys_bytes, uint64_t* pool_byte
 
 he_status he_encode(he_ctx* ctx, const double* vals, size_t n_vals, double scale, int64_t* out) {
     if (!ctx || !vals || !out || n_vals == 0 || (size_t)(ctx->c->N / 2) % n_vals) return HE_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(ctx->c->api_mu);
     ctx->c->enc.encode(vals, (int64_t)n_vals, scale, out);
     return HE_OK;
 }
 
 he_status he_encrypt(he_ctx* ctx, const double* vals, size_t n_vals, uint32_t level, uint64_t nonce, he_ct** out) {
     if (!ctx || !vals || !out || n_vals == 0 || (size_t)(ctx->c->N / 2) % n_vals) return HE_EINVAL;
-    return guard([&]() {
+    return guardc(ctx, [&]() {
         Ctx* c = ctx->c.get();
         std::vector<int64_t> m(c->N);
         c->enc.encode(vals, (int64_t)n_vals, c->scale, m.data());
@@ -1084,26 +1027,30 @@ he_status he_encrypt(he_ctx* ctx, const double* vals, size_t n_vals, uint32_t le
 he_status he_encrypt_coeffs(he_ctx* ctx, const int64_t* coeffs, uint32_t level, double scale, uint64_t nonce,
                             he_ct** out) {
     if (!ctx || !coeffs || !out) return HE_EINVAL;
-    return guard([&]() { *out = wrap(ctx->c.get(), ctx->c->encrypt_coeffs(coeffs, (int)level, scale, nonce)); });
+    return guardc(ctx, [&]() { *out = wrap(ctx->c.get(), ctx->c->encrypt_coeffs(coeffs, (int)level, scale, nonce)); });
 }
 
 he_status he_decrypt_coeffs(he_ctx* ctx, const he_ct* ct, double* out, size_t n) {
     if (!ctx || !ct || !out || n < (size_t)ctx->c->N) return HE_EINVAL;
     if (ct->ctx != ctx->c.get()) return HE_EMISMATCH;
-    return guard([&]() { ctx->c->decrypt_coeffs(*ct->c, out); });
+    return guardc(ctx, [&]() { ctx->c->decrypt_coeffs(*ct->c, out); });
 }
 
 he_status he_decrypt(he_ctx* ctx, const he_ct* ct, double* out, size_t n_out) {
     if (!ctx || !ct || !out) return HE_EINVAL;
     if (ct->ctx != ctx->c.get()) return HE_EMISMATCH;
-    return guard([&]() {
+    return guardc(ctx, [&]() {
         std::vector<double> co(ctx->c->N);
         ctx->c->decrypt_coeffs(*ct->c, co.data());
         ctx->c->enc.decode(co.data(), ct->c->scale, out, (int64_t)n_out);
     });
 }
 
-void he_ct_free(he_ct* ct) { delete ct; }
+void he_ct_free(he_ct* ct) {
+    if (!ct) return;
+    std::lock_guard<std::recursive_mutex> lk(ct->ctx->api_mu);
+    delete ct;
+}
 
 he_status he_ct_info(const he_ct* ct, uint32_t* level, uint32_t* degree, double* scale) {
     if (!ct) return HE_EINVAL;
@@ -1120,7 +1067,7 @@ he_status he_ct_export(he_ctx* ctx, const he_ct* ct, uint64_t* buf, size_t n) {
     const CtData& d = *ct->c;
     const size_t tot = (size_t)(d.deg + 1) * (d.level + 1) * c->N;
     if (n < tot) return HE_EINVAL;
-    return guard([&]() {
+    return guardc(ctx, [&]() {
         DBuf tmp(c, tot);
         hip_check(hipMemcpyAsync(tmp.p, d.buf->p, tot * 8, hipMemcpyDeviceToDevice, c->stream), "export");
         c->ntt(tmp.p, d.deg + 1, d.level + 1, d.level + 1, true, -1);
@@ -1136,7 +1083,7 @@ he_status he_ct_import(he_ctx* ctx, const uint64_t* buf, size_t n, uint32_t leve
     if ((int)level >= c->n_q) return HE_ELEVEL;
     const size_t tot = (size_t)(degree + 1) * (level + 1) * c->N;
     if (n < tot) return HE_EINVAL;
-    return guard([&]() {
+    return guardc(ctx, [&]() {
         CtPtr r = c->new_ct((int)level, (int)degree, scale);
         upload(c, r->buf->p, buf, tot * 8);
         c->ntt(r->buf->p, degree + 1, level + 1, level + 1, false, -1);
@@ -1154,20 +1101,20 @@ he_status he_ct_import(he_ctx* ctx, const uint64_t* buf, size_t n, uint32_t leve
 
 he_status he_add(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out) {
     CHECK2(a, b);
-    return guard([&]() { *out = wrap(ctx->c.get(), ctx->c->add_sub(*a->c, *b->c, false)); });
+    return guardc(ctx, [&]() { *out = wrap(ctx->c.get(), ctx->c->add_sub(*a->c, *b->c, false)); });
 }
 he_status he_sub(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out) {
     CHECK2(a, b);
-    return guard([&]() { *out = wrap(ctx->c.get(), ctx->c->add_sub(*a->c, *b->c, true)); });
+    return guardc(ctx, [&]() { *out = wrap(ctx->c.get(), ctx->c->add_sub(*a->c, *b->c, true)); });
 }
 he_status he_drop(he_ctx* ctx, const he_ct* a, uint32_t level, he_ct** out) {
     CHECK1(a);
-    return guard([&]() { *out = wrap(ctx->c.get(), ctx->c->drop(*a->c, (int)level)); });
+    return guardc(ctx, [&]() { *out = wrap(ctx->c.get(), ctx->c->drop(*a->c, (int)level)); });
 }
 he_status he_mul_plain(he_ctx* ctx, const he_ct* a, const int64_t* coeffs, double pt_scale, he_ct** out) {
     CHECK1(a);
     if (!coeffs) return HE_EINVAL;
-    return guard([&]() {
+    return guardc(ctx, [&]() {
         Ctx* c = ctx->c.get();
         auto pt = c->plaintext_mont(coeffs);
         if (a->c->deg != 1) throw HeError(HE_EMISMATCH);
@@ -1178,38 +1125,38 @@ he_status he_mul_plain(he_ctx* ctx, const he_ct* a, const int64_t* coeffs, doubl
 }
 he_status he_mul_int(he_ctx* ctx, const he_ct* a, int64_t k, he_ct** out) {
     CHECK1(a);
-    return guard([&]() { *out = wrap(ctx->c.get(), ctx->c->mul_int(*a->c, k)); });
+    return guardc(ctx, [&]() { *out = wrap(ctx->c.get(), ctx->c->mul_int(*a->c, k)); });
 }
 he_status he_tensor(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out) {
     CHECK2(a, b);
-    return guard([&]() { *out = wrap(ctx->c.get(), ctx->c->tensor(*a->c, *b->c)); });
+    return guardc(ctx, [&]() { *out = wrap(ctx->c.get(), ctx->c->tensor(*a->c, *b->c)); });
 }
 he_status he_relin(he_ctx* ctx, const he_ct* a, he_ct** out) {
     CHECK1(a);
-    return guard([&]() { *out = wrap(ctx->c.get(), ctx->c->relin(*a->c)); });
+    return guardc(ctx, [&]() { *out = wrap(ctx->c.get(), ctx->c->relin(*a->c)); });
 }
 he_status he_mul(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out) {
     CHECK2(a, b);
-    return guard([&]() { *out = wrap(ctx->c.get(), ctx->c->relin(*ctx->c->tensor(*a->c, *b->c))); });
+    return guardc(ctx, [&]() { *out = wrap(ctx->c.get(), ctx->c->relin(*ctx->c->tensor(*a->c, *b->c))); });
 }
 he_status he_rescale(he_ctx* ctx, const he_ct* a, he_ct** out) {
     CHECK1(a);
-    return guard([&]() { *out = wrap(ctx->c.get(), ctx->c->rescale(*a->c)); });
+    return guardc(ctx, [&]() { *out = wrap(ctx->c.get(), ctx->c->rescale(*a->c)); });
 }
 he_status he_rotate(he_ctx* ctx, const he_ct* a, int64_t k, he_ct** out) {
     CHECK1(a);
-    return guard([&]() { *out = wrap(ctx->c.get(), ctx->c->rotate(*a->c, k)); });
+    return guardc(ctx, [&]() { *out = wrap(ctx->c.get(), ctx->c->rotate(*a->c, k)); });
 }
 he_status he_gen_rotation_key(he_ctx* ctx, int64_t k) {
     if (!ctx) return HE_EINVAL;
-    return guard([&]() {
+    return guardc(ctx, [&]() {
         ctx->c->rot_key(ctx->c->galois(k), true);
         hip_check(hipStreamSynchronize(ctx->c->stream), "genkey");
     });
 }
 he_status he_matmul(he_ctx* ctx, const he_ct* a, const he_ct* b, uint32_t h, he_ct** out) {
     CHECK2(a, b);
-    return guard([&]() { *out = wrap(ctx->c.get(), ctx->c->matmul(*a->c, *b->c, (int)h)); });
+    return guardc(ctx, [&]() { *out = wrap(ctx->c.get(), ctx->c->matmul(*a->c, *b->c, (int)h)); });
 }
 he_status he_matmul_batch(he_ctx* ctx, size_t n, const he_ct* const* a, const he_ct* const* b, const uint32_t* h,
                           he_ct** out) {
@@ -1218,7 +1165,7 @@ he_status he_matmul_batch(he_ctx* ctx, size_t n, const he_ct* const* a, const he
         if (!a[i] || !b[i]) return HE_EINVAL;
         if (a[i]->ctx != ctx->c.get() || b[i]->ctx != ctx->c.get()) return HE_EMISMATCH;
     }
-    return guard([&]() {
+    return guardc(ctx, [&]() {
         std::vector<const CtData*> va(n), vb(n);
         std::vector<int> vh(n);
         for (size_t i = 0; i < n; ++i) {
@@ -1233,7 +1180,31 @@ he_status he_matmul_batch(he_ctx* ctx, size_t n, const he_ct* const* a, const he
 he_status he_sign_approx(he_ctx* ctx, const he_ct* x, uint32_t d, uint32_t k, uint32_t mode, he_ct** out) {
     CHECK1(x);
     if (mode > 1) return HE_EINVAL;
-    return guard([&]() { *out = wrap(ctx->c.get(), ctx->c->sign(*x->c, (int)d, (int)k, (int)mode)); });
+    return guardc(ctx, [&]() { *out = wrap(ctx->c.get(), ctx->c->sign_group({x->c.get()}, (int)d, (int)k, (int)mode)[0]); });
+}
+he_status he_sign_approx_batch(he_ctx* ctx, size_t n, const he_ct* const* x, uint32_t d, uint32_t k, uint32_t mode,
+                               he_ct** out) {
+    if (!ctx || (n && (!x || !out)) || mode > 1) return HE_EINVAL;
+    for (size_t i = 0; i < n; ++i) {
+        if (!x[i]) return HE_EINVAL;
+        if (x[i]->ctx != ctx->c.get()) return HE_EMISMATCH;
+    }
+    return guardc(ctx, [&]() {
+        // lockstep groups of equal level
+        std::map<int, std::vector<size_t>> byl;
+        for (size_t i = 0; i < n; ++i) byl[x[i]->c->level].push_back(i);
+        std::vector<CtPtr> res(n);
+        for (auto& kv : byl) {
+            for (size_t s = 0; s < kv.second.size(); s += (size_t)ctx->c->max_group) {
+                std::vector<const CtData*> v;
+                const size_t e = std::min(kv.second.size(), s + (size_t)ctx->c->max_group);
+                for (size_t t = s; t < e; ++t) v.push_back(x[kv.second[t]]->c.get());
+                auto r = ctx->c->sign_group(v, (int)d, (int)k, (int)mode);
+                for (size_t t = s; t < e; ++t) res[kv.second[t]] = r[t - s];
+            }
+        }
+        for (size_t i = 0; i < n; ++i) out[i] = wrap(ctx->c.get(), res[i]);
+    });
 }
 he_status he_profile_enable(he_ctx* ctx, int on) {
     if (!ctx) return HE_EINVAL;
@@ -1242,7 +1213,7 @@ he_status he_profile_enable(he_ctx* ctx, int on) {
 }
 he_status he_profile_report(he_ctx* ctx, char* buf, size_t n) {
     if (!ctx || !buf || n == 0) return HE_EINVAL;
-    return guard([&]() {
+    return guardc(ctx, [&]() {
         const std::string r = prof_report();
         const size_t m = std::min(n - 1, r.size());
         memcpy(buf, r.data(), m);
@@ -1254,7 +1225,7 @@ he_status he_ntt(he_ctx* ctx, uint64_t* dev_ptr, uint32_t n_limbs, const uint32_
     Ctx* c = ctx->c.get();
     for (uint32_t i = 0; i < n_limbs; ++i)
         if (mod_idx[i] >= c->mods.size()) return HE_EINVAL;
-    return guard([&]() {
+    return guardc(ctx, [&]() {
         for (uint32_t start = 0; start < n_limbs; start += HE_MAXJ) {
             Jobs J;
             J.base = dev_ptr + (size_t)start * c->N;
@@ -1273,26 +1244,3 @@ he_status he_ntt(he_ctx* ctx, uint64_t* dev_ptr, uint32_t n_limbs, const uint32_
 
 }  // extern "C"
 
-// ====================================================================== serving (placeholder until the loop lands)
-extern "C" {
-struct he_server {
-    he_ctx* ctx;
-};
-he_status he_serve_start(he_ctx* ctx, const he_serve_config* cfg, he_server** out) {
-    (void)ctx; (void)cfg; (void)out;
-    return HE_EUNSUPPORTED;
-}
-he_status he_serve_submit(he_server* s, const he_request* req, uint64_t* ticket) {
-    (void)s; (void)req; (void)ticket;
-    return HE_EUNSUPPORTED;
-}
-he_status he_serve_poll(he_server* s, uint64_t ticket, int* done, he_ct** result, he_status* req_status,
-                        double* latency_s) {
-    (void)s; (void)ticket; (void)done; (void)result; (void)req_status; (void)latency_s;
-    return HE_EUNSUPPORTED;
-}
-he_status he_serve_stop(he_server* s) {
-    (void)s;
-    return HE_EUNSUPPORTED;
-}
-}

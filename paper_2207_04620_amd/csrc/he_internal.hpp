@@ -2,7 +2,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <map>
+#include <mutex>
 #include <set>
 #include <memory>
 #include <unordered_map>
@@ -24,8 +26,10 @@ enum { P_SK = 1, P_PK_A = 2, P_PK_E = 3, P_SWK_A = 4, P_SWK_E = 5, P_ENC_V = 6, 
 enum { C_ROT = 0, C_KS = 1, C_MULPT = 2, C_MULCT = 3, C_ADD = 4, C_RS = 5 };
 
 // Size-bucketed cache over hipMalloc; all work is ordered on one stream, so a block
-// released here may be handed out again at once.
+// released here may be handed out again at once.  Thread-safe (the serving thread and
+// the caller release buffers concurrently).
 struct Pool {
+    std::mutex m;
     std::unordered_map<size_t, std::vector<void*>> free_;
     size_t held = 0, cached = 0;
     void* (*dev_alloc)(size_t, void*) = nullptr;
@@ -34,6 +38,7 @@ struct Pool {
     void* alloc(size_t bytes);
     void release(void* p, size_t bytes);
     void trim();
+    void trim_locked();
 };
 
 struct Ctx;
@@ -61,6 +66,24 @@ struct Grp {
     std::shared_ptr<DBuf> buf;
     u64* p = nullptr;
     int64_t ps = 0, cs = 0;  // poly and ciphertext strides (elements)
+};
+
+// resumable state of one lockstep product group
+struct MatmulJob {
+    std::vector<const CtData*> A, B;
+    int h = 0, lvl = 0, phase = 0, k = 0;
+    Grp A0, B0, acc;
+    bool have = false;
+    std::shared_ptr<DBuf> liftA, liftB;
+    std::vector<CtPtr> result;
+};
+// resumable state of one lockstep sign/ReLU group
+struct SignJob {
+    std::vector<const CtData*> X;
+    int lvl = 0, d = 3, k = 1, mode = 0, it = 0;
+    bool started = false;
+    Grp x, cur;
+    std::vector<CtPtr> result;
 };
 
 struct ModUpInfo {
@@ -106,6 +129,7 @@ struct Ctx {
     std::map<MaskKey, std::unique_ptr<DBuf>> masks;
     size_t keys_bytes = 0;
     std::set<int> prepared_h;
+    std::atomic<uint32_t> prepared_mask{0};  // bit log2(h) set once keys and masks for h exist
     int64_t cnt[6] = {0, 0, 0, 0, 0, 0};
 
     int ext_mod(int level, int i) const;
@@ -164,10 +188,14 @@ struct Ctx {
     Grp g_relin(const Grp& a);
     std::vector<CtPtr> matmul_group(const std::vector<const CtData*>& A, const std::vector<const CtData*>& B, int h,
                                     int lvl);
+    bool matmul_step(MatmulJob& J, int k_chunk);
+    Grp g_mul_int(const Grp& a, int64_t k);
+    Grp g_mul_rs(const Grp& x, const Grp& y);
+    Grp g_eval_gd(const Grp& x, int d);
+    bool sign_step(SignJob& J);
+    std::vector<CtPtr> sign_group(const std::vector<const CtData*>& X, int d, int k, int mode);
 
-    CtPtr mul_rs(const CtData& x, const CtData& y);
-    CtPtr eval_gd(const CtData& x, int d);
-    CtPtr sign(const CtData& x, int d, int k, int mode);
+    std::recursive_mutex api_mu;  // every C-ABI call on the context (and the serving thread) holds it
 
     void release_all() {
         masks.clear();
@@ -181,3 +209,13 @@ struct Ctx {
         pool.trim();
     }
 };
+
+// C-ABI handles
+struct he_ct {
+    Ctx* ctx;
+    CtPtr c;
+};
+struct he_ctx {
+    std::unique_ptr<Ctx> c;
+};
+he_ct* wrap(Ctx* c, CtPtr p);

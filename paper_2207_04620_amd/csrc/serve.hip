@@ -1,0 +1,283 @@
+// Serving loop: continuous batching of packed matrix products and sign/ReLU
+// evaluations on one device.
+//
+// A host thread owns execution.  Submitted requests wait in FIFO order and are
+// admitted while the summed device footprint of in-flight requests stays within the
+// budget; admitted requests with the same operation, parameters and level form a
+// cohort that runs in lockstep (group kernels, keys and masks read once per cohort).
+// Each round advances every active cohort by one phase (Step 1 of a product, then a
+// chunk of Step 2-3 rounds, then the final relinearisation/RS; one g_d composition of
+// a sign evaluation), so requests that arrive while others are on the device start at
+// the next round and their kernels interleave with the running cohorts on the stream.
+// A request's result is the same operation DAG as running it alone: bit-identical.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <thread>
+
+#include "he_internal.hpp"
+
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Req {
+    he_request r;
+    const CtData* a = nullptr;
+    const CtData* b = nullptr;
+    CtPtr keep_a, keep_b;  // the inputs stay alive while the request is in flight
+    double t_submit = 0, t_done = 0;
+    size_t footprint = 0;
+    he_status status = HE_OK;
+    CtPtr result;
+    bool done = false, taken = false;
+};
+
+struct Cohort {
+    uint32_t op = 0;
+    std::vector<uint64_t> ids;
+    MatmulJob mj;
+    SignJob sj;
+};
+
+}  // namespace
+
+struct he_server {
+    he_ctx* ctx = nullptr;
+    Ctx* c = nullptr;
+    uint64_t budget = 0;
+    uint32_t max_batch = 32;
+    uint32_t min_batch = 1;
+    double max_wait_s = 0;
+    int k_chunk = 8;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<uint64_t> pending;
+    std::map<uint64_t, Req> reqs;
+    std::vector<Cohort> active;
+    uint64_t inflight = 0, next_id = 1;
+    bool stop = false;
+    std::thread th;
+};
+
+static size_t footprint(const Ctx* c, const he_request& r, int level) {
+    const size_t ct = 2 * (size_t)(level + 1) * c->N * 8;
+    const int beta = (level + 1 + c->alpha - 1) / c->alpha;
+    const size_t lift = (size_t)beta * (level + 1 + c->n_p) * c->N * 8;
+    if (r.op == HE_REQ_MATMUL) return (size_t)(c->bsgs((int)r.h) + 10) * ct + 3 * lift;
+    return 12 * ct + 2 * lift;
+}
+
+static void serve_loop(he_server* S) {
+    for (;;) {
+        std::vector<Cohort> fresh;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            bool ready = false;
+            for (;;) {
+                if (S->stop && S->pending.empty() && S->active.empty()) return;
+                if (!S->pending.empty()) {
+                    const double age = now_s() - S->reqs[S->pending.front()].t_submit;
+                    ready = S->stop || S->pending.size() >= S->min_batch || age >= S->max_wait_s;
+                    if (ready || !S->active.empty()) break;
+                    S->cv.wait_for(lk, std::chrono::duration<double>(S->max_wait_s - age));
+                } else {
+                    if (!S->active.empty()) break;
+                    S->cv.wait(lk);
+                }
+            }
+            // admission in arrival order while the footprint fits (batching window: a new
+            // cohort starts once min_batch requests wait or the oldest waited max_wait)
+            std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, int>, size_t> slot;
+            while (ready && !S->pending.empty()) {
+                const uint64_t id = S->pending.front();
+                Req& q = S->reqs[id];
+                if (S->budget && S->inflight + q.footprint > S->budget && S->inflight > 0) break;
+                S->pending.pop_front();
+                S->inflight += q.footprint;
+                const int lvl = q.r.op == HE_REQ_MATMUL ? std::min(q.a->level, q.b->level) : q.a->level;
+                const auto key = std::make_tuple(q.r.op, q.r.h, q.r.d, q.r.k, q.r.mode, lvl);
+                auto it = slot.find(key);
+                if (it == slot.end() || fresh[it->second].ids.size() >= S->max_batch) {
+                    Cohort co;
+                    co.op = q.r.op;
+                    if (q.r.op == HE_REQ_MATMUL) {
+                        co.mj.h = (int)q.r.h;
+                        co.mj.lvl = lvl;
+                    } else {
+                        co.sj.d = (int)q.r.d;
+                        co.sj.k = (int)q.r.k;
+                        co.sj.mode = (int)q.r.mode;
+                        co.sj.lvl = lvl;
+                    }
+                    fresh.push_back(co);
+                    slot[key] = fresh.size() - 1;
+                    it = slot.find(key);
+                }
+                Cohort& co = fresh[it->second];
+                co.ids.push_back(id);
+                if (q.r.op == HE_REQ_MATMUL) {
+                    co.mj.A.push_back(q.a);
+                    co.mj.B.push_back(q.b);
+                } else {
+                    co.sj.X.push_back(q.a);
+                }
+            }
+            for (auto& co : fresh) S->active.push_back(std::move(co));
+        }
+        // one round: every active cohort advances one phase
+        std::vector<std::pair<size_t, he_status>> finished;
+        {
+            std::lock_guard<std::recursive_mutex> lk(S->c->api_mu);
+            for (size_t i = 0; i < S->active.size(); ++i) {
+                Cohort& co = S->active[i];
+                try {
+                    const bool done = co.op == HE_REQ_MATMUL ? S->c->matmul_step(co.mj, S->k_chunk) : S->c->sign_step(co.sj);
+                    if (done) finished.push_back({i, HE_OK});
+                } catch (const HeError& e) {
+                    finished.push_back({i, e.s});
+                } catch (...) {
+                    finished.push_back({i, HE_EDEVICE});
+                }
+            }
+            if (hipStreamSynchronize(S->c->stream) != hipSuccess) {
+                (void)hipGetLastError();
+                for (size_t i = 0; i < S->active.size(); ++i) finished.push_back({i, HE_EDEVICE});
+            }
+        }
+        const double t = now_s();
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            std::vector<bool> drop(S->active.size(), false);
+            for (auto& f : finished) {
+                if (drop[f.first]) continue;
+                drop[f.first] = true;
+                Cohort& co = S->active[f.first];
+                auto& res = co.op == HE_REQ_MATMUL ? co.mj.result : co.sj.result;
+                for (size_t m = 0; m < co.ids.size(); ++m) {
+                    Req& q = S->reqs[co.ids[m]];
+                    q.status = f.second;
+                    if (f.second == HE_OK && m < res.size()) q.result = res[m];
+                    q.done = true;
+                    q.t_done = t;
+                    q.keep_a.reset();
+                    q.keep_b.reset();
+                    S->inflight -= q.footprint;
+                }
+            }
+            std::vector<Cohort> keep;
+            for (size_t i = 0; i < S->active.size(); ++i)
+                if (!drop[i]) keep.push_back(std::move(S->active[i]));
+            S->active.swap(keep);
+        }
+        S->cv.notify_all();
+    }
+}
+
+extern "C" {
+
+he_status he_serve_start(he_ctx* ctx, const he_serve_config* cfg, he_server** out) {
+    if (!ctx || !out) return HE_EINVAL;
+    auto* S = new he_server();
+    S->ctx = ctx;
+    S->c = ctx->c.get();
+    if (cfg) {
+        S->budget = cfg->mem_budget_bytes;
+        if (cfg->max_batch) S->max_batch = cfg->max_batch;
+        if (cfg->min_batch) S->min_batch = std::min(cfg->min_batch, S->max_batch);
+        S->max_wait_s = cfg->max_wait_us * 1e-6;
+    }
+    S->th = std::thread(serve_loop, S);
+    *out = S;
+    return HE_OK;
+}
+
+he_status he_serve_submit(he_server* S, const he_request* req, uint64_t* ticket) {
+    if (!S || !req || !ticket || !req->a) return HE_EINVAL;
+    if (req->op == HE_REQ_MATMUL && !req->b) return HE_EINVAL;
+    if (req->op > HE_REQ_SIGN) return HE_EINVAL;
+    if (req->a->ctx != S->c || (req->b && req->b->ctx != S->c)) return HE_EMISMATCH;
+    Req q;
+    q.r = *req;
+    q.a = req->a->c.get();
+    q.b = req->b ? req->b->c.get() : nullptr;
+    q.keep_a = req->a->c;
+    if (req->b) q.keep_b = req->b->c;
+    // validate what the device would reject, before queueing
+    if (q.r.op == HE_REQ_MATMUL) {
+        const int h = (int)q.r.h;
+        if (h < 1 || (h & (h - 1)) || (int64_t)h * h > S->c->N / 2) return HE_ESHAPE;
+        if (std::min(q.a->level, q.b->level) < 3) return HE_ELEVEL;
+        if (q.a->deg != 1 || q.b->deg != 1) return HE_EMISMATCH;
+        int lg = 0;
+        while ((1 << lg) < h) ++lg;
+        if (!(S->c->prepared_mask.load() & (1u << lg))) {  // first request of this h: make keys and masks
+            std::lock_guard<std::recursive_mutex> lk(S->c->api_mu);
+            try {
+                S->c->prepare_h(h);
+            } catch (const HeError& e) {
+                return e.s;
+            }
+        }
+    } else {
+        if (q.r.d < 1 || q.r.d > 7 || q.r.mode > 1) return HE_EINVAL;
+        int nb = 0;
+        while ((1u << nb) <= q.r.d) ++nb;
+        if (q.a->level < (int)(q.r.k * (nb + 1) + q.r.mode)) return HE_ELEVEL;
+    }
+    const int lvl = q.r.op == HE_REQ_MATMUL ? std::min(q.a->level, q.b->level) : q.a->level;
+    q.footprint = footprint(S->c, q.r, lvl);
+    if (S->budget && q.footprint > S->budget) return HE_ENOMEM;
+    q.t_submit = std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->stop) return HE_EINVAL;
+        const uint64_t id = S->next_id++;
+        S->reqs[id] = std::move(q);
+        S->pending.push_back(id);
+        *ticket = id;
+    }
+    S->cv.notify_all();
+    return HE_OK;
+}
+
+he_status he_serve_poll(he_server* S, uint64_t ticket, int* done, he_ct** result, he_status* req_status,
+                        double* latency_s) {
+    if (!S || !done) return HE_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end() || it->second.taken) return HE_EINVAL;
+    Req& q = it->second;
+    *done = q.done ? 1 : 0;
+    if (!q.done) return HE_OK;
+    if (req_status) *req_status = q.status;
+    if (latency_s) *latency_s = q.t_done - q.t_submit;
+    if (result) *result = (q.status == HE_OK && q.result) ? wrap(S->c, q.result) : nullptr;
+    q.taken = true;
+    q.result.reset();
+    S->reqs.erase(it);
+    return HE_OK;
+}
+
+he_status he_serve_stop(he_server* S) {
+    if (!S) return HE_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    if (S->th.joinable()) S->th.join();
+    {
+        std::lock_guard<std::recursive_mutex> lk(S->c->api_mu);
+        delete S;
+    }
+    return HE_OK;
+}
+
+}  // extern "C"

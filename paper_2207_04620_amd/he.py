@@ -43,7 +43,8 @@ class _Device(C.Structure):
 
 
 class _ServeConfig(C.Structure):
-    _fields_ = [("mem_budget_bytes", C.c_uint64), ("max_batch", C.c_uint32)]
+    _fields_ = [("mem_budget_bytes", C.c_uint64), ("max_batch", C.c_uint32), ("min_batch", C.c_uint32),
+                ("max_wait_us", C.c_uint32)]
 
 
 class _Request(C.Structure):
@@ -89,6 +90,8 @@ SIGNATURES = {
                                   C.POINTER(C.c_uint32), C.POINTER(C.c_void_p)]),
     "he_sign_approx": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32,
                                  C.POINTER(C.c_void_p)]),
+    "he_sign_approx_batch": (C.c_int, [C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p), C.c_uint32, C.c_uint32,
+                                       C.c_uint32, C.POINTER(C.c_void_p)]),
     "he_ntt": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(C.c_uint32), C.c_int]),
     "he_serve_start": (C.c_int, [C.c_void_p, C.POINTER(_ServeConfig), C.POINTER(C.c_void_p)]),
     "he_serve_submit": (C.c_int, [C.c_void_p, C.POINTER(_Request), C.POINTER(C.c_uint64)]),
@@ -311,6 +314,13 @@ class Context:
     def sign_approx(self, x, d, k, mode=SIGN):
         return self._ct(lib().he_sign_approx, x.ptr, int(d), int(k), int(mode))
 
+    def sign_approx_batch(self, xs, d, k, mode=SIGN):
+        n = len(xs)
+        px = (C.c_void_p * n)(*[x.ptr for x in xs])
+        out = (C.c_void_p * n)()
+        _chk(lib().he_sign_approx_batch(self.ptr, n, px, int(d), int(k), int(mode), out), "he_sign_approx_batch")
+        return [Ciphertext(self, out[i]) for i in range(n)]
+
     def ntt(self, dev_tensor, mod_idx, inverse=False):
         """in-place limb-batched NTT of a (n_limbs, N) uint64/int64 torch tensor on the GPU"""
         n_limbs = dev_tensor.shape[0]
@@ -321,9 +331,9 @@ class Context:
 class Server:
     """Continuous-batching request loop of libhe (he_serve_*)."""
 
-    def __init__(self, ctx: Context, mem_budget_bytes=0, max_batch=0):
+    def __init__(self, ctx: Context, mem_budget_bytes=0, max_batch=0, min_batch=0, max_wait_us=0):
         self.ctx = ctx
-        cfg = _ServeConfig(mem_budget_bytes, max_batch)
+        cfg = _ServeConfig(mem_budget_bytes, max_batch, min_batch, max_wait_us)
         out = C.c_void_p()
         _chk(lib().he_serve_start(ctx.ptr, C.byref(cfg), C.byref(out)), "he_serve_start")
         self.ptr = out.value

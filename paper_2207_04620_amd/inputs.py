@@ -101,3 +101,8 @@ def residues(seed: int, shape, moduli) -> np.ndarray:
     for i, q in enumerate(moduli):
         out[..., i, :] = rng.integers(0, q, size=out[..., i, :].shape, dtype=np.uint64)
     return out
+
+
+def poisson_arrivals(seed: int, rate_per_s: float, count: int) -> np.ndarray:
+    """arrival times (seconds from 0) of a Poisson process with the given rate"""
+    return np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate_per_s, size=count))
