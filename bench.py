@@ -24,12 +24,13 @@ import numpy as np  # noqa: E402
 METRIC = "ct×ct h=64 HE-matmuls/s at N=2^15 vs plain path; p50/p99 serve latency"
 HBM_PEAK_GBS = 8000.0
 # ALU peak of the NTT butterfly on gfx950, from unit counts and clock: 256 CUs x 4 SIMD
-# x 16 lanes x 2.4 GHz = 39.32 T 32-bit lane-ops/s.  One lazy Shoup butterfly compiles to
-# 10 integer multiplies (v_mad_u64_u32 / v_mul_lo_u32 / v_mul_hi_u32, quarter rate: 4 slots
-# each) and 24.4 other VALU ops (full rate), i.e. 64.4 lane-slots.
+# x 16 lanes x 2.4 GHz = 39.32 T VALU lane-instructions/s.  One lazy Shoup butterfly
+# (x' = x - 2q if x >= 2q; t = x1 w - floor(x1 w' / 2^64) q; (x' + t, x' - t + 2q)) is 28 VALU
+# instructions on gfx950: 10 integer multiplies (v_mad_u64_u32, v_mul_lo_u32, v_mul_hi_u32)
+# and 18 adds/subtracts/compares/selects/moves, all issued at the full rate.
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
-BFLY_SLOTS = 10 * 4 + 24.4
-NTT_PEAK_GBFLY = VALU_LANE_OPS / BFLY_SLOTS / 1e9
+BFLY_INSTR = 28
+NTT_PEAK_GBFLY = VALU_LANE_OPS / BFLY_INSTR / 1e9
 NTT_KERNELS = ("ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols")
 
 

@@ -139,7 +139,8 @@ std::shared_ptr<DBuf> Ctx::g_lift(const Grp& a, int poly) {
 
 // ModDown(<lift o sigma_g, key>) (+ add) into out, for every member
 void Ctx::g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, const u64* add0, const u64* add1,
-                     int64_t add_cs, u64* out0, u64* out1, int64_t out_cs, u64 add_g) {
+                     int64_t add_cs, u64* out0, u64* out1, int64_t out_cs, u64 add_g, const u64* mask,
+                     const u64* acc0, const u64* acc1, int64_t acc_cs) {
     const int nl = level + 1, ne = nl + n_p;
     const int beta = (int)mu[level].size();
     const int64_t ucs = 2 * (int64_t)ne * N, ccs = 2 * (int64_t)nl * N;
@@ -224,6 +225,10 @@ void Ctx::g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, c
     E.pinv = d_pinv->p;
     E.pinv_sh = d_pinv->p + n_q;
     E.g = add_g;
+    E.mask = mask;
+    E.acc[0] = acc0;
+    E.acc[1] = acc1;
+    E.acc_cs = acc_cs;
     launch_ntt_moddown(T, J, E, stream);
     cnt[C_KS] += B;
 }
@@ -234,8 +239,30 @@ Grp Ctx::g_rotate_from_lift(const Grp& a, const u64* lift, int64_t k) {
     const u64* key = rot_key(g, false);
     Grp out = g_new(a.B, a.level, 1, a.scale);
     // out0 = ModDown(.) + sigma_g(c0): the automorphism of c0 is a gather in the epilogue
-    g_ks_apply(lift, a.B, a.level, key, g, a.p, nullptr, a.cs, out.p, out.p + out.ps, out.cs, g);
+    g_ks_apply(lift, a.B, a.level, key, g, a.p, nullptr, a.cs, out.p, out.p + out.ps, out.cs, g, nullptr, nullptr,
+               nullptr, 0);
     cnt[C_ROT] += a.B;
+    return out;
+}
+
+// Rot(a, k) . mask (+ acc): the Mul_pt (and the Add of a diagonal sum) fused into the
+// rotation's ModDown epilogue; exact residues, so identical to rotating then masking
+Grp Ctx::g_rotate_mask_from_lift(const Grp& a, const u64* lift, int64_t k, const u64* mask, double mask_scale,
+                                 const Grp* acc) {
+    const u64 g = galois(k);
+    if (g == 1) throw HeError(HE_EUNSUPPORTED);
+    const u64* key = rot_key(g, false);
+    std::vector<double> sc(a.scale);
+    for (auto& v : sc) v *= mask_scale;
+    Grp out = g_new(a.B, a.level, 1, sc);
+    g_ks_apply(lift, a.B, a.level, key, g, a.p, nullptr, a.cs, out.p, out.p + out.ps, out.cs, g, mask,
+               acc ? acc->p : nullptr, acc ? acc->p + acc->ps : nullptr, acc ? acc->cs : 0);
+    cnt[C_ROT] += a.B;
+    cnt[C_MULPT] += a.B;
+    if (acc) {
+        cnt[C_ADD] += a.B;
+        for (int i = 0; i < a.B; ++i) out.scale[i] = std::max(out.scale[i], acc->scale[i]);
+    }
     return out;
 }
 
@@ -334,7 +361,8 @@ Grp Ctx::g_relin(const Grp& a) {
     const u64* key = relin_key();
     auto lift = g_lift(a, 2);
     Grp out = g_new(a.B, a.level, 1, a.scale);
-    g_ks_apply(lift->p, a.B, a.level, key, 1, a.p, a.p + a.ps, a.cs, out.p, out.p + out.ps, out.cs, 1);
+    g_ks_apply(lift->p, a.B, a.level, key, 1, a.p, a.p + a.ps, a.cs, out.p, out.p + out.ps, out.cs, 1, nullptr,
+               nullptr, nullptr, 0);
     return out;
 }
 
@@ -418,9 +446,9 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
             if (k == 0) {
                 Ak = g_mask_sum({{&J.A0, mask(2, h, 0, 0)}}, ms);
             } else {
-                Grp r1 = g_rotate_from_lift(J.A0, J.liftA->p, k);
-                Grp r2 = g_rotate_from_lift(J.A0, J.liftA->p, k - h);
-                Ak = g_mask_sum({{&r1, mask(2, h, k, 0)}, {&r2, mask(3, h, k, 0)}}, ms);
+                // v_k . Rot(A0, k) + v_{k-h} . Rot(A0, k-h), masks applied in the ModDown epilogues
+                Grp t1 = g_rotate_mask_from_lift(J.A0, J.liftA->p, k, mask(2, h, k, 0), ms, nullptr);
+                Ak = g_rotate_mask_from_lift(J.A0, J.liftA->p, k - h, mask(3, h, k, 0), ms, &t1);
             }
             Ak = g_rescale(Ak);
             Grp Bk = k ? g_rotate_from_lift(J.B0, J.liftB->p, (int64_t)h * k) : J.B0;

@@ -178,7 +178,10 @@ struct Ctx {
     void g_add_into(Grp& acc, const Grp& t);
     std::shared_ptr<DBuf> g_lift(const Grp& a, int poly);
     void g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, const u64* add0, const u64* add1,
-                    int64_t add_cs, u64* out0, u64* out1, int64_t out_cs, u64 add_g);
+                    int64_t add_cs, u64* out0, u64* out1, int64_t out_cs, u64 add_g, const u64* mask,
+                    const u64* acc0, const u64* acc1, int64_t acc_cs);
+    Grp g_rotate_mask_from_lift(const Grp& a, const u64* lift, int64_t k, const u64* mask, double mask_scale,
+                                const Grp* acc);
     Grp g_rotate_from_lift(const Grp& a, const u64* lift, int64_t k);
     Grp g_rotate(const Grp& a, int64_t k);
     Grp g_mask_sum(const std::vector<std::pair<const Grp*, const u64*>>& terms, double mask_scale);

@@ -108,8 +108,19 @@ std::string prof_report() {
 
 __device__ __forceinline__ u64 red4(u64 x, u64 q2) { return x >= q2 ? x - q2 : x; }
 
-// stages s0 .. s0+R-1 of a length-2^L forward transform; each thread owns 8/2^R groups
-template <int R>
+// LDS address of element a: the row pass inserts one pad word every 32 words, which
+// spreads the strided accesses of its later rounds over the banks (16-way -> 4-way
+// conflicts at distance 4, 8-way -> 2-way at distance 1); the column pass needs none.
+template <bool PAD>
+__device__ __forceinline__ int lds_at(int a) {
+    return PAD ? a + (a >> 5) : a;
+}
+#define NTT_LDS (NTT_E + NTT_E / 32)
+
+// stages s0 .. s0+R-1 of a length-2^L forward transform; each thread owns 8/2^R groups of
+// 2^R elements.  Within a group, stage s0+r has 2^r distinct twiddles (one per block of
+// 2*half consecutive elements), loaded once each.
+template <int R, bool PAD>
 __device__ __forceinline__ void fwd_round(u64* s, int L, int s0, int logT, u64 X, const u64* __restrict__ W,
                                           const u64* __restrict__ Ws, u64 q) {
     constexpr int G = 1 << R, NG = 8 / G;
@@ -122,28 +133,31 @@ __device__ __forceinline__ void fwd_round(u64* s, int L, int s0, int logT, u64 X
         const int base = ((gi >> ld) << (ld + R)) + (gi & (d - 1));
         u64 x[G];
 #pragma unroll
-        for (int k = 0; k < G; ++k) x[k] = s[((base + k * d) << logT) + u];
+        for (int k = 0; k < G; ++k) x[k] = s[lds_at<PAD>(((base + k * d) << logT) + u)];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int st = s0 + r, half = G >> (r + 1);
+            const int st = s0 + r;
+            const int half = G >> (r + 1);
 #pragma unroll
-            for (int k = 0; k < G; ++k) {
-                if (k & half) continue;
-                const int j = base + k * d;
-                const int idx = (int)(X << st) + (j >> (L - st));
-                const u64 U = red4(x[k], q2);
-                const u64 V = mul_shoup_lazy(x[k + half], W[idx], Ws[idx], q);
-                x[k] = U + V;
-                x[k + half] = U - V + q2;
+            for (int b = 0; b < (1 << r); ++b) {
+                const int idx = (int)(X << st) + ((base + b * 2 * half * d) >> (L - st));
+                const u64 w = W[idx], ws = Ws[idx];
+#pragma unroll
+                for (int k = b * 2 * half; k < b * 2 * half + half; ++k) {
+                    const u64 U = red4(x[k], q2);
+                    const u64 V = mul_shoup_lazy(x[k + half], w, ws, q);
+                    x[k] = U + V;
+                    x[k + half] = U - V + q2;
+                }
             }
         }
 #pragma unroll
-        for (int k = 0; k < G; ++k) s[((base + k * d) << logT) + u] = x[k];
+        for (int k = 0; k < G; ++k) s[lds_at<PAD>(((base + k * d) << logT) + u)] = x[k];
     }
 }
 
 // stages s0 .. s0-R+1 (descending) of a length-2^L inverse transform
-template <int R>
+template <int R, bool PAD>
 __device__ __forceinline__ void inv_round(u64* s, int L, int s0, int logT, u64 X, const u64* __restrict__ W,
                                           const u64* __restrict__ Ws, u64 q) {
     constexpr int G = 1 << R, NG = 8 / G;
@@ -157,53 +171,57 @@ __device__ __forceinline__ void inv_round(u64* s, int L, int s0, int logT, u64 X
         const int base = ((gi >> ld) << (ld + R)) + (gi & (d - 1));
         u64 x[G];
 #pragma unroll
-        for (int k = 0; k < G; ++k) x[k] = s[((base + k * d) << logT) + u];
+        for (int k = 0; k < G; ++k) x[k] = s[lds_at<PAD>(((base + k * d) << logT) + u)];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int st = s0 - r, half = 1 << r;
 #pragma unroll
-            for (int k = 0; k < G; ++k) {
-                if (k & half) continue;
-                const int j = base + k * d;
-                const int idx = (int)(X << st) + (j >> (L - st));
-                const u64 U = x[k], V = x[k + half];
-                x[k] = red4(U + V, q2);
-                x[k + half] = mul_shoup_lazy(U - V + q2, W[idx], Ws[idx], q);
+            for (int b = 0; b < (G >> (r + 1)); ++b) {
+                const int idx = (int)(X << st) + ((base + b * 2 * half * d) >> (L - st));
+                const u64 w = W[idx], ws = Ws[idx];
+#pragma unroll
+                for (int k = b * 2 * half; k < b * 2 * half + half; ++k) {
+                    const u64 U = x[k], V = x[k + half];
+                    x[k] = red4(U + V, q2);
+                    x[k + half] = mul_shoup_lazy(U - V + q2, w, ws, q);
+                }
             }
         }
 #pragma unroll
-        for (int k = 0; k < G; ++k) s[((base + k * d) << logT) + u] = x[k];
+        for (int k = 0; k < G; ++k) s[lds_at<PAD>(((base + k * d) << logT) + u)] = x[k];
     }
 }
 
+template <bool PAD>
 __device__ __forceinline__ void fwd_all(u64* s, int L, int logT, u64 X, const u64* W, const u64* Ws, u64 q) {
     int st = 0;
     while (L - st >= 3) {
-        fwd_round<3>(s, L, st, logT, X, W, Ws, q);
+        fwd_round<3, PAD>(s, L, st, logT, X, W, Ws, q);
         __syncthreads();
         st += 3;
     }
     if (L - st == 2) {
-        fwd_round<2>(s, L, st, logT, X, W, Ws, q);
+        fwd_round<2, PAD>(s, L, st, logT, X, W, Ws, q);
         __syncthreads();
     } else if (L - st == 1) {
-        fwd_round<1>(s, L, st, logT, X, W, Ws, q);
+        fwd_round<1, PAD>(s, L, st, logT, X, W, Ws, q);
         __syncthreads();
     }
 }
 
+template <bool PAD>
 __device__ __forceinline__ void inv_all(u64* s, int L, int logT, u64 X, const u64* W, const u64* Ws, u64 q) {
     int st = L - 1;  // highest stage first
     while (st + 1 >= 3) {
-        inv_round<3>(s, L, st, logT, X, W, Ws, q);
+        inv_round<3, PAD>(s, L, st, logT, X, W, Ws, q);
         __syncthreads();
         st -= 3;
     }
     if (st + 1 == 2) {
-        inv_round<2>(s, L, st, logT, X, W, Ws, q);
+        inv_round<2, PAD>(s, L, st, logT, X, W, Ws, q);
         __syncthreads();
     } else if (st + 1 == 1) {
-        inv_round<1>(s, L, st, logT, X, W, Ws, q);
+        inv_round<1, PAD>(s, L, st, logT, X, W, Ws, q);
         __syncthreads();
     }
 }
@@ -221,7 +239,7 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_cols(DevTables T, Jobs J) {
     const int c0 = blockIdx.x * C;
     for (int e = threadIdx.x; e < NTT_E; e += TPB) s[e] = a[(int64_t)(e >> logC) * N2 + c0 + (e & (C - 1))];
     __syncthreads();
-    fwd_all(s, L1, logC, 1, W, Ws, q);
+    fwd_all<false>(s, L1, logC, 1, W, Ws, q);
     // output stays lazy in [0, 4q) for the row pass
     for (int e = threadIdx.x; e < NTT_E; e += TPB) a[(int64_t)(e >> logC) * N2 + c0 + (e & (C - 1))] = s[e];
 }
@@ -229,7 +247,7 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_cols(DevTables T, Jobs J) {
 __device__ __forceinline__ int perm_g(int j, u64 g, int log_n);
 
 __global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E) {
-    __shared__ u64 s[NTT_E];
+    __shared__ u64 s[NTT_LDS];
     const int N = 1 << T.log_n, L1 = T.n1_log, L2 = T.n2_log, N1 = 1 << L1, N2 = 1 << L2;
     const int job = blockIdx.y, c = job / J.n, k = job % J.n;
     const int r = blockIdx.x;
@@ -238,10 +256,10 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E
     const u64 q = T.mods[mi].q, q2 = 2 * q;
     const u64* W = T.psi + (int64_t)mi * N;
     const u64* Ws = T.psi_sh + (int64_t)mi * N;
-    for (int e = threadIdx.x; e < N2; e += TPB) s[e] = a[e];
+    for (int e = threadIdx.x; e < N2; e += TPB) s[lds_at<true>(e)] = a[e];
     __syncthreads();
     if (N2 == NTT_E) {
-        fwd_all(s, L2, 0, (u64)(N1 + r), W, Ws, q);
+        fwd_all<true>(s, L2, 0, (u64)(N1 + r), W, Ws, q);
     } else {  // small rings: plain radix-2 stages (N2 < 2048 only when N < 2048)
         for (int st = 0; st < L2; st++) {
             const int lt = L2 - st - 1, t = 1 << lt;
@@ -249,17 +267,17 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E
                 const int i = b >> lt, j = b & (t - 1);
                 const int j1 = (i << (lt + 1)) + j;
                 const int idx = (1 << st) * (N1 + r) + i;
-                const u64 U = red4(s[j1], q2);
-                const u64 V = mul_shoup_lazy(s[j1 + t], W[idx], Ws[idx], q);
-                s[j1] = U + V;
-                s[j1 + t] = U - V + q2;
+                const u64 U = red4(s[lds_at<true>(j1)], q2);
+                const u64 V = mul_shoup_lazy(s[lds_at<true>(j1 + t)], W[idx], Ws[idx], q);
+                s[lds_at<true>(j1)] = U + V;
+                s[lds_at<true>(j1 + t)] = U - V + q2;
             }
             __syncthreads();
         }
     }
     if (!E.on) {
         for (int e = threadIdx.x; e < N2; e += TPB) {
-            u64 v = red4(s[e], q2);
+            u64 v = red4(s[lds_at<true>(e)], q2);
             a[e] = v >= q ? v - q : v;
         }
         return;
@@ -269,19 +287,24 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E
     const u64* add = E.add[p] ? E.add[p] + c * E.add_cs + (int64_t)t * N : nullptr;
     u64* out = E.out[p] + c * E.out_cs + (int64_t)t * N;
     const u64 pi = E.pinv[t], pis = E.pinv_sh[t];
+    const u64* mask = E.mask ? E.mask + (int64_t)t * N : nullptr;
+    const u64* acc = E.acc[p] ? E.acc[p] + c * E.acc_cs + (int64_t)t * N : nullptr;
+    const u64 qninv = T.mods[mi].qninv;
     for (int e = threadIdx.x; e < N2; e += TPB) {
-        u64 v = red4(s[e], q2);
+        u64 v = red4(s[lds_at<true>(e)], q2);
         v = v >= q ? v - q : v;
         const int i = r * N2 + e;
         u64 w = mul_shoup(sub_mod(u[i], v, q), pi, pis, q);
         if (add) w = add_mod(w, add[E.g == 1 ? i : perm_g(i, E.g, T.log_n)], q);
+        if (mask) w = mul_mont(w, mask[i], q, qninv);
+        if (acc) w = add_mod(w, acc[i], q);
         out[i] = w;
     }
 }
 
 // Inverse transform: Gentleman-Sande, bit-reversed input, natural output, then N^-1.
 __global__ __launch_bounds__(TPB) void k_ntt_inv_rows(DevTables T, Jobs J) {
-    __shared__ u64 s[NTT_E];
+    __shared__ u64 s[NTT_LDS];
     const int N = 1 << T.log_n, L1 = T.n1_log, L2 = T.n2_log, N1 = 1 << L1, N2 = 1 << L2;
     const int job = blockIdx.y, c = job / J.n, k = job % J.n;
     const int r = blockIdx.x;
@@ -291,10 +314,10 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_rows(DevTables T, Jobs J) {
     const u64 q = mp_.q, q2 = 2 * q;
     const u64* W = T.ipsi + (int64_t)mi * N;
     const u64* Ws = T.ipsi_sh + (int64_t)mi * N;
-    for (int e = threadIdx.x; e < N2; e += TPB) s[e] = a[e];
+    for (int e = threadIdx.x; e < N2; e += TPB) s[lds_at<true>(e)] = a[e];
     __syncthreads();
     if (N2 == NTT_E) {
-        inv_all(s, L2, 0, (u64)(N1 + r), W, Ws, q);
+        inv_all<true>(s, L2, 0, (u64)(N1 + r), W, Ws, q);
     } else {
         for (int st = L2 - 1; st >= 0; st--) {
             const int lt = L2 - st - 1, t = 1 << lt;
@@ -302,17 +325,17 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_rows(DevTables T, Jobs J) {
                 const int i = b >> lt, j = b & (t - 1);
                 const int j1 = (i << (lt + 1)) + j;
                 const int idx = (1 << st) * (N1 + r) + i;
-                const u64 U = s[j1], V = s[j1 + t];
-                s[j1] = red4(U + V, q2);
-                s[j1 + t] = mul_shoup_lazy(U - V + q2, W[idx], Ws[idx], q);
+                const u64 U = s[lds_at<true>(j1)], V = s[lds_at<true>(j1 + t)];
+                s[lds_at<true>(j1)] = red4(U + V, q2);
+                s[lds_at<true>(j1 + t)] = mul_shoup_lazy(U - V + q2, W[idx], Ws[idx], q);
             }
             __syncthreads();
         }
     }
     if (L1 == 0) {
-        for (int e = threadIdx.x; e < N2; e += TPB) a[e] = mul_shoup(s[e], mp_.ninv, mp_.ninv_sh, q);
+        for (int e = threadIdx.x; e < N2; e += TPB) a[e] = mul_shoup(s[lds_at<true>(e)], mp_.ninv, mp_.ninv_sh, q);
     } else {
-        for (int e = threadIdx.x; e < N2; e += TPB) a[e] = s[e];  // lazy in [0, 2q)
+        for (int e = threadIdx.x; e < N2; e += TPB) a[e] = s[lds_at<true>(e)];  // lazy in [0, 2q)
     }
 }
 
@@ -330,7 +353,7 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_cols(DevTables T, Jobs J) {
     const int c0 = blockIdx.x * C;
     for (int e = threadIdx.x; e < NTT_E; e += TPB) s[e] = a[(int64_t)(e >> logC) * N2 + c0 + (e & (C - 1))];
     __syncthreads();
-    inv_all(s, L1, logC, 1, W, Ws, q);
+    inv_all<false>(s, L1, logC, 1, W, Ws, q);
     for (int e = threadIdx.x; e < NTT_E; e += TPB)
         a[(int64_t)(e >> logC) * N2 + c0 + (e & (C - 1))] = mul_shoup(s[e], mp_.ninv, mp_.ninv_sh, q);
 }
@@ -382,33 +405,40 @@ void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st)
 // out_t = sum_s y_s (D/q_s) mod q_t, accumulated in 128 bits and reduced once (REDC).
 template <int NS>
 __global__ __launch_bounds__(TPB) void k_baseconv(DevTables T, ConvDesc D) {
+    // the block's slice of the constant table (NS sources x up to 8 targets) goes to LDS once
+    __shared__ u64 tab[NS * 8 * 2];
+    __shared__ ModP tm[8];
     const int N = 1 << T.log_n;
     const int i = blockIdx.x * TPB + threadIdx.x;
     const int p = blockIdx.z % D.npoly, c = blockIdx.z / D.npoly;
-    const int t0 = blockIdx.y * 8, t1 = min(D.nt, t0 + 8);
+    const int t0 = blockIdx.y * 8, nt = min(D.nt - t0, 8);
+    for (int e = threadIdx.x; e < NS * nt * 2; e += TPB) {
+        const int sI = e / (nt * 2), rem = e % (nt * 2), tt = rem >> 1, w = rem & 1;
+        tab[(sI * 8 + tt) * 2 + w] = D.tab[((int64_t)sI * D.tab_ld + D.tcol[t0 + tt]) * 2 + w];
+    }
+    if (threadIdx.x < nt) tm[threadIdx.x] = T.mods[D.dmod[t0 + threadIdx.x]];
+    __syncthreads();
     if (i >= N) return;
     u64 y[NS];
-    bool neg[NS];
+    u64 negm[NS];
     const u64* src = D.src + c * D.src_cstride + p * D.src_pstride;
 #pragma unroll
     for (int s = 0; s < NS; s++) {
         const ModP m = T.mods[D.smod[s]];
         const u64 v = mul_shoup(src[(int64_t)s * N + i], D.hinv[s], D.hinv_sh[s], m.q);
         y[s] = v;
-        neg[s] = v > m.half;
+        negm[s] = v > m.half ? ~0ull : 0ull;
     }
     u64* dst = D.dst + c * D.dst_cstride + p * D.dst_pstride;
-    for (int t = t0; t < t1; t++) {
-        const ModP m = T.mods[D.dmod[t]];
-        const u64* e = D.tab + (int64_t)D.tcol[t] * 2;
+    for (int tt = 0; tt < nt; tt++) {
+        const ModP m = tm[tt];
         Acc128 acc = {0, 0};
 #pragma unroll
         for (int s = 0; s < NS; s++) {
-            const u64* es = e + (int64_t)s * D.tab_ld * 2;
-            mac128(acc, y[s], es[0]);
-            if (neg[s]) add128(acc, es[1]);
+            mac128(acc, y[s], tab[(s * 8 + tt) * 2]);
+            add128(acc, tab[(s * 8 + tt) * 2 + 1] & negm[s]);
         }
-        dst[(int64_t)D.doff[t] * N + i] = redc(acc.lo, acc.hi, m.q, m.qninv);
+        dst[(int64_t)D.doff[t0 + tt] * N + i] = redc(acc.lo, acc.hi, m.q, m.qninv);
     }
 }
 

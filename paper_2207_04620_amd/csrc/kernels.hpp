@@ -115,6 +115,11 @@ struct Epi {
     const u64* pinv;
     const u64* pinv_sh;
     u64 g;
+    // optional Mul_pt fused into the epilogue: out = w * mask (Montgomery form, [n_q][N])
+    // (+ acc_p[c][t][i] when acc_p is set): one term of a diagonal sum (Eq. 1)
+    const u64* mask;
+    const u64* acc[2];
+    int64_t acc_cs;
 };
 
 // ------------------------------------------------------------------ launch timing

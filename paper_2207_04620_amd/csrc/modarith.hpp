@@ -66,8 +66,19 @@ __device__ __forceinline__ u64 to_mont(u64 a, const ModP& m) { return redc(a * m
 struct Acc128 {
     u64 lo, hi;
 };
+// full 64x64 -> 128 product from four 32x32 -> 64 partial products (v_mad_u64_u32),
+// the carries folded into the multiply-adds
+__device__ __forceinline__ void mul_wide(u64 a, u64 b, u64& lo, u64& hi) {
+    const u32 a0 = (u32)a, a1 = (u32)(a >> 32), b0 = (u32)b, b1 = (u32)(b >> 32);
+    const u64 p00 = (u64)a0 * b0;
+    const u64 t = (u64)a0 * b1 + (p00 >> 32);          // < 2^64
+    const u64 u = (u64)a1 * b0 + (u32)t;               // < 2^64
+    lo = (u << 32) | (u32)p00;
+    hi = (u64)a1 * b1 + (t >> 32) + (u >> 32);
+}
 __device__ __forceinline__ void mac128(Acc128& acc, u64 a, u64 b) {
-    u64 lo = a * b, hi = __umul64hi(a, b);
+    u64 lo, hi;
+    mul_wide(a, b, lo, hi);
     acc.lo += lo;
     acc.hi += hi + (acc.lo < lo ? 1 : 0);
 }
