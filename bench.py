@@ -34,6 +34,20 @@ NTT_PEAK_GBFLY = VALU_LANE_OPS / BFLY_INSTR / 1e9
 NTT_KERNELS = ("ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols")
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed PMC summary, if the kernel sources are the
+    ones the counters were taken on (else None)."""
+    import hashlib
+    f = os.path.join(ROOT, "profiles", f"{kernel}_c3_h64_batch16.traffic.json")
+    if not os.path.exists(f):
+        return None
+    rec = json.load(open(f))
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -107,15 +121,17 @@ def main():
     ctx.sync()
 
     # plain path: one product at a time
-    log("plain path")
-    ctx.matmul(As[0], Bs[0], h)
-    ctx.sync()
-    t0 = time.perf_counter()
-    for i in range(args.plain_iters):
-        ctx.matmul(As[i % args.batch], Bs[i % args.batch], h)
-    ctx.sync()
-    plain_s = (time.perf_counter() - t0) / args.plain_iters
-    log(f"plain {plain_s * 1e3:.1f} ms per product")
+    plain_s = float("nan")
+    if args.plain_iters > 0:
+        log("plain path")
+        ctx.matmul(As[0], Bs[0], h)
+        ctx.sync()
+        t0 = time.perf_counter()
+        for i in range(args.plain_iters):
+            ctx.matmul(As[i % args.batch], Bs[i % args.batch], h)
+        ctx.sync()
+        plain_s = (time.perf_counter() - t0) / args.plain_iters
+        log(f"plain {plain_s * 1e3:.1f} ms per product")
 
     # batched path
     log("batched path: warmup")
@@ -202,11 +218,14 @@ def main():
     if dom in NTT_KERNELS:
         achieved = d["ops"] / max(1, d["launches"]) / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "alu", "achieved": round(achieved, 1), "peak": round(NTT_PEAK_GBFLY, 1),
-                    "unit": "Gbutterfly/s", "frac": round(achieved / NTT_PEAK_GBFLY, 4), "traffic": None}
+                    "unit": "Gbutterfly/s", "frac": round(achieved / NTT_PEAK_GBFLY, 4),
+                    "traffic": measured_traffic(dom) if args.batch == 16 else None,
+                    "algorithmic_bytes_per_launch": round(d["bytes"] / max(1, d["launches"]))}
     else:
         achieved = d["bytes"] / max(1, d["launches"]) / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(dom) if args.batch == 16 else None}
     roofline.update({"kernel": dom, "avg_launch_us": round(avg_ms * 1e3, 2), "launches": d["launches"],
                      "share_of_gpu_time": round(d["ms"] / total_ms, 3),
                      "gpu_busy": round(total_ms / (elapsed * 1e3), 3)})
@@ -225,9 +244,11 @@ def main():
                    "batch": args.batch, "h": h, "log_n": 15,
                    "schedule": "relinearise once per product" if args.schedule == "once" else
                                "relinearise every Step-3 product",
-                   "plain_matmuls_per_s": round(1.0 / plain_s, 4), "plain_ms": round(plain_s * 1e3, 2),
+                   "plain_matmuls_per_s": None if plain_s != plain_s else round(1.0 / plain_s, 4),
+                   "plain_ms": None if plain_s != plain_s else round(plain_s * 1e3, 2),
                    f"batched_matmuls_per_s_relin_{other}": None if other_value is None else round(other_value, 4),
-                   "batched_over_plain": round(value * plain_s, 3), "max_abs_error": err},
+                   "batched_over_plain": None if plain_s != plain_s else round(value * plain_s, 3),
+                   "max_abs_error": err},
         "serve": serve,
         "roofline": roofline,
         "ntt_all_passes": {"achieved": round(ntt_rate, 1), "peak": round(NTT_PEAK_GBFLY, 1), "unit": "Gbutterfly/s",

@@ -140,7 +140,7 @@ std::shared_ptr<DBuf> Ctx::g_lift(const Grp& a, int poly) {
 // ModDown(<lift o sigma_g, key>) (+ add) into out, for every member
 void Ctx::g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, const u64* add0, const u64* add1,
                      int64_t add_cs, u64* out0, u64* out1, int64_t out_cs, u64 add_g, const u64* mask,
-                     const u64* acc0, const u64* acc1, int64_t acc_cs) {
+                     const u64* acc0, const u64* acc1, int64_t acc_cs, const u64* c0, int64_t c0_cs) {
     const int nl = level + 1, ne = nl + n_p;
     const int beta = (int)mu[level].size();
     const int64_t ucs = 2 * (int64_t)ne * N, ccs = 2 * (int64_t)nl * N;
@@ -158,6 +158,10 @@ void Ctx::g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, c
     D.M = n_q + n_p;
     D.g = g;
     for (int t = 0; t < ne; ++t) D.mod[t] = (uint8_t)ext_mod(level, t);
+    D.c0 = c0;
+    D.c0_cs = c0_cs;
+    D.nq = nl;
+    for (int t = 0; t < nl; ++t) D.pmont[t] = hm::to_mont(pmod[t], mods[t]);
     launch_inner_product(T, D, stream);
     {
         Jobs J;
@@ -239,8 +243,8 @@ Grp Ctx::g_rotate_from_lift(const Grp& a, const u64* lift, int64_t k) {
     const u64* key = rot_key(g, false);
     Grp out = g_new(a.B, a.level, 1, a.scale);
     // out0 = ModDown(.) + sigma_g(c0): the automorphism of c0 is a gather in the epilogue
-    g_ks_apply(lift, a.B, a.level, key, g, a.p, nullptr, a.cs, out.p, out.p + out.ps, out.cs, g, nullptr, nullptr,
-               nullptr, 0);
+    g_ks_apply(lift, a.B, a.level, key, g, nullptr, nullptr, 0, out.p, out.p + out.ps, out.cs, g, nullptr, nullptr,
+               nullptr, 0, a.p, a.cs);
     cnt[C_ROT] += a.B;
     return out;
 }
@@ -255,8 +259,8 @@ Grp Ctx::g_rotate_mask_from_lift(const Grp& a, const u64* lift, int64_t k, const
     std::vector<double> sc(a.scale);
     for (auto& v : sc) v *= mask_scale;
     Grp out = g_new(a.B, a.level, 1, sc);
-    g_ks_apply(lift, a.B, a.level, key, g, a.p, nullptr, a.cs, out.p, out.p + out.ps, out.cs, g, mask,
-               acc ? acc->p : nullptr, acc ? acc->p + acc->ps : nullptr, acc ? acc->cs : 0);
+    g_ks_apply(lift, a.B, a.level, key, g, nullptr, nullptr, 0, out.p, out.p + out.ps, out.cs, g, mask,
+               acc ? acc->p : nullptr, acc ? acc->p + acc->ps : nullptr, acc ? acc->cs : 0, a.p, a.cs);
     cnt[C_ROT] += a.B;
     cnt[C_MULPT] += a.B;
     if (acc) {
@@ -362,7 +366,7 @@ Grp Ctx::g_relin(const Grp& a) {
     auto lift = g_lift(a, 2);
     Grp out = g_new(a.B, a.level, 1, a.scale);
     g_ks_apply(lift->p, a.B, a.level, key, 1, a.p, a.p + a.ps, a.cs, out.p, out.p + out.ps, out.cs, 1, nullptr,
-               nullptr, nullptr, 0);
+               nullptr, nullptr, 0, nullptr, 0);
     return out;
 }
 

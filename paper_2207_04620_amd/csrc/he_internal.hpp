@@ -179,7 +179,7 @@ struct Ctx {
     std::shared_ptr<DBuf> g_lift(const Grp& a, int poly);
     void g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, const u64* add0, const u64* add1,
                     int64_t add_cs, u64* out0, u64* out1, int64_t out_cs, u64 add_g, const u64* mask,
-                    const u64* acc0, const u64* acc1, int64_t acc_cs);
+                    const u64* acc0, const u64* acc1, int64_t acc_cs, const u64* c0, int64_t c0_cs);
     Grp g_rotate_mask_from_lift(const Grp& a, const u64* lift, int64_t k, const u64* mask, double mask_scale,
                                 const Grp* acc);
     Grp g_rotate_from_lift(const Grp& a, const u64* lift, int64_t k);

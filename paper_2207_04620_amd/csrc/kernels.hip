@@ -367,8 +367,11 @@ void launch_ntt_moddown(const DevTables& T, const Jobs& J, const Epi& E, hipStre
         ProfScope p(PK_NTT_FWD_COLS, 16.0 * limbs * N, st, limbs * (N / 2) * T.n1_log);
         hipLaunchKernelGGL(k_ntt_fwd_cols, grid_cols, dim3(TPB), 0, st, T, J);
     }
-    // reads the converted limb, u and the gathered add operand; writes the output
-    ProfScope p(PK_NTT_FWD_ROWS, 8.0 * (3 + (E.add[0] ? 1 : 0)) * limbs * N, st, limbs * (N / 2) * T.n2_log);
+    // reads the converted limb and u, writes the output; plus the optional add and
+    // accumulator operands (per ciphertext) and the mask (shared by the group)
+    const double per_ct = (E.add[0] ? 1 : 0) + (E.add[1] ? 1 : 0) + (E.acc[0] ? 1 : 0) + (E.acc[1] ? 1 : 0);
+    const double rows_bytes = 8.0 * N * (3 * limbs + per_ct * E.nl * J.nct + (E.mask ? E.nl : 0));
+    ProfScope p(PK_NTT_FWD_ROWS, rows_bytes, st, limbs * (N / 2) * T.n2_log);
     hipLaunchKernelGGL(k_ntt_fwd_rows, grid_rows, dim3(TPB), 0, st, T, J, E);
 }
 
@@ -678,6 +681,7 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
         kb[j] = D.key[(((int64_t)j * 2 + 0) * D.M + mi) * N + i];
         ka[j] = D.key[(((int64_t)j * 2 + 1) * D.M + mi) * N + i];
     }
+    const bool with_c0 = D.c0 && t < D.nq;
     for (int c = 0; c < D.nct; c++) {
         const u64* lift = D.lift + c * D.lift_cs;
         Acc128 a0 = {0, 0}, a1 = {0, 0};
@@ -686,6 +690,7 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
             mac128(a0, x, kb[j]);
             mac128(a1, x, ka[j]);
         }
+        if (with_c0) mac128(a0, D.c0[c * D.c0_cs + (int64_t)t * N + src], D.pmont[t]);
         u64* u = D.u + c * D.u_cs;
         u[(int64_t)t * N + i] = redc(a0.lo, a0.hi, m.q, m.qninv);
         u[((int64_t)D.ne + t) * N + i] = redc(a1.lo, a1.hi, m.q, m.qninv);
@@ -693,7 +698,10 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
 }
 
 void launch_inner_product(const DevTables& T, const IpDesc& D, hipStream_t st) {
-    ProfScope prof_(PK_INNER, (double)D.ne * (2.0 * D.beta + D.nct * (D.beta + 2.0)) * 8.0 * (1 << T.log_n), st);
+    ProfScope prof_(PK_INNER,
+                    ((double)D.ne * (2.0 * D.beta + D.nct * (D.beta + 2.0)) + (D.c0 ? (double)D.nq * D.nct : 0.0)) * 8.0 *
+                        (1 << T.log_n),
+                    st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), D.ne);
     hipLaunchKernelGGL(k_inner_product, grid, dim3(TPB), 0, st, T, D);

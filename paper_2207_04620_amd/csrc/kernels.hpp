@@ -87,6 +87,12 @@ struct IpDesc {
     int ne, beta, M;
     u64 g;            // Galois element (1 = identity)
     uint8_t mod[HE_MAXT];
+    // optional: u0[t] += P * c0[t][perm_g(i)] on the Q limbs t < nq (c0 of the rotated
+    // ciphertext; ModDown then yields (u0 - conv) P^-1 + sigma_g(c0) exactly)
+    const u64* c0;
+    int64_t c0_cs;
+    int nq;
+    u64 pmont[HE_MAXT];  // (P mod q_t) R mod q_t
 };
 
 struct MacDesc {
