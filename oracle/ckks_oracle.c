@@ -796,15 +796,15 @@ static void modup_digit(const orc_ctx *c, int level, u64 *const *d, int j, int t
 
 /* inner product of lifted digits with the key, then ModDown; d in coefficient form.
  * 'lift' (optional) holds precomputed lifted digits [beta][level+1+K][N] in coefficient form. */
-static void keyswitch_core(orc_ctx *c, int level, u64 *const *d, const u64 *lift, const swk_t *k,
-                           u64 *out0, u64 *out1) {
+/* inner product of the lifted digits with the key over Q_l and P: u0, u1 in coefficient
+ * form, [level+1+K][N] (Q limbs 0..level, then the K special primes) */
+static void ks_inner(orc_ctx *c, int level, u64 *const *d, const u64 *lift, const swk_t *k, u64 *u0, u64 *u1) {
     int64_t N = c->n;
     int nl = level + 1, K = c->n_p, M = c->n_q + c->n_p;
     int beta = (nl + c->alpha - 1) / c->alpha;
     int ext[MAXMOD];
     for (int i = 0; i < nl; i++) ext[i] = i;
     for (int i = 0; i < K; i++) ext[nl + i] = c->n_q + i;
-    u64 *u0 = malloc(sizeof(u64) * (nl + K) * N), *u1 = malloc(sizeof(u64) * (nl + K) * N);
 #pragma omp parallel for num_threads(c->threads)
     for (int ti = 0; ti < nl + K; ti++) {
         int t = ext[ti];
@@ -827,26 +827,40 @@ static void keyswitch_core(orc_ctx *c, int level, u64 *const *d, const u64 *lift
         ntt_inv(c, t, a1);
         free(x);
     }
-    /* ModDown: (u - conv_P(u)) * P^-1 on each Q limb */
+    c->cnt[C_KS]++;
+}
+
+/* ModDown of one polynomial over Q_l and P: out_i = (u_i - conv_P(u)_i) * P^-1 mod q_i */
+static void ks_moddown(orc_ctx *c, int level, const u64 *u, u64 *out) {
+    int64_t N = c->n;
+    int nl = level + 1, K = c->n_p;
     int psrc[MAXMOD];
     for (int i = 0; i < K; i++) psrc[i] = c->n_q + i;
-    for (int w = 0; w < 2; w++) {
-        u64 *u = w ? u1 : u0, *o = w ? out1 : out0;
-        const u64 *px[MAXMOD];
-        for (int i = 0; i < K; i++) px[i] = u + (int64_t)(nl + i) * N;
+    const u64 *px[MAXMOD];
+    for (int i = 0; i < K; i++) px[i] = u + (int64_t)(nl + i) * N;
 #pragma omp parallel for num_threads(c->threads)
-        for (int i = 0; i < nl; i++) {
-            u64 q = c->mod[i], P = 1;
-            for (int kk = 0; kk < K; kk++) P = mulmod(P, c->mod[c->n_q + kk] % q, q);
-            u64 pinv = invmod(P, q);
-            u64 *cv = malloc(sizeof(u64) * N);
-            base_conv(c, K, psrc, px, i, cv);
-            for (int64_t s = 0; s < N; s++) o[(int64_t)i * N + s] = mulmod(submod(u[(int64_t)i * N + s], cv[s], q), pinv, q);
-            free(cv);
-        }
+    for (int i = 0; i < nl; i++) {
+        u64 q = c->mod[i], P = 1;
+        for (int kk = 0; kk < K; kk++) P = mulmod(P, c->mod[c->n_q + kk] % q, q);
+        u64 pinv = invmod(P, q);
+        u64 *cv = malloc(sizeof(u64) * N);
+        base_conv(c, K, psrc, px, i, cv);
+        for (int64_t s = 0; s < N; s++) out[(int64_t)i * N + s] = mulmod(submod(u[(int64_t)i * N + s], cv[s], q), pinv, q);
+        free(cv);
     }
+}
+
+/* inner product of the lifted digits with the key, then ModDown; d in coefficient form.
+ * 'lift' (optional) holds precomputed lifted digits [beta][level+1+K][N] in coefficient form. */
+static void keyswitch_core(orc_ctx *c, int level, u64 *const *d, const u64 *lift, const swk_t *k,
+                           u64 *out0, u64 *out1) {
+    int64_t N = c->n;
+    int nl = level + 1, K = c->n_p;
+    u64 *u0 = malloc(sizeof(u64) * (nl + K) * N), *u1 = malloc(sizeof(u64) * (nl + K) * N);
+    ks_inner(c, level, d, lift, k, u0, u1);
+    ks_moddown(c, level, u0, out0);
+    ks_moddown(c, level, u1, out1);
     free(u0); free(u1);
-    c->cnt[C_KS]++;
 }
 
 orc_ct *orc_relin(orc_ctx *c, const orc_ct *a) {
@@ -1050,6 +1064,58 @@ int orc_matmul_rotations(const orc_ctx *c, int h, int64_t *out, int cap) {
     return n;
 }
 
+/* v_1 . Rot(a, r_1) + v_2 . Rot(a, r_2) with one ModDown: each rotation's key-switch inner
+ * product (plus P * sigma_g(c0) on the Q limbs) is multiplied by its mask in the extended
+ * basis Q_l u P, the two are added there, and the sum is brought down once. */
+static orc_ct *rot_mask_pair_hoisted(orc_ctx *c, const orc_ct *a, const int64_t r[2], const int64_t *const mask[2],
+                                     double ms) {
+    int64_t N = c->n;
+    int nl = a->level + 1, K = c->n_p, ne = nl + K;
+    int ext[MAXMOD];
+    for (int i = 0; i < nl; i++) ext[i] = i;
+    for (int i = 0; i < K; i++) ext[nl + i] = c->n_q + i;
+    u64 *X0 = calloc((size_t)ne * N, sizeof(u64)), *X1 = calloc((size_t)ne * N, sizeof(u64));
+    u64 *u0 = malloc(sizeof(u64) * ne * N), *u1 = malloc(sizeof(u64) * ne * N);
+    u64 *p1 = malloc(sizeof(u64) * nl * N), *c0r = malloc(sizeof(u64) * nl * N);
+    for (int w = 0; w < 2; w++) {
+        u64 g = galois_elt(c, r[w]);
+        const swk_t *key = get_key(c, g);
+        u64 *d[MAXMOD];
+        for (int i = 0; i < nl; i++) {
+            automorph(c, limb(a, 1, i), p1 + (int64_t)i * N, g, c->mod[i]);
+            automorph(c, limb(a, 0, i), c0r + (int64_t)i * N, g, c->mod[i]);
+            d[i] = p1 + (int64_t)i * N;
+        }
+        ks_inner(c, a->level, d, NULL, key, u0, u1);
+#pragma omp parallel for num_threads(c->threads)
+        for (int ti = 0; ti < ne; ti++) {
+            int t = ext[ti];
+            u64 q = c->mod[t];
+            if (ti < nl) {  /* + P sigma_g(c0) on the Q limbs (P = 0 mod the special primes) */
+                u64 P = 1;
+                for (int kk = 0; kk < K; kk++) P = mulmod(P, c->mod[c->n_q + kk] % q, q);
+                for (int64_t s2 = 0; s2 < N; s2++)
+                    u0[(int64_t)ti * N + s2] = addmod(u0[(int64_t)ti * N + s2], mulmod(P, c0r[(int64_t)ti * N + s2], q), q);
+            }
+            u64 *m = malloc(sizeof(u64) * N), *tmp = malloc(sizeof(u64) * N);
+            for (int64_t s2 = 0; s2 < N; s2++) m[s2] = smod(mask[w][s2], q);
+            orc_poly_mul(c, t, u0 + (int64_t)ti * N, m, tmp);
+            for (int64_t s2 = 0; s2 < N; s2++) X0[(int64_t)ti * N + s2] = addmod(X0[(int64_t)ti * N + s2], tmp[s2], q);
+            orc_poly_mul(c, t, u1 + (int64_t)ti * N, m, tmp);
+            for (int64_t s2 = 0; s2 < N; s2++) X1[(int64_t)ti * N + s2] = addmod(X1[(int64_t)ti * N + s2], tmp[s2], q);
+            free(m); free(tmp);
+        }
+        c->cnt[C_ROT]++;
+        c->cnt[C_MULPT]++;
+    }
+    orc_ct *out = ct_new(c, a->level, 1, a->scale * ms);
+    ks_moddown(c, a->level, X0, out->c[0]);
+    ks_moddown(c, a->level, X1, out->c[1]);
+    c->cnt[C_ADD]++;
+    free(X0); free(X1); free(u0); free(u1); free(p1); free(c0r);
+    return out;
+}
+
 orc_ct *orc_matmul(orc_ctx *c, const orc_ct *A, const orc_ct *B, int h, int mode) {
     if (h < 1 || (h & (h - 1)) || (int64_t)h * h > c->n / 2) return NULL;
     int lvl = A->level < B->level ? A->level : B->level;
@@ -1091,8 +1157,10 @@ orc_ct *orc_matmul(orc_ctx *c, const orc_ct *A, const orc_ct *B, int h, int mode
     for (int j = 0; j < b; j++) orc_ct_free(baby[j]);
     free(baby);
     { orc_ct *t = orc_rescale(c, B0); orc_ct_free(B0); B0 = t; }
-    /* B0 is brought to the Step-3 level before its rotations */
-    { orc_ct *t = orc_drop(c, B0, B0->level - 1); orc_ct_free(B0); B0 = t; }
+    const int once = mode & ORC_RELIN_ONCE, hoist = mode & ORC_HOIST_MODDOWN, late = mode & ORC_RESCALE_LATE;
+    /* B0 is brought to the Step-3 level before its rotations (the late-rescale schedule
+     * multiplies one level higher and keeps it) */
+    if (!late) { orc_ct *t = orc_drop(c, B0, B0->level - 1); orc_ct_free(B0); B0 = t; }
 
     /* Steps 2 and 3 */
     orc_ct *acc = NULL;
@@ -1100,6 +1168,10 @@ orc_ct *orc_matmul(orc_ctx *c, const orc_ct *A, const orc_ct *B, int h, int mode
         orc_ct *Ak;
         if (k == 0) {
             Ak = orc_mul_plain(c, A0, get_mask(c, 2, h, 0, 0), ms);
+        } else if (hoist) {
+            const int64_t rr[2] = {k, k - h};
+            const int64_t *mm[2] = {get_mask(c, 2, h, k, 0), get_mask(c, 3, h, k, 0)};
+            Ak = rot_mask_pair_hoisted(c, A0, rr, mm, ms);
         } else {
             orc_ct *r1 = orc_rotate(c, A0, k), *r2 = orc_rotate(c, A0, k - h);
             orc_ct *t1 = orc_mul_plain(c, r1, get_mask(c, 2, h, k, 0), ms);
@@ -1107,15 +1179,16 @@ orc_ct *orc_matmul(orc_ctx *c, const orc_ct *A, const orc_ct *B, int h, int mode
             Ak = orc_add(c, t1, t2);
             orc_ct_free(r1); orc_ct_free(r2); orc_ct_free(t1); orc_ct_free(t2);
         }
-        { orc_ct *t = orc_rescale(c, Ak); orc_ct_free(Ak); Ak = t; }
+        if (!late) { orc_ct *t = orc_rescale(c, Ak); orc_ct_free(Ak); Ak = t; }
         orc_ct *Bk = k ? orc_rotate(c, B0, (int64_t)h * k) : ct_copy(c, B0);
         orc_ct *prod = orc_tensor(c, Ak, Bk);
-        if (mode == ORC_RELIN_EACH) { orc_ct *t = orc_relin(c, prod); orc_ct_free(prod); prod = t; }
+        if (!once) { orc_ct *t = orc_relin(c, prod); orc_ct_free(prod); prod = t; }
         acc = acc_add(c, acc, prod);
         orc_ct_free(Ak); orc_ct_free(Bk);
     }
-    if (mode == ORC_RELIN_ONCE) { orc_ct *t = orc_relin(c, acc); orc_ct_free(acc); acc = t; }
+    if (once) { orc_ct *t = orc_relin(c, acc); orc_ct_free(acc); acc = t; }
     orc_ct *res = orc_rescale(c, acc);
+    if (late) { orc_ct *t = orc_rescale(c, res); orc_ct_free(res); res = t; }
     orc_ct_free(acc); orc_ct_free(A0); orc_ct_free(B0); orc_ct_free(a); orc_ct_free(bb);
     return res;
 }

@@ -90,8 +90,16 @@ orc_ct *orc_rotate(orc_ctx *c, const orc_ct *a, int64_t k);
 void orc_rotate_hoisted(orc_ctx *c, const orc_ct *a, int n, const int64_t *ks, orc_ct **out);
 
 /* ---- the packed matrix product (Alg. 3 + App. B) ---- */
+/* schedule flags of the product (each combination is its own bit-exact reference):
+ * RELIN_ONCE: relinearise the accumulated Step-3 sum once instead of every product;
+ * HOIST_MODDOWN: in Step 2, v_k . Rot(A0, k) + v_(k-h) . Rot(A0, k-h) is formed in the
+ *   extended basis and brought down with one ModDown;
+ * RESCALE_LATE: A^(k) is not rescaled; Step 3 multiplies one level higher and the sum is
+ *   rescaled twice (same depth). */
 #define ORC_RELIN_EACH 0
 #define ORC_RELIN_ONCE 1
+#define ORC_HOIST_MODDOWN 2
+#define ORC_RESCALE_LATE 4
 orc_ct *orc_matmul(orc_ctx *c, const orc_ct *a, const orc_ct *b, int h, int relin_mode);
 /* slot-domain 0/1 vectors of length h*h for the diagonals used by Alg. 3:
  * kind 0: u^mu_k (k in (-h,h)), 1: u^zeta_{h k} (k in [0,h)), 2: v_k (k in [0,h)), 3: v_{k-h} */

@@ -20,6 +20,9 @@ _LIB = os.path.join(_LIB_DIR, "libckks_oracle.so")
 
 RELIN_EACH = 0
 RELIN_ONCE = 1
+HOIST_MODDOWN = 2
+RESCALE_LATE = 4
+FAST = RELIN_ONCE | HOIST_MODDOWN | RESCALE_LATE
 
 
 def build(force: bool = False) -> str:

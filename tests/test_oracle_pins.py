@@ -451,6 +451,55 @@ def test_matmul_relin_once(small):
     assert not np.array_equal(once.export(), each.export())
 
 
+MODES = [O.RELIN_EACH, O.RELIN_ONCE, O.HOIST_MODDOWN, O.RESCALE_LATE,
+         O.RELIN_ONCE | O.HOIST_MODDOWN, O.FAST]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_matmul_schedules_decrypt_and_counts(small, mode):
+    """every schedule computes A B at the same depth; the op counts follow from what
+    each flag moves (one relinearisation instead of h, ModDown shared by a mask pair,
+    two rescales at the end instead of one per A^(k))"""
+    h = 8
+    A, B = I.matrix_pair(40 + mode, h)
+    ca, cb = small.encrypt(A.ravel(), nonce=50), small.encrypt(B.ravel(), nonce=51)
+    small.reset_counters()
+    cm = small.matmul(ca, cb, h, mode)
+    cnt = small.counters()
+    assert cm.level == ca.level - 3
+    assert abs(cm.scale / ca.scale - 1) < 1e-3
+    full = small.decrypt(cm)
+    for r in range(small.n // 2 // (h * h)):
+        assert np.abs(full[r * h * h:(r + 1) * h * h].reshape(h, h) - A @ B).max() < 1e-3
+    assert cnt["rot"] == expected_rotations(h)
+    assert cnt["keyswitch"] == expected_rotations(h) + (1 if mode & O.RELIN_ONCE else h)
+    assert cnt["mul_pt"] == (2 * h - 1) + h + (2 * (h - 1) + 1)
+    assert cnt["rescale"] == 2 + (2 if mode & O.RESCALE_LATE else h + 1)
+
+
+def test_matmul_schedules_agree_at_coefficient_level(small):
+    """the schedules differ only in where rounding happens: the decrypted coefficient
+    vectors agree to far below the scale, and each schedule is a different bit pattern"""
+    h = 8
+    A, B = I.matrix_pair(77, h)
+    ca, cb = small.encrypt(A.ravel(), nonce=60), small.encrypt(B.ravel(), nonce=61)
+    outs = {m: small.matmul(ca, cb, h, m) for m in MODES}
+    ref = small.decrypt_coeffs(outs[O.RELIN_EACH])
+    for m, ct in outs.items():
+        d = np.abs(small.decrypt_coeffs(ct) - ref).max()
+        assert d < ct.scale * 2.0 ** -20, (m, d)
+    assert len({ct.export().tobytes() for ct in outs.values()}) == len(MODES)
+
+
+def test_matmul_fast_schedule_c1plus_bound():
+    """the stated accuracy (1e-3 at scale 2^30, C1+ ring, h = 8) also holds for the
+    schedule with all three flags"""
+    c = O.Ctx.from_params(I.C1P)
+    A, B = I.matrix_pair(2, 8)
+    cm = c.matmul(c.encrypt(A.ravel(), nonce=1), c.encrypt(B.ravel(), nonce=2), 8, O.FAST)
+    assert np.abs(c.decrypt(cm, 64).reshape(8, 8) - A @ B).max() < 1e-3
+
+
 def test_matmul_rejects_bad_shapes(small):
     ct = small.encrypt(np.zeros(4), nonce=1)
     with pytest.raises(ValueError):
