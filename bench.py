@@ -52,9 +52,17 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(prm, seconds_hint=30.0):
+SCHEDULES = {"each": 0, "once": 1, "once+hoist": 3, "fast": 7}
+SCHEDULE_TEXT = {0: "relinearise every Step-3 product",
+                 1: "relinearise once per product",
+                 3: "relinearise once; one ModDown per Step-2 mask pair",
+                 7: "relinearise once; one ModDown per Step-2 mask pair; A^(k) rescaled late (two final rescales)"}
+
+
+def cpu_baseline(prm, flags):
     """The oracle (plain scalar C, OpenMP over limbs) on the host: one h=16 product on the
-    same N=2^15 ring and chain, extrapolated to h=64 by the key-switch + Mul_pt count."""
+    same N=2^15 ring and chain under the same schedule flags, extrapolated to h=64 by the
+    key-switch + Mul_pt count."""
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as O
     from paper_2207_04620_amd import inputs as I
@@ -63,14 +71,16 @@ def cpu_baseline(prm, seconds_hint=30.0):
     o = O.Ctx.from_params(prm, threads=threads)
     A, B = I.matrix_pair(3, 16)
     a, b = o.encrypt(A.ravel(), nonce=1), o.encrypt(B.ravel(), nonce=2)
-    o.matmul(a, b, 16)  # keys and masks for h=16 (not timed)
+    o.matmul(a, b, 16, flags)  # keys and masks for h=16 (not timed)
     o.reset_counters()
     t0 = time.perf_counter()
-    o.matmul(a, b, 16)
+    o.matmul(a, b, 16, flags)
     dt = time.perf_counter() - t0
     c = o.counters()
     work16 = c["keyswitch"] + c["mul_pt"]
-    work64 = (225 + 64) + (127 + 64 + 127)  # key switches + Mul_pt of one h=64 product
+    # key switches + Mul_pt of one h=64 product: 225 rotations, 1 or 64 relinearisations,
+    # 127 + 64 + 127 masks
+    work64 = 225 + (1 if flags & 1 else 64) + (127 + 64 + 127)
     t64 = dt * work64 / work16
     return {"value": 1.0 / t64, "unit": "HE-matmuls/s", "cores": threads, "kind": "oracle",
             "sample": f"one h=16 product at N=2^15 from level 13 ({dt:.2f} s, {c['keyswitch']} key switches, "
@@ -83,11 +93,13 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=16)
-    ap.add_argument("--schedule", choices=["once", "each"], default="once",
-                    help="Step 3: relinearise the accumulated sum once, or every product")
+    ap.add_argument("--schedule", choices=list(SCHEDULES), default="fast",
+                    help="schedule flags of the product (each: relinearise every Step-3 product; once: "
+                         "relinearise the sum; +hoist: one ModDown per Step-2 mask pair; fast: also rescale "
+                         "A^(k) late)")
     ap.add_argument("--plain-iters", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-other", action="store_true", help="skip the other Step-3 schedule")
+    ap.add_argument("--no-other", action="store_true", help="skip timing the other schedules")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / batched capacity")
     ap.add_argument("--serve-min-batch", type=int, default=8)
@@ -109,7 +121,7 @@ def main():
     h = 64
     log("context C3 (keys + masks for h=64)")
     t0 = time.perf_counter()
-    sched = he.SCHED_RELIN_ONCE if args.schedule == "once" else he.SCHED_RELIN_EACH
+    sched = SCHEDULES[args.schedule]
     ctx = he.Context(prm, h_list=[h], stream=stream.cuda_stream, schedule=sched)
     log(f"context ready in {time.perf_counter() - t0:.1f} s")
     level = prm.max_level
@@ -190,24 +202,25 @@ def main():
                  "max_wait_ms": args.serve_max_wait_ms}
         log(f"serve p50 {serve['p50_ms']} ms p99 {serve['p99_ms']} ms, {serve['served_per_s']} /s")
 
-    # the other Step-3 schedule, timed without launch events
-    other = "each" if args.schedule == "once" else "once"
-    other_value = None
+    # the other schedules, one batch each, timed without launch events
+    others = {}
     if not args.no_other:
-        ctx2 = he.Context(prm, h_list=[h], stream=stream.cuda_stream,
-                          schedule=he.SCHED_RELIN_EACH if other == "each" else he.SCHED_RELIN_ONCE)
         pairs = [I.matrix_pair(1000 + i, h) for i in range(args.batch)]
-        As2 = [ctx2.encrypt(p[0].ravel(), level=level, nonce=2 * i) for i, p in enumerate(pairs)]
-        Bs2 = [ctx2.encrypt(p[1].ravel(), level=level, nonce=2 * i + 1) for i, p in enumerate(pairs)]
-        ctx2.matmul_batch(As2, Bs2, [h] * args.batch)
-        ctx2.sync()
-        t0 = time.perf_counter()
-        ctx2.matmul_batch(As2, Bs2, [h] * args.batch)
-        ctx2.sync()
-        other_value = args.batch / (time.perf_counter() - t0)
-        log(f"schedule '{other}': {other_value:.3f} products/s")
-        del As2, Bs2
-        ctx2.close()
+        for name, flags in SCHEDULES.items():
+            if flags == sched:
+                continue
+            ctx2 = he.Context(prm, h_list=[h], stream=stream.cuda_stream, schedule=flags)
+            As2 = [ctx2.encrypt(p[0].ravel(), level=level, nonce=2 * i) for i, p in enumerate(pairs)]
+            Bs2 = [ctx2.encrypt(p[1].ravel(), level=level, nonce=2 * i + 1) for i, p in enumerate(pairs)]
+            ctx2.matmul_batch(As2, Bs2, [h] * args.batch)
+            ctx2.sync()
+            t0 = time.perf_counter()
+            ctx2.matmul_batch(As2, Bs2, [h] * args.batch)
+            ctx2.sync()
+            others[name] = round(args.batch / (time.perf_counter() - t0), 4)
+            log(f"schedule '{name}': {others[name]:.3f} products/s")
+            del As2, Bs2
+            ctx2.close()
 
     # dominant kernel by summed duration; NTT passes are ALU-bound (butterflies), the
     # other kernels are measured against HBM bandwidth
@@ -242,11 +255,10 @@ def main():
         "config": {"workload": "C3: batch of packed ct x ct h=64 products (Alg. 3 + App. B), N=2^15, "
                                "Q=60+13x45 bits, P=3x60+56 bits, dnum=3, scale 2^45, inputs at level 13",
                    "batch": args.batch, "h": h, "log_n": 15,
-                   "schedule": "relinearise once per product" if args.schedule == "once" else
-                               "relinearise every Step-3 product",
+                   "schedule": f"{args.schedule}: {SCHEDULE_TEXT[sched]}",
                    "plain_matmuls_per_s": None if plain_s != plain_s else round(1.0 / plain_s, 4),
                    "plain_ms": None if plain_s != plain_s else round(plain_s * 1e3, 2),
-                   f"batched_matmuls_per_s_relin_{other}": None if other_value is None else round(other_value, 4),
+                   "batched_matmuls_per_s_other_schedules": others or None,
                    "batched_over_plain": None if plain_s != plain_s else round(value * plain_s, 3),
                    "max_abs_error": err},
         "serve": serve,
@@ -258,7 +270,7 @@ def main():
     }
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        result["cpu_baseline"] = cpu_baseline(prm)
+        result["cpu_baseline"] = cpu_baseline(prm, sched)
     print(json.dumps(result), flush=True)
 
 

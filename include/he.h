@@ -57,8 +57,16 @@ typedef struct {
     void *user;
 } he_device;
 
-#define HE_SCHED_RELIN_EACH 0u /* relinearise every Step-3 product (Mul_ct of Fig. 1) */
-#define HE_SCHED_RELIN_ONCE 1u /* accumulate degree-2 products, relinearise once */
+/* Schedule flags of the packed product (Alg. 3).  Every combination computes A B at the
+ * same depth (three levels) with the same rotations; they differ only in where rounding
+ * happens, so each is its own bit-exact reference. */
+#define HE_SCHED_RELIN_EACH 0u    /* relinearise every Step-3 product (Mul_ct of Fig. 1) */
+#define HE_SCHED_RELIN_ONCE 1u    /* accumulate degree-2 products, relinearise once */
+#define HE_SCHED_HOIST_MODDOWN 2u /* Step 2: v_k . Rot(A0,k) + v_(k-h) . Rot(A0,k-h) formed in
+                                   * the extended basis Q_l P, one ModDown for the pair */
+#define HE_SCHED_RESCALE_LATE 4u  /* Step 2: A^(k) kept unrescaled; Step 3 multiplies one level
+                                   * higher and the sum is rescaled twice */
+#define HE_SCHED_ALL 7u
 
 typedef struct {
     uint32_t log_n;          /* ring degree N = 2^log_n, 8 <= log_n <= 17 */
@@ -71,7 +79,7 @@ typedef struct {
     uint64_t seed;           /* ChaCha20 key */
     uint32_t n_h;            /* matrix sides whose rotation keys and masks are made at creation */
     const uint32_t *h_list;
-    uint32_t schedule;       /* HE_SCHED_RELIN_EACH or HE_SCHED_RELIN_ONCE */
+    uint32_t schedule;       /* OR of HE_SCHED_* flags; other bits are HE_EINVAL */
 } he_params;
 
 /* Context: primes, twiddles, secret/public/relinearisation keys, rotation keys and

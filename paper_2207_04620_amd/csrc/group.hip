@@ -137,19 +137,20 @@ std::shared_ptr<DBuf> Ctx::g_lift(const Grp& a, int poly) {
     return lift;
 }
 
-// ModDown(<lift o sigma_g, key>) (+ add) into out, for every member
-void Ctx::g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, const u64* add0, const u64* add1,
-                     int64_t add_cs, u64* out0, u64* out1, int64_t out_cs, u64 add_g, const u64* mask,
-                     const u64* acc0, const u64* acc1, int64_t acc_cs, const u64* c0, int64_t c0_cs) {
+// Key-switch inner product <lift o sigma_g, key> (+ P sigma_g(c0) on the Q limbs) of every
+// member into u [B][2][ne][N]; with a second (g2, key2) and masks, the masked sum of two
+// rotations of the same lift (one ModDown then serves both)
+std::shared_ptr<DBuf> Ctx::g_ks_inner(const u64* lift, int B, int level, const u64* key, u64 g, const u64* c0,
+                                      int64_t c0_cs, const u64* mask, const u64* key2, u64 g2, const u64* mask2) {
     const int nl = level + 1, ne = nl + n_p;
     const int beta = (int)mu[level].size();
-    const int64_t ucs = 2 * (int64_t)ne * N, ccs = 2 * (int64_t)nl * N;
-    DBuf u(this, (size_t)B * ucs);
+    const int64_t ucs = 2 * (int64_t)ne * N;
+    auto u = std::make_shared<DBuf>(this, (size_t)B * ucs);
     IpDesc D;
     memset(&D, 0, sizeof D);
     D.lift = lift;
     D.key = key;
-    D.u = u.p;
+    D.u = u->p;
     D.lift_cs = (int64_t)beta * ne * N;
     D.u_cs = ucs;
     D.nct = B;
@@ -162,7 +163,24 @@ void Ctx::g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, c
     D.c0_cs = c0_cs;
     D.nq = nl;
     for (int t = 0; t < nl; ++t) D.pmont[t] = hm::to_mont(pmod[t], mods[t]);
+    D.nrot = key2 ? 2 : 1;
+    D.key2 = key2;
+    D.g2 = g2;
+    D.mask = mask;
+    D.mask2 = mask2;
     launch_inner_product(T, D, stream);
+    cnt[C_KS] += (int64_t)B * D.nrot;
+    return u;
+}
+
+// out = ModDown(u) (+ add gathered by add_g) (. mask) (+ acc), for every member; u as made
+// by g_ks_inner.  The combine runs in the epilogue of the forward NTT of the converted
+// special-prime part.
+void Ctx::g_moddown(DBuf& u, int B, int level, const u64* add0, const u64* add1, int64_t add_cs, u64* out0,
+                    u64* out1, int64_t out_cs, u64 add_g, const u64* mask, const u64* acc0, const u64* acc1,
+                    int64_t acc_cs) {
+    const int nl = level + 1, ne = nl + n_p;
+    const int64_t ucs = 2 * (int64_t)ne * N, ccs = 2 * (int64_t)nl * N;
     {
         Jobs J;
         J.base = u.p;
@@ -234,7 +252,32 @@ void Ctx::g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, c
     E.acc[1] = acc1;
     E.acc_cs = acc_cs;
     launch_ntt_moddown(T, J, E, stream);
-    cnt[C_KS] += B;
+}
+
+// ModDown(<lift o sigma_g, key>) (+ add) into out, for every member
+void Ctx::g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, const u64* add0, const u64* add1,
+                     int64_t add_cs, u64* out0, u64* out1, int64_t out_cs, u64 add_g, const u64* mask,
+                     const u64* acc0, const u64* acc1, int64_t acc_cs, const u64* c0, int64_t c0_cs) {
+    auto u = g_ks_inner(lift, B, level, key, g, c0, c0_cs, nullptr, nullptr, 1, nullptr);
+    g_moddown(*u, B, level, add0, add1, add_cs, out0, out1, out_cs, add_g, mask, acc0, acc1, acc_cs);
+}
+
+// v1 . Rot(a, k1) + v2 . Rot(a, k2) with both masks applied in the extended basis and a
+// single ModDown (hoisted-ModDown schedule of Step 2)
+Grp Ctx::g_rotate_pair_hoisted(const Grp& a, const u64* lift, int64_t k1, const u64* mask1, int64_t k2,
+                               const u64* mask2, double mask_scale) {
+    const u64 g1 = galois(k1), g2 = galois(k2);
+    if (g1 == 1 || g2 == 1) throw HeError(HE_EUNSUPPORTED);
+    const u64 *key1 = rot_key(g1, false), *key2 = rot_key(g2, false);
+    std::vector<double> sc(a.scale);
+    for (auto& v : sc) v *= mask_scale;
+    Grp out = g_new(a.B, a.level, 1, sc);
+    auto u = g_ks_inner(lift, a.B, a.level, key1, g1, a.p, a.cs, mask1, key2, g2, mask2);
+    g_moddown(*u, a.B, a.level, nullptr, nullptr, 0, out.p, out.p + out.ps, out.cs, 1, nullptr, nullptr, nullptr, 0);
+    cnt[C_ROT] += 2 * a.B;
+    cnt[C_MULPT] += 2 * a.B;
+    cnt[C_ADD] += a.B;
+    return out;
 }
 
 Grp Ctx::g_rotate_from_lift(const Grp& a, const u64* lift, int64_t k) {
@@ -434,7 +477,9 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
                 }
             }
             J.B0 = g_rescale(acc);
-            J.B0 = g_drop(J.B0, J.B0.level - 1);  // brought to the Step-3 level before its rotations
+            // brought to the Step-3 level before its rotations (with late rescaling Step 3
+            // multiplies at this level)
+            if (!(schedule & HE_SCHED_RESCALE_LATE)) J.B0 = g_drop(J.B0, J.B0.level - 1);
         }
         J.liftA = g_lift(J.A0, 1);
         J.liftB = g_lift(J.B0, 1);
@@ -449,14 +494,16 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
             Grp Ak;
             if (k == 0) {
                 Ak = g_mask_sum({{&J.A0, mask(2, h, 0, 0)}}, ms);
+            } else if (schedule & HE_SCHED_HOIST_MODDOWN) {
+                Ak = g_rotate_pair_hoisted(J.A0, J.liftA->p, k, mask(2, h, k, 0), k - h, mask(3, h, k, 0), ms);
             } else {
                 // v_k . Rot(A0, k) + v_{k-h} . Rot(A0, k-h), masks applied in the ModDown epilogues
                 Grp t1 = g_rotate_mask_from_lift(J.A0, J.liftA->p, k, mask(2, h, k, 0), ms, nullptr);
                 Ak = g_rotate_mask_from_lift(J.A0, J.liftA->p, k - h, mask(3, h, k, 0), ms, &t1);
             }
-            Ak = g_rescale(Ak);
+            if (!(schedule & HE_SCHED_RESCALE_LATE)) Ak = g_rescale(Ak);
             Grp Bk = k ? g_rotate_from_lift(J.B0, J.liftB->p, (int64_t)h * k) : J.B0;
-            if (schedule == HE_SCHED_RELIN_EACH) {
+            if (!(schedule & HE_SCHED_RELIN_ONCE)) {
                 Grp prod = g_relin(g_tensor(Ak, Bk));
                 if (!J.have) {
                     J.acc = prod;
@@ -483,8 +530,10 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
         }
         return false;
     }
-    if (schedule == HE_SCHED_RELIN_ONCE) J.acc = g_relin(J.acc);
-    J.result = g_scatter(g_rescale(J.acc));
+    if (schedule & HE_SCHED_RELIN_ONCE) J.acc = g_relin(J.acc);
+    J.acc = g_rescale(J.acc);
+    if (schedule & HE_SCHED_RESCALE_LATE) J.acc = g_rescale(J.acc);
+    J.result = g_scatter(J.acc);
     J.acc = Grp();
     J.phase = 3;
     return true;

@@ -757,14 +757,17 @@ CtPtr Ctx::mul_int(const CtData& a, int64_t k) {
 }
 
 // plaintext (signed integer coefficients) to Montgomery evaluation form over all Q limbs
+// a plaintext's residues on every modulus (Q and P, so that it can also multiply a value
+// in the extended basis), evaluation form, Montgomery form: [M][N]
 std::unique_ptr<DBuf> Ctx::plaintext_mont(const int64_t* coeffs) {
-    auto pt = std::make_unique<DBuf>(this, (size_t)n_q * N);
+    const int M = n_q + n_p;
+    auto pt = std::make_unique<DBuf>(this, (size_t)M * N);
     DBuf dm(this, N);
     upload(this, dm.p, coeffs, N * 8);
-    hip_check(hipMemsetAsync(pt->p, 0, (size_t)n_q * N * 8, stream), "pt zero");
-    launch_add_signed(T, n_q, pt->p, (const int64_t*)dm.p, stream);
-    ntt(pt->p, 1, 0, n_q, false, -1);
-    launch_to_mont(T, qmap(this), n_q, 1, pt->p, 0, stream);
+    hip_check(hipMemsetAsync(pt->p, 0, (size_t)M * N * 8, stream), "pt zero");
+    launch_add_signed(T, M, pt->p, (const int64_t*)dm.p, stream);
+    ntt(pt->p, 1, 0, M, false, -1);
+    launch_to_mont(T, ModMap{1 << 20, n_q}, M, 1, pt->p, 0, stream);
     hip_check(hipStreamSynchronize(stream), "plaintext");
     return pt;
 }
@@ -842,7 +845,7 @@ void Ctx::prepare_masks(const std::vector<MaskKey>& keys) {
     for (auto& t : th) t.join();
     for (size_t i = 0; i < todo.size(); ++i) {
         masks[todo[i]] = plaintext_mont(coeffs[i].data());
-        keys_bytes += (size_t)n_q * N * 8;
+        keys_bytes += (size_t)(n_q + n_p) * N * 8;
     }
 }
 
@@ -932,7 +935,8 @@ he_status he_ctx_create(const he_params* prm, const he_device* dev, he_ctx** out
     if (!prm || !out || !prm->q_bits || (prm->n_p && !prm->p_bits)) return HE_EINVAL;
     return guard([&]() {
         if (prm->log_n < 8 || prm->log_n > 17 || prm->n_q < 1 || prm->n_p < 1 || prm->alpha < 1 ||
-            prm->n_q + prm->n_p > HE_MAXT || prm->alpha > HE_MAXSRC || prm->n_p > HE_MAXSRC)
+            prm->n_q + prm->n_p > HE_MAXT || prm->alpha > HE_MAXSRC || prm->n_p > HE_MAXSRC ||
+            (prm->n_q + prm->alpha - 1) / prm->alpha > HE_MAXSRC || (prm->schedule & ~HE_SCHED_ALL))
             throw HeError(HE_EINVAL);
         auto c = std::make_unique<Ctx>();
         c->log_n = (int)prm->log_n;

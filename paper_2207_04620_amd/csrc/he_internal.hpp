@@ -177,6 +177,13 @@ struct Ctx {
     Grp g_drop(const Grp& a, int level);
     void g_add_into(Grp& acc, const Grp& t);
     std::shared_ptr<DBuf> g_lift(const Grp& a, int poly);
+    std::shared_ptr<DBuf> g_ks_inner(const u64* lift, int B, int level, const u64* key, u64 g, const u64* c0,
+                                     int64_t c0_cs, const u64* mask, const u64* key2, u64 g2, const u64* mask2);
+    void g_moddown(DBuf& u, int B, int level, const u64* add0, const u64* add1, int64_t add_cs, u64* out0,
+                   u64* out1, int64_t out_cs, u64 add_g, const u64* mask, const u64* acc0, const u64* acc1,
+                   int64_t acc_cs);
+    Grp g_rotate_pair_hoisted(const Grp& a, const u64* lift, int64_t k1, const u64* mask1, int64_t k2,
+                              const u64* mask2, double mask_scale);
     void g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, const u64* add0, const u64* add1,
                     int64_t add_cs, u64* out0, u64* out1, int64_t out_cs, u64 add_g, const u64* mask,
                     const u64* acc0, const u64* acc1, int64_t acc_cs, const u64* c0, int64_t c0_cs);

@@ -669,42 +669,100 @@ void launch_swk_finish(const DevTables& T, int M, u64* b, const u64* a, const u6
 // gather: the digits of sigma_g(c1) are the permuted digits of c1 (hoisting).
 // The key values of one (limb, coefficient) are loaded once and reused for every
 // ciphertext of the group: a switching key crosses HBM once per launch.
+// one rotation's key-switch inner product of one member, reduced: sum_j lift_j(sigma_g) key_j
+// (+ P sigma_g(c0) on the Q limbs), optionally times a Montgomery-form mask
+template <int NB>
+__device__ __forceinline__ void ip_member(const IpDesc& D, const u64* lift, const u64* c0, int N, int t, int src,
+                                          const u64* kb, const u64* ka, bool with_c0, const ModP& m, u64 mk,
+                                          bool masked, u64& v0, u64& v1) {
+    Acc128 a0 = {0, 0}, a1 = {0, 0};
+#pragma unroll
+    for (int j = 0; j < NB; j++) {
+        const u64 x = lift[((int64_t)j * D.ne + t) * N + src];
+        mac128(a0, x, kb[j]);
+        mac128(a1, x, ka[j]);
+    }
+    if (with_c0) mac128(a0, c0[(int64_t)t * N + src], D.pmont[t]);
+    v0 = redc(a0.lo, a0.hi, m.q, m.qninv);
+    v1 = redc(a1.lo, a1.hi, m.q, m.qninv);
+    if (masked) {
+        v0 = mul_mont(v0, mk, m.q, m.qninv);
+        v1 = mul_mont(v1, mk, m.q, m.qninv);
+    }
+}
+
+// Grid (N / TPB, ne): one thread per (slot, extended limb) for every member, so each key
+// word (and mask word) is read once per group.  The digit count NB is a template
+// parameter so that the key words stay in registers.
+template <int NB, int NR>
 __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
     const int N = 1 << T.log_n;
     const int i = blockIdx.x * TPB + threadIdx.x;
     const int t = blockIdx.y;
     const int mi = D.mod[t];
     const ModP m = T.mods[mi];
-    const int src = D.g == 1 ? i : perm_g(i, D.g, T.log_n);
-    u64 kb[HE_MAXSRC], ka[HE_MAXSRC];
-    for (int j = 0; j < D.beta; j++) {
-        kb[j] = D.key[(((int64_t)j * 2 + 0) * D.M + mi) * N + i];
-        ka[j] = D.key[(((int64_t)j * 2 + 1) * D.M + mi) * N + i];
+    u64 kb[NR][NB], ka[NR][NB], mk[NR];
+    int src[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const u64 g = r ? D.g2 : D.g;
+        const u64* key = r ? D.key2 : D.key;
+        const u64* mask = r ? D.mask2 : D.mask;
+        src[r] = g == 1 ? i : perm_g(i, g, T.log_n);
+#pragma unroll
+        for (int j = 0; j < NB; j++) {
+            kb[r][j] = key[(((int64_t)j * 2 + 0) * D.M + mi) * N + i];
+            ka[r][j] = key[(((int64_t)j * 2 + 1) * D.M + mi) * N + i];
+        }
+        mk[r] = mask ? mask[(int64_t)mi * N + i] : 0;
     }
     const bool with_c0 = D.c0 && t < D.nq;
     for (int c = 0; c < D.nct; c++) {
         const u64* lift = D.lift + c * D.lift_cs;
-        Acc128 a0 = {0, 0}, a1 = {0, 0};
-        for (int j = 0; j < D.beta; j++) {
-            const u64 x = lift[((int64_t)j * D.ne + t) * N + src];
-            mac128(a0, x, kb[j]);
-            mac128(a1, x, ka[j]);
+        const u64* c0 = D.c0 ? D.c0 + c * D.c0_cs : nullptr;
+        u64 v0, v1;
+        ip_member<NB>(D, lift, c0, N, t, src[0], kb[0], ka[0], with_c0, m, mk[0], D.mask != nullptr, v0, v1);
+        if (NR == 2) {
+            u64 w0, w1;
+            ip_member<NB>(D, lift, c0, N, t, src[NR - 1], kb[NR - 1], ka[NR - 1], with_c0, m, mk[NR - 1],
+                          D.mask2 != nullptr, w0, w1);
+            v0 = add_mod(v0, w0, m.q);
+            v1 = add_mod(v1, w1, m.q);
         }
-        if (with_c0) mac128(a0, D.c0[c * D.c0_cs + (int64_t)t * N + src], D.pmont[t]);
         u64* u = D.u + c * D.u_cs;
-        u[(int64_t)t * N + i] = redc(a0.lo, a0.hi, m.q, m.qninv);
-        u[((int64_t)D.ne + t) * N + i] = redc(a1.lo, a1.hi, m.q, m.qninv);
+        u[(int64_t)t * N + i] = v0;
+        u[((int64_t)D.ne + t) * N + i] = v1;
     }
 }
 
+template <int NB>
+static void launch_ip_nb(const DevTables& T, const IpDesc& D, dim3 grid, hipStream_t st) {
+    if (D.nrot == 2)
+        hipLaunchKernelGGL((k_inner_product<NB, 2>), grid, dim3(TPB), 0, st, T, D);
+    else
+        hipLaunchKernelGGL((k_inner_product<NB, 1>), grid, dim3(TPB), 0, st, T, D);
+}
+
 void launch_inner_product(const DevTables& T, const IpDesc& D, hipStream_t st) {
-    ProfScope prof_(PK_INNER,
-                    ((double)D.ne * (2.0 * D.beta + D.nct * (D.beta + 2.0)) + (D.c0 ? (double)D.nq * D.nct : 0.0)) * 8.0 *
-                        (1 << T.log_n),
-                    st);
+    const int nr = D.nrot == 2 ? 2 : 1;
+    // keys (and masks) once per group; per member the lift digits per rotation, c0 and u
+    const double words = (double)D.ne * (nr * 2.0 * D.beta + (D.mask ? 1.0 : 0.0) + (D.mask2 ? 1.0 : 0.0) +
+                                         D.nct * (nr * (double)D.beta + 2.0)) +
+                         (D.c0 ? (double)D.nq * D.nct * nr : 0.0);
+    ProfScope prof_(PK_INNER, words * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), D.ne);
-    hipLaunchKernelGGL(k_inner_product, grid, dim3(TPB), 0, st, T, D);
+    switch (D.beta) {
+        case 1: launch_ip_nb<1>(T, D, grid, st); break;
+        case 2: launch_ip_nb<2>(T, D, grid, st); break;
+        case 3: launch_ip_nb<3>(T, D, grid, st); break;
+        case 4: launch_ip_nb<4>(T, D, grid, st); break;
+        case 5: launch_ip_nb<5>(T, D, grid, st); break;
+        case 6: launch_ip_nb<6>(T, D, grid, st); break;
+        case 7: launch_ip_nb<7>(T, D, grid, st); break;
+        case 8: launch_ip_nb<8>(T, D, grid, st); break;
+        default: abort();
+    }
 }
 
 __global__ __launch_bounds__(TPB) void k_moddown_combine(DevTables T, int npoly, const u64* u, int64_t u_ps,

@@ -93,6 +93,13 @@ struct IpDesc {
     int64_t c0_cs;
     int nq;
     u64 pmont[HE_MAXT];  // (P mod q_t) R mod q_t
+    // optional second rotation of the same lift: with nrot = 2 the kernel forms
+    // mask . IP(g, key) + mask2 . IP(g2, key2) in the extended basis (one ModDown for both)
+    int nrot;
+    u64 g2;
+    const u64* key2;
+    const u64* mask;   // [M][N] Montgomery form, row = modulus index; null = no mask
+    const u64* mask2;
 };
 
 struct MacDesc {

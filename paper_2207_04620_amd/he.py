@@ -18,6 +18,9 @@ STATUS = ["HE_OK", "HE_EINVAL", "HE_ENOMEM", "HE_ELEVEL", "HE_ESCALE", "HE_EKEY"
           "HE_EMISMATCH", "HE_EDEVICE", "HE_EUNSUPPORTED"]
 SCHED_RELIN_EACH = 0
 SCHED_RELIN_ONCE = 1
+SCHED_HOIST_MODDOWN = 2
+SCHED_RESCALE_LATE = 4
+SCHED_FAST = SCHED_RELIN_ONCE | SCHED_HOIST_MODDOWN | SCHED_RESCALE_LATE
 SIGN = 0
 RELU = 1
 REQ_MATMUL = 0

@@ -188,6 +188,52 @@ def test_matmul_relin_once_parity(he):
     p.same(gm, om)
 
 
+SCHEDULES = [2, 4, 3, 5, 6, 7]  # flag combinations beyond relin-each / relin-once
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_matmul_schedule_parity(he, schedule):
+    """each schedule flag combination is its own reference: the oracle run with the same
+    flags must agree on every residue, and on the operation counts"""
+    prm = I.small(log_n=12, n_q=6, alpha=2, q_bits=40, p_bits=50)
+    p = Pair(he, prm, h_list=[4, 16], schedule=schedule)
+    for h in (4, 16):
+        _log(f"[parity] matmul schedule={schedule} h={h}")
+        A, B = I.matrix_pair(90 + schedule + h, h)
+        ga, gb = p.g.encrypt(A.ravel(), nonce=3), p.g.encrypt(B.ravel(), nonce=4)
+        oa, ob = p.o.encrypt(A.ravel(), nonce=3), p.o.encrypt(B.ravel(), nonce=4)
+        p.g.counters(reset=True)
+        p.o.reset_counters()
+        gm = p.g.matmul(ga, gb, h)
+        om = p.o.matmul(oa, ob, h, schedule)
+        p.same(gm, om)
+        gc, oc = p.g.counters(), p.o.counters()
+        for key in ("rot", "keyswitch", "mul_pt", "mul_ct", "rescale"):
+            assert gc[key] == oc[key], (key, gc[key], oc[key])
+        assert np.abs(p.g.decrypt(gm, h * h).reshape(h, h) - A @ B).max() < 1e-3
+    # a batch of mixed sides and levels under the same schedule equals the single products
+    pairs = [(4, 5), (16, 4), (4, 3)]
+    As, Bs, hs, singles = [], [], [], []
+    for i, (h, lvl) in enumerate(pairs):
+        A, B = I.matrix_pair(300 + i, h)
+        a = p.g.encrypt(A.ravel(), level=lvl, nonce=10 + 2 * i)
+        b = p.g.encrypt(B.ravel(), level=lvl, nonce=11 + 2 * i)
+        As.append(a), Bs.append(b), hs.append(h)
+        singles.append(p.g.export(p.g.matmul(a, b, h)))
+    for r, s in zip(p.g.matmul_batch(As, Bs, hs), singles):
+        assert np.array_equal(p.g.export(r), s)
+
+
+def test_matmul_fast_schedule_c1plus_bound(he):
+    """the stated accuracy (1e-3 at scale 2^30, 2^12 ring, h = 8) under all three flags"""
+    p = Pair(he, I.C1P, schedule=7)
+    A, B = I.matrix_pair(2, 8)
+    gm = p.g.matmul(p.g.encrypt(A.ravel(), nonce=1), p.g.encrypt(B.ravel(), nonce=2), 8)
+    om = p.o.matmul(p.o.encrypt(A.ravel(), nonce=1), p.o.encrypt(B.ravel(), nonce=2), 8, 7)
+    p.same(gm, om)
+    assert np.abs(p.g.decrypt(gm, 64).reshape(8, 8) - A @ B).max() < 1e-3
+
+
 def test_matmul_c1plus_parity_and_bound(c1p):
     """the h=8 product on the 2^12 ring at scale 2^30: bit-exact, and within 1e-3 of FP64"""
     A, B = I.matrix_pair(1, 8)
