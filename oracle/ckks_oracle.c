@@ -1045,8 +1045,16 @@ static orc_ct *acc_add(orc_ctx *c, orc_ct *acc, orc_ct *t) {
     return r;
 }
 
-int orc_matmul_rotations(const orc_ctx *c, int h, int64_t *out, int cap) {
-    int b = 1 << ((ilog2(h) + 1) / 2), n = 0;
+/* baby-step count of the Step-3 split k = bg i + j: bg = 2^ceil((log2 h + 1) / 2), at most h;
+ * without the Step-3 flag the sum is one block of h terms */
+static int step3_baby(int h, int mode) {
+    if (!(mode & ORC_STEP3_BSGS)) return h;
+    int bg = 1 << ((ilog2(h) + 2) / 2);
+    return bg < h ? bg : h;
+}
+
+int orc_matmul_rotations(const orc_ctx *c, int h, int mode, int64_t *out, int cap) {
+    int b = 1 << ((ilog2(h) + 1) / 2), bg = step3_baby(h, mode), n = 0;
     int64_t half = c->n / 2;
     int64_t tmp[4096];
     int m = 0;
@@ -1054,7 +1062,13 @@ int orc_matmul_rotations(const orc_ctx *c, int h, int64_t *out, int cap) {
     for (int i = floordiv(1 - h, b); i <= floordiv(h - 1, b); i++) if (i) tmp[m++] = (int64_t)b * i;
     for (int j = 1; j < b; j++) tmp[m++] = (int64_t)h * j;
     for (int i = 1; i * b < h; i++) tmp[m++] = (int64_t)h * b * i;
-    for (int k = 1; k < h; k++) { tmp[m++] = k; tmp[m++] = k - h; tmp[m++] = (int64_t)h * k; }
+    for (int k = 1; k < h; k++) {
+        int64_t shift = (int64_t)h * bg * (k / bg);
+        tmp[m++] = k - shift;
+        tmp[m++] = k - h - shift;
+    }
+    for (int j = 1; j < bg; j++) tmp[m++] = (int64_t)h * j;
+    for (int i = 1; i * bg < h; i++) tmp[m++] = (int64_t)h * bg * i;
     for (int i = 0; i < m; i++) {
         int64_t v = ((tmp[i] % half) + half) % half;
         int dup = 0;
@@ -1162,31 +1176,47 @@ orc_ct *orc_matmul(orc_ctx *c, const orc_ct *A, const orc_ct *B, int h, int mode
      * multiplies one level higher and keeps it) */
     if (!late) { orc_ct *t = orc_drop(c, B0, B0->level - 1); orc_ct_free(B0); B0 = t; }
 
-    /* Steps 2 and 3 */
+    /* Steps 2 and 3.  The Step-3 sum over k is taken in blocks k = bg i + j:
+     *   sum_i Rot( sum_j Rot(A^(k), -h bg i) . Rot(B0, h j), h bg i ),
+     * where Rot(A^(k), -s) = R(v_k, -s) . Rot(A0, k - s) + R(v_(k-h), -s) . Rot(A0, k - h - s).
+     * Without the Step-3 flag there is one block (bg = h) and no giant-step rotation, which
+     * is Alg. 3's Step 3 as printed. */
+    const int bg = step3_baby(h, mode);
+    orc_ct **bj = calloc(bg, sizeof(orc_ct *));
+    bj[0] = ct_copy(c, B0);
+    for (int j = 1; j < bg; j++) bj[j] = orc_rotate(c, B0, (int64_t)h * j);
     orc_ct *acc = NULL;
-    for (int k = 0; k < h; k++) {
-        orc_ct *Ak;
-        if (k == 0) {
-            Ak = orc_mul_plain(c, A0, get_mask(c, 2, h, 0, 0), ms);
-        } else if (hoist) {
-            const int64_t rr[2] = {k, k - h};
-            const int64_t *mm[2] = {get_mask(c, 2, h, k, 0), get_mask(c, 3, h, k, 0)};
-            Ak = rot_mask_pair_hoisted(c, A0, rr, mm, ms);
-        } else {
-            orc_ct *r1 = orc_rotate(c, A0, k), *r2 = orc_rotate(c, A0, k - h);
-            orc_ct *t1 = orc_mul_plain(c, r1, get_mask(c, 2, h, k, 0), ms);
-            orc_ct *t2 = orc_mul_plain(c, r2, get_mask(c, 3, h, k, 0), ms);
-            Ak = orc_add(c, t1, t2);
-            orc_ct_free(r1); orc_ct_free(r2); orc_ct_free(t1); orc_ct_free(t2);
+    for (int i = 0; i * bg < h; i++) {
+        const int64_t shift = (int64_t)h * bg * i;
+        orc_ct *S = NULL;
+        for (int j = 0; j < bg; j++) {
+            const int k = bg * i + j;
+            orc_ct *Ak;
+            if (k == 0) {
+                Ak = orc_mul_plain(c, A0, get_mask(c, 2, h, 0, 0), ms);
+            } else if (hoist) {
+                const int64_t rr[2] = {k - shift, k - h - shift};
+                const int64_t *mm[2] = {get_mask(c, 2, h, k, -shift), get_mask(c, 3, h, k, -shift)};
+                Ak = rot_mask_pair_hoisted(c, A0, rr, mm, ms);
+            } else {
+                orc_ct *r1 = orc_rotate(c, A0, k - shift), *r2 = orc_rotate(c, A0, k - h - shift);
+                orc_ct *t1 = orc_mul_plain(c, r1, get_mask(c, 2, h, k, -shift), ms);
+                orc_ct *t2 = orc_mul_plain(c, r2, get_mask(c, 3, h, k, -shift), ms);
+                Ak = orc_add(c, t1, t2);
+                orc_ct_free(r1); orc_ct_free(r2); orc_ct_free(t1); orc_ct_free(t2);
+            }
+            if (!late) { orc_ct *t = orc_rescale(c, Ak); orc_ct_free(Ak); Ak = t; }
+            orc_ct *prod = orc_tensor(c, Ak, bj[j]);
+            if (!once) { orc_ct *t = orc_relin(c, prod); orc_ct_free(prod); prod = t; }
+            S = acc_add(c, S, prod);
+            orc_ct_free(Ak);
         }
-        if (!late) { orc_ct *t = orc_rescale(c, Ak); orc_ct_free(Ak); Ak = t; }
-        orc_ct *Bk = k ? orc_rotate(c, B0, (int64_t)h * k) : ct_copy(c, B0);
-        orc_ct *prod = orc_tensor(c, Ak, Bk);
-        if (!once) { orc_ct *t = orc_relin(c, prod); orc_ct_free(prod); prod = t; }
-        acc = acc_add(c, acc, prod);
-        orc_ct_free(Ak); orc_ct_free(Bk);
+        if (once) { orc_ct *t = orc_relin(c, S); orc_ct_free(S); S = t; }
+        if (i) { orc_ct *t = orc_rotate(c, S, shift); orc_ct_free(S); S = t; }
+        acc = acc_add(c, acc, S);
     }
-    if (once) { orc_ct *t = orc_relin(c, acc); orc_ct_free(acc); acc = t; }
+    for (int j = 0; j < bg; j++) orc_ct_free(bj[j]);
+    free(bj);
     orc_ct *res = orc_rescale(c, acc);
     if (late) { orc_ct *t = orc_rescale(c, res); orc_ct_free(res); res = t; }
     orc_ct_free(acc); orc_ct_free(A0); orc_ct_free(B0); orc_ct_free(a); orc_ct_free(bb);

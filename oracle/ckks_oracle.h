@@ -95,17 +95,22 @@ void orc_rotate_hoisted(orc_ctx *c, const orc_ct *a, int n, const int64_t *ks, o
  * HOIST_MODDOWN: in Step 2, v_k . Rot(A0, k) + v_(k-h) . Rot(A0, k-h) is formed in the
  *   extended basis and brought down with one ModDown;
  * RESCALE_LATE: A^(k) is not rescaled; Step 3 multiplies one level higher and the sum is
- *   rescaled twice (same depth). */
+ *   rescaled twice (same depth);
+ * STEP3_BSGS: the Step-3 sum is split into baby and giant steps (k = bg i + j), so that B0
+ *   is rotated bg - 1 times and each of the h / bg block sums once, instead of h - 1 rotations
+ *   of B0; the A-side rotations absorb the giant-step shift. */
 #define ORC_RELIN_EACH 0
 #define ORC_RELIN_ONCE 1
 #define ORC_HOIST_MODDOWN 2
 #define ORC_RESCALE_LATE 4
+#define ORC_STEP3_BSGS 8
 orc_ct *orc_matmul(orc_ctx *c, const orc_ct *a, const orc_ct *b, int h, int relin_mode);
 /* slot-domain 0/1 vectors of length h*h for the diagonals used by Alg. 3:
  * kind 0: u^mu_k (k in (-h,h)), 1: u^zeta_{h k} (k in [0,h)), 2: v_k (k in [0,h)), 3: v_{k-h} */
 void orc_mask_slots(int kind, int h, int k, double *out);
-/* rotation amounts (mod N/2, normalised into [0,N/2)) the product needs for h */
-int orc_matmul_rotations(const orc_ctx *c, int h, int64_t *out, int cap);
+/* rotation amounts (mod N/2, normalised into [0,N/2)) the product needs for h under the
+ * given schedule flags */
+int orc_matmul_rotations(const orc_ctx *c, int h, int mode, int64_t *out, int cap);
 /* 0 rotations, 1 key switches, 2 mul_pt, 3 mul_ct, 4 add, 5 rescale */
 void orc_counters(const orc_ctx *c, int64_t out[6]);
 void orc_reset_counters(orc_ctx *c);

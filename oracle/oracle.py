@@ -22,7 +22,8 @@ RELIN_EACH = 0
 RELIN_ONCE = 1
 HOIST_MODDOWN = 2
 RESCALE_LATE = 4
-FAST = RELIN_ONCE | HOIST_MODDOWN | RESCALE_LATE
+STEP3_BSGS = 8
+FAST = RELIN_ONCE | HOIST_MODDOWN | RESCALE_LATE | STEP3_BSGS
 
 
 def build(force: bool = False) -> str:
@@ -96,7 +97,7 @@ def _declare(L):
         "orc_rotate_hoisted": (None, [vp, vp, i32, P(i64), P(vp)]),
         "orc_matmul": (vp, [vp, vp, vp, i32, i32]),
         "orc_mask_slots": (None, [i32, i32, i32, P(dbl)]),
-        "orc_matmul_rotations": (i32, [vp, i32, P(i64), i32]),
+        "orc_matmul_rotations": (i32, [vp, i32, i32, P(i64), i32]),
         "orc_counters": (None, [vp, P(i64)]),
         "orc_reset_counters": (None, [vp]),
         "orc_sign": (vp, [vp, vp, i32, i32, i32]),
@@ -343,9 +344,9 @@ class Ctx:
     def matmul(self, a, b, h, relin_mode=RELIN_EACH):
         return Ct(self, lib().orc_matmul(self.ptr, a.ptr, b.ptr, h, relin_mode))
 
-    def matmul_rotations(self, h):
+    def matmul_rotations(self, h, mode=RELIN_EACH):
         o = np.zeros(8192, np.int64)
-        n = lib().orc_matmul_rotations(self.ptr, h, i64p(o), 8192)
+        n = lib().orc_matmul_rotations(self.ptr, h, mode, i64p(o), 8192)
         return sorted(int(x) for x in o[:n])
 
     def counters(self):

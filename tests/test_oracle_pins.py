@@ -452,29 +452,85 @@ def test_matmul_relin_once(small):
 
 
 MODES = [O.RELIN_EACH, O.RELIN_ONCE, O.HOIST_MODDOWN, O.RESCALE_LATE,
-         O.RELIN_ONCE | O.HOIST_MODDOWN, O.FAST]
+         O.RELIN_ONCE | O.HOIST_MODDOWN, O.RELIN_ONCE | O.HOIST_MODDOWN | O.RESCALE_LATE,
+         O.STEP3_BSGS, O.STEP3_BSGS | O.RELIN_ONCE, O.FAST]
+
+
+def step3_counts(h, mode):
+    """(rotations, relinearisations) of Steps 2-3: 2(h-1) rotations of A0; with the Step-3
+    split (bg baby steps, bg = 2^ceil((log2 h + 1)/2) capped at h) bg - 1 rotations of B0 and
+    h/bg - 1 giant-step rotations, else h - 1 rotations of B0; one relinearisation per
+    product, or per block sum under relin-once"""
+    bg = min(h, 2 ** ((int(math.log2(h)) + 2) // 2)) if mode & O.STEP3_BSGS else h
+    rots = 2 * (h - 1) + (bg - 1) + (h // bg - 1)
+    relins = h // bg if mode & O.RELIN_ONCE else h
+    return rots, relins
+
+
+def step1_rotations(h):
+    b = 2 ** ((int(math.log2(h)) + 1) // 2)
+    giant11 = len([i for i in range((1 - h) // b, (h - 1) // b + 1) if i != 0])
+    return (b - 1) + giant11 + (b - 1) + (len(range(0, h, b)) - 1)
+
+
+def test_step3_count_helpers_match_default_formula():
+    for h in (4, 8, 16, 32, 64):
+        assert step1_rotations(h) + step3_counts(h, 0)[0] == expected_rotations(h)
 
 
 @pytest.mark.parametrize("mode", MODES)
 def test_matmul_schedules_decrypt_and_counts(small, mode):
     """every schedule computes A B at the same depth; the op counts follow from what
-    each flag moves (one relinearisation instead of h, ModDown shared by a mask pair,
-    two rescales at the end instead of one per A^(k))"""
-    h = 8
-    A, B = I.matrix_pair(40 + mode, h)
-    ca, cb = small.encrypt(A.ravel(), nonce=50), small.encrypt(B.ravel(), nonce=51)
-    small.reset_counters()
-    cm = small.matmul(ca, cb, h, mode)
-    cnt = small.counters()
-    assert cm.level == ca.level - 3
-    assert abs(cm.scale / ca.scale - 1) < 1e-3
-    full = small.decrypt(cm)
-    for r in range(small.n // 2 // (h * h)):
-        assert np.abs(full[r * h * h:(r + 1) * h * h].reshape(h, h) - A @ B).max() < 1e-3
-    assert cnt["rot"] == expected_rotations(h)
-    assert cnt["keyswitch"] == expected_rotations(h) + (1 if mode & O.RELIN_ONCE else h)
-    assert cnt["mul_pt"] == (2 * h - 1) + h + (2 * (h - 1) + 1)
-    assert cnt["rescale"] == 2 + (2 if mode & O.RESCALE_LATE else h + 1)
+    each flag moves (one relinearisation per block instead of per product, ModDown shared
+    by a mask pair, two rescales at the end instead of one per A^(k), fewer B0 rotations)"""
+    for h in (8, 16):
+        A, B = I.matrix_pair(40 + mode, h)
+        ca, cb = small.encrypt(A.ravel(), nonce=50), small.encrypt(B.ravel(), nonce=51)
+        small.reset_counters()
+        cm = small.matmul(ca, cb, h, mode)
+        cnt = small.counters()
+        assert cm.level == ca.level - 3
+        assert abs(cm.scale / ca.scale - 1) < 1e-3
+        full = small.decrypt(cm)
+        for r in range(small.n // 2 // (h * h)):
+            assert np.abs(full[r * h * h:(r + 1) * h * h].reshape(h, h) - A @ B).max() < 1e-3
+        rots, relins = step3_counts(h, mode)
+        assert cnt["rot"] == step1_rotations(h) + rots
+        assert cnt["keyswitch"] == step1_rotations(h) + rots + relins
+        assert cnt["mul_pt"] == (2 * h - 1) + h + (2 * (h - 1) + 1)
+        assert cnt["mul_ct"] == h
+        assert cnt["rescale"] == 2 + (2 if mode & O.RESCALE_LATE else h + 1)
+        # every rotation the product performs has a key in the schedule's rotation list
+        assert len(small.matmul_rotations(h, mode)) <= cnt["rot"]
+
+
+@pytest.mark.parametrize("h,keys", [(16, 44), (32, 79), (64, 160)])
+def test_step3_bsgs_rotation_keys(h, keys):
+    """distinct rotation amounts under the Step-3 split (A-side amounts k - s, k - h - s with
+    the giant shift s, B0 baby steps h j, giant steps h bg i, and Step 1's)"""
+    c = O.Ctx(14, [40, 40], [50], 1, 30.0, 1)
+    got = c.matmul_rotations(h, O.STEP3_BSGS)
+    assert len(got) == keys
+    b = 2 ** ((int(math.log2(h)) + 1) // 2)
+    bg = min(h, 2 ** ((int(math.log2(h)) + 2) // 2))
+    half = c.n // 2
+    want = set()
+    for j in range(1, b):
+        want |= {j, h * j}
+    for i in range((1 - h) // b, (h - 1) // b + 1):
+        if i:
+            want.add((b * i) % half)
+    for i in range(1, (h + b - 1) // b):
+        want.add(h * b * i)
+    for k in range(1, h):
+        s = h * bg * (k // bg)
+        want |= {(k - s) % half, (k - h - s) % half}
+    for j in range(1, bg):
+        want.add(h * j)
+    for i in range(1, h // bg):
+        want.add(h * bg * i)
+    want.discard(0)
+    assert sorted(want) == got
 
 
 def test_matmul_schedules_agree_at_coefficient_level(small):
