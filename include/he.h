@@ -66,7 +66,11 @@ typedef struct {
                                    * the extended basis Q_l P, one ModDown for the pair */
 #define HE_SCHED_RESCALE_LATE 4u  /* Step 2: A^(k) kept unrescaled; Step 3 multiplies one level
                                    * higher and the sum is rescaled twice */
-#define HE_SCHED_ALL 7u
+#define HE_SCHED_STEP3_BSGS 8u    /* Step 3 as sum_i Rot(sum_j Rot(A^(bg i+j), -h bg i) . Rot(B0, h j),
+                                   * h bg i): bg - 1 + h/bg - 1 rotations on the B side instead of
+                                   * h - 1 (bg = 2^ceil((log2 h + 1)/2)); the rotation keys and
+                                   * masks made for each h follow the schedule */
+#define HE_SCHED_ALL 15u
 
 typedef struct {
     uint32_t log_n;          /* ring degree N = 2^log_n, 8 <= log_n <= 17 */

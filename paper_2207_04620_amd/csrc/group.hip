@@ -488,35 +488,65 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
         return false;
     }
     if (J.phase == 1) {
-        // Steps 2 and 3: A^(k) = RS(v_k . Rot(A0, k) + v_{k-h} . Rot(A0, k-h)), B^(k) = Rot(B0, h k)
+        // Steps 2 and 3 in blocks k = bg i + j (one block of h without the Step-3 split):
+        //   A^(k) shifted by s = h bg i: R(v_k, -s) . Rot(A0, k - s) + R(v_{k-h}, -s) . Rot(A0, k - h - s)
+        //   (RS unless late), times Rot(B0, h j), summed over j; the block sum is relinearised
+        //   (relin-once) and rotated by s
+        const int bg = step3_baby(h);
+        const bool keep_baby = bg < h;
+        if (keep_baby && J.babyB.empty()) J.babyB.resize(bg);
         const int kend = std::min(h, J.k + std::max(1, k_chunk));
         for (int k = J.k; k < kend; ++k) {
+            const int i = k / bg, j = k % bg;
+            const int64_t shift = (int64_t)h * bg * i;
             Grp Ak;
             if (k == 0) {
                 Ak = g_mask_sum({{&J.A0, mask(2, h, 0, 0)}}, ms);
             } else if (schedule & HE_SCHED_HOIST_MODDOWN) {
-                Ak = g_rotate_pair_hoisted(J.A0, J.liftA->p, k, mask(2, h, k, 0), k - h, mask(3, h, k, 0), ms);
+                Ak = g_rotate_pair_hoisted(J.A0, J.liftA->p, k - shift, mask(2, h, k, -shift), k - h - shift,
+                                           mask(3, h, k, -shift), ms);
             } else {
-                // v_k . Rot(A0, k) + v_{k-h} . Rot(A0, k-h), masks applied in the ModDown epilogues
-                Grp t1 = g_rotate_mask_from_lift(J.A0, J.liftA->p, k, mask(2, h, k, 0), ms, nullptr);
-                Ak = g_rotate_mask_from_lift(J.A0, J.liftA->p, k - h, mask(3, h, k, 0), ms, &t1);
+                // masks applied in the ModDown epilogues
+                Grp t1 = g_rotate_mask_from_lift(J.A0, J.liftA->p, k - shift, mask(2, h, k, -shift), ms, nullptr);
+                Ak = g_rotate_mask_from_lift(J.A0, J.liftA->p, k - h - shift, mask(3, h, k, -shift), ms, &t1);
             }
             if (!(schedule & HE_SCHED_RESCALE_LATE)) Ak = g_rescale(Ak);
-            Grp Bk = k ? g_rotate_from_lift(J.B0, J.liftB->p, (int64_t)h * k) : J.B0;
+            Grp Bj;
+            if (j == 0) {
+                Bj = J.B0;
+            } else if (i > 0) {
+                Bj = J.babyB[j];
+            } else {
+                Bj = g_rotate_from_lift(J.B0, J.liftB->p, (int64_t)h * j);
+                if (keep_baby) J.babyB[j] = Bj;
+            }
             if (!(schedule & HE_SCHED_RELIN_ONCE)) {
-                Grp prod = g_relin(g_tensor(Ak, Bk));
-                if (!J.have) {
-                    J.acc = prod;
-                    J.have = true;
+                Grp prod = g_relin(g_tensor(Ak, Bj));
+                if (!J.haveS) {
+                    J.S = prod;
+                    J.haveS = true;
                 } else {
-                    g_add_into(J.acc, prod);
+                    g_add_into(J.S, prod);
                 }
             } else {
+                if (!J.haveS) {
+                    J.S = g_tensor(Ak, Bj);
+                    J.haveS = true;
+                } else {
+                    g_tensor_acc(J.S, Ak, Bj);
+                }
+            }
+            if (j == bg - 1 || k == h - 1) {
+                Grp blk = J.S;
+                J.S = Grp();
+                J.haveS = false;
+                if (schedule & HE_SCHED_RELIN_ONCE) blk = g_relin(blk);
+                if (i > 0) blk = g_rotate(blk, shift);
                 if (!J.have) {
-                    J.acc = g_tensor(Ak, Bk);
+                    J.acc = blk;
                     J.have = true;
                 } else {
-                    g_tensor_acc(J.acc, Ak, Bk);
+                    g_add_into(J.acc, blk);
                 }
             }
         }
@@ -526,11 +556,11 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
             J.liftB.reset();
             J.A0 = Grp();
             J.B0 = Grp();
+            J.babyB.clear();
             J.phase = 2;
         }
         return false;
     }
-    if (schedule & HE_SCHED_RELIN_ONCE) J.acc = g_relin(J.acc);
     J.acc = g_rescale(J.acc);
     if (schedule & HE_SCHED_RESCALE_LATE) J.acc = g_rescale(J.acc);
     J.result = g_scatter(J.acc);

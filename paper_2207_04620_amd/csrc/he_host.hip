@@ -856,6 +856,12 @@ static int ilog2i(int h) {
 }
 static int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 int Ctx::bsgs(int h) const { return 1 << ((ilog2i(h) + 1) / 2); }
+// baby steps bg of the Step-3 split k = bg i + j (2^ceil((log2 h + 1) / 2), at most h); one
+// block of h terms without the flag
+int Ctx::step3_baby(int h) const {
+    if (!(schedule & HE_SCHED_STEP3_BSGS)) return h;
+    return std::min(h, 1 << ((ilog2i(h) + 2) / 2));
+}
 
 std::vector<MaskKey> Ctx::matmul_masks(int h) const {
     std::vector<MaskKey> out;
@@ -868,9 +874,11 @@ std::vector<MaskKey> Ctx::matmul_masks(int h) const {
     for (int i = 0; i * b < h; ++i)
         for (int j = 0; j < b && b * i + j < h; ++j) out.push_back({1, h, b * i + j, -(int64_t)h * b * i});
     out.push_back({2, h, 0, 0});
+    const int bg = step3_baby(h);
     for (int k = 1; k < h; ++k) {
-        out.push_back({2, h, k, 0});
-        out.push_back({3, h, k, 0});
+        const int64_t shift = (int64_t)h * bg * (k / bg);
+        out.push_back({2, h, k, -shift});
+        out.push_back({3, h, k, -shift});
     }
     return out;
 }
@@ -883,11 +891,14 @@ std::vector<int64_t> Ctx::matmul_rotations(int h) const {
         if (i) r.push_back((int64_t)b * i);
     for (int j = 1; j < b; ++j) r.push_back((int64_t)h * j);
     for (int i = 1; i * b < h; ++i) r.push_back((int64_t)h * b * i);
+    const int bg = step3_baby(h);
     for (int k = 1; k < h; ++k) {
-        r.push_back(k);
-        r.push_back(k - h);
-        r.push_back((int64_t)h * k);
+        const int64_t shift = (int64_t)h * bg * (k / bg);
+        r.push_back(k - shift);
+        r.push_back(k - h - shift);
     }
+    for (int j = 1; j < bg; ++j) r.push_back((int64_t)h * j);
+    for (int i = 1; i * bg < h; ++i) r.push_back((int64_t)h * bg * i);
     return r;
 }
 

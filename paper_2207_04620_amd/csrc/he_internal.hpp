@@ -72,8 +72,9 @@ struct Grp {
 struct MatmulJob {
     std::vector<const CtData*> A, B;
     int h = 0, lvl = 0, phase = 0, k = 0;
-    Grp A0, B0, acc;
-    bool have = false;
+    Grp A0, B0, acc, S;   // S: the current Step-3 block sum
+    bool have = false, haveS = false;
+    std::vector<Grp> babyB;  // Rot(B0, h j), j < bg, kept across blocks (Step-3 split)
     std::shared_ptr<DBuf> liftA, liftB;
     std::vector<CtPtr> result;
 };
@@ -162,6 +163,7 @@ struct Ctx {
     const u64* mask(int kind, int h, int k, int64_t rot);
     void prepare_masks(const std::vector<MaskKey>& keys);
     int bsgs(int h) const;
+    int step3_baby(int h) const;
     std::vector<MaskKey> matmul_masks(int h) const;
     std::vector<int64_t> matmul_rotations(int h) const;
     void prepare_h(int h);

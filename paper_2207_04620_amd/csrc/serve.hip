@@ -70,7 +70,11 @@ static size_t footprint(const Ctx* c, const he_request& r, int level) {
     const size_t ct = 2 * (size_t)(level + 1) * c->N * 8;
     const int beta = (level + 1 + c->alpha - 1) / c->alpha;
     const size_t lift = (size_t)beta * (level + 1 + c->n_p) * c->N * 8;
-    if (r.op == HE_REQ_MATMUL) return (size_t)(c->bsgs((int)r.h) + 10) * ct + 3 * lift;
+    if (r.op == HE_REQ_MATMUL) {
+        // Step-1 baby steps, the Step-3 baby rotations of B0 kept across blocks, temporaries
+        const int bg = c->step3_baby((int)r.h);
+        return (size_t)(c->bsgs((int)r.h) + (bg < (int)r.h ? bg : 0) + 10) * ct + 3 * lift;
+    }
     return 12 * ct + 2 * lift;
 }
 

@@ -20,7 +20,8 @@ SCHED_RELIN_EACH = 0
 SCHED_RELIN_ONCE = 1
 SCHED_HOIST_MODDOWN = 2
 SCHED_RESCALE_LATE = 4
-SCHED_FAST = SCHED_RELIN_ONCE | SCHED_HOIST_MODDOWN | SCHED_RESCALE_LATE
+SCHED_STEP3_BSGS = 8
+SCHED_FAST = SCHED_RELIN_ONCE | SCHED_HOIST_MODDOWN | SCHED_RESCALE_LATE | SCHED_STEP3_BSGS
 SIGN = 0
 RELU = 1
 REQ_MATMUL = 0

@@ -188,7 +188,7 @@ def test_matmul_relin_once_parity(he):
     p.same(gm, om)
 
 
-SCHEDULES = [2, 4, 3, 5, 6, 7]  # flag combinations beyond relin-each / relin-once
+SCHEDULES = [2, 4, 3, 5, 6, 7, 8, 9, 14, 15]  # flag combinations beyond relin-each / relin-once
 
 
 @pytest.mark.parametrize("schedule", SCHEDULES)
@@ -225,11 +225,11 @@ def test_matmul_schedule_parity(he, schedule):
 
 
 def test_matmul_fast_schedule_c1plus_bound(he):
-    """the stated accuracy (1e-3 at scale 2^30, 2^12 ring, h = 8) under all three flags"""
-    p = Pair(he, I.C1P, schedule=7)
+    """the stated accuracy (1e-3 at scale 2^30, 2^12 ring, h = 8) under all four flags"""
+    p = Pair(he, I.C1P, schedule=15)
     A, B = I.matrix_pair(2, 8)
     gm = p.g.matmul(p.g.encrypt(A.ravel(), nonce=1), p.g.encrypt(B.ravel(), nonce=2), 8)
-    om = p.o.matmul(p.o.encrypt(A.ravel(), nonce=1), p.o.encrypt(B.ravel(), nonce=2), 8, 7)
+    om = p.o.matmul(p.o.encrypt(A.ravel(), nonce=1), p.o.encrypt(B.ravel(), nonce=2), 8, 15)
     p.same(gm, om)
     assert np.abs(p.g.decrypt(gm, 64).reshape(8, 8) - A @ B).max() < 1e-3
 
@@ -321,3 +321,32 @@ def test_c3_rotations_and_h16_matmul_parity(he):
     om = p.o.matmul(oa, ob, 16)
     p.same(gm, om)
     assert np.abs(p.g.decrypt(gm, 256).reshape(16, 16) - A @ B).max() < 1e-6
+
+
+def test_c3_h64_batch16_fast_schedule_full_size(he):
+    """the benchmarked configuration itself: a batch of 16 h=64 products on the N=2^15
+    ring from level 13 under the fastest schedule (all four flags), through the batched
+    entry point the benchmark times.  Member 0 against the oracle on every residue; every
+    member within the FP64 bound of A B, and equal to the same product run alone."""
+    prm = I.C3
+    g = he.Context(prm, h_list=[64], schedule=15)
+    pairs = [I.matrix_pair(1000 + i, 64) for i in range(16)]
+    As = [g.encrypt(A.ravel(), level=13, nonce=2 * i) for i, (A, _) in enumerate(pairs)]
+    Bs = [g.encrypt(B.ravel(), level=13, nonce=2 * i + 1) for i, (_, B) in enumerate(pairs)]
+    _log("[parity] C3 h=64 batch 16, schedule 15: GPU batch")
+    out = g.matmul_batch(As, Bs, [64] * 16)
+    for i, (A, B) in enumerate(pairs):
+        err = np.abs(g.decrypt(out[i], 4096).reshape(64, 64) - A @ B).max()
+        assert err < 1e-5, (i, err)
+    _log("[parity] C3 h=64: member 5 alone")
+    assert np.array_equal(g.export(g.matmul(As[5], Bs[5], 64)), g.export(out[5]))
+    _log("[parity] C3 h=64: oracle, member 0")
+    o = O.Ctx.from_params(prm)
+    A, B = pairs[0]
+    om = o.matmul(o.encrypt(A.ravel(), level=13, nonce=0), o.encrypt(B.ravel(), level=13, nonce=1), 64, 15)
+    gexp, oexp = g.export(out[0]), om.export()
+    assert gexp.shape == oexp.shape
+    bad = np.argwhere(gexp != oexp)
+    assert bad.size == 0, f"{len(bad)} residues differ, first at {bad[:3].tolist()}"
+    _log("[parity] C3 h=64: bit-exact")
+    g.close()
