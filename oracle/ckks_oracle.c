@@ -1078,54 +1078,66 @@ int orc_matmul_rotations(const orc_ctx *c, int h, int mode, int64_t *out, int ca
     return n;
 }
 
-/* v_1 . Rot(a, r_1) + v_2 . Rot(a, r_2) with one ModDown: each rotation's key-switch inner
- * product (plus P * sigma_g(c0) on the Q limbs) is multiplied by its mask in the extended
- * basis Q_l u P, the two are added there, and the sum is brought down once. */
-static orc_ct *rot_mask_pair_hoisted(orc_ctx *c, const orc_ct *a, const int64_t r[2], const int64_t *const mask[2],
-                                     double ms) {
+/* sum_w v_w . Rot(a_w, r_w) (v_w = 1 when masks is NULL or masks[w] is NULL) with one
+ * ModDown: each rotation's key-switch inner product, plus P * sigma_g(c0) on the Q limbs, is
+ * multiplied by its mask in the extended basis Q_l u P; the terms are added there and the
+ * sum is brought down once.  ModDown(X + P c) = ModDown(X) + c exactly, so each term
+ * contributes Rot(a_w, r_w) up to the one shared rounding. */
+static orc_ct *rot_sum_hoisted(orc_ctx *c, int n, orc_ct *const *a, const int64_t *r, const int64_t *const *masks,
+                               double ms) {
     int64_t N = c->n;
-    int nl = a->level + 1, K = c->n_p, ne = nl + K;
+    int level = a[0]->level, nl = level + 1, K = c->n_p, ne = nl + K;
     int ext[MAXMOD];
     for (int i = 0; i < nl; i++) ext[i] = i;
     for (int i = 0; i < K; i++) ext[nl + i] = c->n_q + i;
     u64 *X0 = calloc((size_t)ne * N, sizeof(u64)), *X1 = calloc((size_t)ne * N, sizeof(u64));
     u64 *u0 = malloc(sizeof(u64) * ne * N), *u1 = malloc(sizeof(u64) * ne * N);
     u64 *p1 = malloc(sizeof(u64) * nl * N), *c0r = malloc(sizeof(u64) * nl * N);
-    for (int w = 0; w < 2; w++) {
+    double scale = 0;
+    for (int w = 0; w < n; w++) {
+        const int64_t *mask = masks ? masks[w] : NULL;
         u64 g = galois_elt(c, r[w]);
         const swk_t *key = get_key(c, g);
         u64 *d[MAXMOD];
         for (int i = 0; i < nl; i++) {
-            automorph(c, limb(a, 1, i), p1 + (int64_t)i * N, g, c->mod[i]);
-            automorph(c, limb(a, 0, i), c0r + (int64_t)i * N, g, c->mod[i]);
+            automorph(c, limb(a[w], 1, i), p1 + (int64_t)i * N, g, c->mod[i]);
+            automorph(c, limb(a[w], 0, i), c0r + (int64_t)i * N, g, c->mod[i]);
             d[i] = p1 + (int64_t)i * N;
         }
-        ks_inner(c, a->level, d, NULL, key, u0, u1);
+        ks_inner(c, level, d, NULL, key, u0, u1);
 #pragma omp parallel for num_threads(c->threads)
         for (int ti = 0; ti < ne; ti++) {
             int t = ext[ti];
             u64 q = c->mod[t];
+            u64 *x0 = u0 + (int64_t)ti * N, *x1 = u1 + (int64_t)ti * N;
             if (ti < nl) {  /* + P sigma_g(c0) on the Q limbs (P = 0 mod the special primes) */
                 u64 P = 1;
                 for (int kk = 0; kk < K; kk++) P = mulmod(P, c->mod[c->n_q + kk] % q, q);
-                for (int64_t s2 = 0; s2 < N; s2++)
-                    u0[(int64_t)ti * N + s2] = addmod(u0[(int64_t)ti * N + s2], mulmod(P, c0r[(int64_t)ti * N + s2], q), q);
+                for (int64_t s2 = 0; s2 < N; s2++) x0[s2] = addmod(x0[s2], mulmod(P, c0r[(int64_t)ti * N + s2], q), q);
             }
-            u64 *m = malloc(sizeof(u64) * N), *tmp = malloc(sizeof(u64) * N);
-            for (int64_t s2 = 0; s2 < N; s2++) m[s2] = smod(mask[w][s2], q);
-            orc_poly_mul(c, t, u0 + (int64_t)ti * N, m, tmp);
-            for (int64_t s2 = 0; s2 < N; s2++) X0[(int64_t)ti * N + s2] = addmod(X0[(int64_t)ti * N + s2], tmp[s2], q);
-            orc_poly_mul(c, t, u1 + (int64_t)ti * N, m, tmp);
-            for (int64_t s2 = 0; s2 < N; s2++) X1[(int64_t)ti * N + s2] = addmod(X1[(int64_t)ti * N + s2], tmp[s2], q);
-            free(m); free(tmp);
+            if (mask) {
+                u64 *m = malloc(sizeof(u64) * N), *tmp = malloc(sizeof(u64) * N);
+                for (int64_t s2 = 0; s2 < N; s2++) m[s2] = smod(mask[s2], q);
+                orc_poly_mul(c, t, x0, m, tmp);
+                memcpy(x0, tmp, sizeof(u64) * N);
+                orc_poly_mul(c, t, x1, m, tmp);
+                memcpy(x1, tmp, sizeof(u64) * N);
+                free(m); free(tmp);
+            }
+            for (int64_t s2 = 0; s2 < N; s2++) {
+                X0[(int64_t)ti * N + s2] = addmod(X0[(int64_t)ti * N + s2], x0[s2], q);
+                X1[(int64_t)ti * N + s2] = addmod(X1[(int64_t)ti * N + s2], x1[s2], q);
+            }
         }
         c->cnt[C_ROT]++;
-        c->cnt[C_MULPT]++;
+        if (mask) c->cnt[C_MULPT]++;
+        double sc = a[w]->scale * (mask ? ms : 1.0);
+        if (sc > scale) scale = sc;
     }
-    orc_ct *out = ct_new(c, a->level, 1, a->scale * ms);
-    ks_moddown(c, a->level, X0, out->c[0]);
-    ks_moddown(c, a->level, X1, out->c[1]);
-    c->cnt[C_ADD]++;
+    orc_ct *out = ct_new(c, level, 1, scale);
+    ks_moddown(c, level, X0, out->c[0]);
+    ks_moddown(c, level, X1, out->c[1]);
+    c->cnt[C_ADD] += n - 1;
     free(X0); free(X1); free(u0); free(u1); free(p1); free(c0r);
     return out;
 }
@@ -1137,6 +1149,11 @@ orc_ct *orc_matmul(orc_ctx *c, const orc_ct *A, const orc_ct *B, int h, int mode
     orc_ct *a = orc_drop(c, A, lvl), *bb = orc_drop(c, B, lvl);
     int b = 1 << ((ilog2(h) + 1) / 2);
     double ms = c->scale;
+    const int once = mode & ORC_RELIN_ONCE, hoist = mode & ORC_HOIST_MODDOWN, late = mode & ORC_RESCALE_LATE;
+    /* giant-step terms whose rotations share one ModDown (ModDown-hoisting flag) */
+    orc_ct **gi = calloc(2 * h + 2, sizeof(orc_ct *));
+    int64_t *gr = calloc(2 * h + 2, sizeof(int64_t));
+    int ng = 0;
 
     /* Step 1-1: A0 = sum_i Rot(sum_j R(u_{bi+j}, -bi) . Rot(A, j), b i), then RS */
     orc_ct **baby = calloc(b, sizeof(orc_ct *));
@@ -1151,8 +1168,13 @@ orc_ct *orc_matmul(orc_ctx *c, const orc_ct *A, const orc_ct *B, int h, int mode
             inner = acc_add(c, inner, orc_mul_plain(c, baby[j], get_mask(c, 0, h, k, -(int64_t)b * i), ms));
         }
         if (!inner) continue;
+        if (i && hoist) { gi[ng] = inner; gr[ng++] = (int64_t)b * i; continue; }
         if (i) { orc_ct *t = orc_rotate(c, inner, (int64_t)b * i); orc_ct_free(inner); inner = t; }
         A0 = acc_add(c, A0, inner);
+    }
+    if (ng) {
+        A0 = acc_add(c, A0, rot_sum_hoisted(c, ng, gi, gr, NULL, ms));
+        while (ng) orc_ct_free(gi[--ng]);
     }
     for (int j = 0; j < b; j++) orc_ct_free(baby[j]);
     { orc_ct *t = orc_rescale(c, A0); orc_ct_free(A0); A0 = t; }
@@ -1165,13 +1187,17 @@ orc_ct *orc_matmul(orc_ctx *c, const orc_ct *A, const orc_ct *B, int h, int mode
         orc_ct *inner = NULL;
         for (int j = 0; j < b && b * i + j < h; j++)
             inner = acc_add(c, inner, orc_mul_plain(c, baby[j], get_mask(c, 1, h, b * i + j, -(int64_t)h * b * i), ms));
+        if (i && hoist) { gi[ng] = inner; gr[ng++] = (int64_t)h * b * i; continue; }
         if (i) { orc_ct *t = orc_rotate(c, inner, (int64_t)h * b * i); orc_ct_free(inner); inner = t; }
         B0 = acc_add(c, B0, inner);
+    }
+    if (ng) {
+        B0 = acc_add(c, B0, rot_sum_hoisted(c, ng, gi, gr, NULL, ms));
+        while (ng) orc_ct_free(gi[--ng]);
     }
     for (int j = 0; j < b; j++) orc_ct_free(baby[j]);
     free(baby);
     { orc_ct *t = orc_rescale(c, B0); orc_ct_free(B0); B0 = t; }
-    const int once = mode & ORC_RELIN_ONCE, hoist = mode & ORC_HOIST_MODDOWN, late = mode & ORC_RESCALE_LATE;
     /* B0 is brought to the Step-3 level before its rotations (the late-rescale schedule
      * multiplies one level higher and keeps it) */
     if (!late) { orc_ct *t = orc_drop(c, B0, B0->level - 1); orc_ct_free(B0); B0 = t; }
@@ -1197,7 +1223,8 @@ orc_ct *orc_matmul(orc_ctx *c, const orc_ct *A, const orc_ct *B, int h, int mode
             } else if (hoist) {
                 const int64_t rr[2] = {k - shift, k - h - shift};
                 const int64_t *mm[2] = {get_mask(c, 2, h, k, -shift), get_mask(c, 3, h, k, -shift)};
-                Ak = rot_mask_pair_hoisted(c, A0, rr, mm, ms);
+                orc_ct *const aa[2] = {A0, A0};
+                Ak = rot_sum_hoisted(c, 2, aa, rr, mm, ms);
             } else {
                 orc_ct *r1 = orc_rotate(c, A0, k - shift), *r2 = orc_rotate(c, A0, k - h - shift);
                 orc_ct *t1 = orc_mul_plain(c, r1, get_mask(c, 2, h, k, -shift), ms);
@@ -1212,9 +1239,15 @@ orc_ct *orc_matmul(orc_ctx *c, const orc_ct *A, const orc_ct *B, int h, int mode
             orc_ct_free(Ak);
         }
         if (once) { orc_ct *t = orc_relin(c, S); orc_ct_free(S); S = t; }
+        if (i && hoist) { gi[ng] = S; gr[ng++] = shift; continue; }
         if (i) { orc_ct *t = orc_rotate(c, S, shift); orc_ct_free(S); S = t; }
         acc = acc_add(c, acc, S);
     }
+    if (ng) {
+        acc = acc_add(c, acc, rot_sum_hoisted(c, ng, gi, gr, NULL, 1.0));
+        while (ng) orc_ct_free(gi[--ng]);
+    }
+    free(gi); free(gr);
     for (int j = 0; j < bg; j++) orc_ct_free(bj[j]);
     free(bj);
     orc_ct *res = orc_rescale(c, acc);

@@ -92,8 +92,9 @@ void orc_rotate_hoisted(orc_ctx *c, const orc_ct *a, int n, const int64_t *ks, o
 /* ---- the packed matrix product (Alg. 3 + App. B) ---- */
 /* schedule flags of the product (each combination is its own bit-exact reference):
  * RELIN_ONCE: relinearise the accumulated Step-3 sum once instead of every product;
- * HOIST_MODDOWN: in Step 2, v_k . Rot(A0, k) + v_(k-h) . Rot(A0, k-h) is formed in the
- *   extended basis and brought down with one ModDown;
+ * HOIST_MODDOWN: sums of rotations share one ModDown, the terms being formed in the
+ *   extended basis: Step 2's v_k . Rot(A0, k) + v_(k-h) . Rot(A0, k-h), and the giant-step
+ *   sums of Steps 1-1 and 1-2 (and of Step 3 under STEP3_BSGS);
  * RESCALE_LATE: A^(k) is not rescaled; Step 3 multiplies one level higher and the sum is
  *   rescaled twice (same depth);
  * STEP3_BSGS: the Step-3 sum is split into baby and giant steps (k = bg i + j), so that B0
