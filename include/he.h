@@ -62,8 +62,10 @@ typedef struct {
  * happens, so each is its own bit-exact reference. */
 #define HE_SCHED_RELIN_EACH 0u    /* relinearise every Step-3 product (Mul_ct of Fig. 1) */
 #define HE_SCHED_RELIN_ONCE 1u    /* accumulate degree-2 products, relinearise once */
-#define HE_SCHED_HOIST_MODDOWN 2u /* Step 2: v_k . Rot(A0,k) + v_(k-h) . Rot(A0,k-h) formed in
-                                   * the extended basis Q_l P, one ModDown for the pair */
+#define HE_SCHED_HOIST_MODDOWN 2u /* sums of rotations share one ModDown, their terms formed in
+                                   * the extended basis Q_l P: Step 2's v_k . Rot(A0,k) +
+                                   * v_(k-h) . Rot(A0,k-h), the giant-step sums of Steps 1-1 and
+                                   * 1-2, and of Step 3 under HE_SCHED_STEP3_BSGS */
 #define HE_SCHED_RESCALE_LATE 4u  /* Step 2: A^(k) kept unrescaled; Step 3 multiplies one level
                                    * higher and the sum is rescaled twice */
 #define HE_SCHED_STEP3_BSGS 8u    /* Step 3 as sum_i Rot(sum_j Rot(A^(bg i+j), -h bg i) . Rot(B0, h j),
@@ -191,11 +193,13 @@ he_status he_serve_poll(he_server *s, uint64_t ticket, int *done, he_ct **result
                         double *latency_s);
 he_status he_serve_stop(he_server *s);
 
-/* Launch timing: with profiling on, every kernel launch is bracketed by HIP events on
- * its stream.  The report (JSON text, NUL-terminated, truncated to n bytes) gives per
- * kernel kind the launch count, summed duration in ms and algorithmic bytes (operands
- * read once, results written once); reading it synchronizes and clears the records. */
-he_status he_profile_enable(he_ctx *ctx, int on);
+/* Launch timing: with profiling on, every kernel launch (or, with 'only' naming one kernel
+ * kind of the report, e.g. "ntt_fwd_rows", every launch of that kind) is bracketed by HIP
+ * events on its stream.  The report (JSON text, NUL-terminated, truncated to n bytes) gives
+ * per kernel kind the launch count, summed duration in ms and algorithmic bytes (operands
+ * read once, results written once); reading it synchronizes and clears the records.
+ * An unknown kind name is HE_EINVAL.  The setting is process-wide. */
+he_status he_profile_enable(he_ctx *ctx, int on, const char *only);
 he_status he_profile_report(he_ctx *ctx, char *buf, size_t n);
 
 const char *he_status_string(he_status s);

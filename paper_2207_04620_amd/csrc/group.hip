@@ -138,21 +138,20 @@ std::shared_ptr<DBuf> Ctx::g_lift(const Grp& a, int poly) {
 }
 
 // Key-switch inner product <lift o sigma_g, key> (+ P sigma_g(c0) on the Q limbs) of every
-// member into u [B][2][ne][N]; with a second (g2, key2) and masks, the masked sum of two
-// rotations of the same lift (one ModDown then serves both)
-std::shared_ptr<DBuf> Ctx::g_ks_inner(const u64* lift, int B, int level, const u64* key, u64 g, const u64* c0,
-                                      int64_t c0_cs, const u64* mask, const u64* key2, u64 g2, const u64* mask2) {
+// member into u [B][2][ne][N] (added to what u holds with accumulate); with a second
+// (g2, key2) and masks, the masked sum of two rotations of the same lift (one ModDown then
+// serves both)
+void Ctx::g_ks_inner(DBuf& u, const u64* lift, int B, int level, const u64* key, u64 g, const u64* c0,
+                     int64_t c0_cs, const u64* mask, const u64* key2, u64 g2, const u64* mask2, bool accumulate) {
     const int nl = level + 1, ne = nl + n_p;
     const int beta = (int)mu[level].size();
-    const int64_t ucs = 2 * (int64_t)ne * N;
-    auto u = std::make_shared<DBuf>(this, (size_t)B * ucs);
     IpDesc D;
     memset(&D, 0, sizeof D);
     D.lift = lift;
     D.key = key;
-    D.u = u->p;
+    D.u = u.p;
     D.lift_cs = (int64_t)beta * ne * N;
-    D.u_cs = ucs;
+    D.u_cs = 2 * (int64_t)ne * N;
     D.nct = B;
     D.ne = ne;
     D.beta = beta;
@@ -168,9 +167,9 @@ std::shared_ptr<DBuf> Ctx::g_ks_inner(const u64* lift, int B, int level, const u
     D.g2 = g2;
     D.mask = mask;
     D.mask2 = mask2;
+    D.accumulate = accumulate ? 1 : 0;
     launch_inner_product(T, D, stream);
     cnt[C_KS] += (int64_t)B * D.nrot;
-    return u;
 }
 
 // out = ModDown(u) (+ add gathered by add_g) (. mask) (+ acc), for every member; u as made
@@ -258,8 +257,9 @@ void Ctx::g_moddown(DBuf& u, int B, int level, const u64* add0, const u64* add1,
 void Ctx::g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, const u64* add0, const u64* add1,
                      int64_t add_cs, u64* out0, u64* out1, int64_t out_cs, u64 add_g, const u64* mask,
                      const u64* acc0, const u64* acc1, int64_t acc_cs, const u64* c0, int64_t c0_cs) {
-    auto u = g_ks_inner(lift, B, level, key, g, c0, c0_cs, nullptr, nullptr, 1, nullptr);
-    g_moddown(*u, B, level, add0, add1, add_cs, out0, out1, out_cs, add_g, mask, acc0, acc1, acc_cs);
+    DBuf u(this, (size_t)B * 2 * (level + 1 + n_p) * N);
+    g_ks_inner(u, lift, B, level, key, g, c0, c0_cs, nullptr, nullptr, 1, nullptr, false);
+    g_moddown(u, B, level, add0, add1, add_cs, out0, out1, out_cs, add_g, mask, acc0, acc1, acc_cs);
 }
 
 // v1 . Rot(a, k1) + v2 . Rot(a, k2) with both masks applied in the extended basis and a
@@ -272,11 +272,50 @@ Grp Ctx::g_rotate_pair_hoisted(const Grp& a, const u64* lift, int64_t k1, const 
     std::vector<double> sc(a.scale);
     for (auto& v : sc) v *= mask_scale;
     Grp out = g_new(a.B, a.level, 1, sc);
-    auto u = g_ks_inner(lift, a.B, a.level, key1, g1, a.p, a.cs, mask1, key2, g2, mask2);
-    g_moddown(*u, a.B, a.level, nullptr, nullptr, 0, out.p, out.p + out.ps, out.cs, 1, nullptr, nullptr, nullptr, 0);
+    DBuf u(this, (size_t)a.B * 2 * (a.level + 1 + n_p) * N);
+    g_ks_inner(u, lift, a.B, a.level, key1, g1, a.p, a.cs, mask1, key2, g2, mask2, false);
+    g_moddown(u, a.B, a.level, nullptr, nullptr, 0, out.p, out.p + out.ps, out.cs, 1, nullptr, nullptr, nullptr, 0);
     cnt[C_ROT] += 2 * a.B;
     cnt[C_MULPT] += 2 * a.B;
     cnt[C_ADD] += a.B;
+    return out;
+}
+
+// Hoisted rotation sums: base + sum_w Rot(a_w, r_w) with one ModDown.  Each term's
+// key-switch inner product (with P sigma_g(c0_w)) is accumulated in the extended basis as it
+// arrives (its lift is freed at once); finish brings the sum down once and adds the
+// unrotated base in the ModDown epilogue.  Exact apart from the one shared ModDown rounding.
+void Ctx::g_rotsum_add(RotSum& S, const Grp& a, int64_t r) {
+    if (a.deg != 1) throw HeError(HE_EMISMATCH);
+    if (!S.u) {
+        S.B = a.B;
+        S.level = a.level;
+        S.n = 0;
+        S.scale = a.scale;
+        S.u = std::make_shared<DBuf>(this, (size_t)a.B * 2 * (a.level + 1 + n_p) * N);
+    }
+    if (a.B != S.B || a.level != S.level) throw HeError(HE_EMISMATCH);
+    const u64 g = galois(r);
+    if (g == 1) throw HeError(HE_EUNSUPPORTED);
+    const u64* key = rot_key(g, false);
+    auto lift = g_lift(a, 1);
+    g_ks_inner(*S.u, lift->p, a.B, a.level, key, g, a.p, a.cs, nullptr, nullptr, 1, nullptr, S.n > 0);
+    for (int i = 0; i < a.B; ++i) S.scale[i] = std::max(S.scale[i], a.scale[i]);
+    ++S.n;
+    cnt[C_ROT] += a.B;
+}
+
+Grp Ctx::g_rotsum_finish(RotSum& S, const Grp* base) {
+    if (!S.u) throw HeError(HE_EUNSUPPORTED);
+    if (base && (base->B != S.B || base->level != S.level || base->deg != 1)) throw HeError(HE_EMISMATCH);
+    std::vector<double> sc(S.scale);
+    if (base)
+        for (int i = 0; i < S.B; ++i) sc[i] = std::max(sc[i], base->scale[i]);
+    Grp out = g_new(S.B, S.level, 1, sc);
+    g_moddown(*S.u, S.B, S.level, base ? base->p : nullptr, base ? base->p + base->ps : nullptr, base ? base->cs : 0,
+              out.p, out.p + out.ps, out.cs, 1, nullptr, nullptr, nullptr, 0);
+    cnt[C_ADD] += (int64_t)S.B * (S.n - 1 + (base ? 1 : 0));
+    S = RotSum();
     return out;
 }
 
@@ -422,7 +461,9 @@ static int floordiv_g(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b
 bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
     const int h = J.h, b = bsgs(h);
     const double ms = scale;
+    const bool hoist = (schedule & HE_SCHED_HOIST_MODDOWN) != 0;
     if (J.phase == 0) {
+        RotSum gsum;  // giant steps sharing one ModDown (ModDown hoisting)
         Grp a = g_gather(J.A, J.lvl), bb = g_gather(J.B, J.lvl);
         // Step 1-1: A0 = sum_i Rot(sum_j R(u_{bi+j}, -bi) . Rot(A, j), b i), then RS
         {
@@ -443,6 +484,10 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
                 }
                 if (terms.empty()) continue;
                 Grp inner = g_mask_sum(terms, ms);
+                if (i && hoist) {
+                    g_rotsum_add(gsum, inner, (int64_t)b * i);
+                    continue;
+                }
                 if (i) inner = g_rotate(inner, (int64_t)b * i);
                 if (!have) {
                     acc = inner;
@@ -450,6 +495,10 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
                 } else {
                     g_add_into(acc, inner);
                 }
+            }
+            if (gsum.u) {
+                acc = g_rotsum_finish(gsum, have ? &acc : nullptr);
+                have = true;
             }
             J.A0 = g_rescale(acc);
         }
@@ -468,6 +517,10 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
                 for (int j = 0; j < b && b * i + j < h; ++j)
                     terms.push_back({&baby[j], mask(1, h, b * i + j, -(int64_t)h * b * i)});
                 Grp inner = g_mask_sum(terms, ms);
+                if (i && hoist) {
+                    g_rotsum_add(gsum, inner, (int64_t)h * b * i);
+                    continue;
+                }
                 if (i) inner = g_rotate(inner, (int64_t)h * b * i);
                 if (!have) {
                     acc = inner;
@@ -475,6 +528,10 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
                 } else {
                     g_add_into(acc, inner);
                 }
+            }
+            if (gsum.u) {
+                acc = g_rotsum_finish(gsum, have ? &acc : nullptr);
+                have = true;
             }
             J.B0 = g_rescale(acc);
             // brought to the Step-3 level before its rotations (with late rescaling Step 3
@@ -502,7 +559,7 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
             Grp Ak;
             if (k == 0) {
                 Ak = g_mask_sum({{&J.A0, mask(2, h, 0, 0)}}, ms);
-            } else if (schedule & HE_SCHED_HOIST_MODDOWN) {
+            } else if (hoist) {
                 Ak = g_rotate_pair_hoisted(J.A0, J.liftA->p, k - shift, mask(2, h, k, -shift), k - h - shift,
                                            mask(3, h, k, -shift), ms);
             } else {
@@ -541,6 +598,10 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
                 J.S = Grp();
                 J.haveS = false;
                 if (schedule & HE_SCHED_RELIN_ONCE) blk = g_relin(blk);
+                if (i > 0 && hoist) {
+                    g_rotsum_add(J.giant, blk, shift);
+                    continue;
+                }
                 if (i > 0) blk = g_rotate(blk, shift);
                 if (!J.have) {
                     J.acc = blk;
@@ -561,6 +622,7 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
         }
         return false;
     }
+    if (J.giant.u) J.acc = g_rotsum_finish(J.giant, J.have ? &J.acc : nullptr);
     J.acc = g_rescale(J.acc);
     if (schedule & HE_SCHED_RESCALE_LATE) J.acc = g_rescale(J.acc);
     J.result = g_scatter(J.acc);

@@ -1221,10 +1221,9 @@ he_status he_sign_approx_batch(he_ctx* ctx, size_t n, const he_ct* const* x, uin
         for (size_t i = 0; i < n; ++i) out[i] = wrap(ctx->c.get(), res[i]);
     });
 }
-he_status he_profile_enable(he_ctx* ctx, int on) {
+he_status he_profile_enable(he_ctx* ctx, int on, const char* only) {
     if (!ctx) return HE_EINVAL;
-    prof_enable(on != 0);
-    return HE_OK;
+    return prof_enable(on != 0, only) ? HE_OK : HE_EINVAL;
 }
 he_status he_profile_report(he_ctx* ctx, char* buf, size_t n) {
     if (!ctx || !buf || n == 0) return HE_EINVAL;

@@ -68,6 +68,14 @@ struct Grp {
     int64_t ps = 0, cs = 0;  // poly and ciphertext strides (elements)
 };
 
+// a sum of rotations of different ciphertexts being accumulated in the extended basis
+// before its single ModDown (key-switch inner products + P sigma_g(c0) per term)
+struct RotSum {
+    std::shared_ptr<DBuf> u;
+    int B = 0, level = -1, n = 0;
+    std::vector<double> scale;
+};
+
 // resumable state of one lockstep product group
 struct MatmulJob {
     std::vector<const CtData*> A, B;
@@ -75,6 +83,7 @@ struct MatmulJob {
     Grp A0, B0, acc, S;   // S: the current Step-3 block sum
     bool have = false, haveS = false;
     std::vector<Grp> babyB;  // Rot(B0, h j), j < bg, kept across blocks (Step-3 split)
+    RotSum giant;            // Step-3 giant-step rotations sharing one ModDown (ModDown hoisting)
     std::shared_ptr<DBuf> liftA, liftB;
     std::vector<CtPtr> result;
 };
@@ -179,8 +188,10 @@ struct Ctx {
     Grp g_drop(const Grp& a, int level);
     void g_add_into(Grp& acc, const Grp& t);
     std::shared_ptr<DBuf> g_lift(const Grp& a, int poly);
-    std::shared_ptr<DBuf> g_ks_inner(const u64* lift, int B, int level, const u64* key, u64 g, const u64* c0,
-                                     int64_t c0_cs, const u64* mask, const u64* key2, u64 g2, const u64* mask2);
+    void g_ks_inner(DBuf& u, const u64* lift, int B, int level, const u64* key, u64 g, const u64* c0, int64_t c0_cs,
+                    const u64* mask, const u64* key2, u64 g2, const u64* mask2, bool accumulate);
+    void g_rotsum_add(RotSum& S, const Grp& a, int64_t r);
+    Grp g_rotsum_finish(RotSum& S, const Grp* base);
     void g_moddown(DBuf& u, int B, int level, const u64* add0, const u64* add1, int64_t add_cs, u64* out0,
                    u64* out1, int64_t out_cs, u64 add_g, const u64* mask, const u64* acc0, const u64* acc1,
                    int64_t acc_cs);

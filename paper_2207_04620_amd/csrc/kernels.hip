@@ -6,6 +6,7 @@
 // RNS-CKKS internals are not described by the paper and follow the published
 // constructions named at each kernel.
 #include "kernels.hpp"
+#include <cstring>
 
 #include <cstdio>
 #include <string>
@@ -30,6 +31,7 @@ struct ProfRec {
     double bytes, ops;
 };
 static bool g_prof_on = false;
+static int g_prof_only = -1;  // -1: every kind, else the one kind that is timed
 static std::vector<ProfRec> g_prof;
 static std::vector<hipEvent_t> g_ev_free;
 
@@ -50,7 +52,7 @@ struct ProfScope {
     hipStream_t st;
     hipEvent_t a = nullptr;
     ProfScope(int k, double b, hipStream_t s, double o = 0) : kind(k), bytes(b), ops(o), st(s) {
-        if (g_prof_on) {
+        if (g_prof_on && (g_prof_only < 0 || g_prof_only == k)) {
             a = ev_get();
             (void)hipEventRecord(a, st);
         }
@@ -64,7 +66,17 @@ struct ProfScope {
     }
 };
 
-void prof_enable(bool on) { g_prof_on = on; }
+bool prof_enable(bool on, const char* only) {
+    int k = -1;
+    if (only) {
+        for (int i = 0; i < PK_COUNT; ++i)
+            if (!strcmp(only, kProfNames[i])) k = i;
+        if (k < 0) return false;
+    }
+    g_prof_on = on;
+    g_prof_only = k;
+    return true;
+}
 
 std::string prof_report() {
     double ms[PK_COUNT] = {0}, by[PK_COUNT] = {0}, op[PK_COUNT] = {0};
@@ -730,6 +742,10 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
             v1 = add_mod(v1, w1, m.q);
         }
         u64* u = D.u + c * D.u_cs;
+        if (D.accumulate) {
+            v0 = add_mod(v0, u[(int64_t)t * N + i], m.q);
+            v1 = add_mod(v1, u[((int64_t)D.ne + t) * N + i], m.q);
+        }
         u[(int64_t)t * N + i] = v0;
         u[((int64_t)D.ne + t) * N + i] = v1;
     }
@@ -747,7 +763,7 @@ void launch_inner_product(const DevTables& T, const IpDesc& D, hipStream_t st) {
     const int nr = D.nrot == 2 ? 2 : 1;
     // keys (and masks) once per group; per member the lift digits per rotation, c0 and u
     const double words = (double)D.ne * (nr * 2.0 * D.beta + (D.mask ? 1.0 : 0.0) + (D.mask2 ? 1.0 : 0.0) +
-                                         D.nct * (nr * (double)D.beta + 2.0)) +
+                                         D.nct * (nr * (double)D.beta + (D.accumulate ? 4.0 : 2.0))) +
                          (D.c0 ? (double)D.nq * D.nct * nr : 0.0);
     ProfScope prof_(PK_INNER, words * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;

@@ -100,6 +100,7 @@ struct IpDesc {
     const u64* key2;
     const u64* mask;   // [M][N] Montgomery form, row = modulus index; null = no mask
     const u64* mask2;
+    int accumulate;    // u += the result (a sum of rotations of different ciphertexts)
 };
 
 struct MacDesc {
@@ -128,7 +129,7 @@ struct Epi {
     const u64* pinv;
     const u64* pinv_sh;
     u64 g;
-    // optional Mul_pt fused into the epilogue: out = w * mask (Montgomery form, [n_q][N])
+    // optional Mul_pt fused into the epilogue: out = w * mask (Montgomery form, rows = limbs)
     // (+ acc_p[c][t][i] when acc_p is set): one term of a diagonal sum (Eq. 1)
     const u64* mask;
     const u64* acc[2];
@@ -141,7 +142,8 @@ enum ProfKind {
     PK_RS_SPREAD, PK_RS_COMBINE, PK_TENSOR, PK_MASKMAC, PK_AUTOMORPH, PK_EW, PK_COUNT
 };
 #include <string>
-void prof_enable(bool on);
+// only: null for every kernel kind, else one kind's name; false for an unknown name
+bool prof_enable(bool on, const char* only);
 std::string prof_report();  // JSON: per kernel kind {launches, ms, bytes}; clears the records
 
 // ------------------------------------------------------------------ launchers

@@ -73,7 +73,8 @@ static size_t footprint(const Ctx* c, const he_request& r, int level) {
     if (r.op == HE_REQ_MATMUL) {
         // Step-1 baby steps, the Step-3 baby rotations of B0 kept across blocks, temporaries
         const int bg = c->step3_baby((int)r.h);
-        return (size_t)(c->bsgs((int)r.h) + (bg < (int)r.h ? bg : 0) + 10) * ct + 3 * lift;
+        const size_t ext = 2 * (size_t)(level + 1 + c->n_p) * c->N * 8;  // a hoisted rotation sum
+        return (size_t)(c->bsgs((int)r.h) + (bg < (int)r.h ? bg : 0) + 10) * ct + 3 * lift + ext;
     }
     return 12 * ct + 2 * lift;
 }

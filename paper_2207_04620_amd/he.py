@@ -102,7 +102,7 @@ SIGNATURES = {
     "he_serve_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_void_p),
                                 C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "he_serve_stop": (C.c_int, [C.c_void_p]),
-    "he_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "he_profile_enable": (C.c_int, [C.c_void_p, C.c_int, C.c_char_p]),
     "he_profile_report": (C.c_int, [C.c_void_p, C.c_char_p, C.c_size_t]),
     "he_status_string": (C.c_char_p, [C.c_int]),
 }
@@ -221,8 +221,10 @@ class Context:
         _chk(lib().he_memory(self.ptr, C.byref(k), C.byref(p)), "he_memory")
         return k.value, p.value
 
-    def profile(self, on: bool):
-        _chk(lib().he_profile_enable(self.ptr, int(on)), "he_profile_enable")
+    def profile(self, on: bool, only: str | None = None):
+        """time every launch (or only launches of the kernel kind named) with HIP events"""
+        _chk(lib().he_profile_enable(self.ptr, int(on), None if only is None else only.encode()),
+             "he_profile_enable")
 
     def profile_report(self):
         import json
