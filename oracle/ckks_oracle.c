@@ -1274,13 +1274,11 @@ static void gd_numerators(int d, int64_t *num) {
     for (int i = 0; i <= d; i++) num[i] /= 2;
 }
 
-/* round(num * q / 2^e), half away from zero, exactly */
-static int64_t round_frac(int64_t num, u64 q, int e) {
-    i128 v = (i128)num * (i128)q;
-    i128 den = (i128)1 << e;
-    i128 a = v < 0 ? -v : v;
-    i128 r = (2 * a + den) / (2 * den);
-    return (int64_t)(v < 0 ? -r : r);
+/* the integer constant of x_c = RS(x * K) for the coefficient num / 2^e:
+ * K = round(num / 2^e * q_l * ratio), half away from zero, where ratio = (scale x_c must
+ * carry) / (scale of x); computed in double in this exact order */
+static int64_t scaled_const(int64_t num, int e, u64 ql, double ratio) {
+    return llround((double)num / (double)((int64_t)1 << e) * (double)ql * ratio);
 }
 
 static orc_ct *mul_rs(orc_ctx *c, const orc_ct *x, const orc_ct *y) {
@@ -1292,7 +1290,8 @@ static orc_ct *mul_rs(orc_ctx *c, const orc_ct *x, const orc_ct *y) {
     return r;
 }
 
-static orc_ct *eval_gd(orc_ctx *c, const orc_ct *x, int d) {
+/* g_d(x) with every term landing on the scale 'target' */
+static orc_ct *eval_gd(orc_ctx *c, const orc_ct *x, int d, double target) {
     int64_t num[16];
     gd_numerators(d, num);
     int e = 2 * d - 1;
@@ -1303,9 +1302,21 @@ static orc_ct *eval_gd(orc_ctx *c, const orc_ct *x, int d) {
     orc_ct *y = NULL;
     u64 ql = c->mod[x->level];
     for (int i = 0; i <= d; i++) {
-        orc_ct *t = orc_mul_int(c, x, round_frac(num[i], ql, e));
+        /* scale matching: the finished term c_i x^(2i+1) must land exactly on the scale of
+         * x, so x_c has to carry the scale 'need' that the products with the powers and
+         * their rescales then bring back to it; the ratio need / scale(x) is folded into
+         * the integer constant.  All terms of the sum then share one scale. */
+        double need = target;
+        int lv = x->level - 1;
+        for (int b = 0; b < nb; b++)
+            if ((i >> b) & 1) {
+                int l = lv < pw[b]->level ? lv : pw[b]->level;
+                need = need * (double)c->mod[l] / pw[b]->scale;
+                lv = l - 1;
+            }
+        orc_ct *t = orc_mul_int(c, x, scaled_const(num[i], e, ql, need / x->scale));
         orc_ct *term = orc_rescale(c, t);
-        term->scale = x->scale; /* the constant was carried at scale q_l, removed exactly by RS */
+        term->scale = need; /* value c_i x carried at scale need (K q_l^-1 rides with it) */
         orc_ct_free(t);
         for (int b = 0; b < nb; b++)
             if ((i >> b) & 1) { orc_ct *u = mul_rs(c, term, pw[b]); orc_ct_free(term); term = u; }
@@ -1321,7 +1332,16 @@ orc_ct *orc_sign(orc_ctx *c, const orc_ct *x, int d, int k, int relu) {
     while ((1 << nb) <= d) nb++;
     if (x->level < k * (nb + 1) + (relu ? 1 : 0)) return NULL;
     orc_ct *cur = ct_copy(c, x);
-    for (int it = 0; it < k; it++) { orc_ct *t = eval_gd(c, cur, d); orc_ct_free(cur); cur = t; }
+    for (int it = 0; it < k; it++) {
+        /* each composition returns its input's scale; for ReLU the last one lands on the
+         * prime q_l that the product x g rescales by, so that x g comes out exactly at the
+         * scale of x and the sum x + x g adds equal scales */
+        double target = cur->scale;
+        if (relu && it == k - 1) target = (double)c->mod[cur->level - (nb + 1)];
+        orc_ct *t = eval_gd(c, cur, d, target);
+        orc_ct_free(cur);
+        cur = t;
+    }
     if (!relu) return cur;
     orc_ct *r = mul_rs(c, x, cur);
     orc_ct *xd = orc_drop(c, x, r->level);

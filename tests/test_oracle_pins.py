@@ -639,6 +639,12 @@ def test_sign_decrypts_to_composite_polynomial(d, k):
     nb = int(math.floor(math.log2(d))) + 1
     assert y.level == x.level - k * (nb + 1)
     assert np.abs(c.decrypt(y, 256) - want).max() < 1e-3
+    # scale matching: every term of the sum lands on the input's scale, so the
+    # compositions do not drift (output scale = input scale to double rounding) and the
+    # error stays at the encryption/rescale noise level (2^-40 here) times the Lipschitz
+    # growth of g_d^(k), far below the stated bound
+    assert abs(y.scale / x.scale - 1) < 1e-12
+    assert np.abs(c.decrypt(y, 256) - want).max() < 1e-6
 
 
 def test_relu_decrypts(small):
@@ -647,6 +653,10 @@ def test_relu_decrypts(small):
     y = c.sign(c.encrypt(X, nonce=41), 3, 1, relu=True)
     g = gd_eval(3, X)
     assert np.abs(c.decrypt(y, 256) - (X + X * g) / 2).max() < 1e-3
+    # the last composition lands on the prime the product x g rescales by, so x + x g adds
+    # equal scales and the ReLU output carries exactly twice the input's scale
+    assert abs(y.scale / (2 * c.encrypt(X, nonce=41).scale) - 1) < 1e-12
+    assert np.abs(c.decrypt(y, 256) - (X + X * g) / 2).max() < 1e-6
 
 
 def test_sign_rejects_shallow_level(small):
