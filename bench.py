@@ -98,6 +98,64 @@ def cpu_baseline(prm, flags):
                       f"the op-count ratio {work64}/{work16:.0f}"}
 
 
+def mixed_leg(he, I, prm, sched, stream, count):
+    """The mixed-batch configuration: count products with h uniform over {16, 32, 64} and
+    starting levels uniform over [3, 13] (inputs.batch_mix, seed 3) in one batched call.
+    Four encrypted pairs per h are shared by the members (level drops of them)."""
+    ctx = he.Context(prm, h_list=[16, 32, 64], stream=stream.cuda_stream, schedule=sched)
+    mix = I.batch_mix(3, count)
+    base = {h: [(ctx.encrypt(A.ravel(), nonce=10 * h + 2 * i), ctx.encrypt(B.ravel(), nonce=10 * h + 2 * i + 1))
+                for i, (A, B) in enumerate(I.matrix_pair(700 + h + i, h) for i in range(4))] for h in (16, 32, 64)}
+    As, Bs = [], []
+    for i, (h, lv) in enumerate(mix):
+        a, b = base[h][i % 4]
+        As.append(ctx.drop(a, lv))
+        Bs.append(ctx.drop(b, lv))
+    hs = [h for h, _ in mix]
+    ctx.matmul_batch(As, Bs, hs)
+    ctx.sync()
+    t0 = time.perf_counter()
+    ctx.matmul_batch(As, Bs, hs)
+    ctx.sync()
+    dt = time.perf_counter() - t0
+    ctx.close()
+    counts = {h: hs.count(h) for h in (16, 32, 64)}
+    return {"products": count, "h_counts": counts, "levels": "uniform over [3, 13]",
+            "matmuls_per_s": round(count / dt, 3), "ms": round(dt * 1e3, 1)}
+
+
+def c4_leg(he, I, sched, stream, count):
+    """The sign/ReLU configuration on the N=2^16 ring: count ciphertexts of 32 x 32 inputs
+    (|x| in [2^-8, 1], random sign), ReLU by g_3^(3) in one batched call, then one h=32
+    product of each result with an encrypted W in a second batched call.  Eight distinct
+    encrypted inputs are shared by the members."""
+    prm = I.C4
+    ctx = he.Context(prm, h_list=[32], stream=stream.cuda_stream, schedule=sched)
+    X = I.sign_inputs(4, 8, 32)
+    xs = [ctx.encrypt(X[i % 8].ravel(), nonce=i + 1) for i in range(8)]
+    xs = [xs[i % 8] for i in range(count)]
+    W = np.random.default_rng(4).uniform(-1.0, 1.0, (32, 32))
+    ys = ctx.sign_approx_batch(xs[:8], 3, 3, he.RELU)  # warm-up
+    lvl = ys[0].info()[0]
+    w = ctx.encrypt(W.ravel(), level=lvl, nonce=1000)
+    ctx.matmul_batch(ys, [w] * 8, [32] * 8)
+    ctx.sync()
+    t0 = time.perf_counter()
+    ys = ctx.sign_approx_batch(xs, 3, 3, he.RELU)
+    ctx.sync()
+    t1 = time.perf_counter()
+    ms = ctx.matmul_batch(ys, [w] * count, [32] * count)
+    ctx.sync()
+    t2 = time.perf_counter()
+    g3 = lambda v: (35 * v - 35 * v ** 3 + 21 * v ** 5 - 5 * v ** 7) / 16  # noqa: E731
+    relu = (X[0] + X[0] * g3(g3(g3(X[0])))) / 2
+    err = float(np.abs(ctx.decrypt(ms[0], 1024).reshape(32, 32) - relu @ W).max())
+    ctx.close()
+    return {"ciphertexts": count, "relu_per_s": round(count / (t1 - t0), 2),
+            "h32_matmuls_per_s": round(count / (t2 - t1), 2),
+            "end_to_end_per_s": round(count / (t2 - t0), 2), "max_abs_error": err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +169,8 @@ def main():
     ap.add_argument("--plain-iters", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-other", action="store_true", help="skip timing the other schedules")
+    ap.add_argument("--mix", type=int, default=256, help="mixed-batch products (0: skip)")
+    ap.add_argument("--c4", type=int, default=128, help="ciphertexts of the N=2^16 ReLU + h=32 leg (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / batched capacity")
     ap.add_argument("--serve-min-batch", type=int, default=8)
@@ -292,6 +352,14 @@ def main():
         "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
                         **({"GB/s": hbm[k]} if k in hbm else {})} for k, v in prof.items()},
     }
+    if args.mix > 0:
+        log(f"mixed batch of {args.mix} (h in 16/32/64, levels 3..13)")
+        result["mixed_batch"] = mixed_leg(he, I, prm, sched, stream, args.mix)
+        log(f"mixed batch: {result['mixed_batch']}")
+    if args.c4 > 0:
+        log(f"N=2^16 ReLU + h=32 leg ({args.c4} ciphertexts)")
+        result["c4_relu_then_matmul"] = c4_leg(he, I, sched, stream, args.c4)
+        log(f"c4: {result['c4_relu_then_matmul']}")
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(prm, sched)

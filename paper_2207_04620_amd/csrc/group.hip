@@ -661,29 +661,36 @@ static std::vector<int64_t> gd_numerators(int d) {
     return num;
 }
 
-// round(num q / 2^e), half away from zero
-static int64_t round_num_q(int64_t num, u64 q, int e) {
-    const __int128 v = (__int128)num * q, den = (__int128)1 << e;
-    const __int128 a = v < 0 ? -v : v;
-    const __int128 r = (2 * a + den) / (2 * den);
-    return (int64_t)(v < 0 ? -r : r);
+// the integer constant of x_c = RS(x K) for the coefficient num / 2^e:
+// K = round(num / 2^e * q_l * ratio), half away from zero, ratio = (scale x_c must carry) /
+// (scale of x); double arithmetic in this exact order
+static int64_t scaled_const(int64_t num, int e, u64 ql, double ratio) {
+    return std::llround((double)num / (double)((int64_t)1 << e) * (double)ql * ratio);
 }
 
-Grp Ctx::g_mul_int(const Grp& a, int64_t k) {
+// every member times its own integer constant k[m] (members with equal constants share a
+// launch)
+Grp Ctx::g_mul_int(const Grp& a, const std::vector<int64_t>& k) {
     const int nl = a.level + 1;
-    std::vector<u64> c(2 * nl);
-    for (int i = 0; i < nl; ++i) {
-        const u64 q = mods[i];
-        const u64 r = k >= 0 ? (u64)k % q : (q - (u64)(-(k + 1)) % q - 1) % q;
-        c[i] = r;
-        c[nl + i] = hm::shoup(r, q);
-    }
-    DBuf dc(this, 2 * (size_t)nl);
-    hip_check(hipMemcpyAsync(dc.p, c.data(), c.size() * 8, hipMemcpyHostToDevice, stream), "mul_int consts");
-    hip_check(hipStreamSynchronize(stream), "mul_int consts");
     Grp r = g_new(a.B, a.level, a.deg, a.scale);
-    // the group is (B * (deg+1)) polynomials with a uniform poly stride
-    launch_mul_const(T, ModMap{1 << 20, n_q}, nl, a.B * (a.deg + 1), r.p, r.ps, a.p, a.ps, dc.p, dc.p + nl, stream);
+    std::vector<u64> c(2 * nl);
+    for (int m0 = 0; m0 < a.B;) {
+        int m1 = m0 + 1;
+        while (m1 < a.B && k[m1] == k[m0]) ++m1;
+        for (int i = 0; i < nl; ++i) {
+            const u64 q = mods[i];
+            const u64 v = k[m0] >= 0 ? (u64)k[m0] % q : (q - (u64)(-(k[m0] + 1)) % q - 1) % q;
+            c[i] = v;
+            c[nl + i] = hm::shoup(v, q);
+        }
+        DBuf dc(this, 2 * (size_t)nl);
+        hip_check(hipMemcpyAsync(dc.p, c.data(), c.size() * 8, hipMemcpyHostToDevice, stream), "mul_int consts");
+        hip_check(hipStreamSynchronize(stream), "mul_int consts");
+        // members m0..m1-1 are (m1 - m0) * (deg+1) polynomials with a uniform poly stride
+        launch_mul_const(T, ModMap{1 << 20, n_q}, nl, (m1 - m0) * (a.deg + 1), r.p + (size_t)m0 * r.cs, r.ps,
+                         a.p + (size_t)m0 * a.cs, a.ps, dc.p, dc.p + nl, stream);
+        m0 = m1;
+    }
     return r;
 }
 
@@ -696,7 +703,7 @@ Grp Ctx::g_mul_rs(const Grp& x, const Grp& y) {
 
 // g_d(x) = sum_i c_{2i+1} x^(2i+1): x_c = RS(x * round(c q_l)) lands at the scale of x;
 // x^(2i) comes from the powers x^2, x^4, ... multiplied in along the set bits of i.
-Grp Ctx::g_eval_gd(const Grp& x, int d) {
+Grp Ctx::g_eval_gd(const Grp& x, int d, const std::vector<double>& target) {
     const auto num = gd_numerators(d);
     const int e = 2 * d - 1;
     int nb = 0;
@@ -707,8 +714,25 @@ Grp Ctx::g_eval_gd(const Grp& x, int d) {
     Grp y;
     bool have = false;
     for (int i = 0; i <= d; ++i) {
-        Grp term = g_rescale(g_mul_int(x, round_num_q(num[i], ql, e)));
-        term.scale = x.scale;  // the constant rides at scale q_l, removed exactly by RS
+        // scale matching: x_c carries the scale 'need' that the products with the powers
+        // and their rescales bring back exactly to the scale of x, so every term of the sum
+        // lands on one scale; need / scale(x) is folded into the integer constant
+        std::vector<double> need(x.B);
+        std::vector<int64_t> K(x.B);
+        for (int m = 0; m < x.B; ++m) {
+            double nd = target[m];
+            int lv = x.level - 1;
+            for (int b = 0; b < nb; ++b)
+                if ((i >> b) & 1) {
+                    const int l = std::min(lv, pw[b].level);
+                    nd = nd * (double)mods[l] / pw[b].scale[m];
+                    lv = l - 1;
+                }
+            need[m] = nd;
+            K[m] = scaled_const(num[i], e, ql, nd / x.scale[m]);
+        }
+        Grp term = g_rescale(g_mul_int(x, K));
+        term.scale = need;  // value c_i x carried at scale need
         for (int b = 0; b < nb; ++b)
             if ((i >> b) & 1) term = g_mul_rs(term, pw[b]);
         if (!have) {
@@ -732,7 +756,16 @@ bool Ctx::sign_step(SignJob& J) {
         J.started = true;
     }
     if (J.it < J.k) {
-        J.cur = g_eval_gd(J.cur, J.d);
+        // each composition returns its input's scale; for ReLU the last one lands on the
+        // prime q_l that the product x g rescales by, so x g comes out exactly at the scale
+        // of x and x + x g adds equal scales
+        std::vector<double> target(J.cur.scale);
+        if (J.mode && J.it == J.k - 1) {
+            int nb = 0;
+            while ((1 << nb) <= J.d) ++nb;
+            for (auto& t : target) t = (double)mods[J.cur.level - (nb + 1)];
+        }
+        J.cur = g_eval_gd(J.cur, J.d, target);
         ++J.it;
         if (J.it < J.k || J.mode) return false;
     }

@@ -212,9 +212,9 @@ struct Ctx {
     std::vector<CtPtr> matmul_group(const std::vector<const CtData*>& A, const std::vector<const CtData*>& B, int h,
                                     int lvl);
     bool matmul_step(MatmulJob& J, int k_chunk);
-    Grp g_mul_int(const Grp& a, int64_t k);
+    Grp g_mul_int(const Grp& a, const std::vector<int64_t>& k);
     Grp g_mul_rs(const Grp& x, const Grp& y);
-    Grp g_eval_gd(const Grp& x, int d);
+    Grp g_eval_gd(const Grp& x, int d, const std::vector<double>& target);
     bool sign_step(SignJob& J);
     std::vector<CtPtr> sign_group(const std::vector<const CtData*>& X, int d, int k, int mode);
 

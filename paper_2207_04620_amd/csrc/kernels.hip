@@ -418,18 +418,20 @@ void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st)
 // Centered fast base conversion (Bajard et al. 2016 / Halevi-Polyakov-Shoup 2019 in
 // its centered form): y_s = centered([x_s (D/q_s)^-1]_{q_s}),
 // out_t = sum_s y_s (D/q_s) mod q_t, accumulated in 128 bits and reduced once (REDC).
+#define BC_TG 32  // targets per block of the base conversion
 template <int NS>
 __global__ __launch_bounds__(TPB) void k_baseconv(DevTables T, ConvDesc D) {
-    // the block's slice of the constant table (NS sources x up to 8 targets) goes to LDS once
-    __shared__ u64 tab[NS * 8 * 2];
-    __shared__ ModP tm[8];
+    // the block's slice of the constant table (NS sources x up to BC_TG targets) goes to LDS
+    // once; the sources are read and prepared once for all the targets of the slice
+    __shared__ u64 tab[NS * BC_TG * 2];
+    __shared__ ModP tm[BC_TG];
     const int N = 1 << T.log_n;
     const int i = blockIdx.x * TPB + threadIdx.x;
     const int p = blockIdx.z % D.npoly, c = blockIdx.z / D.npoly;
-    const int t0 = blockIdx.y * 8, nt = min(D.nt - t0, 8);
+    const int t0 = blockIdx.y * BC_TG, nt = min(D.nt - t0, BC_TG);
     for (int e = threadIdx.x; e < NS * nt * 2; e += TPB) {
         const int sI = e / (nt * 2), rem = e % (nt * 2), tt = rem >> 1, w = rem & 1;
-        tab[(sI * 8 + tt) * 2 + w] = D.tab[((int64_t)sI * D.tab_ld + D.tcol[t0 + tt]) * 2 + w];
+        tab[(sI * BC_TG + tt) * 2 + w] = D.tab[((int64_t)sI * D.tab_ld + D.tcol[t0 + tt]) * 2 + w];
     }
     if (threadIdx.x < nt) tm[threadIdx.x] = T.mods[D.dmod[t0 + threadIdx.x]];
     __syncthreads();
@@ -450,8 +452,8 @@ __global__ __launch_bounds__(TPB) void k_baseconv(DevTables T, ConvDesc D) {
         Acc128 acc = {0, 0};
 #pragma unroll
         for (int s = 0; s < NS; s++) {
-            mac128(acc, y[s], tab[(s * 8 + tt) * 2]);
-            add128(acc, tab[(s * 8 + tt) * 2 + 1] & negm[s]);
+            mac128(acc, y[s], tab[(s * BC_TG + tt) * 2]);
+            add128(acc, tab[(s * BC_TG + tt) * 2 + 1] & negm[s]);
         }
         dst[(int64_t)D.doff[t0 + tt] * N + i] = redc(acc.lo, acc.hi, m.q, m.qninv);
     }
@@ -460,7 +462,7 @@ __global__ __launch_bounds__(TPB) void k_baseconv(DevTables T, ConvDesc D) {
 void launch_baseconv(const DevTables& T, const ConvDesc& D, hipStream_t st) {
     ProfScope prof_(PK_BASECONV, (double)(D.ns + D.nt) * D.npoly * D.nct * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
-    dim3 grid(ceil_div(N, TPB), ceil_div(D.nt, 8), D.npoly * D.nct);
+    dim3 grid(ceil_div(N, TPB), ceil_div(D.nt, BC_TG), D.npoly * D.nct);
     switch (D.ns) {
         case 1: hipLaunchKernelGGL(k_baseconv<1>, grid, dim3(TPB), 0, st, T, D); break;
         case 2: hipLaunchKernelGGL(k_baseconv<2>, grid, dim3(TPB), 0, st, T, D); break;
@@ -681,20 +683,19 @@ void launch_swk_finish(const DevTables& T, int M, u64* b, const u64* a, const u6
 // gather: the digits of sigma_g(c1) are the permuted digits of c1 (hoisting).
 // The key values of one (limb, coefficient) are loaded once and reused for every
 // ciphertext of the group: a switching key crosses HBM once per launch.
-// one rotation's key-switch inner product of one member, reduced: sum_j lift_j(sigma_g) key_j
-// (+ P sigma_g(c0) on the Q limbs), optionally times a Montgomery-form mask
+// one rotation's key-switch inner product of one member, reduced: sum_j x_j key_j (+ P
+// sigma_g(c0) on the Q limbs), optionally times a Montgomery-form mask; x are the member's
+// lift words at the automorphism source position
 template <int NB>
-__device__ __forceinline__ void ip_member(const IpDesc& D, const u64* lift, const u64* c0, int N, int t, int src,
-                                          const u64* kb, const u64* ka, bool with_c0, const ModP& m, u64 mk,
-                                          bool masked, u64& v0, u64& v1) {
+__device__ __forceinline__ void ip_reduce(const u64* x, u64 z, const u64* kb, const u64* ka, u64 pmont, bool with_c0,
+                                          const ModP& m, u64 mk, bool masked, u64& v0, u64& v1) {
     Acc128 a0 = {0, 0}, a1 = {0, 0};
 #pragma unroll
     for (int j = 0; j < NB; j++) {
-        const u64 x = lift[((int64_t)j * D.ne + t) * N + src];
-        mac128(a0, x, kb[j]);
-        mac128(a1, x, ka[j]);
+        mac128(a0, x[j], kb[j]);
+        mac128(a1, x[j], ka[j]);
     }
-    if (with_c0) mac128(a0, c0[(int64_t)t * N + src], D.pmont[t]);
+    if (with_c0) mac128(a0, z, pmont);
     v0 = redc(a0.lo, a0.hi, m.q, m.qninv);
     v1 = redc(a1.lo, a1.hi, m.q, m.qninv);
     if (masked) {
@@ -705,7 +706,9 @@ __device__ __forceinline__ void ip_member(const IpDesc& D, const u64* lift, cons
 
 // Grid (N / TPB, ne): one thread per (slot, extended limb) for every member, so each key
 // word (and mask word) is read once per group.  The digit count NB is a template
-// parameter so that the key words stay in registers.
+// parameter so that the key words stay in registers; the member loop is software-
+// pipelined (the next member's lift and c0 words are loaded before the current member's
+// arithmetic) to keep more loads in flight.
 template <int NB, int NR>
 __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
     const int N = 1 << T.log_n;
@@ -729,14 +732,26 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
         mk[r] = mask ? mask[(int64_t)mi * N + i] : 0;
     }
     const bool with_c0 = D.c0 && t < D.nq;
+    const u64 pmont = with_c0 ? D.pmont[t] : 0;
+    u64 x[NR][NB], z[NR];
+    auto load = [&](int c, u64(&xo)[NR][NB], u64(&zo)[NR]) {
+        const u64* lift = D.lift + c * D.lift_cs + (int64_t)t * N;
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+#pragma unroll
+            for (int j = 0; j < NB; j++) xo[r][j] = lift[(int64_t)j * D.ne * N + src[r]];
+            zo[r] = with_c0 ? D.c0[c * D.c0_cs + (int64_t)t * N + src[r]] : 0;
+        }
+    };
+    load(0, x, z);
     for (int c = 0; c < D.nct; c++) {
-        const u64* lift = D.lift + c * D.lift_cs;
-        const u64* c0 = D.c0 ? D.c0 + c * D.c0_cs : nullptr;
+        u64 xn[NR][NB], zn[NR];
+        if (c + 1 < D.nct) load(c + 1, xn, zn);
         u64 v0, v1;
-        ip_member<NB>(D, lift, c0, N, t, src[0], kb[0], ka[0], with_c0, m, mk[0], D.mask != nullptr, v0, v1);
+        ip_reduce<NB>(x[0], z[0], kb[0], ka[0], pmont, with_c0, m, mk[0], D.mask != nullptr, v0, v1);
         if (NR == 2) {
             u64 w0, w1;
-            ip_member<NB>(D, lift, c0, N, t, src[NR - 1], kb[NR - 1], ka[NR - 1], with_c0, m, mk[NR - 1],
+            ip_reduce<NB>(x[NR - 1], z[NR - 1], kb[NR - 1], ka[NR - 1], pmont, with_c0, m, mk[NR - 1],
                           D.mask2 != nullptr, w0, w1);
             v0 = add_mod(v0, w0, m.q);
             v1 = add_mod(v1, w1, m.q);
@@ -748,6 +763,12 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
         }
         u[(int64_t)t * N + i] = v0;
         u[((int64_t)D.ne + t) * N + i] = v1;
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            z[r] = zn[r];
+#pragma unroll
+            for (int j = 0; j < NB; j++) x[r][j] = xn[r][j];
+        }
     }
 }
 

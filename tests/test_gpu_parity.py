@@ -350,3 +350,74 @@ def test_c3_h64_batch16_fast_schedule_full_size(he):
     assert bad.size == 0, f"{len(bad)} residues differ, first at {bad[:3].tolist()}"
     _log("[parity] C3 h=64: bit-exact")
     g.close()
+
+
+def test_c3_mixed_batch_parity(he):
+    """a batch of products of mixed h in {16, 32, 64} and starting levels in [3, 13] on the
+    N=2^15 ring (the mixed-batch configuration, 24 of its members): one batched call; every
+    member within the FP64 bound at its own output level, equal to the same product run
+    alone, and the first h=16 and h=32 members equal to the oracle on every residue"""
+    prm = I.C3
+    g = he.Context(prm, h_list=[16, 32, 64], schedule=15)
+    mix = I.batch_mix(3, 24)
+    _log(f"[parity] C3 mixed batch: {mix}")
+    pairs = [I.matrix_pair(500 + i, h) for i, (h, _) in enumerate(mix)]
+    As = [g.encrypt(A.ravel(), level=lv, nonce=2 * i) for i, ((A, _), (_, lv)) in enumerate(zip(pairs, mix))]
+    Bs = [g.encrypt(B.ravel(), level=lv, nonce=2 * i + 1) for i, ((_, B), (_, lv)) in enumerate(zip(pairs, mix))]
+    out = g.matmul_batch(As, Bs, [h for h, _ in mix])
+    for i, ((A, B), (h, lv)) in enumerate(zip(pairs, mix)):
+        assert out[i].info()[0] == lv - 3
+        err = np.abs(g.decrypt(out[i], h * h).reshape(h, h) - A @ B).max()
+        assert err < 1e-5, (i, h, lv, err)
+    _log("[parity] C3 mixed batch: singles")
+    for i in range(8):
+        h = mix[i][0]
+        assert np.array_equal(g.export(g.matmul(As[i], Bs[i], h)), g.export(out[i])), i
+    o = O.Ctx.from_params(prm)
+    for want_h in (16, 32):
+        i = next(j for j, (h, _) in enumerate(mix) if h == want_h)
+        h, lv = mix[i]
+        _log(f"[parity] C3 mixed batch: oracle member {i} (h={h}, level {lv})")
+        A, B = pairs[i]
+        om = o.matmul(o.encrypt(A.ravel(), level=lv, nonce=2 * i), o.encrypt(B.ravel(), level=lv, nonce=2 * i + 1),
+                      h, 15)
+        gexp, oexp = g.export(out[i]), om.export()
+        assert gexp.shape == oexp.shape and np.array_equal(gexp, oexp), i
+    g.close()
+
+
+def test_c4_sign_relu_then_h32_matmul(he):
+    """the sign/ReLU configuration on the N=2^16 ring (Q = 60 + 16 x 45, P = 5 x 60, dnum 3):
+    a batch of ReLU(x) = (x + x g_3^(3)(x)) / 2 over 32 x 32 inputs with |x| in [2^-8, 1],
+    then an h=32 product of each result with one encrypted W.  Member 0 against the oracle on
+    every residue (both stages); every member within 1e-3 of the FP64 evaluation"""
+    prm = I.C4
+    count = 16
+    g = he.Context(prm, h_list=[32], schedule=15)
+    X = I.sign_inputs(4, count, 32)
+    W = np.random.default_rng(4).uniform(-1.0, 1.0, (32, 32))
+    xs = [g.encrypt(X[i].ravel(), nonce=i + 1) for i in range(count)]
+    _log("[parity] C4 ReLU batch")
+    ys = g.sign_approx_batch(xs, 3, 3, he.RELU)
+    lvl = ys[0].info()[0]
+    w = g.encrypt(W.ravel(), level=lvl, nonce=1000)
+    _log(f"[parity] C4 h=32 products at level {lvl}")
+    ms = g.matmul_batch(ys, [w] * count, [32] * count)
+
+    def g3(v):
+        return (35 * v - 35 * v ** 3 + 21 * v ** 5 - 5 * v ** 7) / 16
+
+    for i in range(count):
+        x = X[i]
+        s = g3(g3(g3(x)))
+        relu = (x + x * s) / 2
+        assert np.abs(g.decrypt(ys[i], 1024).reshape(32, 32) - relu).max() < 1e-3, i
+        assert np.abs(g.decrypt(ms[i], 1024).reshape(32, 32) - relu @ W).max() < 1e-3, i
+    _log("[parity] C4 oracle, member 0")
+    o = O.Ctx.from_params(prm)
+    oy = o.sign(o.encrypt(X[0].ravel(), nonce=1), 3, 3, relu=True)
+    assert np.array_equal(g.export(ys[0]), oy.export())
+    om = o.matmul(oy, o.encrypt(W.ravel(), level=lvl, nonce=1000), 32, 15)
+    assert np.array_equal(g.export(ms[0]), om.export())
+    _log("[parity] C4: bit-exact")
+    g.close()
