@@ -156,6 +156,102 @@ def c4_leg(he, I, sched, stream, count):
             "end_to_end_per_s": round(count / (t2 - t0), 2), "max_abs_error": err}
 
 
+def serve_rings_leg(he, I, sched, nreq, load):
+    """The serving configuration across rings: one server per context (N = 2^14, 2^15,
+    2^16), mixed requests (55% products with h uniform over {8, 16, 32, 64, 128}, 35% sign or
+    ReLU with d = 3 and k uniform over 1..4, 10% the N=2^16 ReLU k = 3) routed to the smallest
+    ring that holds them.  Capacity is measured with a burst of nreq requests; latency with
+    Poisson arrivals (seed 5) at load x capacity, from scheduled arrival to result."""
+    rings = [he.Context(I.C2, h_list=[8, 16, 32, 64], schedule=sched),
+             he.Context(I.C3, h_list=[128], schedule=sched),
+             he.Context(I.C4, h_list=[], schedule=sched)]
+    rng = np.random.default_rng(5)
+    kinds = []
+    for _ in range(nreq):
+        u = rng.random()
+        if u < 0.55:
+            kinds.append(("mm", int(rng.choice([8, 16, 32, 64, 128]))))
+        elif u < 0.90:
+            kinds.append(("sign", 3, int(rng.integers(1, 5)), int(rng.integers(0, 2))))
+        else:
+            kinds.append(("c4relu", 3, 3, he.RELU))
+    inputs = {}
+
+    def operands(w):
+        if w[0] == "mm":
+            ctx = he.smallest_ring(rings, h=w[1], depth=3)
+        elif w[0] == "sign":
+            ctx = he.smallest_ring(rings, h=32, depth=he.sign_depth(w[1], w[2], w[3]))
+        else:
+            ctx = rings[2]
+        key = (id(ctx), w[0], w[1] if w[0] == "mm" else 32)
+        if key not in inputs:
+            h = w[1] if w[0] == "mm" else 32
+            if w[0] == "mm":
+                A, B = I.matrix_pair(900 + h, h)
+                inputs[key] = (ctx.encrypt(A.ravel(), nonce=1), ctx.encrypt(B.ravel(), nonce=2))
+            else:
+                inputs[key] = (ctx.encrypt(I.sign_inputs(901, 1, 32)[0].ravel(), nonce=3), None)
+        return ctx, inputs[key]
+
+    plan = [(w,) + operands(w) for w in kinds]
+    servers = {id(c): he.Server(c, max_batch=16, min_batch=8, max_wait_us=40000) for c in rings}
+
+    def submit(w, ctx, ops):
+        srv = servers[id(ctx)]
+        if w[0] == "mm":
+            return srv, srv.submit(he.REQ_MATMUL, ops[0], ops[1], h=w[1])
+        return srv, srv.submit(he.REQ_SIGN, ops[0], d=w[1], k=w[2], mode=w[3])
+
+    def drain(tk, t_start, arrivals):
+        lat, t_last = {}, t_start
+        while len(lat) < len(tk):
+            for j, (srv, t) in enumerate(tk):
+                if j not in lat:
+                    r = srv.poll(t)
+                    if r is not None:
+                        t_last = time.perf_counter()
+                        lat[j] = (t_last - t_start) - arrivals[j]
+            time.sleep(0.0005)
+        return lat, t_last
+
+    # capacity: a burst of every request at t = 0
+    t0 = time.perf_counter()
+    tk = [submit(*p) for p in plan]
+    _, t_last = drain(tk, t0, [0.0] * nreq)
+    capacity = nreq / (t_last - t0)
+    runs = []
+    for ld in sorted({0.25, 0.5, load}):
+        # latency at ld x capacity
+        arrivals = I.poisson_arrivals(5, ld * capacity, nreq)
+        t0 = time.perf_counter()
+        tk = []
+        for j, p in enumerate(plan):
+            while time.perf_counter() - t0 < arrivals[j]:
+                time.sleep(0.0002)
+            tk.append(submit(*p))
+        lat, t_last = drain(tk, t0, arrivals)
+        lats = np.array([lat[j] for j in range(nreq)])
+        by = {}
+        for name, sel in (("matmul", lambda w: w[0] == "mm"), ("sign", lambda w: w[0] == "sign"),
+                          ("c4_relu", lambda w: w[0] == "c4relu")):
+            v = np.array([lat[j] for j in range(nreq) if sel(kinds[j])])
+            if v.size:
+                by[name] = {"n": int(v.size), "p50_ms": round(float(np.percentile(v, 50)) * 1e3, 1),
+                            "p99_ms": round(float(np.percentile(v, 99)) * 1e3, 1)}
+        runs.append({"load": ld, "arrival_rate_per_s": round(ld * capacity, 1),
+                     "served_per_s": round(nreq / (t_last - t0), 1),
+                     "p50_ms": round(float(np.percentile(lats, 50)) * 1e3, 1),
+                     "p99_ms": round(float(np.percentile(lats, 99)) * 1e3, 1), "by_type": by})
+    for srv in servers.values():
+        srv.stop()
+    for c in rings:
+        c.close()
+    return {"requests": nreq, "rings": "N=2^14 (C2), 2^15 (C3), 2^16 (C4)", "types": len(set(kinds)),
+            "batching_window": {"min_batch": 8, "max_wait_ms": 40, "per_type": True},
+            "burst_capacity_per_s": round(capacity, 1), "poisson": runs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +267,7 @@ def main():
     ap.add_argument("--no-other", action="store_true", help="skip timing the other schedules")
     ap.add_argument("--mix", type=int, default=256, help="mixed-batch products (0: skip)")
     ap.add_argument("--c4", type=int, default=128, help="ciphertexts of the N=2^16 ReLU + h=32 leg (0: skip)")
+    ap.add_argument("--serve-rings", type=int, default=300, help="requests of the cross-ring serving leg (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / batched capacity")
     ap.add_argument("--serve-min-batch", type=int, default=8)
@@ -360,6 +457,10 @@ def main():
         log(f"N=2^16 ReLU + h=32 leg ({args.c4} ciphertexts)")
         result["c4_relu_then_matmul"] = c4_leg(he, I, sched, stream, args.c4)
         log(f"c4: {result['c4_relu_then_matmul']}")
+    if args.serve_rings > 0:
+        log(f"serving across rings ({args.serve_rings} mixed requests)")
+        result["serve_mixed_rings"] = serve_rings_leg(he, I, sched, args.serve_rings, args.serve_load)
+        log(f"serve across rings: {result['serve_mixed_rings']}")
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(prm, sched)

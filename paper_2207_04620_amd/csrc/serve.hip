@@ -1,10 +1,13 @@
 // Serving loop: continuous batching of packed matrix products and sign/ReLU
 // evaluations on one device.
 //
-// A host thread owns execution.  Submitted requests wait in FIFO order and are
-// admitted while the summed device footprint of in-flight requests stays within the
-// budget; admitted requests with the same operation, parameters and level form a
-// cohort that runs in lockstep (group kernels, keys and masks read once per cohort).
+// A host thread owns execution.  Submitted requests wait in FIFO order.  Requests with
+// the same operation, parameters and level are one type; a type is ready once min_batch
+// of its requests wait or its oldest has waited max_wait (the batching window is per
+// type, so a mix of many types still forms full cohorts).  Ready requests are admitted
+// in arrival order while the summed device footprint of in-flight requests stays within
+// the budget; admitted requests of one type form a cohort that runs in lockstep (group
+// kernels, keys and masks read once per cohort).
 // Each round advances every active cohort by one phase (Step 1 of a product, then a
 // chunk of Step 2-3 rounds, then the final relinearisation/RS; one g_d composition of
 // a sign evaluation), so requests that arrive while others are on the device start at
@@ -18,6 +21,7 @@
 #include <deque>
 #include <map>
 #include <thread>
+#include <tuple>
 
 #include "he_internal.hpp"
 
@@ -27,8 +31,11 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+typedef std::tuple<uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, int> ReqKey;  // op, h, d, k, mode, level
+
 struct Req {
     he_request r;
+    ReqKey key;
     const CtData* a = nullptr;
     const CtData* b = nullptr;
     CtPtr keep_a, keep_b;  // the inputs stay alive while the request is in flight
@@ -79,36 +86,70 @@ static size_t footprint(const Ctx* c, const he_request& r, int level) {
     return 12 * ct + 2 * lift;
 }
 
+// types whose batching window has closed, and the time at which the next one closes
+static std::map<ReqKey, bool> ready_types(he_server* S, double now, double* next_close) {
+    std::map<ReqKey, std::pair<size_t, double>> by;  // count, oldest submit time
+    for (uint64_t id : S->pending) {
+        const Req& q = S->reqs[id];
+        auto it = by.find(q.key);
+        if (it == by.end())
+            by[q.key] = {1, q.t_submit};
+        else
+            ++it->second.first;
+    }
+    std::map<ReqKey, bool> ready;
+    *next_close = 1e300;
+    for (auto& kv : by) {
+        const bool r = S->stop || kv.second.first >= S->min_batch || now - kv.second.second >= S->max_wait_s;
+        ready[kv.first] = r;
+        if (!r) *next_close = std::min(*next_close, kv.second.second + S->max_wait_s);
+    }
+    return ready;
+}
+
 static void serve_loop(he_server* S) {
     for (;;) {
         std::vector<Cohort> fresh;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            bool ready = false;
+            std::map<ReqKey, bool> ready;
+            bool any = false;
             for (;;) {
                 if (S->stop && S->pending.empty() && S->active.empty()) return;
                 if (!S->pending.empty()) {
-                    const double age = now_s() - S->reqs[S->pending.front()].t_submit;
-                    ready = S->stop || S->pending.size() >= S->min_batch || age >= S->max_wait_s;
-                    if (ready || !S->active.empty()) break;
-                    S->cv.wait_for(lk, std::chrono::duration<double>(S->max_wait_s - age));
+                    double next_close = 0;
+                    const double now = now_s();
+                    ready = ready_types(S, now, &next_close);
+                    any = false;
+                    for (auto& kv : ready) any |= kv.second;
+                    if (any || !S->active.empty()) break;
+                    S->cv.wait_for(lk, std::chrono::duration<double>(std::max(0.0, next_close - now)));
                 } else {
                     if (!S->active.empty()) break;
                     S->cv.wait(lk);
                 }
             }
-            // admission in arrival order while the footprint fits (batching window: a new
-            // cohort starts once min_batch requests wait or the oldest waited max_wait)
-            std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, int>, size_t> slot;
-            while (ready && !S->pending.empty()) {
+            // admission of ready requests in arrival order while the footprint fits; the
+            // others keep their place in the queue
+            std::map<ReqKey, size_t> slot;
+            std::deque<uint64_t> keep;
+            bool full = false;
+            while (!S->pending.empty()) {
                 const uint64_t id = S->pending.front();
-                Req& q = S->reqs[id];
-                if (S->budget && S->inflight + q.footprint > S->budget && S->inflight > 0) break;
                 S->pending.pop_front();
+                Req& q = S->reqs[id];
+                if (full || !ready[q.key]) {
+                    keep.push_back(id);
+                    continue;
+                }
+                if (S->budget && S->inflight + q.footprint > S->budget && S->inflight > 0) {
+                    full = true;  // head of line: nothing behind it overtakes it
+                    keep.push_back(id);
+                    continue;
+                }
                 S->inflight += q.footprint;
-                const int lvl = q.r.op == HE_REQ_MATMUL ? std::min(q.a->level, q.b->level) : q.a->level;
-                const auto key = std::make_tuple(q.r.op, q.r.h, q.r.d, q.r.k, q.r.mode, lvl);
-                auto it = slot.find(key);
+                const int lvl = std::get<5>(q.key);
+                auto it = slot.find(q.key);
                 if (it == slot.end() || fresh[it->second].ids.size() >= S->max_batch) {
                     Cohort co;
                     co.op = q.r.op;
@@ -122,8 +163,8 @@ static void serve_loop(he_server* S) {
                         co.sj.lvl = lvl;
                     }
                     fresh.push_back(co);
-                    slot[key] = fresh.size() - 1;
-                    it = slot.find(key);
+                    slot[q.key] = fresh.size() - 1;
+                    it = slot.find(q.key);
                 }
                 Cohort& co = fresh[it->second];
                 co.ids.push_back(id);
@@ -134,6 +175,7 @@ static void serve_loop(he_server* S) {
                     co.sj.X.push_back(q.a);
                 }
             }
+            S->pending.swap(keep);
             for (auto& co : fresh) S->active.push_back(std::move(co));
         }
         // one round: every active cohort advances one phase
@@ -239,6 +281,8 @@ he_status he_serve_submit(he_server* S, const he_request* req, uint64_t* ticket)
     const int lvl = q.r.op == HE_REQ_MATMUL ? std::min(q.a->level, q.b->level) : q.a->level;
     q.footprint = footprint(S->c, q.r, lvl);
     if (S->budget && q.footprint > S->budget) return HE_ENOMEM;
+    q.key = std::make_tuple(q.r.op, q.r.op == HE_REQ_MATMUL ? q.r.h : 0u, q.r.op == HE_REQ_SIGN ? q.r.d : 0u,
+                            q.r.op == HE_REQ_SIGN ? q.r.k : 0u, q.r.op == HE_REQ_SIGN ? q.r.mode : 0u, lvl);
     q.t_submit = std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
     {
         std::lock_guard<std::mutex> lk(S->mu);

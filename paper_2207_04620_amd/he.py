@@ -334,6 +334,20 @@ class Context:
         _chk(lib().he_ntt(self.ptr, C.c_void_p(dev_tensor.data_ptr()), n_limbs, mi, int(inverse)), "he_ntt")
 
 
+def sign_depth(d: int, k: int, mode: int = SIGN) -> int:
+    """levels consumed by k compositions of g_d (1 + floor(log2 d) + 1 each), +1 for ReLU"""
+    return k * (d.bit_length() + 1) + (1 if mode == RELU else 0)
+
+
+def smallest_ring(contexts, h: int = 0, depth: int = 3):
+    """the context of the smallest ring that holds an h x h matrix (h^2 <= N/2) and has
+    'depth' levels to spend from its top level; None if none does"""
+    for ctx in sorted(contexts, key=lambda c: c.n):
+        if h * h <= ctx.n // 2 and depth <= ctx.max_level:
+            return ctx
+    return None
+
+
 class Server:
     """Continuous-batching request loop of libhe (he_serve_*)."""
 

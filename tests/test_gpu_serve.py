@@ -113,3 +113,63 @@ def test_serve_admission_and_rejections(ctx):
     assert len(done) == 3
     for t in ts:
         assert np.array_equal(ctx.export(done[t][0]), want)
+
+
+def test_serve_across_rings_equal_alone():
+    """the serving configuration across rings: one server per context (N = 2^14, 2^15,
+    2^16; each with its own stream and request loop, so their work overlaps on the device);
+    matmul requests of h in {8, ..., 128} and sign/ReLU requests of depth 3..13, each routed
+    to the smallest ring that holds its h and depth, submitted in an interleaved burst.
+    Every result equals the same operation run alone on that context, bit for bit."""
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2207_04620_amd import he
+    _log("[serve] contexts C2 / C3 / C4")
+    rings = [he.Context(I.C2, h_list=[8, 16, 32, 64], schedule=he.SCHED_FAST),
+             he.Context(I.C3, h_list=[128], schedule=he.SCHED_FAST),
+             he.Context(I.C4, h_list=[], schedule=he.SCHED_FAST)]
+    work = [("mm", 8), ("mm", 64), ("mm", 128), ("mm", 16), ("sign", 3, 1, he.SIGN), ("sign", 3, 2, he.RELU),
+            ("mm", 32), ("sign", 3, 4, he.RELU), ("sign", 3, 3, he.SIGN), ("mm", 64), ("sign", 3, 4, he.SIGN)]
+    reqs = []
+    for i, w in enumerate(work):
+        if w[0] == "mm":
+            ctx = he.smallest_ring(rings, h=w[1], depth=3)
+            A, B = I.matrix_pair(800 + i, w[1])
+            a = ctx.encrypt(A.ravel(), nonce=2 * i)
+            b = ctx.encrypt(B.ravel(), nonce=2 * i + 1)
+            want = ctx.export(ctx.matmul(a, b, w[1]))
+            reqs.append((ctx, w, a, b, want))
+        else:
+            _, d, k, mode = w
+            depth = he.sign_depth(d, k, mode)
+            # the deepest ReLU also runs on the largest ring (the sign configuration's ring)
+            ctx = rings[2] if depth == 13 else he.smallest_ring(rings, h=32, depth=depth)
+            X = I.sign_inputs(900 + i, 1, 32)[0]
+            x = ctx.encrypt(X.ravel(), nonce=2 * i)
+            want = ctx.export(ctx.sign_approx(x, d, k, mode))
+            reqs.append((ctx, w, x, None, want))
+        _log(f"[serve] request {i}: {w} on N=2^{ctx.n.bit_length() - 1}")
+    assert {id(r[0]) for r in reqs} == {id(c) for c in rings}
+    servers = {id(c): he.Server(c, max_batch=4, min_batch=1) for c in rings}
+    tickets = []
+    for ctx, w, a, b, _ in reqs:
+        srv = servers[id(ctx)]
+        if w[0] == "mm":
+            tickets.append(srv.submit(he.REQ_MATMUL, a, b, h=w[1]))
+        else:
+            tickets.append(srv.submit(he.REQ_SIGN, a, d=w[1], k=w[2], mode=w[3]))
+    done = {}
+    deadline = time.time() + 120
+    while len(done) < len(tickets) and time.time() < deadline:
+        for j, t in enumerate(tickets):
+            if j not in done:
+                r = servers[id(reqs[j][0])].poll(t)
+                if r is not None:
+                    done[j] = r
+        time.sleep(0.002)
+    for s in servers.values():
+        s.stop()
+    assert len(done) == len(tickets)
+    for j, (ctx, w, _, _, want) in enumerate(reqs):
+        assert np.array_equal(ctx.export(done[j][0]), want), (j, w)
+    _log("[serve] across rings: every result equals its run alone")
