@@ -218,7 +218,7 @@ struct orc_ctx {
     int n_keys, cap_keys;
     int64_t cnt[6];
     /* mask cache */
-    struct mask_ent { int kind, h, k; int64_t rot; int64_t *coef; } *masks;
+    struct mask_ent { int kind, h, beta, k; int64_t rot; int64_t *coef; } *masks;
     int n_masks, cap_masks;
 };
 
@@ -1007,33 +1007,42 @@ void orc_mask_slots(int kind, int h, int k, double *out) {
             v = (t % h) == k;
         } else if (kind == 2) { /* v_k: 0 <= [t]_h < h - k  (k = 0 gives all ones) */
             v = (t % h) < h - k;
-        } else {                /* v_{k-h}: h - k <= [t]_h < h */
+        } else if (kind == 3) { /* v_{k-h}: h - k <= [t]_h < h */
             v = (t % h) >= h - k;
+        } else {                /* kind 4, App. C: diagonal (h-1) k of U^T, k in (-h, h).  Output
+                                 * t = h i + j reads a[h j + i] = a[t + (h-1)(j - i)], so the
+                                 * diagonal (h-1) k is 1 exactly where j - i = k */
+            v = (t % h) - (t / h) == k;
         }
         out[t] = v;
     }
 }
-
-/* encoded mask R(u, rot) at scale Delta (cached) */
-static const int64_t *get_mask(orc_ctx *c, int kind, int h, int k, int64_t rot) {
+/* the encoded mask R(u, rot) of kind/h/k (rot in positions of the h^2 vector), expanded for
+ * the packing iota_beta (App. E): entry t of the matrix vector fills slots beta t .. beta t +
+ * beta - 1, so a rotation by beta r of the packed vector is a rotation by r of every matrix */
+static const int64_t *get_mask_b(orc_ctx *c, int kind, int h, int beta, int k, int64_t rot) {
     for (int i = 0; i < c->n_masks; i++) {
         struct mask_ent *m = &c->masks[i];
-        if (m->kind == kind && m->h == h && m->k == k && m->rot == rot) return m->coef;
+        if (m->kind == kind && m->h == h && m->beta == beta && m->k == k && m->rot == rot) return m->coef;
     }
     int n = h * h;
-    double *u = malloc(sizeof(double) * n), *ur = malloc(sizeof(double) * n);
+    double *u = malloc(sizeof(double) * n), *ur = malloc(sizeof(double) * (size_t)n * beta);
     orc_mask_slots(kind, h, k, u);
-    for (int t = 0; t < n; t++) ur[t] = u[(((t + rot) % n) + n) % n]; /* R(u, rot)[t] = u[t + rot] */
+    for (int t = 0; t < n; t++)
+        for (int e = 0; e < beta; e++) ur[(int64_t)beta * t + e] = u[(((t + rot) % n) + n) % n]; /* R(u, rot)[t] = u[t + rot] */
     int64_t *coef = malloc(sizeof(int64_t) * c->n);
-    orc_encode(c, ur, n, c->scale, coef);
+    orc_encode(c, ur, (int64_t)n * beta, c->scale, coef);
     free(u); free(ur);
     if (c->n_masks == c->cap_masks) {
         c->cap_masks = c->cap_masks ? 2 * c->cap_masks : 64;
         c->masks = realloc(c->masks, sizeof(struct mask_ent) * c->cap_masks);
     }
-    struct mask_ent e = {kind, h, k, rot, coef};
+    struct mask_ent e = {kind, h, beta, k, rot, coef};
     c->masks[c->n_masks++] = e;
     return coef;
+}
+static const int64_t *get_mask(orc_ctx *c, int kind, int h, int k, int64_t rot) {
+    return get_mask_b(c, kind, h, 1, k, rot);
 }
 
 static int ilog2(int h) { int l = 0; while ((1 << l) < h) l++; return l; }
@@ -1045,37 +1054,63 @@ static orc_ct *acc_add(orc_ctx *c, orc_ct *acc, orc_ct *t) {
     return r;
 }
 
-/* baby-step count of the Step-3 split k = bg i + j: bg = 2^ceil((log2 h + 1) / 2), at most h;
- * without the Step-3 flag the sum is one block of h terms */
-static int step3_baby(int h, int mode) {
-    if (!(mode & ORC_STEP3_BSGS)) return h;
-    int bg = 1 << ((ilog2(h) + 2) / 2);
-    return bg < h ? bg : h;
+/* baby-step count of the Step-3 split k = bg i + j over t rounds (t = h for a square
+ * product): bg = 2^ceil((log2 t + 1) / 2), at most t; without the Step-3 flag the sum is one
+ * block of t terms */
+static int step3_baby(int t, int mode) {
+    if (!(mode & ORC_STEP3_BSGS)) return t;
+    int bg = 1 << ((ilog2(t) + 2) / 2);
+    return bg < t ? bg : t;
 }
 
-int orc_matmul_rotations(const orc_ctx *c, int h, int mode, int64_t *out, int cap) {
-    int b = 1 << ((ilog2(h) + 1) / 2), bg = step3_baby(h, mode), n = 0;
-    int64_t half = c->n / 2;
-    int64_t tmp[4096];
+/* rotation amounts of HE-LinTrans with BSGS (App. B) over diagonals d in [dlo, dhi] at
+ * rotation unit u: baby steps u j (0 < j < b), giant steps u b i (i != 0) */
+static int lintrans_rotations(int b, int64_t unit, int dlo, int dhi, int64_t *out) {
     int m = 0;
-    for (int j = 1; j < b; j++) tmp[m++] = j;
-    for (int i = floordiv(1 - h, b); i <= floordiv(h - 1, b); i++) if (i) tmp[m++] = (int64_t)b * i;
-    for (int j = 1; j < b; j++) tmp[m++] = (int64_t)h * j;
-    for (int i = 1; i * b < h; i++) tmp[m++] = (int64_t)h * b * i;
-    for (int k = 1; k < h; k++) {
+    for (int j = 1; j < b; j++) out[m++] = unit * j;
+    for (int i = floordiv(dlo, b); i <= floordiv(dhi, b); i++)
+        if (i) out[m++] = unit * b * i;
+    return m;
+}
+
+/* normalise amounts (times beta) into [0, N/2), drop 0 and duplicates */
+static int normalise_rotations(const orc_ctx *c, const int64_t *tmp, int m, int beta, int64_t *out, int cap) {
+    int64_t half = c->n / 2;
+    int n = 0;
+    for (int i = 0; i < m; i++) {
+        int64_t v = (((tmp[i] * beta) % half) + half) % half;
+        int dup = 0;
+        for (int j = 0; j < n && j < cap; j++) dup |= out[j] == v;
+        if (!dup && v != 0) { if (n < cap) out[n] = v; n++; }
+    }
+    return n;
+}
+
+int orc_matmul_rotations_ex(const orc_ctx *c, int h, int t, int beta, int mode, int64_t *out, int cap) {
+    int b = 1 << ((ilog2(h) + 1) / 2), bg = step3_baby(t, mode);
+    int64_t tmp[8192];
+    int m = 0;
+    m += lintrans_rotations(b, 1, 1 - h, h - 1, tmp + m);
+    m += lintrans_rotations(b, h, 0, h - 1, tmp + m);
+    for (int k = 1; k < t; k++) {
         int64_t shift = (int64_t)h * bg * (k / bg);
         tmp[m++] = k - shift;
         tmp[m++] = k - h - shift;
     }
     for (int j = 1; j < bg; j++) tmp[m++] = (int64_t)h * j;
-    for (int i = 1; i * bg < h; i++) tmp[m++] = (int64_t)h * bg * i;
-    for (int i = 0; i < m; i++) {
-        int64_t v = ((tmp[i] % half) + half) % half;
-        int dup = 0;
-        for (int j = 0; j < n; j++) dup |= out[j] == v;
-        if (!dup && v != 0) { if (n < cap) out[n] = v; n++; }
-    }
-    return n;
+    for (int i = 1; i * bg < t; i++) tmp[m++] = (int64_t)h * bg * i;
+    for (int s = 0; (t << s) < h; s++) tmp[m++] = ((int64_t)t * h) << s;
+    return normalise_rotations(c, tmp, m, beta, out, cap);
+}
+
+int orc_matmul_rotations(const orc_ctx *c, int h, int mode, int64_t *out, int cap) {
+    return orc_matmul_rotations_ex(c, h, h, 1, mode, out, cap);
+}
+
+int orc_transpose_rotations(const orc_ctx *c, int h, int beta, int64_t *out, int cap) {
+    int64_t tmp[1024];
+    int m = lintrans_rotations(1 << ((ilog2(h) + 1) / 2), h - 1, 1 - h, h - 1, tmp);
+    return normalise_rotations(c, tmp, m, beta, out, cap);
 }
 
 /* sum_w v_w . Rot(a_w, r_w) (v_w = 1 when masks is NULL or masks[w] is NULL) with one
@@ -1142,105 +1177,112 @@ static orc_ct *rot_sum_hoisted(orc_ctx *c, int n, orc_ct *const *a, const int64_
     return out;
 }
 
-orc_ct *orc_matmul(orc_ctx *c, const orc_ct *A, const orc_ct *B, int h, int mode) {
-    if (h < 1 || (h & (h - 1)) || (int64_t)h * h > c->n / 2) return NULL;
+/* HE-LinTrans (Alg. 2) with the baby-step/giant-step split (App. B): the sum over the
+ * diagonals d in [dlo, dhi] of mask_d . R(a, unit d), evaluated as
+ *   sum_i Rot( sum_j R(mask_{b i + j}, -unit b i) . Rot(a, unit j), unit b i ),
+ * masks of 'kind' for side h under the packing iota_beta (every amount times beta); the giant
+ * steps share one ModDown under the hoisting flag.  No rescale. */
+static orc_ct *lintrans(orc_ctx *c, const orc_ct *a, int kind, int h, int beta, int64_t unit, int dlo, int dhi,
+                        int b, int hoist) {
+    const double ms = c->scale;
+    orc_ct **baby = calloc(b, sizeof(orc_ct *));
+    baby[0] = ct_copy(c, a);
+    for (int j = 1; j < b; j++) baby[j] = orc_rotate(c, a, (int64_t)beta * unit * j);
+    int ngmax = floordiv(dhi, b) - floordiv(dlo, b) + 1, ng = 0;
+    orc_ct **gi = calloc(ngmax, sizeof(orc_ct *));
+    int64_t *gr = calloc(ngmax, sizeof(int64_t));
+    orc_ct *acc = NULL;
+    for (int i = floordiv(dlo, b); i <= floordiv(dhi, b); i++) {
+        orc_ct *inner = NULL;
+        for (int j = 0; j < b; j++) {
+            int d = b * i + j;
+            if (d < dlo || d > dhi) continue;
+            inner = acc_add(c, inner, orc_mul_plain(c, baby[j], get_mask_b(c, kind, h, beta, d, -unit * b * i), ms));
+        }
+        if (!inner) continue;
+        const int64_t r = (int64_t)beta * unit * b * i;
+        if (i && hoist) { gi[ng] = inner; gr[ng++] = r; continue; }
+        if (i) { orc_ct *t = orc_rotate(c, inner, r); orc_ct_free(inner); inner = t; }
+        acc = acc_add(c, acc, inner);
+    }
+    if (ng) {
+        acc = acc_add(c, acc, rot_sum_hoisted(c, ng, gi, gr, NULL, ms));
+        while (ng) orc_ct_free(gi[--ng]);
+    }
+    for (int j = 0; j < b; j++) orc_ct_free(baby[j]);
+    free(baby); free(gi); free(gr);
+    return acc;
+}
+
+static int valid_shape(const orc_ctx *c, int h, int t, int beta) {
+    if (h < 1 || (h & (h - 1)) || t < 1 || (t & (t - 1)) || t > h || beta < 1 || (beta & (beta - 1))) return 0;
+    return (int64_t)beta * h * h <= c->n / 2;
+}
+
+/* HE-MatMult (Alg. 3, t = h) and HE-RMatMult (Alg. 6, App. D: A~ holds h/t vertical copies
+ * of a t x h matrix A; Steps 2-3 run t rounds, then the row blocks are folded by rotations
+ * t h 2^s so every block holds A B), for beta products packed by iota_beta (App. E). */
+orc_ct *orc_matmul_ex(orc_ctx *c, const orc_ct *A, const orc_ct *B, int h, int t, int beta, int mode) {
+    if (!valid_shape(c, h, t, beta)) return NULL;
     int lvl = A->level < B->level ? A->level : B->level;
     if (lvl < 3) return NULL;
     orc_ct *a = orc_drop(c, A, lvl), *bb = orc_drop(c, B, lvl);
-    int b = 1 << ((ilog2(h) + 1) / 2);
-    double ms = c->scale;
+    const int b = 1 << ((ilog2(h) + 1) / 2);
+    const double ms = c->scale;
     const int once = mode & ORC_RELIN_ONCE, hoist = mode & ORC_HOIST_MODDOWN, late = mode & ORC_RESCALE_LATE;
-    /* giant-step terms whose rotations share one ModDown (ModDown-hoisting flag) */
-    orc_ct **gi = calloc(2 * h + 2, sizeof(orc_ct *));
-    int64_t *gr = calloc(2 * h + 2, sizeof(int64_t));
-    int ng = 0;
 
-    /* Step 1-1: A0 = sum_i Rot(sum_j R(u_{bi+j}, -bi) . Rot(A, j), b i), then RS */
-    orc_ct **baby = calloc(b, sizeof(orc_ct *));
-    baby[0] = ct_copy(c, a);
-    for (int j = 1; j < b; j++) baby[j] = orc_rotate(c, a, j);
-    orc_ct *A0 = NULL;
-    for (int i = floordiv(1 - h, b); i <= floordiv(h - 1, b); i++) {
-        orc_ct *inner = NULL;
-        for (int j = 0; j < b; j++) {
-            int k = b * i + j;
-            if (k <= -h || k >= h) continue;
-            inner = acc_add(c, inner, orc_mul_plain(c, baby[j], get_mask(c, 0, h, k, -(int64_t)b * i), ms));
-        }
-        if (!inner) continue;
-        if (i && hoist) { gi[ng] = inner; gr[ng++] = (int64_t)b * i; continue; }
-        if (i) { orc_ct *t = orc_rotate(c, inner, (int64_t)b * i); orc_ct_free(inner); inner = t; }
-        A0 = acc_add(c, A0, inner);
-    }
-    if (ng) {
-        A0 = acc_add(c, A0, rot_sum_hoisted(c, ng, gi, gr, NULL, ms));
-        while (ng) orc_ct_free(gi[--ng]);
-    }
-    for (int j = 0; j < b; j++) orc_ct_free(baby[j]);
-    { orc_ct *t = orc_rescale(c, A0); orc_ct_free(A0); A0 = t; }
-
-    /* Step 1-2: B0 = sum_i Rot(sum_j R(u_{h(bi+j)}, -h b i) . Rot(B, h j), h b i), then RS */
-    baby[0] = ct_copy(c, bb);
-    for (int j = 1; j < b; j++) baby[j] = orc_rotate(c, bb, (int64_t)h * j);
-    orc_ct *B0 = NULL;
-    for (int i = 0; i * b < h; i++) {
-        orc_ct *inner = NULL;
-        for (int j = 0; j < b && b * i + j < h; j++)
-            inner = acc_add(c, inner, orc_mul_plain(c, baby[j], get_mask(c, 1, h, b * i + j, -(int64_t)h * b * i), ms));
-        if (i && hoist) { gi[ng] = inner; gr[ng++] = (int64_t)h * b * i; continue; }
-        if (i) { orc_ct *t = orc_rotate(c, inner, (int64_t)h * b * i); orc_ct_free(inner); inner = t; }
-        B0 = acc_add(c, B0, inner);
-    }
-    if (ng) {
-        B0 = acc_add(c, B0, rot_sum_hoisted(c, ng, gi, gr, NULL, ms));
-        while (ng) orc_ct_free(gi[--ng]);
-    }
-    for (int j = 0; j < b; j++) orc_ct_free(baby[j]);
-    free(baby);
-    { orc_ct *t = orc_rescale(c, B0); orc_ct_free(B0); B0 = t; }
+    /* Step 1-1: A0 = U^mu A, diagonals k in (-h, h) at unit 1, then RS */
+    orc_ct *A0 = lintrans(c, a, 0, h, beta, 1, 1 - h, h - 1, b, hoist);
+    { orc_ct *x = orc_rescale(c, A0); orc_ct_free(A0); A0 = x; }
+    /* Step 1-2: B0 = U^zeta B, diagonals h k, k in [0, h), then RS */
+    orc_ct *B0 = lintrans(c, bb, 1, h, beta, h, 0, h - 1, b, hoist);
+    { orc_ct *x = orc_rescale(c, B0); orc_ct_free(B0); B0 = x; }
     /* B0 is brought to the Step-3 level before its rotations (the late-rescale schedule
      * multiplies one level higher and keeps it) */
-    if (!late) { orc_ct *t = orc_drop(c, B0, B0->level - 1); orc_ct_free(B0); B0 = t; }
+    if (!late) { orc_ct *x = orc_drop(c, B0, B0->level - 1); orc_ct_free(B0); B0 = x; }
 
-    /* Steps 2 and 3.  The Step-3 sum over k is taken in blocks k = bg i + j:
+    /* Steps 2 and 3 over k in [0, t).  The Step-3 sum is taken in blocks k = bg i + j:
      *   sum_i Rot( sum_j Rot(A^(k), -h bg i) . Rot(B0, h j), h bg i ),
      * where Rot(A^(k), -s) = R(v_k, -s) . Rot(A0, k - s) + R(v_(k-h), -s) . Rot(A0, k - h - s).
-     * Without the Step-3 flag there is one block (bg = h) and no giant-step rotation, which
-     * is Alg. 3's Step 3 as printed. */
-    const int bg = step3_baby(h, mode);
+     * Without the Step-3 flag there is one block (bg = t) and no giant-step rotation, which
+     * is Alg. 3's (Alg. 6's) Step 3 as printed.  Rotation amounts are times beta. */
+    const int bg = step3_baby(t, mode);
     orc_ct **bj = calloc(bg, sizeof(orc_ct *));
     bj[0] = ct_copy(c, B0);
-    for (int j = 1; j < bg; j++) bj[j] = orc_rotate(c, B0, (int64_t)h * j);
+    for (int j = 1; j < bg; j++) bj[j] = orc_rotate(c, B0, (int64_t)beta * h * j);
+    orc_ct **gi = calloc(t / bg + 1, sizeof(orc_ct *));
+    int64_t *gr = calloc(t / bg + 1, sizeof(int64_t));
+    int ng = 0;
     orc_ct *acc = NULL;
-    for (int i = 0; i * bg < h; i++) {
+    for (int i = 0; i * bg < t; i++) {
         const int64_t shift = (int64_t)h * bg * i;
         orc_ct *S = NULL;
         for (int j = 0; j < bg; j++) {
             const int k = bg * i + j;
             orc_ct *Ak;
             if (k == 0) {
-                Ak = orc_mul_plain(c, A0, get_mask(c, 2, h, 0, 0), ms);
+                Ak = orc_mul_plain(c, A0, get_mask_b(c, 2, h, beta, 0, 0), ms);
             } else if (hoist) {
-                const int64_t rr[2] = {k - shift, k - h - shift};
-                const int64_t *mm[2] = {get_mask(c, 2, h, k, -shift), get_mask(c, 3, h, k, -shift)};
+                const int64_t rr[2] = {beta * (k - shift), beta * (k - h - shift)};
+                const int64_t *mm[2] = {get_mask_b(c, 2, h, beta, k, -shift), get_mask_b(c, 3, h, beta, k, -shift)};
                 orc_ct *const aa[2] = {A0, A0};
                 Ak = rot_sum_hoisted(c, 2, aa, rr, mm, ms);
             } else {
-                orc_ct *r1 = orc_rotate(c, A0, k - shift), *r2 = orc_rotate(c, A0, k - h - shift);
-                orc_ct *t1 = orc_mul_plain(c, r1, get_mask(c, 2, h, k, -shift), ms);
-                orc_ct *t2 = orc_mul_plain(c, r2, get_mask(c, 3, h, k, -shift), ms);
+                orc_ct *r1 = orc_rotate(c, A0, beta * (k - shift)), *r2 = orc_rotate(c, A0, beta * (k - h - shift));
+                orc_ct *t1 = orc_mul_plain(c, r1, get_mask_b(c, 2, h, beta, k, -shift), ms);
+                orc_ct *t2 = orc_mul_plain(c, r2, get_mask_b(c, 3, h, beta, k, -shift), ms);
                 Ak = orc_add(c, t1, t2);
                 orc_ct_free(r1); orc_ct_free(r2); orc_ct_free(t1); orc_ct_free(t2);
             }
-            if (!late) { orc_ct *t = orc_rescale(c, Ak); orc_ct_free(Ak); Ak = t; }
+            if (!late) { orc_ct *x = orc_rescale(c, Ak); orc_ct_free(Ak); Ak = x; }
             orc_ct *prod = orc_tensor(c, Ak, bj[j]);
-            if (!once) { orc_ct *t = orc_relin(c, prod); orc_ct_free(prod); prod = t; }
+            if (!once) { orc_ct *x = orc_relin(c, prod); orc_ct_free(prod); prod = x; }
             S = acc_add(c, S, prod);
             orc_ct_free(Ak);
         }
-        if (once) { orc_ct *t = orc_relin(c, S); orc_ct_free(S); S = t; }
-        if (i && hoist) { gi[ng] = S; gr[ng++] = shift; continue; }
-        if (i) { orc_ct *t = orc_rotate(c, S, shift); orc_ct_free(S); S = t; }
+        if (once) { orc_ct *x = orc_relin(c, S); orc_ct_free(S); S = x; }
+        if (i && hoist) { gi[ng] = S; gr[ng++] = beta * shift; continue; }
+        if (i) { orc_ct *x = orc_rotate(c, S, beta * shift); orc_ct_free(S); S = x; }
         acc = acc_add(c, acc, S);
     }
     if (ng) {
@@ -1251,9 +1293,29 @@ orc_ct *orc_matmul(orc_ctx *c, const orc_ct *A, const orc_ct *B, int h, int mode
     for (int j = 0; j < bg; j++) orc_ct_free(bj[j]);
     free(bj);
     orc_ct *res = orc_rescale(c, acc);
-    if (late) { orc_ct *t = orc_rescale(c, res); orc_ct_free(res); res = t; }
+    if (late) { orc_ct *x = orc_rescale(c, res); orc_ct_free(res); res = x; }
+    /* Alg. 6's last loop: fold the h/t row blocks of t rows (after the rescales, on fewer limbs) */
+    for (int s2 = 0; (t << s2) < h; s2++) {
+        orc_ct *r = orc_rotate(c, res, (int64_t)beta * t * h << s2);
+        orc_ct *x = orc_add(c, res, r);
+        orc_ct_free(r); orc_ct_free(res);
+        res = x;
+    }
     orc_ct_free(acc); orc_ct_free(A0); orc_ct_free(B0); orc_ct_free(a); orc_ct_free(bb);
     return res;
+}
+
+orc_ct *orc_matmul(orc_ctx *c, const orc_ct *A, const orc_ct *B, int h, int mode) {
+    return orc_matmul_ex(c, A, B, h, h, 1, mode);
+}
+
+/* App. C: A^T = sum_{-h<k<h} t_{(h-1)k} . R(a, (h-1) k), with BSGS (App. B), then RS */
+orc_ct *orc_transpose(orc_ctx *c, const orc_ct *A, int h, int beta, int mode) {
+    if (!valid_shape(c, h, h, beta) || A->level < 1) return NULL;
+    orc_ct *r = lintrans(c, A, 4, h, beta, h - 1, 1 - h, h - 1, 1 << ((ilog2(h) + 1) / 2), mode & ORC_HOIST_MODDOWN);
+    orc_ct *x = orc_rescale(c, r);
+    orc_ct_free(r);
+    return x;
 }
 
 /* ------------------------------------------------------------------ */

@@ -106,12 +106,24 @@ void orc_rotate_hoisted(orc_ctx *c, const orc_ct *a, int n, const int64_t *ks, o
 #define ORC_RESCALE_LATE 4
 #define ORC_STEP3_BSGS 8
 orc_ct *orc_matmul(orc_ctx *c, const orc_ct *a, const orc_ct *b, int h, int relin_mode);
+/* the product for a shape: t = h is Alg. 3; t < h (t | h) is HE-RMatMult (Alg. 6, App. D) with
+ * a holding h/t vertical copies of a t x h matrix, the result holding h/t copies of the t x h
+ * product; beta > 1 multiplies beta pairs of matrices packed by iota_beta (App. E:
+ * matrix m, entry (i, j) at slot beta (h i + j) + m).  h, t, beta powers of two,
+ * beta h^2 <= N/2. */
+orc_ct *orc_matmul_ex(orc_ctx *c, const orc_ct *a, const orc_ct *b, int h, int t, int beta, int mode);
+/* App. C: the transpose of every packed h x h matrix (diagonals (h-1) k, BSGS); depth 1;
+ * the ModDown-hoisting flag of 'mode' applies to its giant steps */
+orc_ct *orc_transpose(orc_ctx *c, const orc_ct *a, int h, int beta, int mode);
 /* slot-domain 0/1 vectors of length h*h for the diagonals used by Alg. 3:
- * kind 0: u^mu_k (k in (-h,h)), 1: u^zeta_{h k} (k in [0,h)), 2: v_k (k in [0,h)), 3: v_{k-h} */
+ * kind 0: u^mu_k (k in (-h,h)), 1: u^zeta_{h k} (k in [0,h)), 2: v_k (k in [0,h)), 3: v_{k-h},
+ * 4: t_{(h-1)k}, the transpose diagonals of App. C (k in (-h,h)) */
 void orc_mask_slots(int kind, int h, int k, double *out);
 /* rotation amounts (mod N/2, normalised into [0,N/2)) the product needs for h under the
  * given schedule flags */
 int orc_matmul_rotations(const orc_ctx *c, int h, int mode, int64_t *out, int cap);
+int orc_matmul_rotations_ex(const orc_ctx *c, int h, int t, int beta, int mode, int64_t *out, int cap);
+int orc_transpose_rotations(const orc_ctx *c, int h, int beta, int64_t *out, int cap);
 /* 0 rotations, 1 key switches, 2 mul_pt, 3 mul_ct, 4 add, 5 rescale */
 void orc_counters(const orc_ctx *c, int64_t out[6]);
 void orc_reset_counters(orc_ctx *c);

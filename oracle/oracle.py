@@ -98,6 +98,10 @@ def _declare(L):
         "orc_matmul": (vp, [vp, vp, vp, i32, i32]),
         "orc_mask_slots": (None, [i32, i32, i32, P(dbl)]),
         "orc_matmul_rotations": (i32, [vp, i32, i32, P(i64), i32]),
+        "orc_matmul_ex": (vp, [vp, vp, vp, i32, i32, i32, i32]),
+        "orc_transpose": (vp, [vp, vp, i32, i32, i32]),
+        "orc_matmul_rotations_ex": (i32, [vp, i32, i32, i32, i32, P(i64), i32]),
+        "orc_transpose_rotations": (i32, [vp, i32, i32, P(i64), i32]),
         "orc_counters": (None, [vp, P(i64)]),
         "orc_reset_counters": (None, [vp]),
         "orc_sign": (vp, [vp, vp, i32, i32, i32]),
@@ -343,6 +347,23 @@ class Ctx:
 
     def matmul(self, a, b, h, relin_mode=RELIN_EACH):
         return Ct(self, lib().orc_matmul(self.ptr, a.ptr, b.ptr, h, relin_mode))
+
+    def matmul_ex(self, a, b, h, t=None, beta=1, mode=RELIN_EACH):
+        """Alg. 3 (t = h) / HE-RMatMult (Alg. 6, t < h) on beta matrices packed by iota_beta"""
+        return Ct(self, lib().orc_matmul_ex(self.ptr, a.ptr, b.ptr, h, h if t is None else t, beta, mode))
+
+    def transpose(self, a, h, beta=1, mode=RELIN_EACH):
+        return Ct(self, lib().orc_transpose(self.ptr, a.ptr, h, beta, mode))
+
+    def matmul_rotations_ex(self, h, t, beta=1, mode=RELIN_EACH):
+        o = np.zeros(8192, np.int64)
+        n = lib().orc_matmul_rotations_ex(self.ptr, h, t, beta, mode, i64p(o), 8192)
+        return sorted(int(x) for x in o[:n])
+
+    def transpose_rotations(self, h, beta=1):
+        o = np.zeros(8192, np.int64)
+        n = lib().orc_transpose_rotations(self.ptr, h, beta, i64p(o), 8192)
+        return sorted(int(x) for x in o[:n])
 
     def matmul_rotations(self, h, mode=RELIN_EACH):
         o = np.zeros(8192, np.int64)

@@ -663,3 +663,143 @@ def test_sign_rejects_shallow_level(small):
     x = small.drop(small.encrypt(np.zeros(4), nonce=1), 2)
     with pytest.raises(ValueError):
         small.sign(x, 3, 1)
+
+
+# ---------------------------------------------------------------- App. C, D, E
+@pytest.mark.parametrize("h", [2, 3, 4, 8, 16])
+def test_transpose_diagonals_from_definition(h):
+    """kind-4 masks t_{(h-1)k}: sum_k t_{(h-1)k} . R(a, (h-1)k) is the transpose of the
+    row-major matrix a (plaintext, numpy); for k >= 0 they match App. C's printed formula
+    t - k = (h+1) j, 0 <= j < h - k; for k < 0 the printed t + k = (h+1) j does not (h > 2),
+    the reading t + h k = (h+1) j, 0 <= j < h + k does"""
+    n = h * h
+    a = np.random.default_rng(h).standard_normal(n)
+    out = np.zeros(n)
+    for k in range(1 - h, h):
+        m = O.mask_slots(4, h, k) if (h & (h - 1)) == 0 else None
+        if m is None:  # the oracle's masks are for powers of two; rebuild the definition
+            m = np.array([1.0 if (t % h) - (t // h) == k else 0.0 for t in range(n)])
+        out += m * np.roll(a, -(h - 1) * k)
+        printed = np.array([1.0 if any(t - k == (h + 1) * j for j in range(0, h - k)) else 0.0 for t in range(n)]) \
+            if k >= 0 else np.array([1.0 if any(t + k == (h + 1) * j for j in range(0, h + k)) else 0.0
+                                     for t in range(n)])
+        reading = np.array([1.0 if any(t + h * k == (h + 1) * j for j in range(0, h + k)) else 0.0
+                            for t in range(n)])
+        if k >= 0:
+            assert np.array_equal(m, printed)
+        else:
+            assert np.array_equal(m, reading)
+            if h > 2:
+                assert not np.array_equal(m, printed)
+    assert np.allclose(out, a.reshape(h, h).T.ravel())
+
+
+def pack_beta(mats):
+    """iota_beta^-1 (App. E): matrix m's entry (i, j) at position beta (h i + j) + m"""
+    beta, h = len(mats), mats[0].shape[0]
+    v = np.zeros(beta * h * h)
+    for m, M in enumerate(mats):
+        v[m::beta] = M.ravel()
+    return v
+
+
+def test_packing_rotation_is_matrixwise():
+    """App. E: a rotation of the packed vector by beta r rotates every matrix by r"""
+    h, beta = 4, 4
+    mats = [np.random.default_rng(m).standard_normal((h, h)) for m in range(beta)]
+    v = pack_beta(mats)
+    for r in (1, 3, h, 5):
+        w = np.roll(v, -beta * r)
+        for m in range(beta):
+            assert np.array_equal(w[m::beta], np.roll(mats[m].ravel(), -r))
+
+
+@pytest.mark.parametrize("h,beta", [(4, 1), (8, 1), (16, 1), (4, 2), (8, 4)])
+def test_transpose_decrypts(small, h, beta):
+    mats = [np.random.default_rng(10 * h + m).uniform(-1, 1, (h, h)) for m in range(beta)]
+    ct = small.encrypt(pack_beta(mats), nonce=70)
+    small.reset_counters()
+    tt = small.transpose(ct, h, beta)
+    cnt = small.counters()
+    assert tt.level == ct.level - 1
+    got = small.decrypt(tt, beta * h * h)
+    for m in range(beta):
+        assert np.abs(got[m::beta].reshape(h, h) - mats[m].T).max() < 1e-6
+    b = 2 ** ((int(math.log2(h)) + 1) // 2)
+    giants = len([i for i in range((1 - h) // b, (h - 1) // b + 1) if i != 0])
+    assert cnt["rot"] == (b - 1) + giants
+    assert cnt["mul_pt"] == 2 * h - 1
+    assert len(small.transpose_rotations(h, beta)) == (b - 1) + giants
+
+
+@pytest.mark.parametrize("h,t", [(8, 1), (8, 2), (8, 4), (16, 4), (16, 8)])
+def test_rectangular_product_decrypts(small, h, t):
+    """Alg. 6: A~ = h/t vertical copies of the t x h matrix A; the result holds h/t copies of
+    the t x h product A B; t - 1 rounds of Steps 2-3 and log2(h/t) fold rotations"""
+    rng = np.random.default_rng(h + t)
+    A = rng.uniform(-1, 1, (t, h))
+    B = rng.uniform(-1, 1, (h, h))
+    ca = small.encrypt(np.tile(A, (h // t, 1)).ravel(), nonce=80)
+    cb = small.encrypt(B.ravel(), nonce=81)
+    small.reset_counters()
+    cm = small.matmul_ex(ca, cb, h, t)
+    cnt = small.counters()
+    assert cm.level == ca.level - 3
+    got = small.decrypt(cm, h * h).reshape(h, h)
+    for blk in range(h // t):
+        assert np.abs(got[blk * t:(blk + 1) * t] - A @ B).max() < 1e-3
+    b = 2 ** ((int(math.log2(h)) + 1) // 2)
+    step1 = step1_rotations(h)
+    fold = int(math.log2(h // t))
+    assert cnt["rot"] == step1 + 3 * (t - 1) + fold
+    assert cnt["mul_ct"] == t
+    assert cnt["mul_pt"] == (2 * h - 1) + h + (2 * (t - 1) + 1)
+
+
+@pytest.mark.parametrize("h,beta,mode", [(4, 4, O.RELIN_EACH), (8, 2, O.FAST), (8, 4, O.RELIN_ONCE)])
+def test_packed_products_decrypt(small, h, beta, mode):
+    """beta products in one ciphertext pair (App. E), same op counts as one product"""
+    rng = np.random.default_rng(h * beta)
+    As = [rng.uniform(-1, 1, (h, h)) for _ in range(beta)]
+    Bs = [rng.uniform(-1, 1, (h, h)) for _ in range(beta)]
+    ca, cb = small.encrypt(pack_beta(As), nonce=90), small.encrypt(pack_beta(Bs), nonce=91)
+    small.reset_counters()
+    cm = small.matmul_ex(ca, cb, h, h, beta, mode)
+    cnt = small.counters()
+    got = small.decrypt(cm, beta * h * h)
+    for m in range(beta):
+        assert np.abs(got[m::beta].reshape(h, h) - As[m] @ Bs[m]).max() < 1e-3
+    rots, relins = step3_counts(h, mode)
+    assert cnt["rot"] == step1_rotations(h) + rots
+
+
+@pytest.mark.parametrize("h,t,beta,mode", [(16, 16, 2, 0), (16, 4, 1, O.FAST), (8, 2, 4, O.STEP3_BSGS)])
+def test_shaped_rotation_keys(h, t, beta, mode):
+    """the rotation amounts of a shaped product, built independently: Step 1-1 (unit 1),
+    Step 1-2 (unit h), Steps 2-3 over t rounds (A-side k - s and k - h - s, B0 baby h j and
+    giant h bg i), the fold t h 2^s; all times beta, mod N/2"""
+    c = O.Ctx(14, [40, 40], [50], 1, 30.0, 1)
+    half = c.n // 2
+    b = 2 ** ((int(math.log2(h)) + 1) // 2)
+    bg = min(t, 2 ** ((int(math.log2(t)) + 2) // 2)) if mode & O.STEP3_BSGS else t
+    want = set()
+    for j in range(1, b):
+        want |= {j, h * j}
+    for i in range((1 - h) // b, (h - 1) // b + 1):
+        if i:
+            want.add(b * i)
+    for i in range(1, (h + b - 1) // b):
+        want.add(h * b * i)
+    for k in range(1, t):
+        s = h * bg * (k // bg)
+        want |= {k - s, k - h - s}
+    for j in range(1, bg):
+        want.add(h * j)
+    for i in range(1, t // bg):
+        want.add(h * bg * i)
+    s = 0
+    while (t << s) < h:
+        want.add((t * h) << s)
+        s += 1
+    want = {(beta * x) % half for x in want} - {0}
+    assert sorted(want) == c.matmul_rotations_ex(h, t, beta, mode)
