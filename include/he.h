@@ -151,6 +151,31 @@ he_status he_matmul(he_ctx *ctx, const he_ct *a, const he_ct *b, uint32_t h, he_
 he_status he_matmul_batch(he_ctx *ctx, size_t n, const he_ct *const *a, const he_ct *const *b,
                           const uint32_t *h, he_ct **out);
 
+/* Shape of a packed product (App. D, App. E).  t = h: the square product of he_matmul.
+ * t < h (t divides h): HE-RMatMult (Alg. 6) of a t x h matrix A by an h x h matrix B; the
+ * caller encrypts A~ = h/t vertical copies of A as an h x h matrix, and the result encrypts
+ * h/t vertical copies of the t x h product (Steps 2-3 run t rounds, then log2(h/t) fold
+ * rotations by t h 2^s).  beta > 1: beta matrix pairs per ciphertext pair under the packing
+ * iota_beta (matrix m's entry (i, j) at slot beta (h i + j) + m, the beta h^2 vector
+ * replicated over the slots); every rotation amount is times beta, so one product computes
+ * beta products at the cost of one.  h, t, beta powers of two, beta h^2 <= N/2, else
+ * HE_ESHAPE. */
+typedef struct {
+    uint32_t h, t, beta;
+} he_mat_shape;
+he_status he_matmul_ex(he_ctx *ctx, const he_ct *a, const he_ct *b, const he_mat_shape *shape, he_ct **out);
+/* n products of mixed shapes and levels, grouped by (shape, level) into lockstep groups;
+ * bit-identical to he_matmul_ex on each pair */
+he_status he_matmul_batch_ex(he_ctx *ctx, size_t n, const he_ct *const *a, const he_ct *const *b,
+                             const he_mat_shape *shapes, he_ct **out);
+/* Matrix transposition on packed ciphertexts (App. C): A^T of each of the beta packed h x h
+ * matrices, as the linear transform over the 2h - 1 diagonals (h-1) k with the baby-step/
+ * giant-step split; one level (a Mul_pt and a rescale).  Keys and masks for (h, beta) are made
+ * on first use.  HE_ESHAPE as for he_matmul_ex; HE_ELEVEL at level 0. */
+he_status he_transpose(he_ctx *ctx, const he_ct *a, uint32_t h, uint32_t beta, he_ct **out);
+he_status he_transpose_batch(he_ctx *ctx, size_t n, const he_ct *const *a, uint32_t h, uint32_t beta,
+                             he_ct **out);
+
 /* Composite sign approximation g_d^(k) (Sec. 4.2; Alg. 5 for ReLU):
  * mode 0: g_d applied k times; mode 1: ReLU(x) = (x + x g_d^(k)(x)) / 2.
  * Depth per composition 1 + floor(log2 d) + 1; HE_ELEVEL if the level is too low. */

@@ -458,86 +458,67 @@ static int floordiv_g(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b
 // Phase 0: Step 1-1 and Step 1-2 and the lifts of A0, B0.  Phases 1..: k_chunk rounds
 // of Steps 2-3 each.  Last phase: relinearisation (relin-once schedule) and the final
 // RS.  The phases follow the order of the unphased evaluation exactly.
+// HE-LinTrans (Alg. 2) with the baby-step/giant-step split (App. B) for every member: the sum
+// over diagonals d in [dlo, dhi] of mask_d . R(a, unit d), as
+//   sum_i Rot( sum_j R(mask_{b i + j}, -unit b i) . Rot(a, unit j), unit b i ),
+// under the packing iota_beta (amounts times beta); baby rotations share one lift, giant
+// steps share one ModDown under the hoisting flag.  No rescale.
+Grp Ctx::g_lintrans(const Grp& a, int kind, int h, int beta, int64_t unit, int dlo, int dhi) {
+    const int b = bsgs(h);
+    const double ms = scale;
+    const bool hoist = (schedule & HE_SCHED_HOIST_MODDOWN) != 0;
+    std::vector<Grp> baby(b);
+    baby[0] = a;
+    if (b > 1) {
+        auto lift = g_lift(a, 1);
+        for (int j = 1; j < b; ++j) baby[j] = g_rotate_from_lift(a, lift->p, (int64_t)beta * unit * j);
+    }
+    RotSum gsum;
+    Grp acc;
+    bool have = false;
+    for (int i = floordiv_g(dlo, b); i <= floordiv_g(dhi, b); ++i) {
+        std::vector<std::pair<const Grp*, const u64*>> terms;
+        for (int j = 0; j < b; ++j) {
+            const int d = b * i + j;
+            if (d < dlo || d > dhi) continue;
+            terms.push_back({&baby[j], mask(kind, h, d, -unit * b * i, beta)});
+        }
+        if (terms.empty()) continue;
+        Grp inner = g_mask_sum(terms, ms);
+        const int64_t r = (int64_t)beta * unit * b * i;
+        if (i && hoist) {
+            g_rotsum_add(gsum, inner, r);
+            continue;
+        }
+        if (i) inner = g_rotate(inner, r);
+        if (!have) {
+            acc = inner;
+            have = true;
+        } else {
+            g_add_into(acc, inner);
+        }
+    }
+    if (gsum.u) acc = g_rotsum_finish(gsum, have ? &acc : nullptr);
+    return acc;
+}
+
+// Phase 0: Step 1-1 and Step 1-2 and the lifts of A0, B0.  Phases 1..: k_chunk rounds
+// of Steps 2-3 each (t rounds in all; t < h for HE-RMatMult).  Last phase: the final RS
+// (twice under late rescaling) and, for t < h, the fold of the h/t row blocks (Alg. 6).
+// The phases follow the order of the unphased evaluation exactly.
 bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
-    const int h = J.h, b = bsgs(h);
+    const int h = J.h, t = J.t ? J.t : J.h, beta = J.beta;
     const double ms = scale;
     const bool hoist = (schedule & HE_SCHED_HOIST_MODDOWN) != 0;
     if (J.phase == 0) {
-        RotSum gsum;  // giant steps sharing one ModDown (ModDown hoisting)
         Grp a = g_gather(J.A, J.lvl), bb = g_gather(J.B, J.lvl);
-        // Step 1-1: A0 = sum_i Rot(sum_j R(u_{bi+j}, -bi) . Rot(A, j), b i), then RS
-        {
-            std::vector<Grp> baby(b);
-            baby[0] = a;
-            {
-                auto lift = g_lift(a, 1);
-                for (int j = 1; j < b; ++j) baby[j] = g_rotate_from_lift(a, lift->p, j);
-            }
-            Grp acc;
-            bool have = false;
-            for (int i = floordiv_g(1 - h, b); i <= floordiv_g(h - 1, b); ++i) {
-                std::vector<std::pair<const Grp*, const u64*>> terms;
-                for (int j = 0; j < b; ++j) {
-                    const int k = b * i + j;
-                    if (k <= -h || k >= h) continue;
-                    terms.push_back({&baby[j], mask(0, h, k, -(int64_t)b * i)});
-                }
-                if (terms.empty()) continue;
-                Grp inner = g_mask_sum(terms, ms);
-                if (i && hoist) {
-                    g_rotsum_add(gsum, inner, (int64_t)b * i);
-                    continue;
-                }
-                if (i) inner = g_rotate(inner, (int64_t)b * i);
-                if (!have) {
-                    acc = inner;
-                    have = true;
-                } else {
-                    g_add_into(acc, inner);
-                }
-            }
-            if (gsum.u) {
-                acc = g_rotsum_finish(gsum, have ? &acc : nullptr);
-                have = true;
-            }
-            J.A0 = g_rescale(acc);
-        }
-        // Step 1-2: B0 = sum_i Rot(sum_j R(u_{h(bi+j)}, -h b i) . Rot(B, h j), h b i), then RS
-        {
-            std::vector<Grp> baby(b);
-            baby[0] = bb;
-            {
-                auto lift = g_lift(bb, 1);
-                for (int j = 1; j < b; ++j) baby[j] = g_rotate_from_lift(bb, lift->p, (int64_t)h * j);
-            }
-            Grp acc;
-            bool have = false;
-            for (int i = 0; i * b < h; ++i) {
-                std::vector<std::pair<const Grp*, const u64*>> terms;
-                for (int j = 0; j < b && b * i + j < h; ++j)
-                    terms.push_back({&baby[j], mask(1, h, b * i + j, -(int64_t)h * b * i)});
-                Grp inner = g_mask_sum(terms, ms);
-                if (i && hoist) {
-                    g_rotsum_add(gsum, inner, (int64_t)h * b * i);
-                    continue;
-                }
-                if (i) inner = g_rotate(inner, (int64_t)h * b * i);
-                if (!have) {
-                    acc = inner;
-                    have = true;
-                } else {
-                    g_add_into(acc, inner);
-                }
-            }
-            if (gsum.u) {
-                acc = g_rotsum_finish(gsum, have ? &acc : nullptr);
-                have = true;
-            }
-            J.B0 = g_rescale(acc);
-            // brought to the Step-3 level before its rotations (with late rescaling Step 3
-            // multiplies at this level)
-            if (!(schedule & HE_SCHED_RESCALE_LATE)) J.B0 = g_drop(J.B0, J.B0.level - 1);
-        }
+        // Step 1-1: A0 = U^mu A (diagonals k in (-h, h) at unit 1), then RS
+        J.A0 = g_rescale(g_lintrans(a, 0, h, beta, 1, 1 - h, h - 1));
+        // Step 1-2: B0 = U^zeta B (diagonals h k, k in [0, h)), then RS
+        J.B0 = g_rescale(g_lintrans(bb, 1, h, beta, h, 0, h - 1));
+        // brought to the Step-3 level before its rotations (with late rescaling Step 3
+        // multiplies at this level)
+        if (!(schedule & HE_SCHED_RESCALE_LATE)) J.B0 = g_drop(J.B0, J.B0.level - 1);
         J.liftA = g_lift(J.A0, 1);
         J.liftB = g_lift(J.B0, 1);
         J.k = 0;
@@ -549,23 +530,25 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
         //   A^(k) shifted by s = h bg i: R(v_k, -s) . Rot(A0, k - s) + R(v_{k-h}, -s) . Rot(A0, k - h - s)
         //   (RS unless late), times Rot(B0, h j), summed over j; the block sum is relinearised
         //   (relin-once) and rotated by s
-        const int bg = step3_baby(h);
-        const bool keep_baby = bg < h;
+        const int bg = step3_baby(t);
+        const bool keep_baby = bg < t;
         if (keep_baby && J.babyB.empty()) J.babyB.resize(bg);
-        const int kend = std::min(h, J.k + std::max(1, k_chunk));
+        const int kend = std::min(t, J.k + std::max(1, k_chunk));
         for (int k = J.k; k < kend; ++k) {
             const int i = k / bg, j = k % bg;
             const int64_t shift = (int64_t)h * bg * i;
             Grp Ak;
             if (k == 0) {
-                Ak = g_mask_sum({{&J.A0, mask(2, h, 0, 0)}}, ms);
+                Ak = g_mask_sum({{&J.A0, mask(2, h, 0, 0, beta)}}, ms);
             } else if (hoist) {
-                Ak = g_rotate_pair_hoisted(J.A0, J.liftA->p, k - shift, mask(2, h, k, -shift), k - h - shift,
-                                           mask(3, h, k, -shift), ms);
+                Ak = g_rotate_pair_hoisted(J.A0, J.liftA->p, beta * (k - shift), mask(2, h, k, -shift, beta),
+                                           beta * (k - h - shift), mask(3, h, k, -shift, beta), ms);
             } else {
                 // masks applied in the ModDown epilogues
-                Grp t1 = g_rotate_mask_from_lift(J.A0, J.liftA->p, k - shift, mask(2, h, k, -shift), ms, nullptr);
-                Ak = g_rotate_mask_from_lift(J.A0, J.liftA->p, k - h - shift, mask(3, h, k, -shift), ms, &t1);
+                Grp t1 = g_rotate_mask_from_lift(J.A0, J.liftA->p, beta * (k - shift), mask(2, h, k, -shift, beta), ms,
+                                                 nullptr);
+                Ak = g_rotate_mask_from_lift(J.A0, J.liftA->p, beta * (k - h - shift), mask(3, h, k, -shift, beta), ms,
+                                             &t1);
             }
             if (!(schedule & HE_SCHED_RESCALE_LATE)) Ak = g_rescale(Ak);
             Grp Bj;
@@ -574,7 +557,7 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
             } else if (i > 0) {
                 Bj = J.babyB[j];
             } else {
-                Bj = g_rotate_from_lift(J.B0, J.liftB->p, (int64_t)h * j);
+                Bj = g_rotate_from_lift(J.B0, J.liftB->p, (int64_t)beta * h * j);
                 if (keep_baby) J.babyB[j] = Bj;
             }
             if (!(schedule & HE_SCHED_RELIN_ONCE)) {
@@ -593,16 +576,16 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
                     g_tensor_acc(J.S, Ak, Bj);
                 }
             }
-            if (j == bg - 1 || k == h - 1) {
+            if (j == bg - 1 || k == t - 1) {
                 Grp blk = J.S;
                 J.S = Grp();
                 J.haveS = false;
                 if (schedule & HE_SCHED_RELIN_ONCE) blk = g_relin(blk);
                 if (i > 0 && hoist) {
-                    g_rotsum_add(J.giant, blk, shift);
+                    g_rotsum_add(J.giant, blk, beta * shift);
                     continue;
                 }
-                if (i > 0) blk = g_rotate(blk, shift);
+                if (i > 0) blk = g_rotate(blk, beta * shift);
                 if (!J.have) {
                     J.acc = blk;
                     J.have = true;
@@ -612,7 +595,7 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
             }
         }
         J.k = kend;
-        if (J.k == h) {
+        if (J.k == t) {
             J.liftA.reset();
             J.liftB.reset();
             J.A0 = Grp();
@@ -625,6 +608,11 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
     if (J.giant.u) J.acc = g_rotsum_finish(J.giant, J.have ? &J.acc : nullptr);
     J.acc = g_rescale(J.acc);
     if (schedule & HE_SCHED_RESCALE_LATE) J.acc = g_rescale(J.acc);
+    // Alg. 6's last loop: fold the h/t row blocks of t rows (after the rescales: fewer limbs)
+    for (int sh = 0; (t << sh) < h; ++sh) {
+        Grp r = g_rotate(J.acc, ((int64_t)beta * t * h) << sh);
+        g_add_into(J.acc, r);
+    }
     J.result = g_scatter(J.acc);
     J.acc = Grp();
     J.phase = 3;
@@ -632,13 +620,15 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
 }
 
 std::vector<CtPtr> Ctx::matmul_group(const std::vector<const CtData*>& A, const std::vector<const CtData*>& Bv,
-                                     int h, int lvl) {
+                                     const MatShape& sh, int lvl) {
     MatmulJob J;
     J.A = A;
     J.B = Bv;
-    J.h = h;
+    J.h = sh.h;
+    J.t = sh.t;
+    J.beta = sh.beta;
     J.lvl = lvl;
-    while (!matmul_step(J, h)) {
+    while (!matmul_step(J, sh.h)) {
     }
     return J.result;
 }
@@ -804,31 +794,25 @@ std::vector<CtPtr> Ctx::sign_group(const std::vector<const CtData*>& X, int d, i
 }
 
 CtPtr Ctx::matmul(const CtData& A, const CtData& B, int h) {
-    if ((h & (h - 1)) || h < 1 || (int64_t)h * h > N / 2) throw HeError(HE_ESHAPE);
-    if (A.deg != 1 || B.deg != 1) throw HeError(HE_EMISMATCH);
-    const int lvl = std::min(A.level, B.level);
-    if (lvl < 3) throw HeError(HE_ELEVEL);
-    prepare_h(h);
-    return matmul_group({&A}, {&B}, h, lvl)[0];
+    return matmul_batch({&A}, {&B}, {MatShape{h, h, 1}})[0];
 }
 
-// Members are grouped by (h, level); each group runs in lockstep.  Group size is
+// Members are grouped by (shape, level); each group runs in lockstep.  Group size is
 // capped so the working set (about 12 ciphertext-sized blocks per member plus two
 // lifted-digit blocks) stays well inside HBM.
 std::vector<CtPtr> Ctx::matmul_batch(const std::vector<const CtData*>& A, const std::vector<const CtData*>& B,
-                                     const std::vector<int>& h) {
+                                     const std::vector<MatShape>& shapes) {
     const size_t n = A.size();
     std::vector<CtPtr> out(n);
-    std::map<std::pair<int, int>, std::vector<size_t>> groups;
+    std::map<std::pair<MatShape, int>, std::vector<size_t>> groups;
     for (size_t i = 0; i < n; ++i) {
-        const int hh = h[i];
-        if ((hh & (hh - 1)) || hh < 1 || (int64_t)hh * hh > N / 2) throw HeError(HE_ESHAPE);
+        check_shape(shapes[i]);
         if (A[i]->deg != 1 || B[i]->deg != 1) throw HeError(HE_EMISMATCH);
         const int lvl = std::min(A[i]->level, B[i]->level);
         if (lvl < 3) throw HeError(HE_ELEVEL);
-        groups[{hh, lvl}].push_back(i);
+        groups[{shapes[i], lvl}].push_back(i);
     }
-    for (auto& kv : groups) prepare_h(kv.first.first);
+    for (auto& kv : groups) prepare_shape(kv.first.first);
     const size_t cap = (size_t)std::max(1, max_group);
     for (auto& kv : groups) {
         const auto& idx = kv.second;
@@ -839,6 +823,30 @@ std::vector<CtPtr> Ctx::matmul_batch(const std::vector<const CtData*>& A, const 
                 b.push_back(B[idx[t]]);
             }
             auto r = matmul_group(a, b, kv.first.first, kv.first.second);
+            for (size_t t = 0; t < r.size(); ++t) out[idx[s + t]] = r[t];
+        }
+    }
+    return out;
+}
+
+// App. C for every member (grouped by level): the transpose of each packed h x h matrix,
+// one linear transform with BSGS, then RS
+std::vector<CtPtr> Ctx::transpose_batch(const std::vector<const CtData*>& X, int h, int beta) {
+    prepare_transpose(h, beta);
+    std::map<int, std::vector<size_t>> groups;
+    for (size_t i = 0; i < X.size(); ++i) {
+        if (X[i]->deg != 1) throw HeError(HE_EMISMATCH);
+        if (X[i]->level < 1) throw HeError(HE_ELEVEL);
+        groups[X[i]->level].push_back(i);
+    }
+    std::vector<CtPtr> out(X.size());
+    const size_t cap = (size_t)std::max(1, max_group);
+    for (auto& kv : groups) {
+        const auto& idx = kv.second;
+        for (size_t s = 0; s < idx.size(); s += cap) {
+            std::vector<const CtData*> v;
+            for (size_t t = s; t < std::min(idx.size(), s + cap); ++t) v.push_back(X[idx[t]]);
+            auto r = g_scatter(g_rescale(g_lintrans(g_gather(v, kv.first), 4, h, beta, h - 1, 1 - h, h - 1)));
             for (size_t t = 0; t < r.size(); ++t) out[idx[s + t]] = r[t];
         }
     }

@@ -808,14 +808,17 @@ static void mask_slots(int kind, int h, int k, std::vector<double>& out) {
                 break;
             case 1: v = (t % h) == k; break;      // u^zeta_{h k}
             case 2: v = (t % h) < h - k; break;   // v_k (all ones for k = 0)
-            default: v = (t % h) >= h - k; break; // v_{k-h}
+            case 3: v = (t % h) >= h - k; break;  // v_{k-h}
+            default:  // App. C: diagonal (h-1) k of the transpose map (output h i + j reads h j + i)
+                v = (t % h) - (t / h) == k;
+                break;
         }
         out[t] = v ? 1.0 : 0.0;
     }
 }
 
-const u64* Ctx::mask(int kind, int h, int k, int64_t rot) {
-    const MaskKey key{kind, h, k, rot};
+const u64* Ctx::mask(int kind, int h, int k, int64_t rot, int beta) {
+    const MaskKey key{kind, h, beta, k, rot};
     auto it = masks.find(key);
     if (it != masks.end()) return it->second->p;
     prepare_masks({key});
@@ -837,9 +840,13 @@ void Ctx::prepare_masks(const std::vector<MaskKey>& keys) {
                 const MaskKey& m = todo[i];
                 mask_slots(m.kind, m.h, m.k, u);
                 const int n = m.h * m.h;
-                ur.resize(n);
-                for (int t = 0; t < n; ++t) ur[t] = u[(size_t)((((t + m.rot) % n) + n) % n)];  // R(u, rot)
-                enc.encode(ur.data(), n, scale, coeffs[i].data());
+                // R(u, rot), each entry repeated beta times (packing iota_beta: entry t of every
+                // matrix sits at slots beta t .. beta t + beta - 1)
+                ur.resize((size_t)n * m.beta);
+                for (int t = 0; t < n; ++t)
+                    for (int e = 0; e < m.beta; ++e)
+                        ur[(size_t)m.beta * t + e] = u[(size_t)((((t + m.rot) % n) + n) % n)];
+                enc.encode(ur.data(), (int64_t)n * m.beta, scale, coeffs[i].data());
             }
         });
     for (auto& t : th) t.join();
@@ -863,55 +870,90 @@ int Ctx::step3_baby(int h) const {
     return std::min(h, 1 << ((ilog2i(h) + 2) / 2));
 }
 
-std::vector<MaskKey> Ctx::matmul_masks(int h) const {
+// masks of HE-LinTrans with BSGS over diagonals [dlo, dhi] at unit u: R(mask_d, -u b floor(d/b))
+static void lintrans_masks(std::vector<MaskKey>& out, int kind, int h, int beta, int64_t unit, int dlo, int dhi,
+                           int b) {
+    for (int d = dlo; d <= dhi; ++d) out.push_back({kind, h, beta, d, -unit * b * floordiv(d, b)});
+}
+// rotation amounts of the same: baby steps u j, giant steps u b i (i != 0)
+static void lintrans_rotations(std::vector<int64_t>& r, int b, int64_t unit, int dlo, int dhi) {
+    for (int j = 1; j < b; ++j) r.push_back(unit * j);
+    for (int i = floordiv(dlo, b); i <= floordiv(dhi, b); ++i)
+        if (i) r.push_back(unit * b * i);
+}
+
+void Ctx::check_shape(const MatShape& s) const {
+    const auto pow2 = [](int x) { return x >= 1 && !(x & (x - 1)); };
+    if (!pow2(s.h) || !pow2(s.t) || s.t > s.h || !pow2(s.beta) || (int64_t)s.beta * s.h * s.h > N / 2)
+        throw HeError(HE_ESHAPE);
+}
+
+std::vector<MaskKey> Ctx::matmul_masks(const MatShape& s) const {
     std::vector<MaskKey> out;
-    const int b = bsgs(h);
-    for (int i = floordiv(1 - h, b); i <= floordiv(h - 1, b); ++i)
-        for (int j = 0; j < b; ++j) {
-            const int k = b * i + j;
-            if (k > -h && k < h) out.push_back({0, h, k, -(int64_t)b * i});
-        }
-    for (int i = 0; i * b < h; ++i)
-        for (int j = 0; j < b && b * i + j < h; ++j) out.push_back({1, h, b * i + j, -(int64_t)h * b * i});
-    out.push_back({2, h, 0, 0});
-    const int bg = step3_baby(h);
-    for (int k = 1; k < h; ++k) {
+    const int h = s.h, b = bsgs(h), bg = step3_baby(s.t);
+    lintrans_masks(out, 0, h, s.beta, 1, 1 - h, h - 1, b);
+    lintrans_masks(out, 1, h, s.beta, h, 0, h - 1, b);
+    out.push_back({2, h, s.beta, 0, 0});
+    for (int k = 1; k < s.t; ++k) {
         const int64_t shift = (int64_t)h * bg * (k / bg);
-        out.push_back({2, h, k, -shift});
-        out.push_back({3, h, k, -shift});
+        out.push_back({2, h, s.beta, k, -shift});
+        out.push_back({3, h, s.beta, k, -shift});
     }
     return out;
 }
 
-std::vector<int64_t> Ctx::matmul_rotations(int h) const {
-    const int b = bsgs(h);
+// amounts before the packing factor; every amount is multiplied by beta
+std::vector<int64_t> Ctx::matmul_rotations(const MatShape& s) const {
+    const int h = s.h, t = s.t, b = bsgs(h), bg = step3_baby(t);
     std::vector<int64_t> r;
-    for (int j = 1; j < b; ++j) r.push_back(j);
-    for (int i = floordiv(1 - h, b); i <= floordiv(h - 1, b); ++i)
-        if (i) r.push_back((int64_t)b * i);
-    for (int j = 1; j < b; ++j) r.push_back((int64_t)h * j);
-    for (int i = 1; i * b < h; ++i) r.push_back((int64_t)h * b * i);
-    const int bg = step3_baby(h);
-    for (int k = 1; k < h; ++k) {
+    lintrans_rotations(r, b, 1, 1 - h, h - 1);
+    lintrans_rotations(r, b, h, 0, h - 1);
+    for (int k = 1; k < t; ++k) {
         const int64_t shift = (int64_t)h * bg * (k / bg);
         r.push_back(k - shift);
         r.push_back(k - h - shift);
     }
     for (int j = 1; j < bg; ++j) r.push_back((int64_t)h * j);
-    for (int i = 1; i * bg < h; ++i) r.push_back((int64_t)h * bg * i);
+    for (int i = 1; i * bg < t; ++i) r.push_back((int64_t)h * bg * i);
+    for (int sh = 0; (t << sh) < h; ++sh) r.push_back(((int64_t)t * h) << sh);
+    for (auto& v : r) v *= s.beta;
     return r;
 }
 
-void Ctx::prepare_h(int h) {
-    if ((h & (h - 1)) || h < 1 || (int64_t)h * h > N / 2) throw HeError(HE_ESHAPE);
-    if (prepared_h.count(h)) return;
-    for (int64_t k : matmul_rotations(h)) rot_key(galois(k), true);
-    prepare_masks(matmul_masks(h));
-    hip_check(hipStreamSynchronize(stream), "prepare_h");
-    prepared_h.insert(h);
-    int lg = 0;
-    while ((1 << lg) < h) ++lg;
-    prepared_mask.fetch_or(1u << lg);
+std::vector<MaskKey> Ctx::transpose_masks(int h, int beta) const {
+    std::vector<MaskKey> out;
+    lintrans_masks(out, 4, h, beta, h - 1, 1 - h, h - 1, bsgs(h));
+    return out;
+}
+
+std::vector<int64_t> Ctx::transpose_rotations(int h, int beta) const {
+    std::vector<int64_t> r;
+    lintrans_rotations(r, bsgs(h), h - 1, 1 - h, h - 1);
+    for (auto& v : r) v *= beta;
+    return r;
+}
+
+void Ctx::prepare_shape(const MatShape& s) {
+    check_shape(s);
+    if (prepared.count(s)) return;
+    for (int64_t k : matmul_rotations(s)) rot_key(galois(k), true);
+    prepare_masks(matmul_masks(s));
+    hip_check(hipStreamSynchronize(stream), "prepare_shape");
+    prepared.insert(s);
+    if (s.t == s.h && s.beta == 1) {
+        int lg = 0;
+        while ((1 << lg) < s.h) ++lg;
+        prepared_mask.fetch_or(1u << lg);
+    }
+}
+
+void Ctx::prepare_transpose(int h, int beta) {
+    check_shape(MatShape{h, h, beta});
+    if (prepared_tr.count({h, beta})) return;
+    for (int64_t k : transpose_rotations(h, beta)) rot_key(galois(k), true);
+    prepare_masks(transpose_masks(h, beta));
+    hip_check(hipStreamSynchronize(stream), "prepare_transpose");
+    prepared_tr.insert({h, beta});
 }
 
 // ====================================================================== C ABI
@@ -1188,7 +1230,48 @@ he_status he_matmul_batch(he_ctx* ctx, size_t n, const he_ct* const* a, const he
             vb[i] = b[i]->c.get();
             vh[i] = (int)h[i];
         }
-        auto res = ctx->c->matmul_batch(va, vb, vh);
+        std::vector<MatShape> sh(n);
+        for (size_t i = 0; i < n; ++i) sh[i] = MatShape{vh[i], vh[i], 1};
+        auto res = ctx->c->matmul_batch(va, vb, sh);
+        for (size_t i = 0; i < n; ++i) out[i] = wrap(ctx->c.get(), res[i]);
+    });
+}
+he_status he_matmul_ex(he_ctx* ctx, const he_ct* a, const he_ct* b, const he_mat_shape* shape, he_ct** out) {
+    return he_matmul_batch_ex(ctx, 1, &a, &b, shape, out);
+}
+he_status he_matmul_batch_ex(he_ctx* ctx, size_t n, const he_ct* const* a, const he_ct* const* b,
+                             const he_mat_shape* shapes, he_ct** out) {
+    if (!ctx || (n && (!a || !b || !shapes || !out))) return HE_EINVAL;
+    for (size_t i = 0; i < n; ++i) {
+        if (!a[i] || !b[i]) return HE_EINVAL;
+        if (a[i]->ctx != ctx->c.get() || b[i]->ctx != ctx->c.get()) return HE_EMISMATCH;
+    }
+    return guardc(ctx, [&]() {
+        std::vector<const CtData*> va(n), vb(n);
+        std::vector<MatShape> sh(n);
+        for (size_t i = 0; i < n; ++i) {
+            va[i] = a[i]->c.get();
+            vb[i] = b[i]->c.get();
+            sh[i] = MatShape{(int)shapes[i].h, (int)shapes[i].t, (int)shapes[i].beta};
+        }
+        auto res = ctx->c->matmul_batch(va, vb, sh);
+        for (size_t i = 0; i < n; ++i) out[i] = wrap(ctx->c.get(), res[i]);
+    });
+}
+he_status he_transpose(he_ctx* ctx, const he_ct* a, uint32_t h, uint32_t beta, he_ct** out) {
+    return he_transpose_batch(ctx, 1, &a, h, beta, out);
+}
+he_status he_transpose_batch(he_ctx* ctx, size_t n, const he_ct* const* a, uint32_t h, uint32_t beta,
+                             he_ct** out) {
+    if (!ctx || (n && (!a || !out))) return HE_EINVAL;
+    for (size_t i = 0; i < n; ++i) {
+        if (!a[i]) return HE_EINVAL;
+        if (a[i]->ctx != ctx->c.get()) return HE_EMISMATCH;
+    }
+    return guardc(ctx, [&]() {
+        std::vector<const CtData*> va(n);
+        for (size_t i = 0; i < n; ++i) va[i] = a[i]->c.get();
+        auto res = ctx->c->transpose_batch(va, (int)h, (int)beta);
         for (size_t i = 0; i < n; ++i) out[i] = wrap(ctx->c.get(), res[i]);
     });
 }

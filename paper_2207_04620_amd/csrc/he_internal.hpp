@@ -6,6 +6,7 @@
 #include <map>
 #include <mutex>
 #include <set>
+#include <tuple>
 #include <memory>
 #include <unordered_map>
 #include <vector>
@@ -79,7 +80,7 @@ struct RotSum {
 // resumable state of one lockstep product group
 struct MatmulJob {
     std::vector<const CtData*> A, B;
-    int h = 0, lvl = 0, phase = 0, k = 0;
+    int h = 0, t = 0, beta = 1, lvl = 0, phase = 0, k = 0;  // t: Step-2/3 rounds (h, or t < h)
     Grp A0, B0, acc, S;   // S: the current Step-3 block sum
     bool have = false, haveS = false;
     std::vector<Grp> babyB;  // Rot(B0, h j), j < bg, kept across blocks (Step-3 split)
@@ -102,16 +103,24 @@ struct ModUpInfo {
     u64 hinv[HE_MAXSRC] = {0}, hinv_sh[HE_MAXSRC] = {0};
 };
 
+// a diagonal mask: kind (Alg. 3 / App. C diagonal family), side h, packing beta (App. E),
+// diagonal index k, pre-rotation rot (positions of the h^2 vector)
 struct MaskKey {
-    int kind, h, k;
+    int kind, h, beta, k;
     int64_t rot;
     bool operator<(const MaskKey& o) const {
-        if (kind != o.kind) return kind < o.kind;
-        if (h != o.h) return h < o.h;
-        if (k != o.k) return k < o.k;
-        return rot < o.rot;
+        return std::tie(kind, h, beta, k, rot) < std::tie(o.kind, o.h, o.beta, o.k, o.rot);
     }
-    bool operator==(const MaskKey& o) const { return kind == o.kind && h == o.h && k == o.k && rot == o.rot; }
+    bool operator==(const MaskKey& o) const {
+        return kind == o.kind && h == o.h && beta == o.beta && k == o.k && rot == o.rot;
+    }
+};
+
+// shape of a packed product: h x h (t = h, Alg. 3) or t x h by h x h (t < h, HE-RMatMult,
+// App. D), beta matrix pairs per ciphertext pair (iota_beta, App. E)
+struct MatShape {
+    int h = 0, t = 0, beta = 1;
+    bool operator<(const MatShape& o) const { return std::tie(h, t, beta) < std::tie(o.h, o.t, o.beta); }
 };
 
 struct Ctx {
@@ -138,7 +147,8 @@ struct Ctx {
     std::map<u64, std::unique_ptr<DBuf>> rot_keys;
     std::map<MaskKey, std::unique_ptr<DBuf>> masks;
     size_t keys_bytes = 0;
-    std::set<int> prepared_h;
+    std::set<MatShape> prepared;                // shapes whose rotation keys and masks exist
+    std::set<std::pair<int, int>> prepared_tr;  // (h, beta) of transposes
     std::atomic<uint32_t> prepared_mask{0};  // bit log2(h) set once keys and masks for h exist
     int64_t cnt[6] = {0, 0, 0, 0, 0, 0};
 
@@ -169,16 +179,22 @@ struct Ctx {
     std::unique_ptr<DBuf> plaintext_mont(const int64_t* coeffs);
     CtPtr mask_sum(const std::vector<std::pair<const CtData*, const u64*>>& terms, double mask_scale);
 
-    const u64* mask(int kind, int h, int k, int64_t rot);
+    const u64* mask(int kind, int h, int k, int64_t rot, int beta = 1);
     void prepare_masks(const std::vector<MaskKey>& keys);
     int bsgs(int h) const;
     int step3_baby(int h) const;
-    std::vector<MaskKey> matmul_masks(int h) const;
-    std::vector<int64_t> matmul_rotations(int h) const;
-    void prepare_h(int h);
+    std::vector<MaskKey> matmul_masks(const MatShape& s) const;
+    std::vector<int64_t> matmul_rotations(const MatShape& s) const;
+    std::vector<MaskKey> transpose_masks(int h, int beta) const;
+    std::vector<int64_t> transpose_rotations(int h, int beta) const;
+    void check_shape(const MatShape& s) const;
+    void prepare_shape(const MatShape& s);
+    void prepare_h(int h) { prepare_shape(MatShape{h, h, 1}); }
+    void prepare_transpose(int h, int beta);
     CtPtr matmul(const CtData& A, const CtData& B, int h);
     std::vector<CtPtr> matmul_batch(const std::vector<const CtData*>& A, const std::vector<const CtData*>& B,
-                                    const std::vector<int>& h);
+                                    const std::vector<MatShape>& shapes);
+    std::vector<CtPtr> transpose_batch(const std::vector<const CtData*>& X, int h, int beta);
     int max_group = 32;
 
     // lockstep group operations (group.hip)
@@ -209,8 +225,9 @@ struct Ctx {
     Grp g_tensor(const Grp& a, const Grp& b);
     void g_tensor_acc(Grp& acc, const Grp& a, const Grp& b);
     Grp g_relin(const Grp& a);
-    std::vector<CtPtr> matmul_group(const std::vector<const CtData*>& A, const std::vector<const CtData*>& B, int h,
-                                    int lvl);
+    Grp g_lintrans(const Grp& a, int kind, int h, int beta, int64_t unit, int dlo, int dhi);
+    std::vector<CtPtr> matmul_group(const std::vector<const CtData*>& A, const std::vector<const CtData*>& B,
+                                    const MatShape& s, int lvl);
     bool matmul_step(MatmulJob& J, int k_chunk);
     Grp g_mul_int(const Grp& a, const std::vector<int64_t>& k);
     Grp g_mul_rs(const Grp& x, const Grp& y);

@@ -92,6 +92,12 @@ SIGNATURES = {
     "he_matmul": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(C.c_void_p)]),
     "he_matmul_batch": (C.c_int, [C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                   C.POINTER(C.c_uint32), C.POINTER(C.c_void_p)]),
+    "he_matmul_ex": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "he_matmul_batch_ex": (C.c_int, [C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                     C.c_void_p, C.POINTER(C.c_void_p)]),
+    "he_transpose": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.POINTER(C.c_void_p)]),
+    "he_transpose_batch": (C.c_int, [C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p), C.c_uint32, C.c_uint32,
+                                     C.POINTER(C.c_void_p)]),
     "he_sign_approx": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32,
                                  C.POINTER(C.c_void_p)]),
     "he_sign_approx_batch": (C.c_int, [C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p), C.c_uint32, C.c_uint32,
@@ -167,6 +173,21 @@ class Ciphertext:
     @property
     def scale(self):
         return self.info()[2]
+
+
+class _MatShape(C.Structure):
+    _fields_ = [("h", C.c_uint32), ("t", C.c_uint32), ("beta", C.c_uint32)]
+
+
+def pack_beta(mats):
+    """the packing iota_beta (App. E) as a slot vector: matrix m's entry (i, j) at
+    position beta (h i + j) + m"""
+    mats = [np.asarray(m, np.float64) for m in mats]
+    beta = len(mats)
+    v = np.empty(beta * mats[0].size)
+    for m, M in enumerate(mats):
+        v[m::beta] = M.ravel()
+    return v
 
 
 class Context:
@@ -315,6 +336,30 @@ class Context:
         ph = (C.c_uint32 * n)(*[int(h) for h in hs])
         out = (C.c_void_p * n)()
         _chk(lib().he_matmul_batch(self.ptr, n, pa, pb, ph, out), "he_matmul_batch")
+        return [Ciphertext(self, out[i]) for i in range(n)]
+
+    def matmul_ex(self, a, b, h, t=None, beta=1):
+        """HE-MatMult (t = h) / HE-RMatMult (t < h, a holds h/t copies of a t x h matrix) on
+        beta matrix pairs packed by iota_beta"""
+        return self.matmul_batch_ex([a], [b], [(h, h if t is None else t, beta)])[0]
+
+    def matmul_batch_ex(self, As, Bs, shapes):
+        n = len(As)
+        pa = (C.c_void_p * n)(*[x.ptr for x in As])
+        pb = (C.c_void_p * n)(*[x.ptr for x in Bs])
+        sh = (_MatShape * n)(*[_MatShape(int(h), int(t), int(bt)) for h, t, bt in shapes])
+        out = (C.c_void_p * n)()
+        _chk(lib().he_matmul_batch_ex(self.ptr, n, pa, pb, sh, out), "he_matmul_batch_ex")
+        return [Ciphertext(self, out[i]) for i in range(n)]
+
+    def transpose(self, a, h, beta=1):
+        return self.transpose_batch([a], h, beta)[0]
+
+    def transpose_batch(self, xs, h, beta=1):
+        n = len(xs)
+        px = (C.c_void_p * n)(*[x.ptr for x in xs])
+        out = (C.c_void_p * n)()
+        _chk(lib().he_transpose_batch(self.ptr, n, px, int(h), int(beta), out), "he_transpose_batch")
         return [Ciphertext(self, out[i]) for i in range(n)]
 
     def sign_approx(self, x, d, k, mode=SIGN):

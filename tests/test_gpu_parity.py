@@ -421,3 +421,71 @@ def test_c4_sign_relu_then_h32_matmul(he):
     assert np.array_equal(g.export(ms[0]), om.export())
     _log("[parity] C4: bit-exact")
     g.close()
+
+
+# ---------------------------------------------------------------- App. C, D, E
+def _packed(beta, h, seed):
+    rng = np.random.default_rng(seed)
+    return [rng.uniform(-1.0, 1.0, (h, h)) for _ in range(beta)]
+
+
+@pytest.mark.parametrize("schedule", [0, 15])
+def test_transpose_rect_packed_parity(he, schedule):
+    """transposition (App. C), HE-RMatMult (Alg. 6) and iota_beta packing (App. E) on a 2^12
+    ring: every result against the oracle on every residue (same schedule flags), decrypting
+    to the FP64 transpose / product; mixed shapes in one batch equal their single runs"""
+    prm = I.small(log_n=12, n_q=6, alpha=2, q_bits=40, p_bits=50)
+    p = Pair(he, prm, h_list=[], schedule=schedule)
+    H = he
+    for h, beta in ((4, 1), (8, 1), (16, 1), (8, 4), (4, 8)):
+        _log(f"[parity] transpose h={h} beta={beta} schedule={schedule}")
+        mats = _packed(beta, h, 10 * h + beta)
+        v = H.pack_beta(mats)
+        g = p.g.transpose(p.g.encrypt(v, nonce=5), h, beta)
+        o = p.o.transpose(p.o.encrypt(v, nonce=5), h, beta, schedule)
+        p.same(g, o)
+        got = p.g.decrypt(g, beta * h * h)
+        for m in range(beta):
+            assert np.abs(got[m::beta].reshape(h, h) - mats[m].T).max() < 1e-6
+    shapes = [(8, 2, 1), (16, 4, 1), (16, 1, 1), (8, 8, 4), (8, 4, 2), (4, 4, 8)]
+    As, Bs, want, sing = [], [], [], []
+    for n_, (h, t, beta) in enumerate(shapes):
+        _log(f"[parity] shaped product h={h} t={t} beta={beta} schedule={schedule}")
+        rng = np.random.default_rng(100 + n_)
+        A = [rng.uniform(-1, 1, (t, h)) for _ in range(beta)]
+        B = [rng.uniform(-1, 1, (h, h)) for _ in range(beta)]
+        va = H.pack_beta([np.tile(x, (h // t, 1)) for x in A])
+        vb = H.pack_beta(B)
+        ga, gb = p.g.encrypt(va, nonce=2 * n_), p.g.encrypt(vb, nonce=2 * n_ + 1)
+        g = p.g.matmul_ex(ga, gb, h, t, beta)
+        o = p.o.matmul_ex(p.o.encrypt(va, nonce=2 * n_), p.o.encrypt(vb, nonce=2 * n_ + 1), h, t, beta, schedule)
+        p.same(g, o)
+        got = p.g.decrypt(g, beta * h * h)
+        for m in range(beta):
+            M = got[m::beta].reshape(h, h)
+            for blk in range(h // t):
+                assert np.abs(M[blk * t:(blk + 1) * t] - A[m] @ B[m]).max() < 1e-3
+        As.append(ga), Bs.append(gb), sing.append(p.g.export(g))
+    batch = p.g.matmul_batch_ex(As, Bs, shapes)
+    for r, s_ in zip(batch, sing):
+        assert np.array_equal(p.g.export(r), s_)
+
+
+def test_c3_packed_h64_beta4_full_size(he):
+    """four h=64 products in one ciphertext pair on the N=2^15 ring (iota_4 fills all 16384
+    slots): against the oracle on every residue under the headline schedule, and each of the
+    four products within 1e-5 of FP64"""
+    prm = I.C3
+    g = he.Context(prm, h_list=[], schedule=15)
+    As, Bs = _packed(4, 64, 31), _packed(4, 64, 32)
+    va, vb = he.pack_beta(As), he.pack_beta(Bs)
+    _log("[parity] C3 packed beta=4 h=64: GPU")
+    gm = g.matmul_ex(g.encrypt(va, nonce=1), g.encrypt(vb, nonce=2), 64, 64, 4)
+    got = g.decrypt(gm, 4 * 4096)
+    for m in range(4):
+        assert np.abs(got[m::4].reshape(64, 64) - As[m] @ Bs[m]).max() < 1e-5
+    _log("[parity] C3 packed beta=4 h=64: oracle")
+    o = O.Ctx.from_params(prm)
+    om = o.matmul_ex(o.encrypt(va, nonce=1), o.encrypt(vb, nonce=2), 64, 64, 4, 15)
+    assert np.array_equal(g.export(gm), om.export())
+    g.close()
