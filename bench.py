@@ -252,6 +252,38 @@ def serve_rings_leg(he, I, sched, nreq, load):
             "burst_capacity_per_s": round(capacity, 1), "poisson": runs}
 
 
+def shapes_leg(he, I, prm, sched, stream, batch):
+    """The other matrix operations of the paper on the same ring, each a batch of 'batch'
+    independent ciphertexts: four h=64 products packed per ciphertext pair (iota_4, App. E),
+    a 16 x 64 by 64 x 64 product (HE-RMatMult, Alg. 6), and h=64 transposition (App. C)."""
+    ctx = he.Context(prm, h_list=[], stream=stream.cuda_stream, schedule=sched)
+    out = {}
+    rng = np.random.default_rng(6)
+    packed = [(he.pack_beta([rng.uniform(-1, 1, (64, 64)) for _ in range(4)]),
+               he.pack_beta([rng.uniform(-1, 1, (64, 64)) for _ in range(4)])) for _ in range(4)]
+    As = [ctx.encrypt(packed[i % 4][0], nonce=2 * i) for i in range(batch)]
+    Bs = [ctx.encrypt(packed[i % 4][1], nonce=2 * i + 1) for i in range(batch)]
+    for name, shape, count in (("packed_beta4_h64", (64, 64, 4), 4), ("rect_t16_h64", (64, 16, 1), 1)):
+        ctx.matmul_batch_ex(As, Bs, [shape] * batch)
+        ctx.sync()
+        t0 = time.perf_counter()
+        ctx.matmul_batch_ex(As, Bs, [shape] * batch)
+        ctx.sync()
+        dt = time.perf_counter() - t0
+        out[name] = {"ciphertext_products_per_s": round(batch / dt, 2),
+                     "matrix_products_per_s": round(batch * count / dt, 2), "ms_per_batch": round(dt * 1e3, 1)}
+    ctx.transpose_batch(As, 64, 1)
+    ctx.sync()
+    t0 = time.perf_counter()
+    ctx.transpose_batch(As, 64, 1)
+    ctx.sync()
+    dt = time.perf_counter() - t0
+    out["transpose_h64"] = {"transposes_per_s": round(batch / dt, 2), "ms_per_batch": round(dt * 1e3, 1)}
+    ctx.close()
+    out["batch"] = batch
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,6 +300,7 @@ def main():
     ap.add_argument("--mix", type=int, default=256, help="mixed-batch products (0: skip)")
     ap.add_argument("--c4", type=int, default=128, help="ciphertexts of the N=2^16 ReLU + h=32 leg (0: skip)")
     ap.add_argument("--serve-rings", type=int, default=300, help="requests of the cross-ring serving leg (0: skip)")
+    ap.add_argument("--no-shapes", action="store_true", help="skip the packed / rectangular / transpose leg")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / batched capacity")
     ap.add_argument("--serve-min-batch", type=int, default=8)
@@ -449,6 +482,10 @@ def main():
         "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
                         **({"GB/s": hbm[k]} if k in hbm else {})} for k, v in prof.items()},
     }
+    if not args.no_shapes:
+        log("packed (iota_4), rectangular (16 x 64) and transposition legs")
+        result["shapes"] = shapes_leg(he, I, prm, sched, stream, args.batch)
+        log(f"shapes: {result['shapes']}")
     if args.mix > 0:
         log(f"mixed batch of {args.mix} (h in 16/32/64, levels 3..13)")
         result["mixed_batch"] = mixed_leg(he, I, prm, sched, stream, args.mix)
