@@ -80,7 +80,9 @@ typedef struct {
     const uint32_t *q_bits;  /* bit size of each Q prime, q_0 first (<= 60) */
     uint32_t n_p;            /* special primes K */
     const uint32_t *p_bits;  /* bit size of each special prime (<= 60) */
-    uint32_t alpha;          /* Q limbs per key-switching digit; dnum = ceil(n_q/alpha) */
+    uint32_t alpha;          /* Q limbs per key-switching digit; dnum = ceil(n_q/alpha).  The
+                              * key-switching noise scales with (largest digit modulus) / P, so
+                              * P should be at least as wide as a digit */
     double log_scale;        /* scale Delta = 2^log_scale of fresh ciphertexts and masks */
     uint64_t seed;           /* ChaCha20 key */
     uint32_t n_h;            /* matrix sides whose rotation keys and masks are made at creation */

@@ -1412,3 +1412,61 @@ orc_ct *orc_sign(orc_ctx *c, const orc_ct *x, int d, int k, int relu) {
     orc_ct_free(cur); orc_ct_free(r); orc_ct_free(xd);
     return y;
 }
+
+/* Alg. 5: AppMax(a, b) = (a + b) / 2 + (a - b) / 2 . g_d^(k)(a - b), evaluated as
+ * ((a + b) + m g_d^(k)(m)) with m = a - b and the halving kept in the scale; the last
+ * composition lands on the prime the product m g rescales by, so both terms of the sum share
+ * one scale (as for ReLU, the case b = 0) */
+orc_ct *orc_appmax(orc_ctx *c, const orc_ct *a, const orc_ct *b, int d, int k) {
+    if (d < 1 || d > 7 || k < 1) return NULL;
+    int nb = 0;
+    while ((1 << nb) <= d) nb++;
+    int lvl = a->level < b->level ? a->level : b->level;
+    if (lvl < k * (nb + 1) + 1) return NULL;
+    orc_ct *m = orc_sub(c, a, b), *s = orc_add(c, a, b);
+    orc_ct *cur = ct_copy(c, m);
+    for (int it = 0; it < k; it++) {
+        double target = cur->scale;
+        if (it == k - 1) target = (double)c->mod[cur->level - (nb + 1)];
+        orc_ct *t = eval_gd(c, cur, d, target);
+        orc_ct_free(cur);
+        cur = t;
+    }
+    orc_ct *r = mul_rs(c, m, cur);
+    orc_ct *sd = orc_drop(c, s, r->level);
+    orc_ct *y = orc_add(c, r, sd);
+    y->scale *= 2.0;
+    orc_ct_free(m); orc_ct_free(s); orc_ct_free(cur); orc_ct_free(r); orc_ct_free(sd);
+    return y;
+}
+
+/* 2 x 2 max pooling of a row-major h x h matrix: AppMax over horizontal neighbours
+ * (rotation by 1), then over vertical neighbours (rotation by h); entry (i, j) holds the
+ * maximum of the window with top-left corner (i, j) (cyclically at the last row/column) */
+orc_ct *orc_maxpool2(orc_ctx *c, const orc_ct *x, int h, int d, int k) {
+    orc_ct *r1 = orc_rotate(c, x, 1);
+    orc_ct *m1 = orc_appmax(c, x, r1, d, k);
+    orc_ct_free(r1);
+    if (!m1) return NULL;
+    orc_ct *r2 = orc_rotate(c, m1, h);
+    orc_ct *m2 = orc_appmax(c, m1, r2, d, k);
+    orc_ct_free(r2); orc_ct_free(m1);
+    return m2;
+}
+
+/* Alg. 6, aggregation: W - (eta / (B N)) sum_i G_i; the constant is a plaintext encoded at
+ * the scale Delta (one Mul_pt and one rescale), W is dropped to the result's level */
+orc_ct *orc_fl_update(orc_ctx *c, const orc_ct *w, orc_ct *const *g, int n, double coeff) {
+    if (n < 1) return NULL;
+    orc_ct *sum = ct_copy(c, g[0]);
+    for (int i = 1; i < n; i++) sum = acc_add(c, sum, ct_copy(c, g[i]));
+    if (sum->level < 1) { orc_ct_free(sum); return NULL; }
+    int64_t *pt = malloc(sizeof(int64_t) * c->n);
+    orc_encode(c, &coeff, 1, c->scale, pt);
+    orc_ct *t = orc_mul_plain(c, sum, pt, c->scale);
+    orc_ct *u = orc_rescale(c, t);
+    orc_ct *wd = orc_drop(c, w, u->level < w->level ? u->level : w->level);
+    orc_ct *r = orc_sub(c, wd, u);
+    free(pt); orc_ct_free(sum); orc_ct_free(t); orc_ct_free(u); orc_ct_free(wd);
+    return r;
+}

@@ -130,5 +130,11 @@ void orc_reset_counters(orc_ctx *c);
 
 /* ---- composite sign approximation (Sec. 4.2) ---- */
 orc_ct *orc_sign(orc_ctx *c, const orc_ct *x, int d, int k, int relu);
+/* Alg. 5: max(a, b) ~ (a + b)/2 + (a - b)/2 . g_d^(k)(a - b) */
+orc_ct *orc_appmax(orc_ctx *c, const orc_ct *a, const orc_ct *b, int d, int k);
+/* 2 x 2 max pooling of a packed h x h matrix by two AppMax levels (rotations 1 and h) */
+orc_ct *orc_maxpool2(orc_ctx *c, const orc_ct *x, int h, int d, int k);
+/* Alg. 6 aggregation: W - coeff . sum_i G_i (coeff = eta / (B N)) */
+orc_ct *orc_fl_update(orc_ctx *c, const orc_ct *w, orc_ct *const *g, int n, double coeff);
 
 #endif

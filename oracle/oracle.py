@@ -105,6 +105,9 @@ def _declare(L):
         "orc_counters": (None, [vp, P(i64)]),
         "orc_reset_counters": (None, [vp]),
         "orc_sign": (vp, [vp, vp, i32, i32, i32]),
+        "orc_appmax": (vp, [vp, vp, vp, i32, i32]),
+        "orc_maxpool2": (vp, [vp, vp, i32, i32, i32]),
+        "orc_fl_update": (vp, [vp, vp, P(vp), i32, dbl]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -377,6 +380,16 @@ class Ctx:
 
     def reset_counters(self):
         lib().orc_reset_counters(self.ptr)
+
+    def appmax(self, a, b, d, k):
+        return Ct(self, lib().orc_appmax(self.ptr, a.ptr, b.ptr, d, k))
+
+    def maxpool2(self, x, h, d, k):
+        return Ct(self, lib().orc_maxpool2(self.ptr, x.ptr, h, d, k))
+
+    def fl_update(self, w, grads, coeff):
+        arr = (C.c_void_p * len(grads))(*[g.ptr for g in grads])
+        return Ct(self, lib().orc_fl_update(self.ptr, w.ptr, arr, len(grads), float(coeff)))
 
     def sign(self, x, d, k, relu=False):
         return Ct(self, lib().orc_sign(self.ptr, x.ptr, d, k, int(bool(relu))))

@@ -803,3 +803,63 @@ def test_shaped_rotation_keys(h, t, beta, mode):
         s += 1
     want = {(beta * x) % half for x in want} - {0}
     assert sorted(want) == c.matmul_rotations_ex(h, t, beta, mode)
+
+
+# ---------------------------------------------------------------- Alg. 5 AppMax, pooling; Alg. 6
+def appmax_fp64(a, b, d, k):
+    m = a - b
+    g = m.copy()
+    for _ in range(k):
+        g = gd_eval(d, g)
+    return ((a + b) + m * g) / 2
+
+
+def test_appmax_decrypts_and_approaches_max():
+    """Alg. 5 against its FP64 evaluation (tight), against max(a, b) where |a - b| >= 1/4 (the
+    composite sign has converged there for d = 3, k = 3), and ReLU as the case b = 0"""
+    c = O.Ctx.from_params(I.small(log_n=10, n_q=12, alpha=3, q_bits=40, log_scale=40.0))
+    rng = np.random.default_rng(21)
+    a, b = rng.uniform(-0.5, 0.5, 256), rng.uniform(-0.5, 0.5, 256)
+    ca, cb = c.encrypt(a, nonce=1), c.encrypt(b, nonce=2)
+    y = c.appmax(ca, cb, 3, 3)
+    got = c.decrypt(y, 256)
+    assert np.abs(got - appmax_fp64(a, b, 3, 3)).max() < 1e-6
+    far = np.abs(a - b) >= 0.25
+    assert np.abs(got[far] - np.maximum(a, b)[far]).max() < 2e-3
+    assert y.level == ca.level - (3 * 3 + 1)
+    assert abs(y.scale / (2 * ca.scale) - 1) < 1e-12
+    z = c.appmax(ca, c.encrypt(np.zeros(256), nonce=3), 3, 2)
+    r = c.sign(ca, 3, 2, relu=True)
+    assert np.abs(c.decrypt(z, 256) - c.decrypt(r, 256)).max() < 1e-6
+
+
+def test_maxpool2_matches_window_formula():
+    # alpha = 2: every key-switching digit (<= 90 bits) stays below P (100 bits); rotations
+    # with wider digits carry digit / P times more noise
+    c = O.Ctx.from_params(I.small(log_n=10, n_q=12, alpha=2, q_bits=40, log_scale=40.0))
+    h = 8
+    X = np.random.default_rng(22).uniform(-0.5, 0.5, (h, h))
+    y = c.maxpool2(c.encrypt(X.ravel(), nonce=4), h, 3, 1)
+    v = X.ravel()
+    m1 = appmax_fp64(v, np.roll(v, -1), 3, 1)
+    m2 = appmax_fp64(m1, np.roll(m1, -h), 3, 1)
+    got = c.decrypt(y, h * h)
+    assert np.abs(got - m2).max() < 1e-6
+    # the stride-2 outputs are window maxima up to the method's error (window spreads >= 1/4)
+    W = np.array([[X[i:i + 2, j:j + 2].max() for j in range(0, h, 2)] for i in range(0, h, 2)])
+    G = got.reshape(h, h)[::2, ::2]
+    assert np.abs(G - W).max() < 0.2
+
+
+def test_fl_update_decrypts():
+    """Alg. 6 aggregation: W - eta / (B N) sum_i G_i, one level"""
+    c = O.Ctx.from_params(I.small(log_n=10, n_q=5, alpha=2))
+    rng = np.random.default_rng(23)
+    n, coeff = 5, 0.05 / (10 * 5)
+    W = rng.uniform(-1, 1, 64)
+    G = [rng.uniform(-1, 1, 64) for _ in range(n)]
+    cw = c.encrypt(W, nonce=1)
+    cg = [c.encrypt(g, nonce=10 + i) for i, g in enumerate(G)]
+    r = c.fl_update(cw, cg, coeff)
+    assert r.level == cw.level - 1
+    assert np.abs(c.decrypt(r, 64) - (W - coeff * np.sum(G, axis=0))).max() < 1e-6
