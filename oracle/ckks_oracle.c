@@ -1455,15 +1455,17 @@ orc_ct *orc_maxpool2(orc_ctx *c, const orc_ct *x, int h, int d, int k) {
 }
 
 /* Alg. 6, aggregation: W - (eta / (B N)) sum_i G_i; the constant is a plaintext encoded at
- * the scale Delta (one Mul_pt and one rescale), W is dropped to the result's level */
+ * the scale q_l of the prime the rescale removes (one Mul_pt and one rescale), so the product
+ * returns exactly to the gradients' scale; W is dropped to the result's level */
 orc_ct *orc_fl_update(orc_ctx *c, const orc_ct *w, orc_ct *const *g, int n, double coeff) {
     if (n < 1) return NULL;
     orc_ct *sum = ct_copy(c, g[0]);
     for (int i = 1; i < n; i++) sum = acc_add(c, sum, ct_copy(c, g[i]));
     if (sum->level < 1) { orc_ct_free(sum); return NULL; }
     int64_t *pt = malloc(sizeof(int64_t) * c->n);
-    orc_encode(c, &coeff, 1, c->scale, pt);
-    orc_ct *t = orc_mul_plain(c, sum, pt, c->scale);
+    const double ql = (double)c->mod[sum->level];
+    orc_encode(c, &coeff, 1, ql, pt);
+    orc_ct *t = orc_mul_plain(c, sum, pt, ql);
     orc_ct *u = orc_rescale(c, t);
     orc_ct *wd = orc_drop(c, w, u->level < w->level ? u->level : w->level);
     orc_ct *r = orc_sub(c, wd, u);

@@ -862,4 +862,5 @@ def test_fl_update_decrypts():
     cg = [c.encrypt(g, nonce=10 + i) for i, g in enumerate(G)]
     r = c.fl_update(cw, cg, coeff)
     assert r.level == cw.level - 1
-    assert np.abs(c.decrypt(r, 64) - (W - coeff * np.sum(G, axis=0))).max() < 1e-6
+    assert abs(r.scale / cw.scale - 1) < 1e-12  # the product lands on the gradients' scale
+    assert np.abs(c.decrypt(r, 64) - (W - coeff * np.sum(G, axis=0))).max() < 1e-7
