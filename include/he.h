@@ -220,6 +220,28 @@ he_status he_serve_poll(he_server *s, uint64_t ticket, int *done, he_ct **result
                         double *latency_s);
 he_status he_serve_stop(he_server *s);
 
+/* AppMax (Alg. 5): max(a, b) ~ (a + b)/2 + (a - b)/2 . g_d^(k)(a - b), evaluated as
+ * ((a + b) + m g_d^(k)(m)) with m = a - b and the halving kept in the scale (ReLU is the case
+ * b = 0).  |a - b| <= 1 is the input range of g_d.  Depth k (1 + floor(log2 d) + 1) + 1 below
+ * min(level a, level b); HE_ELEVEL if less remains, HE_EINVAL for d outside [1, 7] or k = 0. */
+he_status he_appmax(he_ctx *ctx, const he_ct *a, const he_ct *b, uint32_t d, uint32_t k, he_ct **out);
+he_status he_appmax_batch(he_ctx *ctx, size_t n, const he_ct *const *a, const he_ct *const *b, uint32_t d,
+                          uint32_t k, he_ct **out);
+/* 2 x 2 max pooling of a packed row-major h x h matrix: AppMax over horizontal neighbours
+ * (rotation by 1), then over vertical neighbours (rotation by h); entry (i, j) of the result
+ * holds the maximum of the window with top-left corner (i, j) (cyclic at the last row and
+ * column; the stride-2 pooling outputs are the entries with even i and j).  Twice the depth of
+ * he_appmax; rotation keys for 1 and h are made on first use. */
+he_status he_maxpool2(he_ctx *ctx, const he_ct *x, uint32_t h, uint32_t d, uint32_t k, he_ct **out);
+he_status he_maxpool2_batch(he_ctx *ctx, size_t n, const he_ct *const *x, uint32_t h, uint32_t d, uint32_t k,
+                            he_ct **out);
+/* Aggregation step of federated training (Alg. 6): W - coeff . sum_i G_i with
+ * coeff = eta / (B N).  The n gradients (at any levels; the sum is taken at the lowest) are
+ * added in one pass, multiplied by coeff encoded at the scale q_l of the prime the rescale
+ * removes (Mul_pt; the product returns exactly to the gradients' scale), rescaled, and
+ * subtracted from W dropped to that level: one level below the gradients. */
+he_status he_fl_update(he_ctx *ctx, const he_ct *w, size_t n, const he_ct *const *grads, double coeff, he_ct **out);
+
 /* Launch timing: with profiling on, every kernel launch (or, with 'only' naming one kernel
  * kind of the report, e.g. "ntt_fwd_rows", every launch of that kind) is bracketed by HIP
  * events on its stream.  The report (JSON text, NUL-terminated, truncated to n bytes) gives

@@ -739,16 +739,35 @@ Grp Ctx::g_eval_gd(const Grp& x, int d, const std::vector<double>& target) {
     return y;
 }
 
+Grp Ctx::g_ew(const Grp& a, const Grp& b, int op) {
+    if (a.B != b.B || a.level != b.level || a.deg != b.deg) throw HeError(HE_EMISMATCH);
+    std::vector<double> sc(a.B);
+    for (int i = 0; i < a.B; ++i) sc[i] = std::max(a.scale[i], b.scale[i]);  // Fig. 1 Add/Sub
+    Grp out = g_new(a.B, a.level, a.deg, sc);
+    launch_ew(T, ModMap{1 << 20, n_q}, a.level + 1, a.deg + 1, out.p, out.ps, a.p, a.ps, b.p, b.ps, op, stream, a.B,
+              out.cs, a.cs, b.cs);
+    cnt[C_ADD] += a.B;
+    return out;
+}
+
 bool Ctx::sign_step(SignJob& J) {
     if (J.it == 0 && !J.started) {
-        J.x = g_gather(J.X, J.lvl);
+        if (J.mode == 2) {  // AppMax: m = a - b, s = a + b
+            Grp a = J.pre ? J.ga : g_gather(J.X, J.lvl), b = J.pre ? J.gb : g_gather(J.Y, J.lvl);
+            J.x = g_ew(a, b, EW_SUB);
+            J.s = g_ew(a, b, EW_ADD);
+            J.ga = Grp();
+            J.gb = Grp();
+        } else {
+            J.x = J.pre ? J.ga : g_gather(J.X, J.lvl);
+        }
         J.cur = J.x;
         J.started = true;
     }
     if (J.it < J.k) {
-        // each composition returns its input's scale; for ReLU the last one lands on the
-        // prime q_l that the product x g rescales by, so x g comes out exactly at the scale
-        // of x and x + x g adds equal scales
+        // each composition returns its input's scale; for ReLU / AppMax the last one lands on
+        // the prime q_l that the product x g rescales by, so x g comes out exactly at the
+        // scale of x and the final sum adds equal scales
         std::vector<double> target(J.cur.scale);
         if (J.mode && J.it == J.k - 1) {
             int nb = 0;
@@ -759,21 +778,74 @@ bool Ctx::sign_step(SignJob& J) {
         ++J.it;
         if (J.it < J.k || J.mode) return false;
     }
-    if (J.mode) {  // ReLU(x) = (x + x g) / 2, the halving kept in the scale
+    if (J.mode) {  // ReLU: (x + x g) / 2; AppMax: ((a + b) + m g) / 2; the halving kept in the scale
         Grp r = g_mul_rs(J.x, J.cur);
-        Grp xd = g_drop(J.x, r.level);
+        Grp xd = g_drop(J.mode == 2 ? J.s : J.x, r.level);
         g_add_into(r, xd);
-        for (auto& s : r.scale) s *= 2.0;
+        for (auto& sc : r.scale) sc *= 2.0;
         J.cur = r;
     }
-    J.result = g_scatter(J.cur);
+    if (J.keep)
+        J.out = J.cur;
+    else
+        J.result = g_scatter(J.cur);
     J.x = Grp();
+    J.s = Grp();
     J.cur = Grp();
     return true;
 }
 
-std::vector<CtPtr> Ctx::sign_group(const std::vector<const CtData*>& X, int d, int k, int mode) {
-    if (d < 1 || d > 7 || k < 0) throw HeError(HE_EINVAL);
+// Alg. 5 on groups (used by max pooling)
+Grp Ctx::g_appmax(const Grp& a, const Grp& b, int d, int k) {
+    SignJob J;
+    J.pre = J.keep = true;
+    J.ga = a;
+    J.gb = b;
+    J.d = d;
+    J.k = k;
+    J.mode = 2;
+    J.lvl = a.level;
+    while (!sign_step(J)) {
+    }
+    return J.out;
+}
+
+// 2 x 2 max pooling of packed h x h matrices: AppMax over horizontal neighbours (rotation by
+// 1), then over vertical neighbours (rotation by h), for every member (grouped by level)
+std::vector<CtPtr> Ctx::maxpool_batch(const std::vector<const CtData*>& X, int h, int d, int k) {
+    if (h < 2 || (h & (h - 1)) || (int64_t)h * h > N / 2) throw HeError(HE_ESHAPE);
+    if (d < 1 || d > 7 || k < 1) throw HeError(HE_EINVAL);
+    int nb = 0;
+    while ((1 << nb) <= d) ++nb;
+    rot_key(galois(1), true);
+    rot_key(galois(h), true);
+    std::map<int, std::vector<size_t>> groups;
+    for (size_t i = 0; i < X.size(); ++i) {
+        if (X[i]->deg != 1) throw HeError(HE_EMISMATCH);
+        if (X[i]->level < 2 * (k * (nb + 1) + 1)) throw HeError(HE_ELEVEL);
+        groups[X[i]->level].push_back(i);
+    }
+    std::vector<CtPtr> out(X.size());
+    const size_t cap = (size_t)std::max(1, max_group);
+    for (auto& kv : groups) {
+        const auto& idx = kv.second;
+        for (size_t s0 = 0; s0 < idx.size(); s0 += cap) {
+            std::vector<const CtData*> v;
+            for (size_t t = s0; t < std::min(idx.size(), s0 + cap); ++t) v.push_back(X[idx[t]]);
+            Grp x = g_gather(v, kv.first);
+            Grp m1 = g_appmax(x, g_rotate(x, 1), d, k);
+            Grp m2 = g_appmax(m1, g_rotate(m1, h), d, k);
+            auto r = g_scatter(m2);
+            for (size_t t = 0; t < r.size(); ++t) out[idx[s0 + t]] = r[t];
+        }
+    }
+    return out;
+}
+
+std::vector<CtPtr> Ctx::sign_group(const std::vector<const CtData*>& X, int d, int k, int mode,
+                                   const std::vector<const CtData*>& Y) {
+    if (d < 1 || d > 7 || k < 0 || mode > 2 || (mode == 2 && (k < 1 || Y.size() != X.size())))
+        throw HeError(HE_EINVAL);
     int nb = 0;
     while ((1 << nb) <= d) ++nb;
     int lvl = 1 << 30;
@@ -781,9 +853,14 @@ std::vector<CtPtr> Ctx::sign_group(const std::vector<const CtData*>& X, int d, i
         if (x->deg != 1) throw HeError(HE_EMISMATCH);
         lvl = std::min(lvl, x->level);
     }
+    for (auto* y : Y) {
+        if (y->deg != 1) throw HeError(HE_EMISMATCH);
+        lvl = std::min(lvl, y->level);
+    }
     if (lvl < k * (nb + 1) + (mode ? 1 : 0)) throw HeError(HE_ELEVEL);
     SignJob J;
     J.X = X;
+    J.Y = Y;
     J.lvl = lvl;
     J.d = d;
     J.k = k;

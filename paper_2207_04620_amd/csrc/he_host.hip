@@ -772,6 +772,43 @@ std::unique_ptr<DBuf> Ctx::plaintext_mont(const int64_t* coeffs) {
     return pt;
 }
 
+// Alg. 6 aggregation: W - coeff sum_i G_i.  The n gradients are summed in one pass over HBM
+// (16 inputs per launch), multiplied by the constant coeff = eta / (B N) encoded at the scale
+// q_l of the prime the rescale removes (Mul_pt; the product returns exactly to the gradients'
+// scale), rescaled, and subtracted from W dropped to the result's level.
+CtPtr Ctx::fl_update(const CtData& w, const std::vector<const CtData*>& grads, double coeff) {
+    if (grads.empty()) throw HeError(HE_EINVAL);
+    int lvl = grads[0]->level;
+    double sc = grads[0]->scale;
+    for (auto* g : grads) {
+        if (g->deg != 1) throw HeError(HE_EMISMATCH);
+        lvl = std::min(lvl, g->level);
+        sc = std::max(sc, g->scale);
+    }
+    if (lvl < 1 || w.deg != 1) throw HeError(lvl < 1 ? HE_ELEVEL : HE_EMISMATCH);
+    const int nl = lvl + 1;
+    CtPtr sum = new_ct(lvl, 1, sc);
+    for (size_t base = 0; base < grads.size(); base += 16) {
+        SumDesc D;
+        memset(&D, 0, sizeof D);
+        D.n = (int)std::min<size_t>(16, grads.size() - base);
+        for (int t = 0; t < D.n; ++t) {
+            D.in[t] = grads[base + t]->buf->p;
+            D.in_ps[t] = (int64_t)(grads[base + t]->level + 1) * N;
+        }
+        launch_sum_many(T, nl, 2, D, sum->buf->p, (int64_t)nl * N, base > 0, stream);
+    }
+    cnt[C_ADD] += (int64_t)grads.size() - 1;
+    std::vector<int64_t> m(N);
+    const double ql = (double)mods[lvl];
+    enc.encode(&coeff, 1, ql, m.data());
+    auto pt = plaintext_mont(m.data());
+    CtPtr t = mask_sum({{sum.get(), pt->p}}, ql);
+    CtPtr u = rescale(*t);
+    CtPtr wd = drop(w, std::min(u->level, w.level));
+    return add_sub(*wd, *u, true);
+}
+
 // sum_r in_r * mask_r (Mul_pt terms of one diagonal sum, Alg. 2 / Eq. 1)
 CtPtr Ctx::mask_sum(const std::vector<std::pair<const CtData*, const u64*>>& terms, double mask_scale) {
     const CtData& a0 = *terms[0].first;
@@ -1302,6 +1339,66 @@ he_status he_sign_approx_batch(he_ctx* ctx, size_t n, const he_ct* const* x, uin
             }
         }
         for (size_t i = 0; i < n; ++i) out[i] = wrap(ctx->c.get(), res[i]);
+    });
+}
+he_status he_appmax(he_ctx* ctx, const he_ct* a, const he_ct* b, uint32_t d, uint32_t k, he_ct** out) {
+    return he_appmax_batch(ctx, 1, &a, &b, d, k, out);
+}
+he_status he_appmax_batch(he_ctx* ctx, size_t n, const he_ct* const* a, const he_ct* const* b, uint32_t d,
+                          uint32_t k, he_ct** out) {
+    if (!ctx || (n && (!a || !b || !out))) return HE_EINVAL;
+    for (size_t i = 0; i < n; ++i) {
+        if (!a[i] || !b[i]) return HE_EINVAL;
+        if (a[i]->ctx != ctx->c.get() || b[i]->ctx != ctx->c.get()) return HE_EMISMATCH;
+    }
+    return guardc(ctx, [&]() {
+        // lockstep groups of equal operand levels
+        std::map<std::pair<int, int>, std::vector<size_t>> byl;
+        for (size_t i = 0; i < n; ++i) byl[{a[i]->c->level, b[i]->c->level}].push_back(i);
+        std::vector<CtPtr> res(n);
+        for (auto& kv : byl) {
+            for (size_t s = 0; s < kv.second.size(); s += (size_t)ctx->c->max_group) {
+                std::vector<const CtData*> va, vb;
+                const size_t e = std::min(kv.second.size(), s + (size_t)ctx->c->max_group);
+                for (size_t t = s; t < e; ++t) {
+                    va.push_back(a[kv.second[t]]->c.get());
+                    vb.push_back(b[kv.second[t]]->c.get());
+                }
+                auto r = ctx->c->sign_group(va, (int)d, (int)k, 2, vb);
+                for (size_t t = s; t < e; ++t) res[kv.second[t]] = r[t - s];
+            }
+        }
+        for (size_t i = 0; i < n; ++i) out[i] = wrap(ctx->c.get(), res[i]);
+    });
+}
+he_status he_maxpool2(he_ctx* ctx, const he_ct* x, uint32_t h, uint32_t d, uint32_t k, he_ct** out) {
+    return he_maxpool2_batch(ctx, 1, &x, h, d, k, out);
+}
+he_status he_maxpool2_batch(he_ctx* ctx, size_t n, const he_ct* const* x, uint32_t h, uint32_t d, uint32_t k,
+                            he_ct** out) {
+    if (!ctx || (n && (!x || !out))) return HE_EINVAL;
+    for (size_t i = 0; i < n; ++i) {
+        if (!x[i]) return HE_EINVAL;
+        if (x[i]->ctx != ctx->c.get()) return HE_EMISMATCH;
+    }
+    return guardc(ctx, [&]() {
+        std::vector<const CtData*> v(n);
+        for (size_t i = 0; i < n; ++i) v[i] = x[i]->c.get();
+        auto r = ctx->c->maxpool_batch(v, (int)h, (int)d, (int)k);
+        for (size_t i = 0; i < n; ++i) out[i] = wrap(ctx->c.get(), r[i]);
+    });
+}
+he_status he_fl_update(he_ctx* ctx, const he_ct* w, size_t n, const he_ct* const* grads, double coeff, he_ct** out) {
+    if (!ctx || !w || !out || n == 0 || !grads) return HE_EINVAL;
+    if (w->ctx != ctx->c.get()) return HE_EMISMATCH;
+    for (size_t i = 0; i < n; ++i) {
+        if (!grads[i]) return HE_EINVAL;
+        if (grads[i]->ctx != ctx->c.get()) return HE_EMISMATCH;
+    }
+    return guardc(ctx, [&]() {
+        std::vector<const CtData*> g(n);
+        for (size_t i = 0; i < n; ++i) g[i] = grads[i]->c.get();
+        *out = wrap(ctx->c.get(), ctx->c->fl_update(*w->c, g, coeff));
     });
 }
 he_status he_profile_enable(he_ctx* ctx, int on, const char* only) {

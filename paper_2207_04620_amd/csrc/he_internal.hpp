@@ -89,11 +89,15 @@ struct MatmulJob {
     std::vector<CtPtr> result;
 };
 // resumable state of one lockstep sign/ReLU group
+// mode 0: g_d^(k)(x); mode 1: ReLU (x + x g) / 2; mode 2: AppMax(a, b) (Alg. 5) with
+// a = X, b = Y: ((a + b) + m g_d^(k)(m)) / 2, m = a - b
 struct SignJob {
-    std::vector<const CtData*> X;
+    std::vector<const CtData*> X, Y;
     int lvl = 0, d = 3, k = 1, mode = 0, it = 0;
     bool started = false;
-    Grp x, cur;
+    bool pre = false, keep = false;  // inputs given as groups (ga, gb); result kept as a group
+    Grp ga, gb, out;
+    Grp x, s, cur;
     std::vector<CtPtr> result;
 };
 
@@ -233,7 +237,12 @@ struct Ctx {
     Grp g_mul_rs(const Grp& x, const Grp& y);
     Grp g_eval_gd(const Grp& x, int d, const std::vector<double>& target);
     bool sign_step(SignJob& J);
-    std::vector<CtPtr> sign_group(const std::vector<const CtData*>& X, int d, int k, int mode);
+    std::vector<CtPtr> sign_group(const std::vector<const CtData*>& X, int d, int k, int mode,
+                                  const std::vector<const CtData*>& Y = {});
+    Grp g_ew(const Grp& a, const Grp& b, int op);
+    Grp g_appmax(const Grp& a, const Grp& b, int d, int k);
+    std::vector<CtPtr> maxpool_batch(const std::vector<const CtData*>& X, int h, int d, int k);
+    CtPtr fl_update(const CtData& w, const std::vector<const CtData*>& grads, double coeff);
 
     std::recursive_mutex api_mu;  // every C-ABI call on the context (and the serving thread) holds it
 

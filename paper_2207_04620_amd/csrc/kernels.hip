@@ -832,6 +832,26 @@ void launch_moddown_combine(const DevTables& T, int nl, int npoly, const u64* u,
                        add, add_ps, out, out_ps, u_cs, conv_cs, add_cs, out_cs);
 }
 
+// ------------------------------------------------------------------ n-ary sum
+__global__ __launch_bounds__(TPB) void k_sum_many(DevTables T, SumDesc D, u64* out, int64_t out_ps, int accumulate) {
+    const int N = 1 << T.log_n;
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int l = blockIdx.y, p = blockIdx.z;
+    const u64 q = T.mods[l].q;
+    const int64_t o = (int64_t)l * N + i;
+    u64 v = accumulate ? out[p * out_ps + o] : 0;
+    for (int t = 0; t < D.n; t++) v = add_mod(v, D.in[t][p * D.in_ps[t] + o], q);
+    out[p * out_ps + o] = v;
+}
+
+void launch_sum_many(const DevTables& T, int nl, int npoly, const SumDesc& D, u64* out, int64_t out_ps,
+                     int accumulate, hipStream_t st) {
+    ProfScope prof_(PK_EW, (D.n + 1.0 + accumulate) * nl * npoly * 8.0 * (1 << T.log_n), st);
+    const int N = 1 << T.log_n;
+    dim3 grid(ceil_div(N, TPB), nl, npoly);
+    hipLaunchKernelGGL(k_sum_many, grid, dim3(TPB), 0, st, T, D, out, out_ps, accumulate);
+}
+
 // ------------------------------------------------------------------ rescale
 __global__ __launch_bounds__(TPB) void k_rescale_spread(DevTables T, const u64* last, int64_t last_ps, int last_mod,
                                                         u64* tmp, int64_t tmp_ps) {

@@ -103,6 +103,16 @@ struct IpDesc {
     int accumulate;    // u += the result (a sum of rotations of different ciphertexts)
 };
 
+// n-ary sum of ciphertext polynomials (up to 16 inputs per launch), each input with its own
+// poly stride (inputs above the output level contribute their limb prefix)
+struct SumDesc {
+    const u64* in[16];
+    int64_t in_ps[16];
+    int n;
+};
+void launch_sum_many(const DevTables& T, int nl, int npoly, const SumDesc& D, u64* out, int64_t out_ps,
+                     int accumulate, hipStream_t st);
+
 struct MacDesc {
     const u64* in[16];
     const u64* mask[16];

@@ -96,6 +96,14 @@ SIGNATURES = {
     "he_matmul_batch_ex": (C.c_int, [C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                      C.c_void_p, C.POINTER(C.c_void_p)]),
     "he_transpose": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.POINTER(C.c_void_p)]),
+    "he_appmax": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.POINTER(C.c_void_p)]),
+    "he_appmax_batch": (C.c_int, [C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_uint32,
+                                  C.c_uint32, C.POINTER(C.c_void_p)]),
+    "he_maxpool2": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_void_p)]),
+    "he_maxpool2_batch": (C.c_int, [C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p), C.c_uint32, C.c_uint32,
+                                    C.c_uint32, C.POINTER(C.c_void_p)]),
+    "he_fl_update": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p), C.c_double,
+                               C.POINTER(C.c_void_p)]),
     "he_transpose_batch": (C.c_int, [C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p), C.c_uint32, C.c_uint32,
                                      C.POINTER(C.c_void_p)]),
     "he_sign_approx": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32,
@@ -361,6 +369,36 @@ class Context:
         out = (C.c_void_p * n)()
         _chk(lib().he_transpose_batch(self.ptr, n, px, int(h), int(beta), out), "he_transpose_batch")
         return [Ciphertext(self, out[i]) for i in range(n)]
+
+    def appmax(self, a, b, d, k):
+        """AppMax (Alg. 5): max(a, b) by the composite sign g_d^(k)"""
+        return self.appmax_batch([a], [b], d, k)[0]
+
+    def appmax_batch(self, As, Bs, d, k):
+        n = len(As)
+        pa = (C.c_void_p * n)(*[x.ptr for x in As])
+        pb = (C.c_void_p * n)(*[x.ptr for x in Bs])
+        out = (C.c_void_p * n)()
+        _chk(lib().he_appmax_batch(self.ptr, n, pa, pb, int(d), int(k), out), "he_appmax_batch")
+        return [Ciphertext(self, out[i]) for i in range(n)]
+
+    def maxpool2(self, x, h, d, k):
+        return self.maxpool2_batch([x], h, d, k)[0]
+
+    def maxpool2_batch(self, xs, h, d, k):
+        n = len(xs)
+        px = (C.c_void_p * n)(*[x.ptr for x in xs])
+        out = (C.c_void_p * n)()
+        _chk(lib().he_maxpool2_batch(self.ptr, n, px, int(h), int(d), int(k), out), "he_maxpool2_batch")
+        return [Ciphertext(self, out[i]) for i in range(n)]
+
+    def fl_update(self, w, grads, coeff):
+        """Alg. 6 aggregation: W - coeff sum_i G_i"""
+        n = len(grads)
+        pg = (C.c_void_p * n)(*[g.ptr for g in grads])
+        out = C.c_void_p()
+        _chk(lib().he_fl_update(self.ptr, w.ptr, n, pg, float(coeff), C.byref(out)), "he_fl_update")
+        return Ciphertext(self, out.value)
 
     def sign_approx(self, x, d, k, mode=SIGN):
         return self._ct(lib().he_sign_approx, x.ptr, int(d), int(k), int(mode))

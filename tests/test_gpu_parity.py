@@ -489,3 +489,56 @@ def test_c3_packed_h64_beta4_full_size(he):
     om = o.matmul_ex(o.encrypt(va, nonce=1), o.encrypt(vb, nonce=2), 64, 64, 4, 15)
     assert np.array_equal(g.export(gm), om.export())
     g.close()
+
+
+# ---------------------------------------------------------------- Alg. 5 AppMax, pooling; Alg. 6
+def _gd3(v):
+    return (35 * v - 35 * v ** 3 + 21 * v ** 5 - 5 * v ** 7) / 16
+
+
+def _appmax64(a, b, k):
+    m = a - b
+    g = m.copy()
+    for _ in range(k):
+        g = _gd3(g)
+    return ((a + b) + m * g) / 2
+
+
+def test_appmax_maxpool_flupdate_parity(he):
+    """AppMax (Alg. 5), 2 x 2 max pooling and the aggregation step of Alg. 6 on a 2^12 ring:
+    every result against the oracle on every residue, and within 1e-6 of the FP64 evaluation;
+    batched AppMax equals single"""
+    prm = I.small(log_n=12, n_q=14, alpha=2, q_bits=40, p_bits=50)
+    p = Pair(he, prm, h_list=[])
+    rng = np.random.default_rng(41)
+    a, b = rng.uniform(-0.5, 0.5, 256), rng.uniform(-0.5, 0.5, 256)
+    ga, gb = p.g.encrypt(a, nonce=1), p.g.encrypt(b, nonce=2)
+    oa, ob = p.o.encrypt(a, nonce=1), p.o.encrypt(b, nonce=2)
+    for k in (1, 3):
+        _log(f"[parity] appmax d=3 k={k}")
+        g = p.g.appmax(ga, gb, 3, k)
+        p.same(g, p.o.appmax(oa, ob, 3, k))
+        assert np.abs(p.g.decrypt(g, 256) - _appmax64(a, b, k)).max() < 1e-6
+    gl = p.g.encrypt(b, level=9, nonce=3)
+    batch = p.g.appmax_batch([ga, gb, ga], [gb, ga, gl], 3, 1)
+    for r, (x, y) in zip(batch, [(ga, gb), (gb, ga), (ga, gl)]):
+        assert np.array_equal(p.g.export(r), p.g.export(p.g.appmax(x, y, 3, 1)))
+    _log("[parity] maxpool2 h=16")
+    h = 16
+    X = rng.uniform(-0.5, 0.5, (h, h))
+    g = p.g.maxpool2(p.g.encrypt(X.ravel(), nonce=4), h, 3, 1)
+    p.same(g, p.o.maxpool2(p.o.encrypt(X.ravel(), nonce=4), h, 3, 1))
+    v = X.ravel()
+    m1 = _appmax64(v, np.roll(v, -1), 1)
+    assert np.abs(p.g.decrypt(g, h * h) - _appmax64(m1, np.roll(m1, -h), 1)).max() < 1e-6
+    _log("[parity] fl_update n=20")
+    n, coeff = 20, 0.1 / (16 * 20)
+    W = rng.uniform(-1, 1, 512)
+    G = [rng.uniform(-1, 1, 512) for _ in range(n)]
+    gw = p.g.encrypt(W, nonce=100)
+    gg = [p.g.encrypt(x, level=12 if i % 3 else 13, nonce=101 + i) for i, x in enumerate(G)]
+    ow = p.o.encrypt(W, nonce=100)
+    og = [p.o.encrypt(x, level=12 if i % 3 else 13, nonce=101 + i) for i, x in enumerate(G)]
+    g = p.g.fl_update(gw, gg, coeff)
+    p.same(g, p.o.fl_update(ow, og, coeff))
+    assert np.abs(p.g.decrypt(g, 512) - (W - coeff * np.sum(G, axis=0))).max() < 1e-6
