@@ -476,26 +476,59 @@ Grp Ctx::g_lintrans(const Grp& a, int kind, int h, int beta, int64_t unit, int d
     RotSum gsum;
     Grp acc;
     bool have = false;
-    for (int i = floordiv_g(dlo, b); i <= floordiv_g(dhi, b); ++i) {
-        std::vector<std::pair<const Grp*, const u64*>> terms;
+    // the giant-step inner sums sum_j R(mask_{b i + j}, -unit b i) . baby_j, computed a few
+    // giant steps per launch (the babies are read once per launch), each chunk consumed
+    // before the next is made
+    const int glo = floordiv_g(dlo, b), ghi = floordiv_g(dhi, b);
+    const int per = b > 8 ? 2 : MM_OUT;
+    for (int i0 = glo; i0 <= ghi; i0 += per) {
+        MultiMacDesc D;
+        memset(&D, 0, sizeof D);
+        D.nin = b;
+        D.nct = a.B;
         for (int j = 0; j < b; ++j) {
-            const int d = b * i + j;
-            if (d < dlo || d > dhi) continue;
-            terms.push_back({&baby[j], mask(kind, h, d, -unit * b * i, beta)});
+            D.in[j] = baby[j].p;
+            D.in_ps[j] = baby[j].ps;
+            D.in_cs[j] = baby[j].cs;
         }
-        if (terms.empty()) continue;
-        Grp inner = g_mask_sum(terms, ms);
-        const int64_t r = (int64_t)beta * unit * b * i;
-        if (i && hoist) {
-            g_rotsum_add(gsum, inner, r);
-            continue;
+        std::vector<std::pair<int, Grp>> inners;
+        for (int i = i0; i <= std::min(ghi, i0 + per - 1); ++i) {
+            int nterm = 0;
+            const u64* mk[16] = {nullptr};
+            for (int j = 0; j < b; ++j) {
+                const int d = b * i + j;
+                if (d < dlo || d > dhi) continue;
+                mk[j] = mask(kind, h, d, -unit * b * i, beta);
+                ++nterm;
+            }
+            if (!nterm) continue;
+            std::vector<double> sc(a.scale);
+            for (auto& v : sc) v *= ms;
+            Grp g = g_new(a.B, a.level, 1, sc);
+            D.out_ps = g.ps;
+            D.out_cs = g.cs;
+            for (int j = 0; j < b; ++j) D.mask[D.nout][j] = mk[j];
+            D.out[D.nout++] = g.p;
+            inners.push_back({i, g});
+            cnt[C_MULPT] += (int64_t)nterm * a.B;
+            cnt[C_ADD] += (int64_t)(nterm - 1) * a.B;
         }
-        if (i) inner = g_rotate(inner, r);
-        if (!have) {
-            acc = inner;
-            have = true;
-        } else {
-            g_add_into(acc, inner);
+        if (D.nout) launch_mask_mac_multi(T, a.level + 1, 2, D, stream);
+        for (auto& ig : inners) {
+            const int i = ig.first;
+            Grp inner = ig.second;
+            const int64_t r = (int64_t)beta * unit * b * i;
+            if (i && hoist) {
+                g_rotsum_add(gsum, inner, r);
+                continue;
+            }
+            if (i) inner = g_rotate(inner, r);
+            if (!have) {
+                acc = inner;
+                have = true;
+            } else {
+                g_add_into(acc, inner);
+            }
         }
     }
     if (gsum.u) acc = g_rotsum_finish(gsum, have ? &acc : nullptr);

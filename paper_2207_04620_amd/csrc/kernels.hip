@@ -965,6 +965,54 @@ void launch_mask_mac(const DevTables& T, int nl, int npoly, const MacDesc& D, u6
     hipLaunchKernelGGL(k_mask_mac, grid, dim3(TPB), 0, st, T, D, out, out_ps, acc, out_cs);
 }
 
+// Up to MM_OUT diagonal sums of one BSGS linear transform at once: each thread keeps the masks
+// of every output in registers and reads each input word once per member, so the baby-step
+// rotations cross HBM once per MM_OUT giant steps instead of once per giant step.
+template <int NI>
+__global__ __launch_bounds__(TPB) void k_mask_mac_multi(DevTables T, MultiMacDesc D) {
+    constexpr int G = NI > 8 ? 2 : MM_OUT;
+    const int N = 1 << T.log_n;
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int l = blockIdx.y, p = blockIdx.z;
+    const ModP m = T.mods[l];
+    const int64_t o = (int64_t)l * N + i;
+    u64 mk[G][NI];
+#pragma unroll
+    for (int g = 0; g < G; g++)
+#pragma unroll
+        for (int j = 0; j < NI; j++) mk[g][j] = (g < D.nout && D.mask[g][j]) ? D.mask[g][j][o] : 0;
+    for (int c = 0; c < D.nct; c++) {
+        u64 x[NI];
+#pragma unroll
+        for (int j = 0; j < NI; j++) x[j] = D.in[j][c * D.in_cs[j] + p * D.in_ps[j] + o];
+#pragma unroll
+        for (int g = 0; g < G; g++) {
+            if (g >= D.nout) break;
+            Acc128 s = {0, 0};
+#pragma unroll
+            for (int j = 0; j < NI; j++) mac128(s, x[j], mk[g][j]);
+            // NI q^2 < q 2^64 for NI <= 16 and q < 2^60
+            D.out[g][c * D.out_cs + p * D.out_ps + o] = redc(s.lo, s.hi, m.q, m.qninv);
+        }
+    }
+}
+
+void launch_mask_mac_multi(const DevTables& T, int nl, int npoly, const MultiMacDesc& D, hipStream_t st) {
+    int terms = 0;
+    for (int g = 0; g < D.nout; g++)
+        for (int j = 0; j < D.nin; j++) terms += D.mask[g][j] != nullptr;
+    ProfScope prof_(PK_MASKMAC, (terms + D.nct * npoly * ((double)D.nin + D.nout)) * nl * 8.0 * (1 << T.log_n), st);
+    const int N = 1 << T.log_n;
+    dim3 grid(ceil_div(N, TPB), nl, npoly);
+    switch (D.nin) {
+        case 1: hipLaunchKernelGGL(k_mask_mac_multi<1>, grid, dim3(TPB), 0, st, T, D); break;
+        case 2: hipLaunchKernelGGL(k_mask_mac_multi<2>, grid, dim3(TPB), 0, st, T, D); break;
+        case 4: hipLaunchKernelGGL(k_mask_mac_multi<4>, grid, dim3(TPB), 0, st, T, D); break;
+        case 8: hipLaunchKernelGGL(k_mask_mac_multi<8>, grid, dim3(TPB), 0, st, T, D); break;
+        default: hipLaunchKernelGGL(k_mask_mac_multi<16>, grid, dim3(TPB), 0, st, T, D); break;
+    }
+}
+
 // ------------------------------------------------------------------ encrypt / decrypt
 __global__ __launch_bounds__(TPB) void k_dec_dot(DevTables T, int deg, const u64* c, int64_t c_ps, const u64* s,
                                                  const u64* s2, u64* mo) {

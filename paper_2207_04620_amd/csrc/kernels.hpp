@@ -113,6 +113,19 @@ struct SumDesc {
 void launch_sum_many(const DevTables& T, int nl, int npoly, const SumDesc& D, u64* out, int64_t out_ps,
                      int accumulate, hipStream_t st);
 
+// several diagonal sums over the same inputs (the giant steps of one BSGS linear transform):
+// out[g] = sum_j mask[g][j] . in[j]; a null mask is an absent term
+#define MM_OUT 4
+struct MultiMacDesc {
+    const u64* in[16];
+    int64_t in_ps[16], in_cs[16];
+    const u64* mask[MM_OUT][16];  // Montgomery form, rows = limbs
+    u64* out[MM_OUT];
+    int64_t out_ps, out_cs;
+    int nin, nout, nct;
+};
+void launch_mask_mac_multi(const DevTables& T, int nl, int npoly, const MultiMacDesc& D, hipStream_t st);
+
 struct MacDesc {
     const u64* in[16];
     const u64* mask[16];
