@@ -442,6 +442,44 @@ void Ctx::g_tensor_acc(Grp& acc, const Grp& a, const Grp& b) {
     cnt[C_ADD] += a.B;
 }
 
+// J.S (+)= sum over the pending pairs of A (x) B in one pass (relin-once schedules)
+void Ctx::g_tensor_sum(MatmulJob& J) {
+    if (J.pendA.empty()) return;
+    const Grp& a0 = J.pendA[0];
+    if (!J.haveS) {
+        std::vector<double> sc(a0.B);
+        for (int i = 0; i < a0.B; ++i) sc[i] = a0.scale[i] * J.pendB[0].scale[i];
+        J.S = g_new(a0.B, a0.level, 2, sc);
+    }
+    TensorSumDesc D;
+    memset(&D, 0, sizeof D);
+    D.n = (int)J.pendA.size();
+    D.nct = a0.B;
+    D.acc = J.haveS ? 1 : 0;
+    D.d = J.S.p;
+    D.d_ps = J.S.ps;
+    D.d_cs = J.S.cs;
+    for (int j = 0; j < D.n; ++j) {
+        const Grp &a = J.pendA[j], &b = J.pendB[j];
+        if (a.deg != 1 || b.deg != 1 || a.level != J.S.level || b.level != J.S.level || a.B != a0.B)
+            throw HeError(HE_EMISMATCH);
+        D.a[j] = a.p;
+        D.a_ps[j] = a.ps;
+        D.a_cs[j] = a.cs;
+        D.b[j] = b.p;
+        D.b_ps[j] = b.ps;
+        D.b_cs[j] = b.cs;
+        // Add of Fig. 1: scale max (all terms of a block share one scale)
+        for (int i = 0; i < a0.B; ++i) J.S.scale[i] = std::max(J.S.scale[i], a.scale[i] * b.scale[i]);
+    }
+    launch_tensor_sum(T, J.S.level + 1, D, stream);
+    cnt[C_MULCT] += (int64_t)D.n * a0.B;
+    cnt[C_ADD] += (int64_t)(D.n - 1 + D.acc) * a0.B;
+    J.haveS = true;
+    J.pendA.clear();
+    J.pendB.clear();
+}
+
 Grp Ctx::g_relin(const Grp& a) {
     if (a.deg != 2) throw HeError(HE_EMISMATCH);
     const u64* key = relin_key();
@@ -602,14 +640,13 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
                     g_add_into(J.S, prod);
                 }
             } else {
-                if (!J.haveS) {
-                    J.S = g_tensor(Ak, Bj);
-                    J.haveS = true;
-                } else {
-                    g_tensor_acc(J.S, Ak, Bj);
-                }
+                // products of a block are summed in one pass (at most 16 pairs per pass)
+                J.pendA.push_back(Ak);
+                J.pendB.push_back(Bj);
+                if (J.pendA.size() == 16) g_tensor_sum(J);
             }
             if (j == bg - 1 || k == t - 1) {
+                g_tensor_sum(J);
                 Grp blk = J.S;
                 J.S = Grp();
                 J.haveS = false;

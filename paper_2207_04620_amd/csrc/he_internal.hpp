@@ -85,6 +85,7 @@ struct MatmulJob {
     bool have = false, haveS = false;
     std::vector<Grp> babyB;  // Rot(B0, h j), j < bg, kept across blocks (Step-3 split)
     RotSum giant;            // Step-3 giant-step rotations sharing one ModDown (ModDown hoisting)
+    std::vector<Grp> pendA, pendB;  // Step-3 pairs awaiting one block tensor-sum (relin-once)
     std::shared_ptr<DBuf> liftA, liftB;
     std::vector<CtPtr> result;
 };
@@ -228,6 +229,7 @@ struct Ctx {
     Grp g_rescale(const Grp& a);
     Grp g_tensor(const Grp& a, const Grp& b);
     void g_tensor_acc(Grp& acc, const Grp& a, const Grp& b);
+    void g_tensor_sum(MatmulJob& J);
     Grp g_relin(const Grp& a);
     Grp g_lintrans(const Grp& a, int kind, int h, int beta, int64_t unit, int dlo, int dhi);
     std::vector<CtPtr> matmul_group(const std::vector<const CtData*>& A, const std::vector<const CtData*>& B,

@@ -935,6 +935,49 @@ void launch_tensor(const DevTables& T, int nl, const u64* a, int64_t a_ps, const
     hipLaunchKernelGGL(k_tensor, grid, dim3(TPB), 0, st, T, a, a_ps, b, b_ps, d, d_ps, acc, a_cs, b_cs, d_cs);
 }
 
+// Step-3 block: d = sum_j a_j (x) b_j (d0 = sum a0 b0, d1 = sum a0 b1 + a1 b0, d2 = sum a1 b1),
+// one pass over the inputs and one write of d.  Plain products are accumulated in 128 bits
+// (n q^2 < q 2^64 for n <= 16, q < 2^60; d1 keeps its two halves apart) and reduced once per
+// output: REDC gives the sum times R^-1, a Montgomery product with R^2 removes it.
+__global__ __launch_bounds__(TPB) void k_tensor_sum(DevTables T, TensorSumDesc D) {
+    const int N = 1 << T.log_n;
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int l = blockIdx.y, c = blockIdx.z;
+    const ModP m = T.mods[l];
+    const int64_t o = (int64_t)l * N + i;
+    Acc128 s0 = {0, 0}, s1a = {0, 0}, s1b = {0, 0}, s2 = {0, 0};
+    for (int j = 0; j < D.n; j++) {
+        const u64* a = D.a[j] + c * D.a_cs[j];
+        const u64* b = D.b[j] + c * D.b_cs[j];
+        const u64 a0 = a[o], a1 = a[D.a_ps[j] + o], b0 = b[o], b1 = b[D.b_ps[j] + o];
+        mac128(s0, a0, b0);
+        mac128(s1a, a0, b1);
+        mac128(s1b, a1, b0);
+        mac128(s2, a1, b1);
+    }
+    const u64 t0 = redc(s0.lo, s0.hi, m.q, m.qninv);
+    const u64 t1 = add_mod(redc(s1a.lo, s1a.hi, m.q, m.qninv), redc(s1b.lo, s1b.hi, m.q, m.qninv), m.q);
+    const u64 t2 = redc(s2.lo, s2.hi, m.q, m.qninv);
+    u64 v0 = mul_mont(t0, m.r2, m.q, m.qninv), v1 = mul_mont(t1, m.r2, m.q, m.qninv),
+        v2 = mul_mont(t2, m.r2, m.q, m.qninv);
+    u64* d = D.d + c * D.d_cs;
+    if (D.acc) {
+        v0 = add_mod(v0, d[o], m.q);
+        v1 = add_mod(v1, d[D.d_ps + o], m.q);
+        v2 = add_mod(v2, d[2 * D.d_ps + o], m.q);
+    }
+    d[o] = v0;
+    d[D.d_ps + o] = v1;
+    d[2 * D.d_ps + o] = v2;
+}
+
+void launch_tensor_sum(const DevTables& T, int nl, const TensorSumDesc& D, hipStream_t st) {
+    ProfScope prof_(PK_TENSOR, (4.0 * D.n + 3.0 * (1 + D.acc)) * nl * D.nct * 8.0 * (1 << T.log_n), st);
+    const int N = 1 << T.log_n;
+    dim3 grid(ceil_div(N, TPB), nl, D.nct);
+    hipLaunchKernelGGL(k_tensor_sum, grid, dim3(TPB), 0, st, T, D);
+}
+
 // sum of up to 16 (ciphertext limb x mask) products, one REDC per output
 // masks are shared by every ciphertext of the group: loaded once, reused per member
 __global__ __launch_bounds__(TPB) void k_mask_mac(DevTables T, MacDesc D, u64* out, int64_t out_ps, int acc,

@@ -126,6 +126,17 @@ struct MultiMacDesc {
 };
 void launch_mask_mac_multi(const DevTables& T, int nl, int npoly, const MultiMacDesc& D, hipStream_t st);
 
+// sum_j A_j (x) B_j of up to 16 pairs of degree-1 groups into a degree-2 group (+= with acc)
+struct TensorSumDesc {
+    const u64* a[16];
+    const u64* b[16];
+    int64_t a_ps[16], a_cs[16], b_ps[16], b_cs[16];
+    u64* d;
+    int64_t d_ps, d_cs;
+    int n, nct, acc;
+};
+void launch_tensor_sum(const DevTables& T, int nl, const TensorSumDesc& D, hipStream_t st);
+
 struct MacDesc {
     const u64* in[16];
     const u64* mask[16];
