@@ -7,6 +7,7 @@
 // constructions named at each kernel.
 #include "kernels.hpp"
 #include <cstring>
+#include <stdexcept>
 
 #include <cstdio>
 #include <string>
@@ -129,6 +130,12 @@ __device__ __forceinline__ int lds_at(int a) {
 }
 #define NTT_LDS (NTT_E + NTT_E / 32)
 
+// two consecutive residues per lane: 16-byte global loads and stores (the limb buffers and
+// their strides are multiples of 2 elements and 16-byte aligned; the launchers check)
+typedef u64 u64x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u64x2 ld2(const u64* p) { return *reinterpret_cast<const u64x2*>(p); }
+__device__ __forceinline__ void st2(u64* p, u64x2 v) { *reinterpret_cast<u64x2*>(p) = v; }
+
 // stages s0 .. s0+R-1 of a length-2^L forward transform; each thread owns 8/2^R groups of
 // 2^R elements.  Within a group, stage s0+r has 2^r distinct twiddles (one per block of
 // 2*half consecutive elements), loaded once each.
@@ -249,11 +256,16 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_cols(DevTables T, Jobs J) {
     const u64* W = T.psi + (int64_t)mi * N;
     const u64* Ws = T.psi_sh + (int64_t)mi * N;
     const int c0 = blockIdx.x * C;
-    for (int e = threadIdx.x; e < NTT_E; e += TPB) s[e] = a[(int64_t)(e >> logC) * N2 + c0 + (e & (C - 1))];
+    for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB) {
+        const u64x2 v = ld2(a + (int64_t)(e >> logC) * N2 + c0 + (e & (C - 1)));
+        s[e] = v.x;
+        s[e + 1] = v.y;
+    }
     __syncthreads();
     fwd_all<false>(s, L1, logC, 1, W, Ws, q);
     // output stays lazy in [0, 4q) for the row pass
-    for (int e = threadIdx.x; e < NTT_E; e += TPB) a[(int64_t)(e >> logC) * N2 + c0 + (e & (C - 1))] = s[e];
+    for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB)
+        st2(a + (int64_t)(e >> logC) * N2 + c0 + (e & (C - 1)), u64x2{s[e], s[e + 1]});
 }
 
 __device__ __forceinline__ int perm_g(int j, u64 g, int log_n);
@@ -268,7 +280,11 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E
     const u64 q = T.mods[mi].q, q2 = 2 * q;
     const u64* W = T.psi + (int64_t)mi * N;
     const u64* Ws = T.psi_sh + (int64_t)mi * N;
-    for (int e = threadIdx.x; e < N2; e += TPB) s[lds_at<true>(e)] = a[e];
+    for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
+        const u64x2 v = ld2(a + e);
+        s[lds_at<true>(e)] = v.x;
+        s[lds_at<true>(e + 1)] = v.y;
+    }
     __syncthreads();
     if (N2 == NTT_E) {
         fwd_all<true>(s, L2, 0, (u64)(N1 + r), W, Ws, q);
@@ -288,9 +304,9 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E
         }
     }
     if (!E.on) {
-        for (int e = threadIdx.x; e < N2; e += TPB) {
-            u64 v = red4(s[lds_at<true>(e)], q2);
-            a[e] = v >= q ? v - q : v;
+        for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
+            const u64 v0 = red4(s[lds_at<true>(e)], q2), v1 = red4(s[lds_at<true>(e + 1)], q2);
+            st2(a + e, u64x2{v0 >= q ? v0 - q : v0, v1 >= q ? v1 - q : v1});
         }
         return;
     }
@@ -302,15 +318,37 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E
     const u64* mask = E.mask ? E.mask + (int64_t)t * N : nullptr;
     const u64* acc = E.acc[p] ? E.acc[p] + c * E.acc_cs + (int64_t)t * N : nullptr;
     const u64 qninv = T.mods[mi].qninv;
-    for (int e = threadIdx.x; e < N2; e += TPB) {
-        u64 v = red4(s[lds_at<true>(e)], q2);
-        v = v >= q ? v - q : v;
+    for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
         const int i = r * N2 + e;
-        u64 w = mul_shoup(sub_mod(u[i], v, q), pi, pis, q);
-        if (add) w = add_mod(w, add[E.g == 1 ? i : perm_g(i, E.g, T.log_n)], q);
-        if (mask) w = mul_mont(w, mask[i], q, qninv);
-        if (acc) w = add_mod(w, acc[i], q);
-        out[i] = w;
+        const u64x2 uu = ld2(u + i);
+        u64 w[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            u64 v = red4(s[lds_at<true>(e + h)], q2);
+            v = v >= q ? v - q : v;
+            w[h] = mul_shoup(sub_mod(uu[h], v, q), pi, pis, q);
+        }
+        if (add) {
+            if (E.g == 1) {
+                const u64x2 ad = ld2(add + i);
+                w[0] = add_mod(w[0], ad.x, q);
+                w[1] = add_mod(w[1], ad.y, q);
+            } else {
+                w[0] = add_mod(w[0], add[perm_g(i, E.g, T.log_n)], q);
+                w[1] = add_mod(w[1], add[perm_g(i + 1, E.g, T.log_n)], q);
+            }
+        }
+        if (mask) {
+            const u64x2 m = ld2(mask + i);
+            w[0] = mul_mont(w[0], m.x, q, qninv);
+            w[1] = mul_mont(w[1], m.y, q, qninv);
+        }
+        if (acc) {
+            const u64x2 ac = ld2(acc + i);
+            w[0] = add_mod(w[0], ac.x, q);
+            w[1] = add_mod(w[1], ac.y, q);
+        }
+        st2(out + i, u64x2{w[0], w[1]});
     }
 }
 
@@ -326,7 +364,11 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_rows(DevTables T, Jobs J) {
     const u64 q = mp_.q, q2 = 2 * q;
     const u64* W = T.ipsi + (int64_t)mi * N;
     const u64* Ws = T.ipsi_sh + (int64_t)mi * N;
-    for (int e = threadIdx.x; e < N2; e += TPB) s[lds_at<true>(e)] = a[e];
+    for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
+        const u64x2 v = ld2(a + e);
+        s[lds_at<true>(e)] = v.x;
+        s[lds_at<true>(e + 1)] = v.y;
+    }
     __syncthreads();
     if (N2 == NTT_E) {
         inv_all<true>(s, L2, 0, (u64)(N1 + r), W, Ws, q);
@@ -345,9 +387,12 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_rows(DevTables T, Jobs J) {
         }
     }
     if (L1 == 0) {
-        for (int e = threadIdx.x; e < N2; e += TPB) a[e] = mul_shoup(s[lds_at<true>(e)], mp_.ninv, mp_.ninv_sh, q);
+        for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB)
+            st2(a + e, u64x2{mul_shoup(s[lds_at<true>(e)], mp_.ninv, mp_.ninv_sh, q),
+                             mul_shoup(s[lds_at<true>(e + 1)], mp_.ninv, mp_.ninv_sh, q)});
     } else {
-        for (int e = threadIdx.x; e < N2; e += TPB) a[e] = s[lds_at<true>(e)];  // lazy in [0, 2q)
+        for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB)  // lazy in [0, 2q)
+            st2(a + e, u64x2{s[lds_at<true>(e)], s[lds_at<true>(e + 1)]});
     }
 }
 
@@ -363,15 +408,35 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_cols(DevTables T, Jobs J) {
     const u64* W = T.ipsi + (int64_t)mi * N;
     const u64* Ws = T.ipsi_sh + (int64_t)mi * N;
     const int c0 = blockIdx.x * C;
-    for (int e = threadIdx.x; e < NTT_E; e += TPB) s[e] = a[(int64_t)(e >> logC) * N2 + c0 + (e & (C - 1))];
+    for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB) {
+        const u64x2 v = ld2(a + (int64_t)(e >> logC) * N2 + c0 + (e & (C - 1)));
+        s[e] = v.x;
+        s[e + 1] = v.y;
+    }
     __syncthreads();
     inv_all<false>(s, L1, logC, 1, W, Ws, q);
-    for (int e = threadIdx.x; e < NTT_E; e += TPB)
-        a[(int64_t)(e >> logC) * N2 + c0 + (e & (C - 1))] = mul_shoup(s[e], mp_.ninv, mp_.ninv_sh, q);
+    for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB)
+        st2(a + (int64_t)(e >> logC) * N2 + c0 + (e & (C - 1)),
+            u64x2{mul_shoup(s[e], mp_.ninv, mp_.ninv_sh, q), mul_shoup(s[e + 1], mp_.ninv, mp_.ninv_sh, q)});
+}
+
+static bool misaligned16(const void* p) { return ((uintptr_t)p & 15) != 0; }
+
+// the NTT kernels move two residues per lane with 16-byte accesses
+static void check_ntt_alignment(const Jobs& J, const Epi* E) {
+    bool bad = misaligned16(J.base) || (J.cstride & 1);
+    if (E && E->on) {
+        bad = bad || misaligned16(E->u) || ((E->u_cs | E->u_ps | E->add_cs | E->out_cs | E->acc_cs) & 1) ||
+              misaligned16(E->mask);
+        for (int p = 0; p < 2; ++p) bad = bad || misaligned16(E->add[p]) || misaligned16(E->out[p]) ||
+                                          misaligned16(E->acc[p]);
+    }
+    if (bad) throw std::runtime_error("NTT operand not 16-byte aligned");
 }
 
 void launch_ntt_moddown(const DevTables& T, const Jobs& J, const Epi& E, hipStream_t st) {
     if (J.n == 0 || J.nct == 0) return;
+    check_ntt_alignment(J, &E);
     const int N = 1 << T.log_n, N1 = 1 << T.n1_log;
     dim3 grid_rows(N1, J.n * J.nct), grid_cols(N / NTT_E, J.n * J.nct);
     const double limbs = (double)J.n * J.nct;
@@ -389,6 +454,7 @@ void launch_ntt_moddown(const DevTables& T, const Jobs& J, const Epi& E, hipStre
 
 void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st) {
     if (J.n == 0 || J.nct == 0) return;
+    check_ntt_alignment(J, nullptr);
     Epi E;
     E.on = 0;
     const int N = 1 << T.log_n, N1 = 1 << T.n1_log;
