@@ -219,6 +219,54 @@ void Ctx::build_tables() {
     T.n1_log = log_n - T.n2_log;
     host_mods = mp;
 
+    // ---- row-pass twiddles in consumption order (N >= 2^11): row r of the second pass works
+    // on twiddle exponents (N1 + r) 2^st + j; a group J of a round starting at stage s0 uses, for
+    // its stages s0 + i (forward) or s0 - i (inverse), the pairs at (N1 + r) 2^st + (J << shift) + b
+    T.rtw = T.irtw = nullptr;
+    if (T.n2_log == 11) {
+        const int N1 = 1 << T.n1_log;
+        std::vector<u64> rtw((size_t)M * N1 * ROW_TW * 2), irtw((size_t)M * N1 * ROW_TW * 2);
+        static const int fr[4][2] = {{0, 3}, {3, 3}, {6, 3}, {9, 2}};
+        static const int ir[4][2] = {{10, 3}, {7, 3}, {4, 3}, {1, 2}};
+        for (int m = 0; m < M; ++m)
+            for (int r = 0; r < N1; ++r) {
+                const int64_t X = N1 + r;
+                const size_t o = ((size_t)m * N1 + r) * ROW_TW * 2;
+                size_t pos = 0;
+                for (const auto& rd : fr) {
+                    const int s0 = rd[0], R = rd[1];
+                    for (int J = 0; J < (1 << s0); ++J)
+                        for (int i = 0; i < R; ++i)
+                            for (int b = 0; b < (1 << i); ++b) {
+                                const size_t k = (size_t)m * N + (X << (s0 + i)) + ((int64_t)J << i) + b;
+                                rtw[o + 2 * pos] = psi[k];
+                                rtw[o + 2 * pos + 1] = psi_sh[k];
+                                ++pos;
+                            }
+                }
+                if (pos != ROW_TW) throw HeError(HE_EINVAL);
+                pos = 0;
+                for (const auto& rd : ir) {
+                    const int s0 = rd[0], R = rd[1], G = 1 << R;
+                    for (int J = 0; J < ((2048 / G) >> (11 - s0 - 1)); ++J)
+                        for (int i = 0; i < R; ++i)
+                            for (int b = 0; b < (G >> (i + 1)); ++b) {
+                                const size_t k = (size_t)m * N + (X << (s0 - i)) + ((int64_t)J << (R - 1 - i)) + b;
+                                irtw[o + 2 * pos] = ipsi[k];
+                                irtw[o + 2 * pos + 1] = ipsi_sh[k];
+                                ++pos;
+                            }
+                }
+                if (pos != ROW_TW) throw HeError(HE_EINVAL);
+            }
+        d_rtw = std::make_unique<DBuf>(this, rtw.size());
+        d_irtw = std::make_unique<DBuf>(this, irtw.size());
+        upload(this, d_rtw->p, rtw.data(), rtw.size() * 8);
+        upload(this, d_irtw->p, irtw.data(), irtw.size() * 8);
+        T.rtw = d_rtw->p;
+        T.irtw = d_irtw->p;
+    }
+
     // ---- rescale constants: qinv[l][i] = q_l^-1 mod q_i
     std::vector<u64> qi((size_t)n_q * n_q, 0), qis((size_t)n_q * n_q, 0);
     for (int l = 1; l < n_q; ++l)

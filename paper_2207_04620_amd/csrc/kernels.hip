@@ -245,6 +245,224 @@ __device__ __forceinline__ void inv_all(u64* s, int L, int logT, u64 X, const u6
     }
 }
 
+// ---- row pass of a 2048-point block (N2 = 2^11), round structure fixed at compile time:
+// forward stages 0-2, 3-5, 6-8, 9-10; inverse 10-8, 7-5, 4-2, 1-0.  A group of 2^R elements
+// base + k d (base = (J << (ld + R)) + (g mod d)) sits at padded offsets base' + k d + (k d >> 5)
+// from its padded base, so its LDS accesses are one address plus constants; its 2^R - 1
+// twiddle pairs (w, w') are contiguous in a per-row table built on the host in the order the
+// round consumes them (ROW_TW pairs per row, round after round, group J after group J).
+template <int R, int S0>
+__device__ __forceinline__ void fwd_row_round(u64* s, const u64* __restrict__ tw, int off, u64 q) {
+    constexpr int G = 1 << R, NG = 8 / G, LD = 11 - S0 - R, D = 1 << LD;
+    const u64 q2 = 2 * q;
+#pragma unroll
+    for (int gg = 0; gg < NG; ++gg) {
+        const int g = gg * TPB + threadIdx.x;
+        const int J = g >> LD;
+        const int base = (J << (LD + R)) + (g & (D - 1));
+        u64* sb = s + base + (base >> 5);
+        u64 x[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) x[k] = sb[k * D + ((k * D) >> 5)];
+        const u64* t = tw + 2 * (off + J * (G - 1));
+        u64x2 w[G - 1];
+#pragma unroll
+        for (int i = 0; i < G - 1; ++i) w[i] = ld2(t + 2 * i);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int half = G >> (r + 1);
+#pragma unroll
+            for (int b = 0; b < (1 << r); ++b) {
+                const u64x2 wb = w[(1 << r) - 1 + b];
+#pragma unroll
+                for (int k = b * 2 * half; k < b * 2 * half + half; ++k) {
+                    const u64 U = red4(x[k], q2);
+                    const u64 V = mul_shoup_lazy(x[k + half], wb.x, wb.y, q);
+                    x[k] = U + V;
+                    x[k + half] = U - V + q2;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) sb[k * D + ((k * D) >> 5)] = x[k];
+    }
+}
+
+template <int R, int S0>
+__device__ __forceinline__ void inv_row_round(u64* s, const u64* __restrict__ tw, int off, u64 q) {
+    constexpr int G = 1 << R, NG = 8 / G, LD = 11 - S0 - 1, D = 1 << LD;
+    const u64 q2 = 2 * q;
+#pragma unroll
+    for (int gg = 0; gg < NG; ++gg) {
+        const int g = gg * TPB + threadIdx.x;
+        const int J = g >> LD;
+        const int base = (J << (LD + R)) + (g & (D - 1));
+        u64* sb = s + base + (base >> 5);
+        u64 x[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) x[k] = sb[k * D + ((k * D) >> 5)];
+        const u64* t = tw + 2 * (off + J * (G - 1));
+        u64x2 w[G - 1];
+#pragma unroll
+        for (int i = 0; i < G - 1; ++i) w[i] = ld2(t + 2 * i);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int half = 1 << r;
+#pragma unroll
+            for (int b = 0; b < (G >> (r + 1)); ++b) {
+                const u64x2 wb = w[G - (G >> r) + b];
+#pragma unroll
+                for (int k = b * 2 * half; k < b * 2 * half + half; ++k) {
+                    const u64 U = x[k], V = x[k + half];
+                    x[k] = red4(U + V, q2);
+                    x[k + half] = mul_shoup_lazy(U - V + q2, wb.x, wb.y, q);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) sb[k * D + ((k * D) >> 5)] = x[k];
+    }
+}
+
+__device__ __forceinline__ void fwd_rows_2048(u64* s, const u64* tw, u64 q) {
+    fwd_row_round<3, 0>(s, tw, 0, q);
+    __syncthreads();
+    fwd_row_round<3, 3>(s, tw, 7, q);
+    __syncthreads();
+    fwd_row_round<3, 6>(s, tw, 63, q);
+    __syncthreads();
+    fwd_row_round<2, 9>(s, tw, 511, q);
+    __syncthreads();
+}
+
+__device__ __forceinline__ void inv_rows_2048(u64* s, const u64* tw, u64 q) {
+    inv_row_round<3, 10>(s, tw, 0, q);
+    __syncthreads();
+    inv_row_round<3, 7>(s, tw, 1792, q);
+    __syncthreads();
+    inv_row_round<3, 4>(s, tw, 2016, q);
+    __syncthreads();
+    inv_row_round<2, 1>(s, tw, 2044, q);
+    __syncthreads();
+}
+
+// ---- column pass with L1 <= 5 stages (N <= 2^16): the 2^(11 - L1) >= 64 columns of a
+// block make the group index g >> (11 - L1) the same for the 64 lanes of a wave, so each
+// twiddle is one scalar load shared by the wave.
+template <int R, int S0, int L1>
+__device__ __forceinline__ void fwd_col_round(u64* s, const u64* __restrict__ W, const u64* __restrict__ Ws,
+                                              u64 q) {
+    constexpr int G = 1 << R, NG = 8 / G, LD = L1 - S0 - R, D = 1 << LD, LOGT = 11 - L1, TC = 1 << LOGT;
+    const u64 q2 = 2 * q;
+#pragma unroll
+    for (int gg = 0; gg < NG; ++gg) {
+        const int g = gg * TPB + threadIdx.x;
+        const int u = g & (TC - 1);
+        const int gi = __builtin_amdgcn_readfirstlane(g >> LOGT);
+        const int J = gi >> LD;
+        const int base = (J << (LD + R)) + (gi & (D - 1));
+        u64 x[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) x[k] = s[((base + k * D) << LOGT) + u];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int half = G >> (r + 1);
+#pragma unroll
+            for (int b = 0; b < (1 << r); ++b) {
+                const int idx = (1 << (S0 + r)) + (J << r) + b;
+                const u64 w = W[idx], ws = Ws[idx];
+#pragma unroll
+                for (int k = b * 2 * half; k < b * 2 * half + half; ++k) {
+                    const u64 U = red4(x[k], q2);
+                    const u64 V = mul_shoup_lazy(x[k + half], w, ws, q);
+                    x[k] = U + V;
+                    x[k + half] = U - V + q2;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) s[((base + k * D) << LOGT) + u] = x[k];
+    }
+}
+
+template <int R, int S0, int L1>
+__device__ __forceinline__ void inv_col_round(u64* s, const u64* __restrict__ W, const u64* __restrict__ Ws,
+                                              u64 q) {
+    constexpr int G = 1 << R, NG = 8 / G, LD = L1 - S0 - 1, D = 1 << LD, LOGT = 11 - L1, TC = 1 << LOGT;
+    const u64 q2 = 2 * q;
+#pragma unroll
+    for (int gg = 0; gg < NG; ++gg) {
+        const int g = gg * TPB + threadIdx.x;
+        const int u = g & (TC - 1);
+        const int gi = __builtin_amdgcn_readfirstlane(g >> LOGT);
+        const int J = gi >> LD;
+        const int base = (J << (LD + R)) + (gi & (D - 1));
+        u64 x[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) x[k] = s[((base + k * D) << LOGT) + u];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int half = 1 << r;
+#pragma unroll
+            for (int b = 0; b < (G >> (r + 1)); ++b) {
+                const int idx = (1 << (S0 - r)) + (J << (R - 1 - r)) + b;
+                const u64 w = W[idx], ws = Ws[idx];
+#pragma unroll
+                for (int k = b * 2 * half; k < b * 2 * half + half; ++k) {
+                    const u64 U = x[k], V = x[k + half];
+                    x[k] = red4(U + V, q2);
+                    x[k + half] = mul_shoup_lazy(U - V + q2, w, ws, q);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) s[((base + k * D) << LOGT) + u] = x[k];
+    }
+}
+
+template <int L1, int S0>
+__device__ __forceinline__ void fwd_cols_from(u64* s, const u64* W, const u64* Ws, u64 q) {
+    if constexpr (S0 < L1) {
+        constexpr int R = L1 - S0 >= 3 ? 3 : L1 - S0;
+        fwd_col_round<R, S0, L1>(s, W, Ws, q);
+        __syncthreads();
+        fwd_cols_from<L1, S0 + R>(s, W, Ws, q);
+    }
+}
+
+template <int L1, int ST>
+__device__ __forceinline__ void inv_cols_from(u64* s, const u64* W, const u64* Ws, u64 q) {
+    if constexpr (ST >= 0) {
+        constexpr int R = ST + 1 >= 3 ? 3 : ST + 1;
+        inv_col_round<R, ST, L1>(s, W, Ws, q);
+        __syncthreads();
+        inv_cols_from<L1, ST - R>(s, W, Ws, q);
+    }
+}
+
+// column stages of a block: compile-time rounds for L1 <= 5, the generic rounds beyond
+__device__ __forceinline__ void fwd_cols_any(u64* s, int L1, const u64* W, const u64* Ws, u64 q) {
+    switch (L1) {
+        case 1: fwd_cols_from<1, 0>(s, W, Ws, q); break;
+        case 2: fwd_cols_from<2, 0>(s, W, Ws, q); break;
+        case 3: fwd_cols_from<3, 0>(s, W, Ws, q); break;
+        case 4: fwd_cols_from<4, 0>(s, W, Ws, q); break;
+        case 5: fwd_cols_from<5, 0>(s, W, Ws, q); break;
+        default: fwd_all<false>(s, L1, 11 - L1, 1, W, Ws, q); break;
+    }
+}
+
+__device__ __forceinline__ void inv_cols_any(u64* s, int L1, const u64* W, const u64* Ws, u64 q) {
+    switch (L1) {
+        case 1: inv_cols_from<1, 0>(s, W, Ws, q); break;
+        case 2: inv_cols_from<2, 1>(s, W, Ws, q); break;
+        case 3: inv_cols_from<3, 2>(s, W, Ws, q); break;
+        case 4: inv_cols_from<4, 3>(s, W, Ws, q); break;
+        case 5: inv_cols_from<5, 4>(s, W, Ws, q); break;
+        default: inv_all<false>(s, L1, 11 - L1, 1, W, Ws, q); break;
+    }
+}
+
 __global__ __launch_bounds__(TPB) void k_ntt_fwd_cols(DevTables T, Jobs J) {
     __shared__ u64 s[NTT_E];
     const int N = 1 << T.log_n, L1 = T.n1_log, N2 = N >> L1;
@@ -262,7 +480,7 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_cols(DevTables T, Jobs J) {
         s[e + 1] = v.y;
     }
     __syncthreads();
-    fwd_all<false>(s, L1, logC, 1, W, Ws, q);
+    fwd_cols_any(s, L1, W, Ws, q);
     // output stays lazy in [0, 4q) for the row pass
     for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB)
         st2(a + (int64_t)(e >> logC) * N2 + c0 + (e & (C - 1)), u64x2{s[e], s[e + 1]});
@@ -287,7 +505,7 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E
     }
     __syncthreads();
     if (N2 == NTT_E) {
-        fwd_all<true>(s, L2, 0, (u64)(N1 + r), W, Ws, q);
+        fwd_rows_2048(s, T.rtw + ((int64_t)mi * N1 + r) * (2 * ROW_TW), q);
     } else {  // small rings: plain radix-2 stages (N2 < 2048 only when N < 2048)
         for (int st = 0; st < L2; st++) {
             const int lt = L2 - st - 1, t = 1 << lt;
@@ -371,7 +589,7 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_rows(DevTables T, Jobs J) {
     }
     __syncthreads();
     if (N2 == NTT_E) {
-        inv_all<true>(s, L2, 0, (u64)(N1 + r), W, Ws, q);
+        inv_rows_2048(s, T.irtw + ((int64_t)mi * N1 + r) * (2 * ROW_TW), q);
     } else {
         for (int st = L2 - 1; st >= 0; st--) {
             const int lt = L2 - st - 1, t = 1 << lt;
@@ -414,7 +632,7 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_cols(DevTables T, Jobs J) {
         s[e + 1] = v.y;
     }
     __syncthreads();
-    inv_all<false>(s, L1, logC, 1, W, Ws, q);
+    inv_cols_any(s, L1, W, Ws, q);
     for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB)
         st2(a + (int64_t)(e >> logC) * N2 + c0 + (e & (C - 1)),
             u64x2{mul_shoup(s[e], mp_.ninv, mp_.ninv_sh, q), mul_shoup(s[e + 1], mp_.ninv, mp_.ninv_sh, q)});

@@ -34,12 +34,18 @@ struct ModMap {
 };
 
 // Device-resident tables of one context.
+#define ROW_TW 2047  // twiddle pairs per row of the 2048-point row pass
+
 struct DevTables {
     const ModP* mods;    // [M]
     const u64* psi;      // [M][N]  psi^(bitrev k)
     const u64* psi_sh;   // [M][N]
     const u64* ipsi;     // [M][N]  psi^-(bitrev k)
     const u64* ipsi_sh;  // [M][N]
+    // row-pass twiddle pairs (w, w') for N >= 2^11, [M][N1][ROW_TW][2], each row's in the order
+    // its rounds consume them (forward: rtw, inverse: irtw)
+    const u64* rtw;
+    const u64* irtw;
     int log_n;
     int n1_log;  // column-pass stages
     int n2_log;  // row-pass stages

@@ -64,7 +64,7 @@ def test_moduli_match(small):
     assert small.g.moduli == small.o.moduli
 
 
-@pytest.mark.parametrize("log_n", [11, 12, 14, 15, 16])
+@pytest.mark.parametrize("log_n", [8, 10, 11, 12, 13, 14, 15, 16, 17])
 def test_ntt_matches_oracle_evaluation_order(he, log_n):
     import torch
     prm = I.Params(f"ntt{log_n}", log_n, [60, 45, 40], [50], 1, 40.0, 3, [])
