@@ -161,8 +161,10 @@ class Ciphertext:
         self.ctx, self.ptr = ctx, ptr
 
     def __del__(self):
+        # the context holds the free function, so this also works while the interpreter
+        # tears down module globals
         if getattr(self, "ptr", None) and self.ctx.ptr:
-            lib().he_ct_free(self.ptr)
+            self.ctx._ct_free(self.ptr)
             self.ptr = None
 
     def info(self):
@@ -203,6 +205,7 @@ class Context:
 
     def __init__(self, params, schedule: int = SCHED_RELIN_EACH, h_list=None, stream=None):
         L = lib()
+        self._ct_free, self._ctx_destroy = L.he_ct_free, L.he_ctx_destroy
         self.params = params
         self.n = 1 << params.log_n
         qb = (C.c_uint32 * len(params.q_bits))(*params.q_bits)
@@ -224,8 +227,8 @@ class Context:
         self.scale = 2.0 ** params.log_scale
 
     def close(self):
-        if self.ptr:
-            lib().he_ctx_destroy(self.ptr)
+        if getattr(self, "ptr", None):
+            self._ctx_destroy(self.ptr)
             self.ptr = None
 
     def __del__(self):
@@ -438,6 +441,8 @@ class Server:
         self.ctx = ctx
         cfg = _ServeConfig(mem_budget_bytes, max_batch, min_batch, max_wait_us)
         out = C.c_void_p()
+        self.ptr = None
+        self._stop = lib().he_serve_stop
         _chk(lib().he_serve_start(ctx.ptr, C.byref(cfg), C.byref(out)), "he_serve_start")
         self.ptr = out.value
         self._inputs = {}
@@ -461,9 +466,11 @@ class Server:
         return Ciphertext(self.ctx, res.value), lat.value
 
     def stop(self):
-        if self.ptr:
-            _chk(lib().he_serve_stop(self.ptr), "he_serve_stop")
+        if getattr(self, "ptr", None):
+            code = self._stop(self.ptr)
             self.ptr = None
+            if code != 0:
+                raise HEError(code, "he_serve_stop")
 
     def __del__(self):
         self.stop()
