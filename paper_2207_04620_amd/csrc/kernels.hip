@@ -8,6 +8,7 @@
 #include "kernels.hpp"
 #include <cstring>
 #include <stdexcept>
+#include <type_traits>
 
 #include <cstdio>
 #include <string>
@@ -706,47 +707,66 @@ void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st)
 template <int NS>
 __global__ __launch_bounds__(TPB) void k_baseconv(DevTables T, ConvDesc D) {
     // the block's slice of the constant table (NS sources x up to BC_TG targets) goes to LDS
-    // once; the sources are read and prepared once for all the targets of the slice
+    // once; the sources are read and prepared once for all the targets of the slice.  Each
+    // thread converts two adjacent slots (16-byte loads and stores, two independent sums).
     __shared__ u64 tab[NS * BC_TG * 2];
     __shared__ ModP tm[BC_TG];
     const int N = 1 << T.log_n;
-    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int i = 2 * (blockIdx.x * TPB + threadIdx.x);
     const int p = blockIdx.z % D.npoly, c = blockIdx.z / D.npoly;
     const int t0 = blockIdx.y * BC_TG, nt = min(D.nt - t0, BC_TG);
     for (int e = threadIdx.x; e < NS * nt * 2; e += TPB) {
         const int sI = e / (nt * 2), rem = e % (nt * 2), tt = rem >> 1, w = rem & 1;
-        tab[(sI * BC_TG + tt) * 2 + w] = D.tab[((int64_t)sI * D.tab_ld + D.tcol[t0 + tt]) * 2 + w];
+        const u64 v = D.tab[((int64_t)sI * D.tab_ld + D.tcol[t0 + tt]) * 2 + w];
+        if (w == 0) {  // the multiplier, split at bit 30 (hi word: bits 30.., lo word: bits 0..29)
+            const Split30 sp = split30(v);
+            tab[(sI * BC_TG + tt) * 2] = ((u64)sp.hi << 32) | sp.lo;
+        } else {
+            tab[(sI * BC_TG + tt) * 2 + 1] = v;
+        }
     }
     if (threadIdx.x < nt) tm[threadIdx.x] = T.mods[D.dmod[t0 + threadIdx.x]];
     __syncthreads();
     if (i >= N) return;
-    u64 y[NS];
-    u64 negm[NS];
+    Split30 y[NS][2];
+    u64 negm[NS][2];
     const u64* src = D.src + c * D.src_cstride + p * D.src_pstride;
 #pragma unroll
     for (int s = 0; s < NS; s++) {
         const ModP m = T.mods[D.smod[s]];
-        const u64 v = mul_shoup(src[(int64_t)s * N + i], D.hinv[s], D.hinv_sh[s], m.q);
-        y[s] = v;
-        negm[s] = v > m.half ? ~0ull : 0ull;
+        const u64x2 x = ld2(src + (int64_t)s * N + i);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const u64 v = mul_shoup(x[h], D.hinv[s], D.hinv_sh[s], m.q);
+            y[s][h] = split30(v);
+            negm[s][h] = v > m.half ? ~0ull : 0ull;
+        }
     }
     u64* dst = D.dst + c * D.dst_cstride + p * D.dst_pstride;
     for (int tt = 0; tt < nt; tt++) {
         const ModP m = tm[tt];
-        Acc128 acc = {0, 0};
+        // NS <= 8 terms y_s t_s plus the centering corrections: column sums stay below 2^64
+        Acc3 acc0 = {0, 0, 0}, acc1 = {0, 0, 0};
 #pragma unroll
         for (int s = 0; s < NS; s++) {
-            mac128(acc, y[s], tab[(s * BC_TG + tt) * 2]);
-            add128(acc, tab[(s * BC_TG + tt) * 2 + 1] & negm[s]);
+            const u64 tw = tab[(s * BC_TG + tt) * 2], tc = tab[(s * BC_TG + tt) * 2 + 1];
+            const Split30 ts = {(u32)tw, (u32)(tw >> 32)};
+            mac3(acc0, y[s][0], ts);
+            mac3(acc1, y[s][1], ts);
+            acc0.c0 += tc & negm[s][0];
+            acc1.c0 += tc & negm[s][1];
         }
-        dst[(int64_t)D.doff[t0 + tt] * N + i] = redc(acc.lo, acc.hi, m.q, m.qninv);
+        st2(dst + (int64_t)D.doff[t0 + tt] * N + i, u64x2{redc3(acc0, m.q, m.qninv), redc3(acc1, m.q, m.qninv)});
     }
 }
 
 void launch_baseconv(const DevTables& T, const ConvDesc& D, hipStream_t st) {
     ProfScope prof_(PK_BASECONV, (double)(D.ns + D.nt) * D.npoly * D.nct * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
-    dim3 grid(ceil_div(N, TPB), ceil_div(D.nt, BC_TG), D.npoly * D.nct);
+    if (misaligned16(D.src) || misaligned16(D.dst) || ((D.src_pstride | D.dst_pstride | D.src_cstride |
+                                                         D.dst_cstride) & 1))
+        throw std::runtime_error("base conversion operand not 16-byte aligned");
+    dim3 grid(ceil_div(N, 2 * TPB), ceil_div(D.nt, BC_TG), D.npoly * D.nct);
     switch (D.ns) {
         case 1: hipLaunchKernelGGL(k_baseconv<1>, grid, dim3(TPB), 0, st, T, D); break;
         case 2: hipLaunchKernelGGL(k_baseconv<2>, grid, dim3(TPB), 0, st, T, D); break;
@@ -970,18 +990,41 @@ void launch_swk_finish(const DevTables& T, int M, u64* b, const u64* a, const u6
 // one rotation's key-switch inner product of one member, reduced: sum_j x_j key_j (+ P
 // sigma_g(c0) on the Q limbs), optionally times a Montgomery-form mask; x are the member's
 // lift words at the automorphism source position
+// up to seven digits (plus the c0 term) use the carry-free column sums with the key words
+// split at bit 30; eight digits use 128-bit accumulation
 template <int NB>
-__device__ __forceinline__ void ip_reduce(const u64* x, u64 z, const u64* kb, const u64* ka, u64 pmont, bool with_c0,
-                                          const ModP& m, u64 mk, bool masked, u64& v0, u64& v1) {
-    Acc128 a0 = {0, 0}, a1 = {0, 0};
+using IpKey = typename std::conditional<(NB <= 7), Split30, u64>::type;
+template <int NB>
+__device__ __forceinline__ IpKey<NB> ip_key(u64 v) {
+    if constexpr (NB <= 7) return split30(v);
+    else return v;
+}
+
+template <int NB>
+__device__ __forceinline__ void ip_reduce(const u64* x, u64 z, const IpKey<NB>* kb, const IpKey<NB>* ka, u64 pmont,
+                                          bool with_c0, const ModP& m, u64 mk, bool masked, u64& v0, u64& v1) {
+    if constexpr (NB <= 7) {
+        Acc3 a0 = {0, 0, 0}, a1 = {0, 0, 0};
 #pragma unroll
-    for (int j = 0; j < NB; j++) {
-        mac128(a0, x[j], kb[j]);
-        mac128(a1, x[j], ka[j]);
+        for (int j = 0; j < NB; j++) {
+            const Split30 xs = split30(x[j]);
+            mac3(a0, xs, kb[j]);
+            mac3(a1, xs, ka[j]);
+        }
+        if (with_c0) mac3(a0, split30(z), split30(pmont));
+        v0 = redc3(a0, m.q, m.qninv);
+        v1 = redc3(a1, m.q, m.qninv);
+    } else {
+        Acc128 a0 = {0, 0}, a1 = {0, 0};
+#pragma unroll
+        for (int j = 0; j < NB; j++) {
+            mac128(a0, x[j], kb[j]);
+            mac128(a1, x[j], ka[j]);
+        }
+        if (with_c0) mac128(a0, z, pmont);
+        v0 = redc(a0.lo, a0.hi, m.q, m.qninv);
+        v1 = redc(a1.lo, a1.hi, m.q, m.qninv);
     }
-    if (with_c0) mac128(a0, z, pmont);
-    v0 = redc(a0.lo, a0.hi, m.q, m.qninv);
-    v1 = redc(a1.lo, a1.hi, m.q, m.qninv);
     if (masked) {
         v0 = mul_mont(v0, mk, m.q, m.qninv);
         v1 = mul_mont(v1, mk, m.q, m.qninv);
@@ -1000,7 +1043,8 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
     const int t = blockIdx.y;
     const int mi = D.mod[t];
     const ModP m = T.mods[mi];
-    u64 kb[NR][NB], ka[NR][NB], mk[NR];
+    IpKey<NB> kb[NR][NB], ka[NR][NB];
+    u64 mk[NR];
     int src[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) {
@@ -1010,8 +1054,8 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
         src[r] = g == 1 ? i : perm_g(i, g, T.log_n);
 #pragma unroll
         for (int j = 0; j < NB; j++) {
-            kb[r][j] = key[(((int64_t)j * 2 + 0) * D.M + mi) * N + i];
-            ka[r][j] = key[(((int64_t)j * 2 + 1) * D.M + mi) * N + i];
+            kb[r][j] = ip_key<NB>(key[(((int64_t)j * 2 + 0) * D.M + mi) * N + i]);
+            ka[r][j] = ip_key<NB>(key[(((int64_t)j * 2 + 1) * D.M + mi) * N + i]);
         }
         mk[r] = mask ? mask[(int64_t)mi * N + i] : 0;
     }

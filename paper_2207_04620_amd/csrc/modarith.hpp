@@ -87,6 +87,39 @@ __device__ __forceinline__ void add128(Acc128& acc, u64 a) {
     acc.hi += (acc.lo < a ? 1 : 0);
 }
 
+// Sums of up to eight products of residues below 2^60 with no carry handling: each operand
+// is split at bit 30 (x = x.hi 2^30 + x.lo), and the four 30 x 30-bit partial products go
+// into three 64-bit column sums, value = c0 + c1 2^30 + c2 2^60.  A product adds < 2^60 to
+// c0 and c2 and < 2^61 to c1, so eight of them (plus one residue per product added to c0)
+// stay below 2^64.  Each partial product is one v_mad_u64_u32.
+struct Split30 {
+    u32 lo, hi;
+};
+struct Acc3 {
+    u64 c0, c1, c2;
+};
+__device__ __forceinline__ Split30 split30(u64 v) { return {(u32)v & 0x3fffffffu, (u32)(v >> 30)}; }
+__device__ __forceinline__ void mac3(Acc3& a, Split30 x, Split30 y) {
+    a.c0 += (u64)x.lo * y.lo;
+    a.c1 += (u64)x.lo * y.hi;
+    a.c1 += (u64)x.hi * y.lo;
+    a.c2 += (u64)x.hi * y.hi;
+}
+// the 128-bit value of the column sums
+__device__ __forceinline__ void acc3_wide(const Acc3& a, u64& lo, u64& hi) {
+    const u64 m1 = a.c1 << 30, m2 = a.c2 << 60;
+    lo = a.c0 + m1;
+    u64 cy = lo < m1 ? 1 : 0;
+    lo += m2;
+    cy += lo < m2 ? 1 : 0;
+    hi = (a.c1 >> 34) + (a.c2 >> 4) + cy;
+}
+__device__ __forceinline__ u64 redc3(const Acc3& a, u64 q, u64 qninv) {
+    u64 lo, hi;
+    acc3_wide(a, lo, hi);
+    return redc(lo, hi, q, qninv);
+}
+
 // x mod q for any 64-bit x
 __device__ __forceinline__ u64 reduce64(u64 x, const ModP& m) {
     u64 qh = __umul64hi(x, m.bar);
