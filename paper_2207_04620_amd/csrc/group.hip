@@ -81,6 +81,9 @@ std::shared_ptr<DBuf> Ctx::g_lift(const Grp& a, int poly) {
     auto lift = std::make_shared<DBuf>(this, (size_t)B * lcs);
     DBuf coef(this, (size_t)B * nl * N);
     copy2d(this, coef.p, (int64_t)nl * N, a.p + poly * a.ps, a.cs, (int64_t)nl * N, B);
+    // with the fused conversion, the inverse transform also applies each digit's (D/q_s)^-1
+    bool fused = true;
+    for (const auto& inf : infos) fused = fused && conv_cols_fits(T, inf.hi - inf.lo);
     {
         Jobs J;
         J.base = coef.p;
@@ -91,7 +94,7 @@ std::shared_ptr<DBuf> Ctx::g_lift(const Grp& a, int poly) {
             J.off[i] = (uint16_t)i;
             J.mod[i] = (uint8_t)i;
         }
-        launch_ntt(T, J, true, stream);
+        launch_ntt(T, J, true, stream, fused ? d_mu_scale->p + (size_t)level * n_q * 2 : nullptr, nl);
     }
     Jobs J;
     J.base = lift->p;
@@ -129,11 +132,13 @@ std::shared_ptr<DBuf> Ctx::g_lift(const Grp& a, int poly) {
             D.hinv[s] = inf.hinv[s];
             D.hinv_sh[s] = inf.hinv_sh[s];
         }
-        launch_baseconv(T, D, stream);
+        D.prescaled = fused ? 1 : 0;
+        if (fused) launch_conv_cols(T, D, stream);
+        else launch_baseconv(T, D, stream);
         copy2d(this, lift->p + ((size_t)j * ne + inf.lo) * N, lcs, a.p + poly * a.ps + (size_t)inf.lo * N, a.cs,
                (int64_t)(inf.hi - inf.lo) * N, B);
     }
-    launch_ntt(T, J, false, stream);
+    launch_ntt(T, J, false, stream, nullptr, 0, !fused);
     return lift;
 }
 
@@ -180,6 +185,8 @@ void Ctx::g_moddown(DBuf& u, int B, int level, const u64* add0, const u64* add1,
                     int64_t acc_cs) {
     const int nl = level + 1, ne = nl + n_p;
     const int64_t ucs = 2 * (int64_t)ne * N, ccs = 2 * (int64_t)nl * N;
+    // with the fused conversion, the inverse transform also applies (P/p_k)^-1
+    const bool fused = conv_cols_fits(T, n_p);
     {
         Jobs J;
         J.base = u.p;
@@ -192,7 +199,7 @@ void Ctx::g_moddown(DBuf& u, int B, int level, const u64* add0, const u64* add1,
                 J.mod[J.n] = (uint8_t)(n_q + k);
                 ++J.n;
             }
-        launch_ntt(T, J, true, stream);
+        launch_ntt(T, J, true, stream, fused ? d_md_scale->p : nullptr, n_p);
     }
     DBuf conv(this, (size_t)B * ccs);
     ConvDesc C;
@@ -219,7 +226,9 @@ void Ctx::g_moddown(DBuf& u, int B, int level, const u64* add0, const u64* add1,
         C.dmod[t] = (uint8_t)t;
         C.tcol[t] = (uint16_t)t;
     }
-    launch_baseconv(T, C, stream);
+    C.prescaled = fused ? 1 : 0;
+    if (fused) launch_conv_cols(T, C, stream);
+    else launch_baseconv(T, C, stream);
     Jobs J;
     J.base = conv.p;
     J.cstride = ccs;
@@ -250,7 +259,7 @@ void Ctx::g_moddown(DBuf& u, int B, int level, const u64* add0, const u64* add1,
     E.acc[0] = acc0;
     E.acc[1] = acc1;
     E.acc_cs = acc_cs;
-    launch_ntt_moddown(T, J, E, stream);
+    launch_ntt_moddown(T, J, E, stream, !fused);
 }
 
 // ModDown(<lift o sigma_g, key>) (+ add) into out, for every member

@@ -353,6 +353,28 @@ void Ctx::build_tables() {
     }
     d_mu_tab = std::make_unique<DBuf>(this, std::max<size_t>(total, 1));
     upload(this, d_mu_tab->p, tab.data(), total * 8);
+
+    // ---- output constants of the inverse transforms that feed a fused base conversion:
+    // N^-1 (D/q_s)^-1 mod q_s as Shoup pairs, ModUp per (level, limb), ModDown per P prime
+    {
+        std::vector<u64> mus((size_t)n_q * n_q * 2, 0), mds((size_t)n_p * 2);
+        for (int l = 0; l < n_q; ++l)
+            for (const auto& inf : mu[l])
+                for (int i = inf.lo; i < inf.hi; ++i) {
+                    const u64 q = mods[i], f = mulmod(invmod((u64)N % q, q), inf.hinv[i - inf.lo], q);
+                    mus[((size_t)l * n_q + i) * 2] = f;
+                    mus[((size_t)l * n_q + i) * 2 + 1] = shoup(f, q);
+                }
+        for (int k = 0; k < n_p; ++k) {
+            const u64 q = mods[n_q + k], f = mulmod(invmod((u64)N % q, q), md_hinv[k], q);
+            mds[2 * k] = f;
+            mds[2 * k + 1] = shoup(f, q);
+        }
+        d_mu_scale = std::make_unique<DBuf>(this, mus.size());
+        upload(this, d_mu_scale->p, mus.data(), mus.size() * 8);
+        d_md_scale = std::make_unique<DBuf>(this, mds.size());
+        upload(this, d_md_scale->p, mds.data(), mds.size() * 8);
+    }
     gauss_cdt(cdt);
 }
 

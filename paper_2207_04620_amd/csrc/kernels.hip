@@ -26,7 +26,8 @@ static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // and each result written once (tables of constants excluded).
 static const char* const kProfNames[PK_COUNT] = {
     "ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "baseconv", "inner_product",
-    "moddown_combine", "rescale_spread", "rescale_combine", "tensor", "mask_mac", "automorph", "elementwise"};
+    "moddown_combine", "rescale_spread", "rescale_combine", "tensor", "mask_mac", "automorph", "elementwise",
+    "conv_ntt_cols"};
 struct ProfRec {
     int kind;
     hipEvent_t a, b;
@@ -572,7 +573,10 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E
 }
 
 // Inverse transform: Gentleman-Sande, bit-reversed input, natural output, then N^-1.
-__global__ __launch_bounds__(TPB) void k_ntt_inv_rows(DevTables T, Jobs J) {
+// The last pass of the inverse transform multiplies by N^-1, or, with 'scale' set, by the
+// per-job constant scale[k mod scale_n] (pairs (c, c')): N^-1 times the (D/q_s)^-1 of a base
+// conversion that follows, so the conversion reads its prepared inputs directly.
+__global__ __launch_bounds__(TPB) void k_ntt_inv_rows(DevTables T, Jobs J, const u64* scale, int scale_n) {
     __shared__ u64 s[NTT_LDS];
     const int N = 1 << T.log_n, L1 = T.n1_log, L2 = T.n2_log, N1 = 1 << L1, N2 = 1 << L2;
     const int job = blockIdx.y, c = job / J.n, k = job % J.n;
@@ -606,16 +610,16 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_rows(DevTables T, Jobs J) {
         }
     }
     if (L1 == 0) {
+        const u64 f = scale ? scale[2 * (k % scale_n)] : mp_.ninv, fs = scale ? scale[2 * (k % scale_n) + 1] : mp_.ninv_sh;
         for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB)
-            st2(a + e, u64x2{mul_shoup(s[lds_at<true>(e)], mp_.ninv, mp_.ninv_sh, q),
-                             mul_shoup(s[lds_at<true>(e + 1)], mp_.ninv, mp_.ninv_sh, q)});
+            st2(a + e, u64x2{mul_shoup(s[lds_at<true>(e)], f, fs, q), mul_shoup(s[lds_at<true>(e + 1)], f, fs, q)});
     } else {
         for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB)  // lazy in [0, 2q)
             st2(a + e, u64x2{s[lds_at<true>(e)], s[lds_at<true>(e + 1)]});
     }
 }
 
-__global__ __launch_bounds__(TPB) void k_ntt_inv_cols(DevTables T, Jobs J) {
+__global__ __launch_bounds__(TPB) void k_ntt_inv_cols(DevTables T, Jobs J, const u64* scale, int scale_n) {
     __shared__ u64 s[NTT_E];
     const int N = 1 << T.log_n, L1 = T.n1_log, N2 = N >> L1;
     const int logC = 11 - L1, C = 1 << logC;
@@ -634,9 +638,66 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_cols(DevTables T, Jobs J) {
     }
     __syncthreads();
     inv_cols_any(s, L1, W, Ws, q);
+    const u64 f = scale ? scale[2 * (k % scale_n)] : mp_.ninv, fs = scale ? scale[2 * (k % scale_n) + 1] : mp_.ninv_sh;
     for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB)
-        st2(a + (int64_t)(e >> logC) * N2 + c0 + (e & (C - 1)),
-            u64x2{mul_shoup(s[e], mp_.ninv, mp_.ninv_sh, q), mul_shoup(s[e + 1], mp_.ninv, mp_.ninv_sh, q)});
+        st2(a + (int64_t)(e >> logC) * N2 + c0 + (e & (C - 1)), u64x2{mul_shoup(s[e], f, fs, q), mul_shoup(s[e + 1], f, fs, q)});
+}
+
+// ---- base conversion fused with the column pass of the forward transform.  A block converts
+// one column block (N1 rows x 2^(11 - L1) columns, 2048 slots) of one target limb from the
+// ns source limbs, which the inverse transform has already multiplied by their (D/q_s)^-1,
+// and runs the column stages on it; the row pass follows as usual.  Workgroups are handed to
+// the 8 XCDs round-robin, so the blocks of all targets of one source block are numbered to
+// run back to back on one XCD, where the source words stay in that XCD's L2.
+template <int NS>
+__global__ __launch_bounds__(TPB) void k_conv_cols(DevTables T, ConvDesc D) {
+    __shared__ u64 s[NTT_E];
+    const int N = 1 << T.log_n, L1 = T.n1_log, N2 = N >> L1;
+    const int logC = 11 - L1, C = 1 << logC;
+    const int tiles = N / NTT_E, npairs = tiles * D.npoly * D.nct;
+    const int lb = blockIdx.x;
+    int pair, t;
+    if ((npairs & 7) == 0) {
+        const int j = lb >> 3;
+        pair = ((j / D.nt) << 3) + (lb & 7);
+        t = j % D.nt;
+    } else {
+        pair = lb / D.nt;
+        t = lb % D.nt;
+    }
+    const int x = pair % tiles, pc = pair / tiles, p = pc % D.npoly, c = pc / D.npoly;
+    const int mi = D.dmod[t];
+    const ModP m = T.mods[mi];
+    Split30 tw[NS];
+    u64 tc[NS], half[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        const int64_t o = ((int64_t)i * D.tab_ld + D.tcol[t]) * 2;
+        tw[i] = split30(D.tab[o]);
+        tc[i] = D.tab[o + 1];
+        half[i] = T.mods[D.smod[i]].half;
+    }
+    const u64* src = D.src + c * D.src_cstride + p * D.src_pstride;
+    const int col0 = x * C;
+    for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB) {
+        const int64_t slot = (int64_t)(e >> logC) * N2 + col0 + (e & (C - 1));
+        Acc3 a0 = {0, 0, 0}, a1 = {0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            const u64x2 y = ld2(src + (int64_t)i * N + slot);
+            mac3(a0, split30(y.x), tw[i]);
+            mac3(a1, split30(y.y), tw[i]);
+            a0.c0 += y.x > half[i] ? tc[i] : 0;
+            a1.c0 += y.y > half[i] ? tc[i] : 0;
+        }
+        s[e] = redc3(a0, m.q, m.qninv);
+        s[e + 1] = redc3(a1, m.q, m.qninv);
+    }
+    __syncthreads();
+    fwd_cols_any(s, L1, T.psi + (int64_t)mi * N, T.psi_sh + (int64_t)mi * N, m.q);
+    u64* a = D.dst + c * D.dst_cstride + p * D.dst_pstride + (int64_t)D.doff[t] * N;
+    for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB)
+        st2(a + (int64_t)(e >> logC) * N2 + col0 + (e & (C - 1)), u64x2{s[e], s[e + 1]});
 }
 
 static bool misaligned16(const void* p) { return ((uintptr_t)p & 15) != 0; }
@@ -653,13 +714,13 @@ static void check_ntt_alignment(const Jobs& J, const Epi* E) {
     if (bad) throw std::runtime_error("NTT operand not 16-byte aligned");
 }
 
-void launch_ntt_moddown(const DevTables& T, const Jobs& J, const Epi& E, hipStream_t st) {
+void launch_ntt_moddown(const DevTables& T, const Jobs& J, const Epi& E, hipStream_t st, bool cols) {
     if (J.n == 0 || J.nct == 0) return;
     check_ntt_alignment(J, &E);
     const int N = 1 << T.log_n, N1 = 1 << T.n1_log;
     dim3 grid_rows(N1, J.n * J.nct), grid_cols(N / NTT_E, J.n * J.nct);
     const double limbs = (double)J.n * J.nct;
-    if (T.n1_log > 0) {
+    if (T.n1_log > 0 && cols) {
         ProfScope p(PK_NTT_FWD_COLS, 16.0 * limbs * N, st, limbs * (N / 2) * T.n1_log);
         hipLaunchKernelGGL(k_ntt_fwd_cols, grid_cols, dim3(TPB), 0, st, T, J);
     }
@@ -671,8 +732,10 @@ void launch_ntt_moddown(const DevTables& T, const Jobs& J, const Epi& E, hipStre
     hipLaunchKernelGGL(k_ntt_fwd_rows, grid_rows, dim3(TPB), 0, st, T, J, E);
 }
 
-void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st) {
+void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st, const u64* scale, int scale_n,
+                bool cols) {
     if (J.n == 0 || J.nct == 0) return;
+    if (scale && (!inverse || scale_n < 1)) throw std::runtime_error("NTT output scale: inverse transforms only");
     check_ntt_alignment(J, nullptr);
     Epi E;
     E.on = 0;
@@ -681,7 +744,7 @@ void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st)
     const double limbs = (double)J.n * J.nct;
     const double bytes = 16.0 * limbs * N, b1 = limbs * (N / 2) * T.n1_log, b2 = limbs * (N / 2) * T.n2_log;
     if (!inverse) {
-        if (T.n1_log > 0) {
+        if (T.n1_log > 0 && cols) {
             ProfScope p(PK_NTT_FWD_COLS, bytes, st, b1);
             hipLaunchKernelGGL(k_ntt_fwd_cols, grid_cols, dim3(TPB), 0, st, T, J);
         }
@@ -690,11 +753,11 @@ void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st)
     } else {
         {
             ProfScope p(PK_NTT_INV_ROWS, bytes, st, b2);
-            hipLaunchKernelGGL(k_ntt_inv_rows, grid_rows, dim3(TPB), 0, st, T, J);
+            hipLaunchKernelGGL(k_ntt_inv_rows, grid_rows, dim3(TPB), 0, st, T, J, scale, scale_n);
         }
         if (T.n1_log > 0) {
             ProfScope p(PK_NTT_INV_COLS, bytes, st, b1);
-            hipLaunchKernelGGL(k_ntt_inv_cols, grid_cols, dim3(TPB), 0, st, T, J);
+            hipLaunchKernelGGL(k_ntt_inv_cols, grid_cols, dim3(TPB), 0, st, T, J, scale, scale_n);
         }
     }
 }
@@ -737,7 +800,7 @@ __global__ __launch_bounds__(TPB) void k_baseconv(DevTables T, ConvDesc D) {
         const u64x2 x = ld2(src + (int64_t)s * N + i);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const u64 v = mul_shoup(x[h], D.hinv[s], D.hinv_sh[s], m.q);
+            const u64 v = D.prescaled ? x[h] : mul_shoup(x[h], D.hinv[s], D.hinv_sh[s], m.q);
             y[s][h] = split30(v);
             negm[s][h] = v > m.half ? ~0ull : 0ull;
         }
@@ -776,6 +839,30 @@ void launch_baseconv(const DevTables& T, const ConvDesc& D, hipStream_t st) {
         case 6: hipLaunchKernelGGL(k_baseconv<6>, grid, dim3(TPB), 0, st, T, D); break;
         case 7: hipLaunchKernelGGL(k_baseconv<7>, grid, dim3(TPB), 0, st, T, D); break;
         default: hipLaunchKernelGGL(k_baseconv<8>, grid, dim3(TPB), 0, st, T, D); break;
+    }
+}
+
+bool conv_cols_fits(const DevTables& T, int ns) { return T.n1_log >= 1 && ns >= 1 && ns <= HE_MAXSRC; }
+
+void launch_conv_cols(const DevTables& T, const ConvDesc& D, hipStream_t st) {
+    if (!conv_cols_fits(T, D.ns) || !D.prescaled) throw std::runtime_error("conv_cols: unsupported shape");
+    if (misaligned16(D.src) || misaligned16(D.dst) || ((D.src_pstride | D.dst_pstride | D.src_cstride |
+                                                         D.dst_cstride) & 1))
+        throw std::runtime_error("conv_cols operand not 16-byte aligned");
+    const int N = 1 << T.log_n;
+    const double units = (double)D.nt * D.npoly * D.nct;
+    ProfScope prof_(PK_CONV_COLS, ((double)D.ns * D.npoly * D.nct + units) * 8.0 * N, st,
+                    units * (N / 2) * T.n1_log);
+    dim3 grid((N / NTT_E) * D.npoly * D.nct * D.nt);
+    switch (D.ns) {
+        case 1: hipLaunchKernelGGL(k_conv_cols<1>, grid, dim3(TPB), 0, st, T, D); break;
+        case 2: hipLaunchKernelGGL(k_conv_cols<2>, grid, dim3(TPB), 0, st, T, D); break;
+        case 3: hipLaunchKernelGGL(k_conv_cols<3>, grid, dim3(TPB), 0, st, T, D); break;
+        case 4: hipLaunchKernelGGL(k_conv_cols<4>, grid, dim3(TPB), 0, st, T, D); break;
+        case 5: hipLaunchKernelGGL(k_conv_cols<5>, grid, dim3(TPB), 0, st, T, D); break;
+        case 6: hipLaunchKernelGGL(k_conv_cols<6>, grid, dim3(TPB), 0, st, T, D); break;
+        case 7: hipLaunchKernelGGL(k_conv_cols<7>, grid, dim3(TPB), 0, st, T, D); break;
+        default: hipLaunchKernelGGL(k_conv_cols<8>, grid, dim3(TPB), 0, st, T, D); break;
     }
 }
 

@@ -63,6 +63,7 @@ struct ConvDesc {
     int64_t dst_pstride;
     int64_t src_cstride = 0, dst_cstride = 0;  // ciphertext strides
     int nct = 1;
+    int prescaled = 0;  // sources already multiplied by (D/q_s)^-1 (in the inverse NTT)
     const u64* tab;
     int tab_ld;  // table row length: entry (s, col) at tab[(s * tab_ld + col) * 2]
     int ns, nt, npoly;
@@ -179,7 +180,7 @@ struct Epi {
 // ------------------------------------------------------------------ launch timing
 enum ProfKind {
     PK_NTT_FWD_COLS = 0, PK_NTT_FWD_ROWS, PK_NTT_INV_ROWS, PK_NTT_INV_COLS, PK_BASECONV, PK_INNER, PK_MODDOWN,
-    PK_RS_SPREAD, PK_RS_COMBINE, PK_TENSOR, PK_MASKMAC, PK_AUTOMORPH, PK_EW, PK_COUNT
+    PK_RS_SPREAD, PK_RS_COMBINE, PK_TENSOR, PK_MASKMAC, PK_AUTOMORPH, PK_EW, PK_CONV_COLS, PK_COUNT
 };
 #include <string>
 // only: null for every kernel kind, else one kind's name; false for an unknown name
@@ -187,9 +188,17 @@ bool prof_enable(bool on, const char* only);
 std::string prof_report();  // JSON: per kernel kind {launches, ms, bytes}; clears the records
 
 // ------------------------------------------------------------------ launchers
-void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st);
-void launch_ntt_moddown(const DevTables& T, const Jobs& J, const Epi& E, hipStream_t st);
+// inverse: the last pass multiplies limb job k by scale[k mod scale_n] (a (c, c') Shoup pair)
+// instead of N^-1 when scale is set; forward: cols = false skips the column pass (done by
+// launch_conv_cols)
+void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st, const u64* scale = nullptr,
+                int scale_n = 0, bool cols = true);
+void launch_ntt_moddown(const DevTables& T, const Jobs& J, const Epi& E, hipStream_t st, bool cols = true);
 void launch_baseconv(const DevTables& T, const ConvDesc& D, hipStream_t st);
+// base conversion of prescaled sources fused with the forward column pass of every target
+// (N > 2^11); the row pass is then run with launch_ntt(..., cols = false)
+bool conv_cols_fits(const DevTables& T, int ns);
+void launch_conv_cols(const DevTables& T, const ConvDesc& D, hipStream_t st);
 void launch_sample(const DevTables& T, const Jobs& J, const SampleArgs& A, hipStream_t st);
 // out[p][i] = a[p][i] (op) b[p][i] over nl limbs (prime map mm) and npoly polys;
 // b_ps = 0 broadcasts one b polynomial to every poly
