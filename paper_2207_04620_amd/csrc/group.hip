@@ -146,7 +146,7 @@ std::shared_ptr<DBuf> Ctx::g_lift(const Grp& a, int poly) {
 // member into u [B][2][ne][N] (added to what u holds with accumulate); with a second
 // (g2, key2) and masks, the masked sum of two rotations of the same lift (one ModDown then
 // serves both)
-void Ctx::g_ks_inner(DBuf& u, const u64* lift, int B, int level, const u64* key, u64 g, const u64* c0,
+void Ctx::g_ks_inner(u64* u, const u64* lift, int B, int level, const u64* key, u64 g, const u64* c0,
                      int64_t c0_cs, const u64* mask, const u64* key2, u64 g2, const u64* mask2, bool accumulate) {
     const int nl = level + 1, ne = nl + n_p;
     const int beta = (int)mu[level].size();
@@ -154,7 +154,7 @@ void Ctx::g_ks_inner(DBuf& u, const u64* lift, int B, int level, const u64* key,
     memset(&D, 0, sizeof D);
     D.lift = lift;
     D.key = key;
-    D.u = u.p;
+    D.u = u;
     D.lift_cs = (int64_t)beta * ne * N;
     D.u_cs = 2 * (int64_t)ne * N;
     D.nct = B;
@@ -180,7 +180,7 @@ void Ctx::g_ks_inner(DBuf& u, const u64* lift, int B, int level, const u64* key,
 // out = ModDown(u) (+ add gathered by add_g) (. mask) (+ acc), for every member; u as made
 // by g_ks_inner.  The combine runs in the epilogue of the forward NTT of the converted
 // special-prime part.
-void Ctx::g_moddown(DBuf& u, int B, int level, const u64* add0, const u64* add1, int64_t add_cs, u64* out0,
+void Ctx::g_moddown(u64* u, int B, int level, const u64* add0, const u64* add1, int64_t add_cs, u64* out0,
                     u64* out1, int64_t out_cs, u64 add_g, const u64* mask, const u64* acc0, const u64* acc1,
                     int64_t acc_cs) {
     const int nl = level + 1, ne = nl + n_p;
@@ -189,7 +189,7 @@ void Ctx::g_moddown(DBuf& u, int B, int level, const u64* add0, const u64* add1,
     const bool fused = conv_cols_fits(T, n_p);
     {
         Jobs J;
-        J.base = u.p;
+        J.base = u;
         J.cstride = ucs;
         J.nct = B;
         J.n = 0;
@@ -204,7 +204,7 @@ void Ctx::g_moddown(DBuf& u, int B, int level, const u64* add0, const u64* add1,
     DBuf conv(this, (size_t)B * ccs);
     ConvDesc C;
     memset(&C, 0, sizeof C);
-    C.src = u.p + (size_t)nl * N;
+    C.src = u + (size_t)nl * N;
     C.src_pstride = (int64_t)ne * N;
     C.src_cstride = ucs;
     C.dst = conv.p;
@@ -243,7 +243,7 @@ void Ctx::g_moddown(DBuf& u, int B, int level, const u64* add0, const u64* add1,
     memset(&E, 0, sizeof E);
     E.on = 1;
     E.nl = nl;
-    E.u = u.p;
+    E.u = u;
     E.u_cs = ucs;
     E.u_ps = (int64_t)ne * N;
     E.add[0] = add0;
@@ -267,27 +267,43 @@ void Ctx::g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, c
                      int64_t add_cs, u64* out0, u64* out1, int64_t out_cs, u64 add_g, const u64* mask,
                      const u64* acc0, const u64* acc1, int64_t acc_cs, const u64* c0, int64_t c0_cs) {
     DBuf u(this, (size_t)B * 2 * (level + 1 + n_p) * N);
-    g_ks_inner(u, lift, B, level, key, g, c0, c0_cs, nullptr, nullptr, 1, nullptr, false);
-    g_moddown(u, B, level, add0, add1, add_cs, out0, out1, out_cs, add_g, mask, acc0, acc1, acc_cs);
+    g_ks_inner(u.p, lift, B, level, key, g, c0, c0_cs, nullptr, nullptr, 1, nullptr, false);
+    g_moddown(u.p, B, level, add0, add1, add_cs, out0, out1, out_cs, add_g, mask, acc0, acc1, acc_cs);
 }
 
-// v1 . Rot(a, k1) + v2 . Rot(a, k2) with both masks applied in the extended basis and a
-// single ModDown (hoisted-ModDown schedule of Step 2)
-Grp Ctx::g_rotate_pair_hoisted(const Grp& a, const u64* lift, int64_t k1, const u64* mask1, int64_t k2,
-                               const u64* mask2, double mask_scale) {
-    const u64 g1 = galois(k1), g2 = galois(k2);
-    if (g1 == 1 || g2 == 1) throw HeError(HE_EUNSUPPORTED);
-    const u64 *key1 = rot_key(g1, false), *key2 = rot_key(g2, false);
-    std::vector<double> sc(a.scale);
-    for (auto& v : sc) v *= mask_scale;
-    Grp out = g_new(a.B, a.level, 1, sc);
-    DBuf u(this, (size_t)a.B * 2 * (a.level + 1 + n_p) * N);
-    g_ks_inner(u, lift, a.B, a.level, key1, g1, a.p, a.cs, mask1, key2, g2, mask2, false);
-    g_moddown(u, a.B, a.level, nullptr, nullptr, 0, out.p, out.p + out.ps, out.cs, 1, nullptr, nullptr, nullptr, 0);
-    cnt[C_ROT] += 2 * a.B;
-    cnt[C_MULPT] += 2 * a.B;
-    cnt[C_ADD] += a.B;
-    return out;
+// Several mask pairs of one ciphertext at once (Step 2 under the hoisted-ModDown schedule):
+// each pair's inner product goes into its slice of one extended-basis buffer, and a single
+// ModDown then serves all pairs, so its transforms and conversion run as one launch over
+// P x B members; the results are views into one block
+std::vector<Grp> Ctx::g_rotate_pairs_hoisted(const Grp& a, const u64* lift, const std::vector<MaskPair>& pr,
+                                             double mask_scale) {
+    const int P = (int)pr.size(), B = a.B, ne = a.level + 1 + n_p;
+    if (a.deg != 1) throw HeError(HE_EMISMATCH);
+    std::vector<double> sc;
+    for (int j = 0; j < P; ++j)
+        for (double v : a.scale) sc.push_back(v * mask_scale);
+    Grp out = g_new(P * B, a.level, 1, sc);
+    const int64_t ucs = 2 * (int64_t)ne * N;
+    DBuf u(this, (size_t)P * B * ucs);
+    for (int j = 0; j < P; ++j) {
+        const u64 g1 = galois(pr[j].k1), g2 = galois(pr[j].k2);
+        if (g1 == 1 || g2 == 1) throw HeError(HE_EUNSUPPORTED);
+        g_ks_inner(u.p + (size_t)j * B * ucs, lift, B, a.level, rot_key(g1, false), g1, a.p, a.cs, pr[j].m1,
+                   rot_key(g2, false), g2, pr[j].m2, false);
+    }
+    g_moddown(u.p, P * B, a.level, nullptr, nullptr, 0, out.p, out.p + out.ps, out.cs, 1, nullptr, nullptr, nullptr,
+              0);
+    cnt[C_ROT] += 2 * P * B;
+    cnt[C_MULPT] += 2 * P * B;
+    cnt[C_ADD] += P * B;
+    std::vector<Grp> res(P);
+    for (int j = 0; j < P; ++j) {
+        res[j] = out;
+        res[j].B = B;
+        res[j].p = out.p + (size_t)j * B * out.cs;
+        res[j].scale.assign(sc.begin() + (size_t)j * B, sc.begin() + (size_t)(j + 1) * B);
+    }
+    return res;
 }
 
 // Hoisted rotation sums: base + sum_w Rot(a_w, r_w) with one ModDown.  Each term's
@@ -308,7 +324,7 @@ void Ctx::g_rotsum_add(RotSum& S, const Grp& a, int64_t r) {
     if (g == 1) throw HeError(HE_EUNSUPPORTED);
     const u64* key = rot_key(g, false);
     auto lift = g_lift(a, 1);
-    g_ks_inner(*S.u, lift->p, a.B, a.level, key, g, a.p, a.cs, nullptr, nullptr, 1, nullptr, S.n > 0);
+    g_ks_inner(S.u->p, lift->p, a.B, a.level, key, g, a.p, a.cs, nullptr, nullptr, 1, nullptr, S.n > 0);
     for (int i = 0; i < a.B; ++i) S.scale[i] = std::max(S.scale[i], a.scale[i]);
     ++S.n;
     cnt[C_ROT] += a.B;
@@ -321,7 +337,7 @@ Grp Ctx::g_rotsum_finish(RotSum& S, const Grp* base) {
     if (base)
         for (int i = 0; i < S.B; ++i) sc[i] = std::max(sc[i], base->scale[i]);
     Grp out = g_new(S.B, S.level, 1, sc);
-    g_moddown(*S.u, S.B, S.level, base ? base->p : nullptr, base ? base->p + base->ps : nullptr, base ? base->cs : 0,
+    g_moddown(S.u->p, S.B, S.level, base ? base->p : nullptr, base ? base->p + base->ps : nullptr, base ? base->cs : 0,
               out.p, out.p + out.ps, out.cs, 1, nullptr, nullptr, nullptr, 0);
     cnt[C_ADD] += (int64_t)S.B * (S.n - 1 + (base ? 1 : 0));
     S = RotSum();
@@ -614,6 +630,9 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
         const bool keep_baby = bg < t;
         if (keep_baby && J.babyB.empty()) J.babyB.resize(bg);
         const int kend = std::min(t, J.k + std::max(1, k_chunk));
+        // hoisted schedule: the mask pairs of up to pair_batch consecutive k share one ModDown
+        std::vector<Grp> pairs;
+        int pairs_k0 = 0;
         for (int k = J.k; k < kend; ++k) {
             const int i = k / bg, j = k % bg;
             const int64_t shift = (int64_t)h * bg * i;
@@ -621,8 +640,17 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
             if (k == 0) {
                 Ak = g_mask_sum({{&J.A0, mask(2, h, 0, 0, beta)}}, ms);
             } else if (hoist) {
-                Ak = g_rotate_pair_hoisted(J.A0, J.liftA->p, beta * (k - shift), mask(2, h, k, -shift, beta),
-                                           beta * (k - h - shift), mask(3, h, k, -shift, beta), ms);
+                if (pairs.empty() || k - pairs_k0 >= (int)pairs.size()) {
+                    std::vector<MaskPair> pr;
+                    for (int kk = k; kk < std::min(kend, k + std::max(1, pair_batch)); ++kk) {
+                        const int64_t sh = (int64_t)h * bg * (kk / bg);
+                        pr.push_back({beta * (kk - sh), mask(2, h, kk, -sh, beta), beta * (kk - h - sh),
+                                      mask(3, h, kk, -sh, beta)});
+                    }
+                    pairs = g_rotate_pairs_hoisted(J.A0, J.liftA->p, pr, ms);
+                    pairs_k0 = k;
+                }
+                Ak = pairs[k - pairs_k0];
             } else {
                 // masks applied in the ModDown epilogues
                 Grp t1 = g_rotate_mask_from_lift(J.A0, J.liftA->p, beta * (k - shift), mask(2, h, k, -shift, beta), ms,

@@ -128,6 +128,14 @@ struct MatShape {
     bool operator<(const MatShape& o) const { return std::tie(h, t, beta) < std::tie(o.h, o.t, o.beta); }
 };
 
+// one Step-2 term: v1 . Rot(a, k1) + v2 . Rot(a, k2)
+struct MaskPair {
+    int64_t k1;
+    const u64* m1;
+    int64_t k2;
+    const u64* m2;
+};
+
 struct Ctx {
     int log_n = 0;
     int64_t N = 0;
@@ -202,6 +210,7 @@ struct Ctx {
                                     const std::vector<MatShape>& shapes);
     std::vector<CtPtr> transpose_batch(const std::vector<const CtData*>& X, int h, int beta);
     int max_group = 32;
+    int pair_batch = 4;  // Step-2 mask pairs per shared ModDown launch
 
     // lockstep group operations (group.hip)
     Grp g_new(int B, int level, int deg, const std::vector<double>& sc);
@@ -210,15 +219,15 @@ struct Ctx {
     Grp g_drop(const Grp& a, int level);
     void g_add_into(Grp& acc, const Grp& t);
     std::shared_ptr<DBuf> g_lift(const Grp& a, int poly);
-    void g_ks_inner(DBuf& u, const u64* lift, int B, int level, const u64* key, u64 g, const u64* c0, int64_t c0_cs,
+    void g_ks_inner(u64* u, const u64* lift, int B, int level, const u64* key, u64 g, const u64* c0, int64_t c0_cs,
                     const u64* mask, const u64* key2, u64 g2, const u64* mask2, bool accumulate);
     void g_rotsum_add(RotSum& S, const Grp& a, int64_t r);
     Grp g_rotsum_finish(RotSum& S, const Grp* base);
-    void g_moddown(DBuf& u, int B, int level, const u64* add0, const u64* add1, int64_t add_cs, u64* out0,
+    void g_moddown(u64* u, int B, int level, const u64* add0, const u64* add1, int64_t add_cs, u64* out0,
                    u64* out1, int64_t out_cs, u64 add_g, const u64* mask, const u64* acc0, const u64* acc1,
                    int64_t acc_cs);
-    Grp g_rotate_pair_hoisted(const Grp& a, const u64* lift, int64_t k1, const u64* mask1, int64_t k2,
-                              const u64* mask2, double mask_scale);
+    std::vector<Grp> g_rotate_pairs_hoisted(const Grp& a, const u64* lift, const std::vector<MaskPair>& pr,
+                                            double mask_scale);
     void g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, const u64* add0, const u64* add1,
                     int64_t add_cs, u64* out0, u64* out1, int64_t out_cs, u64 add_g, const u64* mask,
                     const u64* acc0, const u64* acc1, int64_t acc_cs, const u64* c0, int64_t c0_cs);

@@ -1197,10 +1197,11 @@ static void launch_ip_nb(const DevTables& T, const IpDesc& D, dim3 grid, hipStre
 
 void launch_inner_product(const DevTables& T, const IpDesc& D, hipStream_t st) {
     const int nr = D.nrot == 2 ? 2 : 1;
-    // keys (and masks) once per group; per member the lift digits per rotation, c0 and u
+    // keys (and masks) once per group; per member the lift digits and c0 once (the rotations
+    // of a pair gather the same lift) and u
     const double words = (double)D.ne * (nr * 2.0 * D.beta + (D.mask ? 1.0 : 0.0) + (D.mask2 ? 1.0 : 0.0) +
-                                         D.nct * (nr * (double)D.beta + (D.accumulate ? 4.0 : 2.0))) +
-                         (D.c0 ? (double)D.nq * D.nct * nr : 0.0);
+                                         D.nct * ((double)D.beta + (D.accumulate ? 4.0 : 2.0))) +
+                         (D.c0 ? (double)D.nq * D.nct : 0.0);
     ProfScope prof_(PK_INNER, words * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), D.ne);
