@@ -203,34 +203,39 @@ def serve_rings_leg(he, I, sched, nreq, load):
             return srv, srv.submit(he.REQ_MATMUL, ops[0], ops[1], h=w[1])
         return srv, srv.submit(he.REQ_SIGN, ops[0], d=w[1], k=w[2], mode=w[3])
 
-    def drain(tk, t_start, arrivals):
-        lat, t_last = {}, t_start
+    def drain(tk, late, arrivals):
+        """latency = submit delay + the server's submit -> completion time (taken after the
+        stream synchronises); completion offsets give the served rate"""
+        lat = {}
         while len(lat) < len(tk):
             for j, (srv, t) in enumerate(tk):
                 if j not in lat:
                     r = srv.poll(t)
                     if r is not None:
-                        t_last = time.perf_counter()
-                        lat[j] = (t_last - t_start) - arrivals[j]
+                        lat[j] = late[j] + r[1]
             time.sleep(0.0005)
-        return lat, t_last
+        return lat, max(arrivals[j] + lat[j] for j in lat)
+
+    def submit_all(arrivals):
+        tk, late = [], []
+        t0 = time.perf_counter()
+        for j, p in enumerate(plan):
+            while time.perf_counter() - t0 < arrivals[j]:
+                time.sleep(0.0002)
+            late.append((time.perf_counter() - t0) - arrivals[j])
+            tk.append(submit(*p))
+        return tk, late
 
     # capacity: a burst of every request at t = 0
-    t0 = time.perf_counter()
-    tk = [submit(*p) for p in plan]
-    _, t_last = drain(tk, t0, [0.0] * nreq)
-    capacity = nreq / (t_last - t0)
+    tk, late = submit_all([0.0] * nreq)
+    _, span = drain(tk, late, [0.0] * nreq)
+    capacity = nreq / span
     runs = []
     for ld in sorted({0.25, 0.5, load}):
         # latency at ld x capacity
         arrivals = I.poisson_arrivals(5, ld * capacity, nreq)
-        t0 = time.perf_counter()
-        tk = []
-        for j, p in enumerate(plan):
-            while time.perf_counter() - t0 < arrivals[j]:
-                time.sleep(0.0002)
-            tk.append(submit(*p))
-        lat, t_last = drain(tk, t0, arrivals)
+        tk, late = submit_all(arrivals)
+        lat, span = drain(tk, late, arrivals)
         lats = np.array([lat[j] for j in range(nreq)])
         by = {}
         for name, sel in (("matmul", lambda w: w[0] == "mm"), ("sign", lambda w: w[0] == "sign"),
@@ -240,7 +245,7 @@ def serve_rings_leg(he, I, sched, nreq, load):
                 by[name] = {"n": int(v.size), "p50_ms": round(float(np.percentile(v, 50)) * 1e3, 1),
                             "p99_ms": round(float(np.percentile(v, 99)) * 1e3, 1)}
         runs.append({"load": ld, "arrival_rate_per_s": round(ld * capacity, 1),
-                     "served_per_s": round(nreq / (t_last - t0), 1),
+                     "served_per_s": round(nreq / span, 1),
                      "p50_ms": round(float(np.percentile(lats, 50)) * 1e3, 1),
                      "p99_ms": round(float(np.percentile(lats, 99)) * 1e3, 1), "by_type": by})
     for srv in servers.values():
