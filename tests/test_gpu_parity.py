@@ -288,6 +288,22 @@ def test_sign_parity(he, d, k, mode):
     assert np.abs(p.g.decrypt(gy, 256) - want).max() < 1e-3
 
 
+@pytest.mark.parametrize("log_n", [13, 17])
+def test_relu_parity_ring_sizes(he, log_n):
+    """every relinearisation goes through the fused base conversion + forward column pass;
+    N = 2^13 has 2 column stages, N = 2^17 has 6 (the generic column rounds): bit-exact
+    residues against the oracle, ModUp digits of 3 limbs, a 2-prime P"""
+    prm = I.small(log_n=log_n, n_q=8, alpha=3, q_bits=40, p_bits=50)
+    _log(f"[parity] relu d=3 k=1 at N=2^{log_n}")
+    p = Pair(he, prm, h_list=[])
+    X = I.sign_inputs(5, 1, 16)[0].ravel()
+    gx, ox = p.g.encrypt(X, nonce=9), p.o.encrypt(X, nonce=9)
+    gy, oy = p.g.sign_approx(gx, 3, 1, 1), p.o.sign(ox, 3, 1, relu=True)
+    p.same(gy, oy)
+    y = sum(c * X ** (2 * i + 1) for i, c in enumerate([35 / 16, -35 / 16, 21 / 16, -5 / 16]))
+    assert np.abs(p.g.decrypt(gy, 256) - (X + X * y) / 2).max() < 1e-3
+
+
 # ---------------------------------------------------------------- full-size configurations
 def test_c2_h64_matmul_parity(he):
     """N=2^14, 7 x 40-bit Q + 60-bit P, scale 2^40: the whole h=64 product, every residue"""
