@@ -214,7 +214,7 @@ def serve_rings_leg(he, I, sched, nreq, load):
                     if r is not None:
                         lat[j] = late[j] + r[1]
             time.sleep(0.0005)
-        return lat, max(arrivals[j] + lat[j] for j in lat)
+        return lat, float(max(arrivals[j] + lat[j] for j in lat))
 
     def submit_all(arrivals):
         tk, late = [], []
