@@ -158,10 +158,11 @@ def c4_leg(he, I, sched, stream, count):
 
 def serve_rings_leg(he, I, sched, nreq, load):
     """The serving configuration across rings: one server per context (N = 2^14, 2^15,
-    2^16), mixed requests (55% products with h uniform over {8, 16, 32, 64, 128}, 35% sign or
-    ReLU with d = 3 and k uniform over 1..4, 10% the N=2^16 ReLU k = 3) routed to the smallest
-    ring that holds them.  Capacity is measured with a burst of nreq requests; latency with
-    Poisson arrivals (seed 5) at load x capacity, from scheduled arrival to result."""
+    2^16), mixed requests (60% products with h uniform over {8, 16, 32, 64, 128}; 40% sign or
+    ReLU with d = 3 and k uniform over 1..4, a quarter of them the N=2^16 ReLU k = 3 so that the
+    largest ring serves too) routed to the smallest ring that holds them.  Capacity is measured
+    with a burst of nreq requests; latency with Poisson arrivals (seed 5) at 0.5, 0.8 and 0.95 x
+    capacity, from scheduled arrival to completion."""
     rings = [he.Context(I.C2, h_list=[8, 16, 32, 64], schedule=sched),
              he.Context(I.C3, h_list=[128], schedule=sched),
              he.Context(I.C4, h_list=[], schedule=sched)]
@@ -169,7 +170,7 @@ def serve_rings_leg(he, I, sched, nreq, load):
     kinds = []
     for _ in range(nreq):
         u = rng.random()
-        if u < 0.55:
+        if u < 0.60:
             kinds.append(("mm", int(rng.choice([8, 16, 32, 64, 128]))))
         elif u < 0.90:
             kinds.append(("sign", 3, int(rng.integers(1, 5)), int(rng.integers(0, 2))))
@@ -231,7 +232,7 @@ def serve_rings_leg(he, I, sched, nreq, load):
     _, span = drain(tk, late, [0.0] * nreq)
     capacity = nreq / span
     runs = []
-    for ld in sorted({0.25, 0.5, load}):
+    for ld in sorted({0.5, 0.95, load}):
         # latency at ld x capacity
         arrivals = I.poisson_arrivals(5, ld * capacity, nreq)
         tk, late = submit_all(arrivals)
@@ -304,7 +305,7 @@ def main():
     ap.add_argument("--no-other", action="store_true", help="skip timing the other schedules")
     ap.add_argument("--mix", type=int, default=256, help="mixed-batch products (0: skip)")
     ap.add_argument("--c4", type=int, default=128, help="ciphertexts of the N=2^16 ReLU + h=32 leg (0: skip)")
-    ap.add_argument("--serve-rings", type=int, default=300, help="requests of the cross-ring serving leg (0: skip)")
+    ap.add_argument("--serve-rings", type=int, default=2000, help="requests of the cross-ring serving leg (0: skip)")
     ap.add_argument("--no-shapes", action="store_true", help="skip the packed / rectangular / transpose leg")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / batched capacity")
