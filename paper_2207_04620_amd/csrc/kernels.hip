@@ -1087,34 +1087,57 @@ __device__ __forceinline__ IpKey<NB> ip_key(u64 v) {
     else return v;
 }
 
-template <int NB>
-__device__ __forceinline__ void ip_reduce(const u64* x, u64 z, const IpKey<NB>* kb, const IpKey<NB>* ka, u64 pmont,
-                                          bool with_c0, const ModP& m, u64 mk, bool masked, u64& v0, u64& v1) {
-    if constexpr (NB <= 7) {
+// The inner products of all NR rotations of one member for one slot: sum_r sum_j x_rj k_rj
+// (+ z_r pm_r on the Q limbs), the masks already folded into the key words and the c0
+// constant (mask . sum_j x_j k_j = sum_j x_j (k_j . mask) mod q).  Up to eight products share
+// one set of column sums and one REDC; otherwise each rotation is reduced on its own.
+template <int NB, int NR>
+__device__ __forceinline__ void ip_reduce(const u64 (&x)[NR][NB], const u64 (&z)[NR], const IpKey<NB> (&kb)[NR][NB],
+                                          const IpKey<NB> (&ka)[NR][NB], const IpKey<NB> (&pm)[NR], bool with_c0,
+                                          const ModP& m, u64& v0, u64& v1) {
+    if constexpr (NB <= 7 && NR * (NB + 1) <= 8) {
         Acc3 a0 = {0, 0, 0}, a1 = {0, 0, 0};
 #pragma unroll
-        for (int j = 0; j < NB; j++) {
-            const Split30 xs = split30(x[j]);
-            mac3(a0, xs, kb[j]);
-            mac3(a1, xs, ka[j]);
+        for (int r = 0; r < NR; r++) {
+#pragma unroll
+            for (int j = 0; j < NB; j++) {
+                const Split30 xs = split30(x[r][j]);
+                mac3(a0, xs, kb[r][j]);
+                mac3(a1, xs, ka[r][j]);
+            }
+            if (with_c0) mac3(a0, split30(z[r]), pm[r]);
         }
-        if (with_c0) mac3(a0, split30(z), split30(pmont));
         v0 = redc3(a0, m.q, m.qninv);
         v1 = redc3(a1, m.q, m.qninv);
-    } else {
-        Acc128 a0 = {0, 0}, a1 = {0, 0};
+    } else if constexpr (NB <= 7) {
+        v0 = v1 = 0;
 #pragma unroll
-        for (int j = 0; j < NB; j++) {
-            mac128(a0, x[j], kb[j]);
-            mac128(a1, x[j], ka[j]);
+        for (int r = 0; r < NR; r++) {
+            Acc3 a0 = {0, 0, 0}, a1 = {0, 0, 0};
+#pragma unroll
+            for (int j = 0; j < NB; j++) {
+                const Split30 xs = split30(x[r][j]);
+                mac3(a0, xs, kb[r][j]);
+                mac3(a1, xs, ka[r][j]);
+            }
+            if (with_c0) mac3(a0, split30(z[r]), pm[r]);
+            v0 = add_mod(v0, redc3(a0, m.q, m.qninv), m.q);
+            v1 = add_mod(v1, redc3(a1, m.q, m.qninv), m.q);
         }
-        if (with_c0) mac128(a0, z, pmont);
-        v0 = redc(a0.lo, a0.hi, m.q, m.qninv);
-        v1 = redc(a1.lo, a1.hi, m.q, m.qninv);
-    }
-    if (masked) {
-        v0 = mul_mont(v0, mk, m.q, m.qninv);
-        v1 = mul_mont(v1, mk, m.q, m.qninv);
+    } else {
+        v0 = v1 = 0;
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            Acc128 a0 = {0, 0}, a1 = {0, 0};
+#pragma unroll
+            for (int j = 0; j < NB; j++) {
+                mac128(a0, x[r][j], kb[r][j]);
+                mac128(a1, x[r][j], ka[r][j]);
+            }
+            if (with_c0) mac128(a0, z[r], pm[r]);
+            v0 = add_mod(v0, redc(a0.lo, a0.hi, m.q, m.qninv), m.q);
+            v1 = add_mod(v1, redc(a1.lo, a1.hi, m.q, m.qninv), m.q);
+        }
     }
 }
 
@@ -1130,8 +1153,10 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
     const int t = blockIdx.y;
     const int mi = D.mod[t];
     const ModP m = T.mods[mi];
-    IpKey<NB> kb[NR][NB], ka[NR][NB];
-    u64 mk[NR];
+    // key words (and P . c0's constant) with the rotation's mask folded in, Montgomery form
+    const bool with_c0 = D.c0 && t < D.nq;
+    const u64 pmont = with_c0 ? D.pmont[t] : 0;
+    IpKey<NB> kb[NR][NB], ka[NR][NB], pm[NR];
     int src[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) {
@@ -1139,15 +1164,20 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
         const u64* key = r ? D.key2 : D.key;
         const u64* mask = r ? D.mask2 : D.mask;
         src[r] = g == 1 ? i : perm_g(i, g, T.log_n);
+        const u64 mk = mask ? mask[(int64_t)mi * N + i] : 0;
 #pragma unroll
         for (int j = 0; j < NB; j++) {
-            kb[r][j] = ip_key<NB>(key[(((int64_t)j * 2 + 0) * D.M + mi) * N + i]);
-            ka[r][j] = ip_key<NB>(key[(((int64_t)j * 2 + 1) * D.M + mi) * N + i]);
+            u64 b = key[(((int64_t)j * 2 + 0) * D.M + mi) * N + i];
+            u64 a = key[(((int64_t)j * 2 + 1) * D.M + mi) * N + i];
+            if (mask) {
+                b = mul_mont(b, mk, m.q, m.qninv);
+                a = mul_mont(a, mk, m.q, m.qninv);
+            }
+            kb[r][j] = ip_key<NB>(b);
+            ka[r][j] = ip_key<NB>(a);
         }
-        mk[r] = mask ? mask[(int64_t)mi * N + i] : 0;
+        pm[r] = ip_key<NB>(mask ? mul_mont(pmont, mk, m.q, m.qninv) : pmont);
     }
-    const bool with_c0 = D.c0 && t < D.nq;
-    const u64 pmont = with_c0 ? D.pmont[t] : 0;
     u64 x[NR][NB], z[NR];
     auto load = [&](int c, u64(&xo)[NR][NB], u64(&zo)[NR]) {
         const u64* lift = D.lift + c * D.lift_cs + (int64_t)t * N;
@@ -1163,14 +1193,7 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
         u64 xn[NR][NB], zn[NR];
         if (c + 1 < D.nct) load(c + 1, xn, zn);
         u64 v0, v1;
-        ip_reduce<NB>(x[0], z[0], kb[0], ka[0], pmont, with_c0, m, mk[0], D.mask != nullptr, v0, v1);
-        if (NR == 2) {
-            u64 w0, w1;
-            ip_reduce<NB>(x[NR - 1], z[NR - 1], kb[NR - 1], ka[NR - 1], pmont, with_c0, m, mk[NR - 1],
-                          D.mask2 != nullptr, w0, w1);
-            v0 = add_mod(v0, w0, m.q);
-            v1 = add_mod(v1, w1, m.q);
-        }
+        ip_reduce<NB, NR>(x, z, kb, ka, pm, with_c0, m, v0, v1);
         u64* u = D.u + c * D.u_cs;
         if (D.accumulate) {
             v0 = add_mod(v0, u[(int64_t)t * N + i], m.q);
