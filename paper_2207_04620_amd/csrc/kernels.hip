@@ -575,7 +575,8 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
 // Inverse transform: Gentleman-Sande, bit-reversed input, natural output, then N^-1.
 // The last pass of the inverse transform multiplies by N^-1, or, with 'scale' set, by the
 // per-job constant scale[k mod scale_n] (pairs (c, c')): N^-1 times the (D/q_s)^-1 of a base
-// conversion that follows, so the conversion reads its prepared inputs directly.
+// conversion that follows, and then stores the centred representative (y - q when y > (q-1)/2,
+// as a two's-complement word), so the conversion reads its prepared inputs directly.
 __global__ __launch_bounds__(TPB) void k_ntt_inv_rows(DevTables T, Jobs J, const u64* scale, int scale_n) {
     __shared__ u64 s[NTT_LDS];
     const int N = 1 << T.log_n, L1 = T.n1_log, L2 = T.n2_log, N1 = 1 << L1, N2 = 1 << L2;
@@ -611,8 +612,14 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_rows(DevTables T, Jobs J, const
     }
     if (L1 == 0) {
         const u64 f = scale ? scale[2 * (k % scale_n)] : mp_.ninv, fs = scale ? scale[2 * (k % scale_n) + 1] : mp_.ninv_sh;
-        for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB)
-            st2(a + e, u64x2{mul_shoup(s[lds_at<true>(e)], f, fs, q), mul_shoup(s[lds_at<true>(e + 1)], f, fs, q)});
+        for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
+            u64 y0 = mul_shoup(s[lds_at<true>(e)], f, fs, q), y1 = mul_shoup(s[lds_at<true>(e + 1)], f, fs, q);
+            if (scale) {
+                y0 = y0 > mp_.half ? y0 - q : y0;
+                y1 = y1 > mp_.half ? y1 - q : y1;
+            }
+            st2(a + e, u64x2{y0, y1});
+        }
     } else {
         for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB)  // lazy in [0, 2q)
             st2(a + e, u64x2{s[lds_at<true>(e)], s[lds_at<true>(e + 1)]});
@@ -639,14 +646,22 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_cols(DevTables T, Jobs J, const
     __syncthreads();
     inv_cols_any(s, L1, W, Ws, q);
     const u64 f = scale ? scale[2 * (k % scale_n)] : mp_.ninv, fs = scale ? scale[2 * (k % scale_n) + 1] : mp_.ninv_sh;
-    for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB)
-        st2(a + (int64_t)(e >> logC) * N2 + c0 + (e & (C - 1)), u64x2{mul_shoup(s[e], f, fs, q), mul_shoup(s[e + 1], f, fs, q)});
+    for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB) {
+        u64 y0 = mul_shoup(s[e], f, fs, q), y1 = mul_shoup(s[e + 1], f, fs, q);
+        if (scale) {
+            y0 = y0 > mp_.half ? y0 - q : y0;
+            y1 = y1 > mp_.half ? y1 - q : y1;
+        }
+        st2(a + (int64_t)(e >> logC) * N2 + c0 + (e & (C - 1)), u64x2{y0, y1});
+    }
 }
 
 // ---- base conversion fused with the column pass of the forward transform.  A block converts
 // one column block (N1 rows x 2^(11 - L1) columns, 2048 slots) of one target limb from the
-// ns source limbs, which the inverse transform has already multiplied by their (D/q_s)^-1,
-// and runs the column stages on it; the row pass follows as usual.  Workgroups are handed to
+// ns source limbs, which the inverse transform has already multiplied by their (D/q_s)^-1 and
+// centred (signed words), so out_t = sum_s y_s (D/q_s) mod q_t needs no correction term; the
+// sum stays lazy in [0, 3q), which the forward butterflies accept, and the column stages run on
+// it; the row pass follows as usual.  Workgroups are handed to
 // the 8 XCDs round-robin, so the blocks of all targets of one source block are numbered to
 // run back to back on one XCD, where the source words stay in that XCD's L2.
 template <int NS>
@@ -668,30 +683,26 @@ __global__ __launch_bounds__(TPB) void k_conv_cols(DevTables T, ConvDesc D) {
     const int x = pair % tiles, pc = pair / tiles, p = pc % D.npoly, c = pc / D.npoly;
     const int mi = D.dmod[t];
     const ModP m = T.mods[mi];
+    constexpr bool BAL = NS > 5;  // the balanced split keeps six to eight products in int64
     Split30 tw[NS];
-    u64 tc[NS], half[NS];
 #pragma unroll
-    for (int i = 0; i < NS; ++i) {
-        const int64_t o = ((int64_t)i * D.tab_ld + D.tcol[t]) * 2;
-        tw[i] = split30(D.tab[o]);
-        tc[i] = D.tab[o + 1];
-        half[i] = T.mods[D.smod[i]].half;
-    }
+    for (int i = 0; i < NS; ++i) tw[i] = split30(D.tab[((int64_t)i * D.tab_ld + D.tcol[t]) * 2]);
     const u64* src = D.src + c * D.src_cstride + p * D.src_pstride;
     const int col0 = x * C;
     for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB) {
         const int64_t slot = (int64_t)(e >> logC) * N2 + col0 + (e & (C - 1));
-        Acc3 a0 = {0, 0, 0}, a1 = {0, 0, 0};
+        AccS a0 = {0, 0, 0}, a1 = {0, 0, 0};
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
             const u64x2 y = ld2(src + (int64_t)i * N + slot);
-            mac3(a0, split30(y.x), tw[i]);
-            mac3(a1, split30(y.y), tw[i]);
-            a0.c0 += y.x > half[i] ? tc[i] : 0;
-            a1.c0 += y.y > half[i] ? tc[i] : 0;
+            int32_t lo, hi;
+            split30s<BAL>((int64_t)y.x, lo, hi);
+            macs(a0, lo, hi, tw[i]);
+            split30s<BAL>((int64_t)y.y, lo, hi);
+            macs(a1, lo, hi, tw[i]);
         }
-        s[e] = redc3(a0, m.q, m.qninv);
-        s[e + 1] = redc3(a1, m.q, m.qninv);
+        s[e] = redcs_lazy(a0, m.q, m.qninv);
+        s[e + 1] = redcs_lazy(a1, m.q, m.qninv);
     }
     __syncthreads();
     fwd_cols_any(s, L1, T.psi + (int64_t)mi * N, T.psi_sh + (int64_t)mi * N, m.q);
@@ -800,7 +811,7 @@ __global__ __launch_bounds__(TPB) void k_baseconv(DevTables T, ConvDesc D) {
         const u64x2 x = ld2(src + (int64_t)s * N + i);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const u64 v = D.prescaled ? x[h] : mul_shoup(x[h], D.hinv[s], D.hinv_sh[s], m.q);
+            const u64 v = mul_shoup(x[h], D.hinv[s], D.hinv_sh[s], m.q);
             y[s][h] = split30(v);
             negm[s][h] = v > m.half ? ~0ull : 0ull;
         }
@@ -826,6 +837,7 @@ __global__ __launch_bounds__(TPB) void k_baseconv(DevTables T, ConvDesc D) {
 void launch_baseconv(const DevTables& T, const ConvDesc& D, hipStream_t st) {
     ProfScope prof_(PK_BASECONV, (double)(D.ns + D.nt) * D.npoly * D.nct * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
+    if (D.prescaled) throw std::runtime_error("base conversion: prescaled sources are read by conv_cols only");
     if (misaligned16(D.src) || misaligned16(D.dst) || ((D.src_pstride | D.dst_pstride | D.src_cstride |
                                                          D.dst_cstride) & 1))
         throw std::runtime_error("base conversion operand not 16-byte aligned");

@@ -63,7 +63,7 @@ struct ConvDesc {
     int64_t dst_pstride;
     int64_t src_cstride = 0, dst_cstride = 0;  // ciphertext strides
     int nct = 1;
-    int prescaled = 0;  // sources already multiplied by (D/q_s)^-1 (in the inverse NTT)
+    int prescaled = 0;  // sources multiplied by (D/q_s)^-1 and centred by the inverse NTT (conv_cols)
     const u64* tab;
     int tab_ld;  // table row length: entry (s, col) at tab[(s * tab_ld + col) * 2]
     int ns, nt, npoly;
@@ -189,7 +189,7 @@ std::string prof_report();  // JSON: per kernel kind {launches, ms, bytes}; clea
 
 // ------------------------------------------------------------------ launchers
 // inverse: the last pass multiplies limb job k by scale[k mod scale_n] (a (c, c') Shoup pair)
-// instead of N^-1 when scale is set; forward: cols = false skips the column pass (done by
+// instead of N^-1 when scale is set, and stores centred two's-complement words; forward: cols = false skips the column pass (done by
 // launch_conv_cols)
 void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st, const u64* scale = nullptr,
                 int scale_n = 0, bool cols = true);

@@ -120,6 +120,44 @@ __device__ __forceinline__ u64 redc3(const Acc3& a, u64 q, u64 qninv) {
     return redc(lo, hi, q, qninv);
 }
 
+// Signed form for centred inputs |y| < 2^59 (y = y_c, the centred representative of a residue
+// of a prime below 2^60): y = hi 2^30 + lo, the four partial products with the (unsigned) 30-bit
+// halves of t are signed v_mad_i64_i32 into three int64 column sums.  With lo in [0, 2^30) a
+// product adds |.| < 1.5 2^60 to c1, so up to five products fit; the balanced split
+// (lo in [-2^29, 2^29)) keeps every term below 2^60 in magnitude, for up to eight.
+struct AccS {
+    int64_t c0, c1, c2;
+};
+template <bool BAL>
+__device__ __forceinline__ void split30s(int64_t y, int32_t& lo, int32_t& hi) {
+    if constexpr (BAL) {
+        const int64_t z = y + (1ll << 29);
+        hi = (int32_t)(z >> 30);
+        lo = (int32_t)(z & 0x3fffffff) - (1 << 29);
+    } else {
+        hi = (int32_t)(y >> 30);
+        lo = (int32_t)(y & 0x3fffffff);
+    }
+}
+__device__ __forceinline__ void macs(AccS& a, int32_t lo, int32_t hi, Split30 t) {
+    a.c0 += (int64_t)lo * (int64_t)(int32_t)t.lo;
+    a.c1 += (int64_t)lo * (int64_t)(int32_t)t.hi;
+    a.c1 += (int64_t)hi * (int64_t)(int32_t)t.lo;
+    a.c2 += (int64_t)hi * (int64_t)(int32_t)t.hi;
+}
+// V R^-1 mod q for the signed V = c0 + c1 2^30 + c2 2^60 with |V| < q 2^64, lazy in [0, 3q):
+// REDC of V + q 2^64, which lies in (0, 2q 2^64)
+__device__ __forceinline__ u64 redcs_lazy(const AccS& a, u64 q, u64 qninv) {
+    const u64 l1 = (u64)a.c1 << 30, l2 = (u64)a.c2 << 60;
+    u64 lo = (u64)a.c0 + l1;
+    u64 cy = lo < l1 ? 1 : 0;
+    lo += l2;
+    cy += lo < l2 ? 1 : 0;
+    const u64 hi = (u64)((a.c0 >> 63) + (a.c1 >> 34) + (a.c2 >> 4)) + cy + q;
+    const u64 m = lo * qninv;
+    return hi + __umul64hi(m, q) + (lo != 0 ? 1 : 0);
+}
+
 // x mod q for any 64-bit x
 __device__ __forceinline__ u64 reduce64(u64 x, const ModP& m) {
     u64 qh = __umul64hi(x, m.bar);
