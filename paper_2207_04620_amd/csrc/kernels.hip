@@ -544,9 +544,10 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
         u64 w[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            u64 v = red4(s[lds_at<true>(e + h)], q2);
-            v = v >= q ? v - q : v;
-            w[h] = mul_shoup(sub_mod(uu[h], v, q), pi, pis, q);
+            // v is lazy in [0, 4q) and u < q, so u + 4q - v lies in (0, 5q); the Shoup product
+            // reduces any 64-bit operand to [0, q)
+            const u64 v = s[lds_at<true>(e + h)];
+            w[h] = mul_shoup(uu[h] + 2 * q2 - v, pi, pis, q);
         }
         if (add) {
             if (E.g == 1) {
