@@ -1471,23 +1471,44 @@ __global__ __launch_bounds__(TPB) void k_mask_mac_multi(DevTables T, MultiMacDes
     const int l = blockIdx.y, p = blockIdx.z;
     const ModP m = T.mods[l];
     const int64_t o = (int64_t)l * N + i;
-    u64 mk[G][NI];
+    // up to eight terms: carry-free column sums (the inputs split once for all outputs);
+    // sixteen: 128-bit accumulation.  NI q^2 < q 2^64 for NI <= 16 and q < 2^60.
+    constexpr bool COLS = NI <= 8;
+    using MK = typename std::conditional<COLS, Split30, u64>::type;
+    MK mk[G][NI];
 #pragma unroll
     for (int g = 0; g < G; g++)
 #pragma unroll
-        for (int j = 0; j < NI; j++) mk[g][j] = (g < D.nout && D.mask[g][j]) ? D.mask[g][j][o] : 0;
+        for (int j = 0; j < NI; j++) {
+            const u64 v = (g < D.nout && D.mask[g][j]) ? D.mask[g][j][o] : 0;
+            if constexpr (COLS) mk[g][j] = split30(v);
+            else mk[g][j] = v;
+        }
     for (int c = 0; c < D.nct; c++) {
         u64 x[NI];
 #pragma unroll
         for (int j = 0; j < NI; j++) x[j] = D.in[j][c * D.in_cs[j] + p * D.in_ps[j] + o];
+        if constexpr (COLS) {
+            Split30 xs[NI];
 #pragma unroll
-        for (int g = 0; g < G; g++) {
-            if (g >= D.nout) break;
-            Acc128 s = {0, 0};
+            for (int j = 0; j < NI; j++) xs[j] = split30(x[j]);
 #pragma unroll
-            for (int j = 0; j < NI; j++) mac128(s, x[j], mk[g][j]);
-            // NI q^2 < q 2^64 for NI <= 16 and q < 2^60
-            D.out[g][c * D.out_cs + p * D.out_ps + o] = redc(s.lo, s.hi, m.q, m.qninv);
+            for (int g = 0; g < G; g++) {
+                if (g >= D.nout) break;
+                Acc3 s = {0, 0, 0};
+#pragma unroll
+                for (int j = 0; j < NI; j++) mac3(s, xs[j], mk[g][j]);
+                D.out[g][c * D.out_cs + p * D.out_ps + o] = redc3(s, m.q, m.qninv);
+            }
+        } else {
+#pragma unroll
+            for (int g = 0; g < G; g++) {
+                if (g >= D.nout) break;
+                Acc128 s = {0, 0};
+#pragma unroll
+                for (int j = 0; j < NI; j++) mac128(s, x[j], mk[g][j]);
+                D.out[g][c * D.out_cs + p * D.out_ps + o] = redc(s.lo, s.hi, m.q, m.qninv);
+            }
         }
     }
 }
