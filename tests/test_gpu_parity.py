@@ -304,6 +304,22 @@ def test_relu_parity_ring_sizes(he, log_n):
     assert np.abs(p.g.decrypt(gy, 256) - (X + X * y) / 2).max() < 1e-3
 
 
+@pytest.mark.parametrize("schedule", [0, 15])
+def test_largest_shape_for_ring_and_empty_batch(he, schedule):
+    """h^2 = N/2 (N = 2^13, h = 64): one replica of the matrix, so every Step-2 and Step-3
+    rotation spans the whole slot vector; every residue against the oracle under Alg. 3 as
+    printed (0) and the headline schedule (15).  An empty batch returns nothing."""
+    prm = I.small(log_n=13, n_q=6, alpha=2, q_bits=40, p_bits=50)
+    _log(f"[parity] h=64 at N=2^13, schedule {schedule}")
+    p = Pair(he, prm, h_list=[64], schedule=schedule)
+    assert p.g.matmul_batch([], [], []) == []
+    A, B = I.matrix_pair(64 + schedule, 64)
+    gm = p.g.matmul(p.g.encrypt(A.ravel(), nonce=40), p.g.encrypt(B.ravel(), nonce=41), 64)
+    om = p.o.matmul(p.o.encrypt(A.ravel(), nonce=40), p.o.encrypt(B.ravel(), nonce=41), 64, schedule)
+    p.same(gm, om)
+    assert np.abs(p.g.decrypt(gm, 64 * 64).reshape(64, 64) - A @ B).max() < 1e-3
+
+
 # ---------------------------------------------------------------- full-size configurations
 def test_c2_h64_matmul_parity(he):
     """N=2^14, 7 x 40-bit Q + 60-bit P, scale 2^40: the whole h=64 product, every residue"""
