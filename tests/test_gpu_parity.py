@@ -272,6 +272,28 @@ def test_matmul_batch_equals_single(small):
         assert np.array_equal(small.g.export(r), s)
 
 
+def test_matmul_batch_beyond_group_cap(he):
+    """33 products of one shape and level under the headline schedule: a full lockstep group
+    of 32 and a ragged group of 1 (the cap on the working set); every result equals the product
+    run alone, and the lone member equals the oracle"""
+    prm = I.small(log_n=12, n_q=6, alpha=2, q_bits=40, p_bits=50)
+    p = Pair(he, prm, h_list=[8], schedule=15)
+    As, Bs, mats = [], [], []
+    for i in range(33):
+        A, B = I.matrix_pair(300 + i, 8)
+        mats.append((A, B))
+        As.append(p.g.encrypt(A.ravel(), nonce=2 * i))
+        Bs.append(p.g.encrypt(B.ravel(), nonce=2 * i + 1))
+    res = p.g.matmul_batch(As, Bs, [8] * 33)
+    for i in (0, 17, 31, 32):
+        assert np.array_equal(p.g.export(res[i]), p.g.export(p.g.matmul(As[i], Bs[i], 8))), i
+    for i, (A, B) in enumerate(mats):
+        assert np.abs(p.g.decrypt(res[i], 64).reshape(8, 8) - A @ B).max() < 1e-3, i
+    A, B = mats[32]
+    om = p.o.matmul(p.o.encrypt(A.ravel(), nonce=64), p.o.encrypt(B.ravel(), nonce=65), 8, 15)
+    p.same(res[32], om)
+
+
 @pytest.mark.parametrize("d,k,mode", [(3, 1, 0), (1, 2, 0), (2, 1, 0), (3, 1, 1)])
 def test_sign_parity(he, d, k, mode):
     prm = I.small(log_n=12, n_q=8, alpha=3, q_bits=40, p_bits=50)
