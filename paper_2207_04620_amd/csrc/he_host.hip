@@ -223,6 +223,7 @@ void Ctx::build_tables() {
     // on twiddle exponents (N1 + r) 2^st + j; a group J of a round starting at stage s0 uses, for
     // its stages s0 + i (forward) or s0 - i (inverse), the pairs at (N1 + r) 2^st + (J << shift) + b
     T.rtw = T.irtw = nullptr;
+    T.rtwd = T.irtwd = T.cold = T.icold = nullptr;
     if (T.n2_log == 11) {
         const int N1 = 1 << T.n1_log;
         std::vector<u64> rtw((size_t)M * N1 * ROW_TW * 2), irtw((size_t)M * N1 * ROW_TW * 2);
@@ -265,6 +266,40 @@ void Ctx::build_tables() {
         upload(this, d_irtw->p, irtw.data(), irtw.size() * 8);
         T.rtw = d_rtw->p;
         T.irtw = d_irtw->p;
+        // FP64 forms for primes below 2^46 (exact as doubles): w and fl(w / q)
+        std::vector<double> rtwd(rtw.size(), 0.0), irtwd(irtw.size(), 0.0), cold((size_t)M * N1 * 2, 0.0),
+            icold((size_t)M * N1 * 2, 0.0);
+        for (int m = 0; m < M; ++m) {
+            const u64 q = mods[m];
+            if (q >= (1ull << 46)) continue;
+            const double qd = (double)q;
+            const size_t o = (size_t)m * N1 * ROW_TW * 2;
+            for (size_t k = 0; k < (size_t)N1 * ROW_TW; ++k) {
+                rtwd[o + 2 * k] = (double)rtw[o + 2 * k];
+                rtwd[o + 2 * k + 1] = (double)rtw[o + 2 * k] / qd;
+                irtwd[o + 2 * k] = (double)irtw[o + 2 * k];
+                irtwd[o + 2 * k + 1] = (double)irtw[o + 2 * k] / qd;
+            }
+            for (int j = 0; j < N1; ++j) {
+                const size_t c = ((size_t)m * N1 + j) * 2;
+                cold[c] = (double)psi[(size_t)m * N + j];
+                cold[c + 1] = cold[c] / qd;
+                icold[c] = (double)ipsi[(size_t)m * N + j];
+                icold[c + 1] = icold[c] / qd;
+            }
+        }
+        d_rtwd = std::make_unique<DBuf>(this, rtwd.size());
+        d_irtwd = std::make_unique<DBuf>(this, irtwd.size());
+        d_cold = std::make_unique<DBuf>(this, cold.size());
+        d_icold = std::make_unique<DBuf>(this, icold.size());
+        upload(this, d_rtwd->p, rtwd.data(), rtwd.size() * 8);
+        upload(this, d_irtwd->p, irtwd.data(), irtwd.size() * 8);
+        upload(this, d_cold->p, cold.data(), cold.size() * 8);
+        upload(this, d_icold->p, icold.data(), icold.size() * 8);
+        T.rtwd = (const double*)d_rtwd->p;
+        T.irtwd = (const double*)d_irtwd->p;
+        T.cold = (const double*)d_cold->p;
+        T.icold = (const double*)d_icold->p;
     }
 
     // ---- rescale constants: qinv[l][i] = q_l^-1 mod q_i

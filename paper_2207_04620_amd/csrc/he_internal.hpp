@@ -152,8 +152,8 @@ struct Ctx {
     DevTables T{};
     u64 cdt[19];
     // device tables
-    std::unique_ptr<DBuf> d_mods, d_psi, d_psi_sh, d_ipsi, d_ipsi_sh, d_rtw, d_irtw, d_rs, d_md_tab, d_pinv, d_mu_tab,
-        d_mu_scale, d_md_scale;
+    std::unique_ptr<DBuf> d_mods, d_psi, d_psi_sh, d_ipsi, d_ipsi_sh, d_rtw, d_irtw, d_rtwd, d_irtwd, d_cold, d_icold, d_rs, d_md_tab,
+        d_pinv, d_mu_tab, d_mu_scale, d_md_scale;
     std::vector<u64> md_hinv, md_hinv_sh;
     std::vector<std::vector<ModUpInfo>> mu;  // [level][digit]
     // keys
@@ -266,7 +266,8 @@ struct Ctx {
         s2_eval.reset();
         s_eval.reset();
         d_mods.reset(); d_psi.reset(); d_psi_sh.reset(); d_ipsi.reset(); d_ipsi_sh.reset();
-        d_rtw.reset(); d_irtw.reset(); d_mu_scale.reset(); d_md_scale.reset();
+        d_rtw.reset(); d_irtw.reset(); d_rtwd.reset(); d_irtwd.reset(); d_cold.reset(); d_icold.reset();
+        d_mu_scale.reset(); d_md_scale.reset();
         d_rs.reset(); d_md_tab.reset(); d_pinv.reset(); d_mu_tab.reset();
         pool.trim();
     }

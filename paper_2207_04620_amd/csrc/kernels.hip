@@ -465,6 +465,252 @@ __device__ __forceinline__ void inv_cols_any(u64* s, int L1, const u64* W, const
     }
 }
 
+// ---- FP64 butterflies for primes below 2^46.  A residue is held as an integer-valued double
+// (balanced: any sign, |x| a small multiple of q).  x w mod q: the product is split exactly as
+// hi + lo (hi = fl(x w), lo = fma(x, w, -hi)), c = rint(x fl(w / q)) is within one of the
+// rounded quotient, and fma(-c, q, hi) + lo = x w - c q exactly; for |x| < 32 q and q < 2^46 the
+// result lies in (-q, q).  Forward (Cooley-Tukey) passes add at most q per stage, so 15 stages
+// from |x| < 4q need no reduction; inverse (Gentleman-Sande) rounds reduce their inputs to
+// |x| <= q/2 + 1 first (x - rint(x / q) q).  One FP64 butterfly is 8 instructions (v_mul_f64,
+// v_fma_f64, v_rndne_f64, v_add_f64), against 27 for the 64-bit integer Shoup butterfly.
+// Between the two passes of a transform the limb holds the raw double words; the transform's
+// output is canonical.  Both passes of a limb decide by the same rule (fp64_limb).
+#define FP64_QMAX (1ull << 46)
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ f64x2 ld2d(const double* p) { return *reinterpret_cast<const f64x2*>(p); }
+__device__ __forceinline__ bool fp64_limb(u64 q, int L1, int N2) { return q < FP64_QMAX && N2 == NTT_E && L1 <= 5; }
+// exact for x < 2^52
+__device__ __forceinline__ double u2d(u64 x) {
+    return __longlong_as_double((long long)(x | 0x4330000000000000ull)) - 4503599627370496.0;
+}
+__device__ __forceinline__ double bits_d(u64 x) { return __longlong_as_double((long long)x); }
+__device__ __forceinline__ u64 d_bits(double x) { return (u64)__double_as_longlong(x); }
+__device__ __forceinline__ double red_d(double x, double q, double qinv) {
+#pragma clang fp contract(off)
+    return __fma_rn(-rint(x * qinv), q, x);
+}
+// any integer-valued |x| < 2^50 -> its residue in [0, q) as a word
+__device__ __forceinline__ u64 canon_d(double x, double q, double qinv) {
+#pragma clang fp contract(off)
+    double r = red_d(x, q, qinv);
+    r = r < 0.0 ? r + q : r;
+    return (u64)__double_as_longlong(r + 4503599627370496.0) & 0xFFFFFFFFFFFFFull;
+}
+__device__ __forceinline__ double mulmod_d(double a, double w, double wq, double q) {
+#pragma clang fp contract(off)
+    const double hi = a * w;
+    const double lo = __fma_rn(a, w, -hi);
+    const double c = rint(a * wq);
+    return __fma_rn(-c, q, hi) + lo;
+}
+
+template <int R, int S0>
+__device__ __forceinline__ void fwd_row_round_d(double* s, const double* __restrict__ tw, int off, double q) {
+#pragma clang fp contract(off)
+    constexpr int G = 1 << R, NG = 8 / G, LD = 11 - S0 - R, D = 1 << LD;
+#pragma unroll
+    for (int gg = 0; gg < NG; ++gg) {
+        const int g = gg * TPB + threadIdx.x;
+        const int J = g >> LD;
+        const int base = (J << (LD + R)) + (g & (D - 1));
+        double* sb = s + base + (base >> 5);
+        double x[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) x[k] = sb[k * D + ((k * D) >> 5)];
+        const double* t = tw + 2 * (off + J * (G - 1));
+        f64x2 w[G - 1];
+#pragma unroll
+        for (int i = 0; i < G - 1; ++i) w[i] = ld2d(t + 2 * i);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int half = G >> (r + 1);
+#pragma unroll
+            for (int b = 0; b < (1 << r); ++b) {
+                const f64x2 wb = w[(1 << r) - 1 + b];
+#pragma unroll
+                for (int k = b * 2 * half; k < b * 2 * half + half; ++k) {
+                    const double V = mulmod_d(x[k + half], wb.x, wb.y, q);
+                    const double U = x[k];
+                    x[k] = U + V;
+                    x[k + half] = U - V;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) sb[k * D + ((k * D) >> 5)] = x[k];
+    }
+}
+
+template <int R, int S0>
+__device__ __forceinline__ void inv_row_round_d(double* s, const double* __restrict__ tw, int off, double q,
+                                                double qinv) {
+#pragma clang fp contract(off)
+    constexpr int G = 1 << R, NG = 8 / G, LD = 11 - S0 - 1, D = 1 << LD;
+#pragma unroll
+    for (int gg = 0; gg < NG; ++gg) {
+        const int g = gg * TPB + threadIdx.x;
+        const int J = g >> LD;
+        const int base = (J << (LD + R)) + (g & (D - 1));
+        double* sb = s + base + (base >> 5);
+        double x[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) x[k] = red_d(sb[k * D + ((k * D) >> 5)], q, qinv);
+        const double* t = tw + 2 * (off + J * (G - 1));
+        f64x2 w[G - 1];
+#pragma unroll
+        for (int i = 0; i < G - 1; ++i) w[i] = ld2d(t + 2 * i);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int half = 1 << r;
+#pragma unroll
+            for (int b = 0; b < (G >> (r + 1)); ++b) {
+                const f64x2 wb = w[G - (G >> r) + b];
+#pragma unroll
+                for (int k = b * 2 * half; k < b * 2 * half + half; ++k) {
+                    const double U = x[k], V = x[k + half];
+                    x[k] = U + V;
+                    x[k + half] = mulmod_d(U - V, wb.x, wb.y, q);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) sb[k * D + ((k * D) >> 5)] = x[k];
+    }
+}
+
+__device__ __forceinline__ void fwd_rows_2048_d(double* s, const double* tw, double q) {
+    fwd_row_round_d<3, 0>(s, tw, 0, q);
+    __syncthreads();
+    fwd_row_round_d<3, 3>(s, tw, 7, q);
+    __syncthreads();
+    fwd_row_round_d<3, 6>(s, tw, 63, q);
+    __syncthreads();
+    fwd_row_round_d<2, 9>(s, tw, 511, q);
+    __syncthreads();
+}
+
+__device__ __forceinline__ void inv_rows_2048_d(double* s, const double* tw, double q, double qinv) {
+    inv_row_round_d<3, 10>(s, tw, 0, q, qinv);
+    __syncthreads();
+    inv_row_round_d<3, 7>(s, tw, 1792, q, qinv);
+    __syncthreads();
+    inv_row_round_d<3, 4>(s, tw, 2016, q, qinv);
+    __syncthreads();
+    inv_row_round_d<2, 1>(s, tw, 2044, q, qinv);
+    __syncthreads();
+}
+
+// column rounds (L1 <= 5): wave-uniform twiddles (w, fl(w / q)) from the [M][N1] column table
+template <int R, int S0, int L1>
+__device__ __forceinline__ void fwd_col_round_d(double* s, const double* __restrict__ W, double q) {
+#pragma clang fp contract(off)
+    constexpr int G = 1 << R, NG = 8 / G, LD = L1 - S0 - R, D = 1 << LD, LOGT = 11 - L1, TC = 1 << LOGT;
+#pragma unroll
+    for (int gg = 0; gg < NG; ++gg) {
+        const int g = gg * TPB + threadIdx.x;
+        const int u = g & (TC - 1);
+        const int gi = __builtin_amdgcn_readfirstlane(g >> LOGT);
+        const int J = gi >> LD;
+        const int base = (J << (LD + R)) + (gi & (D - 1));
+        double x[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) x[k] = s[((base + k * D) << LOGT) + u];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int half = G >> (r + 1);
+#pragma unroll
+            for (int b = 0; b < (1 << r); ++b) {
+                const int idx = (1 << (S0 + r)) + (J << r) + b;
+                const double w = W[2 * idx], wq = W[2 * idx + 1];
+#pragma unroll
+                for (int k = b * 2 * half; k < b * 2 * half + half; ++k) {
+                    const double V = mulmod_d(x[k + half], w, wq, q);
+                    const double U = x[k];
+                    x[k] = U + V;
+                    x[k + half] = U - V;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) s[((base + k * D) << LOGT) + u] = x[k];
+    }
+}
+
+template <int R, int S0, int L1>
+__device__ __forceinline__ void inv_col_round_d(double* s, const double* __restrict__ W, double q, double qinv) {
+#pragma clang fp contract(off)
+    constexpr int G = 1 << R, NG = 8 / G, LD = L1 - S0 - 1, D = 1 << LD, LOGT = 11 - L1, TC = 1 << LOGT;
+#pragma unroll
+    for (int gg = 0; gg < NG; ++gg) {
+        const int g = gg * TPB + threadIdx.x;
+        const int u = g & (TC - 1);
+        const int gi = __builtin_amdgcn_readfirstlane(g >> LOGT);
+        const int J = gi >> LD;
+        const int base = (J << (LD + R)) + (gi & (D - 1));
+        double x[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) x[k] = red_d(s[((base + k * D) << LOGT) + u], q, qinv);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int half = 1 << r;
+#pragma unroll
+            for (int b = 0; b < (G >> (r + 1)); ++b) {
+                const int idx = (1 << (S0 - r)) + (J << (R - 1 - r)) + b;
+                const double w = W[2 * idx], wq = W[2 * idx + 1];
+#pragma unroll
+                for (int k = b * 2 * half; k < b * 2 * half + half; ++k) {
+                    const double U = x[k], V = x[k + half];
+                    x[k] = U + V;
+                    x[k + half] = mulmod_d(U - V, w, wq, q);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) s[((base + k * D) << LOGT) + u] = x[k];
+    }
+}
+
+template <int L1, int S0>
+__device__ __forceinline__ void fwd_cols_from_d(double* s, const double* W, double q) {
+    if constexpr (S0 < L1) {
+        constexpr int R = L1 - S0 >= 3 ? 3 : L1 - S0;
+        fwd_col_round_d<R, S0, L1>(s, W, q);
+        __syncthreads();
+        fwd_cols_from_d<L1, S0 + R>(s, W, q);
+    }
+}
+
+template <int L1, int ST>
+__device__ __forceinline__ void inv_cols_from_d(double* s, const double* W, double q, double qinv) {
+    if constexpr (ST >= 0) {
+        constexpr int R = ST + 1 >= 3 ? 3 : ST + 1;
+        inv_col_round_d<R, ST, L1>(s, W, q, qinv);
+        __syncthreads();
+        inv_cols_from_d<L1, ST - R>(s, W, q, qinv);
+    }
+}
+
+// L1 in 1..5 (fp64_limb holds)
+__device__ __forceinline__ void fwd_cols_any_d(double* s, int L1, const double* W, double q) {
+    switch (L1) {
+        case 1: fwd_cols_from_d<1, 0>(s, W, q); break;
+        case 2: fwd_cols_from_d<2, 0>(s, W, q); break;
+        case 3: fwd_cols_from_d<3, 0>(s, W, q); break;
+        case 4: fwd_cols_from_d<4, 0>(s, W, q); break;
+        default: fwd_cols_from_d<5, 0>(s, W, q); break;
+    }
+}
+
+__device__ __forceinline__ void inv_cols_any_d(double* s, int L1, const double* W, double q, double qinv) {
+    switch (L1) {
+        case 1: inv_cols_from_d<1, 0>(s, W, q, qinv); break;
+        case 2: inv_cols_from_d<2, 1>(s, W, q, qinv); break;
+        case 3: inv_cols_from_d<3, 2>(s, W, q, qinv); break;
+        case 4: inv_cols_from_d<4, 3>(s, W, q, qinv); break;
+        default: inv_cols_from_d<5, 4>(s, W, q, qinv); break;
+    }
+}
+
 __global__ __launch_bounds__(TPB) void k_ntt_fwd_cols(DevTables T, Jobs J) {
     __shared__ u64 s[NTT_E];
     const int N = 1 << T.log_n, L1 = T.n1_log, N2 = N >> L1;
@@ -476,6 +722,20 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_cols(DevTables T, Jobs J) {
     const u64* W = T.psi + (int64_t)mi * N;
     const u64* Ws = T.psi_sh + (int64_t)mi * N;
     const int c0 = blockIdx.x * C;
+    if (fp64_limb(q, L1, N2)) {
+        double* sd = reinterpret_cast<double*>(s);
+        for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB) {
+            const u64x2 v = ld2(a + (int64_t)(e >> logC) * N2 + c0 + (e & (C - 1)));
+            sd[e] = u2d(v.x);
+            sd[e + 1] = u2d(v.y);
+        }
+        __syncthreads();
+        fwd_cols_any_d(sd, L1, T.cold + (int64_t)mi * (2 << L1), (double)q);
+        // raw double words for the FP64 row pass of this limb
+        for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB)
+            st2(a + (int64_t)(e >> logC) * N2 + c0 + (e & (C - 1)), u64x2{d_bits(sd[e]), d_bits(sd[e + 1])});
+        return;
+    }
     for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB) {
         const u64x2 v = ld2(a + (int64_t)(e >> logC) * N2 + c0 + (e & (C - 1)));
         s[e] = v.x;
@@ -500,13 +760,23 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
     const u64 q = T.mods[mi].q, q2 = 2 * q;
     const u64* W = T.psi + (int64_t)mi * N;
     const u64* Ws = T.psi_sh + (int64_t)mi * N;
+    const bool fp = fp64_limb(q, L1, N2);
+    const double qd = (double)q, qinv = 1.0 / qd;
+    double* sd = reinterpret_cast<double*>(s);
     for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
         const u64x2 v = ld2(a + e);
-        s[lds_at<true>(e)] = v.x;
-        s[lds_at<true>(e + 1)] = v.y;
+        if (fp) {  // the column pass left raw doubles (N1 > 1), else canonical words
+            sd[lds_at<true>(e)] = L1 ? bits_d(v.x) : u2d(v.x);
+            sd[lds_at<true>(e + 1)] = L1 ? bits_d(v.y) : u2d(v.y);
+        } else {
+            s[lds_at<true>(e)] = v.x;
+            s[lds_at<true>(e + 1)] = v.y;
+        }
     }
     __syncthreads();
-    if (N2 == NTT_E) {
+    if (fp) {
+        fwd_rows_2048_d(sd, T.rtwd + ((int64_t)mi * N1 + r) * (2 * ROW_TW), qd);
+    } else if (N2 == NTT_E) {
         fwd_rows_2048(s, T.rtw + ((int64_t)mi * N1 + r) * (2 * ROW_TW), q);
     } else {  // small rings: plain radix-2 stages (N2 < 2048 only when N < 2048)
         for (int st = 0; st < L2; st++) {
@@ -523,10 +793,18 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
             __syncthreads();
         }
     }
+    // element e as a word: canonical (FP64 path) or lazy in [0, 4q) (integer path)
+    auto val = [&](int e) -> u64 { return fp ? canon_d(sd[lds_at<true>(e)], qd, qinv) : s[lds_at<true>(e)]; };
     if (!E.on) {
         for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
-            const u64 v0 = red4(s[lds_at<true>(e)], q2), v1 = red4(s[lds_at<true>(e + 1)], q2);
-            st2(a + e, u64x2{v0 >= q ? v0 - q : v0, v1 >= q ? v1 - q : v1});
+            u64 v0 = val(e), v1 = val(e + 1);
+            if (!fp) {
+                v0 = red4(v0, q2);
+                v1 = red4(v1, q2);
+                v0 = v0 >= q ? v0 - q : v0;
+                v1 = v1 >= q ? v1 - q : v1;
+            }
+            st2(a + e, u64x2{v0, v1});
         }
         return;
     }
@@ -544,9 +822,9 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
         u64 w[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            // v is lazy in [0, 4q) and u < q, so u + 4q - v lies in (0, 5q); the Shoup product
+            // v is below 4q and u < q, so u + 4q - v lies in (0, 5q); the Shoup product
             // reduces any 64-bit operand to [0, q)
-            const u64 v = s[lds_at<true>(e + h)];
+            const u64 v = val(e + h);
             w[h] = mul_shoup(uu[h] + 2 * q2 - v, pi, pis, q);
         }
         if (add) {
@@ -589,6 +867,34 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_rows(DevTables T, Jobs J, const
     const u64 q = mp_.q, q2 = 2 * q;
     const u64* W = T.ipsi + (int64_t)mi * N;
     const u64* Ws = T.ipsi_sh + (int64_t)mi * N;
+    if (fp64_limb(q, L1, N2)) {
+        const double qd = (double)q, qinv = 1.0 / qd;
+        double* sd = reinterpret_cast<double*>(s);
+        for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
+            const u64x2 v = ld2(a + e);
+            sd[lds_at<true>(e)] = u2d(v.x);
+            sd[lds_at<true>(e + 1)] = u2d(v.y);
+        }
+        __syncthreads();
+        inv_rows_2048_d(sd, T.irtwd + ((int64_t)mi * N1 + r) * (2 * ROW_TW), qd, qinv);
+        if (L1 == 0) {
+            const u64 f = scale ? scale[2 * (k % scale_n)] : mp_.ninv;
+            const double fd = (double)f, fq = fd / qd;
+            for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
+                u64 y[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    y[h] = canon_d(mulmod_d(sd[lds_at<true>(e + h)], fd, fq, qd), qd, qinv);
+                    if (scale) y[h] = y[h] > mp_.half ? y[h] - q : y[h];
+                }
+                st2(a + e, u64x2{y[0], y[1]});
+            }
+        } else {  // raw double words for the FP64 column pass of this limb
+            for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB)
+                st2(a + e, u64x2{d_bits(sd[lds_at<true>(e)]), d_bits(sd[lds_at<true>(e + 1)])});
+        }
+        return;
+    }
     for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
         const u64x2 v = ld2(a + e);
         s[lds_at<true>(e)] = v.x;
@@ -639,6 +945,29 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_cols(DevTables T, Jobs J, const
     const u64* W = T.ipsi + (int64_t)mi * N;
     const u64* Ws = T.ipsi_sh + (int64_t)mi * N;
     const int c0 = blockIdx.x * C;
+    if (fp64_limb(q, L1, N2)) {
+        const double qd = (double)q, qinv = 1.0 / qd;
+        double* sd = reinterpret_cast<double*>(s);
+        for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB) {  // raw doubles of the row pass
+            const u64x2 v = ld2(a + (int64_t)(e >> logC) * N2 + c0 + (e & (C - 1)));
+            sd[e] = bits_d(v.x);
+            sd[e + 1] = bits_d(v.y);
+        }
+        __syncthreads();
+        inv_cols_any_d(sd, L1, T.icold + (int64_t)mi * (2 << L1), qd, qinv);
+        const u64 f = scale ? scale[2 * (k % scale_n)] : mp_.ninv;
+        const double fd = (double)f, fq = fd / qd;
+        for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB) {
+            u64 y[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                y[h] = canon_d(mulmod_d(sd[e + h], fd, fq, qd), qd, qinv);
+                if (scale) y[h] = y[h] > mp_.half ? y[h] - q : y[h];
+            }
+            st2(a + (int64_t)(e >> logC) * N2 + c0 + (e & (C - 1)), u64x2{y[0], y[1]});
+        }
+        return;
+    }
     for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB) {
         const u64x2 v = ld2(a + (int64_t)(e >> logC) * N2 + c0 + (e & (C - 1)));
         s[e] = v.x;
@@ -684,6 +1013,8 @@ __global__ __launch_bounds__(TPB) void k_conv_cols(DevTables T, ConvDesc D) {
     const int x = pair % tiles, pc = pair / tiles, p = pc % D.npoly, c = pc / D.npoly;
     const int mi = D.dmod[t];
     const ModP m = T.mods[mi];
+    const bool fp = fp64_limb(m.q, L1, N2);
+    double* sd = reinterpret_cast<double*>(s);
     constexpr bool BAL = NS > 5;  // the balanced split keeps six to eight products in int64
     Split30 tw[NS];
 #pragma unroll
@@ -702,12 +1033,24 @@ __global__ __launch_bounds__(TPB) void k_conv_cols(DevTables T, ConvDesc D) {
             split30s<BAL>((int64_t)y.y, lo, hi);
             macs(a1, lo, hi, tw[i]);
         }
-        s[e] = redcs_lazy(a0, m.q, m.qninv);
-        s[e + 1] = redcs_lazy(a1, m.q, m.qninv);
+        const u64 r0 = redcs_lazy(a0, m.q, m.qninv), r1 = redcs_lazy(a1, m.q, m.qninv);
+        if (fp) {
+            sd[e] = u2d(r0);
+            sd[e + 1] = u2d(r1);
+        } else {
+            s[e] = r0;
+            s[e + 1] = r1;
+        }
     }
     __syncthreads();
-    fwd_cols_any(s, L1, T.psi + (int64_t)mi * N, T.psi_sh + (int64_t)mi * N, m.q);
     u64* a = D.dst + c * D.dst_cstride + p * D.dst_pstride + (int64_t)D.doff[t] * N;
+    if (fp) {  // raw double words for the FP64 row pass of this limb
+        fwd_cols_any_d(sd, L1, T.cold + (int64_t)mi * (2 << L1), (double)m.q);
+        for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB)
+            st2(a + (int64_t)(e >> logC) * N2 + col0 + (e & (C - 1)), u64x2{d_bits(sd[e]), d_bits(sd[e + 1])});
+        return;
+    }
+    fwd_cols_any(s, L1, T.psi + (int64_t)mi * N, T.psi_sh + (int64_t)mi * N, m.q);
     for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB)
         st2(a + (int64_t)(e >> logC) * N2 + col0 + (e & (C - 1)), u64x2{s[e], s[e + 1]});
 }

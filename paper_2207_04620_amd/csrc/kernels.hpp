@@ -46,6 +46,12 @@ struct DevTables {
     // its rounds consume them (forward: rtw, inverse: irtw)
     const u64* rtw;
     const u64* irtw;
+    // the same twiddles as doubles (w, fl(w / q)) for the FP64 butterflies of primes below
+    // 2^46 (zero for the others): row tables as above, column tables [M][N1]
+    const double* rtwd;
+    const double* irtwd;
+    const double* cold;
+    const double* icold;
     int log_n;
     int n1_log;  // column-pass stages
     int n2_log;  // row-pass stages
