@@ -856,7 +856,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
 // per-job constant scale[k mod scale_n] (pairs (c, c')): N^-1 times the (D/q_s)^-1 of a base
 // conversion that follows, and then stores the centred representative (y - q when y > (q-1)/2,
 // as a two's-complement word), so the conversion reads its prepared inputs directly.
-__global__ __launch_bounds__(TPB) void k_ntt_inv_rows(DevTables T, Jobs J, const u64* scale, int scale_n) {
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k_ntt_inv_rows(DevTables T, Jobs J, const u64* scale, int scale_n) {
     __shared__ u64 s[NTT_LDS];
     const int N = 1 << T.log_n, L1 = T.n1_log, L2 = T.n2_log, N1 = 1 << L1, N2 = 1 << L2;
     const int job = blockIdx.y, c = job / J.n, k = job % J.n;
@@ -995,7 +995,7 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_cols(DevTables T, Jobs J, const
 // the 8 XCDs round-robin, so the blocks of all targets of one source block are numbered to
 // run back to back on one XCD, where the source words stay in that XCD's L2.
 template <int NS>
-__global__ __launch_bounds__(TPB) void k_conv_cols(DevTables T, ConvDesc D) {
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k_conv_cols(DevTables T, ConvDesc D) {
     __shared__ u64 s[NTT_E];
     const int N = 1 << T.log_n, L1 = T.n1_log, N2 = N >> L1;
     const int logC = 11 - L1, C = 1 << logC;
