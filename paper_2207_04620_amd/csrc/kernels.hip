@@ -750,7 +750,7 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_cols(DevTables T, Jobs J) {
 
 __device__ __forceinline__ int perm_g(int j, u64 g, int log_n);
 
-__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E) {
+__global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E) {
     __shared__ u64 s[NTT_LDS];
     const int N = 1 << T.log_n, L1 = T.n1_log, L2 = T.n2_log, N1 = 1 << L1, N2 = 1 << L2;
     const int job = blockIdx.y, c = job / J.n, k = job % J.n;
