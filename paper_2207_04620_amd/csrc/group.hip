@@ -142,18 +142,25 @@ std::shared_ptr<DBuf> Ctx::g_lift(const Grp& a, int poly) {
     return lift;
 }
 
-// Key-switch inner product <lift o sigma_g, key> (+ P sigma_g(c0) on the Q limbs) of every
-// member into u [B][2][ne][N] (added to what u holds with accumulate); with a second
-// (g2, key2) and masks, the masked sum of two rotations of the same lift (one ModDown then
-// serves both)
-void Ctx::g_ks_inner(u64* u, const u64* lift, int B, int level, const u64* key, u64 g, const u64* c0,
-                     int64_t c0_cs, const u64* mask, const u64* key2, u64 g2, const u64* mask2, bool accumulate) {
+// g^-1 mod 2N (g odd): Newton's iteration x <- x (2 - g x) doubles the correct low bits
+static u64 galois_inverse(u64 g, int log_n) {
+    u64 x = g;  // g g = 1 mod 8
+    for (int it = 0; it < 6; ++it) x *= 2 - g * x;
+    return x & ((2ull << log_n) - 1);
+}
+
+// Key-switch inner products of several rotation sets of one lift in one launch: set s writes
+// <lift o sigma_g, key> (+ P sigma_g(c0) on the Q limbs) of every member into
+// u + s B [2][ne][N] (added to what u holds with accumulate); with nrot = 2 a set is the
+// masked sum of two rotations (one ModDown then serves both)
+void Ctx::g_ks_inner_sets(u64* u, const u64* lift, int B, int level, std::vector<IpSet> sets, int nrot,
+                          const u64* c0, int64_t c0_cs, bool accumulate) {
     const int nl = level + 1, ne = nl + n_p;
     const int beta = (int)mu[level].size();
+    if (sets.empty() || sets.size() > IP_MAXSET) throw HeError(HE_EUNSUPPORTED);
     IpDesc D;
     memset(&D, 0, sizeof D);
     D.lift = lift;
-    D.key = key;
     D.u = u;
     D.lift_cs = (int64_t)beta * ne * N;
     D.u_cs = 2 * (int64_t)ne * N;
@@ -161,20 +168,37 @@ void Ctx::g_ks_inner(u64* u, const u64* lift, int B, int level, const u64* key, 
     D.ne = ne;
     D.beta = beta;
     D.M = n_q + n_p;
-    D.g = g;
     for (int t = 0; t < ne; ++t) D.mod[t] = (uint8_t)ext_mod(level, t);
     D.c0 = c0;
     D.c0_cs = c0_cs;
     D.nq = nl;
     for (int t = 0; t < nl; ++t) D.pmont[t] = hm::to_mont(pmod[t], mods[t]);
-    D.nrot = key2 ? 2 : 1;
-    D.key2 = key2;
-    D.g2 = g2;
-    D.mask = mask;
-    D.mask2 = mask2;
+    D.nrot = nrot;
+    D.nset = (int)sets.size();
+    for (size_t j = 0; j < sets.size(); ++j) {
+        D.s[j] = sets[j];
+        D.s[j].ginv = galois_inverse(sets[j].g, log_n);
+    }
     D.accumulate = accumulate ? 1 : 0;
     launch_inner_product(T, D, stream);
-    cnt[C_KS] += (int64_t)B * D.nrot;
+    cnt[C_KS] += (int64_t)B * nrot * D.nset;
+}
+
+// Key-switch inner product <lift o sigma_g, key> (+ P sigma_g(c0) on the Q limbs) of every
+// member into u [B][2][ne][N] (added to what u holds with accumulate); with a second
+// (g2, key2) and masks, the masked sum of two rotations of the same lift (one ModDown then
+// serves both)
+void Ctx::g_ks_inner(u64* u, const u64* lift, int B, int level, const u64* key, u64 g, const u64* c0,
+                     int64_t c0_cs, const u64* mask, const u64* key2, u64 g2, const u64* mask2, bool accumulate) {
+    IpSet S;
+    memset(&S, 0, sizeof S);
+    S.key = key;
+    S.g = g;
+    S.mask = mask;
+    S.key2 = key2;
+    S.g2 = g2;
+    S.mask2 = mask2;
+    g_ks_inner_sets(u, lift, B, level, {S}, key2 ? 2 : 1, c0, c0_cs, accumulate);
 }
 
 // out = ModDown(u) (+ add gathered by add_g) (. mask) (+ acc), for every member; u as made
@@ -271,13 +295,13 @@ void Ctx::g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, c
     g_moddown(u.p, B, level, add0, add1, add_cs, out0, out1, out_cs, add_g, mask, acc0, acc1, acc_cs);
 }
 
-// Several mask pairs of one ciphertext at once (Step 2 under the hoisted-ModDown schedule):
-// each pair's inner product goes into its slice of one extended-basis buffer, and a single
-// ModDown then serves all pairs, so its transforms and conversion run as one launch over
-// P x B members; the results are views into one block
-std::vector<Grp> Ctx::g_rotate_pairs_hoisted(const Grp& a, const u64* lift, const std::vector<MaskPair>& pr,
-                                             double mask_scale) {
-    const int P = (int)pr.size(), B = a.B, ne = a.level + 1 + n_p;
+// Several rotation sets of one ciphertext at once: each set's inner product goes into its
+// slice of one extended-basis buffer (one launch: the sets' gathers of the shared lift meet
+// in L2), and a single ModDown then serves all sets, so its transforms and conversion run as
+// one launch over nset x B members; the results are views into one block
+std::vector<Grp> Ctx::g_rotate_sets_hoisted(const Grp& a, const u64* lift, const std::vector<IpSet>& sets,
+                                            int nrot, double mask_scale) {
+    const int P = (int)sets.size(), B = a.B, ne = a.level + 1 + n_p;
     if (a.deg != 1) throw HeError(HE_EMISMATCH);
     std::vector<double> sc;
     for (int j = 0; j < P; ++j)
@@ -285,17 +309,9 @@ std::vector<Grp> Ctx::g_rotate_pairs_hoisted(const Grp& a, const u64* lift, cons
     Grp out = g_new(P * B, a.level, 1, sc);
     const int64_t ucs = 2 * (int64_t)ne * N;
     DBuf u(this, (size_t)P * B * ucs);
-    for (int j = 0; j < P; ++j) {
-        const u64 g1 = galois(pr[j].k1), g2 = galois(pr[j].k2);
-        if (g1 == 1 || g2 == 1) throw HeError(HE_EUNSUPPORTED);
-        g_ks_inner(u.p + (size_t)j * B * ucs, lift, B, a.level, rot_key(g1, false), g1, a.p, a.cs, pr[j].m1,
-                   rot_key(g2, false), g2, pr[j].m2, false);
-    }
+    g_ks_inner_sets(u.p, lift, B, a.level, sets, nrot, a.p, a.cs, false);
     g_moddown(u.p, P * B, a.level, nullptr, nullptr, 0, out.p, out.p + out.ps, out.cs, 1, nullptr, nullptr, nullptr,
               0);
-    cnt[C_ROT] += 2 * P * B;
-    cnt[C_MULPT] += 2 * P * B;
-    cnt[C_ADD] += P * B;
     std::vector<Grp> res(P);
     for (int j = 0; j < P; ++j) {
         res[j] = out;
@@ -303,6 +319,47 @@ std::vector<Grp> Ctx::g_rotate_pairs_hoisted(const Grp& a, const u64* lift, cons
         res[j].p = out.p + (size_t)j * B * out.cs;
         res[j].scale.assign(sc.begin() + (size_t)j * B, sc.begin() + (size_t)(j + 1) * B);
     }
+    return res;
+}
+
+// Several mask pairs of one ciphertext at once (Step 2 under the hoisted-ModDown schedule):
+// mask1 . Rot(a, k1) + mask2 . Rot(a, k2) for every pair, with one shared ModDown
+std::vector<Grp> Ctx::g_rotate_pairs_hoisted(const Grp& a, const u64* lift, const std::vector<MaskPair>& pr,
+                                             double mask_scale) {
+    const int P = (int)pr.size(), B = a.B;
+    std::vector<IpSet> sets(P);
+    for (int j = 0; j < P; ++j) {
+        const u64 g1 = galois(pr[j].k1), g2 = galois(pr[j].k2);
+        if (g1 == 1 || g2 == 1) throw HeError(HE_EUNSUPPORTED);
+        memset(&sets[j], 0, sizeof(IpSet));
+        sets[j].key = rot_key(g1, false);
+        sets[j].g = g1;
+        sets[j].mask = pr[j].m1;
+        sets[j].key2 = rot_key(g2, false);
+        sets[j].g2 = g2;
+        sets[j].mask2 = pr[j].m2;
+    }
+    auto res = g_rotate_sets_hoisted(a, lift, sets, 2, mask_scale);
+    cnt[C_ROT] += 2 * P * B;
+    cnt[C_MULPT] += 2 * P * B;
+    cnt[C_ADD] += P * B;
+    return res;
+}
+
+// Rot(a, k) for several k of one lift, with one shared ModDown (Step 3's baby rotations
+// under the hoisted-ModDown schedule); identical to rotating one at a time
+std::vector<Grp> Ctx::g_rotate_many_hoisted(const Grp& a, const u64* lift, const std::vector<int64_t>& ks) {
+    const int P = (int)ks.size(), B = a.B;
+    std::vector<IpSet> sets(P);
+    for (int j = 0; j < P; ++j) {
+        const u64 g = galois(ks[j]);
+        if (g == 1) throw HeError(HE_EUNSUPPORTED);
+        memset(&sets[j], 0, sizeof(IpSet));
+        sets[j].key = rot_key(g, false);
+        sets[j].g = g;
+    }
+    auto res = g_rotate_sets_hoisted(a, lift, sets, 1, 1.0);
+    cnt[C_ROT] += (int64_t)P * B;
     return res;
 }
 
@@ -631,8 +688,8 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
         if (keep_baby && J.babyB.empty()) J.babyB.resize(bg);
         const int kend = std::min(t, J.k + std::max(1, k_chunk));
         // hoisted schedule: the mask pairs of up to pair_batch consecutive k share one ModDown
-        std::vector<Grp> pairs;
-        int pairs_k0 = 0;
+        std::vector<Grp> pairs, babies;
+        int pairs_k0 = 0, babies_j0 = 0;
         for (int k = J.k; k < kend; ++k) {
             const int i = k / bg, j = k % bg;
             const int64_t shift = (int64_t)h * bg * i;
@@ -664,6 +721,19 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
                 Bj = J.B0;
             } else if (i > 0) {
                 Bj = J.babyB[j];
+            } else if (hoist) {
+                // baby rotations of B0, up to pair_batch at a time with one shared ModDown
+                // (kept for the later blocks, or until used within this chunk)
+                if (keep_baby ? !J.babyB[j].p : (babies.empty() || j - babies_j0 >= (int)babies.size())) {
+                    const int jend = std::min(keep_baby ? bg : kend, j + std::max(1, pair_batch));
+                    std::vector<int64_t> ks;
+                    for (int jj = j; jj < jend; ++jj) ks.push_back((int64_t)beta * h * jj);
+                    babies = g_rotate_many_hoisted(J.B0, J.liftB->p, ks);
+                    babies_j0 = j;
+                    if (keep_baby)
+                        for (int jj = j; jj < jend; ++jj) J.babyB[jj] = babies[jj - j];
+                }
+                Bj = keep_baby ? J.babyB[j] : babies[j - babies_j0];
             } else {
                 Bj = g_rotate_from_lift(J.B0, J.liftB->p, (int64_t)beta * h * j);
                 if (keep_baby) J.babyB[j] = Bj;

@@ -721,12 +721,14 @@ void Ctx::ks_apply(const u64* lift, int level, const u64* key, u64 g, const u64*
     IpDesc D;
     memset(&D, 0, sizeof D);
     D.lift = lift;
-    D.key = key;
     D.u = u.p;
     D.ne = ne;
     D.beta = beta;
     D.M = n_q + n_p;
-    D.g = g;
+    D.nrot = 1;
+    D.nset = 1;
+    D.s[0].key = key;
+    D.s[0].g = g;
     D.nct = 1;
     D.lift_cs = 0;
     D.u_cs = 0;

@@ -221,11 +221,16 @@ struct Ctx {
     std::shared_ptr<DBuf> g_lift(const Grp& a, int poly);
     void g_ks_inner(u64* u, const u64* lift, int B, int level, const u64* key, u64 g, const u64* c0, int64_t c0_cs,
                     const u64* mask, const u64* key2, u64 g2, const u64* mask2, bool accumulate);
+    void g_ks_inner_sets(u64* u, const u64* lift, int B, int level, std::vector<IpSet> sets, int nrot,
+                         const u64* c0, int64_t c0_cs, bool accumulate);
     void g_rotsum_add(RotSum& S, const Grp& a, int64_t r);
     Grp g_rotsum_finish(RotSum& S, const Grp* base);
     void g_moddown(u64* u, int B, int level, const u64* add0, const u64* add1, int64_t add_cs, u64* out0,
                    u64* out1, int64_t out_cs, u64 add_g, const u64* mask, const u64* acc0, const u64* acc1,
                    int64_t acc_cs);
+    std::vector<Grp> g_rotate_sets_hoisted(const Grp& a, const u64* lift, const std::vector<IpSet>& sets, int nrot,
+                                           double mask_scale);
+    std::vector<Grp> g_rotate_many_hoisted(const Grp& a, const u64* lift, const std::vector<int64_t>& ks);
     std::vector<Grp> g_rotate_pairs_hoisted(const Grp& a, const u64* lift, const std::vector<MaskPair>& pr,
                                             double mask_scale);
     void g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, const u64* add0, const u64* add1,

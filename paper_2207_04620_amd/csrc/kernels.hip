@@ -1497,15 +1497,35 @@ __device__ __forceinline__ void ip_reduce(const u64 (&x)[NR][NB], const u64 (&z)
     }
 }
 
-// Grid (N / TPB, ne): one thread per (slot, extended limb) for every member, so each key
-// word (and mask word) is read once per group.  The digit count NB is a template
+// Grid (nset N / TPB, ne): one thread per (set, slot, extended limb) for every member, so
+// each key word (and mask word) is read once per group.  The digit count NB is a template
 // parameter so that the key words stay in registers; the member loop is software-
 // pipelined (the next member's lift and c0 words are loaded before the current member's
-// arithmetic) to keep more loads in flight.
+// arithmetic) to keep more loads in flight.  sigma_g maps each aligned block of TPB slots
+// onto one aligned block of TPB source slots (the top bits of perm_g(i) depend only on the
+// top bits of i), so with several sets the blocks are numbered by the lift block they
+// gather: the sets' blocks of one source block get consecutive numbers on one XCD
+// (workgroups are dealt to the 8 XCDs round-robin), run together there, and read the
+// lift and c0 words of each member through that XCD's L2 once for all sets.
 template <int NB, int NR>
 __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
-    const int N = 1 << T.log_n;
-    const int i = blockIdx.x * TPB + threadIdx.x;
+    const int N = 1 << T.log_n, nb = N / TPB;
+    int xb = blockIdx.x, sj = 0;
+    if (D.nset > 1) {
+        int R;
+        if ((nb & 7) == 0) {
+            const int hi = xb >> 3;
+            sj = hi % D.nset;
+            R = (hi / D.nset) * 8 + (xb & 7);
+        } else {
+            sj = xb / nb;
+            R = xb % nb;
+        }
+        // the output block whose first rotation gathers from source block R
+        xb = perm_g(R * TPB, D.s[sj].ginv, T.log_n) / TPB;
+    }
+    const IpSet& S = D.s[sj];
+    const int i = xb * TPB + threadIdx.x;
     const int t = blockIdx.y;
     const int mi = D.mod[t];
     const ModP m = T.mods[mi];
@@ -1516,9 +1536,9 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
     int src[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) {
-        const u64 g = r ? D.g2 : D.g;
-        const u64* key = r ? D.key2 : D.key;
-        const u64* mask = r ? D.mask2 : D.mask;
+        const u64 g = r ? S.g2 : S.g;
+        const u64* key = r ? S.key2 : S.key;
+        const u64* mask = r ? S.mask2 : S.mask;
         src[r] = g == 1 ? i : perm_g(i, g, T.log_n);
         const u64 mk = mask ? mask[(int64_t)mi * N + i] : 0;
 #pragma unroll
@@ -1544,13 +1564,14 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
             zo[r] = with_c0 ? D.c0[c * D.c0_cs + (int64_t)t * N + src[r]] : 0;
         }
     };
+    u64* const ub = D.u + (int64_t)sj * D.nct * D.u_cs;
     load(0, x, z);
     for (int c = 0; c < D.nct; c++) {
         u64 xn[NR][NB], zn[NR];
         if (c + 1 < D.nct) load(c + 1, xn, zn);
         u64 v0, v1;
         ip_reduce<NB, NR>(x, z, kb, ka, pm, with_c0, m, v0, v1);
-        u64* u = D.u + c * D.u_cs;
+        u64* u = ub + c * D.u_cs;
         if (D.accumulate) {
             v0 = add_mod(v0, u[(int64_t)t * N + i], m.q);
             v1 = add_mod(v1, u[((int64_t)D.ne + t) * N + i], m.q);
@@ -1575,15 +1596,19 @@ static void launch_ip_nb(const DevTables& T, const IpDesc& D, dim3 grid, hipStre
 }
 
 void launch_inner_product(const DevTables& T, const IpDesc& D, hipStream_t st) {
-    const int nr = D.nrot == 2 ? 2 : 1;
-    // keys (and masks) once per group; per member the lift digits and c0 once (the rotations
-    // of a pair gather the same lift) and u
-    const double words = (double)D.ne * (nr * 2.0 * D.beta + (D.mask ? 1.0 : 0.0) + (D.mask2 ? 1.0 : 0.0) +
-                                         D.nct * ((double)D.beta + (D.accumulate ? 4.0 : 2.0))) +
-                         (D.c0 ? (double)D.nq * D.nct : 0.0);
-    ProfScope prof_(PK_INNER, words * 8.0 * (1 << T.log_n), st);
+    const int nr = D.nrot == 2 ? 2 : 1, ns = D.nset;
     const int N = 1 << T.log_n;
-    dim3 grid(ceil_div(N, TPB), D.ne);
+    if (ns < 1 || ns > IP_MAXSET) throw std::runtime_error("inner product: set count out of range");
+    if (N < TPB) throw std::runtime_error("inner product: ring smaller than a block");
+    // keys (and masks) once per group; per member the lift digits and c0 once (the rotations
+    // of a pair and the sets of a launch gather the same lift) and u per set
+    double masks = 0;
+    for (int j = 0; j < ns; ++j) masks += (D.s[j].mask ? 1.0 : 0.0) + (nr == 2 && D.s[j].mask2 ? 1.0 : 0.0);
+    const double words = (double)D.ne * (ns * nr * 2.0 * D.beta + masks +
+                                         D.nct * ((double)D.beta + ns * (D.accumulate ? 4.0 : 2.0))) +
+                         (D.c0 ? (double)D.nq * D.nct : 0.0);
+    ProfScope prof_(PK_INNER, words * 8.0 * N, st);
+    dim3 grid((N / TPB) * ns, D.ne);
     switch (D.beta) {
         case 1: launch_ip_nb<1>(T, D, grid, st); break;
         case 2: launch_ip_nb<2>(T, D, grid, st); break;

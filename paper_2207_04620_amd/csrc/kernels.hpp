@@ -91,14 +91,24 @@ struct SampleArgs {
 
 // Key switch inner product: for ext limb t (prime mod[t]) and coefficient i,
 //  u0[t][i] = sum_j lift[j][t][perm_g(i)] kb[j][mod[t]][i], u1 likewise with ka.
+// One rotation set of a key-switch inner product: a rotation (g, key), or with nrot = 2 the
+// masked sum mask . IP(g, key) + mask2 . IP(g2, key2) of two rotations of the same lift (one
+// ModDown then serves both).  ginv = g^-1 mod 2N numbers the set's blocks by lift region.
+struct IpSet {
+    const u64* key;    // [beta_top][2][M][N] Montgomery form
+    const u64* key2;
+    const u64* mask;   // [M][N] Montgomery form, row = modulus index; null = no mask
+    const u64* mask2;
+    u64 g, g2, ginv;   // Galois elements (1 = identity)
+};
+#define IP_MAXSET 16
+
 struct IpDesc {
     const u64* lift;  // [nct][beta][ne][N] (ciphertext stride lift_cs)
-    const u64* key;   // [beta_top][2][M][N] Montgomery form
-    u64* u;           // [nct][2][ne][N] (ciphertext stride u_cs)
+    u64* u;           // [nset][nct][2][ne][N] (ciphertext stride u_cs)
     int64_t lift_cs, u_cs;
     int nct;
     int ne, beta, M;
-    u64 g;            // Galois element (1 = identity)
     uint8_t mod[HE_MAXT];
     // optional: u0[t] += P * c0[t][perm_g(i)] on the Q limbs t < nq (c0 of the rotated
     // ciphertext; ModDown then yields (u0 - conv) P^-1 + sigma_g(c0) exactly)
@@ -106,13 +116,9 @@ struct IpDesc {
     int64_t c0_cs;
     int nq;
     u64 pmont[HE_MAXT];  // (P mod q_t) R mod q_t
-    // optional second rotation of the same lift: with nrot = 2 the kernel forms
-    // mask . IP(g, key) + mask2 . IP(g2, key2) in the extended basis (one ModDown for both)
-    int nrot;
-    u64 g2;
-    const u64* key2;
-    const u64* mask;   // [M][N] Montgomery form, row = modulus index; null = no mask
-    const u64* mask2;
+    int nrot;            // rotations per set (1 or 2)
+    int nset;            // sets of the same lift in this launch (at most IP_MAXSET)
+    IpSet s[IP_MAXSET];
     int accumulate;    // u += the result (a sum of rotations of different ciphertexts)
 };
 
