@@ -591,7 +591,24 @@ Grp Ctx::g_lintrans(const Grp& a, int kind, int h, int beta, int64_t unit, int d
     baby[0] = a;
     if (b > 1) {
         auto lift = g_lift(a, 1);
-        for (int j = 1; j < b; ++j) baby[j] = g_rotate_from_lift(a, lift->p, (int64_t)beta * unit * j);
+        if (hoist) {
+            // up to pair_batch babies per launch, with one shared ModDown
+            // (a rotation that is the identity on the slots is the ciphertext itself)
+            std::vector<int> js;
+            for (int j = 1; j < b; ++j) {
+                if (galois((int64_t)beta * unit * j) == 1) baby[j] = g_drop(a, a.level);
+                else js.push_back(j);
+            }
+            const size_t pb = (size_t)std::max(1, pair_batch);
+            for (size_t j0 = 0; j0 < js.size(); j0 += pb) {
+                std::vector<int64_t> ks;
+                for (size_t j = j0; j < std::min(js.size(), j0 + pb); ++j) ks.push_back((int64_t)beta * unit * js[j]);
+                auto r = g_rotate_many_hoisted(a, lift->p, ks);
+                for (size_t j = 0; j < r.size(); ++j) baby[js[j0 + j]] = r[j];
+            }
+        } else {
+            for (int j = 1; j < b; ++j) baby[j] = g_rotate_from_lift(a, lift->p, (int64_t)beta * unit * j);
+        }
     }
     RotSum gsum;
     Grp acc;
