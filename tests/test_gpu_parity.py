@@ -224,6 +224,29 @@ def test_matmul_schedule_parity(he, schedule):
         assert np.array_equal(p.g.export(r), s)
 
 
+@pytest.mark.parametrize("log_n", [8, 10])
+@pytest.mark.parametrize("schedule", [2, 15])
+def test_matmul_rings_of_few_blocks(he, log_n, schedule):
+    """rings with fewer than eight 256-slot blocks per limb (the rotation-set launches number
+    their blocks without the XCD grouping there): single and batched products bit-exact"""
+    prm = I.small(log_n=log_n, n_q=5, alpha=2, q_bits=40, p_bits=50, h_list=(4, 8))
+    p = Pair(he, prm, schedule=schedule)
+    for h in (4, 8):
+        _log(f"[parity] matmul N=2^{log_n} schedule={schedule} h={h}")
+        A, B = I.matrix_pair(500 + log_n + h, h)
+        gm = p.g.matmul(p.g.encrypt(A.ravel(), nonce=1), p.g.encrypt(B.ravel(), nonce=2), h)
+        om = p.o.matmul(p.o.encrypt(A.ravel(), nonce=1), p.o.encrypt(B.ravel(), nonce=2), h, schedule)
+        p.same(gm, om)
+    As, Bs, singles = [], [], []
+    for i in range(3):
+        A, B = I.matrix_pair(520 + i, 8)
+        a, b = p.g.encrypt(A.ravel(), nonce=20 + 2 * i), p.g.encrypt(B.ravel(), nonce=21 + 2 * i)
+        As.append(a), Bs.append(b)
+        singles.append(p.g.export(p.g.matmul(a, b, 8)))
+    for r, s1 in zip(p.g.matmul_batch(As, Bs, [8, 8, 8]), singles):
+        assert np.array_equal(p.g.export(r), s1)
+
+
 def test_matmul_fast_schedule_c1plus_bound(he):
     """the stated accuracy (1e-3 at scale 2^30, 2^12 ring, h = 8) under all four flags"""
     p = Pair(he, I.C1P, schedule=15)
