@@ -217,6 +217,9 @@ void Ctx::build_tables() {
     T.log_n = log_n;
     T.n2_log = std::min(log_n, 11);
     T.n1_log = log_n - T.n2_log;
+    T.fp64_mods = 0;
+    for (int m = 0; m < M; ++m)
+        if (fp64_limb(mp[m].q, T.n1_log, 1 << T.n2_log)) T.fp64_mods |= 1ull << m;
     host_mods = mp;
 
     // ---- row-pass twiddles in consumption order (N >= 2^11): row r of the second pass works

@@ -31,7 +31,7 @@ static const char* const kProfNames[PK_COUNT] = {
 struct ProfRec {
     int kind;
     hipEvent_t a, b;
-    double bytes, ops;
+    double bytes, ops, fp_ops;
 };
 static bool g_prof_on = false;
 static int g_prof_only = -1;  // -1: every kind, else the one kind that is timed
@@ -51,10 +51,12 @@ static hipEvent_t ev_get() {
 
 struct ProfScope {
     int kind;
-    double bytes, ops;
+    double bytes, ops, fp_ops;
     hipStream_t st;
     hipEvent_t a = nullptr;
-    ProfScope(int k, double b, hipStream_t s, double o = 0) : kind(k), bytes(b), ops(o), st(s) {
+    // ops: butterflies of the launch, fp_ops of them FP64
+    ProfScope(int k, double b, hipStream_t s, double o = 0, double fo = 0)
+        : kind(k), bytes(b), ops(o), fp_ops(fo), st(s) {
         if (g_prof_on && (g_prof_only < 0 || g_prof_only == k)) {
             a = ev_get();
             (void)hipEventRecord(a, st);
@@ -64,7 +66,7 @@ struct ProfScope {
         if (g_prof_on && a) {
             hipEvent_t b = ev_get();
             (void)hipEventRecord(b, st);
-            g_prof.push_back({kind, a, b, bytes, ops});
+            g_prof.push_back({kind, a, b, bytes, ops, fp_ops});
         }
     }
 };
@@ -82,7 +84,7 @@ bool prof_enable(bool on, const char* only) {
 }
 
 std::string prof_report() {
-    double ms[PK_COUNT] = {0}, by[PK_COUNT] = {0}, op[PK_COUNT] = {0};
+    double ms[PK_COUNT] = {0}, by[PK_COUNT] = {0}, op[PK_COUNT] = {0}, fo[PK_COUNT] = {0};
     long cnt[PK_COUNT] = {0};
     for (auto& r : g_prof) {
         (void)hipEventSynchronize(r.b);
@@ -91,6 +93,7 @@ std::string prof_report() {
         ms[r.kind] += t;
         by[r.kind] += r.bytes;
         op[r.kind] += r.ops;
+        fo[r.kind] += r.fp_ops;
         cnt[r.kind]++;
         g_ev_free.push_back(r.a);
         g_ev_free.push_back(r.b);
@@ -99,8 +102,9 @@ std::string prof_report() {
     std::string out = "{";
     for (int k = 0; k < PK_COUNT; ++k) {
         char buf[256];
-        snprintf(buf, sizeof buf, "%s\"%s\": {\"launches\": %ld, \"ms\": %.6f, \"bytes\": %.0f, \"ops\": %.0f}",
-                 k ? ", " : "", kProfNames[k], cnt[k], ms[k], by[k], op[k]);
+        snprintf(buf, sizeof buf,
+                 "%s\"%s\": {\"launches\": %ld, \"ms\": %.6f, \"bytes\": %.0f, \"ops\": %.0f, \"fp_ops\": %.0f}",
+                 k ? ", " : "", kProfNames[k], cnt[k], ms[k], by[k], op[k], fo[k]);
         out += buf;
     }
     return out + "}";
@@ -475,10 +479,9 @@ __device__ __forceinline__ void inv_cols_any(u64* s, int L1, const u64* W, const
 // v_fma_f64, v_rndne_f64, v_add_f64), against 27 for the 64-bit integer Shoup butterfly.
 // Between the two passes of a transform the limb holds the raw double words; the transform's
 // output is canonical.  Both passes of a limb decide by the same rule (fp64_limb).
-#define FP64_QMAX (1ull << 46)
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ f64x2 ld2d(const double* p) { return *reinterpret_cast<const f64x2*>(p); }
-__device__ __forceinline__ bool fp64_limb(u64 q, int L1, int N2) { return q < FP64_QMAX && N2 == NTT_E && L1 <= 5; }
+static_assert(NTT_E == 2048, "the FP64 rule assumes 2048-element rows");
 // exact for x < 2^52
 __device__ __forceinline__ double u2d(u64 x) {
     return __longlong_as_double((long long)(x | 0x4330000000000000ull)) - 4503599627370496.0;
@@ -750,6 +753,9 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_cols(DevTables T, Jobs J) {
 
 __device__ __forceinline__ int perm_g(int j, u64 g, int log_n);
 
+// EPI: the ModDown epilogue (E.on) is compiled in; without it the plain transform keeps its
+// smaller register footprint
+template <bool EPI>
 __global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E) {
     __shared__ u64 s[NTT_LDS];
     const int N = 1 << T.log_n, L1 = T.n1_log, L2 = T.n2_log, N1 = 1 << L1, N2 = 1 << L2;
@@ -795,7 +801,7 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E
     }
     // element e as a word: canonical (FP64 path) or lazy in [0, 4q) (integer path)
     auto val = [&](int e) -> u64 { return fp ? canon_d(sd[lds_at<true>(e)], qd, qinv) : s[lds_at<true>(e)]; };
-    if (!E.on) {
+    if constexpr (!EPI) {
         for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
             u64 v0 = val(e), v1 = val(e + 1);
             if (!fp) {
@@ -1069,22 +1075,30 @@ static void check_ntt_alignment(const Jobs& J, const Epi* E) {
     if (bad) throw std::runtime_error("NTT operand not 16-byte aligned");
 }
 
+// limbs of a job list that run FP64 butterflies (for the profile's operation counts)
+static double fp64_limbs(const DevTables& T, const Jobs& J) {
+    int n = 0;
+    for (int k = 0; k < J.n; ++k) n += (int)((T.fp64_mods >> J.mod[k]) & 1);
+    return (double)n * J.nct;
+}
+
 void launch_ntt_moddown(const DevTables& T, const Jobs& J, const Epi& E, hipStream_t st, bool cols) {
     if (J.n == 0 || J.nct == 0) return;
     check_ntt_alignment(J, &E);
     const int N = 1 << T.log_n, N1 = 1 << T.n1_log;
     dim3 grid_rows(N1, J.n * J.nct), grid_cols(N / NTT_E, J.n * J.nct);
-    const double limbs = (double)J.n * J.nct;
+    const double limbs = (double)J.n * J.nct, fl = fp64_limbs(T, J);
     if (T.n1_log > 0 && cols) {
-        ProfScope p(PK_NTT_FWD_COLS, 16.0 * limbs * N, st, limbs * (N / 2) * T.n1_log);
+        ProfScope p(PK_NTT_FWD_COLS, 16.0 * limbs * N, st, limbs * (N / 2) * T.n1_log, fl * (N / 2) * T.n1_log);
         hipLaunchKernelGGL(k_ntt_fwd_cols, grid_cols, dim3(TPB), 0, st, T, J);
     }
     // reads the converted limb and u, writes the output; plus the optional add and
     // accumulator operands (per ciphertext) and the mask (shared by the group)
     const double per_ct = (E.add[0] ? 1 : 0) + (E.add[1] ? 1 : 0) + (E.acc[0] ? 1 : 0) + (E.acc[1] ? 1 : 0);
     const double rows_bytes = 8.0 * N * (3 * limbs + per_ct * E.nl * J.nct + (E.mask ? E.nl : 0));
-    ProfScope p(PK_NTT_FWD_ROWS, rows_bytes, st, limbs * (N / 2) * T.n2_log);
-    hipLaunchKernelGGL(k_ntt_fwd_rows, grid_rows, dim3(TPB), 0, st, T, J, E);
+    ProfScope p(PK_NTT_FWD_ROWS, rows_bytes, st, limbs * (N / 2) * T.n2_log, fl * (N / 2) * T.n2_log);
+    if (!E.on) throw std::runtime_error("ModDown row pass without its epilogue");
+    hipLaunchKernelGGL(k_ntt_fwd_rows<true>, grid_rows, dim3(TPB), 0, st, T, J, E);
 }
 
 void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st, const u64* scale, int scale_n,
@@ -1098,20 +1112,21 @@ void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st,
     dim3 grid_rows(N1, J.n * J.nct), grid_cols(N / NTT_E, J.n * J.nct);
     const double limbs = (double)J.n * J.nct;
     const double bytes = 16.0 * limbs * N, b1 = limbs * (N / 2) * T.n1_log, b2 = limbs * (N / 2) * T.n2_log;
+    const double fl = fp64_limbs(T, J), f1 = fl * (N / 2) * T.n1_log, f2 = fl * (N / 2) * T.n2_log;
     if (!inverse) {
         if (T.n1_log > 0 && cols) {
-            ProfScope p(PK_NTT_FWD_COLS, bytes, st, b1);
+            ProfScope p(PK_NTT_FWD_COLS, bytes, st, b1, f1);
             hipLaunchKernelGGL(k_ntt_fwd_cols, grid_cols, dim3(TPB), 0, st, T, J);
         }
-        ProfScope p(PK_NTT_FWD_ROWS, bytes, st, b2);
-        hipLaunchKernelGGL(k_ntt_fwd_rows, grid_rows, dim3(TPB), 0, st, T, J, E);
+        ProfScope p(PK_NTT_FWD_ROWS, bytes, st, b2, f2);
+        hipLaunchKernelGGL(k_ntt_fwd_rows<false>, grid_rows, dim3(TPB), 0, st, T, J, E);
     } else {
         {
-            ProfScope p(PK_NTT_INV_ROWS, bytes, st, b2);
+            ProfScope p(PK_NTT_INV_ROWS, bytes, st, b2, f2);
             hipLaunchKernelGGL(k_ntt_inv_rows, grid_rows, dim3(TPB), 0, st, T, J, scale, scale_n);
         }
         if (T.n1_log > 0) {
-            ProfScope p(PK_NTT_INV_COLS, bytes, st, b1);
+            ProfScope p(PK_NTT_INV_COLS, bytes, st, b1, f1);
             hipLaunchKernelGGL(k_ntt_inv_cols, grid_cols, dim3(TPB), 0, st, T, J, scale, scale_n);
         }
     }
@@ -1207,8 +1222,10 @@ void launch_conv_cols(const DevTables& T, const ConvDesc& D, hipStream_t st) {
         throw std::runtime_error("conv_cols operand not 16-byte aligned");
     const int N = 1 << T.log_n;
     const double units = (double)D.nt * D.npoly * D.nct;
+    double fpu = 0;
+    for (int t = 0; t < D.nt; ++t) fpu += (double)((T.fp64_mods >> D.dmod[t]) & 1) * D.npoly * D.nct;
     ProfScope prof_(PK_CONV_COLS, ((double)D.ns * D.npoly * D.nct + units) * 8.0 * N, st,
-                    units * (N / 2) * T.n1_log);
+                    units * (N / 2) * T.n1_log, fpu * (N / 2) * T.n1_log);
     dim3 grid((N / NTT_E) * D.npoly * D.nct * D.nt);
     switch (D.ns) {
         case 1: hipLaunchKernelGGL(k_conv_cols<1>, grid, dim3(TPB), 0, st, T, D); break;

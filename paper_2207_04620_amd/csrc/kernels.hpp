@@ -55,7 +55,14 @@ struct DevTables {
     int log_n;
     int n1_log;  // column-pass stages
     int n2_log;  // row-pass stages
+    u64 fp64_mods;  // bit m set: limbs of prime m run the FP64 butterflies (host-side count)
 };
+
+// The transforms of a limb use FP64 butterflies when its prime is below 2^46, the row pass
+// holds 2048 elements and the column pass has at most five stages; both passes of a limb
+// decide by this one rule.
+#define FP64_QMAX (1ull << 46)
+__host__ __device__ inline bool fp64_limb(u64 q, int L1, int N2) { return q < FP64_QMAX && N2 == 2048 && L1 <= 5; }
 
 // Centered fast base conversion from ns source limbs to nt target limbs, for npoly
 // polynomials.  Source limb s of poly p at src + p * src_pstride + s * N (coefficient
