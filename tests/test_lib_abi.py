@@ -26,7 +26,7 @@ def libpath():
     return he.LIB_PATH
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_hot_path_calls():
     names = declared()
     for n in ("he_ctx_create", "he_encrypt", "he_matmul", "he_rotate", "he_sign_approx", "he_decrypt",
               "he_matmul_batch", "he_ct_export", "he_ct_import", "he_encrypt_coeffs", "he_serve_start"):
