@@ -363,25 +363,46 @@ std::vector<Grp> Ctx::g_rotate_many_hoisted(const Grp& a, const u64* lift, const
     return res;
 }
 
-// Hoisted rotation sums: base + sum_w Rot(a_w, r_w) with one ModDown.  Each term's
-// key-switch inner product (with P sigma_g(c0_w)) is accumulated in the extended basis as it
-// arrives (its lift is freed at once); finish brings the sum down once and adds the
-// unrotated base in the ModDown epilogue.  Exact apart from the one shared ModDown rounding.
+// Hoisted rotation sums: base + sum_w Rot(a_w, r_w) with one ModDown.  The terms' key-switch
+// inner products (with P sigma_g(c0_w)) are accumulated in the extended basis two at a time
+// (a term waits for the next one, then both go in one launch and their lifts are freed);
+// finish adds a last unpaired term, brings the sum down once and adds the unrotated base in
+// the ModDown epilogue.  Exact apart from the one shared ModDown rounding.
 void Ctx::g_rotsum_add(RotSum& S, const Grp& a, int64_t r) {
     if (a.deg != 1) throw HeError(HE_EMISMATCH);
     if (!S.u) {
         S.B = a.B;
         S.level = a.level;
         S.n = 0;
+        S.filled = false;
         S.scale = a.scale;
         S.u = std::make_shared<DBuf>(this, (size_t)a.B * 2 * (a.level + 1 + n_p) * N);
     }
     if (a.B != S.B || a.level != S.level) throw HeError(HE_EMISMATCH);
     const u64 g = galois(r);
     if (g == 1) throw HeError(HE_EUNSUPPORTED);
-    const u64* key = rot_key(g, false);
+    rot_key(g, false);
     auto lift = g_lift(a, 1);
-    g_ks_inner(S.u->p, lift->p, a.B, a.level, key, g, a.p, a.cs, nullptr, nullptr, 1, nullptr, S.n > 0);
+    if (!S.plift) {
+        S.plift = lift;
+        S.pa = a;
+        S.pg = g;
+    } else {
+        // the waiting term and this one in one launch, each rotation gathering its own lift
+        IpSet st;
+        memset(&st, 0, sizeof st);
+        st.key = rot_key(S.pg, false);
+        st.g = S.pg;
+        st.key2 = rot_key(g, false);
+        st.g2 = g;
+        st.lift2 = lift->p;
+        st.c0_2 = a.p;
+        st.c0_2_cs = a.cs;
+        g_ks_inner_sets(S.u->p, S.plift->p, a.B, a.level, {st}, 2, S.pa.p, S.pa.cs, S.filled);
+        S.filled = true;
+        S.plift.reset();
+        S.pa = Grp();
+    }
     for (int i = 0; i < a.B; ++i) S.scale[i] = std::max(S.scale[i], a.scale[i]);
     ++S.n;
     cnt[C_ROT] += a.B;
@@ -390,6 +411,13 @@ void Ctx::g_rotsum_add(RotSum& S, const Grp& a, int64_t r) {
 Grp Ctx::g_rotsum_finish(RotSum& S, const Grp* base) {
     if (!S.u) throw HeError(HE_EUNSUPPORTED);
     if (base && (base->B != S.B || base->level != S.level || base->deg != 1)) throw HeError(HE_EMISMATCH);
+    if (S.plift) {  // a last term without a partner
+        g_ks_inner(S.u->p, S.plift->p, S.B, S.level, rot_key(S.pg, false), S.pg, S.pa.p, S.pa.cs, nullptr, nullptr,
+                   1, nullptr, S.filled);
+        S.filled = true;
+        S.plift.reset();
+        S.pa = Grp();
+    }
     std::vector<double> sc(S.scale);
     if (base)
         for (int i = 0; i < S.B; ++i) sc[i] = std::max(sc[i], base->scale[i]);

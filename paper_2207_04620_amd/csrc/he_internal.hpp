@@ -74,7 +74,13 @@ struct Grp {
 struct RotSum {
     std::shared_ptr<DBuf> u;
     int B = 0, level = -1, n = 0;
+    bool filled = false;  // u holds at least one term
     std::vector<double> scale;
+    // a term waiting for a partner: two terms share one inner-product launch, so u is read
+    // and rewritten once per pair (its lift, its ciphertext for c0, its Galois element)
+    std::shared_ptr<DBuf> plift;
+    Grp pa;
+    u64 pg = 0;
 };
 
 // resumable state of one lockstep product group

@@ -1572,13 +1572,24 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
         pm[r] = ip_key<NB>(mask ? mul_mont(pmont, mk, m.q, m.qninv) : pmont);
     }
     u64 x[NR][NB], z[NR];
+    // the second rotation may read another ciphertext's lift and c0 (a rotation-sum term)
+    const u64* lift_r[NR];
+    const u64* c0_r[NR];
+    int64_t c0cs_r[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const bool other = r && S.lift2;
+        lift_r[r] = other ? S.lift2 : D.lift;
+        c0_r[r] = other ? S.c0_2 : D.c0;
+        c0cs_r[r] = other ? S.c0_2_cs : D.c0_cs;
+    }
     auto load = [&](int c, u64(&xo)[NR][NB], u64(&zo)[NR]) {
-        const u64* lift = D.lift + c * D.lift_cs + (int64_t)t * N;
 #pragma unroll
         for (int r = 0; r < NR; r++) {
+            const u64* lift = lift_r[r] + c * D.lift_cs + (int64_t)t * N;
 #pragma unroll
             for (int j = 0; j < NB; j++) xo[r][j] = lift[(int64_t)j * D.ne * N + src[r]];
-            zo[r] = with_c0 ? D.c0[c * D.c0_cs + (int64_t)t * N + src[r]] : 0;
+            zo[r] = with_c0 ? c0_r[r][c * c0cs_r[r] + (int64_t)t * N + src[r]] : 0;
         }
     };
     u64* const ub = D.u + (int64_t)sj * D.nct * D.u_cs;
@@ -1619,11 +1630,17 @@ void launch_inner_product(const DevTables& T, const IpDesc& D, hipStream_t st) {
     if (N < TPB) throw std::runtime_error("inner product: ring smaller than a block");
     // keys (and masks) once per group; per member the lift digits and c0 once (the rotations
     // of a pair and the sets of a launch gather the same lift) and u per set
-    double masks = 0;
-    for (int j = 0; j < ns; ++j) masks += (D.s[j].mask ? 1.0 : 0.0) + (nr == 2 && D.s[j].mask2 ? 1.0 : 0.0);
+    double masks = 0, lifts = 1;
+    for (int j = 0; j < ns; ++j) {
+        masks += (D.s[j].mask ? 1.0 : 0.0) + (nr == 2 && D.s[j].mask2 ? 1.0 : 0.0);
+        if (nr == 2 && D.s[j].lift2) lifts += 1;  // another ciphertext's lift and c0
+    }
     const double words = (double)D.ne * (ns * nr * 2.0 * D.beta + masks +
-                                         D.nct * ((double)D.beta + ns * (D.accumulate ? 4.0 : 2.0))) +
-                         (D.c0 ? (double)D.nq * D.nct : 0.0);
+                                         D.nct * (lifts * D.beta + ns * (D.accumulate ? 4.0 : 2.0))) +
+                         (D.c0 ? lifts * D.nq * D.nct : 0.0);
+    for (int j = 0; j < ns; ++j)
+        if (D.s[j].lift2 && (nr != 2 || (D.c0 != nullptr) != (D.s[j].c0_2 != nullptr)))
+            throw std::runtime_error("inner product: second lift without a second rotation or c0");
     ProfScope prof_(PK_INNER, words * 8.0 * N, st);
     dim3 grid((N / TPB) * ns, D.ne);
     switch (D.beta) {

@@ -107,6 +107,11 @@ struct IpSet {
     const u64* mask;   // [M][N] Montgomery form, row = modulus index; null = no mask
     const u64* mask2;
     u64 g, g2, ginv;   // Galois elements (1 = identity)
+    // optional: the second rotation is of another ciphertext (a term of a rotation sum): its
+    // lift and c0 (same level and strides as the descriptor's lift, c0 stride c0_2_cs)
+    const u64* lift2;
+    const u64* c0_2;
+    int64_t c0_2_cs;
 };
 #define IP_MAXSET 16
 

@@ -79,11 +79,12 @@ static size_t footprint(const Ctx* c, const he_request& r, int level) {
     const size_t lift = (size_t)beta * (level + 1 + c->n_p) * c->N * 8;
     if (r.op == HE_REQ_MATMUL) {
         // Step-1 baby steps, the Step-3 baby rotations of B0 kept across blocks, temporaries,
-        // and the Step-2 mask pairs that share one ModDown (their extended-basis sums and results)
+        // the Step-2 mask pairs that share one ModDown (their extended-basis sums and results),
+        // and the lifts of A0 and B0 beside a rotation-sum term waiting for its partner
         const int bg = c->step3_baby((int)r.h);
         const size_t ext = 2 * (size_t)(level + 1 + c->n_p) * c->N * 8;  // a hoisted rotation sum
         const size_t pb = (size_t)std::max(1, c->pair_batch);
-        return (size_t)(c->bsgs((int)r.h) + (bg < (int)r.h ? bg : 0) + 10 + pb) * ct + 3 * lift + (1 + pb) * ext;
+        return (size_t)(c->bsgs((int)r.h) + (bg < (int)r.h ? bg : 0) + 11 + pb) * ct + 4 * lift + (1 + pb) * ext;
     }
     return 12 * ct + 2 * lift;
 }
