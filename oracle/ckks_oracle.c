@@ -1336,6 +1336,10 @@ static void gd_numerators(int d, int64_t *num) {
     for (int i = 0; i <= d; i++) num[i] /= 2;
 }
 
+void orc_gd_numerators(int d, int64_t *num) {
+    if (d >= 1 && d <= 7) gd_numerators(d, num);
+}
+
 /* the integer constant of x_c = RS(x * K) for the coefficient num / 2^e:
  * K = round(num / 2^e * q_l * ratio), half away from zero, where ratio = (scale x_c must
  * carry) / (scale of x); computed in double in this exact order */

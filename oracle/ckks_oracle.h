@@ -130,6 +130,8 @@ void orc_reset_counters(orc_ctx *c);
 
 /* ---- composite sign approximation (Sec. 4.2) ---- */
 orc_ct *orc_sign(orc_ctx *c, const orc_ct *x, int d, int k, int relu);
+/* numerators n_0 .. n_d of g_d's coefficients of x, x^3, ..., x^(2d+1), each over 2^(2d-1) */
+void orc_gd_numerators(int d, int64_t *num);
 /* Alg. 5: max(a, b) ~ (a + b)/2 + (a - b)/2 . g_d^(k)(a - b) */
 orc_ct *orc_appmax(orc_ctx *c, const orc_ct *a, const orc_ct *b, int d, int k);
 /* 2 x 2 max pooling of a packed h x h matrix by two AppMax levels (rotations 1 and h) */

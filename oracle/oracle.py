@@ -108,6 +108,7 @@ def _declare(L):
         "orc_appmax": (vp, [vp, vp, vp, i32, i32]),
         "orc_maxpool2": (vp, [vp, vp, i32, i32, i32]),
         "orc_fl_update": (vp, [vp, vp, P(vp), i32, dbl]),
+        "orc_gd_numerators": (None, [i32, P(i64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -176,6 +177,13 @@ def sample_uniform(seed, purpose, index, q, n):
     o = np.zeros(n, np.uint64)
     lib().orc_sample_uniform(seed, purpose, index, q, n, u64p(o))
     return o
+
+
+def gd_numerators(d: int) -> list:
+    """numerators of g_d's coefficients of x, x^3, ..., x^(2d+1), each over 2^(2d-1)"""
+    o = np.zeros(d + 1, np.int64)
+    lib().orc_gd_numerators(d, i64p(o))
+    return [int(x) for x in o]
 
 
 def mask_slots(kind: int, h: int, k: int) -> np.ndarray:

@@ -317,18 +317,30 @@ def test_matmul_batch_beyond_group_cap(he):
     p.same(res[32], om)
 
 
-@pytest.mark.parametrize("d,k,mode", [(3, 1, 0), (1, 2, 0), (2, 1, 0), (3, 1, 1)])
+# coefficients of x, x^3, x^5, ... of g_1 .. g_4 as printed in Sec. 4.2
+GD_COEF = {1: [3 / 2, -1 / 2], 2: [15 / 8, -10 / 8, 3 / 8], 3: [35 / 16, -35 / 16, 21 / 16, -5 / 16],
+           4: [315 / 128, -420 / 128, 378 / 128, -180 / 128, 35 / 128]}
+
+
+def _gdk(d, k, x):
+    """g_d^(k) in FP64 from the printed coefficients"""
+    y = np.asarray(x, np.float64).copy()
+    for _ in range(k):
+        y = sum(c * y ** (2 * i + 1) for i, c in enumerate(GD_COEF[d]))
+    return y
+
+
+@pytest.mark.parametrize("d,k,mode", [(3, 1, 0), (1, 2, 0), (2, 1, 0), (3, 1, 1), (4, 1, 0), (4, 1, 1)])
 def test_sign_parity(he, d, k, mode):
+    """g_d^(k) and ReLU on a 2^12 ring, every residue against the oracle; g_4 is the polynomial
+    of the paper's experiments (x^9 term: the powers x^2, x^4, x^8, depth 4 per composition)"""
     prm = I.small(log_n=12, n_q=8, alpha=3, q_bits=40, p_bits=50)
     p = Pair(he, prm, h_list=[])
     X = I.sign_inputs(5, 1, 16)[0].ravel()
     gx, ox = p.g.encrypt(X, nonce=9), p.o.encrypt(X, nonce=9)
     gy, oy = p.g.sign_approx(gx, d, k, mode), p.o.sign(ox, d, k, relu=bool(mode))
     p.same(gy, oy)
-    y = X.copy()
-    coef = {1: [1.5, -0.5], 2: [15 / 8, -10 / 8, 3 / 8], 3: [35 / 16, -35 / 16, 21 / 16, -5 / 16]}[d]
-    for _ in range(k):
-        y = sum(c * y ** (2 * i + 1) for i, c in enumerate(coef))
+    y = _gdk(d, k, X)
     want = (X + X * y) / 2 if mode else y
     assert np.abs(p.g.decrypt(gy, 256) - want).max() < 1e-3
 
@@ -400,40 +412,59 @@ def test_c3_rotations_and_h16_matmul_parity(he):
     assert np.abs(p.g.decrypt(gm, 256).reshape(16, 16) - A @ B).max() < 1e-6
 
 
-def test_c3_h64_batch16_fast_schedule_full_size(he):
-    """the benchmarked configuration itself: a batch of 16 h=64 products on the N=2^15
-    ring from level 13 under the fastest schedule (all four flags), through the batched
-    entry point the benchmark times.  Member 0 against the oracle on every residue; every
-    member within the FP64 bound of A B, and equal to the same product run alone."""
+@pytest.fixture(scope="module")
+def c3_oracle():
+    """one oracle context for the N=2^15 configuration, shared by the tests below so that its
+    rotation keys (cached per Galois element) are made once"""
+    return O.Ctx.from_params(I.C3)
+
+
+def _oracle_member(o, pairs, i, lvl, h, mode):
+    A, B = pairs[i]
+    return o.matmul(o.encrypt(A.ravel(), level=lvl, nonce=2 * i), o.encrypt(B.ravel(), level=lvl, nonce=2 * i + 1),
+                    h, mode).export()
+
+
+def _same_residues(gexp, oexp, what):
+    assert gexp.shape == oexp.shape, (what, gexp.shape, oexp.shape)
+    bad = np.argwhere(gexp != oexp)
+    assert bad.size == 0, f"{what}: {len(bad)} residues differ, first at {bad[:3].tolist()}"
+
+
+@pytest.mark.parametrize("schedule", [15, 0])
+def test_c3_h64_batch16_full_size(he, c3_oracle, schedule):
+    """the benchmarked configuration itself: a batch of 16 h=64 products on the N=2^15 ring
+    from level 13, through the batched entry point the benchmark times, under the headline
+    schedule (all four flags) and under Alg. 3 as printed (schedule 0: relinearisation of every
+    Step-3 product, one ModDown per rotation, every A^(k) rescaled, Step 3 unsplit).  The
+    first and the last member against the oracle in the same schedule on every residue; every
+    member within the FP64 bound of A B, and member 5 equal to the same product run alone."""
     prm = I.C3
-    g = he.Context(prm, h_list=[64], schedule=15)
+    g = he.Context(prm, h_list=[64], schedule=schedule)
     pairs = [I.matrix_pair(1000 + i, 64) for i in range(16)]
     As = [g.encrypt(A.ravel(), level=13, nonce=2 * i) for i, (A, _) in enumerate(pairs)]
     Bs = [g.encrypt(B.ravel(), level=13, nonce=2 * i + 1) for i, (_, B) in enumerate(pairs)]
-    _log("[parity] C3 h=64 batch 16, schedule 15: GPU batch")
+    _log(f"[parity] C3 h=64 batch 16, schedule {schedule}: GPU batch")
     out = g.matmul_batch(As, Bs, [64] * 16)
     for i, (A, B) in enumerate(pairs):
         err = np.abs(g.decrypt(out[i], 4096).reshape(64, 64) - A @ B).max()
         assert err < 1e-5, (i, err)
-    _log("[parity] C3 h=64: member 5 alone")
+    _log(f"[parity] C3 h=64 schedule {schedule}: member 5 alone")
     assert np.array_equal(g.export(g.matmul(As[5], Bs[5], 64)), g.export(out[5]))
-    _log("[parity] C3 h=64: oracle, member 0")
-    o = O.Ctx.from_params(prm)
-    A, B = pairs[0]
-    om = o.matmul(o.encrypt(A.ravel(), level=13, nonce=0), o.encrypt(B.ravel(), level=13, nonce=1), 64, 15)
-    gexp, oexp = g.export(out[0]), om.export()
-    assert gexp.shape == oexp.shape
-    bad = np.argwhere(gexp != oexp)
-    assert bad.size == 0, f"{len(bad)} residues differ, first at {bad[:3].tolist()}"
-    _log("[parity] C3 h=64: bit-exact")
+    for i in (0, 15):
+        _log(f"[parity] C3 h=64 schedule {schedule}: oracle, member {i}")
+        _same_residues(g.export(out[i]), _oracle_member(c3_oracle, pairs, i, 13, 64, schedule), f"member {i}")
+    _log(f"[parity] C3 h=64 schedule {schedule}: bit-exact")
     g.close()
 
 
-def test_c3_mixed_batch_parity(he):
+def test_c3_mixed_batch_parity(he, c3_oracle):
     """a batch of products of mixed h in {16, 32, 64} and starting levels in [3, 13] on the
     N=2^15 ring (the mixed-batch configuration, 24 of its members): one batched call; every
     member within the FP64 bound at its own output level, equal to the same product run
-    alone, and the first h=16 and h=32 members equal to the oracle on every residue"""
+    alone, and four members equal to the oracle on every residue: the first h=16 and h=32
+    members, the first h=64 member (level 7) and the h=64 member that starts at the lowest
+    level a product accepts (3)"""
     prm = I.C3
     g = he.Context(prm, h_list=[16, 32, 64], schedule=15)
     mix = I.batch_mix(3, 24)
@@ -450,16 +481,12 @@ def test_c3_mixed_batch_parity(he):
     for i in range(8):
         h = mix[i][0]
         assert np.array_equal(g.export(g.matmul(As[i], Bs[i], h)), g.export(out[i])), i
-    o = O.Ctx.from_params(prm)
-    for want_h in (16, 32):
-        i = next(j for j, (h, _) in enumerate(mix) if h == want_h)
+    picks = [next(j for j, (h, _) in enumerate(mix) if h == want) for want in (16, 32, 64)]
+    picks.append(next(j for j, (h, lv) in enumerate(mix) if h == 64 and lv == 3))
+    for i in picks:
         h, lv = mix[i]
         _log(f"[parity] C3 mixed batch: oracle member {i} (h={h}, level {lv})")
-        A, B = pairs[i]
-        om = o.matmul(o.encrypt(A.ravel(), level=lv, nonce=2 * i), o.encrypt(B.ravel(), level=lv, nonce=2 * i + 1),
-                      h, 15)
-        gexp, oexp = g.export(out[i]), om.export()
-        assert gexp.shape == oexp.shape and np.array_equal(gexp, oexp), i
+        _same_residues(g.export(out[i]), _oracle_member(c3_oracle, pairs, i, lv, h, 15), f"member {i}")
     g.close()
 
 
@@ -467,7 +494,8 @@ def test_c4_sign_relu_then_h32_matmul(he):
     """the sign/ReLU configuration on the N=2^16 ring (Q = 60 + 16 x 45, P = 5 x 60, dnum 3):
     a batch of ReLU(x) = (x + x g_3^(3)(x)) / 2 over 32 x 32 inputs with |x| in [2^-8, 1],
     then an h=32 product of each result with one encrypted W.  Member 0 against the oracle on
-    every residue (both stages); every member within 1e-3 of the FP64 evaluation"""
+    every residue (both stages), and so is the last member; every member within 1e-3 of the FP64
+    evaluation"""
     prm = I.C4
     count = 16
     g = he.Context(prm, h_list=[32], schedule=15)
@@ -490,13 +518,40 @@ def test_c4_sign_relu_then_h32_matmul(he):
         relu = (x + x * s) / 2
         assert np.abs(g.decrypt(ys[i], 1024).reshape(32, 32) - relu).max() < 1e-3, i
         assert np.abs(g.decrypt(ms[i], 1024).reshape(32, 32) - relu @ W).max() < 1e-3, i
-    _log("[parity] C4 oracle, member 0")
     o = O.Ctx.from_params(prm)
-    oy = o.sign(o.encrypt(X[0].ravel(), nonce=1), 3, 3, relu=True)
-    assert np.array_equal(g.export(ys[0]), oy.export())
-    om = o.matmul(oy, o.encrypt(W.ravel(), level=lvl, nonce=1000), 32, 15)
-    assert np.array_equal(g.export(ms[0]), om.export())
+    ow = o.encrypt(W.ravel(), level=lvl, nonce=1000)
+    for i in (0, count - 1):
+        _log(f"[parity] C4 oracle, member {i}")
+        oy = o.sign(o.encrypt(X[i].ravel(), nonce=i + 1), 3, 3, relu=True)
+        _same_residues(g.export(ys[i]), oy.export(), f"ReLU member {i}")
+        _same_residues(g.export(ms[i]), o.matmul(oy, ow, 32, 15).export(), f"product member {i}")
     _log("[parity] C4: bit-exact")
+    g.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_c4_g4_sign_and_relu(he, mode):
+    """g_4 (the polynomial of the paper's experiments, Sec. 4.2) at k = 1 on the N=2^16 ring:
+    a batch of 8 sign (mode 0) or ReLU (mode 1) evaluations over 32 x 32 inputs with |x| in
+    [2^-8, 1]; the first and the last member against the oracle on every residue, every member
+    within 1e-3 of the FP64 evaluation of the printed polynomial"""
+    prm = I.C4
+    count = 8
+    g = he.Context(prm, h_list=[], schedule=15)
+    X = I.sign_inputs(44, count, 32)
+    xs = [g.encrypt(X[i].ravel(), nonce=i + 1) for i in range(count)]
+    _log(f"[parity] C4 g_4 k=1 mode {mode}: GPU batch")
+    ys = g.sign_approx_batch(xs, 4, 1, mode)
+    for i in range(count):
+        x = X[i].ravel()
+        y = _gdk(4, 1, x)
+        want = (x + x * y) / 2 if mode else y
+        assert np.abs(g.decrypt(ys[i], 1024) - want).max() < 1e-3, i
+    o = O.Ctx.from_params(prm)
+    for i in (0, count - 1):
+        _log(f"[parity] C4 g_4 mode {mode}: oracle member {i}")
+        oy = o.sign(o.encrypt(X[i].ravel(), nonce=i + 1), 4, 1, relu=bool(mode))
+        _same_residues(g.export(ys[i]), oy.export(), f"member {i}")
     g.close()
 
 
@@ -569,20 +624,13 @@ def test_c3_packed_h64_beta4_full_size(he):
 
 
 # ---------------------------------------------------------------- Alg. 5 AppMax, pooling; Alg. 6
-def _gd3(v):
-    return (35 * v - 35 * v ** 3 + 21 * v ** 5 - 5 * v ** 7) / 16
-
-
-def _appmax64(a, b, k):
+def _appmax64(a, b, k, d=3):
     m = a - b
-    g = m.copy()
-    for _ in range(k):
-        g = _gd3(g)
-    return ((a + b) + m * g) / 2
+    return ((a + b) + m * _gdk(d, k, m)) / 2
 
 
 def test_appmax_maxpool_flupdate_parity(he):
-    """AppMax (Alg. 5), 2 x 2 max pooling and the aggregation step of Alg. 6 on a 2^12 ring:
+    """AppMax (Alg. 5) with g_3 and g_4, 2 x 2 max pooling and the aggregation step of Alg. 6 on a 2^12 ring:
     every result against the oracle on every residue, and within 1e-6 of the FP64 evaluation;
     batched AppMax equals single"""
     prm = I.small(log_n=12, n_q=14, alpha=2, q_bits=40, p_bits=50)
@@ -596,6 +644,11 @@ def test_appmax_maxpool_flupdate_parity(he):
         g = p.g.appmax(ga, gb, 3, k)
         p.same(g, p.o.appmax(oa, ob, 3, k))
         assert np.abs(p.g.decrypt(g, 256) - _appmax64(a, b, k)).max() < 1e-6
+    for k in (1, 2):
+        _log(f"[parity] appmax d=4 k={k}")
+        g = p.g.appmax(ga, gb, 4, k)
+        p.same(g, p.o.appmax(oa, ob, 4, k))
+        assert np.abs(p.g.decrypt(g, 256) - _appmax64(a, b, k, 4)).max() < 1e-6
     gl = p.g.encrypt(b, level=9, nonce=3)
     batch = p.g.appmax_batch([ga, gb, ga], [gb, ga, gl], 3, 1)
     for r, (x, y) in zip(batch, [(ga, gb), (gb, ga), (ga, gl)]):
