@@ -103,6 +103,16 @@ he_status he_counters(const he_ctx *ctx, int64_t out[6], int reset);
 /* device bytes held by keys + masks, and by the allocation cache */
 he_status he_memory(const he_ctx *ctx, uint64_t *keys_bytes, uint64_t *pool_bytes);
 
+/* Cap on the device bytes the context's allocation cache may hold (keys, masks, ciphertexts and
+ * temporaries alike; 0: no cap).  Setting a cap below the bytes held returns the cached blocks to
+ * the device (after the queued work is done).  An allocation beyond the cap, once the cache is
+ * trimmed, fails and the call returns HE_ENOMEM (a serving cohort fails with HE_ENOMEM and the
+ * server goes on).  Synchronizes. */
+he_status he_pool_limit(he_ctx *ctx, uint64_t bytes);
+/* bytes of the allocation cache in use now and the largest in-use figure since the last reset
+ * (reset != 0 restarts it from the current figure) */
+he_status he_pool_stats(he_ctx *ctx, uint64_t *in_use, uint64_t *peak, int reset);
+
 /* Ecd + Enc (Fig. 1 items 3 and 5): n_vals values (n_vals divides N/2) replicated to
  * N/2 slots, encoded at Delta (exact rounding, computed in 113-bit floating point),
  * encrypted with the public key at 'level' (<= L) using stream index 'nonce'. */
@@ -250,6 +260,13 @@ he_status he_fl_update(he_ctx *ctx, const he_ct *w, size_t n, const he_ct *const
  * An unknown kind name is HE_EINVAL.  The setting is process-wide. */
 he_status he_profile_enable(he_ctx *ctx, int on, const char *only);
 he_status he_profile_report(he_ctx *ctx, char *buf, size_t n);
+
+/* Error-path testing: the n-th kernel launch from now on in this process (n >= 1) fails before
+ * anything is queued, and the call that issued it returns HE_EDEVICE (a serving cohort fails
+ * with HE_EDEVICE and the server goes on).  No kernel runs for the failed launch, so the device
+ * is never at fault.  n = 0 disarms.  Every launch is also checked as it is issued: a launch the
+ * runtime rejects is HE_EDEVICE from the call that issued it. */
+he_status he_debug_fail_launch(uint64_t n);
 
 const char *he_status_string(he_status s);
 

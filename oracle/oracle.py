@@ -44,10 +44,26 @@ def build(force: bool = False) -> str:
 _lib = None
 
 
+def build_sanitized() -> str:
+    """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer (host code only),
+    for the sanitizer run of the pins; load it by setting ORACLE_LIB to the returned path in a
+    process started with the sanitizer runtimes preloaded."""
+    os.makedirs(_LIB_DIR, exist_ok=True)
+    out = os.path.join(_LIB_DIR, "libckks_oracle_san.so")
+    tmp = out + f".tmp{os.getpid()}"
+    subprocess.check_call(
+        ["gcc", "-O1", "-g", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unused-function",
+         "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+         "-o", tmp, _SRC, "-lquadmath", "-lm"]
+    )
+    os.replace(tmp, out)
+    return out
+
+
 def lib():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build())
+        _lib = C.CDLL(os.environ.get("ORACLE_LIB") or build())
         _declare(_lib)
     return _lib
 

@@ -51,9 +51,14 @@ void* Pool::alloc(size_t bytes) {
         void* p = it->second.back();
         it->second.pop_back();
         cached -= bytes;
+        peak = std::max(peak, held - cached);
         return p;
     }
     void* p = nullptr;
+    if (limit && held + bytes > limit) {
+        trim_locked();  // cached blocks of other sizes go back to the device first
+        if (held + bytes > limit) throw HeError(HE_ENOMEM);
+    }
     if (dev_alloc) {
         p = dev_alloc(bytes, user);
     } else if (hipMalloc(&p, bytes) != hipSuccess) {
@@ -66,6 +71,7 @@ void* Pool::alloc(size_t bytes) {
     }
     if (!p) throw HeError(HE_ENOMEM);
     held += bytes;
+    peak = std::max(peak, held - cached);
     return p;
 }
 void Pool::release(void* p, size_t bytes) {
@@ -1120,6 +1126,8 @@ static he_status guard(F&& f) {
         return HE_OK;
     } catch (const HeError& e) {
         return e.s;
+    } catch (const LaunchError&) {
+        return HE_EDEVICE;
     } catch (const std::bad_alloc&) {
         return HE_ENOMEM;
     } catch (...) {
@@ -1211,6 +1219,27 @@ he_status he_memory(const he_ctx* ctx, uint64_t* keys_bytes, uint64_t* pool_byte
     return HE_OK;
 }
 
+he_status he_pool_limit(he_ctx* ctx, uint64_t bytes) {
+    if (!ctx) return HE_EINVAL;
+    return guardc(ctx, [&]() {
+        // cached blocks above the new cap go back to the device once queued work is done
+        hip_check(hipStreamSynchronize(ctx->c->stream), "pool limit");
+        Pool& P = ctx->c->pool;
+        std::lock_guard<std::mutex> lk(P.m);
+        P.limit = bytes;
+        if (bytes && P.held > bytes) P.trim_locked();
+    });
+}
+he_status he_pool_stats(he_ctx* ctx, uint64_t* in_use, uint64_t* peak, int reset) {
+    if (!ctx) return HE_EINVAL;
+    Pool& P = ctx->c->pool;
+    std::lock_guard<std::mutex> lk(P.m);
+    if (in_use) *in_use = P.held - P.cached;
+    if (peak) *peak = P.peak;
+    if (reset) P.peak = P.held - P.cached;
+    return HE_OK;
+}
+
 he_status he_encode(he_ctx* ctx, const double* vals, size_t n_vals, double scale, int64_t* out) {
     if (!ctx || !vals || !out || n_vals == 0 || (size_t)(ctx->c->N / 2) % n_vals) return HE_EINVAL;
     std::lock_guard<std::recursive_mutex> lk(ctx->c->api_mu);
@@ -1287,6 +1316,16 @@ he_status he_ct_import(he_ctx* ctx, const uint64_t* buf, size_t n, uint32_t leve
     if ((int)level >= c->n_q) return HE_ELEVEL;
     const size_t tot = (size_t)(degree + 1) * (level + 1) * c->N;
     if (n < tot) return HE_EINVAL;
+    // every residue of limb i must lie in [0, q_i): the transform takes canonical words (its
+    // FP64 butterflies convert a word exactly only below 2^52), so a corrupt or foreign
+    // checkpoint is refused here instead of becoming a silently wrong ciphertext
+    for (size_t p = 0; p <= degree; ++p)
+        for (size_t i = 0; i <= level; ++i) {
+            const uint64_t q = c->mods[i];
+            const uint64_t* w = buf + (p * (level + 1) + i) * c->N;
+            for (int64_t t = 0; t < c->N; ++t)
+                if (w[t] >= q) return HE_EINVAL;
+        }
     return guardc(ctx, [&]() {
         CtPtr r = c->new_ct((int)level, (int)degree, scale);
         upload(c, r->buf->p, buf, tot * 8);
@@ -1514,6 +1553,10 @@ he_status he_fl_update(he_ctx* ctx, const he_ct* w, size_t n, const he_ct* const
 he_status he_profile_enable(he_ctx* ctx, int on, const char* only) {
     if (!ctx) return HE_EINVAL;
     return prof_enable(on != 0, only) ? HE_OK : HE_EINVAL;
+}
+he_status he_debug_fail_launch(uint64_t n) {
+    launch_inject(n);
+    return HE_OK;
 }
 he_status he_profile_report(he_ctx* ctx, char* buf, size_t n) {
     if (!ctx || !buf || n == 0) return HE_EINVAL;

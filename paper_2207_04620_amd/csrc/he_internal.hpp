@@ -32,7 +32,9 @@ enum { C_ROT = 0, C_KS = 1, C_MULPT = 2, C_MULCT = 3, C_ADD = 4, C_RS = 5 };
 struct Pool {
     std::mutex m;
     std::unordered_map<size_t, std::vector<void*>> free_;
-    size_t held = 0, cached = 0;
+    size_t held = 0, cached = 0;  // device bytes held (in use + cached), of them cached
+    size_t limit = 0;             // cap on held bytes (0: none); beyond it alloc is HE_ENOMEM
+    size_t peak = 0;              // largest in-use byte count (held - cached) since the last reset
     void* (*dev_alloc)(size_t, void*) = nullptr;
     void (*dev_free)(void*, void*) = nullptr;
     void* user = nullptr;

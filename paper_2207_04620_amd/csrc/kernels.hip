@@ -6,6 +6,7 @@
 // RNS-CKKS internals are not described by the paper and follow the published
 // constructions named at each kernel.
 #include "kernels.hpp"
+#include <atomic>
 #include <cstring>
 #include <stdexcept>
 #include <type_traits>
@@ -70,6 +71,30 @@ struct ProfScope {
         }
     }
 };
+
+// ------------------------------------------------------------------ launch checks
+static std::atomic<uint64_t> g_inject{0};  // launches until the injected failure (0: none)
+
+void launch_inject(uint64_t n) { g_inject.store(n); }
+
+void launch_gate(const char* what) {
+    (void)hipGetLastError();  // the launch's own status is read right after it
+    uint64_t n = g_inject.load();
+    while (n) {
+        if (g_inject.compare_exchange_weak(n, n - 1)) {
+            if (n == 1) throw LaunchError{hipErrorLaunchFailure, what};
+            break;
+        }
+    }
+}
+
+void launch_check(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        fprintf(stderr, "libhe: launch of %s failed: %s\n", what, hipGetErrorString(e));
+        throw LaunchError{e, what};
+    }
+}
 
 bool prof_enable(bool on, const char* only) {
     int k = -1;
@@ -1090,7 +1115,7 @@ void launch_ntt_moddown(const DevTables& T, const Jobs& J, const Epi& E, hipStre
     const double limbs = (double)J.n * J.nct, fl = fp64_limbs(T, J);
     if (T.n1_log > 0 && cols) {
         ProfScope p(PK_NTT_FWD_COLS, 16.0 * limbs * N, st, limbs * (N / 2) * T.n1_log, fl * (N / 2) * T.n1_log);
-        hipLaunchKernelGGL(k_ntt_fwd_cols, grid_cols, dim3(TPB), 0, st, T, J);
+        HE_LAUNCH(k_ntt_fwd_cols, grid_cols, dim3(TPB), 0, st, T, J);
     }
     // reads the converted limb and u, writes the output; plus the optional add and
     // accumulator operands (per ciphertext) and the mask (shared by the group)
@@ -1098,7 +1123,7 @@ void launch_ntt_moddown(const DevTables& T, const Jobs& J, const Epi& E, hipStre
     const double rows_bytes = 8.0 * N * (3 * limbs + per_ct * E.nl * J.nct + (E.mask ? E.nl : 0));
     ProfScope p(PK_NTT_FWD_ROWS, rows_bytes, st, limbs * (N / 2) * T.n2_log, fl * (N / 2) * T.n2_log);
     if (!E.on) throw std::runtime_error("ModDown row pass without its epilogue");
-    hipLaunchKernelGGL(k_ntt_fwd_rows<true>, grid_rows, dim3(TPB), 0, st, T, J, E);
+    HE_LAUNCH(k_ntt_fwd_rows<true>, grid_rows, dim3(TPB), 0, st, T, J, E);
 }
 
 void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st, const u64* scale, int scale_n,
@@ -1116,18 +1141,18 @@ void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st,
     if (!inverse) {
         if (T.n1_log > 0 && cols) {
             ProfScope p(PK_NTT_FWD_COLS, bytes, st, b1, f1);
-            hipLaunchKernelGGL(k_ntt_fwd_cols, grid_cols, dim3(TPB), 0, st, T, J);
+            HE_LAUNCH(k_ntt_fwd_cols, grid_cols, dim3(TPB), 0, st, T, J);
         }
         ProfScope p(PK_NTT_FWD_ROWS, bytes, st, b2, f2);
-        hipLaunchKernelGGL(k_ntt_fwd_rows<false>, grid_rows, dim3(TPB), 0, st, T, J, E);
+        HE_LAUNCH(k_ntt_fwd_rows<false>, grid_rows, dim3(TPB), 0, st, T, J, E);
     } else {
         {
             ProfScope p(PK_NTT_INV_ROWS, bytes, st, b2, f2);
-            hipLaunchKernelGGL(k_ntt_inv_rows, grid_rows, dim3(TPB), 0, st, T, J, scale, scale_n);
+            HE_LAUNCH(k_ntt_inv_rows, grid_rows, dim3(TPB), 0, st, T, J, scale, scale_n);
         }
         if (T.n1_log > 0) {
             ProfScope p(PK_NTT_INV_COLS, bytes, st, b1, f1);
-            hipLaunchKernelGGL(k_ntt_inv_cols, grid_cols, dim3(TPB), 0, st, T, J, scale, scale_n);
+            HE_LAUNCH(k_ntt_inv_cols, grid_cols, dim3(TPB), 0, st, T, J, scale, scale_n);
         }
     }
 }
@@ -1202,14 +1227,14 @@ void launch_baseconv(const DevTables& T, const ConvDesc& D, hipStream_t st) {
         throw std::runtime_error("base conversion operand not 16-byte aligned");
     dim3 grid(ceil_div(N, 2 * TPB), ceil_div(D.nt, BC_TG), D.npoly * D.nct);
     switch (D.ns) {
-        case 1: hipLaunchKernelGGL(k_baseconv<1>, grid, dim3(TPB), 0, st, T, D); break;
-        case 2: hipLaunchKernelGGL(k_baseconv<2>, grid, dim3(TPB), 0, st, T, D); break;
-        case 3: hipLaunchKernelGGL(k_baseconv<3>, grid, dim3(TPB), 0, st, T, D); break;
-        case 4: hipLaunchKernelGGL(k_baseconv<4>, grid, dim3(TPB), 0, st, T, D); break;
-        case 5: hipLaunchKernelGGL(k_baseconv<5>, grid, dim3(TPB), 0, st, T, D); break;
-        case 6: hipLaunchKernelGGL(k_baseconv<6>, grid, dim3(TPB), 0, st, T, D); break;
-        case 7: hipLaunchKernelGGL(k_baseconv<7>, grid, dim3(TPB), 0, st, T, D); break;
-        default: hipLaunchKernelGGL(k_baseconv<8>, grid, dim3(TPB), 0, st, T, D); break;
+        case 1: HE_LAUNCH(k_baseconv<1>, grid, dim3(TPB), 0, st, T, D); break;
+        case 2: HE_LAUNCH(k_baseconv<2>, grid, dim3(TPB), 0, st, T, D); break;
+        case 3: HE_LAUNCH(k_baseconv<3>, grid, dim3(TPB), 0, st, T, D); break;
+        case 4: HE_LAUNCH(k_baseconv<4>, grid, dim3(TPB), 0, st, T, D); break;
+        case 5: HE_LAUNCH(k_baseconv<5>, grid, dim3(TPB), 0, st, T, D); break;
+        case 6: HE_LAUNCH(k_baseconv<6>, grid, dim3(TPB), 0, st, T, D); break;
+        case 7: HE_LAUNCH(k_baseconv<7>, grid, dim3(TPB), 0, st, T, D); break;
+        default: HE_LAUNCH(k_baseconv<8>, grid, dim3(TPB), 0, st, T, D); break;
     }
 }
 
@@ -1228,14 +1253,14 @@ void launch_conv_cols(const DevTables& T, const ConvDesc& D, hipStream_t st) {
                     units * (N / 2) * T.n1_log, fpu * (N / 2) * T.n1_log);
     dim3 grid((N / NTT_E) * D.npoly * D.nct * D.nt);
     switch (D.ns) {
-        case 1: hipLaunchKernelGGL(k_conv_cols<1>, grid, dim3(TPB), 0, st, T, D); break;
-        case 2: hipLaunchKernelGGL(k_conv_cols<2>, grid, dim3(TPB), 0, st, T, D); break;
-        case 3: hipLaunchKernelGGL(k_conv_cols<3>, grid, dim3(TPB), 0, st, T, D); break;
-        case 4: hipLaunchKernelGGL(k_conv_cols<4>, grid, dim3(TPB), 0, st, T, D); break;
-        case 5: hipLaunchKernelGGL(k_conv_cols<5>, grid, dim3(TPB), 0, st, T, D); break;
-        case 6: hipLaunchKernelGGL(k_conv_cols<6>, grid, dim3(TPB), 0, st, T, D); break;
-        case 7: hipLaunchKernelGGL(k_conv_cols<7>, grid, dim3(TPB), 0, st, T, D); break;
-        default: hipLaunchKernelGGL(k_conv_cols<8>, grid, dim3(TPB), 0, st, T, D); break;
+        case 1: HE_LAUNCH(k_conv_cols<1>, grid, dim3(TPB), 0, st, T, D); break;
+        case 2: HE_LAUNCH(k_conv_cols<2>, grid, dim3(TPB), 0, st, T, D); break;
+        case 3: HE_LAUNCH(k_conv_cols<3>, grid, dim3(TPB), 0, st, T, D); break;
+        case 4: HE_LAUNCH(k_conv_cols<4>, grid, dim3(TPB), 0, st, T, D); break;
+        case 5: HE_LAUNCH(k_conv_cols<5>, grid, dim3(TPB), 0, st, T, D); break;
+        case 6: HE_LAUNCH(k_conv_cols<6>, grid, dim3(TPB), 0, st, T, D); break;
+        case 7: HE_LAUNCH(k_conv_cols<7>, grid, dim3(TPB), 0, st, T, D); break;
+        default: HE_LAUNCH(k_conv_cols<8>, grid, dim3(TPB), 0, st, T, D); break;
     }
 }
 
@@ -1321,10 +1346,10 @@ void launch_sample(const DevTables& T, const Jobs& J, const SampleArgs& A, hipSt
     const int N = 1 << T.log_n;
     if (A.kind == 2) {
         dim3 grid(ceil_div(N / 4, TPB), J.n);
-        hipLaunchKernelGGL(k_sample_uniform, grid, dim3(TPB), 0, st, T, J, A);
+        HE_LAUNCH(k_sample_uniform, grid, dim3(TPB), 0, st, T, J, A);
     } else {
         dim3 grid(ceil_div(N / 8, TPB));
-        hipLaunchKernelGGL(k_sample_small, grid, dim3(TPB), 0, st, T, J, A);
+        HE_LAUNCH(k_sample_small, grid, dim3(TPB), 0, st, T, J, A);
     }
 }
 
@@ -1357,7 +1382,7 @@ void launch_ew(const DevTables& T, ModMap mm, int nl, int npoly, u64* out, int64
     ProfScope prof_(PK_EW, 3.0 * nl * npoly * nct * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl, npoly * nct);
-    hipLaunchKernelGGL(k_ew, grid, dim3(TPB), 0, st, T, mm, npoly, out, out_ps, a, a_ps, b, b_ps, op, out_cs, a_cs,
+    HE_LAUNCH(k_ew, grid, dim3(TPB), 0, st, T, mm, npoly, out, out_ps, a, a_ps, b, b_ps, op, out_cs, a_cs,
                        b_cs);
 }
 
@@ -1376,7 +1401,7 @@ void launch_mul_const(const DevTables& T, ModMap mm, int nl, int npoly, u64* out
     ProfScope prof_(PK_EW, 2.0 * nl * npoly * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl, npoly);
-    hipLaunchKernelGGL(k_mul_const, grid, dim3(TPB), 0, st, T, mm, out, out_ps, a, a_ps, c, c_sh);
+    HE_LAUNCH(k_mul_const, grid, dim3(TPB), 0, st, T, mm, out, out_ps, a, a_ps, c, c_sh);
 }
 
 // position j of the bit-reversed evaluation layout holds a(psi^(2 brev(j) + 1)); sigma_g
@@ -1401,7 +1426,7 @@ void launch_automorph(const DevTables& T, int nl, int npoly, u64* out, int64_t o
     ProfScope prof_(PK_AUTOMORPH, 2.0 * nl * npoly * nct * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl, npoly * nct);
-    hipLaunchKernelGGL(k_automorph, grid, dim3(TPB), 0, st, T, npoly, out, out_ps, in, in_ps, g, out_cs, in_cs);
+    HE_LAUNCH(k_automorph, grid, dim3(TPB), 0, st, T, npoly, out, out_ps, in, in_ps, g, out_cs, in_cs);
 }
 
 __global__ __launch_bounds__(TPB) void k_to_mont(DevTables T, ModMap mm, u64* x, int64_t ps) {
@@ -1417,7 +1442,7 @@ void launch_to_mont(const DevTables& T, ModMap mm, int nl, int npoly, u64* x, in
     ProfScope prof_(PK_EW, 2.0 * nl * npoly * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl, npoly);
-    hipLaunchKernelGGL(k_to_mont, grid, dim3(TPB), 0, st, T, mm, x, ps);
+    HE_LAUNCH(k_to_mont, grid, dim3(TPB), 0, st, T, mm, x, ps);
 }
 
 __global__ __launch_bounds__(TPB) void k_swk_finish(DevTables T, u64* b, const u64* a, const u64* e,
@@ -1438,7 +1463,7 @@ void launch_swk_finish(const DevTables& T, int M, u64* b, const u64* a, const u6
     ProfScope prof_(PK_EW, 6.0 * M * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), M);
-    hipLaunchKernelGGL(k_swk_finish, grid, dim3(TPB), 0, st, T, b, a, e, s, sp, pmod, in_digit);
+    HE_LAUNCH(k_swk_finish, grid, dim3(TPB), 0, st, T, b, a, e, s, sp, pmod, in_digit);
 }
 
 // ------------------------------------------------------------------ key switching
@@ -1618,9 +1643,9 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
 template <int NB>
 static void launch_ip_nb(const DevTables& T, const IpDesc& D, dim3 grid, hipStream_t st) {
     if (D.nrot == 2)
-        hipLaunchKernelGGL((k_inner_product<NB, 2>), grid, dim3(TPB), 0, st, T, D);
+        HE_LAUNCH((k_inner_product<NB, 2>), grid, dim3(TPB), 0, st, T, D);
     else
-        hipLaunchKernelGGL((k_inner_product<NB, 1>), grid, dim3(TPB), 0, st, T, D);
+        HE_LAUNCH((k_inner_product<NB, 1>), grid, dim3(TPB), 0, st, T, D);
 }
 
 void launch_inner_product(const DevTables& T, const IpDesc& D, hipStream_t st) {
@@ -1682,7 +1707,7 @@ void launch_moddown_combine(const DevTables& T, int nl, int npoly, const u64* u,
     ProfScope prof_(PK_MODDOWN, (add ? 4.0 : 3.0) * nl * npoly * nct * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl, npoly * nct);
-    hipLaunchKernelGGL(k_moddown_combine, grid, dim3(TPB), 0, st, T, npoly, u, u_ps, conv, conv_ps, pinv, pinv_sh,
+    HE_LAUNCH(k_moddown_combine, grid, dim3(TPB), 0, st, T, npoly, u, u_ps, conv, conv_ps, pinv, pinv_sh,
                        add, add_ps, out, out_ps, u_cs, conv_cs, add_cs, out_cs);
 }
 
@@ -1703,7 +1728,7 @@ void launch_sum_many(const DevTables& T, int nl, int npoly, const SumDesc& D, u6
     ProfScope prof_(PK_EW, (D.n + 1.0 + accumulate) * nl * npoly * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl, npoly);
-    hipLaunchKernelGGL(k_sum_many, grid, dim3(TPB), 0, st, T, D, out, out_ps, accumulate);
+    HE_LAUNCH(k_sum_many, grid, dim3(TPB), 0, st, T, D, out, out_ps, accumulate);
 }
 
 // ------------------------------------------------------------------ rescale
@@ -1724,7 +1749,7 @@ void launch_rescale_spread(const DevTables& T, int nl_out, int npoly, const u64*
     ProfScope prof_(PK_RS_SPREAD, (1.0 + nl_out) * npoly * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl_out, npoly);
-    hipLaunchKernelGGL(k_rescale_spread, grid, dim3(TPB), 0, st, T, last, last_ps, last_mod, tmp, tmp_ps);
+    HE_LAUNCH(k_rescale_spread, grid, dim3(TPB), 0, st, T, last, last_ps, last_mod, tmp, tmp_ps);
 }
 
 __global__ __launch_bounds__(TPB) void k_rescale_combine(DevTables T, int npoly, const u64* c, int64_t c_ps,
@@ -1746,7 +1771,7 @@ void launch_rescale_combine(const DevTables& T, int nl_out, int npoly, const u64
     ProfScope prof_(PK_RS_COMBINE, 3.0 * nl_out * npoly * nct * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl_out, npoly * nct);
-    hipLaunchKernelGGL(k_rescale_combine, grid, dim3(TPB), 0, st, T, npoly, c, c_ps, tmp, tmp_ps, qinv, qinv_sh, out,
+    HE_LAUNCH(k_rescale_combine, grid, dim3(TPB), 0, st, T, npoly, c, c_ps, tmp, tmp_ps, qinv, qinv_sh, out,
                        out_ps, c_cs, tmp_cs, out_cs);
 }
 
@@ -1786,7 +1811,7 @@ void launch_tensor(const DevTables& T, int nl, const u64* a, int64_t a_ps, const
     ProfScope prof_(PK_TENSOR, (acc ? 10.0 : 7.0) * nl * nct * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl, nct);
-    hipLaunchKernelGGL(k_tensor, grid, dim3(TPB), 0, st, T, a, a_ps, b, b_ps, d, d_ps, acc, a_cs, b_cs, d_cs);
+    HE_LAUNCH(k_tensor, grid, dim3(TPB), 0, st, T, a, a_ps, b, b_ps, d, d_ps, acc, a_cs, b_cs, d_cs);
 }
 
 // Step-3 block: d = sum_j a_j (x) b_j (d0 = sum a0 b0, d1 = sum a0 b1 + a1 b0, d2 = sum a1 b1),
@@ -1829,7 +1854,7 @@ void launch_tensor_sum(const DevTables& T, int nl, const TensorSumDesc& D, hipSt
     ProfScope prof_(PK_TENSOR, (4.0 * D.n + 3.0 * (1 + D.acc)) * nl * D.nct * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl, D.nct);
-    hipLaunchKernelGGL(k_tensor_sum, grid, dim3(TPB), 0, st, T, D);
+    HE_LAUNCH(k_tensor_sum, grid, dim3(TPB), 0, st, T, D);
 }
 
 // sum of up to 16 (ciphertext limb x mask) products, one REDC per output
@@ -1859,7 +1884,7 @@ void launch_mask_mac(const DevTables& T, int nl, int npoly, const MacDesc& D, u6
     ProfScope prof_(PK_MASKMAC, (D.nterm + D.nct * npoly * (D.nterm + 1.0 + acc)) * nl * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl, npoly);
-    hipLaunchKernelGGL(k_mask_mac, grid, dim3(TPB), 0, st, T, D, out, out_ps, acc, out_cs);
+    HE_LAUNCH(k_mask_mac, grid, dim3(TPB), 0, st, T, D, out, out_ps, acc, out_cs);
 }
 
 // Up to MM_OUT diagonal sums of one BSGS linear transform at once: each thread keeps the masks
@@ -1923,11 +1948,11 @@ void launch_mask_mac_multi(const DevTables& T, int nl, int npoly, const MultiMac
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl, npoly);
     switch (D.nin) {
-        case 1: hipLaunchKernelGGL(k_mask_mac_multi<1>, grid, dim3(TPB), 0, st, T, D); break;
-        case 2: hipLaunchKernelGGL(k_mask_mac_multi<2>, grid, dim3(TPB), 0, st, T, D); break;
-        case 4: hipLaunchKernelGGL(k_mask_mac_multi<4>, grid, dim3(TPB), 0, st, T, D); break;
-        case 8: hipLaunchKernelGGL(k_mask_mac_multi<8>, grid, dim3(TPB), 0, st, T, D); break;
-        default: hipLaunchKernelGGL(k_mask_mac_multi<16>, grid, dim3(TPB), 0, st, T, D); break;
+        case 1: HE_LAUNCH(k_mask_mac_multi<1>, grid, dim3(TPB), 0, st, T, D); break;
+        case 2: HE_LAUNCH(k_mask_mac_multi<2>, grid, dim3(TPB), 0, st, T, D); break;
+        case 4: HE_LAUNCH(k_mask_mac_multi<4>, grid, dim3(TPB), 0, st, T, D); break;
+        case 8: HE_LAUNCH(k_mask_mac_multi<8>, grid, dim3(TPB), 0, st, T, D); break;
+        default: HE_LAUNCH(k_mask_mac_multi<16>, grid, dim3(TPB), 0, st, T, D); break;
     }
 }
 
@@ -1949,7 +1974,7 @@ void launch_dec_dot(const DevTables& T, int nl, int deg, const u64* c, int64_t c
     ProfScope prof_(PK_EW, (2.0 + 2.0 * deg) * nl * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl);
-    hipLaunchKernelGGL(k_dec_dot, grid, dim3(TPB), 0, st, T, deg, c, c_ps, s, s2, m);
+    HE_LAUNCH(k_dec_dot, grid, dim3(TPB), 0, st, T, deg, c, c_ps, s, s2, m);
 }
 
 __global__ __launch_bounds__(TPB) void k_enc_combine(DevTables T, const u64* v, const u64* pk0, const u64* pk1,
@@ -1968,7 +1993,7 @@ void launch_enc_combine(const DevTables& T, int nl, const u64* v, const u64* pk0
     ProfScope prof_(PK_EW, 7.0 * nl * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl);
-    hipLaunchKernelGGL(k_enc_combine, grid, dim3(TPB), 0, st, T, v, pk0, pk1, x0, x1, c0, c1);
+    HE_LAUNCH(k_enc_combine, grid, dim3(TPB), 0, st, T, v, pk0, pk1, x0, x1, c0, c1);
 }
 
 __global__ __launch_bounds__(TPB) void k_add_signed(DevTables T, u64* x, const int64_t* msg) {
@@ -1985,5 +2010,5 @@ void launch_add_signed(const DevTables& T, int nl, u64* x, const int64_t* m, hip
     ProfScope prof_(PK_EW, 3.0 * nl * 8.0 * (1 << T.log_n), st);
     const int N = 1 << T.log_n;
     dim3 grid(ceil_div(N, TPB), nl);
-    hipLaunchKernelGGL(k_add_signed, grid, dim3(TPB), 0, st, T, x, m);
+    HE_LAUNCH(k_add_signed, grid, dim3(TPB), 0, st, T, x, m);
 }

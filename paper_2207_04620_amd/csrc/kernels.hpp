@@ -208,6 +208,27 @@ enum ProfKind {
 };
 #include <string>
 // only: null for every kernel kind, else one kind's name; false for an unknown name
+// Launch discipline: every kernel launch goes through HE_LAUNCH.  launch_gate() clears the
+// thread's last HIP error and, while a host-side failure injection is armed
+// (launch_inject), fails the launch before anything is queued, so tests of the error paths
+// never run a faulty kernel.  launch_check() reads the launch status at once, so a launch
+// that fails is reported by the call that issued it, not at a later synchronisation.  Both
+// throw LaunchError, which every C-ABI entry point returns as HE_EDEVICE.
+struct LaunchError {
+    hipError_t e;
+    const char* what;
+};
+void launch_gate(const char* what);
+void launch_check(const char* what);
+// fail the n-th launch from now on in this process (n >= 1); n = 0 disarms
+void launch_inject(uint64_t n);
+#define HE_LAUNCH(kernel, ...)                     \
+    do {                                           \
+        launch_gate(#kernel);                      \
+        hipLaunchKernelGGL(kernel, __VA_ARGS__);   \
+        launch_check(#kernel);                     \
+    } while (0)
+
 bool prof_enable(bool on, const char* only);
 std::string prof_report();  // JSON: per kernel kind {launches, ms, bytes}; clears the records
 

@@ -192,6 +192,8 @@ static void serve_loop(he_server* S) {
                     if (done) finished.push_back({i, HE_OK});
                 } catch (const HeError& e) {
                     finished.push_back({i, e.s});
+                } catch (const LaunchError&) {
+                    finished.push_back({i, HE_EDEVICE});
                 } catch (...) {
                     finished.push_back({i, HE_EDEVICE});
                 }

@@ -119,6 +119,9 @@ SIGNATURES = {
     "he_profile_enable": (C.c_int, [C.c_void_p, C.c_int, C.c_char_p]),
     "he_profile_report": (C.c_int, [C.c_void_p, C.c_char_p, C.c_size_t]),
     "he_status_string": (C.c_char_p, [C.c_int]),
+    "he_debug_fail_launch": (C.c_int, [C.c_uint64]),
+    "he_pool_limit": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "he_pool_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.c_int]),
 }
 
 
@@ -247,6 +250,15 @@ class Context:
         o = np.zeros(6, np.int64)
         _chk(lib().he_counters(self.ptr, _i64p(o), int(reset)), "he_counters")
         return dict(zip(["rot", "keyswitch", "mul_pt", "mul_ct", "add", "rescale"], (int(x) for x in o)))
+
+    def pool_limit(self, nbytes: int):
+        _chk(lib().he_pool_limit(self.ptr, int(nbytes)), "he_pool_limit")
+
+    def pool_stats(self, reset=False):
+        """(bytes in use, peak bytes in use since the last reset)"""
+        a, b = C.c_uint64(), C.c_uint64()
+        _chk(lib().he_pool_stats(self.ptr, C.byref(a), C.byref(b), int(reset)), "he_pool_stats")
+        return a.value, b.value
 
     def memory(self):
         k, p = C.c_uint64(), C.c_uint64()
@@ -418,6 +430,12 @@ class Context:
         n_limbs = dev_tensor.shape[0]
         mi = (C.c_uint32 * n_limbs)(*[int(x) for x in mod_idx])
         _chk(lib().he_ntt(self.ptr, C.c_void_p(dev_tensor.data_ptr()), n_limbs, mi, int(inverse)), "he_ntt")
+
+
+def fail_launch(n: int):
+    """error-path testing: the n-th kernel launch from now on fails before it is queued (the
+    call that issued it returns HE_EDEVICE); 0 disarms"""
+    _chk(lib().he_debug_fail_launch(int(n)), "he_debug_fail_launch")
 
 
 def sign_depth(d: int, k: int, mode: int = SIGN) -> int:
