@@ -66,41 +66,106 @@ SCHEDULE_TEXT = {0: "relinearise every Step-3 product (Alg. 3 as printed)",
                      "Step 3 split into 16 baby x 4 giant steps"}
 
 
+def host_cpu():
+    """the host's CPU model and core counts (lscpu), and the threads this process may use"""
+    import subprocess
+    info = {"model": None, "sockets": None, "cores_per_socket": None, "threads_per_core": None}
+    try:
+        out = subprocess.check_output(["lscpu"], text=True, env=dict(os.environ, LC_ALL="C"))
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            v = v.strip()
+            if k == "Model name":
+                info["model"] = v
+            elif k == "Socket(s)":
+                info["sockets"] = int(v)
+            elif k == "Core(s) per socket":
+                info["cores_per_socket"] = int(v)
+            elif k == "Thread(s) per core":
+                info["threads_per_core"] = int(v)
+    except (OSError, ValueError, subprocess.CalledProcessError):
+        pass
+    phys = info["sockets"] * info["cores_per_socket"] if info["sockets"] and info["cores_per_socket"] else None
+    return {"cpu_model": info["model"], "physical_cores": phys, "nproc": os.cpu_count(),
+            "usable_threads": len(os.sched_getaffinity(0))}
+
+
+def _median3(fn):
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[1]
+
+
 def cpu_baseline(prm, flags):
-    """The oracle (plain scalar C, OpenMP over limbs) on the host: h=16 products on the same
-    N=2^15 ring and chain under the same schedule flags, repeated for about 10 s, extrapolated
-    to h=64 by the key-switch + Mul_pt count."""
+    """The oracle (plain scalar C, OpenMP over limbs) on the host, at one thread and at every
+    usable thread.  Bounded sample of the h=64 product itself: each operation the product
+    performs, timed on the N=2^15 ring at the level where the product spends its work (level
+    12: Steps 2-3 after Step 1's rescale), median of three runs; the product's time is the
+    sum of these times weighted by the operation counts of one h=64 product under the same
+    schedule (counted exactly by running the oracle's product on a 2^13 ring, where the
+    counts are the same).  A directly timed h=16 product at every thread checks the model."""
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as O
     from paper_2207_04620_amd import inputs as I
 
-    threads = os.cpu_count() or 1
-    o = O.Ctx.from_params(prm, threads=threads)
+    host = host_cpu()
+    nthr = host["usable_threads"]
+
+    def counts(h):
+        c = O.Ctx(13, [50, 40, 40, 40, 40], [50, 50], 2, 40.0, 7, threads=nthr)
+        A, B = I.matrix_pair(3, h)
+        a, b = c.encrypt(A.ravel(), nonce=1), c.encrypt(B.ravel(), nonce=2)
+        c.reset_counters()
+        c.matmul(a, b, h, flags)
+        return c.counters()
+
+    cnt64, cnt16 = counts(64), counts(16)
+
+    def op_times(threads):
+        o = O.Ctx.from_params(prm, threads=threads)
+        A, B = I.matrix_pair(5, 64)
+        lvl = prm.max_level - 1
+        a, b = o.encrypt(A.ravel(), level=lvl, nonce=1), o.encrypt(B.ravel(), level=lvl, nonce=2)
+        pt = o.encode(np.ones(8))[0]
+        o.rotate(a, 1)  # the key (not timed)
+        t = o.tensor(a, b)
+        o.relin(t)      # the relinearisation key is made with the context
+        return {"rot": _median3(lambda: o.rotate(a, 1)),
+                "relin": _median3(lambda: o.relin(t)),
+                "mul_pt": _median3(lambda: o.mul_plain(a, pt, o.scale)),
+                "mul_ct": _median3(lambda: o.tensor(a, b)),
+                "add": _median3(lambda: o.add(a, b)),
+                "rescale": _median3(lambda: o.rescale(a))}
+
+    def model(cnt, t):
+        relins = cnt["keyswitch"] - cnt["rot"] if cnt["keyswitch"] >= cnt["rot"] else cnt["mul_ct"]
+        return (cnt["rot"] * t["rot"] + max(0, relins) * t["relin"] + cnt["mul_pt"] * t["mul_pt"] +
+                cnt["mul_ct"] * t["mul_ct"] + cnt["add"] * t["add"] + cnt["rescale"] * t["rescale"])
+
+    t_all = op_times(nthr)
+    t_one = op_times(1)
+    est_all, est_one = model(cnt64, t_all), model(cnt64, t_one)
+    # check: one h=16 product timed directly at every thread against the model's h=16 figure
+    o = O.Ctx.from_params(prm, threads=nthr)
     A, B = I.matrix_pair(3, 16)
     a, b = o.encrypt(A.ravel(), nonce=1), o.encrypt(B.ravel(), nonce=2)
     o.matmul(a, b, 16, flags)  # keys and masks for h=16 (not timed)
-    o.reset_counters()
-    reps, t0 = 0, time.perf_counter()
-    while True:  # a bounded sample of about 10 s
-        o.matmul(a, b, 16, flags)
-        reps += 1
-        if time.perf_counter() - t0 > 10.0:
-            break
-    dt = (time.perf_counter() - t0) / reps
-    c = o.counters()
-    work16 = (c["keyswitch"] + c["mul_pt"]) / reps
-    # key switches + Mul_pt of one h=64 product: 225 rotations (180 with the Step-3 split:
-    # 15 + 3 instead of 63 on the B side), 64 relinearisations (1 under relin-once, 4 with
-    # both flags), 127 + 64 + 127 masks
-    bsgs3 = bool(flags & 8)
-    rots = 225 - 63 + 18 if bsgs3 else 225
-    relins = (4 if bsgs3 else 1) if flags & 1 else 64
-    work64 = rots + relins + (127 + 64 + 127)
-    t64 = dt * work64 / work16
-    return {"value": 1.0 / t64, "unit": "HE-matmuls/s", "cores": threads, "kind": "oracle",
-            "sample": f"{reps} h=16 products at N=2^15 from level 13 under the same schedule ({dt:.2f} s each, "
-                      f"{c['keyswitch'] // reps} key switches, {c['mul_pt'] // reps} Mul_pt), extrapolated to h=64 by "
-                      f"the op-count ratio {work64}/{work16:.0f}"}
+    t0 = time.perf_counter()
+    o.matmul(a, b, 16, flags)
+    direct16 = time.perf_counter() - t0
+    return {"value": round(1.0 / est_all, 5), "unit": "HE-matmuls/s", "cores": nthr, "kind": "oracle",
+            "value_1_thread": round(1.0 / est_one, 6), **host,
+            "sample": "each operation of the h=64 product timed on the N=2^15 ring at level 12 (median of 3, at "
+                      f"{nthr} threads and at 1 thread), weighted by the product's operation counts under the same "
+                      f"schedule ({cnt64['rot']} rotations, {cnt64['keyswitch']} key switches, {cnt64['mul_pt']} "
+                      f"Mul_pt, {cnt64['mul_ct']} Mul_ct, {cnt64['rescale']} rescales)",
+            "op_seconds_all_threads": {k: round(v, 4) for k, v in t_all.items()},
+            "op_seconds_1_thread": {k: round(v, 4) for k, v in t_one.items()},
+            "h64_seconds_all_threads": round(est_all, 2), "h64_seconds_1_thread": round(est_one, 2),
+            "check_h16": {"direct_seconds": round(direct16, 2), "model_seconds": round(model(cnt16, t_all), 2)}}
 
 
 def mixed_leg(he, I, prm, sched, stream, count):

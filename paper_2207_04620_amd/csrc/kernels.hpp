@@ -207,7 +207,6 @@ enum ProfKind {
     PK_RS_SPREAD, PK_RS_COMBINE, PK_TENSOR, PK_MASKMAC, PK_AUTOMORPH, PK_EW, PK_CONV_COLS, PK_COUNT
 };
 #include <string>
-// only: null for every kernel kind, else one kind's name; false for an unknown name
 // Launch discipline: every kernel launch goes through HE_LAUNCH.  launch_gate() clears the
 // thread's last HIP error and, while a host-side failure injection is armed
 // (launch_inject), fails the launch before anything is queued, so tests of the error paths
@@ -229,6 +228,7 @@ void launch_inject(uint64_t n);
         launch_check(#kernel);                     \
     } while (0)
 
+// only: null for every kernel kind, else one kind's name; false for an unknown name
 bool prof_enable(bool on, const char* only);
 std::string prof_report();  // JSON: per kernel kind {launches, ms, bytes}; clears the records
 

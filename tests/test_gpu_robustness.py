@@ -78,20 +78,37 @@ def test_import_rejects_residues_out_of_range(H, ctx):
     assert _code(H, ctx.import_, bad, lv, sc, dg) == EINVAL
 
 
+def _launches(ctx, fn):
+    """kernel launches one call makes (from the launch-timing records)"""
+    ctx.profile(True)
+    try:
+        fn()
+        rep = ctx.profile_report()
+    finally:
+        ctx.profile(False)
+    return sum(v["launches"] for v in rep.values())
+
+
 def test_injected_launch_failure_fails_only_that_call(H, ctx):
     A, B = I.matrix_pair(4, 8)
     a, b = ctx.encrypt(A.ravel(), nonce=4), ctx.encrypt(B.ravel(), nonce=5)
     want = ctx.export(ctx.matmul(a, b, 8))
-    for n in (1, 40, 400):
-        _log(f"[robust] launch {n} of a product fails")
-        H.fail_launch(n)
-        assert _code(H, ctx.matmul, a, b, 8) == EDEVICE
+    n_prod = _launches(ctx, lambda: ctx.matmul(a, b, 8))
+    n_batch = _launches(ctx, lambda: ctx.matmul_batch([a, a], [b, b], [8, 8]))
+    _log(f"[robust] a product makes {n_prod} launches, a batch of two {n_batch}")
+    assert n_prod > 10 and n_batch > 10
+    try:
+        for n in (1, n_prod // 2, n_prod):  # the first, a middle and the last launch
+            _log(f"[robust] launch {n} of a product fails")
+            H.fail_launch(n)
+            assert _code(H, ctx.matmul, a, b, 8) == EDEVICE
+            H.fail_launch(0)
+            assert np.array_equal(ctx.export(ctx.matmul(a, b, 8)), want)
+        _log(f"[robust] a batch whose launch {n_batch // 2} fails, then the same batch")
+        H.fail_launch(n_batch // 2)
+        assert _code(H, ctx.matmul_batch, [a, a], [b, b], [8, 8]) == EDEVICE
+    finally:
         H.fail_launch(0)
-        assert np.array_equal(ctx.export(ctx.matmul(a, b, 8)), want)
-    _log("[robust] a batch whose 100th launch fails, then the same batch")
-    H.fail_launch(100)
-    assert _code(H, ctx.matmul_batch, [a, a], [b, b], [8, 8]) == EDEVICE
-    H.fail_launch(0)
     for r in ctx.matmul_batch([a, a], [b, b], [8, 8]):
         assert np.array_equal(ctx.export(r), want)
 
