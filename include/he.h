@@ -151,6 +151,22 @@ he_status he_rescale(he_ctx *ctx, const he_ct *a, he_ct **out);
 he_status he_rotate(he_ctx *ctx, const he_ct *a, int64_t k, he_ct **out);
 /* rotation key for amount k (made on demand; no-op when it exists) */
 he_status he_gen_rotation_key(he_ctx *ctx, int64_t k);
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops
+ * and harnesses that forbid allocation): Rot(a, k) as he_rotate computes it, bit for bit, on
+ * caller memory.  in: device address of the two polynomials of a ciphertext at 'level',
+ * u64[2][level+1][N], every limb in the evaluation domain of he_ntt (forward, limb i modulo
+ * prime i); out: device address of the result in the same layout, not overlapping in.  The
+ * call allocates nothing: its temporaries live in a static device scratch of 64 MiB, one copy
+ * per device, held until the process ends, and shared by every call on that device, so calls
+ * on one device that overlap in time (other contexts, other streams) race; calls on one
+ * stream are ordered.  Sizes are bounded by the scratch: (beta (level + 1 + K) + 2 (level + 1
+ * + K) + 2 (level + 1)) N words must fit (beta the digits at that level, K the special
+ * primes), else HE_ENOMEM with a message on stderr (every level of an N = 2^15, 14 + 4 limb
+ * ring fits).  The key for 5^k mod 2N must exist (HE_EKEY; he_gen_rotation_key makes it,
+ * allocating).  HE_ELEVEL for a level above the top, HE_EINVAL for null or overlapping
+ * buffers, HE_EMISMATCH when the current device is not the context's.  Asynchronous on the
+ * context stream. */
+he_status he_rotate_noalloc(he_ctx *ctx, const uint64_t *in, uint32_t level, int64_t k, uint64_t *out);
 
 /* HE-MatMult (Alg. 3 with the baby-step/giant-step Steps 1-1/1-2 of App. B): A and B
  * encrypt row-major h x h matrices (Sec. 3.4) replicated over the slots; the result

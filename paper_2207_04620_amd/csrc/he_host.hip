@@ -668,14 +668,22 @@ CtPtr Ctx::tensor(const CtData& a, const CtData& b) {
 // Digits of d (evaluation form, limbs 0..level) lifted to Q_l and P: [beta][ne][N]
 std::unique_ptr<DBuf> Ctx::ks_lift(const u64* d, int level) {
     const int nl = level + 1, ne = nl + n_p;
-    const auto& infos = mu[level];
-    const int beta = (int)infos.size();
+    const int beta = (int)mu[level].size();
     auto lift = std::make_unique<DBuf>(this, (size_t)beta * ne * N);
     DBuf coef(this, (size_t)nl * N);
-    hip_check(hipMemcpyAsync(coef.p, d, (size_t)nl * N * 8, hipMemcpyDeviceToDevice, stream), "lift copy");
-    ntt(coef.p, 1, 0, nl, true, -1);
+    ks_lift_into(d, level, lift->p, coef.p);
+    return lift;
+}
+
+// the same into caller buffers: lift [beta][ne][N], coef [nl][N] (the digits' coefficient form)
+void Ctx::ks_lift_into(const u64* d, int level, u64* lift, u64* coef) {
+    const int nl = level + 1, ne = nl + n_p;
+    const auto& infos = mu[level];
+    const int beta = (int)infos.size();
+    hip_check(hipMemcpyAsync(coef, d, (size_t)nl * N * 8, hipMemcpyDeviceToDevice, stream), "lift copy");
+    ntt(coef, 1, 0, nl, true, -1);
     Jobs J;
-    J.base = lift->p;
+    J.base = lift;
     J.cstride = 0;
     J.nct = 1;
     J.n = 0;
@@ -684,9 +692,9 @@ std::unique_ptr<DBuf> Ctx::ks_lift(const u64* d, int level) {
         ConvDesc D;
         memset(&D, 0, sizeof D);
         D.nct = 1;
-        D.src = coef.p + (size_t)inf.lo * N;
+        D.src = coef + (size_t)inf.lo * N;
         D.src_pstride = 0;
-        D.dst = lift->p + (size_t)j * ne * N;
+        D.dst = lift + (size_t)j * ne * N;
         D.dst_pstride = 0;
         D.tab = d_mu_tab->p + inf.off;
         D.ns = inf.hi - inf.lo;
@@ -713,24 +721,31 @@ std::unique_ptr<DBuf> Ctx::ks_lift(const u64* d, int level) {
         }
         launch_baseconv(T, D, stream);
         // the digit's own limbs are d itself
-        hip_check(hipMemcpyAsync(lift->p + ((size_t)j * ne + inf.lo) * N, d + (size_t)inf.lo * N,
+        hip_check(hipMemcpyAsync(lift + ((size_t)j * ne + inf.lo) * N, d + (size_t)inf.lo * N,
                                  (size_t)(inf.hi - inf.lo) * N * 8, hipMemcpyDeviceToDevice, stream),
                   "lift digit");
     }
     launch_ntt(T, J, false, stream);
-    return lift;
 }
 
 // (out0, out1) = ModDown(<lift permuted by g, key>) (+ add0, add1); out pointers [nl][N]
 void Ctx::ks_apply(const u64* lift, int level, const u64* key, u64 g, const u64* add0, const u64* add1, u64* out0,
                    u64* out1) {
     const int nl = level + 1, ne = nl + n_p;
-    const int beta = (int)mu[level].size();
     DBuf u(this, 2 * (size_t)ne * N);
+    DBuf conv(this, 2 * (size_t)nl * N);
+    ks_apply_into(lift, level, key, g, add0, add1, out0, out1, u.p, conv.p);
+}
+
+// the same with caller buffers: u [2][ne][N] (the inner product over Q_l and P), conv [2][nl][N]
+void Ctx::ks_apply_into(const u64* lift, int level, const u64* key, u64 g, const u64* add0, const u64* add1,
+                        u64* out0, u64* out1, u64* u, u64* conv) {
+    const int nl = level + 1, ne = nl + n_p;
+    const int beta = (int)mu[level].size();
     IpDesc D;
     memset(&D, 0, sizeof D);
     D.lift = lift;
-    D.u = u.p;
+    D.u = u;
     D.ne = ne;
     D.beta = beta;
     D.M = n_q + n_p;
@@ -745,7 +760,7 @@ void Ctx::ks_apply(const u64* lift, int level, const u64* key, u64 g, const u64*
     launch_inner_product(T, D, stream);
     // ModDown
     Jobs J;
-    J.base = u.p;
+    J.base = u;
     J.cstride = 0;
     J.nct = 1;
     J.n = 0;
@@ -756,13 +771,12 @@ void Ctx::ks_apply(const u64* lift, int level, const u64* key, u64 g, const u64*
             ++J.n;
         }
     launch_ntt(T, J, true, stream);
-    DBuf conv(this, 2 * (size_t)nl * N);
     ConvDesc C;
     memset(&C, 0, sizeof C);
     C.nct = 1;
-    C.src = u.p + (size_t)nl * N;
+    C.src = u + (size_t)nl * N;
     C.src_pstride = (int64_t)ne * N;
-    C.dst = conv.p;
+    C.dst = conv;
     C.dst_pstride = (int64_t)nl * N;
     C.tab = d_md_tab->p;
     C.tab_ld = n_q;
@@ -780,10 +794,10 @@ void Ctx::ks_apply(const u64* lift, int level, const u64* key, u64 g, const u64*
         C.tcol[t] = (uint16_t)t;
     }
     launch_baseconv(T, C, stream);
-    ntt(conv.p, 2, nl, nl, false, -1);
+    ntt(conv, 2, nl, nl, false, -1);
     const u64* pinv = d_pinv->p;
-    launch_moddown_combine(T, nl, 1, u.p, 0, conv.p, 0, pinv, pinv + n_q, add0, 0, out0, 0, stream);
-    launch_moddown_combine(T, nl, 1, u.p + (size_t)ne * N, 0, conv.p + (size_t)nl * N, 0, pinv, pinv + n_q, add1, 0,
+    launch_moddown_combine(T, nl, 1, u, 0, conv, 0, pinv, pinv + n_q, add0, 0, out0, 0, stream);
+    launch_moddown_combine(T, nl, 1, u + (size_t)ne * N, 0, conv + (size_t)nl * N, 0, pinv, pinv + n_q, add1, 0,
                            out1, 0, stream);
     cnt[C_KS]++;
 }
@@ -1139,6 +1153,32 @@ he_ct* wrap(Ctx* c, CtPtr p) { return new he_ct{c, std::move(p)}; }
 
 extern "C" {
 
+// ====================================================================== allocation-free rotation
+// Scratch of he_rotate_noalloc: file-scope device memory, one copy on every device the library
+// runs on, held until the process ends.  Host code never passes the array's name to a kernel or
+// a copy (on the host it only names the symbol); it uses the device address taken once per
+// device by hipGetSymbolAddress with that device current.
+#define HE_SCRATCH_BYTES (64ull << 20)
+#define HE_MAX_DEVICES 64
+static __device__ __align__(256) u64 scratch[HE_SCRATCH_BYTES / 8];
+static std::mutex g_scratch_mu;
+static u64* g_scratch_dev[HE_MAX_DEVICES];
+
+// the current device's scratch address (taken on the first call for that device)
+static u64* scratch_of_current_device(int* dev_out) {
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "scratch device");
+    if (dev < 0 || dev >= HE_MAX_DEVICES) throw HeError(HE_EUNSUPPORTED);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch address");
+        g_scratch_dev[dev] = (u64*)p;
+    }
+    *dev_out = dev;
+    return g_scratch_dev[dev];
+}
+
 he_status he_ctx_create(const he_params* prm, const he_device* dev, he_ctx** out) {
     if (!prm || !out || !prm->q_bits || (prm->n_p && !prm->p_bits)) return HE_EINVAL;
     return guard([&]() {
@@ -1147,6 +1187,7 @@ he_status he_ctx_create(const he_params* prm, const he_device* dev, he_ctx** out
             (prm->n_q + prm->alpha - 1) / prm->alpha > HE_MAXSRC || (prm->schedule & ~HE_SCHED_ALL))
             throw HeError(HE_EINVAL);
         auto c = std::make_unique<Ctx>();
+        c->scratch = scratch_of_current_device(&c->device);
         c->log_n = (int)prm->log_n;
         c->N = (int64_t)1 << prm->log_n;
         c->n_q = (int)prm->n_q;
@@ -1389,6 +1430,43 @@ he_status he_rescale(he_ctx* ctx, const he_ct* a, he_ct** out) {
 he_status he_rotate(he_ctx* ctx, const he_ct* a, int64_t k, he_ct** out) {
     CHECK1(a);
     return guardc(ctx, [&]() { *out = wrap(ctx->c.get(), ctx->c->rotate(*a->c, k)); });
+}
+
+// Rot(a, k) with every temporary in the static scratch: the digit lift [beta][ne][N], the
+// inner product over Q_l and P [2][ne][N], and one region shared by the digits' coefficient
+// form (used while lifting) and the converted P part (used by ModDown afterwards) [2][nl][N].
+// Every scratch word a call reads was written earlier in that call, so nothing is cleared.
+he_status he_rotate_noalloc(he_ctx* ctx, const uint64_t* in, uint32_t level, int64_t k, uint64_t* out) {
+    if (!ctx || !in || !out) return HE_EINVAL;
+    Ctx* c = ctx->c.get();
+    if ((int)level >= c->n_q) return HE_ELEVEL;
+    const int nl = (int)level + 1, ne = nl + c->n_p;
+    const int64_t N = c->N;
+    const size_t ct_words = 2 * (size_t)nl * N;
+    if (in < out + ct_words && out < in + ct_words) return HE_EINVAL;  // in and out overlap
+    const int beta = (int)c->mu[level].size();
+    const size_t lift_w = (size_t)beta * ne * N, u_w = 2 * (size_t)ne * N, tmp_w = 2 * (size_t)nl * N;
+    if ((lift_w + u_w + tmp_w) * 8 > HE_SCRATCH_BYTES) {
+        fprintf(stderr, "libhe: he_rotate_noalloc needs %zu scratch bytes at level %u, more than the %llu it has\n",
+                (lift_w + u_w + tmp_w) * 8, level, HE_SCRATCH_BYTES);
+        return HE_ENOMEM;
+    }
+    return guardc(ctx, [&]() {
+        int dev = 0;
+        hip_check(hipGetDevice(&dev), "device");
+        if (dev != c->device) throw HeError(HE_EMISMATCH);  // the scratch address is per device
+        const u64 g = c->galois(k);
+        if (g == 1) {
+            hip_check(hipMemcpyAsync(out, in, ct_words * 8, hipMemcpyDeviceToDevice, c->stream), "rotate copy");
+            return;
+        }
+        const u64* key = c->rot_key(g, false);
+        u64 *lift = c->scratch, *u = lift + lift_w, *tmp = u + u_w;
+        c->ks_lift_into(in + (size_t)nl * N, (int)level, lift, tmp);
+        launch_automorph(c->T, nl, 1, out, 0, in, 0, g, c->stream);
+        c->ks_apply_into(lift, (int)level, key, g, out, nullptr, out, out + (size_t)nl * N, u, tmp);
+        c->cnt[C_ROT]++;
+    });
 }
 he_status he_gen_rotation_key(he_ctx* ctx, int64_t k) {
     if (!ctx) return HE_EINVAL;

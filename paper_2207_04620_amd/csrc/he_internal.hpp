@@ -151,6 +151,8 @@ struct Ctx {
     double scale = 1.0;
     u64 seed = 0;
     uint32_t schedule = 0;
+    int device = 0;            // the HIP device current at creation
+    u64* scratch = nullptr;    // that device's copy of the allocation-free entry point's scratch
     hipStream_t stream = nullptr;
     bool own_stream = false;
     Pool pool;
@@ -191,6 +193,9 @@ struct Ctx {
     CtPtr add_sub(const CtData& a, const CtData& b, bool sub);
     CtPtr tensor(const CtData& a, const CtData& b);
     std::unique_ptr<DBuf> ks_lift(const u64* d, int level);
+    void ks_lift_into(const u64* d, int level, u64* lift, u64* coef);
+    void ks_apply_into(const u64* lift, int level, const u64* key, u64 g, const u64* add0, const u64* add1,
+                       u64* out0, u64* out1, u64* u, u64* conv);
     void ks_apply(const u64* lift, int level, const u64* key, u64 g, const u64* add0, const u64* add1, u64* out0,
                   u64* out1);
     CtPtr relin(const CtData& a);

@@ -120,6 +120,7 @@ SIGNATURES = {
     "he_profile_report": (C.c_int, [C.c_void_p, C.c_char_p, C.c_size_t]),
     "he_status_string": (C.c_char_p, [C.c_int]),
     "he_debug_fail_launch": (C.c_int, [C.c_uint64]),
+    "he_rotate_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_int64, C.c_void_p]),
     "he_pool_limit": (C.c_int, [C.c_void_p, C.c_uint64]),
     "he_pool_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.c_int]),
 }
@@ -349,6 +350,12 @@ class Context:
         _chk(lib().he_gen_rotation_key(self.ptr, int(k)), "he_gen_rotation_key")
 
     # -- the packed product and the sign approximation
+    def rotate_noalloc(self, in_ptr: int, level: int, k: int, out_ptr: int):
+        """Rot by k on caller device memory (u64[2][level+1][N], evaluation domain); allocates
+        nothing"""
+        _chk(lib().he_rotate_noalloc(self.ptr, C.c_void_p(in_ptr), level, k, C.c_void_p(out_ptr)),
+             "he_rotate_noalloc")
+
     def matmul(self, a, b, h):
         return self._ct(lib().he_matmul, a.ptr, b.ptr, int(h))
 
