@@ -247,6 +247,25 @@ def test_matmul_rings_of_few_blocks(he, log_n, schedule):
         assert np.array_equal(p.g.export(r), s1)
 
 
+def test_c1_as_stated_primitives(he):
+    """C1 exactly as stated (N = 2^12, q0 40 bits, q1 30 bits, P 40 bits, scale 2^30: one
+    rescale level): encryption of an h = 8 matrix, one multiply (Fig. 1 Mul_ct: tensor +
+    relinearisation, then RS) and rotations by 1 and by h, every residue against the oracle;
+    the product decrypts to the slot-wise product within 1e-3 of FP64"""
+    p = Pair(he, I.C1, h_list=[])
+    A, B = I.matrix_pair(11, 8)
+    ga, gb = p.g.encrypt(A.ravel(), nonce=1), p.g.encrypt(B.ravel(), nonce=2)
+    oa, ob = p.o.encrypt(A.ravel(), nonce=1), p.o.encrypt(B.ravel(), nonce=2)
+    p.same(ga, oa)
+    gm, om = p.g.rescale(p.g.mul(ga, gb)), p.o.rescale(p.o.mul(oa, ob))
+    p.same(gm, om)
+    assert gm.info()[0] == 0
+    assert np.abs(p.g.decrypt(gm, 64) - (A * B).ravel()).max() < 1e-3
+    for k in (1, 8):
+        p.g.gen_rotation_key(k)
+        p.same(p.g.rotate(ga, k), p.o.rotate(oa, k))
+
+
 def test_matmul_fast_schedule_c1plus_bound(he):
     """the stated accuracy (1e-3 at scale 2^30, 2^12 ring, h = 8) under all four flags"""
     p = Pair(he, I.C1P, schedule=15)

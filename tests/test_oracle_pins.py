@@ -432,6 +432,23 @@ def test_matmul_decrypts_to_product_and_counts(small, h):
     assert cnt["rescale"] == 2 + h + 1  # Step 1-1, Step 1-2, each A^(k), the final sum
 
 
+def test_c1_as_stated_one_multiply():
+    """C1 as stated (40 + 30-bit chain, 40-bit P, scale 2^30): one Mul_ct + RS decrypts to the
+    slot-wise product of two h = 8 matrices within 1e-3, and rotations by 1 and h rotate the
+    slots; the packed product (depth 3) is refused on this one-level chain"""
+    c = O.Ctx.from_params(I.C1)
+    A, B = I.matrix_pair(11, 8)
+    a, b = c.encrypt(A.ravel(), nonce=1), c.encrypt(B.ravel(), nonce=2)
+    m = c.rescale(c.mul(a, b))
+    assert m.level == 0
+    assert np.abs(c.decrypt(m, 64) - (A * B).ravel()).max() < 1e-3
+    v = A.ravel()
+    for k in (1, 8):
+        assert np.abs(c.decrypt(c.rotate(a, k), 64) - np.roll(v, -k)).max() < 1e-3
+    with pytest.raises(ValueError):
+        c.matmul(a, b, 8)
+
+
 def test_matmul_c1plus_bound():
     """the stated accuracy: max abs error <= 1e-3 at scale 2^30 (C1+ ring, h = 8)"""
     c = O.Ctx.from_params(I.C1P)
