@@ -228,11 +228,13 @@ def c4_leg(he, I, sched, stream, count):
 
 def serve_rings_leg(he, I, sched, nreq, load):
     """The serving configuration across rings: one server per context (N = 2^14, 2^15,
-    2^16), mixed requests (60% products with h uniform over {8, 16, 32, 64, 128}; 40% sign or
-    ReLU with d = 3 and k uniform over 1..4, a quarter of them the N=2^16 ReLU k = 3 so that the
-    largest ring serves too) routed to the smallest ring that holds them.  Capacity is measured
-    with a burst of nreq requests; latency with Poisson arrivals (seed 5) at 0.5, 0.8 and 0.95 x
-    capacity, from scheduled arrival to completion."""
+    2^16), mixed requests (60% products with h uniform over {8, 16, 32, 64, 128}; 25% sign or
+    ReLU with d = 3 and k uniform over 1..4 (depth 3..13); 5% of depth 1 and 2 (x^2, x . x^2);
+    10% the N=2^16 ReLU k = 3, so that the largest ring serves too) routed to the smallest ring
+    that holds them.  The burst capacity is measured with nreq requests at once; the Poisson
+    capacity, the highest Poisson arrival rate the servers keep up with, by bisection; latency
+    with Poisson arrivals (seed 5) at 0.5, 0.8 and 0.95 x the Poisson capacity, from scheduled
+    arrival to completion."""
     rings = [he.Context(I.C2, h_list=[8, 16, 32, 64], schedule=sched),
              he.Context(I.C3, h_list=[128], schedule=sched),
              he.Context(I.C4, h_list=[], schedule=sched)]
@@ -242,8 +244,10 @@ def serve_rings_leg(he, I, sched, nreq, load):
         u = rng.random()
         if u < 0.60:
             kinds.append(("mm", int(rng.choice([8, 16, 32, 64, 128]))))
-        elif u < 0.90:
+        elif u < 0.85:
             kinds.append(("sign", 3, int(rng.integers(1, 5)), int(rng.integers(0, 2))))
+        elif u < 0.90:  # depth 1 and 2: a square, a square and a product
+            kinds.append(("pow", int(rng.integers(2, 4))))
         else:
             kinds.append(("c4relu", 3, 3, he.RELU))
     inputs = {}
@@ -253,9 +257,11 @@ def serve_rings_leg(he, I, sched, nreq, load):
             ctx = he.smallest_ring(rings, h=w[1], depth=3)
         elif w[0] == "sign":
             ctx = he.smallest_ring(rings, h=32, depth=he.sign_depth(w[1], w[2], w[3]))
+        elif w[0] == "pow":
+            ctx = he.smallest_ring(rings, h=32, depth=w[1] - 1)
         else:
             ctx = rings[2]
-        key = (id(ctx), w[0], w[1] if w[0] == "mm" else 32)
+        key = (id(ctx), w[0] if w[0] == "mm" else "x", w[1] if w[0] == "mm" else 32)
         if key not in inputs:
             h = w[1] if w[0] == "mm" else 32
             if w[0] == "mm":
@@ -272,6 +278,8 @@ def serve_rings_leg(he, I, sched, nreq, load):
         srv = servers[id(ctx)]
         if w[0] == "mm":
             return srv, srv.submit(he.REQ_MATMUL, ops[0], ops[1], h=w[1])
+        if w[0] == "pow":
+            return srv, srv.submit(he.REQ_POWER, ops[0], k=w[1])
         return srv, srv.submit(he.REQ_SIGN, ops[0], d=w[1], k=w[2], mode=w[3])
 
     def drain(tk, late, arrivals):
@@ -297,35 +305,49 @@ def serve_rings_leg(he, I, sched, nreq, load):
             tk.append(submit(*p))
         return tk, late
 
-    # capacity: a burst of every request at t = 0
-    tk, late = submit_all([0.0] * nreq)
-    _, span = drain(tk, late, [0.0] * nreq)
-    capacity = nreq / span
-    runs = []
-    for ld in sorted({0.5, 0.95, load}):
-        # latency at ld x capacity
-        arrivals = I.poisson_arrivals(5, ld * capacity, nreq)
+    def run_at(rate):
+        arrivals = I.poisson_arrivals(5, rate, nreq)
         tk, late = submit_all(arrivals)
         lat, span = drain(tk, late, arrivals)
         lats = np.array([lat[j] for j in range(nreq)])
         by = {}
         for name, sel in (("matmul", lambda w: w[0] == "mm"), ("sign", lambda w: w[0] == "sign"),
-                          ("c4_relu", lambda w: w[0] == "c4relu")):
+                          ("power", lambda w: w[0] == "pow"), ("c4_relu", lambda w: w[0] == "c4relu")):
             v = np.array([lat[j] for j in range(nreq) if sel(kinds[j])])
             if v.size:
                 by[name] = {"n": int(v.size), "p50_ms": round(float(np.percentile(v, 50)) * 1e3, 1),
                             "p99_ms": round(float(np.percentile(v, 99)) * 1e3, 1)}
-        runs.append({"load": ld, "arrival_rate_per_s": round(ld * capacity, 1),
-                     "served_per_s": round(nreq / span, 1),
-                     "p50_ms": round(float(np.percentile(lats, 50)) * 1e3, 1),
-                     "p99_ms": round(float(np.percentile(lats, 99)) * 1e3, 1), "by_type": by})
+        return {"arrival_rate_per_s": round(rate, 1), "served_per_s": round(nreq / span, 1),
+                "p50_ms": round(float(np.percentile(lats, 50)) * 1e3, 1),
+                "p99_ms": round(float(np.percentile(lats, 99)) * 1e3, 1), "by_type": by}
+
+    # burst capacity: every request at t = 0
+    tk, late = submit_all([0.0] * nreq)
+    _, span = drain(tk, late, [0.0] * nreq)
+    capacity = nreq / span
+    # Poisson capacity: the highest arrival rate the servers keep up with (served >= 98 % of the
+    # arrival rate, p99 within 5 x p50), by bisection between 0.6 and 1.0 x the burst capacity
+    lo, hi, search = 0.6, 1.0, []
+    for _ in range(3):
+        mid = 0.5 * (lo + hi)
+        r = run_at(mid * capacity)
+        ok = r["served_per_s"] >= 0.98 * r["arrival_rate_per_s"] and r["p99_ms"] <= 5 * r["p50_ms"]
+        search.append({"fraction_of_burst": round(mid, 3), "served_per_s": r["served_per_s"],
+                       "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"], "kept_up": ok})
+        lo, hi = (mid, hi) if ok else (lo, mid)
+    pcap = lo * capacity
+    runs = []
+    for ld in sorted({0.5, 0.95, load}):
+        runs.append({"load": ld, **run_at(ld * pcap)})
     for srv in servers.values():
         srv.stop()
     for c in rings:
         c.close()
     return {"requests": nreq, "rings": "N=2^14 (C2), 2^15 (C3), 2^16 (C4)", "types": len(set(kinds)),
             "batching_window": {"min_batch": 8, "max_wait_ms": 40, "per_type": True},
-            "burst_capacity_per_s": round(capacity, 1), "poisson": runs}
+            "burst_capacity_per_s": round(capacity, 1), "poisson_capacity_per_s": round(pcap, 1),
+            "poisson_capacity_search": search,
+            "loads": "fractions of the Poisson capacity", "poisson": runs}
 
 
 def shapes_leg(he, I, prm, sched, stream, batch):
@@ -377,7 +399,7 @@ def main():
     ap.add_argument("--c4", type=int, default=128, help="ciphertexts of the N=2^16 ReLU + h=32 leg (0: skip)")
     ap.add_argument("--serve-rings", type=int, default=2000, help="requests of the cross-ring serving leg (0: skip)")
     ap.add_argument("--no-shapes", action="store_true", help="skip the packed / rectangular / transpose leg")
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / batched capacity")
     ap.add_argument("--serve-min-batch", type=int, default=8)
     ap.add_argument("--serve-max-wait-ms", type=float, default=60.0)

@@ -219,8 +219,13 @@ he_status he_sign_approx_batch(he_ctx *ctx, size_t n, const he_ct *const *x, uin
  * primitive 2N-th root of unity mod q.  inverse = 1 undoes it. */
 he_status he_ntt(he_ctx *ctx, uint64_t *dev_ptr, uint32_t n_limbs, const uint32_t *mod_idx, int inverse);
 
-/* Serving: a host thread admits requests by device-memory footprint and runs them
- * with continuous batching; each request's result is the same as running it alone. */
+/* Serving: a host thread admits requests by device-memory footprint and runs them with
+ * continuous batching; each request's result is the same as running it alone.  Rounds are
+ * pipelined (the issuing thread never synchronises the stream) and a completion thread hands
+ * each cohort's results out when its own kernels are done.  Admission footprints are measured:
+ * the largest per-member figure of the allocation cache seen while a cohort of that type ran
+ * (bytes held plus the transient peak of each phase); a type not yet measured is admitted on a
+ * conservative estimate. */
 typedef struct he_server he_server;
 typedef struct {
     uint64_t mem_budget_bytes; /* admission budget for in-flight requests (0: no limit) */
@@ -230,10 +235,11 @@ typedef struct {
 } he_serve_config;
 #define HE_REQ_MATMUL 0u
 #define HE_REQ_SIGN 1u
+#define HE_REQ_POWER 2u /* x^k for k = 2 (one Mul_ct and RS, depth 1) or 3 (x . x^2, depth 2) */
 typedef struct {
-    uint32_t op;      /* HE_REQ_MATMUL or HE_REQ_SIGN */
+    uint32_t op;      /* HE_REQ_MATMUL, HE_REQ_SIGN or HE_REQ_POWER */
     uint32_t h;       /* matmul side */
-    uint32_t d, k;    /* sign degree parameter and compositions */
+    uint32_t d, k;    /* sign degree parameter and compositions; the power's exponent (k) */
     uint32_t mode;    /* sign mode */
     const he_ct *a;   /* inputs (borrowed until the request completes) */
     const he_ct *b;
@@ -245,6 +251,12 @@ he_status he_serve_submit(he_server *s, const he_request *req, uint64_t *ticket)
 he_status he_serve_poll(he_server *s, uint64_t ticket, int *done, he_ct **result, he_status *req_status,
                         double *latency_s);
 he_status he_serve_stop(he_server *s);
+/* bytes admitted and not yet completed, the largest measured cohort footprint, the allocation
+ * cache's largest in-use byte count seen while serving (keys, masks and inputs included), and the
+ * measured per-member footprints of up to n_types request types (n_measured: how many types are
+ * measured) */
+he_status he_serve_stats(he_server *s, uint64_t *inflight_bytes, uint64_t *peak_cohort_bytes, uint64_t *peak_in_use,
+                         size_t n_types, uint64_t *type_bytes, size_t *n_measured);
 
 /* AppMax (Alg. 5): max(a, b) ~ (a + b)/2 + (a - b)/2 . g_d^(k)(a - b), evaluated as
  * ((a + b) + m g_d^(k)(m)) with m = a - b and the halving kept in the scale (ReLU is the case

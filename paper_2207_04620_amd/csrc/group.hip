@@ -986,6 +986,14 @@ bool Ctx::sign_step(SignJob& J) {
         J.cur = J.x;
         J.started = true;
     }
+    if (J.mode == 3) {  // x^2 or x . x^2
+        J.cur = g_mul_rs(J.x, J.x);
+        if (J.k == 3) J.cur = g_mul_rs(J.x, J.cur);
+        J.result = g_scatter(J.cur);
+        J.x = Grp();
+        J.cur = Grp();
+        return true;
+    }
     if (J.it < J.k) {
         // each composition returns its input's scale; for ReLU / AppMax the last one lands on
         // the prime q_l that the product x g rescales by, so x g comes out exactly at the

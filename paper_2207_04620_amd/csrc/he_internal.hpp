@@ -42,6 +42,17 @@ struct Pool {
     void release(void* p, size_t bytes);
     void trim();
     void trim_locked();
+    // bytes in use now; restart the peak figure from it
+    size_t restart_peak() {
+        std::lock_guard<std::mutex> lk(m);
+        peak = held - cached;
+        return peak;
+    }
+    // (bytes in use now, peak since the last restart)
+    std::pair<size_t, size_t> usage() {
+        std::lock_guard<std::mutex> lk(m);
+        return {held - cached, peak};
+    }
 };
 
 struct Ctx;
@@ -99,7 +110,8 @@ struct MatmulJob {
 };
 // resumable state of one lockstep sign/ReLU group
 // mode 0: g_d^(k)(x); mode 1: ReLU (x + x g) / 2; mode 2: AppMax(a, b) (Alg. 5) with
-// a = X, b = Y: ((a + b) + m g_d^(k)(m)) / 2, m = a - b
+// a = X, b = Y: ((a + b) + m g_d^(k)(m)) / 2, m = a - b; mode 3: the power x^k (k = 2: one
+// Mul_ct and RS, depth 1; k = 3: x . x^2, depth 2), the served requests of depth 1 and 2
 struct SignJob {
     std::vector<const CtData*> X, Y;
     int lvl = 0, d = 3, k = 1, mode = 0, it = 0;

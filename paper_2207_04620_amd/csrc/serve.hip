@@ -1,17 +1,27 @@
-// Serving loop: continuous batching of packed matrix products and sign/ReLU
-// evaluations on one device.
+// Serving loop: continuous batching of packed matrix products, sign/ReLU evaluations and
+// low powers on one device.
 //
-// A host thread owns execution.  Submitted requests wait in FIFO order.  Requests with
-// the same operation, parameters and level are one type; a type is ready once min_batch
-// of its requests wait or its oldest has waited max_wait (the batching window is per
-// type, so a mix of many types still forms full cohorts).  Ready requests are admitted
-// in arrival order while the summed device footprint of in-flight requests stays within
-// the budget; admitted requests of one type form a cohort that runs in lockstep (group
-// kernels, keys and masks read once per cohort).
-// Each round advances every active cohort by one phase (Step 1 of a product, then a
-// chunk of Step 2-3 rounds, then the final relinearisation/RS; one g_d composition of
-// a sign evaluation), so requests that arrive while others are on the device start at
-// the next round and their kernels interleave with the running cohorts on the stream.
+// An issuing thread owns execution.  Submitted requests wait in FIFO order.  Requests with
+// the same operation, parameters and level are one type; a type is ready once min_batch of
+// its requests wait or its oldest has waited max_wait (the batching window is per type, so
+// a mix of many types still forms full cohorts).  Ready requests are admitted in arrival
+// order while the device footprint of in-flight requests stays within the budget; admitted
+// requests of one type form a cohort that runs in lockstep (group kernels, keys and masks
+// read once per cohort).
+// Each round advances every active cohort by one phase (Step 1 of a product, then a chunk
+// of Step 2-3 rounds, then the final relinearisation/RS; one g_d composition of a sign
+// evaluation), so requests that arrive while others are on the device start at the next
+// round and their kernels interleave with the running cohorts on the stream.  Rounds are
+// pipelined: the issuing thread never synchronises the stream; it records an event after
+// each round and, before issuing the next, waits only for the round before it, so the
+// device always has the current round queued while the host prepares the next one.  A
+// cohort that has issued its last phase records an event; a completion thread waits for
+// these events in order and hands the results out, so a request completes when its own
+// kernels are done, not at a round boundary.
+// Footprints are measured: while a cohort issues a phase, the allocation cache's in-use and
+// peak figures give the bytes the cohort holds and its transient peak; the largest
+// per-member figure seen for a type is its admission footprint (a first request of a type is
+// admitted on a conservative estimate).
 // A request's result is the same operation DAG as running it alone: bit-identical.
 #include <hip/hip_runtime.h>
 
@@ -48,9 +58,20 @@ struct Req {
 
 struct Cohort {
     uint32_t op = 0;
+    ReqKey key;
     std::vector<uint64_t> ids;
     MatmulJob mj;
     SignJob sj;
+    int64_t held = 0;   // bytes of the allocation cache the cohort holds between phases
+    int64_t peak = 0;   // the most it held at any point of a phase
+};
+
+// a cohort whose last phase is queued: its results are handed out once its event completes
+struct Done {
+    std::vector<uint64_t> ids;
+    std::vector<CtPtr> res;
+    he_status st = HE_OK;
+    hipEvent_t ev = nullptr;
 };
 
 }  // namespace
@@ -64,29 +85,39 @@ struct he_server {
     double max_wait_s = 0;
     int k_chunk = 8;
     std::mutex mu;
-    std::condition_variable cv;
+    std::condition_variable cv;       // submissions, completions, stop
+    std::condition_variable done_cv;  // work for the completion thread
     std::deque<uint64_t> pending;
     std::map<uint64_t, Req> reqs;
     std::vector<Cohort> active;
+    std::deque<Done> completing;
+    std::map<ReqKey, size_t> measured;  // admission footprint per member, per type
+    std::vector<hipEvent_t> ev_free;
     uint64_t inflight = 0, next_id = 1;
-    bool stop = false;
-    std::thread th;
+    uint64_t peak_cohort_bytes = 0;    // the largest measured cohort footprint
+    uint64_t peak_in_use = 0;          // the allocation cache's largest in-use figure while serving
+    bool stop = false, issuing_done = false;
+    std::thread th, done_th;
 };
 
-static size_t footprint(const Ctx* c, const he_request& r, int level) {
+// a conservative first estimate of a request's device footprint (before its type is measured)
+static size_t footprint_estimate(const Ctx* c, const he_request& r, int level) {
     const size_t ct = 2 * (size_t)(level + 1) * c->N * 8;
     const int beta = (level + 1 + c->alpha - 1) / c->alpha;
     const size_t lift = (size_t)beta * (level + 1 + c->n_p) * c->N * 8;
+    const size_t ext = 2 * (size_t)(level + 1 + c->n_p) * c->N * 8;  // an extended-basis sum
     if (r.op == HE_REQ_MATMUL) {
-        // Step-1 baby steps, the Step-3 baby rotations of B0 kept across blocks, temporaries,
-        // the Step-2 mask pairs that share one ModDown (their extended-basis sums and results),
-        // and the lifts of A0 and B0 beside a rotation-sum term waiting for its partner
         const int bg = c->step3_baby((int)r.h);
-        const size_t ext = 2 * (size_t)(level + 1 + c->n_p) * c->N * 8;  // a hoisted rotation sum
         const size_t pb = (size_t)std::max(1, c->pair_batch);
-        return (size_t)(c->bsgs((int)r.h) + (bg < (int)r.h ? bg : 0) + 11 + pb) * ct + 4 * lift + (1 + pb) * ext;
+        return 2 * ((size_t)(c->bsgs((int)r.h) + (bg < (int)r.h ? bg : 0) + 11 + pb) * ct + 4 * lift +
+                    (1 + pb) * ext);
     }
-    return 12 * ct + 2 * lift;
+    return 2 * (12 * ct + 2 * lift + 2 * ext);
+}
+
+static size_t footprint(he_server* S, const Req& q) {
+    auto it = S->measured.find(q.key);
+    return it != S->measured.end() ? it->second : footprint_estimate(S->c, q.r, std::get<5>(q.key));
 }
 
 // types whose batching window has closed, and the time at which the next one closes
@@ -110,123 +141,218 @@ static std::map<ReqKey, bool> ready_types(he_server* S, double now, double* next
     return ready;
 }
 
+static hipEvent_t take_event(he_server* S) {
+    if (!S->ev_free.empty()) {
+        hipEvent_t e = S->ev_free.back();
+        S->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+// admission of ready requests in arrival order while the footprint fits; the others keep
+// their place in the queue (called with S->mu held)
+static void admit(he_server* S, const std::map<ReqKey, bool>& ready) {
+    std::map<ReqKey, size_t> slot;
+    std::vector<Cohort> fresh;
+    std::deque<uint64_t> keep;
+    bool full = false;
+    while (!S->pending.empty()) {
+        const uint64_t id = S->pending.front();
+        S->pending.pop_front();
+        Req& q = S->reqs[id];
+        auto rt = ready.find(q.key);
+        if (full || rt == ready.end() || !rt->second) {
+            keep.push_back(id);
+            continue;
+        }
+        q.footprint = footprint(S, q);
+        if (S->budget && S->inflight + q.footprint > S->budget && S->inflight > 0) {
+            full = true;  // head of line: nothing behind it overtakes it
+            keep.push_back(id);
+            continue;
+        }
+        S->inflight += q.footprint;
+        const int lvl = std::get<5>(q.key);
+        auto it = slot.find(q.key);
+        if (it == slot.end() || fresh[it->second].ids.size() >= S->max_batch) {
+            Cohort co;
+            co.op = q.r.op;
+            co.key = q.key;
+            if (q.r.op == HE_REQ_MATMUL) {
+                co.mj.h = (int)q.r.h;
+                co.mj.lvl = lvl;
+            } else {
+                co.sj.d = (int)q.r.d;
+                co.sj.k = (int)q.r.k;
+                co.sj.mode = q.r.op == HE_REQ_POWER ? 3 : (int)q.r.mode;
+                co.sj.lvl = lvl;
+            }
+            fresh.push_back(co);
+            slot[q.key] = fresh.size() - 1;
+            it = slot.find(q.key);
+        }
+        Cohort& co = fresh[it->second];
+        co.ids.push_back(id);
+        if (q.r.op == HE_REQ_MATMUL) {
+            co.mj.A.push_back(q.a);
+            co.mj.B.push_back(q.b);
+        } else {
+            co.sj.X.push_back(q.a);
+        }
+    }
+    S->pending.swap(keep);
+    for (auto& co : fresh) S->active.push_back(std::move(co));
+}
+
 static void serve_loop(he_server* S) {
+    hipEvent_t prev_round = nullptr;
     for (;;) {
-        std::vector<Cohort> fresh;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            std::map<ReqKey, bool> ready;
-            bool any = false;
             for (;;) {
-                if (S->stop && S->pending.empty() && S->active.empty()) return;
-                if (!S->pending.empty()) {
-                    double next_close = 0;
-                    const double now = now_s();
-                    ready = ready_types(S, now, &next_close);
-                    any = false;
-                    for (auto& kv : ready) any |= kv.second;
-                    if (any || !S->active.empty()) break;
-                    S->cv.wait_for(lk, std::chrono::duration<double>(std::max(0.0, next_close - now)));
-                } else {
-                    if (!S->active.empty()) break;
-                    S->cv.wait(lk);
-                }
-            }
-            // admission of ready requests in arrival order while the footprint fits; the
-            // others keep their place in the queue
-            std::map<ReqKey, size_t> slot;
-            std::deque<uint64_t> keep;
-            bool full = false;
-            while (!S->pending.empty()) {
-                const uint64_t id = S->pending.front();
-                S->pending.pop_front();
-                Req& q = S->reqs[id];
-                if (full || !ready[q.key]) {
-                    keep.push_back(id);
-                    continue;
-                }
-                if (S->budget && S->inflight + q.footprint > S->budget && S->inflight > 0) {
-                    full = true;  // head of line: nothing behind it overtakes it
-                    keep.push_back(id);
-                    continue;
-                }
-                S->inflight += q.footprint;
-                const int lvl = std::get<5>(q.key);
-                auto it = slot.find(q.key);
-                if (it == slot.end() || fresh[it->second].ids.size() >= S->max_batch) {
-                    Cohort co;
-                    co.op = q.r.op;
-                    if (q.r.op == HE_REQ_MATMUL) {
-                        co.mj.h = (int)q.r.h;
-                        co.mj.lvl = lvl;
-                    } else {
-                        co.sj.d = (int)q.r.d;
-                        co.sj.k = (int)q.r.k;
-                        co.sj.mode = (int)q.r.mode;
-                        co.sj.lvl = lvl;
+                if (S->stop && S->pending.empty() && S->active.empty()) {
+                    S->issuing_done = true;
+                    S->done_cv.notify_all();
+                    lk.unlock();
+                    if (prev_round) {
+                        (void)hipEventSynchronize(prev_round);
+                        (void)hipEventDestroy(prev_round);
                     }
-                    fresh.push_back(co);
-                    slot[q.key] = fresh.size() - 1;
-                    it = slot.find(q.key);
+                    return;
                 }
-                Cohort& co = fresh[it->second];
-                co.ids.push_back(id);
-                if (q.r.op == HE_REQ_MATMUL) {
-                    co.mj.A.push_back(q.a);
-                    co.mj.B.push_back(q.b);
-                } else {
-                    co.sj.X.push_back(q.a);
-                }
+                double next_close = 1e300;
+                const double now = now_s();
+                if (!S->pending.empty()) admit(S, ready_types(S, now, &next_close));
+                if (!S->active.empty()) break;
+                // nothing to issue: wait for a submission, a completion (budget freed), a
+                // closing window or stop
+                if (next_close < 1e299)
+                    S->cv.wait_for(lk, std::chrono::duration<double>(std::max(0.0, next_close - now)));
+                else
+                    S->cv.wait(lk);
             }
-            S->pending.swap(keep);
-            for (auto& co : fresh) S->active.push_back(std::move(co));
         }
-        // one round: every active cohort advances one phase
+        // one round: every active cohort advances one phase; a cohort whose last phase is now
+        // queued records its completion event right behind its own kernels
         std::vector<std::pair<size_t, he_status>> finished;
+        std::vector<hipEvent_t> evs(S->active.size(), nullptr);
         {
             std::lock_guard<std::recursive_mutex> lk(S->c->api_mu);
             for (size_t i = 0; i < S->active.size(); ++i) {
                 Cohort& co = S->active[i];
+                const size_t in0 = S->c->pool.restart_peak();
+                bool done = false;
+                he_status st = HE_OK;
                 try {
-                    const bool done = co.op == HE_REQ_MATMUL ? S->c->matmul_step(co.mj, S->k_chunk) : S->c->sign_step(co.sj);
-                    if (done) finished.push_back({i, HE_OK});
+                    // Step-2/3 rounds per phase: large products advance in larger chunks, so that
+                    // their number of phases (and rounds) stays near that of the smaller ones
+                    const int chunk = std::max(S->k_chunk, co.mj.h / 4);
+                    done = co.op == HE_REQ_MATMUL ? S->c->matmul_step(co.mj, chunk) : S->c->sign_step(co.sj);
                 } catch (const HeError& e) {
-                    finished.push_back({i, e.s});
+                    st = e.s;
                 } catch (const LaunchError&) {
-                    finished.push_back({i, HE_EDEVICE});
+                    st = HE_EDEVICE;
                 } catch (...) {
-                    finished.push_back({i, HE_EDEVICE});
+                    st = HE_EDEVICE;
                 }
-            }
-            if (hipStreamSynchronize(S->c->stream) != hipSuccess) {
-                (void)hipGetLastError();
-                for (size_t i = 0; i < S->active.size(); ++i) finished.push_back({i, HE_EDEVICE});
+                const auto use = S->c->pool.usage();
+                S->peak_in_use = std::max<uint64_t>(S->peak_in_use, use.second);
+                co.peak = std::max(co.peak, co.held + (int64_t)use.second - (int64_t)in0);
+                co.held += (int64_t)use.first - (int64_t)in0;
+                if (done && st == HE_OK) {
+                    {
+                        std::lock_guard<std::mutex> lk2(S->mu);
+                        evs[i] = take_event(S);
+                    }
+                    if (!evs[i] || hipEventRecord(evs[i], S->c->stream) != hipSuccess) {
+                        (void)hipGetLastError();
+                        st = HE_EDEVICE;
+                    }
+                }
+                if (st != HE_OK || done) finished.push_back({i, st});
             }
         }
-        const double t = now_s();
         {
             std::lock_guard<std::mutex> lk(S->mu);
             std::vector<bool> drop(S->active.size(), false);
             for (auto& f : finished) {
-                if (drop[f.first]) continue;
-                drop[f.first] = true;
                 Cohort& co = S->active[f.first];
-                auto& res = co.op == HE_REQ_MATMUL ? co.mj.result : co.sj.result;
-                for (size_t m = 0; m < co.ids.size(); ++m) {
-                    Req& q = S->reqs[co.ids[m]];
-                    q.status = f.second;
-                    if (f.second == HE_OK && m < res.size()) q.result = res[m];
-                    q.done = true;
-                    q.t_done = t;
-                    q.keep_a.reset();
-                    q.keep_b.reset();
-                    S->inflight -= q.footprint;
+                drop[f.first] = true;
+                Done d;
+                d.ids = co.ids;
+                d.st = f.second;
+                d.ev = evs[f.first];
+                if (f.second == HE_OK) {
+                    d.res = co.op == HE_REQ_MATMUL ? co.mj.result : co.sj.result;
+                    // the type's footprint per member, as measured
+                    const size_t per = (size_t)std::max<int64_t>(co.peak, 0) / std::max<size_t>(1, co.ids.size());
+                    size_t& m = S->measured[co.key];
+                    m = std::max(m, per);
+                    S->peak_cohort_bytes = std::max<uint64_t>(S->peak_cohort_bytes, (uint64_t)std::max<int64_t>(co.peak, 0));
                 }
+                S->completing.push_back(std::move(d));
             }
             std::vector<Cohort> keep;
             for (size_t i = 0; i < S->active.size(); ++i)
                 if (!drop[i]) keep.push_back(std::move(S->active[i]));
             S->active.swap(keep);
+        }
+        S->done_cv.notify_all();
+        // pipelining: the round just issued stays queued while the host prepares the next;
+        // the host waits only for the round before it
+        hipEvent_t r = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            r = take_event(S);
+        }
+        if (r && hipEventRecord(r, S->c->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            r = nullptr;
+        }
+        if (prev_round) {
+            (void)hipEventSynchronize(prev_round);
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->ev_free.push_back(prev_round);
+        }
+        prev_round = r;
+    }
+}
+
+// completion thread: waits for the finished cohorts' events in order and hands out results
+static void done_loop(he_server* S) {
+    for (;;) {
+        Done d;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->done_cv.wait(lk, [&] { return !S->completing.empty() || S->issuing_done; });
+            if (S->completing.empty()) return;  // issuing has ended and everything is handed out
+            d = std::move(S->completing.front());
+            S->completing.pop_front();
+        }
+        if (d.ev && hipEventSynchronize(d.ev) != hipSuccess) {
+            (void)hipGetLastError();
+            d.st = HE_EDEVICE;
+        }
+        const double t = now_s();
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (d.ev) S->ev_free.push_back(d.ev);
+            for (size_t m = 0; m < d.ids.size(); ++m) {
+                Req& q = S->reqs[d.ids[m]];
+                q.status = d.st;
+                if (d.st == HE_OK && m < d.res.size()) q.result = d.res[m];
+                q.done = true;
+                q.t_done = t;
+                q.keep_a.reset();
+                q.keep_b.reset();
+                S->inflight -= q.footprint;
+            }
         }
         S->cv.notify_all();
     }
@@ -246,6 +372,7 @@ he_status he_serve_start(he_ctx* ctx, const he_serve_config* cfg, he_server** ou
         S->max_wait_s = cfg->max_wait_us * 1e-6;
     }
     S->th = std::thread(serve_loop, S);
+    S->done_th = std::thread(done_loop, S);
     *out = S;
     return HE_OK;
 }
@@ -253,7 +380,7 @@ he_status he_serve_start(he_ctx* ctx, const he_serve_config* cfg, he_server** ou
 he_status he_serve_submit(he_server* S, const he_request* req, uint64_t* ticket) {
     if (!S || !req || !ticket || !req->a) return HE_EINVAL;
     if (req->op == HE_REQ_MATMUL && !req->b) return HE_EINVAL;
-    if (req->op > HE_REQ_SIGN) return HE_EINVAL;
+    if (req->op > HE_REQ_POWER) return HE_EINVAL;
     if (req->a->ctx != S->c || (req->b && req->b->ctx != S->c)) return HE_EMISMATCH;
     Req q;
     q.r = *req;
@@ -277,17 +404,26 @@ he_status he_serve_submit(he_server* S, const he_request* req, uint64_t* ticket)
                 return e.s;
             }
         }
-    } else {
+    } else if (q.r.op == HE_REQ_SIGN) {
         if (q.r.d < 1 || q.r.d > 7 || q.r.mode > 1) return HE_EINVAL;
+        if (q.a->deg != 1) return HE_EMISMATCH;
         int nb = 0;
         while ((1u << nb) <= q.r.d) ++nb;
         if (q.a->level < (int)(q.r.k * (nb + 1) + q.r.mode)) return HE_ELEVEL;
+    } else {  // x^2 (depth 1) or x^3 (depth 2)
+        if (q.r.k < 2 || q.r.k > 3) return HE_EINVAL;
+        if (q.a->deg != 1) return HE_EMISMATCH;
+        if (q.a->level < (int)q.r.k - 1) return HE_ELEVEL;
     }
     const int lvl = q.r.op == HE_REQ_MATMUL ? std::min(q.a->level, q.b->level) : q.a->level;
-    q.footprint = footprint(S->c, q.r, lvl);
+    const bool sg = q.r.op == HE_REQ_SIGN;
+    q.key = std::make_tuple(q.r.op, q.r.op == HE_REQ_MATMUL ? q.r.h : 0u, sg ? q.r.d : 0u,
+                            q.r.op != HE_REQ_MATMUL ? q.r.k : 0u, sg ? q.r.mode : 0u, lvl);
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        q.footprint = footprint(S, q);
+    }
     if (S->budget && q.footprint > S->budget) return HE_ENOMEM;
-    q.key = std::make_tuple(q.r.op, q.r.op == HE_REQ_MATMUL ? q.r.h : 0u, q.r.op == HE_REQ_SIGN ? q.r.d : 0u,
-                            q.r.op == HE_REQ_SIGN ? q.r.k : 0u, q.r.op == HE_REQ_SIGN ? q.r.mode : 0u, lvl);
     q.t_submit = std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
     {
         std::lock_guard<std::mutex> lk(S->mu);
@@ -327,10 +463,29 @@ he_status he_serve_stop(he_server* S) {
     }
     S->cv.notify_all();
     if (S->th.joinable()) S->th.join();
+    S->done_cv.notify_all();
+    if (S->done_th.joinable()) S->done_th.join();
     {
         std::lock_guard<std::recursive_mutex> lk(S->c->api_mu);
+        for (hipEvent_t e : S->ev_free) (void)hipEventDestroy(e);
         delete S;
     }
+    return HE_OK;
+}
+
+he_status he_serve_stats(he_server* S, uint64_t* inflight_bytes, uint64_t* peak_cohort_bytes, uint64_t* peak_in_use,
+                         size_t n_types, uint64_t* type_bytes, size_t* n_measured) {
+    if (!S) return HE_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (inflight_bytes) *inflight_bytes = S->inflight;
+    if (peak_cohort_bytes) *peak_cohort_bytes = S->peak_cohort_bytes;
+    if (peak_in_use) *peak_in_use = S->peak_in_use;
+    size_t i = 0;
+    for (auto& kv : S->measured) {
+        if (type_bytes && i < n_types) type_bytes[i] = kv.second;
+        ++i;
+    }
+    if (n_measured) *n_measured = i;
     return HE_OK;
 }
 

@@ -26,6 +26,7 @@ SIGN = 0
 RELU = 1
 REQ_MATMUL = 0
 REQ_SIGN = 1
+REQ_POWER = 2
 
 
 class HEError(RuntimeError):
@@ -116,6 +117,8 @@ SIGNATURES = {
     "he_serve_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_void_p),
                                 C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "he_serve_stop": (C.c_int, [C.c_void_p]),
+    "he_serve_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                 C.c_size_t, C.POINTER(C.c_uint64), C.POINTER(C.c_size_t)]),
     "he_profile_enable": (C.c_int, [C.c_void_p, C.c_int, C.c_char_p]),
     "he_profile_report": (C.c_int, [C.c_void_p, C.c_char_p, C.c_size_t]),
     "he_status_string": (C.c_char_p, [C.c_int]),
@@ -489,6 +492,16 @@ class Server:
         if st.value != 0:
             raise HEError(st.value, "request")
         return Ciphertext(self.ctx, res.value), lat.value
+
+    def stats(self):
+        """dict: bytes in flight, largest measured cohort footprint, the allocation cache's peak
+        in-use bytes while serving, measured per-member footprints"""
+        a, b, c, n = C.c_uint64(), C.c_uint64(), C.c_uint64(), C.c_size_t()
+        buf = (C.c_uint64 * 64)()
+        _chk(lib().he_serve_stats(self.ptr, C.byref(a), C.byref(b), C.byref(c), 64, buf, C.byref(n)),
+             "he_serve_stats")
+        return {"inflight": a.value, "peak_cohort": b.value, "peak_in_use": c.value,
+                "per_member": [buf[i] for i in range(min(64, n.value))]}
 
     def stop(self):
         if getattr(self, "ptr", None):

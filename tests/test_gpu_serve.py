@@ -51,11 +51,20 @@ def test_serve_mixed_requests_equal_alone(ctx):
         mode = i % 2
         reqs.append(("sign", mode, x, None))
         alone.append(ctx.export(ctx.sign_approx(x, 3, 1, mode)))
+    # the served requests of depth 1 and 2: x^2 (Mul_ct, RS) and x . x^2
+    for i, k in enumerate((2, 3, 2)):
+        x = ctx.encrypt(X[i].ravel(), level=6 - i, nonce=600 + i)
+        x2 = ctx.rescale(ctx.mul(x, x))
+        want = x2 if k == 2 else ctx.rescale(ctx.mul(ctx.drop(x, x2.level), x2))
+        reqs.append(("pow", k, x, None))
+        alone.append(ctx.export(want))
     srv = he.Server(ctx, max_batch=4)
     tickets = []
     for j, r in enumerate(reqs):
         if r[0] == "mm":
             tickets.append(srv.submit(he.REQ_MATMUL, r[2], r[3], h=r[1]))
+        elif r[0] == "pow":
+            tickets.append(srv.submit(he.REQ_POWER, r[2], k=r[1]))
         else:
             tickets.append(srv.submit(he.REQ_SIGN, r[2], d=3, k=1, mode=r[1]))
         if j % 3 == 2:
@@ -173,3 +182,46 @@ def test_serve_across_rings_equal_alone():
     for j, (ctx, w, _, _, want) in enumerate(reqs):
         assert np.array_equal(ctx.export(done[j][0]), want), (j, w)
     _log("[serve] across rings: every result equals its run alone")
+
+
+def test_serve_budget_from_measured_footprints():
+    """admission by measured footprints on the N=2^15 ring: a burst of 40 h=64 products (16 of
+    them first, so that the type is measured, then 24 more) under a budget of 2.5 GB; the
+    allocation cache's in-use bytes while serving stay within the budget above what was in use
+    before (keys, masks, inputs), every request completes, and results equal the product run
+    alone"""
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2207_04620_amd import he
+    _log("[serve] budget test: context C3, h=64")
+    ctx = he.Context(I.C3, h_list=[64], schedule=he.SCHED_FAST)
+    pairs = [I.matrix_pair(950 + i, 64) for i in range(4)]
+    As = [ctx.encrypt(A.ravel(), level=13, nonce=2 * i) for i, (A, _) in enumerate(pairs)]
+    Bs = [ctx.encrypt(B.ravel(), level=13, nonce=2 * i + 1) for i, (_, B) in enumerate(pairs)]
+    want = [ctx.export(ctx.matmul(a, b, 64)) for a, b in zip(As, Bs)]
+    ctx.sync()
+    base, _ = ctx.pool_stats()
+    budget = 2500 << 20
+    srv = he.Server(ctx, mem_budget_bytes=budget, max_batch=16, min_batch=1)
+    try:
+        for wave, n in enumerate((16, 24)):
+            ts = [srv.submit(he.REQ_MATMUL, As[i % 4], Bs[i % 4], h=64) for i in range(n)]
+            done = {}
+            deadline = time.time() + 120
+            while len(done) < n and time.time() < deadline:
+                for j, t in enumerate(ts):
+                    if j not in done:
+                        r = srv.poll(t)
+                        if r is not None:
+                            done[j] = ctx.export(r[0]) if j < 4 else True  # results dropped at once
+                time.sleep(0.002)
+            assert len(done) == n, wave
+            for j in range(4):
+                assert np.array_equal(done[j], want[j % 4])
+            st = srv.stats()
+            _log(f"[serve] wave {wave}: {st}, base {base}")
+            assert st["per_member"] and st["inflight"] == 0
+            assert st["peak_in_use"] - base <= budget, (st, base)
+    finally:
+        srv.stop()
+    ctx.close()
