@@ -394,6 +394,8 @@ def main():
                          "A^(k) late)")
     ap.add_argument("--plain-iters", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default scheduling knobs")
+    ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay of the batched step")
     ap.add_argument("--no-other", action="store_true", help="skip timing the other schedules")
     ap.add_argument("--mix", type=int, default=256, help="mixed-batch products (0: skip)")
     ap.add_argument("--c4", type=int, default=128, help="ciphertexts of the N=2^16 ReLU + h=32 leg (0: skip)")
@@ -444,6 +446,14 @@ def main():
         plain_s = (time.perf_counter() - t0) / args.plain_iters
         log(f"plain {plain_s * 1e3:.1f} ms per product")
 
+    # the autotuner's choice of the scheduling knobs for this shape (untimed; results do not
+    # depend on it)
+    tune = None
+    if not args.no_tune:
+        log("autotune")
+        tune = ctx.autotune(h, level, args.batch)
+        log(f"autotune: {tune['chosen']} ({tune['source']})")
+
     # batched path
     log("batched path: warmup")
     for _ in range(args.warmup):
@@ -477,6 +487,28 @@ def main():
     value = args.batch * args.steps / elapsed
     err = float(np.abs(ctx.decrypt(out[0], h * h).reshape(h, h) - np.dot(*I.matrix_pair(1000, h))).max())
     log(f"batched {value:.3f} products/s ({step_ms:.1f} ms per step of {args.batch}); max abs error {err:.2e}")
+
+    # the same batched step captured once into a HIP graph and replayed (no host launch work)
+    graph = None
+    if not args.no_graph:
+        log("graph capture of the batched step")
+        g, gouts = ctx.matmul_batch_graph(As, Bs, [h] * args.batch)
+        ctx.sync()
+        same = bool(np.array_equal(ctx.export(gouts[0]), ctx.export(out[0])))
+        g.launch()
+        ctx.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.launch()
+        ctx.sync()
+        torch.cuda.synchronize()
+        gdt = (time.perf_counter() - t0) / args.steps
+        graph = {"matmuls_per_s": round(args.batch / gdt, 3), "ms_per_step": round(gdt * 1e3, 2),
+                 "over_eager": round(step_ms / (gdt * 1e3), 3), "bit_identical_to_eager": same, **g.info()}
+        log(f"graph replay {gdt * 1e3:.1f} ms per step ({graph['matmuls_per_s']} products/s), identical {same}")
+        g.close()
+        del gouts
 
     # serving: Poisson arrivals of h=64 products at a fraction of the batched capacity
     serve = None
@@ -585,7 +617,9 @@ def main():
                    "plain_ms": None if plain_s != plain_s else round(plain_s * 1e3, 2),
                    "batched_matmuls_per_s_other_schedules": others or None,
                    "batched_over_plain": None if plain_s != plain_s else round(value * plain_s, 3),
-                   "max_abs_error": err},
+                   "max_abs_error": err,
+                   "autotune": tune,
+                   "graph_replay": graph},
         "serve": serve,
         "roofline": roofline,
         "ntt_all_passes": {"achieved": round(ntt_rate, 1), "unit": "Gbutterfly/s",

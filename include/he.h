@@ -179,6 +179,23 @@ he_status he_matmul(he_ctx *ctx, const he_ct *a, const he_ct *b, uint32_t h, he_
 he_status he_matmul_batch(he_ctx *ctx, size_t n, const he_ct *const *a, const he_ct *const *b,
                           const uint32_t *h, he_ct **out);
 
+/* The batched product captured once into a HIP graph and replayed: he_graph_launch recomputes
+ * every out[i] = a[i] b[i] from the inputs' current contents with the launches and copies of one
+ * he_matmul_batch call, without host-side launch work (bit-identical to he_matmul_batch).  The
+ * graph owns every device buffer its replays touch (the product's temporaries, taken on the
+ * graph's own account during the capture) and keeps the inputs and outputs alive until
+ * he_graph_destroy; out[i] are ordinary handles the caller frees.  The capture runs the product
+ * once (the first result is in out) after making its keys and masks; it is refused
+ * (HE_EUNSUPPORTED) while launch timing is on.  Launches are asynchronous on the context stream;
+ * he_graph_destroy waits for queued replays. */
+typedef struct he_graph he_graph;
+he_status he_matmul_batch_capture(he_ctx *ctx, size_t n, const he_ct *const *a, const he_ct *const *b,
+                                  const uint32_t *h, he_graph **graph, he_ct **out);
+he_status he_graph_launch(he_graph *graph);
+/* nodes of the graph and device bytes it owns */
+he_status he_graph_info(const he_graph *graph, size_t *nodes, uint64_t *bytes);
+void he_graph_destroy(he_graph *graph);
+
 /* Shape of a packed product (App. D, App. E).  t = h: the square product of he_matmul.
  * t < h (t divides h): HE-RMatMult (Alg. 6) of a t x h matrix A by an h x h matrix B; the
  * caller encrypts A~ = h/t vertical copies of A as an h x h matrix, and the result encrypts
@@ -203,6 +220,25 @@ he_status he_matmul_batch_ex(he_ctx *ctx, size_t n, const he_ct *const *a, const
 he_status he_transpose(he_ctx *ctx, const he_ct *a, uint32_t h, uint32_t beta, he_ct **out);
 he_status he_transpose_batch(he_ctx *ctx, size_t n, const he_ct *const *a, uint32_t h, uint32_t beta,
                              he_ct **out);
+
+/* Scheduling knobs of the lockstep products; results never depend on them.  pair_batch:
+ * rotation sets (Step-2 mask pairs, baby rotations) that share one key-switch inner-product
+ * launch and one ModDown launch (1..16); max_group: members per lockstep group (1..256). */
+typedef struct {
+    uint32_t pair_batch;
+    uint32_t max_group;
+} he_tuning;
+he_status he_tuning_get(const he_ctx *ctx, he_tuning *out);
+he_status he_tuning_set(he_ctx *ctx, const he_tuning *t);
+/* Autotuner: times he_matmul_batch of 'batch' h x h pairs at 'level' on the device under each
+ * candidate (pair_batch 1, 2, 4, 8; max_group = batch, and batch / 2 when batch >= 16; the best
+ * of two timed runs each after a warm-up), applies the fastest to the context (a later candidate
+ * must be 1 % faster to displace an earlier one) and caches it per (N, limbs, alpha, schedule, h,
+ * level, batch, device) in the process and, when cache_path is set, in that text file (a line
+ * already there is used without timing).  report: optional JSON of the candidates' times and the
+ * choice, truncated to report_n bytes.  HE_ESHAPE / HE_ELEVEL as for he_matmul.  Synchronizes. */
+he_status he_autotune(he_ctx *ctx, uint32_t h, uint32_t level, uint32_t batch, const char *cache_path,
+                      he_tuning *out, char *report, size_t report_n);
 
 /* Composite sign approximation g_d^(k) (Sec. 4.2; Alg. 5 for ReLU):
  * mode 0: g_d applied k times; mode 1: ReLU(x) = (x + x g_d^(k)(x)) / 2.

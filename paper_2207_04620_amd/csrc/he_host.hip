@@ -46,6 +46,19 @@ void hip_check(hipError_t e, const char* what) {
 void* Pool::alloc(size_t bytes) {
     std::lock_guard<std::mutex> lk(m);
     bytes = (bytes + 255) & ~(size_t)255;
+    if (capture) {  // a graph reuses its own blocks first; whatever it takes becomes its own
+        auto gi = capture->free_.find(bytes);
+        if (gi != capture->free_.end() && !gi->second.empty()) {
+            void* p = gi->second.back();
+            gi->second.pop_back();
+            return p;
+        }
+    }
+    void* p0 = alloc_locked(bytes);
+    if (capture) capture->owned[p0] = bytes;
+    return p0;
+}
+void* Pool::alloc_locked(size_t bytes) {
     auto it = free_.find(bytes);
     if (it != free_.end() && !it->second.empty()) {
         void* p = it->second.back();
@@ -78,6 +91,11 @@ void Pool::release(void* p, size_t bytes) {
     if (!p) return;
     std::lock_guard<std::mutex> lk(m);
     bytes = (bytes + 255) & ~(size_t)255;
+    if (capture) {  // released while capturing: the graph's, reused only by that capture
+        capture->owned[p] = bytes;
+        capture->free_[bytes].push_back(p);
+        return;
+    }
     free_[bytes].push_back(p);
     cached += bytes;
 }

@@ -29,9 +29,18 @@ enum { C_ROT = 0, C_KS = 1, C_MULPT = 2, C_MULCT = 3, C_ADD = 4, C_RS = 5 };
 // Size-bucketed cache over hipMalloc; all work is ordered on one stream, so a block
 // released here may be handed out again at once.  Thread-safe (the serving thread and
 // the caller release buffers concurrently).
+// Blocks of a captured HIP graph: every block handed out or released while a stream capture
+// records into the graph belongs to it (the graph's kernels and copies keep reading and writing
+// those addresses on every replay), and its blocks are reused only within that capture.
+struct GraphBlocks {
+    std::unordered_map<void*, size_t> owned;
+    std::unordered_map<size_t, std::vector<void*>> free_;
+};
+
 struct Pool {
     std::mutex m;
     std::unordered_map<size_t, std::vector<void*>> free_;
+    GraphBlocks* capture = nullptr;  // set while a graph is being captured
     size_t held = 0, cached = 0;  // device bytes held (in use + cached), of them cached
     size_t limit = 0;             // cap on held bytes (0: none); beyond it alloc is HE_ENOMEM
     size_t peak = 0;              // largest in-use byte count (held - cached) since the last reset
@@ -39,6 +48,7 @@ struct Pool {
     void (*dev_free)(void*, void*) = nullptr;
     void* user = nullptr;
     void* alloc(size_t bytes);
+    void* alloc_locked(size_t bytes);
     void release(void* p, size_t bytes);
     void trim();
     void trim_locked();
@@ -312,3 +322,21 @@ struct he_ctx {
     std::unique_ptr<Ctx> c;
 };
 he_ct* wrap(Ctx* c, CtPtr p);
+
+// runs f under the context's API lock, turning exceptions into status codes
+template <class F>
+inline he_status run_guarded(he_ctx* ctx, F&& f) {
+    std::lock_guard<std::recursive_mutex> lk(ctx->c->api_mu);
+    try {
+        f();
+        return HE_OK;
+    } catch (const HeError& e) {
+        return e.s;
+    } catch (const LaunchError&) {
+        return HE_EDEVICE;
+    } catch (const std::bad_alloc&) {
+        return HE_ENOMEM;
+    } catch (...) {
+        return HE_EDEVICE;
+    }
+}

@@ -96,6 +96,8 @@ void launch_check(const char* what) {
     }
 }
 
+bool prof_active() { return g_prof_on; }
+
 bool prof_enable(bool on, const char* only) {
     int k = -1;
     if (only) {

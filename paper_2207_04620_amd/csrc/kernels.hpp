@@ -230,6 +230,7 @@ void launch_inject(uint64_t n);
 
 // only: null for every kernel kind, else one kind's name; false for an unknown name
 bool prof_enable(bool on, const char* only);
+bool prof_active();
 std::string prof_report();  // JSON: per kernel kind {launches, ms, bytes}; clears the records
 
 // ------------------------------------------------------------------ launchers

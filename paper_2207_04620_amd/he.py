@@ -52,6 +52,10 @@ class _ServeConfig(C.Structure):
                 ("max_wait_us", C.c_uint32)]
 
 
+class _Tuning(C.Structure):
+    _fields_ = [("pair_batch", C.c_uint32), ("max_group", C.c_uint32)]
+
+
 class _Request(C.Structure):
     _fields_ = [("op", C.c_uint32), ("h", C.c_uint32), ("d", C.c_uint32), ("k", C.c_uint32),
                 ("mode", C.c_uint32), ("a", C.c_void_p), ("b", C.c_void_p)]
@@ -123,6 +127,15 @@ SIGNATURES = {
     "he_profile_report": (C.c_int, [C.c_void_p, C.c_char_p, C.c_size_t]),
     "he_status_string": (C.c_char_p, [C.c_int]),
     "he_debug_fail_launch": (C.c_int, [C.c_uint64]),
+    "he_matmul_batch_capture": (C.c_int, [C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                          C.POINTER(C.c_uint32), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
+    "he_graph_launch": (C.c_int, [C.c_void_p]),
+    "he_graph_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_uint64)]),
+    "he_graph_destroy": (None, [C.c_void_p]),
+    "he_tuning_get": (C.c_int, [C.c_void_p, C.POINTER(_Tuning)]),
+    "he_tuning_set": (C.c_int, [C.c_void_p, C.POINTER(_Tuning)]),
+    "he_autotune": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_char_p, C.POINTER(_Tuning),
+                              C.c_char_p, C.c_size_t]),
     "he_rotate_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_int64, C.c_void_p]),
     "he_pool_limit": (C.c_int, [C.c_void_p, C.c_uint64]),
     "he_pool_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.c_int]),
@@ -255,6 +268,25 @@ class Context:
         _chk(lib().he_counters(self.ptr, _i64p(o), int(reset)), "he_counters")
         return dict(zip(["rot", "keyswitch", "mul_pt", "mul_ct", "add", "rescale"], (int(x) for x in o)))
 
+    def tuning(self):
+        t = _Tuning()
+        _chk(lib().he_tuning_get(self.ptr, C.byref(t)), "he_tuning_get")
+        return {"pair_batch": t.pair_batch, "max_group": t.max_group}
+
+    def set_tuning(self, pair_batch: int, max_group: int):
+        t = _Tuning(pair_batch, max_group)
+        _chk(lib().he_tuning_set(self.ptr, C.byref(t)), "he_tuning_set")
+
+    def autotune(self, h: int, level: int, batch: int, cache_path: str | None = None):
+        """time the batched product under each candidate tuning, apply the fastest; returns the
+        report (candidates' times and the choice)"""
+        import json
+        t = _Tuning()
+        buf = C.create_string_buffer(1 << 14)
+        _chk(lib().he_autotune(self.ptr, h, level, batch, cache_path.encode() if cache_path else None, C.byref(t),
+                               buf, len(buf)), "he_autotune")
+        return json.loads(buf.value.decode())
+
     def pool_limit(self, nbytes: int):
         _chk(lib().he_pool_limit(self.ptr, int(nbytes)), "he_pool_limit")
 
@@ -371,6 +403,17 @@ class Context:
         _chk(lib().he_matmul_batch(self.ptr, n, pa, pb, ph, out), "he_matmul_batch")
         return [Ciphertext(self, out[i]) for i in range(n)]
 
+    def matmul_batch_graph(self, As, Bs, hs):
+        """capture the batched product into a HIP graph: (Graph, first results)"""
+        n = len(As)
+        pa = (C.c_void_p * n)(*[x.ptr for x in As])
+        pb = (C.c_void_p * n)(*[x.ptr for x in Bs])
+        ph = (C.c_uint32 * n)(*hs)
+        po = (C.c_void_p * n)()
+        g = C.c_void_p()
+        _chk(lib().he_matmul_batch_capture(self.ptr, n, pa, pb, ph, C.byref(g), po), "he_matmul_batch_capture")
+        return Graph(self, g.value, (As, Bs)), [Ciphertext(self, po[i]) for i in range(n)]
+
     def matmul_ex(self, a, b, h, t=None, beta=1):
         """HE-MatMult (t = h) / HE-RMatMult (t < h, a holds h/t copies of a t x h matrix) on
         beta matrix pairs packed by iota_beta"""
@@ -440,6 +483,31 @@ class Context:
         n_limbs = dev_tensor.shape[0]
         mi = (C.c_uint32 * n_limbs)(*[int(x) for x in mod_idx])
         _chk(lib().he_ntt(self.ptr, C.c_void_p(dev_tensor.data_ptr()), n_limbs, mi, int(inverse)), "he_ntt")
+
+
+class Graph:
+    """A captured batched product (he_matmul_batch_capture): launch() replays it on the context
+    stream, rewriting the results the capture returned."""
+
+    def __init__(self, ctx, ptr, keep):
+        self.ctx, self.ptr, self._keep = ctx, ptr, keep
+        self._destroy = lib().he_graph_destroy
+
+    def launch(self):
+        _chk(lib().he_graph_launch(self.ptr), "he_graph_launch")
+
+    def info(self):
+        n, b = C.c_size_t(), C.c_uint64()
+        _chk(lib().he_graph_info(self.ptr, C.byref(n), C.byref(b)), "he_graph_info")
+        return {"nodes": n.value, "bytes": b.value}
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            self._destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        self.close()
 
 
 def fail_launch(n: int):
