@@ -41,17 +41,37 @@ Grp Ctx::g_gather(const std::vector<const CtData*>& v, int level) {
         sc.push_back(c->scale);
     }
     Grp g = g_new((int)v.size(), level, 1, sc);
-    for (size_t i = 0; i < v.size(); ++i)
-        copy2d(this, g.p + i * g.cs, g.ps, v[i]->buf->p, (int64_t)(v[i]->level + 1) * N, g.ps, 2);
+    // the members' limb prefixes, up to CP_MAX members per copy launch
+    CopyDesc D;
+    for (size_t i = 0; i < v.size(); ++i) {
+        D.src[D.n] = v[i]->buf->p;
+        D.dst[D.n] = g.p + i * g.cs;
+        D.width[D.n] = g.ps;
+        D.spitch[D.n] = (int64_t)(v[i]->level + 1) * N;
+        D.dpitch[D.n] = g.ps;
+        D.rows[D.n] = 2;
+        if (++D.n == CP_MAX || i + 1 == v.size()) {
+            launch_copy(D, stream);
+            D.n = 0;
+        }
+    }
     return g;
 }
 
 std::vector<CtPtr> Ctx::g_scatter(const Grp& g) {
     std::vector<CtPtr> out;
+    CopyDesc D;
     for (int i = 0; i < g.B; ++i) {
         CtPtr c = new_ct(g.level, g.deg, g.scale[i]);
-        hip_check(hipMemcpyAsync(c->buf->p, g.p + i * g.cs, (size_t)g.cs * 8, hipMemcpyDeviceToDevice, stream),
-                  "scatter");
+        D.src[D.n] = g.p + i * g.cs;
+        D.dst[D.n] = c->buf->p;
+        D.width[D.n] = g.cs;
+        D.spitch[D.n] = D.dpitch[D.n] = g.cs;
+        D.rows[D.n] = 1;
+        if (++D.n == CP_MAX || i + 1 == g.B) {
+            launch_copy(D, stream);
+            D.n = 0;
+        }
         out.push_back(c);
     }
     return out;
@@ -80,14 +100,16 @@ std::shared_ptr<DBuf> Ctx::g_lift(const Grp& a, int poly) {
     const int64_t lcs = (int64_t)beta * ne * N;
     auto lift = std::make_shared<DBuf>(this, (size_t)B * lcs);
     DBuf coef(this, (size_t)B * nl * N);
-    copy2d(this, coef.p, (int64_t)nl * N, a.p + poly * a.ps, a.cs, (int64_t)nl * N, B);
-    // with the fused conversion, the inverse transform also applies each digit's (D/q_s)^-1
+    // with the fused conversion, the inverse transform also applies each digit's (D/q_s)^-1;
+    // it reads the polynomial in place and writes its coefficient form to coef
     bool fused = true;
     for (const auto& inf : infos) fused = fused && conv_cols_fits(T, inf.hi - inf.lo);
     {
         Jobs J;
         J.base = coef.p;
         J.cstride = (int64_t)nl * N;
+        J.src = a.p + poly * a.ps;
+        J.src_cstride = a.cs;
         J.nct = B;
         J.n = nl;
         for (int i = 0; i < nl; ++i) {
@@ -135,10 +157,11 @@ std::shared_ptr<DBuf> Ctx::g_lift(const Grp& a, int poly) {
         D.prescaled = fused ? 1 : 0;
         if (fused) launch_conv_cols(T, D, stream);
         else launch_baseconv(T, D, stream);
-        copy2d(this, lift->p + ((size_t)j * ne + inf.lo) * N, lcs, a.p + poly * a.ps + (size_t)inf.lo * N, a.cs,
-               (int64_t)(inf.hi - inf.lo) * N, B);
     }
     launch_ntt(T, J, false, stream, nullptr, 0, !fused);
+    // the digits' own limbs stay where they are: the inner product reads them from the
+    // polynomial (which outlives the lift wherever a lift is used)
+    lift_own[lift->p] = {a.p + poly * a.ps, a.cs};
     return lift;
 }
 
@@ -173,11 +196,29 @@ void Ctx::g_ks_inner_sets(u64* u, const u64* lift, int B, int level, std::vector
     D.c0_cs = c0_cs;
     D.nq = nl;
     for (int t = 0; t < nl; ++t) D.pmont[t] = hm::to_mont(pmod[t], mods[t]);
+    // every group lift leaves its digits' own limbs in the lifted polynomial
+    auto own_of = [&](const u64* l) {
+        auto it = lift_own.find(l);
+        if (it == lift_own.end()) throw HeError(HE_EUNSUPPORTED);
+        return it->second;
+    };
+    const auto own = own_of(lift);
+    D.own = own.first;
+    D.own_cs = own.second;
+    for (int j = 0; j < beta; ++j) {
+        D.dlo[j] = (uint8_t)mu[level][j].lo;
+        D.dhi[j] = (uint8_t)mu[level][j].hi;
+    }
     D.nrot = nrot;
     D.nset = (int)sets.size();
     for (size_t j = 0; j < sets.size(); ++j) {
         D.s[j] = sets[j];
         D.s[j].ginv = galois_inverse(sets[j].g, log_n);
+        if (sets[j].lift2) {
+            const auto o2 = own_of(sets[j].lift2);
+            D.s[j].own2 = o2.first;
+            D.s[j].own2_cs = o2.second;
+        }
     }
     D.accumulate = accumulate ? 1 : 0;
     launch_inner_product(T, D, stream);

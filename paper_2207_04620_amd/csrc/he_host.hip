@@ -698,8 +698,19 @@ void Ctx::ks_lift_into(const u64* d, int level, u64* lift, u64* coef) {
     const int nl = level + 1, ne = nl + n_p;
     const auto& infos = mu[level];
     const int beta = (int)infos.size();
-    hip_check(hipMemcpyAsync(coef, d, (size_t)nl * N * 8, hipMemcpyDeviceToDevice, stream), "lift copy");
-    ntt(coef, 1, 0, nl, true, -1);
+    {  // the digits' coefficient form: the inverse transform reads d in place, writes coef
+        Jobs Ji;
+        Ji.base = coef;
+        Ji.cstride = 0;
+        Ji.src = d;
+        Ji.nct = 1;
+        Ji.n = nl;
+        for (int i = 0; i < nl; ++i) {
+            Ji.off[i] = (uint16_t)i;
+            Ji.mod[i] = (uint8_t)i;
+        }
+        launch_ntt(T, Ji, true, stream);
+    }
     Jobs J;
     J.base = lift;
     J.cstride = 0;

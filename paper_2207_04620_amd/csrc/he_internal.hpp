@@ -246,6 +246,9 @@ struct Ctx {
     std::vector<CtPtr> transpose_batch(const std::vector<const CtData*>& X, int h, int beta);
     int max_group = 32;
     int pair_batch = 4;  // Step-2 mask pairs per shared ModDown launch
+    // a group lift holds only the converted limbs of each digit; its own limbs are read from the
+    // lifted polynomial: lift buffer -> (that polynomial of member 0, member stride)
+    std::unordered_map<const u64*, std::pair<const u64*, int64_t>> lift_own;
 
     // lockstep group operations (group.hip)
     Grp g_new(int B, int level, int deg, const std::vector<double>& sc);

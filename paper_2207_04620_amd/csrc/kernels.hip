@@ -19,6 +19,7 @@
 #define NTT_E 2048  // elements held in LDS by one NTT block (16 KiB)
 
 static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static bool misaligned16(const void* p) { return ((uintptr_t)p & 15) != 0; }
 
 // ------------------------------------------------------------------ launch timing
 // Optional HIP-event timing of every launch (he_profile_enable): a pair of events on
@@ -28,7 +29,7 @@ static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 static const char* const kProfNames[PK_COUNT] = {
     "ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "baseconv", "inner_product",
     "moddown_combine", "rescale_spread", "rescale_combine", "tensor", "mask_mac", "automorph", "elementwise",
-    "conv_ntt_cols"};
+    "conv_ntt_cols", "copy"};
 struct ProfRec {
     int kind;
     hipEvent_t a, b;
@@ -895,6 +896,8 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
     const int job = blockIdx.y, c = job / J.n, k = job % J.n;
     const int r = blockIdx.x;
     u64* a = J.base + c * J.cstride + (int64_t)J.off[k] * N + (int64_t)r * N2;
+    // out of place: the row comes from the source, the result goes to base
+    const u64* src = J.src ? J.src + c * J.src_cstride + (int64_t)J.off[k] * N + (int64_t)r * N2 : a;
     const int mi = J.mod[k];
     const ModP mp_ = T.mods[mi];
     const u64 q = mp_.q, q2 = 2 * q;
@@ -904,7 +907,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
         const double qd = (double)q, qinv = 1.0 / qd;
         double* sd = reinterpret_cast<double*>(s);
         for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
-            const u64x2 v = ld2(a + e);
+            const u64x2 v = ld2(src + e);
             sd[lds_at<true>(e)] = u2d(v.x);
             sd[lds_at<true>(e + 1)] = u2d(v.y);
         }
@@ -929,7 +932,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
         return;
     }
     for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
-        const u64x2 v = ld2(a + e);
+        const u64x2 v = ld2(src + e);
         s[lds_at<true>(e)] = v.x;
         s[lds_at<true>(e + 1)] = v.y;
     }
@@ -1088,7 +1091,6 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
         st2(a + (int64_t)(e >> logC) * N2 + col0 + (e & (C - 1)), u64x2{s[e], s[e + 1]});
 }
 
-static bool misaligned16(const void* p) { return ((uintptr_t)p & 15) != 0; }
 
 // the NTT kernels move two residues per lane with 16-byte accesses
 static void check_ntt_alignment(const Jobs& J, const Epi* E) {
@@ -1132,6 +1134,8 @@ void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st,
                 bool cols) {
     if (J.n == 0 || J.nct == 0) return;
     if (scale && (!inverse || scale_n < 1)) throw std::runtime_error("NTT output scale: inverse transforms only");
+    if (J.src && (!inverse || misaligned16(J.src) || (J.src_cstride & 1)))
+        throw std::runtime_error("NTT source: inverse transforms with aligned sources only");
     check_ntt_alignment(J, nullptr);
     Epi E;
     E.on = 0;
@@ -1157,6 +1161,41 @@ void launch_ntt(const DevTables& T, const Jobs& J, bool inverse, hipStream_t st,
             HE_LAUNCH(k_ntt_inv_cols, grid_cols, dim3(TPB), 0, st, T, J, scale, scale_n);
         }
     }
+}
+
+// ------------------------------------------------------------------ batched copies
+// grid (x, row, region): each block row copies a slice of one row of one region
+__global__ __launch_bounds__(TPB) void k_copy(CopyDesc D) {
+    const int r = blockIdx.z, row = blockIdx.y;
+    if (row >= D.rows[r]) return;
+    const u64* src = D.src[r] + row * D.spitch[r];
+    u64* dst = D.dst[r] + row * D.dpitch[r];
+    const int64_t w = D.width[r];
+    for (int64_t c = 2 * ((int64_t)blockIdx.x * TPB + threadIdx.x); c < w; c += 2 * (int64_t)gridDim.x * TPB)
+        st2(dst + c, ld2(src + c));
+}
+
+void launch_copy(CopyDesc& D, hipStream_t st) {
+    if (D.n <= 0) return;
+    if (D.n > CP_MAX) throw std::runtime_error("copy: too many regions");
+    D.start[0] = 0;
+    double bytes = 0;
+    int64_t wmax = 0;
+    int rmax = 0;
+    for (int r = 0; r < D.n; ++r) {
+        if ((D.width[r] & 1) || (D.spitch[r] & 1) || (D.dpitch[r] & 1) || misaligned16(D.src[r]) ||
+            misaligned16(D.dst[r]) || D.rows[r] < 0 || D.width[r] < 0 || D.rows[r] > 65535)
+            throw std::runtime_error("copy: region not 16-byte aligned");
+        D.start[r + 1] = D.start[r] + (D.width[r] >> 1) * D.rows[r];
+        bytes += 16.0 * D.width[r] * D.rows[r];
+        wmax = std::max(wmax, D.width[r]);
+        rmax = std::max(rmax, D.rows[r]);
+    }
+    if (D.start[D.n] == 0) return;
+    // about 4 word pairs per thread along a row
+    const int64_t bx = std::max<int64_t>(1, std::min<int64_t>(ceil_div(wmax / 2, 4 * TPB), 1024));
+    ProfScope p(PK_COPY, bytes, st);
+    HE_LAUNCH(k_copy, dim3((unsigned)bx, (unsigned)rmax, (unsigned)D.n), dim3(TPB), 0, st, D);
 }
 
 // ------------------------------------------------------------------ base conversion
@@ -1602,20 +1641,31 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
     // the second rotation may read another ciphertext's lift and c0 (a rotation-sum term)
     const u64* lift_r[NR];
     const u64* c0_r[NR];
-    int64_t c0cs_r[NR];
+    const u64* own_r[NR];
+    int64_t c0cs_r[NR], owncs_r[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) {
         const bool other = r && S.lift2;
         lift_r[r] = other ? S.lift2 : D.lift;
         c0_r[r] = other ? S.c0_2 : D.c0;
         c0cs_r[r] = other ? S.c0_2_cs : D.c0_cs;
+        own_r[r] = other ? S.own2 : D.own;
+        owncs_r[r] = other ? S.own2_cs : D.own_cs;
     }
+    // the digit whose own limbs include t (none for the special primes): read from the lifted
+    // polynomial, the same for every lane of the block
+    int jo = -1;
+#pragma unroll
+    for (int j = 0; j < NB; j++)
+        if (t >= D.dlo[j] && t < D.dhi[j]) jo = j;
     auto load = [&](int c, u64(&xo)[NR][NB], u64(&zo)[NR]) {
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             const u64* lift = lift_r[r] + c * D.lift_cs + (int64_t)t * N;
 #pragma unroll
-            for (int j = 0; j < NB; j++) xo[r][j] = lift[(int64_t)j * D.ne * N + src[r]];
+            for (int j = 0; j < NB; j++)
+                xo[r][j] = (own_r[r] && j == jo) ? own_r[r][c * owncs_r[r] + (int64_t)t * N + src[r]]
+                                                 : lift[(int64_t)j * D.ne * N + src[r]];
             zo[r] = with_c0 ? c0_r[r][c * c0cs_r[r] + (int64_t)t * N + src[r]] : 0;
         }
     };
@@ -1665,9 +1715,12 @@ void launch_inner_product(const DevTables& T, const IpDesc& D, hipStream_t st) {
     const double words = (double)D.ne * (ns * nr * 2.0 * D.beta + masks +
                                          D.nct * (lifts * D.beta + ns * (D.accumulate ? 4.0 : 2.0))) +
                          (D.c0 ? lifts * D.nq * D.nct : 0.0);
-    for (int j = 0; j < ns; ++j)
+    for (int j = 0; j < ns; ++j) {
         if (D.s[j].lift2 && (nr != 2 || (D.c0 != nullptr) != (D.s[j].c0_2 != nullptr)))
             throw std::runtime_error("inner product: second lift without a second rotation or c0");
+        if (D.s[j].lift2 && (D.own != nullptr) != (D.s[j].own2 != nullptr))
+            throw std::runtime_error("inner product: lifts with and without their own limbs in one launch");
+    }
     ProfScope prof_(PK_INNER, words * 8.0 * N, st);
     dim3 grid((N / TPB) * ns, D.ne);
     switch (D.beta) {

@@ -24,6 +24,23 @@ struct Jobs {
     int nct;
     uint16_t off[HE_MAXJ];
     uint8_t mod[HE_MAXJ];
+    // inverse transforms only: the first pass reads limb k of copy c from
+    // src + c * src_cstride + off[k] * N instead of from base (the transform out of place)
+    const u64* src = nullptr;
+    int64_t src_cstride = 0;
+};
+
+// Several 2-D device copies in one launch: region r moves rows[r] rows of width[r] words
+// (even) from src[r] (row pitch spitch[r]) to dst[r] (pitch dpitch[r]); every address and
+// pitch is a multiple of two words (16-byte accesses)
+#define CP_MAX 40
+struct CopyDesc {
+    int n = 0;
+    const u64* src[CP_MAX];
+    u64* dst[CP_MAX];
+    int64_t width[CP_MAX], spitch[CP_MAX], dpitch[CP_MAX];
+    int rows[CP_MAX];
+    int64_t start[CP_MAX + 1];  // word pairs before region r
 };
 
 // limb i of an (extended) polynomial -> prime index
@@ -112,6 +129,8 @@ struct IpSet {
     const u64* lift2;
     const u64* c0_2;
     int64_t c0_2_cs;
+    const u64* own2;  // where lift2's own digit limbs are read (see IpDesc::own)
+    int64_t own2_cs;
 };
 #define IP_MAXSET 16
 
@@ -128,6 +147,11 @@ struct IpDesc {
     int64_t c0_cs;
     int nq;
     u64 pmont[HE_MAXT];  // (P mod q_t) R mod q_t
+    // optional: each digit's own limbs [dlo[j], dhi[j]) are not in the lift but read from the
+    // lifted polynomial itself (evaluation form): limb t of member c at own + c * own_cs + t N
+    const u64* own;
+    int64_t own_cs;
+    uint8_t dlo[HE_MAXSRC], dhi[HE_MAXSRC];
     int nrot;            // rotations per set (1 or 2)
     int nset;            // sets of the same lift in this launch (at most IP_MAXSET)
     IpSet s[IP_MAXSET];
@@ -204,7 +228,7 @@ struct Epi {
 // ------------------------------------------------------------------ launch timing
 enum ProfKind {
     PK_NTT_FWD_COLS = 0, PK_NTT_FWD_ROWS, PK_NTT_INV_ROWS, PK_NTT_INV_COLS, PK_BASECONV, PK_INNER, PK_MODDOWN,
-    PK_RS_SPREAD, PK_RS_COMBINE, PK_TENSOR, PK_MASKMAC, PK_AUTOMORPH, PK_EW, PK_CONV_COLS, PK_COUNT
+    PK_RS_SPREAD, PK_RS_COMBINE, PK_TENSOR, PK_MASKMAC, PK_AUTOMORPH, PK_EW, PK_CONV_COLS, PK_COPY, PK_COUNT
 };
 #include <string>
 // Launch discipline: every kernel launch goes through HE_LAUNCH.  launch_gate() clears the
@@ -246,6 +270,8 @@ void launch_baseconv(const DevTables& T, const ConvDesc& D, hipStream_t st);
 bool conv_cols_fits(const DevTables& T, int ns);
 void launch_conv_cols(const DevTables& T, const ConvDesc& D, hipStream_t st);
 void launch_sample(const DevTables& T, const Jobs& J, const SampleArgs& A, hipStream_t st);
+// the regions of D (start[] is filled here)
+void launch_copy(CopyDesc& D, hipStream_t st);
 // out[p][i] = a[p][i] (op) b[p][i] over nl limbs (prime map mm) and npoly polys;
 // b_ps = 0 broadcasts one b polynomial to every poly
 void launch_ew(const DevTables& T, ModMap mm, int nl, int npoly, u64* out, int64_t out_ps, const u64* a,
