@@ -285,10 +285,57 @@ __device__ __forceinline__ void inv_all(u64* s, int L, int logT, u64 X, const u6
 // from its padded base, so its LDS accesses are one address plus constants; its 2^R - 1
 // twiddle pairs (w, w') are contiguous in a per-row table built on the host in the order the
 // round consumes them (ROW_TW pairs per row, round after round, group J after group J).
+// butterflies of one forward group of 2^R elements in registers, twiddle pairs at t
+template <int R>
+__device__ __forceinline__ void fwd_group(u64 (&x)[1 << R], const u64* __restrict__ t, u64 q) {
+    constexpr int G = 1 << R;
+    const u64 q2 = 2 * q;
+    u64x2 w[G - 1];
+#pragma unroll
+    for (int i = 0; i < G - 1; ++i) w[i] = ld2(t + 2 * i);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int half = G >> (r + 1);
+#pragma unroll
+        for (int b = 0; b < (1 << r); ++b) {
+            const u64x2 wb = w[(1 << r) - 1 + b];
+#pragma unroll
+            for (int k = b * 2 * half; k < b * 2 * half + half; ++k) {
+                const u64 U = red4(x[k], q2);
+                const u64 V = mul_shoup_lazy(x[k + half], wb.x, wb.y, q);
+                x[k] = U + V;
+                x[k + half] = U - V + q2;
+            }
+        }
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void inv_group(u64 (&x)[1 << R], const u64* __restrict__ t, u64 q) {
+    constexpr int G = 1 << R;
+    const u64 q2 = 2 * q;
+    u64x2 w[G - 1];
+#pragma unroll
+    for (int i = 0; i < G - 1; ++i) w[i] = ld2(t + 2 * i);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int half = 1 << r;
+#pragma unroll
+        for (int b = 0; b < (G >> (r + 1)); ++b) {
+            const u64x2 wb = w[G - (G >> r) + b];
+#pragma unroll
+            for (int k = b * 2 * half; k < b * 2 * half + half; ++k) {
+                const u64 U = x[k], V = x[k + half];
+                x[k] = red4(U + V, q2);
+                x[k + half] = mul_shoup_lazy(U - V + q2, wb.x, wb.y, q);
+            }
+        }
+    }
+}
+
 template <int R, int S0>
 __device__ __forceinline__ void fwd_row_round(u64* s, const u64* __restrict__ tw, int off, u64 q) {
     constexpr int G = 1 << R, NG = 8 / G, LD = 11 - S0 - R, D = 1 << LD;
-    const u64 q2 = 2 * q;
 #pragma unroll
     for (int gg = 0; gg < NG; ++gg) {
         const int g = gg * TPB + threadIdx.x;
@@ -298,25 +345,7 @@ __device__ __forceinline__ void fwd_row_round(u64* s, const u64* __restrict__ tw
         u64 x[G];
 #pragma unroll
         for (int k = 0; k < G; ++k) x[k] = sb[k * D + ((k * D) >> 5)];
-        const u64* t = tw + 2 * (off + J * (G - 1));
-        u64x2 w[G - 1];
-#pragma unroll
-        for (int i = 0; i < G - 1; ++i) w[i] = ld2(t + 2 * i);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int half = G >> (r + 1);
-#pragma unroll
-            for (int b = 0; b < (1 << r); ++b) {
-                const u64x2 wb = w[(1 << r) - 1 + b];
-#pragma unroll
-                for (int k = b * 2 * half; k < b * 2 * half + half; ++k) {
-                    const u64 U = red4(x[k], q2);
-                    const u64 V = mul_shoup_lazy(x[k + half], wb.x, wb.y, q);
-                    x[k] = U + V;
-                    x[k + half] = U - V + q2;
-                }
-            }
-        }
+        fwd_group<R>(x, tw + 2 * (off + J * (G - 1)), q);
 #pragma unroll
         for (int k = 0; k < G; ++k) sb[k * D + ((k * D) >> 5)] = x[k];
     }
@@ -325,7 +354,6 @@ __device__ __forceinline__ void fwd_row_round(u64* s, const u64* __restrict__ tw
 template <int R, int S0>
 __device__ __forceinline__ void inv_row_round(u64* s, const u64* __restrict__ tw, int off, u64 q) {
     constexpr int G = 1 << R, NG = 8 / G, LD = 11 - S0 - 1, D = 1 << LD;
-    const u64 q2 = 2 * q;
 #pragma unroll
     for (int gg = 0; gg < NG; ++gg) {
         const int g = gg * TPB + threadIdx.x;
@@ -335,49 +363,64 @@ __device__ __forceinline__ void inv_row_round(u64* s, const u64* __restrict__ tw
         u64 x[G];
 #pragma unroll
         for (int k = 0; k < G; ++k) x[k] = sb[k * D + ((k * D) >> 5)];
-        const u64* t = tw + 2 * (off + J * (G - 1));
-        u64x2 w[G - 1];
-#pragma unroll
-        for (int i = 0; i < G - 1; ++i) w[i] = ld2(t + 2 * i);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int half = 1 << r;
-#pragma unroll
-            for (int b = 0; b < (G >> (r + 1)); ++b) {
-                const u64x2 wb = w[G - (G >> r) + b];
-#pragma unroll
-                for (int k = b * 2 * half; k < b * 2 * half + half; ++k) {
-                    const u64 U = x[k], V = x[k + half];
-                    x[k] = red4(U + V, q2);
-                    x[k + half] = mul_shoup_lazy(U - V + q2, wb.x, wb.y, q);
-                }
-            }
-        }
+        inv_group<R>(x, tw + 2 * (off + J * (G - 1)), q);
 #pragma unroll
         for (int k = 0; k < G; ++k) sb[k * D + ((k * D) >> 5)] = x[k];
     }
 }
 
-__device__ __forceinline__ void fwd_rows_2048(u64* s, const u64* tw, u64 q) {
-    fwd_row_round<3, 0>(s, tw, 0, q);
+// The first and last rounds of a row pass run on registers: the first round's group of a
+// lane is the lane's own slice of the row (forward: elements tid + 256 k; inverse: the eight
+// contiguous elements 8 tid + k), loaded by the caller straight from global memory, and the
+// last round's groups (forward: elements 4 g + k; inverse: g + 512 k, for g = tid and
+// 256 + tid) go back to the caller, which stores them with its epilogue.  Two LDS round
+// trips and two barriers fewer than staging the whole row through LDS.
+__device__ __forceinline__ void fwd_rows_2048(u64* s, const u64* tw, u64 q, u64 (&x)[8], u64 (&y)[8]) {
+    const int tid = threadIdx.x;
+    fwd_group<3>(x, tw, q);
+    u64* sb = s + tid + (tid >> 5);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sb[264 * k] = x[k];
     __syncthreads();
     fwd_row_round<3, 3>(s, tw, 7, q);
     __syncthreads();
     fwd_row_round<3, 6>(s, tw, 63, q);
     __syncthreads();
-    fwd_row_round<2, 9>(s, tw, 511, q);
-    __syncthreads();
+#pragma unroll
+    for (int gg = 0; gg < 2; ++gg) {
+        const int g = gg * TPB + tid;
+        const u64* sg = s + 4 * g + (g >> 3);
+        u64 z[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) z[k] = sg[k];
+        fwd_group<2>(z, tw + 2 * (511 + 3 * g), q);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) y[4 * gg + k] = z[k];
+    }
 }
 
-__device__ __forceinline__ void inv_rows_2048(u64* s, const u64* tw, u64 q) {
-    inv_row_round<3, 10>(s, tw, 0, q);
+__device__ __forceinline__ void inv_rows_2048(u64* s, const u64* tw, u64 q, u64 (&x)[8], u64 (&y)[8]) {
+    const int tid = threadIdx.x;
+    inv_group<3>(x, tw + 2 * 7 * tid, q);
+    u64* sb = s + 8 * tid + (tid >> 2);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sb[k] = x[k];
     __syncthreads();
     inv_row_round<3, 7>(s, tw, 1792, q);
     __syncthreads();
     inv_row_round<3, 4>(s, tw, 2016, q);
     __syncthreads();
-    inv_row_round<2, 1>(s, tw, 2044, q);
-    __syncthreads();
+#pragma unroll
+    for (int gg = 0; gg < 2; ++gg) {
+        const int g = gg * TPB + tid;
+        const u64* sg = s + g + (g >> 5);
+        u64 z[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) z[k] = sg[528 * k];
+        inv_group<2>(z, tw + 2 * 2044, q);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) y[4 * gg + k] = z[k];
+    }
 }
 
 // ---- column pass with L1 <= 5 stages (N <= 2^16): the 2^(11 - L1) >= 64 columns of a
@@ -535,9 +578,59 @@ __device__ __forceinline__ double mulmod_d(double a, double w, double wq, double
     return __fma_rn(-c, q, hi) + lo;
 }
 
+template <int R>
+__device__ __forceinline__ void fwd_group_d(double (&x)[1 << R], const double* __restrict__ t, double q) {
+#pragma clang fp contract(off)
+    constexpr int G = 1 << R;
+    f64x2 w[G - 1];
+#pragma unroll
+    for (int i = 0; i < G - 1; ++i) w[i] = ld2d(t + 2 * i);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int half = G >> (r + 1);
+#pragma unroll
+        for (int b = 0; b < (1 << r); ++b) {
+            const f64x2 wb = w[(1 << r) - 1 + b];
+#pragma unroll
+            for (int k = b * 2 * half; k < b * 2 * half + half; ++k) {
+                const double V = mulmod_d(x[k + half], wb.x, wb.y, q);
+                const double U = x[k];
+                x[k] = U + V;
+                x[k + half] = U - V;
+            }
+        }
+    }
+}
+
+// the inverse group reduces its inputs first (|x| <= q/2 + 1)
+template <int R>
+__device__ __forceinline__ void inv_group_d(double (&x)[1 << R], const double* __restrict__ t, double q,
+                                            double qinv) {
+#pragma clang fp contract(off)
+    constexpr int G = 1 << R;
+#pragma unroll
+    for (int k = 0; k < G; ++k) x[k] = red_d(x[k], q, qinv);
+    f64x2 w[G - 1];
+#pragma unroll
+    for (int i = 0; i < G - 1; ++i) w[i] = ld2d(t + 2 * i);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int half = 1 << r;
+#pragma unroll
+        for (int b = 0; b < (G >> (r + 1)); ++b) {
+            const f64x2 wb = w[G - (G >> r) + b];
+#pragma unroll
+            for (int k = b * 2 * half; k < b * 2 * half + half; ++k) {
+                const double U = x[k], V = x[k + half];
+                x[k] = U + V;
+                x[k + half] = mulmod_d(U - V, wb.x, wb.y, q);
+            }
+        }
+    }
+}
+
 template <int R, int S0>
 __device__ __forceinline__ void fwd_row_round_d(double* s, const double* __restrict__ tw, int off, double q) {
-#pragma clang fp contract(off)
     constexpr int G = 1 << R, NG = 8 / G, LD = 11 - S0 - R, D = 1 << LD;
 #pragma unroll
     for (int gg = 0; gg < NG; ++gg) {
@@ -548,25 +641,7 @@ __device__ __forceinline__ void fwd_row_round_d(double* s, const double* __restr
         double x[G];
 #pragma unroll
         for (int k = 0; k < G; ++k) x[k] = sb[k * D + ((k * D) >> 5)];
-        const double* t = tw + 2 * (off + J * (G - 1));
-        f64x2 w[G - 1];
-#pragma unroll
-        for (int i = 0; i < G - 1; ++i) w[i] = ld2d(t + 2 * i);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int half = G >> (r + 1);
-#pragma unroll
-            for (int b = 0; b < (1 << r); ++b) {
-                const f64x2 wb = w[(1 << r) - 1 + b];
-#pragma unroll
-                for (int k = b * 2 * half; k < b * 2 * half + half; ++k) {
-                    const double V = mulmod_d(x[k + half], wb.x, wb.y, q);
-                    const double U = x[k];
-                    x[k] = U + V;
-                    x[k + half] = U - V;
-                }
-            }
-        }
+        fwd_group_d<R>(x, tw + 2 * (off + J * (G - 1)), q);
 #pragma unroll
         for (int k = 0; k < G; ++k) sb[k * D + ((k * D) >> 5)] = x[k];
     }
@@ -575,7 +650,6 @@ __device__ __forceinline__ void fwd_row_round_d(double* s, const double* __restr
 template <int R, int S0>
 __device__ __forceinline__ void inv_row_round_d(double* s, const double* __restrict__ tw, int off, double q,
                                                 double qinv) {
-#pragma clang fp contract(off)
     constexpr int G = 1 << R, NG = 8 / G, LD = 11 - S0 - 1, D = 1 << LD;
 #pragma unroll
     for (int gg = 0; gg < NG; ++gg) {
@@ -585,50 +659,62 @@ __device__ __forceinline__ void inv_row_round_d(double* s, const double* __restr
         double* sb = s + base + (base >> 5);
         double x[G];
 #pragma unroll
-        for (int k = 0; k < G; ++k) x[k] = red_d(sb[k * D + ((k * D) >> 5)], q, qinv);
-        const double* t = tw + 2 * (off + J * (G - 1));
-        f64x2 w[G - 1];
-#pragma unroll
-        for (int i = 0; i < G - 1; ++i) w[i] = ld2d(t + 2 * i);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int half = 1 << r;
-#pragma unroll
-            for (int b = 0; b < (G >> (r + 1)); ++b) {
-                const f64x2 wb = w[G - (G >> r) + b];
-#pragma unroll
-                for (int k = b * 2 * half; k < b * 2 * half + half; ++k) {
-                    const double U = x[k], V = x[k + half];
-                    x[k] = U + V;
-                    x[k + half] = mulmod_d(U - V, wb.x, wb.y, q);
-                }
-            }
-        }
+        for (int k = 0; k < G; ++k) x[k] = sb[k * D + ((k * D) >> 5)];
+        inv_group_d<R>(x, tw + 2 * (off + J * (G - 1)), q, qinv);
 #pragma unroll
         for (int k = 0; k < G; ++k) sb[k * D + ((k * D) >> 5)] = x[k];
     }
 }
 
-__device__ __forceinline__ void fwd_rows_2048_d(double* s, const double* tw, double q) {
-    fwd_row_round_d<3, 0>(s, tw, 0, q);
+// register-first and register-last row passes, as the integer ones above
+__device__ __forceinline__ void fwd_rows_2048_d(double* s, const double* tw, double q, double (&x)[8],
+                                                double (&y)[8]) {
+    const int tid = threadIdx.x;
+    fwd_group_d<3>(x, tw, q);
+    double* sb = s + tid + (tid >> 5);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sb[264 * k] = x[k];
     __syncthreads();
     fwd_row_round_d<3, 3>(s, tw, 7, q);
     __syncthreads();
     fwd_row_round_d<3, 6>(s, tw, 63, q);
     __syncthreads();
-    fwd_row_round_d<2, 9>(s, tw, 511, q);
-    __syncthreads();
+#pragma unroll
+    for (int gg = 0; gg < 2; ++gg) {
+        const int g = gg * TPB + tid;
+        const double* sg = s + 4 * g + (g >> 3);
+        double z[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) z[k] = sg[k];
+        fwd_group_d<2>(z, tw + 2 * (511 + 3 * g), q);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) y[4 * gg + k] = z[k];
+    }
 }
 
-__device__ __forceinline__ void inv_rows_2048_d(double* s, const double* tw, double q, double qinv) {
-    inv_row_round_d<3, 10>(s, tw, 0, q, qinv);
+__device__ __forceinline__ void inv_rows_2048_d(double* s, const double* tw, double q, double qinv,
+                                                double (&x)[8], double (&y)[8]) {
+    const int tid = threadIdx.x;
+    inv_group_d<3>(x, tw + 2 * 7 * tid, q, qinv);
+    double* sb = s + 8 * tid + (tid >> 2);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sb[k] = x[k];
     __syncthreads();
     inv_row_round_d<3, 7>(s, tw, 1792, q, qinv);
     __syncthreads();
     inv_row_round_d<3, 4>(s, tw, 2016, q, qinv);
     __syncthreads();
-    inv_row_round_d<2, 1>(s, tw, 2044, q, qinv);
-    __syncthreads();
+#pragma unroll
+    for (int gg = 0; gg < 2; ++gg) {
+        const int g = gg * TPB + tid;
+        const double* sg = s + g + (g >> 5);
+        double z[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) z[k] = sg[528 * k];
+        inv_group_d<2>(z, tw + 2 * 2044, q, qinv);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) y[4 * gg + k] = z[k];
+    }
 }
 
 // column rounds (L1 <= 5): wave-uniform twiddles (w, fl(w / q)) from the [M][N1] column table
@@ -788,34 +874,42 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E
     __shared__ u64 s[NTT_LDS];
     const int N = 1 << T.log_n, L1 = T.n1_log, L2 = T.n2_log, N1 = 1 << L1, N2 = 1 << L2;
     const int job = blockIdx.y, c = job / J.n, k = job % J.n;
-    const int r = blockIdx.x;
+    const int r = blockIdx.x, tid = threadIdx.x;
     u64* a = J.base + c * J.cstride + (int64_t)J.off[k] * N + (int64_t)r * N2;
     const int mi = J.mod[k];
     const u64 q = T.mods[mi].q, q2 = 2 * q;
-    const u64* W = T.psi + (int64_t)mi * N;
-    const u64* Ws = T.psi_sh + (int64_t)mi * N;
-    const bool fp = fp64_limb(q, L1, N2);
-    const double qd = (double)q, qinv = 1.0 / qd;
-    double* sd = reinterpret_cast<double*>(s);
-    for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
-        const u64x2 v = ld2(a + e);
-        if (fp) {  // the column pass left raw doubles (N1 > 1), else canonical words
-            sd[lds_at<true>(e)] = L1 ? bits_d(v.x) : u2d(v.x);
-            sd[lds_at<true>(e + 1)] = L1 ? bits_d(v.y) : u2d(v.y);
-        } else {
+    const bool fp = fp64_limb(q, L1, N2), full = N2 == NTT_E;
+    // 2048-element rows: the last round's elements 4 g + k (g = tid, 256 + tid) as words,
+    // canonical (FP64 path) or lazy in [0, 4q) (integer path)
+    u64 y[8];
+    if (fp) {
+        const double qd = (double)q, qinv = 1.0 / qd;
+        double x[8], yd[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {  // the column pass left raw doubles (N1 > 1), else canonical words
+            const u64 v = a[tid + TPB * i];
+            x[i] = L1 ? bits_d(v) : u2d(v);
+        }
+        fwd_rows_2048_d(reinterpret_cast<double*>(s), T.rtwd + ((int64_t)mi * N1 + r) * (2 * ROW_TW), qd, x, yd);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) y[i] = canon_d(yd[i], qd, qinv);
+    } else if (full) {
+        u64 x[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[i] = a[tid + TPB * i];
+        fwd_rows_2048(s, T.rtw + ((int64_t)mi * N1 + r) * (2 * ROW_TW), q, x, y);
+    } else {  // small rings (N < 2048): the row through LDS, plain radix-2 stages
+        const u64* W = T.psi + (int64_t)mi * N;
+        const u64* Ws = T.psi_sh + (int64_t)mi * N;
+        for (int e = 2 * tid; e < N2; e += 2 * TPB) {
+            const u64x2 v = ld2(a + e);
             s[lds_at<true>(e)] = v.x;
             s[lds_at<true>(e + 1)] = v.y;
         }
-    }
-    __syncthreads();
-    if (fp) {
-        fwd_rows_2048_d(sd, T.rtwd + ((int64_t)mi * N1 + r) * (2 * ROW_TW), qd);
-    } else if (N2 == NTT_E) {
-        fwd_rows_2048(s, T.rtw + ((int64_t)mi * N1 + r) * (2 * ROW_TW), q);
-    } else {  // small rings: plain radix-2 stages (N2 < 2048 only when N < 2048)
+        __syncthreads();
         for (int st = 0; st < L2; st++) {
             const int lt = L2 - st - 1, t = 1 << lt;
-            for (int b = threadIdx.x; b < N2 / 2; b += TPB) {
+            for (int b = tid; b < N2 / 2; b += TPB) {
                 const int i = b >> lt, j = b & (t - 1);
                 const int j1 = (i << (lt + 1)) + j;
                 const int idx = (1 << st) * (N1 + r) + i;
@@ -827,11 +921,17 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E
             __syncthreads();
         }
     }
-    // element e as a word: canonical (FP64 path) or lazy in [0, 4q) (integer path)
-    auto val = [&](int e) -> u64 { return fp ? canon_d(sd[lds_at<true>(e)], qd, qinv) : s[lds_at<true>(e)]; };
+    // emit(e, v0, v1): elements e, e + 1 of the row (words below 4q) to their destination
+    auto for_pairs = [&](auto&& emit) {
+        if (fp || full) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) emit(4 * ((i >> 1) * TPB + tid) + 2 * (i & 1), y[2 * i], y[2 * i + 1]);
+        } else {
+            for (int e = 2 * tid; e < N2; e += 2 * TPB) emit(e, s[lds_at<true>(e)], s[lds_at<true>(e + 1)]);
+        }
+    };
     if constexpr (!EPI) {
-        for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
-            u64 v0 = val(e), v1 = val(e + 1);
+        for_pairs([&](int e, u64 v0, u64 v1) {
             if (!fp) {
                 v0 = red4(v0, q2);
                 v1 = red4(v1, q2);
@@ -839,7 +939,7 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E
                 v1 = v1 >= q ? v1 - q : v1;
             }
             st2(a + e, u64x2{v0, v1});
-        }
+        });
         return;
     }
     const int p = J.off[k] / E.nl, t = J.off[k] % E.nl;
@@ -850,17 +950,12 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E
     const u64* mask = E.mask ? E.mask + (int64_t)t * N : nullptr;
     const u64* acc = E.acc[p] ? E.acc[p] + c * E.acc_cs + (int64_t)t * N : nullptr;
     const u64 qninv = T.mods[mi].qninv;
-    for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
+    for_pairs([&](int e, u64 v0, u64 v1) {
         const int i = r * N2 + e;
         const u64x2 uu = ld2(u + i);
-        u64 w[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            // v is below 4q and u < q, so u + 4q - v lies in (0, 5q); the Shoup product
-            // reduces any 64-bit operand to [0, q)
-            const u64 v = val(e + h);
-            w[h] = mul_shoup(uu[h] + 2 * q2 - v, pi, pis, q);
-        }
+        // v is below 4q and u < q, so u + 4q - v lies in (0, 5q); the Shoup product
+        // reduces any 64-bit operand to [0, q)
+        u64 w[2] = {mul_shoup(uu.x + 2 * q2 - v0, pi, pis, q), mul_shoup(uu.y + 2 * q2 - v1, pi, pis, q)};
         if (add) {
             if (E.g == 1) {
                 const u64x2 ad = ld2(add + i);
@@ -882,7 +977,7 @@ __global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E
             w[1] = add_mod(w[1], ac.y, q);
         }
         st2(out + i, u64x2{w[0], w[1]});
-    }
+    });
 }
 
 // Inverse transform: Gentleman-Sande, bit-reversed input, natural output, then N^-1.
@@ -894,78 +989,95 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
     __shared__ u64 s[NTT_LDS];
     const int N = 1 << T.log_n, L1 = T.n1_log, L2 = T.n2_log, N1 = 1 << L1, N2 = 1 << L2;
     const int job = blockIdx.y, c = job / J.n, k = job % J.n;
-    const int r = blockIdx.x;
+    const int r = blockIdx.x, tid = threadIdx.x;
     u64* a = J.base + c * J.cstride + (int64_t)J.off[k] * N + (int64_t)r * N2;
     // out of place: the row comes from the source, the result goes to base
     const u64* src = J.src ? J.src + c * J.src_cstride + (int64_t)J.off[k] * N + (int64_t)r * N2 : a;
     const int mi = J.mod[k];
     const ModP mp_ = T.mods[mi];
     const u64 q = mp_.q, q2 = 2 * q;
-    const u64* W = T.ipsi + (int64_t)mi * N;
-    const u64* Ws = T.ipsi_sh + (int64_t)mi * N;
+    // 2048-element rows: every lane loads its eight elements 8 tid + k before the first
+    // barrier and stores g + 512 k (g = tid, 256 + tid) after the last, so in place is safe
     if (fp64_limb(q, L1, N2)) {
         const double qd = (double)q, qinv = 1.0 / qd;
-        double* sd = reinterpret_cast<double*>(s);
-        for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
-            const u64x2 v = ld2(src + e);
-            sd[lds_at<true>(e)] = u2d(v.x);
-            sd[lds_at<true>(e + 1)] = u2d(v.y);
+        double x[8], y[8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const u64x2 v = ld2(src + 8 * tid + 2 * i);
+            x[2 * i] = u2d(v.x);
+            x[2 * i + 1] = u2d(v.y);
         }
-        __syncthreads();
-        inv_rows_2048_d(sd, T.irtwd + ((int64_t)mi * N1 + r) * (2 * ROW_TW), qd, qinv);
+        inv_rows_2048_d(reinterpret_cast<double*>(s), T.irtwd + ((int64_t)mi * N1 + r) * (2 * ROW_TW), qd, qinv, x,
+                        y);
         if (L1 == 0) {
             const u64 f = scale ? scale[2 * (k % scale_n)] : mp_.ninv;
             const double fd = (double)f, fq = fd / qd;
-            for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
-                u64 y[2];
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    y[h] = canon_d(mulmod_d(sd[lds_at<true>(e + h)], fd, fq, qd), qd, qinv);
-                    if (scale) y[h] = y[h] > mp_.half ? y[h] - q : y[h];
-                }
-                st2(a + e, u64x2{y[0], y[1]});
+            for (int i = 0; i < 8; ++i) {
+                u64 w = canon_d(mulmod_d(y[i], fd, fq, qd), qd, qinv);
+                if (scale) w = w > mp_.half ? w - q : w;
+                a[(i >> 2) * TPB + tid + 512 * (i & 3)] = w;
             }
         } else {  // raw double words for the FP64 column pass of this limb
-            for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB)
-                st2(a + e, u64x2{d_bits(sd[lds_at<true>(e)]), d_bits(sd[lds_at<true>(e + 1)])});
+#pragma unroll
+            for (int i = 0; i < 8; ++i) a[(i >> 2) * TPB + tid + 512 * (i & 3)] = d_bits(y[i]);
         }
         return;
     }
-    for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
+    if (N2 == NTT_E) {
+        u64 x[8], y[8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const u64x2 v = ld2(src + 8 * tid + 2 * i);
+            x[2 * i] = v.x;
+            x[2 * i + 1] = v.y;
+        }
+        inv_rows_2048(s, T.irtw + ((int64_t)mi * N1 + r) * (2 * ROW_TW), q, x, y);
+        if (L1 == 0) {
+            const u64 f = scale ? scale[2 * (k % scale_n)] : mp_.ninv;
+            const u64 fs = scale ? scale[2 * (k % scale_n) + 1] : mp_.ninv_sh;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                u64 w = mul_shoup(y[i], f, fs, q);
+                if (scale) w = w > mp_.half ? w - q : w;
+                a[(i >> 2) * TPB + tid + 512 * (i & 3)] = w;
+            }
+        } else {  // lazy in [0, 2q)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) a[(i >> 2) * TPB + tid + 512 * (i & 3)] = y[i];
+        }
+        return;
+    }
+    // small rings (N < 2048): the row through LDS, plain radix-2 stages, then N^-1
+    const u64* W = T.ipsi + (int64_t)mi * N;
+    const u64* Ws = T.ipsi_sh + (int64_t)mi * N;
+    for (int e = 2 * tid; e < N2; e += 2 * TPB) {
         const u64x2 v = ld2(src + e);
         s[lds_at<true>(e)] = v.x;
         s[lds_at<true>(e + 1)] = v.y;
     }
     __syncthreads();
-    if (N2 == NTT_E) {
-        inv_rows_2048(s, T.irtw + ((int64_t)mi * N1 + r) * (2 * ROW_TW), q);
-    } else {
-        for (int st = L2 - 1; st >= 0; st--) {
-            const int lt = L2 - st - 1, t = 1 << lt;
-            for (int b = threadIdx.x; b < N2 / 2; b += TPB) {
-                const int i = b >> lt, j = b & (t - 1);
-                const int j1 = (i << (lt + 1)) + j;
-                const int idx = (1 << st) * (N1 + r) + i;
-                const u64 U = s[lds_at<true>(j1)], V = s[lds_at<true>(j1 + t)];
-                s[lds_at<true>(j1)] = red4(U + V, q2);
-                s[lds_at<true>(j1 + t)] = mul_shoup_lazy(U - V + q2, W[idx], Ws[idx], q);
-            }
-            __syncthreads();
+    for (int st = L2 - 1; st >= 0; st--) {
+        const int lt = L2 - st - 1, t = 1 << lt;
+        for (int b = tid; b < N2 / 2; b += TPB) {
+            const int i = b >> lt, j = b & (t - 1);
+            const int j1 = (i << (lt + 1)) + j;
+            const int idx = (1 << st) * (N1 + r) + i;
+            const u64 U = s[lds_at<true>(j1)], V = s[lds_at<true>(j1 + t)];
+            s[lds_at<true>(j1)] = red4(U + V, q2);
+            s[lds_at<true>(j1 + t)] = mul_shoup_lazy(U - V + q2, W[idx], Ws[idx], q);
         }
+        __syncthreads();
     }
-    if (L1 == 0) {
-        const u64 f = scale ? scale[2 * (k % scale_n)] : mp_.ninv, fs = scale ? scale[2 * (k % scale_n) + 1] : mp_.ninv_sh;
-        for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB) {
-            u64 y0 = mul_shoup(s[lds_at<true>(e)], f, fs, q), y1 = mul_shoup(s[lds_at<true>(e + 1)], f, fs, q);
-            if (scale) {
-                y0 = y0 > mp_.half ? y0 - q : y0;
-                y1 = y1 > mp_.half ? y1 - q : y1;
-            }
-            st2(a + e, u64x2{y0, y1});
+    // N < 2048 means one row (L1 = 0)
+    const u64 f = scale ? scale[2 * (k % scale_n)] : mp_.ninv, fs = scale ? scale[2 * (k % scale_n) + 1] : mp_.ninv_sh;
+    for (int e = 2 * tid; e < N2; e += 2 * TPB) {
+        u64 y0 = mul_shoup(s[lds_at<true>(e)], f, fs, q), y1 = mul_shoup(s[lds_at<true>(e + 1)], f, fs, q);
+        if (scale) {
+            y0 = y0 > mp_.half ? y0 - q : y0;
+            y1 = y1 > mp_.half ? y1 - q : y1;
         }
-    } else {
-        for (int e = 2 * threadIdx.x; e < N2; e += 2 * TPB)  // lazy in [0, 2q)
-            st2(a + e, u64x2{s[lds_at<true>(e)], s[lds_at<true>(e + 1)]});
+        st2(a + e, u64x2{y0, y1});
     }
 }
 
