@@ -870,7 +870,7 @@ __device__ __forceinline__ int perm_g(int j, u64 g, int log_n);
 // EPI: the ModDown epilogue (E.on) is compiled in; without it the plain transform keeps its
 // smaller register footprint
 template <bool EPI>
-__global__ __launch_bounds__(TPB) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E) {
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E) {
     __shared__ u64 s[NTT_LDS];
     const int N = 1 << T.log_n, L1 = T.n1_log, L2 = T.n2_log, N1 = 1 << L1, N2 = 1 << L2;
     const int job = blockIdx.y, c = job / J.n, k = job % J.n;
@@ -1749,59 +1749,87 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
         }
         pm[r] = ip_key<NB>(mask ? mul_mont(pmont, mk, m.q, m.qninv) : pmont);
     }
-    u64 x[NR][NB], z[NR];
-    // the second rotation may read another ciphertext's lift and c0 (a rotation-sum term)
-    const u64* lift_r[NR];
-    const u64* c0_r[NR];
-    const u64* own_r[NR];
-    int64_t c0cs_r[NR], owncs_r[NR];
-#pragma unroll
-    for (int r = 0; r < NR; r++) {
-        const bool other = r && S.lift2;
-        lift_r[r] = other ? S.lift2 : D.lift;
-        c0_r[r] = other ? S.c0_2 : D.c0;
-        c0cs_r[r] = other ? S.c0_2_cs : D.c0_cs;
-        own_r[r] = other ? S.own2 : D.own;
-        owncs_r[r] = other ? S.own2_cs : D.own_cs;
-    }
-    // the digit whose own limbs include t (none for the special primes): read from the lifted
-    // polynomial, the same for every lane of the block
+    // the second rotation may read another ciphertext's lift and c0 (a rotation-sum term); the
+    // digit whose own limbs include t (none for the special primes) is read from the lifted
+    // polynomial itself.  Every operand word of member c sits at a block-uniform base plus c
+    // times a uniform stride plus the lane's gather offset, so the member loop only advances
+    // uniform pointers and loads with one 32-bit lane offset per rotation.
     int jo = -1;
 #pragma unroll
     for (int j = 0; j < NB; j++)
         if (t >= D.dlo[j] && t < D.dhi[j]) jo = j;
-    auto load = [&](int c, u64(&xo)[NR][NB], u64(&zo)[NR]) {
+    const u64* xp[NR][NB];
+    int64_t xcs[NR][NB];
+    const u64* zb[NR];
+    int64_t zcs[NR];
+    uint32_t so[NR];  // byte offset of the lane's source slot
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const bool other = r && S.lift2;
+        const u64* lift = (other ? S.lift2 : D.lift) + (int64_t)t * N;
+        const u64* own = other ? S.own2 : D.own;
+        const int64_t owncs = other ? S.own2_cs : D.own_cs;
+#pragma unroll
+        for (int j = 0; j < NB; j++) {
+            const bool from_own = own && j == jo;
+            xp[r][j] = from_own ? own + (int64_t)t * N : lift + (int64_t)j * D.ne * N;
+            xcs[r][j] = from_own ? owncs : D.lift_cs;
+        }
+        zb[r] = with_c0 ? (other ? S.c0_2 : D.c0) + (int64_t)t * N : nullptr;
+        zcs[r] = other ? S.c0_2_cs : D.c0_cs;
+        so[r] = (uint32_t)src[r] * 8u;
+    }
+    auto at = [](const u64* base, uint32_t off) { return *reinterpret_cast<const u64*>(reinterpret_cast<const char*>(base) + off); };
+    auto load = [&](u64(&xo)[NR][NB], u64(&zo)[NR]) {
 #pragma unroll
         for (int r = 0; r < NR; r++) {
-            const u64* lift = lift_r[r] + c * D.lift_cs + (int64_t)t * N;
 #pragma unroll
-            for (int j = 0; j < NB; j++)
-                xo[r][j] = (own_r[r] && j == jo) ? own_r[r][c * owncs_r[r] + (int64_t)t * N + src[r]]
-                                                 : lift[(int64_t)j * D.ne * N + src[r]];
-            zo[r] = with_c0 ? c0_r[r][c * c0cs_r[r] + (int64_t)t * N + src[r]] : 0;
+            for (int j = 0; j < NB; j++) xo[r][j] = at(xp[r][j], so[r]);
+            zo[r] = with_c0 ? at(zb[r], so[r]) : 0;
         }
     };
-    u64* const ub = D.u + (int64_t)sj * D.nct * D.u_cs;
-    load(0, x, z);
-    for (int c = 0; c < D.nct; c++) {
-        u64 xn[NR][NB], zn[NR];
-        if (c + 1 < D.nct) load(c + 1, xn, zn);
-        u64 v0, v1;
-        ip_reduce<NB, NR>(x, z, kb, ka, pm, with_c0, m, v0, v1);
-        u64* u = ub + c * D.u_cs;
-        if (D.accumulate) {
-            v0 = add_mod(v0, u[(int64_t)t * N + i], m.q);
-            v1 = add_mod(v1, u[((int64_t)D.ne + t) * N + i], m.q);
-        }
-        u[(int64_t)t * N + i] = v0;
-        u[((int64_t)D.ne + t) * N + i] = v1;
+    auto advance = [&]() {
 #pragma unroll
         for (int r = 0; r < NR; r++) {
-            z[r] = zn[r];
 #pragma unroll
-            for (int j = 0; j < NB; j++) x[r][j] = xn[r][j];
+            for (int j = 0; j < NB; j++) xp[r][j] += xcs[r][j];
+            if (with_c0) zb[r] += zcs[r];
         }
+    };
+    u64* u0 = D.u + (int64_t)sj * D.nct * D.u_cs + (int64_t)t * N;
+    u64* u1 = u0 + (int64_t)D.ne * N;
+    const uint32_t io = (uint32_t)i * 8u;
+    auto finish = [&](const u64(&xv)[NR][NB], const u64(&zv)[NR]) {
+        u64 v0, v1;
+        ip_reduce<NB, NR>(xv, zv, kb, ka, pm, with_c0, m, v0, v1);
+        u64* p0 = reinterpret_cast<u64*>(reinterpret_cast<char*>(u0) + io);
+        u64* p1 = reinterpret_cast<u64*>(reinterpret_cast<char*>(u1) + io);
+        if (D.accumulate) {
+            v0 = add_mod(v0, *p0, m.q);
+            v1 = add_mod(v1, *p1, m.q);
+        }
+        *p0 = v0;
+        *p1 = v1;
+        u0 += D.u_cs;
+        u1 += D.u_cs;
+    };
+    // software pipeline over the members, two register sets in turn: the next member's lift
+    // and c0 words are in flight during the current member's arithmetic
+    u64 xa[NR][NB], za[NR], xn[NR][NB], zn[NR];
+    load(xa, za);
+    advance();
+    int c = 0;
+    for (; c + 1 < D.nct; c += 2) {
+        load(xn, zn);
+        advance();
+        finish(xa, za);
+        if (c + 2 < D.nct) {
+            load(xa, za);
+            advance();
+        }
+        finish(xn, zn);
     }
+    if (c < D.nct) finish(xa, za);
 }
 
 template <int NB>

@@ -105,14 +105,16 @@ __device__ __forceinline__ void mac3(Acc3& a, Split30 x, Split30 y) {
     a.c1 += (u64)x.hi * y.lo;
     a.c2 += (u64)x.hi * y.hi;
 }
-// the 128-bit value of the column sums
+// the 128-bit value of the column sums, without carry detection: with t = c1 + (c0 >> 30) and
+// t2 = c2 + (t >> 30) the value is (c0 mod 2^30) + (t mod 2^30) 2^30 + t2 2^60, whose part
+// below t2's top bits, (t2 mod 16) 2^60 + ..., is below 2^64; so hi = t2 >> 4 and lo is the
+// value mod 2^64.  Bounds: c0, c2 < 2^63 and c1 < 2^64 - 2^35 (eight products), so t and t2
+// do not wrap.
 __device__ __forceinline__ void acc3_wide(const Acc3& a, u64& lo, u64& hi) {
-    const u64 m1 = a.c1 << 30, m2 = a.c2 << 60;
-    lo = a.c0 + m1;
-    u64 cy = lo < m1 ? 1 : 0;
-    lo += m2;
-    cy += lo < m2 ? 1 : 0;
-    hi = (a.c1 >> 34) + (a.c2 >> 4) + cy;
+    const u64 t = a.c1 + (a.c0 >> 30);
+    const u64 t2 = a.c2 + (t >> 30);
+    hi = t2 >> 4;
+    lo = a.c0 + (a.c1 << 30) + (a.c2 << 60);
 }
 __device__ __forceinline__ u64 redc3(const Acc3& a, u64 q, u64 qninv) {
     u64 lo, hi;
@@ -146,14 +148,13 @@ __device__ __forceinline__ void macs(AccS& a, int32_t lo, int32_t hi, Split30 t)
     a.c2 += (int64_t)hi * (int64_t)(int32_t)t.hi;
 }
 // V R^-1 mod q for the signed V = c0 + c1 2^30 + c2 2^60 with |V| < q 2^64, lazy in [0, 3q):
-// REDC of V + q 2^64, which lies in (0, 2q 2^64)
+// REDC of V + q 2^64, which lies in (0, 2q 2^64).  floor(V / 2^64) is t2 >> 4 (arithmetic
+// shifts, as in acc3_wide; |c1| < 7.5 2^60 keeps t in range), the low word V mod 2^64.
 __device__ __forceinline__ u64 redcs_lazy(const AccS& a, u64 q, u64 qninv) {
-    const u64 l1 = (u64)a.c1 << 30, l2 = (u64)a.c2 << 60;
-    u64 lo = (u64)a.c0 + l1;
-    u64 cy = lo < l1 ? 1 : 0;
-    lo += l2;
-    cy += lo < l2 ? 1 : 0;
-    const u64 hi = (u64)((a.c0 >> 63) + (a.c1 >> 34) + (a.c2 >> 4)) + cy + q;
+    const int64_t t = a.c1 + (a.c0 >> 30);
+    const int64_t t2 = a.c2 + (t >> 30);
+    const u64 lo = (u64)a.c0 + ((u64)a.c1 << 30) + ((u64)a.c2 << 60);
+    const u64 hi = (u64)(t2 >> 4) + q;
     const u64 m = lo * qninv;
     return hi + __umul64hi(m, q) + (lo != 0 ? 1 : 0);
 }
