@@ -13,8 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhe.so")
 SOURCES = ["kernels.hip", "he_host.hip", "group.hip", "serve.hip", "tune.hip", "graph.hip"]
 
-# Packed FP32 instructions are disabled for all device code; no kernel here uses
-# floating point, the flag keeps the compiler from emitting them anyway.
+# Packed FP32 instructions are disabled for all device code: the kernels compute in 64-bit
+# integers and FP64 only, and the flag keeps the compiler from ever emitting packed FP32.
 HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

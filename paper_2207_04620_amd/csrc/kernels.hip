@@ -375,12 +375,17 @@ __device__ __forceinline__ void inv_row_round(u64* s, const u64* __restrict__ tw
 // last round's groups (forward: elements 4 g + k; inverse: g + 512 k, for g = tid and
 // 256 + tid) go back to the caller, which stores them with its epilogue.  Two LDS round
 // trips and two barriers fewer than staging the whole row through LDS.
-__device__ __forceinline__ void fwd_rows_2048(u64* s, const u64* tw, u64 q, u64 (&x)[8], u64 (&y)[8]) {
+// after_first() runs once the first round's results are in LDS: the lane's registers of the
+// first round are free there, so the caller can start its epilogue loads early
+template <class F>
+__device__ __forceinline__ void fwd_rows_2048(u64* s, const u64* tw, u64 q, u64 (&x)[8], u64 (&y)[8],
+                                              F&& after_first) {
     const int tid = threadIdx.x;
     fwd_group<3>(x, tw, q);
     u64* sb = s + tid + (tid >> 5);
 #pragma unroll
     for (int k = 0; k < 8; ++k) sb[264 * k] = x[k];
+    after_first();
     __syncthreads();
     fwd_row_round<3, 3>(s, tw, 7, q);
     __syncthreads();
@@ -667,13 +672,15 @@ __device__ __forceinline__ void inv_row_round_d(double* s, const double* __restr
 }
 
 // register-first and register-last row passes, as the integer ones above
+template <class F>
 __device__ __forceinline__ void fwd_rows_2048_d(double* s, const double* tw, double q, double (&x)[8],
-                                                double (&y)[8]) {
+                                                double (&y)[8], F&& after_first) {
     const int tid = threadIdx.x;
     fwd_group_d<3>(x, tw, q);
     double* sb = s + tid + (tid >> 5);
 #pragma unroll
     for (int k = 0; k < 8; ++k) sb[264 * k] = x[k];
+    after_first();
     __syncthreads();
     fwd_row_round_d<3, 3>(s, tw, 7, q);
     __syncthreads();
@@ -870,7 +877,7 @@ __device__ __forceinline__ int perm_g(int j, u64 g, int log_n);
 // EPI: the ModDown epilogue (E.on) is compiled in; without it the plain transform keeps its
 // smaller register footprint
 template <bool EPI>
-__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E) {
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(6))) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E) {
     __shared__ u64 s[NTT_LDS];
     const int N = 1 << T.log_n, L1 = T.n1_log, L2 = T.n2_log, N1 = 1 << L1, N2 = 1 << L2;
     const int job = blockIdx.y, c = job / J.n, k = job % J.n;
@@ -882,6 +889,19 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
     // 2048-element rows: the last round's elements 4 g + k (g = tid, 256 + tid) as words,
     // canonical (FP64 path) or lazy in [0, 4q) (integer path)
     u64 y[8];
+    // the ModDown epilogue's u words of those elements, loaded while the middle rounds run
+    u64x2 uu[4];
+    const u64* u = nullptr;
+    if constexpr (EPI) {
+        const int p = J.off[k] / E.nl, t = J.off[k] % E.nl;
+        u = E.u + c * E.u_cs + p * E.u_ps + (int64_t)t * N;
+    }
+    auto prefetch_u = [&]() {
+        if constexpr (EPI) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) uu[i] = ld2(u + r * N2 + 4 * ((i >> 1) * TPB + tid) + 2 * (i & 1));
+        }
+    };
     if (fp) {
         const double qd = (double)q, qinv = 1.0 / qd;
         double x[8], yd[8];
@@ -890,14 +910,15 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
             const u64 v = a[tid + TPB * i];
             x[i] = L1 ? bits_d(v) : u2d(v);
         }
-        fwd_rows_2048_d(reinterpret_cast<double*>(s), T.rtwd + ((int64_t)mi * N1 + r) * (2 * ROW_TW), qd, x, yd);
+        fwd_rows_2048_d(reinterpret_cast<double*>(s), T.rtwd + ((int64_t)mi * N1 + r) * (2 * ROW_TW), qd, x, yd,
+                        prefetch_u);
 #pragma unroll
         for (int i = 0; i < 8; ++i) y[i] = canon_d(yd[i], qd, qinv);
     } else if (full) {
         u64 x[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) x[i] = a[tid + TPB * i];
-        fwd_rows_2048(s, T.rtw + ((int64_t)mi * N1 + r) * (2 * ROW_TW), q, x, y);
+        fwd_rows_2048(s, T.rtw + ((int64_t)mi * N1 + r) * (2 * ROW_TW), q, x, y, prefetch_u);
     } else {  // small rings (N < 2048): the row through LDS, plain radix-2 stages
         const u64* W = T.psi + (int64_t)mi * N;
         const u64* Ws = T.psi_sh + (int64_t)mi * N;
@@ -921,17 +942,18 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
             __syncthreads();
         }
     }
-    // emit(e, v0, v1): elements e, e + 1 of the row (words below 4q) to their destination
+    // emit(i, e, v0, v1): elements e, e + 1 of the row (words below 4q) to their destination;
+    // i is the pair's slot in uu (2048-element rows), or -1
     auto for_pairs = [&](auto&& emit) {
         if (fp || full) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) emit(4 * ((i >> 1) * TPB + tid) + 2 * (i & 1), y[2 * i], y[2 * i + 1]);
+            for (int i = 0; i < 4; ++i) emit(i, 4 * ((i >> 1) * TPB + tid) + 2 * (i & 1), y[2 * i], y[2 * i + 1]);
         } else {
-            for (int e = 2 * tid; e < N2; e += 2 * TPB) emit(e, s[lds_at<true>(e)], s[lds_at<true>(e + 1)]);
+            for (int e = 2 * tid; e < N2; e += 2 * TPB) emit(-1, e, s[lds_at<true>(e)], s[lds_at<true>(e + 1)]);
         }
     };
     if constexpr (!EPI) {
-        for_pairs([&](int e, u64 v0, u64 v1) {
+        for_pairs([&](int, int e, u64 v0, u64 v1) {
             if (!fp) {
                 v0 = red4(v0, q2);
                 v1 = red4(v1, q2);
@@ -943,19 +965,18 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
         return;
     }
     const int p = J.off[k] / E.nl, t = J.off[k] % E.nl;
-    const u64* u = E.u + c * E.u_cs + p * E.u_ps + (int64_t)t * N;
     const u64* add = E.add[p] ? E.add[p] + c * E.add_cs + (int64_t)t * N : nullptr;
     u64* out = E.out[p] + c * E.out_cs + (int64_t)t * N;
     const u64 pi = E.pinv[t], pis = E.pinv_sh[t];
     const u64* mask = E.mask ? E.mask + (int64_t)t * N : nullptr;
     const u64* acc = E.acc[p] ? E.acc[p] + c * E.acc_cs + (int64_t)t * N : nullptr;
     const u64 qninv = T.mods[mi].qninv;
-    for_pairs([&](int e, u64 v0, u64 v1) {
+    for_pairs([&](int slot, int e, u64 v0, u64 v1) {
         const int i = r * N2 + e;
-        const u64x2 uu = ld2(u + i);
+        const u64x2 uw = slot >= 0 ? uu[slot] : ld2(u + i);
         // v is below 4q and u < q, so u + 4q - v lies in (0, 5q); the Shoup product
         // reduces any 64-bit operand to [0, q)
-        u64 w[2] = {mul_shoup(uu.x + 2 * q2 - v0, pi, pis, q), mul_shoup(uu.y + 2 * q2 - v1, pi, pis, q)};
+        u64 w[2] = {mul_shoup(uw.x + 2 * q2 - v0, pi, pis, q), mul_shoup(uw.y + 2 * q2 - v1, pi, pis, q)};
         if (add) {
             if (E.g == 1) {
                 const u64x2 ad = ld2(add + i);
