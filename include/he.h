@@ -208,6 +208,12 @@ void he_graph_destroy(he_graph *graph);
 typedef struct {
     uint32_t h, t, beta;
 } he_mat_shape;
+/* The packing iota_beta itself (App. E), a host-side layout step before he_encrypt: mats[m]
+ * points to matrix m's n entries in row-major order (n = h h, or t h for the row-block operand),
+ * m < beta; out (beta n doubles, caller-owned) receives entry e of matrix m at position
+ * beta e + m.  Host memory only, no device work.  HE_EINVAL on null pointers, beta = 0 or
+ * n = 0. */
+he_status he_pack_beta(size_t beta, size_t n, const double *const *mats, double *out);
 he_status he_matmul_ex(he_ctx *ctx, const he_ct *a, const he_ct *b, const he_mat_shape *shape, he_ct **out);
 /* n products of mixed shapes and levels, grouped by (shape, level) into lockstep groups;
  * bit-identical to he_matmul_ex on each pair */

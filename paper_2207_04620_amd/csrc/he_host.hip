@@ -1182,6 +1182,16 @@ he_ct* wrap(Ctx* c, CtPtr p) { return new he_ct{c, std::move(p)}; }
 
 extern "C" {
 
+// iota_beta (App. E): entry e of matrix m at position beta e + m
+he_status he_pack_beta(size_t beta, size_t n, const double* const* mats, double* out) {
+    if (!mats || !out || beta == 0 || n == 0) return HE_EINVAL;
+    for (size_t m = 0; m < beta; ++m)
+        if (!mats[m]) return HE_EINVAL;
+    for (size_t e = 0; e < n; ++e)
+        for (size_t m = 0; m < beta; ++m) out[beta * e + m] = mats[m][e];
+    return HE_OK;
+}
+
 // ====================================================================== allocation-free rotation
 // Scratch of he_rotate_noalloc: file-scope device memory, one copy on every device the library
 // runs on, held until the process ends.  Host code never passes the array's name to a kernel or

@@ -138,6 +138,7 @@ SIGNATURES = {
                               C.c_char_p, C.c_size_t]),
     "he_rotate_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_int64, C.c_void_p]),
     "he_pool_limit": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "he_pack_beta": (C.c_int, [C.c_size_t, C.c_size_t, C.c_void_p, C.POINTER(C.c_double)]),
     "he_pool_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.c_int]),
 }
 
@@ -211,12 +212,14 @@ class _MatShape(C.Structure):
 
 def pack_beta(mats):
     """the packing iota_beta (App. E) as a slot vector: matrix m's entry (i, j) at
-    position beta (h i + j) + m"""
-    mats = [np.asarray(m, np.float64) for m in mats]
-    beta = len(mats)
-    v = np.empty(beta * mats[0].size)
-    for m, M in enumerate(mats):
-        v[m::beta] = M.ravel()
+    position beta (h i + j) + m (he_pack_beta)"""
+    mats = [np.ascontiguousarray(np.asarray(m, np.float64).ravel()) for m in mats]
+    beta, n = len(mats), mats[0].size
+    if any(m.size != n for m in mats):
+        raise ValueError("pack_beta: matrices of different sizes")
+    ptrs = (C.POINTER(C.c_double) * beta)(*[m.ctypes.data_as(C.POINTER(C.c_double)) for m in mats])
+    v = np.empty(beta * n)
+    _chk(lib().he_pack_beta(beta, n, ptrs, v.ctypes.data_as(C.POINTER(C.c_double))), "he_pack_beta")
     return v
 
 

@@ -60,3 +60,24 @@ def test_oracle_and_library_share_no_code():
         assert "import oracle" not in txt and "from oracle" not in txt
     otxt = open(os.path.join(ROOT, "oracle", "ckks_oracle.c")).read()
     assert "he_internal" not in otxt and "modarith" not in otxt
+
+
+def test_pack_beta_layout(libpath):
+    """he_pack_beta (host memory only, App. E's iota_beta): entry (i, j) of matrix m at slot
+    beta (h i + j) + m, against the layout written out index by index; and its argument checks"""
+    import numpy as np
+    from paper_2207_04620_amd import he
+    rng = np.random.default_rng(5)
+    for beta, h, t in ((1, 4, 4), (2, 4, 4), (4, 8, 2)):
+        mats = [rng.standard_normal((t, h)) for _ in range(beta)]
+        v = he.pack_beta(mats)
+        want = np.empty(beta * t * h)
+        for m in range(beta):
+            for i in range(t):
+                for j in range(h):
+                    want[beta * (h * i + j) + m] = mats[m][i, j]
+        assert np.array_equal(v, want)
+    import ctypes as C
+    out = (C.c_double * 4)()
+    assert he.lib().he_pack_beta(0, 4, None, out) == 1
+    assert he.lib().he_pack_beta(1, 4, None, out) == 1
