@@ -1834,23 +1834,35 @@ __global__ __launch_bounds__(TPB) void k_inner_product(DevTables T, IpDesc D) {
         u0 += D.u_cs;
         u1 += D.u_cs;
     };
-    // software pipeline over the members, two register sets in turn: the next member's lift
-    // and c0 words are in flight during the current member's arithmetic
-    u64 xa[NR][NB], za[NR], xn[NR][NB], zn[NR];
-    load(xa, za);
+    // software pipeline over the members, three register sets in turn: the lift and c0 words
+    // of the next two members are in flight during the current member's arithmetic (one
+    // member's arithmetic is shorter than a load's latency under full bandwidth)
+    u64 x0[NR][NB], z0[NR], x1[NR][NB], z1[NR], x2[NR][NB], z2[NR];
+    load(x0, z0);
     advance();
-    int c = 0;
-    for (; c + 1 < D.nct; c += 2) {
-        load(xn, zn);
+    if (D.nct > 1) {
+        load(x1, z1);
         advance();
-        finish(xa, za);
+    }
+    for (int c = 0; c < D.nct; c += 3) {
         if (c + 2 < D.nct) {
-            load(xa, za);
+            load(x2, z2);
             advance();
         }
-        finish(xn, zn);
+        finish(x0, z0);
+        if (c + 1 >= D.nct) break;
+        if (c + 3 < D.nct) {
+            load(x0, z0);
+            advance();
+        }
+        finish(x1, z1);
+        if (c + 2 >= D.nct) break;
+        if (c + 4 < D.nct) {
+            load(x1, z1);
+            advance();
+        }
+        finish(x2, z2);
     }
-    if (c < D.nct) finish(xa, za);
 }
 
 template <int NB>
