@@ -100,13 +100,15 @@ def _median3(fn):
 
 
 def cpu_baseline(prm, flags):
-    """The oracle (plain scalar C, OpenMP over limbs) on the host, at one thread and at every
-    usable thread.  Bounded sample of the h=64 product itself: each operation the product
-    performs, timed on the N=2^15 ring at the level where the product spends its work (level
-    12: Steps 2-3 after Step 1's rescale), median of three runs; the product's time is the
-    sum of these times weighted by the operation counts of one h=64 product under the same
-    schedule (counted exactly by running the oracle's product on a 2^13 ring, where the
-    counts are the same).  A directly timed h=16 product at every thread checks the model."""
+    """The oracle (plain scalar C, OpenMP over limbs) on the host, as it stands.  Bounded sample:
+    the benchmark's own unit, one C3 h=64 product from level 13 under the same schedule, timed
+    directly three times at every usable thread (median; the rotation keys and masks come from
+    an untimed first product).  Beside it, one directly timed C3 product for h = 16 and 32 and
+    one C2 h=64 product, and a one-thread figure from an operation-level model: each operation
+    the product performs, timed on the N=2^15 ring at level 12 (median of three, at one thread
+    and at every thread), weighted by the product's operation counts under the same schedule
+    (counted exactly by running the oracle's product on a 2^13 ring, where the counts are the
+    same); the all-thread model against the direct timing checks the model."""
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as O
     from paper_2207_04620_amd import inputs as I
@@ -114,15 +116,30 @@ def cpu_baseline(prm, flags):
     host = host_cpu()
     nthr = host["usable_threads"]
 
-    def counts(h):
-        c = O.Ctx(13, [50, 40, 40, 40, 40], [50, 50], 2, 40.0, 7, threads=nthr)
+    def direct(p, h, reps):
+        o = O.Ctx.from_params(p, threads=nthr)
         A, B = I.matrix_pair(3, h)
-        a, b = c.encrypt(A.ravel(), nonce=1), c.encrypt(B.ravel(), nonce=2)
-        c.reset_counters()
-        c.matmul(a, b, h, flags)
-        return c.counters()
+        a, b = o.encrypt(A.ravel(), nonce=1), o.encrypt(B.ravel(), nonce=2)
+        o.matmul(a, b, h, flags)  # rotation keys and masks for h (not timed)
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            o.matmul(a, b, h, flags)
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[len(ts) // 2]
 
-    cnt64, cnt16 = counts(64), counts(16)
+    log("cpu baseline: C3 h=64 products on the oracle")
+    t64 = direct(prm, 64, 3)
+    per_h = {"16": round(direct(prm, 16, 1), 3), "32": round(direct(prm, 32, 1), 3), "64": round(t64, 3)}
+    log("cpu baseline: C2 h=64 product")
+    c2_64 = direct(I.C2, 64, 1)
+
+    c = O.Ctx(13, [50, 40, 40, 40, 40], [50, 50], 2, 40.0, 7, threads=nthr)
+    A, B = I.matrix_pair(3, 64)
+    a, b = c.encrypt(A.ravel(), nonce=1), c.encrypt(B.ravel(), nonce=2)
+    c.reset_counters()
+    c.matmul(a, b, 64, flags)
+    cnt = c.counters()
 
     def op_times(threads):
         o = O.Ctx.from_params(prm, threads=threads)
@@ -140,32 +157,26 @@ def cpu_baseline(prm, flags):
                 "add": _median3(lambda: o.add(a, b)),
                 "rescale": _median3(lambda: o.rescale(a))}
 
-    def model(cnt, t):
+    def model(t):
         relins = cnt["keyswitch"] - cnt["rot"] if cnt["keyswitch"] >= cnt["rot"] else cnt["mul_ct"]
         return (cnt["rot"] * t["rot"] + max(0, relins) * t["relin"] + cnt["mul_pt"] * t["mul_pt"] +
                 cnt["mul_ct"] * t["mul_ct"] + cnt["add"] * t["add"] + cnt["rescale"] * t["rescale"])
 
-    t_all = op_times(nthr)
-    t_one = op_times(1)
-    est_all, est_one = model(cnt64, t_all), model(cnt64, t_one)
-    # check: one h=16 product timed directly at every thread against the model's h=16 figure
-    o = O.Ctx.from_params(prm, threads=nthr)
-    A, B = I.matrix_pair(3, 16)
-    a, b = o.encrypt(A.ravel(), nonce=1), o.encrypt(B.ravel(), nonce=2)
-    o.matmul(a, b, 16, flags)  # keys and masks for h=16 (not timed)
-    t0 = time.perf_counter()
-    o.matmul(a, b, 16, flags)
-    direct16 = time.perf_counter() - t0
-    return {"value": round(1.0 / est_all, 5), "unit": "HE-matmuls/s", "cores": nthr, "kind": "oracle",
+    log("cpu baseline: operation-level model at one thread")
+    t_all, t_one = op_times(nthr), op_times(1)
+    est_all, est_one = model(t_all), model(t_one)
+    return {"value": round(1.0 / t64, 5), "unit": "HE-matmuls/s", "cores": nthr, "kind": "oracle",
+            "sample": f"one C3 h=64 product from level 13 under the same schedule, timed directly three times at "
+                      f"{nthr} threads (median); keys and masks from an untimed first product",
+            "h64_seconds": round(t64, 3), "c3_seconds_by_h": per_h, "c2_h64_seconds": round(c2_64, 3),
             "value_1_thread": round(1.0 / est_one, 6), **host,
-            "sample": "each operation of the h=64 product timed on the N=2^15 ring at level 12 (median of 3, at "
-                      f"{nthr} threads and at 1 thread), weighted by the product's operation counts under the same "
-                      f"schedule ({cnt64['rot']} rotations, {cnt64['keyswitch']} key switches, {cnt64['mul_pt']} "
-                      f"Mul_pt, {cnt64['mul_ct']} Mul_ct, {cnt64['rescale']} rescales)",
-            "op_seconds_all_threads": {k: round(v, 4) for k, v in t_all.items()},
-            "op_seconds_1_thread": {k: round(v, 4) for k, v in t_one.items()},
-            "h64_seconds_all_threads": round(est_all, 2), "h64_seconds_1_thread": round(est_one, 2),
-            "check_h16": {"direct_seconds": round(direct16, 2), "model_seconds": round(model(cnt16, t_all), 2)}}
+            "model": {"note": "each operation of the h=64 product timed on the N=2^15 ring at level 12 (median of "
+                              f"3), weighted by the product's operation counts ({cnt['rot']} rotations, "
+                              f"{cnt['keyswitch']} key switches, {cnt['mul_pt']} Mul_pt, {cnt['mul_ct']} Mul_ct, "
+                              f"{cnt['rescale']} rescales)",
+                      "h64_seconds_all_threads": round(est_all, 2), "h64_seconds_1_thread": round(est_one, 2),
+                      "op_seconds_all_threads": {k: round(v, 4) for k, v in t_all.items()},
+                      "op_seconds_1_thread": {k: round(v, 4) for k, v in t_one.items()}}}
 
 
 def mixed_leg(he, I, prm, sched, stream, count):
