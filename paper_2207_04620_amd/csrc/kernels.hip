@@ -880,7 +880,9 @@ template <bool EPI>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(6))) void k_ntt_fwd_rows(DevTables T, Jobs J, Epi E) {
     __shared__ u64 s[NTT_LDS];
     const int N = 1 << T.log_n, L1 = T.n1_log, L2 = T.n2_log, N1 = 1 << L1, N2 = 1 << L2;
-    const int job = blockIdx.y, c = job / J.n, k = job % J.n;
+    // jobs in reverse order: the column pass before it wrote the last jobs last, so their limbs
+    // are the likeliest to still be in the memory-side cache
+    const int job = (int)gridDim.y - 1 - (int)blockIdx.y, c = job / J.n, k = job % J.n;
     const int r = blockIdx.x, tid = threadIdx.x;
     u64* a = J.base + c * J.cstride + (int64_t)J.off[k] * N + (int64_t)r * N2;
     const int mi = J.mod[k];
