@@ -229,19 +229,23 @@ he_status he_transpose_batch(he_ctx *ctx, size_t n, const he_ct *const *a, uint3
 
 /* Scheduling knobs of the lockstep products; results never depend on them.  pair_batch:
  * rotation sets (Step-2 mask pairs, baby rotations) that share one key-switch inner-product
- * launch and one ModDown launch (1..16); max_group: members per lockstep group (1..256). */
+ * launch and one ModDown launch (1..16); max_group: members per lockstep group (1..256);
+ * overlap (0 or 1): the next Step-2 pair group's inner products run on the context's second
+ * stream while the current group's ModDown runs on the context stream. */
 typedef struct {
     uint32_t pair_batch;
     uint32_t max_group;
+    uint32_t overlap;
 } he_tuning;
 he_status he_tuning_get(const he_ctx *ctx, he_tuning *out);
 he_status he_tuning_set(he_ctx *ctx, const he_tuning *t);
 /* Autotuner: times he_matmul_batch of 'batch' h x h pairs at 'level' on the device under each
- * candidate (pair_batch 1, 2, 4, 8; max_group = batch, and batch / 2 when batch >= 16; the best
- * of two timed runs each after a warm-up), applies the fastest to the context (a later candidate
- * must be 1 % faster to displace an earlier one) and caches it per (N, limbs, alpha, schedule, h,
- * level, batch, device) in the process and, when cache_path is set, in that text file (a line
- * already there is used without timing).  report: optional JSON of the candidates' times and the
+ * candidate (pair_batch 1, 2, 4, 8; max_group = batch, and batch / 2 when batch >= 16; then
+ * overlap off against on for the best of those; the best of two timed runs each after a
+ * warm-up), applies the fastest to the context (a later candidate must be 1 % faster to displace
+ * an earlier one) and caches it per (N, limbs, alpha, schedule, h, level, batch, device) in the
+ * process and, when cache_path is set, in that text file (a line already there is used without
+ * timing).  report: optional JSON of the candidates' times and the
  * choice, truncated to report_n bytes.  HE_ESHAPE / HE_ELEVEL as for he_matmul.  Synchronizes. */
 he_status he_autotune(he_ctx *ctx, uint32_t h, uint32_t level, uint32_t batch, const char *cache_path,
                       he_tuning *out, char *report, size_t report_n);

@@ -71,6 +71,13 @@ he_status he_matmul_batch_capture(he_ctx* ctx, size_t n, const he_ct* const* a, 
                 }
             }
         } end{c, g};
+        // the capture records the context stream alone: no side-stream overlap inside the graph
+        struct NoOverlap {
+            Ctx* c;
+            int saved;
+            ~NoOverlap() { c->overlap = saved; }
+        } no_overlap{c, c->overlap};
+        c->overlap = 0;
         hip_check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed), "begin capture");
         res = c->matmul_batch(va, vb, sh);
         end.open = false;

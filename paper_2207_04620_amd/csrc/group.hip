@@ -340,33 +340,48 @@ void Ctx::g_ks_apply(const u64* lift, int B, int level, const u64* key, u64 g, c
 // slice of one extended-basis buffer (one launch: the sets' gathers of the shared lift meet
 // in L2), and a single ModDown then serves all sets, so its transforms and conversion run as
 // one launch over nset x B members; the results are views into one block
-std::vector<Grp> Ctx::g_rotate_sets_hoisted(const Grp& a, const u64* lift, const std::vector<IpSet>& sets,
-                                            int nrot, double mask_scale) {
+Ctx::PendingSets Ctx::g_sets_ip(const Grp& a, const u64* lift, const std::vector<IpSet>& sets, int nrot,
+                                double mask_scale) {
     const int P = (int)sets.size(), B = a.B, ne = a.level + 1 + n_p;
     if (a.deg != 1) throw HeError(HE_EMISMATCH);
-    std::vector<double> sc;
+    PendingSets ps;
     for (int j = 0; j < P; ++j)
-        for (double v : a.scale) sc.push_back(v * mask_scale);
-    Grp out = g_new(P * B, a.level, 1, sc);
-    const int64_t ucs = 2 * (int64_t)ne * N;
-    DBuf u(this, (size_t)P * B * ucs);
-    g_ks_inner_sets(u.p, lift, B, a.level, sets, nrot, a.p, a.cs, false);
-    g_moddown(u.p, P * B, a.level, nullptr, nullptr, 0, out.p, out.p + out.ps, out.cs, 1, nullptr, nullptr, nullptr,
-              0);
+        for (double v : a.scale) ps.sc.push_back(v * mask_scale);
+    ps.out = g_new(P * B, a.level, 1, ps.sc);
+    ps.u = std::make_shared<DBuf>(this, (size_t)P * B * 2 * ne * N);
+    ps.P = P;
+    ps.B = B;
+    ps.level = a.level;
+    g_ks_inner_sets(ps.u->p, lift, B, a.level, sets, nrot, a.p, a.cs, false);
+    return ps;
+}
+
+std::vector<Grp> Ctx::g_sets_finish(PendingSets& ps) {
+    const int P = ps.P, B = ps.B;
+    Grp& out = ps.out;
+    g_moddown(ps.u->p, P * B, ps.level, nullptr, nullptr, 0, out.p, out.p + out.ps, out.cs, 1, nullptr, nullptr,
+              nullptr, 0);
+    ps.u.reset();
     std::vector<Grp> res(P);
     for (int j = 0; j < P; ++j) {
         res[j] = out;
         res[j].B = B;
         res[j].p = out.p + (size_t)j * B * out.cs;
-        res[j].scale.assign(sc.begin() + (size_t)j * B, sc.begin() + (size_t)(j + 1) * B);
+        res[j].scale.assign(ps.sc.begin() + (size_t)j * B, ps.sc.begin() + (size_t)(j + 1) * B);
     }
     return res;
 }
 
+std::vector<Grp> Ctx::g_rotate_sets_hoisted(const Grp& a, const u64* lift, const std::vector<IpSet>& sets,
+                                            int nrot, double mask_scale) {
+    PendingSets ps = g_sets_ip(a, lift, sets, nrot, mask_scale);
+    return g_sets_finish(ps);
+}
+
 // Several mask pairs of one ciphertext at once (Step 2 under the hoisted-ModDown schedule):
-// mask1 . Rot(a, k1) + mask2 . Rot(a, k2) for every pair, with one shared ModDown
-std::vector<Grp> Ctx::g_rotate_pairs_hoisted(const Grp& a, const u64* lift, const std::vector<MaskPair>& pr,
-                                             double mask_scale) {
+// mask1 . Rot(a, k1) + mask2 . Rot(a, k2) for every pair, with one shared ModDown; the inner
+// products here, the ModDown by g_sets_finish
+Ctx::PendingSets Ctx::g_pairs_ip(const Grp& a, const u64* lift, const std::vector<MaskPair>& pr, double mask_scale) {
     const int P = (int)pr.size(), B = a.B;
     std::vector<IpSet> sets(P);
     for (int j = 0; j < P; ++j) {
@@ -380,11 +395,17 @@ std::vector<Grp> Ctx::g_rotate_pairs_hoisted(const Grp& a, const u64* lift, cons
         sets[j].g2 = g2;
         sets[j].mask2 = pr[j].m2;
     }
-    auto res = g_rotate_sets_hoisted(a, lift, sets, 2, mask_scale);
+    PendingSets ps = g_sets_ip(a, lift, sets, 2, mask_scale);
     cnt[C_ROT] += 2 * P * B;
     cnt[C_MULPT] += 2 * P * B;
     cnt[C_ADD] += P * B;
-    return res;
+    return ps;
+}
+
+std::vector<Grp> Ctx::g_rotate_pairs_hoisted(const Grp& a, const u64* lift, const std::vector<MaskPair>& pr,
+                                             double mask_scale) {
+    PendingSets ps = g_pairs_ip(a, lift, pr, mask_scale);
+    return g_sets_finish(ps);
 }
 
 // Rot(a, k) for several k of one lift, with one shared ModDown (Step 3's baby rotations
@@ -773,9 +794,29 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
         const bool keep_baby = bg < t;
         if (keep_baby && J.babyB.empty()) J.babyB.resize(bg);
         const int kend = std::min(t, J.k + std::max(1, k_chunk));
-        // hoisted schedule: the mask pairs of up to pair_batch consecutive k share one ModDown
+        // hoisted schedule: the mask pairs of up to pair_batch consecutive k share one ModDown;
+        // with overlap, the next group's inner products run on the side stream during this
+        // group's ModDown (within this chunk of rounds only)
         std::vector<Grp> pairs, babies;
         int pairs_k0 = 0, babies_j0 = 0;
+        auto pair_group = [&](int k0) {
+            std::vector<MaskPair> pr;
+            for (int kk = k0; kk < std::min(kend, k0 + std::max(1, pair_batch)); ++kk) {
+                const int64_t sh = (int64_t)h * bg * (kk / bg);
+                pr.push_back({beta * (kk - sh), mask(2, h, kk, -sh, beta), beta * (kk - h - sh),
+                              mask(3, h, kk, -sh, beta)});
+            }
+            return pr;
+        };
+        PendingSets next;
+        int next_k0 = -1;
+        struct SideJoin {  // side-stream work still queued (an error path) ends before its buffers go
+            Ctx* c;
+            const int* pending;
+            ~SideJoin() {
+                if (*pending >= 0) (void)hipStreamSynchronize(c->side);
+            }
+        } side_join{this, &next_k0};
         for (int k = J.k; k < kend; ++k) {
             const int i = k / bg, j = k % bg;
             const int64_t shift = (int64_t)h * bg * i;
@@ -784,13 +825,33 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
                 Ak = g_mask_sum({{&J.A0, mask(2, h, 0, 0, beta)}}, ms);
             } else if (hoist) {
                 if (pairs.empty() || k - pairs_k0 >= (int)pairs.size()) {
-                    std::vector<MaskPair> pr;
-                    for (int kk = k; kk < std::min(kend, k + std::max(1, pair_batch)); ++kk) {
-                        const int64_t sh = (int64_t)h * bg * (kk / bg);
-                        pr.push_back({beta * (kk - sh), mask(2, h, kk, -sh, beta), beta * (kk - h - sh),
-                                      mask(3, h, kk, -sh, beta)});
+                    PendingSets cur;
+                    if (next_k0 == k) {  // issued on the side stream: join it
+                        hip_check(hipStreamWaitEvent(stream, ev_join, 0), "join side stream");
+                        cur = std::move(next);
+                        next = PendingSets();
+                        next_k0 = -1;
+                    } else {
+                        cur = g_pairs_ip(J.A0, J.liftA->p, pair_group(k), ms);
                     }
-                    pairs = g_rotate_pairs_hoisted(J.A0, J.liftA->p, pr, ms);
+                    const int k1 = k + cur.P;
+                    if (overlap && side && k1 < kend) {
+                        std::vector<MaskPair> pr = pair_group(k1);  // masks on the context stream
+                        hip_check(hipEventRecord(ev_fork, stream), "fork side stream");
+                        hip_check(hipStreamWaitEvent(side, ev_fork, 0), "fork side stream");
+                        hipStream_t main_stream = stream;
+                        stream = side;
+                        try {
+                            next = g_pairs_ip(J.A0, J.liftA->p, pr, ms);
+                            next_k0 = k1;
+                            hip_check(hipEventRecord(ev_join, side), "side stream done");
+                        } catch (...) {
+                            stream = main_stream;
+                            throw;
+                        }
+                        stream = main_stream;
+                    }
+                    pairs = g_sets_finish(cur);
                     pairs_k0 = k;
                 }
                 Ak = pairs[k - pairs_k0];

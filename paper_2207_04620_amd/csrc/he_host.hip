@@ -1246,6 +1246,10 @@ he_status he_ctx_create(const he_params* prm, const he_device* dev, he_ctx** out
             hip_check(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "stream");
             c->own_stream = true;
         }
+        // the side stream (default priority) and its fork/join events
+        hip_check(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "side stream");
+        hip_check(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "fork event");
+        hip_check(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "join event");
         std::vector<uint32_t> qb(prm->q_bits, prm->q_bits + prm->n_q), pb(prm->p_bits, prm->p_bits + prm->n_p);
         gen_primes(c->log_n, qb, c->mods);
         gen_primes(c->log_n, pb, c->mods);
@@ -1266,6 +1270,7 @@ void he_ctx_destroy(he_ctx* ctx) {
     if (!ctx) return;
     try {
         (void)hipStreamSynchronize(ctx->c->stream);
+        if (ctx->c->side) (void)hipStreamSynchronize(ctx->c->side);
         ctx->c->release_all();
         if (ctx->c->own_stream) (void)hipStreamDestroy(ctx->c->stream);
     } catch (...) {

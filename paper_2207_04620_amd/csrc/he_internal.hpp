@@ -177,6 +177,18 @@ struct Ctx {
     u64* scratch = nullptr;    // that device's copy of the allocation-free entry point's scratch
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // second stream of the context: the next Step-2 pair group's key-switch inner products
+    // run there while the current group's ModDown runs on the context stream (fork and join by
+    // the two events; every buffer it touches is allocated after the fork and released only
+    // after the join, so the allocation cache stays ordered by the context stream)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    ~Ctx() {
+        if (side) (void)hipStreamSynchronize(side);
+        if (side) (void)hipStreamDestroy(side);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+    }
     Pool pool;
     hm::Encoder enc;
     std::vector<u64> mods, roots, pmod;
@@ -246,6 +258,7 @@ struct Ctx {
     std::vector<CtPtr> transpose_batch(const std::vector<const CtData*>& X, int h, int beta);
     int max_group = 32;
     int pair_batch = 4;  // Step-2 mask pairs per shared ModDown launch
+    int overlap = 0;     // Step-2 pair groups pipelined over the two streams (measured slower: off)
     // a group lift holds only the converted limbs of each digit; its own limbs are read from the
     // lifted polynomial: lift buffer -> (that polynomial of member 0, member stride)
     std::unordered_map<const u64*, std::pair<const u64*, int64_t>> lift_own;
@@ -268,6 +281,17 @@ struct Ctx {
                    int64_t acc_cs);
     std::vector<Grp> g_rotate_sets_hoisted(const Grp& a, const u64* lift, const std::vector<IpSet>& sets, int nrot,
                                            double mask_scale);
+    // the two halves of g_rotate_sets_hoisted: the inner products of every set (on the stream
+    // current in the context), then the shared ModDown
+    struct PendingSets {
+        Grp out;
+        std::shared_ptr<DBuf> u;
+        std::vector<double> sc;
+        int P = 0, B = 0, level = 0;
+    };
+    PendingSets g_sets_ip(const Grp& a, const u64* lift, const std::vector<IpSet>& sets, int nrot, double mask_scale);
+    std::vector<Grp> g_sets_finish(PendingSets& ps);
+    PendingSets g_pairs_ip(const Grp& a, const u64* lift, const std::vector<MaskPair>& pr, double mask_scale);
     std::vector<Grp> g_rotate_many_hoisted(const Grp& a, const u64* lift, const std::vector<int64_t>& ks);
     std::vector<Grp> g_rotate_pairs_hoisted(const Grp& a, const u64* lift, const std::vector<MaskPair>& pr,
                                             double mask_scale);

@@ -1,10 +1,11 @@
 // Autotuner of the batched product's scheduling knobs.
 //
-// Two knobs shape the launches of a lockstep product without changing any result: the number
+// Three knobs shape the launches of a lockstep product without changing any result: the number
 // of rotation sets that share one key-switch inner-product launch and one ModDown launch
-// (pair_batch: Step-2 mask pairs, baby rotations), and the cap on members per lockstep group
+// (pair_batch: Step-2 mask pairs, baby rotations), the cap on members per lockstep group
 // (max_group: larger groups read each key and mask once for more members; smaller ones keep
-// the working set nearer the device caches).  The tuner times the batched product of the
+// the working set nearer the device caches), and whether the next Step-2 pair group's inner
+// products overlap the current group's ModDown on a second stream (overlap).  The tuner times the batched product of the
 // requested shape on the device under each candidate, keeps the fastest, applies it to the
 // context and caches it per (ring, chain, shape, batch, device), in the process and optionally
 // in a text file.
@@ -51,10 +52,11 @@ bool file_lookup(const char* path, const std::string& key, he_tuning* t) {
     while (std::getline(f, line)) {
         std::istringstream in(line);
         std::string k;
-        unsigned pb = 0, mg = 0;
-        if ((in >> k >> pb >> mg) && k == key && pb >= 1 && mg >= 1) {
+        unsigned pb = 0, mg = 0, ov = 0;
+        if ((in >> k >> pb >> mg >> ov) && k == key && pb >= 1 && mg >= 1 && ov <= 1) {
             t->pair_batch = pb;
             t->max_group = mg;
+            t->overlap = ov;
             return true;
         }
     }
@@ -69,15 +71,18 @@ he_status he_tuning_get(const he_ctx* ctx, he_tuning* out) {
     if (!ctx || !out) return HE_EINVAL;
     out->pair_batch = (uint32_t)ctx->c->pair_batch;
     out->max_group = (uint32_t)ctx->c->max_group;
+    out->overlap = (uint32_t)ctx->c->overlap;
     return HE_OK;
 }
 
 he_status he_tuning_set(he_ctx* ctx, const he_tuning* t) {
-    if (!ctx || !t || t->pair_batch < 1 || t->pair_batch > IP_MAXSET || t->max_group < 1 || t->max_group > 256)
+    if (!ctx || !t || t->pair_batch < 1 || t->pair_batch > IP_MAXSET || t->max_group < 1 || t->max_group > 256 ||
+        t->overlap > 1)
         return HE_EINVAL;
     std::lock_guard<std::recursive_mutex> lk(ctx->c->api_mu);
     ctx->c->pair_batch = (int)t->pair_batch;
     ctx->c->max_group = (int)t->max_group;
+    ctx->c->overlap = (int)t->overlap;
     return HE_OK;
 }
 
@@ -118,46 +123,55 @@ he_status he_autotune(he_ctx* ctx, uint32_t h, uint32_t level, uint32_t batch, c
             // the context's knobs come back whatever happens to a candidate
             struct Restore {
                 Ctx* c;
-                int pb, mg;
+                int pb, mg, ov;
                 ~Restore() {
                     c->pair_batch = pb;
                     c->max_group = mg;
+                    c->overlap = ov;
                 }
-            } restore{c, c->pair_batch, c->max_group};
+            } restore{c, c->pair_batch, c->max_group, c->overlap};
             hipEvent_t e0, e1;
             hip_check(hipEventCreate(&e0), "tune event");
             hip_check(hipEventCreate(&e1), "tune event");
             double best_ms = 1e300;
             rep += ", \"candidates\": [";
             bool first = true;
+            auto time_it = [&]() {
+                c->matmul_batch(va, vb, sh);  // warm-up: the cache holds this shape's buffers
+                double ms = 1e300;
+                for (int rep_i = 0; rep_i < 2; ++rep_i) {
+                    hip_check(hipEventRecord(e0, c->stream), "tune record");
+                    c->matmul_batch(va, vb, sh);
+                    hip_check(hipEventRecord(e1, c->stream), "tune record");
+                    hip_check(hipEventSynchronize(e1), "tune sync");
+                    float t = 0;
+                    hip_check(hipEventElapsedTime(&t, e0, e1), "tune time");
+                    ms = std::min(ms, (double)t);
+                }
+                return ms;
+            };
+            auto candidate = [&](int pb, int mg, int ov) {
+                c->pair_batch = pb;
+                c->max_group = mg;
+                c->overlap = ov;
+                const double ms = time_it();
+                char buf[160];
+                snprintf(buf, sizeof buf, "%s{\"pair_batch\": %d, \"max_group\": %d, \"overlap\": %d, \"ms\": %.3f}",
+                         first ? "" : ", ", pb, mg, ov, ms);
+                rep += buf;
+                first = false;
+                // the fastest wins; a later candidate must be faster by 1 % to displace it
+                if (ms < best_ms * 0.99) {
+                    best_ms = ms;
+                    best.pair_batch = (uint32_t)pb;
+                    best.max_group = (uint32_t)mg;
+                    best.overlap = (uint32_t)ov;
+                }
+            };
             const int groups[2] = {(int)batch, (int)batch / 2};
             for (int gi = 0; gi < (batch >= 16 ? 2 : 1); ++gi)
-                for (int pb : {1, 2, 4, 8}) {
-                    c->pair_batch = pb;
-                    c->max_group = groups[gi];
-                    c->matmul_batch(va, vb, sh);  // warm-up: the cache holds this shape's buffers
-                    double ms = 1e300;
-                    for (int rep_i = 0; rep_i < 2; ++rep_i) {
-                        hip_check(hipEventRecord(e0, c->stream), "tune record");
-                        c->matmul_batch(va, vb, sh);
-                        hip_check(hipEventRecord(e1, c->stream), "tune record");
-                        hip_check(hipEventSynchronize(e1), "tune sync");
-                        float t = 0;
-                        hip_check(hipEventElapsedTime(&t, e0, e1), "tune time");
-                        ms = std::min(ms, (double)t);
-                    }
-                    char buf[128];
-                    snprintf(buf, sizeof buf, "%s{\"pair_batch\": %d, \"max_group\": %d, \"ms\": %.3f}",
-                             first ? "" : ", ", pb, groups[gi], ms);
-                    rep += buf;
-                    first = false;
-                    // the fastest wins; a later candidate must be faster by 1 % to displace it
-                    if (ms < best_ms * 0.99) {
-                        best_ms = ms;
-                        best.pair_batch = (uint32_t)pb;
-                        best.max_group = (uint32_t)groups[gi];
-                    }
-                }
+                for (int pb : {1, 2, 4, 8}) candidate(pb, groups[gi], 0);
+            candidate((int)best.pair_batch, (int)best.max_group, 1);
             rep += "]";
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
@@ -167,7 +181,7 @@ he_status he_autotune(he_ctx* ctx, uint32_t h, uint32_t level, uint32_t batch, c
         g_tune_cache[key] = best;
         if (cache_path && *cache_path) {
             std::ofstream f(cache_path, std::ios::app);
-            f << key << " " << best.pair_batch << " " << best.max_group << "\n";
+            f << key << " " << best.pair_batch << " " << best.max_group << " " << best.overlap << "\n";
         }
         rep += ", \"source\": \"timed\"";
     }
@@ -175,10 +189,11 @@ he_status he_autotune(he_ctx* ctx, uint32_t h, uint32_t level, uint32_t batch, c
         std::lock_guard<std::recursive_mutex> lk(c->api_mu);
         c->pair_batch = (int)best.pair_batch;
         c->max_group = (int)best.max_group;
+        c->overlap = (int)best.overlap;
     }
-    char buf[96];
-    snprintf(buf, sizeof buf, ", \"chosen\": {\"pair_batch\": %u, \"max_group\": %u}}", best.pair_batch,
-             best.max_group);
+    char buf[128];
+    snprintf(buf, sizeof buf, ", \"chosen\": {\"pair_batch\": %u, \"max_group\": %u, \"overlap\": %u}}",
+             best.pair_batch, best.max_group, best.overlap);
     rep += buf;
     if (report && report_n) {
         const size_t m = std::min(report_n - 1, rep.size());

@@ -20,8 +20,8 @@ def H():
 
 
 def test_tunings_do_not_change_results(H):
-    """a mixed batch (h = 8 and 16, two levels) under every pair_batch and group cap gives the
-    same residues as under the defaults"""
+    """a mixed batch (h = 8 and 16, two levels) under every pair_batch, group cap and overlap
+    setting gives the same residues as under the defaults"""
     ctx = H.Context(I.small(log_n=12, n_q=6, alpha=2, q_bits=40, p_bits=50, h_list=(8, 16)), schedule=15)
     mix = [(8, 5), (16, 5), (8, 4), (16, 5), (8, 5), (16, 4), (8, 5)]
     As, Bs = [], []
@@ -31,13 +31,16 @@ def test_tunings_do_not_change_results(H):
         Bs.append(ctx.encrypt(B.ravel(), level=lv, nonce=2 * i + 1))
     hs = [h for h, _ in mix]
     ref = [ctx.export(r) for r in ctx.matmul_batch(As, Bs, hs)]
-    for pb in (1, 2, 8, 16):
-        for mg in (1, 2, 32):
-            ctx.set_tuning(pb, mg)
-            for r, w in zip(ctx.matmul_batch(As, Bs, hs), ref):
-                assert np.array_equal(ctx.export(r), w), (pb, mg)
+    for ov in (0, 1):
+        for pb in (1, 2, 8, 16):
+            for mg in (1, 2, 32):
+                ctx.set_tuning(pb, mg, ov)
+                for r, w in zip(ctx.matmul_batch(As, Bs, hs), ref):
+                    assert np.array_equal(ctx.export(r), w), (pb, mg, ov)
     with pytest.raises(H.HEError):
         ctx.set_tuning(0, 4)
+    with pytest.raises(H.HEError):
+        ctx.set_tuning(4, 4, 2)
     ctx.close()
 
 
@@ -47,15 +50,16 @@ def test_autotune_applies_and_caches(H, tmp_path):
     rep = ctx.autotune(16, 5, 16, cache_path=path)
     assert rep["source"] == "timed"
     cands = rep["candidates"]
-    assert len(cands) == 8 and all(c["ms"] > 0 for c in cands)
+    assert len(cands) == 9 and all(c["ms"] > 0 for c in cands)
+    assert [c["overlap"] for c in cands] == [0] * 8 + [1]
     chosen = rep["chosen"]
-    assert chosen in [{"pair_batch": c["pair_batch"], "max_group": c["max_group"]} for c in cands]
+    keys = ("pair_batch", "max_group", "overlap")
+    assert chosen in [{k: c[k] for k in keys} for c in cands]
     assert ctx.tuning() == chosen
     best = min(c["ms"] for c in cands)
-    assert next(c["ms"] for c in cands if c["pair_batch"] == chosen["pair_batch"] and
-                c["max_group"] == chosen["max_group"]) <= best / 0.99 ** 8
+    assert next(c["ms"] for c in cands if all(c[k] == chosen[k] for k in keys)) <= best / 0.99 ** 9
     line = open(path).read().split()
-    assert line[0] == rep["key"] and [int(line[1]), int(line[2])] == [chosen["pair_batch"], chosen["max_group"]]
+    assert line[0] == rep["key"] and [int(x) for x in line[1:4]] == [chosen[k] for k in keys]
     # the same key again: answered from the cache without timing, and applied
     ctx.set_tuning(1, 1)
     again = ctx.autotune(16, 5, 16, cache_path=path)
