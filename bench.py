@@ -614,6 +614,7 @@ def main():
     ntt_rate = ntt_ops / (ntt_ms * 1e-3) / 1e9
     hbm = {k: round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) for k, v in prof.items()
            if k not in NTT_KERNELS and v["ms"] > 0}
+    step_bytes = sum(v["bytes"] for v in prof.values())
 
     result = {
         "metric": METRIC, "value": round(value, 4), "unit": "HE-matmuls/s", "n_gpus": 1,
@@ -641,6 +642,11 @@ def main():
                            "note": "butterfly_valu_frac: the butterflies' VALU instructions (28 per 64-bit integer "
                                    "butterfly of a 60-bit prime, 8 per FP64 butterfly of a prime below 2^46) over "
                                    "the VALU rate of 39.32 T lane-instructions/s"},
+        "step_traffic": {"algorithmic_GB": round(step_bytes / 1e9, 2),
+                         "per_product_GB": round(step_bytes / args.batch / 1e9, 3),
+                         "hbm_frac": round(step_bytes / (step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+                         "note": "every launch's algorithmic bytes (its operands read once, its results "
+                                 "written once) summed over one step, over the timed step time at 8 TB/s"},
         "kernels_note": "one untimed step with every launch timed by HIP events",
         "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
                         **({"GB/s": hbm[k]} if k in hbm else {})} for k, v in prof.items()},
