@@ -71,13 +71,17 @@ he_status he_matmul_batch_capture(he_ctx* ctx, size_t n, const he_ct* const* a, 
                 }
             }
         } end{c, g};
-        // the capture records the context stream alone: no side-stream overlap inside the graph
+        // the capture records the context stream alone: no side-stream work inside the graph
         struct NoOverlap {
             Ctx* c;
-            int saved;
-            ~NoOverlap() { c->overlap = saved; }
-        } no_overlap{c, c->overlap};
+            int saved, saved_groups;
+            ~NoOverlap() {
+                c->overlap = saved;
+                c->concurrent_groups = saved_groups;
+            }
+        } no_overlap{c, c->overlap, c->concurrent_groups};
         c->overlap = 0;
+        c->concurrent_groups = 0;
         hip_check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed), "begin capture");
         res = c->matmul_batch(va, vb, sh);
         end.open = false;

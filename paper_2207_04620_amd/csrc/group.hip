@@ -835,7 +835,7 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
                         cur = g_pairs_ip(J.A0, J.liftA->p, pair_group(k), ms);
                     }
                     const int k1 = k + cur.P;
-                    if (overlap && side && k1 < kend) {
+                    if (overlap && side && stream != side && k1 < kend) {
                         std::vector<MaskPair> pr = pair_group(k1);  // masks on the context stream
                         hip_check(hipEventRecord(ev_fork, stream), "fork side stream");
                         hip_check(hipStreamWaitEvent(side, ev_fork, 0), "fork side stream");
@@ -937,8 +937,10 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
         Grp r = g_rotate(J.acc, ((int64_t)beta * t * h) << sh);
         g_add_into(J.acc, r);
     }
-    J.result = g_scatter(J.acc);
-    J.acc = Grp();
+    if (!J.keep_acc) {
+        J.result = g_scatter(J.acc);
+        J.acc = Grp();
+    }
     J.phase = 3;
     return true;
 }
@@ -1223,17 +1225,97 @@ std::vector<CtPtr> Ctx::matmul_batch(const std::vector<const CtData*>& A, const 
     }
     for (auto& kv : groups) prepare_shape(kv.first.first);
     const size_t cap = (size_t)std::max(1, max_group);
+    struct Chunk {
+        MatShape sh;
+        int lvl;
+        std::vector<size_t> idx;
+    };
+    std::vector<Chunk> chunks;
     for (auto& kv : groups) {
         const auto& idx = kv.second;
-        for (size_t s = 0; s < idx.size(); s += cap) {
-            std::vector<const CtData*> a, b;
-            for (size_t t = s; t < std::min(idx.size(), s + cap); ++t) {
-                a.push_back(A[idx[t]]);
-                b.push_back(B[idx[t]]);
-            }
-            auto r = matmul_group(a, b, kv.first.first, kv.first.second);
-            for (size_t t = 0; t < r.size(); ++t) out[idx[s + t]] = r[t];
+        for (size_t s = 0; s < idx.size(); s += cap)
+            chunks.push_back({kv.first.first, kv.first.second,
+                              std::vector<size_t>(idx.begin() + s, idx.begin() + std::min(idx.size(), s + cap))});
+    }
+    auto run = [&](const Chunk& ch, bool keep_acc, Grp* acc) {
+        MatmulJob J;
+        for (size_t i : ch.idx) {
+            J.A.push_back(A[i]);
+            J.B.push_back(B[i]);
         }
+        J.h = ch.sh.h;
+        J.t = ch.sh.t;
+        J.beta = ch.sh.beta;
+        J.lvl = ch.lvl;
+        J.keep_acc = keep_acc;
+        while (!matmul_step(J, ch.sh.h)) {
+        }
+        if (keep_acc) *acc = J.acc;
+        else
+            for (size_t t = 0; t < J.result.size(); ++t) out[ch.idx[t]] = J.result[t];
+    };
+    if (chunks.size() < 2 || !concurrent_groups || !side) {
+        for (auto& ch : chunks) run(ch, false, nullptr);
+        return out;
+    }
+    // Groups of a mixed batch alternate between the two streams so that the small launches of
+    // different groups fill the device together.  The side stream starts after the work issued
+    // so far, takes its buffers from its own allocation cache, and leaves each group's result
+    // in that group's accumulator; after the join the context stream copies the results out
+    // (into buffers of the main cache) and the side cache's free blocks return to the main one.
+    struct Absorb {
+        Ctx* c;
+        ~Absorb() { c->pool.absorb(c->pool_side); }
+    } absorb{this};
+    std::vector<Grp> side_acc(chunks.size());
+    struct SideGuard {  // error path: side work ends before its buffers go back
+        Ctx* c;
+        bool pending = false;
+        ~SideGuard() {
+            c->alloc_side = false;
+            if (pending) (void)hipStreamSynchronize(c->side);
+        }
+    } guard{this};
+    hip_check(hipEventRecord(ev_fork, stream), "fork side stream");
+    hip_check(hipStreamWaitEvent(side, ev_fork, 0), "fork side stream");
+    guard.pending = true;
+    const hipStream_t main_stream = stream;
+    // largest groups first, alternating streams
+    std::vector<size_t> order(chunks.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    auto work = [&](const Chunk& ch) {
+        return (double)ch.idx.size() * ch.sh.t * ch.sh.h * (ch.lvl + 1 + n_p);
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t x, size_t y) { return work(chunks[x]) > work(chunks[y]); });
+    double load[2] = {0, 0};
+    for (size_t i : order) {
+        const int sidx = load[1] < load[0] ? 1 : 0;  // the less loaded stream
+        load[sidx] += work(chunks[i]);
+        if (sidx == 0) {
+            run(chunks[i], false, nullptr);
+            continue;
+        }
+        stream = side;
+        alloc_side = true;
+        try {
+            run(chunks[i], true, &side_acc[i]);
+        } catch (...) {
+            stream = main_stream;
+            alloc_side = false;
+            throw;
+        }
+        stream = main_stream;
+        alloc_side = false;
+    }
+    hip_check(hipEventRecord(ev_join, side), "join side stream");
+    hip_check(hipStreamWaitEvent(stream, ev_join, 0), "join side stream");
+    guard.pending = false;
+    for (size_t i = 0; i < chunks.size(); ++i) {
+        if (!side_acc[i].p) continue;
+        auto r = g_scatter(side_acc[i]);
+        for (size_t t = 0; t < r.size(); ++t) out[chunks[i].idx[t]] = r[t];
+        side_acc[i] = Grp();
     }
     return out;
 }

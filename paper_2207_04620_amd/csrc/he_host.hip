@@ -114,9 +114,26 @@ void Pool::trim_locked() {
     free_.clear();
 }
 
-DBuf::DBuf(Ctx* c, size_t n_u64) : ctx(c), n(n_u64) { p = (u64*)c->pool.alloc(n_u64 * 8); }
+DBuf::DBuf(Ctx* c, size_t n_u64) : ctx(c), pool(c->alloc_side ? &c->pool_side : &c->pool), n(n_u64) {
+    p = (u64*)pool->alloc(n_u64 * 8);
+}
 DBuf::~DBuf() {
-    if (p) ctx->pool.release(p, n * 8);
+    if (p) pool->release(p, n * 8);
+}
+void Pool::absorb(Pool& o) {
+    if (&o == this) return;
+    std::scoped_lock lk(m, o.m);
+    for (auto& kv : o.free_) {
+        auto& dst = free_[kv.first];
+        for (void* p : kv.second) {
+            dst.push_back(p);
+            o.held -= kv.first;
+            o.cached -= kv.first;
+            held += kv.first;
+            cached += kv.first;
+        }
+    }
+    o.free_.clear();
 }
 
 // ====================================================================== context setup
@@ -1236,9 +1253,9 @@ he_status he_ctx_create(const he_params* prm, const he_device* dev, he_ctx** out
         c->seed = prm->seed;
         c->schedule = prm->schedule;
         if (dev) {
-            c->pool.dev_alloc = dev->alloc;
-            c->pool.dev_free = dev->free;
-            c->pool.user = dev->user;
+            c->pool.dev_alloc = c->pool_side.dev_alloc = dev->alloc;
+            c->pool.dev_free = c->pool_side.dev_free = dev->free;
+            c->pool.user = c->pool_side.user = dev->user;
         }
         if (dev && dev->stream) {
             c->stream = (hipStream_t)dev->stream;

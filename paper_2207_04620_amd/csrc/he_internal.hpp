@@ -52,6 +52,8 @@ struct Pool {
     void release(void* p, size_t bytes);
     void trim();
     void trim_locked();
+    // take over o's cached (free) blocks; only when none of o's work can still be pending
+    void absorb(Pool& o);
     // bytes in use now; restart the peak figure from it
     size_t restart_peak() {
         std::lock_guard<std::mutex> lk(m);
@@ -68,6 +70,7 @@ struct Pool {
 struct Ctx;
 struct DBuf {
     Ctx* ctx;
+    Pool* pool;  // the allocation cache it came from and goes back to
     u64* p = nullptr;
     size_t n;
     DBuf(Ctx* c, size_t n_u64);
@@ -117,6 +120,7 @@ struct MatmulJob {
     std::vector<Grp> pendA, pendB;  // Step-3 pairs awaiting one block tensor-sum (relin-once)
     std::shared_ptr<DBuf> liftA, liftB;
     std::vector<CtPtr> result;
+    bool keep_acc = false;  // leave the result as the group acc (the caller scatters it)
 };
 // resumable state of one lockstep sign/ReLU group
 // mode 0: g_d^(k)(x); mode 1: ReLU (x + x g) / 2; mode 2: AppMax(a, b) (Alg. 5) with
@@ -190,6 +194,11 @@ struct Ctx {
         if (ev_join) (void)hipEventDestroy(ev_join);
     }
     Pool pool;
+    // the side stream's own allocation cache: lockstep groups issued on the side stream take
+    // their buffers from it (alloc_side set), so a block never passes between the streams while
+    // either may still use it; its free blocks return to the main cache after the streams join
+    Pool pool_side;
+    bool alloc_side = false;
     hm::Encoder enc;
     std::vector<u64> mods, roots, pmod;
     std::vector<ModP> host_mods;
@@ -259,6 +268,7 @@ struct Ctx {
     int max_group = 32;
     int pair_batch = 4;  // Step-2 mask pairs per shared ModDown launch
     int overlap = 0;     // Step-2 pair groups pipelined over the two streams (measured slower: off)
+    int concurrent_groups = 1;  // lockstep groups of a mixed batch spread over the two streams
     // a group lift holds only the converted limbs of each digit; its own limbs are read from the
     // lifted polynomial: lift buffer -> (that polynomial of member 0, member stride)
     std::unordered_map<const u64*, std::pair<const u64*, int64_t>> lift_own;
@@ -337,6 +347,7 @@ struct Ctx {
         d_mu_scale.reset(); d_md_scale.reset();
         d_rs.reset(); d_md_tab.reset(); d_pinv.reset(); d_mu_tab.reset();
         pool.trim();
+        pool_side.trim();
     }
 };
 

@@ -72,17 +72,19 @@ he_status he_tuning_get(const he_ctx* ctx, he_tuning* out) {
     out->pair_batch = (uint32_t)ctx->c->pair_batch;
     out->max_group = (uint32_t)ctx->c->max_group;
     out->overlap = (uint32_t)ctx->c->overlap;
+    out->concurrent_groups = (uint32_t)ctx->c->concurrent_groups;
     return HE_OK;
 }
 
 he_status he_tuning_set(he_ctx* ctx, const he_tuning* t) {
     if (!ctx || !t || t->pair_batch < 1 || t->pair_batch > IP_MAXSET || t->max_group < 1 || t->max_group > 256 ||
-        t->overlap > 1)
+        t->overlap > 1 || t->concurrent_groups > 1)
         return HE_EINVAL;
     std::lock_guard<std::recursive_mutex> lk(ctx->c->api_mu);
     ctx->c->pair_batch = (int)t->pair_batch;
     ctx->c->max_group = (int)t->max_group;
     ctx->c->overlap = (int)t->overlap;
+    ctx->c->concurrent_groups = (int)t->concurrent_groups;
     return HE_OK;
 }
 
@@ -95,6 +97,7 @@ he_status he_autotune(he_ctx* ctx, uint32_t h, uint32_t level, uint32_t batch, c
     const std::string key = tune_key(c, (int)h, (int)level, (int)batch);
     std::string rep = "{\"key\": \"" + key + "\"";
     he_tuning best{};
+    best.concurrent_groups = (uint32_t)c->concurrent_groups;  // not a tuned knob
     bool have = false;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -109,6 +112,7 @@ he_status he_autotune(he_ctx* ctx, uint32_t h, uint32_t level, uint32_t batch, c
         have = true;
         rep += ", \"source\": \"file cache\"";
     }
+    best.concurrent_groups = (uint32_t)c->concurrent_groups;
     he_status st = HE_OK;
     if (!have) {
         st = run_guarded(ctx, [&]() {
@@ -192,8 +196,9 @@ he_status he_autotune(he_ctx* ctx, uint32_t h, uint32_t level, uint32_t batch, c
         c->overlap = (int)best.overlap;
     }
     char buf[128];
-    snprintf(buf, sizeof buf, ", \"chosen\": {\"pair_batch\": %u, \"max_group\": %u, \"overlap\": %u}}",
-             best.pair_batch, best.max_group, best.overlap);
+    snprintf(buf, sizeof buf,
+             ", \"chosen\": {\"pair_batch\": %u, \"max_group\": %u, \"overlap\": %u, \"concurrent_groups\": %u}}",
+             best.pair_batch, best.max_group, best.overlap, best.concurrent_groups);
     rep += buf;
     if (report && report_n) {
         const size_t m = std::min(report_n - 1, rep.size());

@@ -53,7 +53,8 @@ class _ServeConfig(C.Structure):
 
 
 class _Tuning(C.Structure):
-    _fields_ = [("pair_batch", C.c_uint32), ("max_group", C.c_uint32), ("overlap", C.c_uint32)]
+    _fields_ = [("pair_batch", C.c_uint32), ("max_group", C.c_uint32), ("overlap", C.c_uint32),
+                ("concurrent_groups", C.c_uint32)]
 
 
 class _Request(C.Structure):
@@ -274,10 +275,11 @@ class Context:
     def tuning(self):
         t = _Tuning()
         _chk(lib().he_tuning_get(self.ptr, C.byref(t)), "he_tuning_get")
-        return {"pair_batch": t.pair_batch, "max_group": t.max_group, "overlap": t.overlap}
+        return {"pair_batch": t.pair_batch, "max_group": t.max_group, "overlap": t.overlap,
+                "concurrent_groups": t.concurrent_groups}
 
-    def set_tuning(self, pair_batch: int, max_group: int, overlap: int = 0):
-        t = _Tuning(pair_batch, max_group, overlap)
+    def set_tuning(self, pair_batch: int, max_group: int, overlap: int = 0, concurrent_groups: int = 1):
+        t = _Tuning(pair_batch, max_group, overlap, concurrent_groups)
         _chk(lib().he_tuning_set(self.ptr, C.byref(t)), "he_tuning_set")
 
     def autotune(self, h: int, level: int, batch: int, cache_path: str | None = None):
