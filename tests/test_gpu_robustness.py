@@ -113,6 +113,33 @@ def test_injected_launch_failure_fails_only_that_call(H, ctx):
         assert np.array_equal(ctx.export(r), want)
 
 
+def test_injected_failure_in_a_two_stream_batch(H, ctx):
+    """a batch of two shapes runs its groups on the context's two streams; a launch that fails
+    on either stream fails the call with HE_EDEVICE, the queued work of the other stream drains
+    before its buffers return to the cache, and the same batch then gives the residues of a
+    clean run"""
+    hs = [8, 8, 4, 4]
+    As, Bs = [], []
+    for i, h in enumerate(hs):
+        A, B = I.matrix_pair(40 + i, h)
+        As.append(ctx.encrypt(A.ravel(), nonce=40 + 2 * i))
+        Bs.append(ctx.encrypt(B.ravel(), nonce=41 + 2 * i))
+    ctx.set_tuning(4, 32, 0, 1)
+    want = [ctx.export(r) for r in ctx.matmul_batch(As, Bs, hs)]
+    n = _launches(ctx, lambda: ctx.matmul_batch(As, Bs, hs))
+    _log(f"[robust] a two-shape batch makes {n} launches")
+    try:
+        for k in (n // 4, n // 2, (3 * n) // 4, n):
+            _log(f"[robust] launch {k} of the two-stream batch fails")
+            H.fail_launch(k)
+            assert _code(H, ctx.matmul_batch, As, Bs, hs) == EDEVICE
+            H.fail_launch(0)
+            got = [ctx.export(r) for r in ctx.matmul_batch(As, Bs, hs)]
+            assert all(np.array_equal(g, w) for g, w in zip(got, want))
+    finally:
+        H.fail_launch(0)
+
+
 def test_pool_cap_gives_enomem_then_recovers(H, ctx):
     A, B = I.matrix_pair(6, 8)
     a, b = ctx.encrypt(A.ravel(), nonce=6), ctx.encrypt(B.ravel(), nonce=7)
