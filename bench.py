@@ -6,7 +6,8 @@ P = 3 x 60 + 56 bits, dnum 3, scale 2^45; inputs are fresh encryptions at the to
 level (13) of matrices with entries uniform in [-1, 1], resident in HBM before the
 timed region.  The plain path (one he_matmul at a time) is timed beside it.
 
-Prints one JSON line (see the design doc for the roofline and traffic derivations).
+Prints one JSON line: the headline rate and its roofline, the step's traffic, the per-kernel
+breakdown, the other configurations and the oracle baseline.
 """
 from __future__ import annotations
 

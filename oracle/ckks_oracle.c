@@ -17,7 +17,7 @@
  * The RNS-CKKS internals (hybrid key switching, centered fast base conversion,
  * rescale by the last prime) are not described by the paper; they follow the
  * standard published constructions (Cheon-Han-Kim-Kim-Song 2018 RNS-CKKS,
- * Han-Ki 2020 hybrid key switching) under the readings listed in the design doc.
+ * Han-Ki 2020 hybrid key switching) under the conventions stated in ckks_oracle.h.
  */
 #include "ckks_oracle.h"
 

@@ -9,7 +9,7 @@
  * (Sec. 4.2, Alg. 5).  Only the test suite, the smoke check and the CPU-baseline
  * leg of the benchmark may load it.  It shares no code with the GPU library.
  *
- * Conventions (readings where the paper is silent; each is listed in the design doc):
+ * Conventions (readings where the paper is silent):
  *  - ring Z_Q[X]/(X^N+1), Q = q_0 ... q_L, special modulus P = p_0 ... p_{K-1};
  *  - primes: for each requested bit size, in list order (Q list, then P list),
  *    the largest unused prime p < 2^bits with p = 1 mod 2N;
