@@ -662,6 +662,10 @@ def main():
         "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
                         **({"GB/s": hbm[k]} if k in hbm else {})} for k, v in prof.items()},
     }
+    # the other legs make contexts of their own: the headline context gives its cached device
+    # blocks back first (it keeps its keys and inputs)
+    ctx.pool_limit(1)
+    ctx.pool_limit(0)
     if not args.no_shapes:
         log("packed (iota_4), rectangular (16 x 64) and transposition legs")
         result["shapes"] = shapes_leg(he, I, prm, sched, stream, args.batch)

@@ -232,8 +232,8 @@ he_status he_transpose_batch(he_ctx *ctx, size_t n, const he_ct *const *a, uint3
  * launch and one ModDown launch (1..16); max_group: members per lockstep group (1..256);
  * overlap (0 or 1): the next Step-2 pair group's inner products run on the context's second
  * stream while the current group's ModDown runs on the context stream; concurrent_groups (0 or
- * 1): the lockstep groups of a batch with several (shape, level) groups, or more members than
- * max_group, are spread over the two streams (the autotuner leaves it as set). */
+ * 1): the (shape, level) groups of a batch with several of them are spread over the two
+ * streams (the autotuner leaves it as set). */
 typedef struct {
     uint32_t pair_batch;
     uint32_t max_group;

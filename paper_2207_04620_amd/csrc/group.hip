@@ -1254,12 +1254,12 @@ std::vector<CtPtr> Ctx::matmul_batch(const std::vector<const CtData*>& A, const 
         else
             for (size_t t = 0; t < J.result.size(); ++t) out[ch.idx[t]] = J.result[t];
     };
-    if (chunks.size() < 2 || !concurrent_groups || !side) {
+    if (groups.size() < 2 || !concurrent_groups || !side) {
         for (auto& ch : chunks) run(ch, false, nullptr);
         return out;
     }
-    // Groups of a mixed batch alternate between the two streams so that the small launches of
-    // different groups fill the device together.  The side stream starts after the work issued
+    // The (shape, level) groups of a mixed batch share out the two streams so that the smaller
+    // launches of different groups fill the device together.  The side stream starts after the work issued
     // so far, takes its buffers from its own allocation cache, and leaves each group's result
     // in that group's accumulator; after the join the context stream copies the results out
     // (into buffers of the main cache) and the side cache's free blocks return to the main one.
@@ -1280,18 +1280,30 @@ std::vector<CtPtr> Ctx::matmul_batch(const std::vector<const CtData*>& A, const 
     hip_check(hipStreamWaitEvent(side, ev_fork, 0), "fork side stream");
     guard.pending = true;
     const hipStream_t main_stream = stream;
-    // largest groups first, alternating streams
-    std::vector<size_t> order(chunks.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    // (shape, level) groups, largest first, each onto the less loaded stream; the chunks of one
+    // group stay on one stream (one group's working set in flight at a time)
     auto work = [&](const Chunk& ch) {
         return (double)ch.idx.size() * ch.sh.t * ch.sh.h * (ch.lvl + 1 + n_p);
     };
-    std::stable_sort(order.begin(), order.end(),
-                     [&](size_t x, size_t y) { return work(chunks[x]) > work(chunks[y]); });
+    std::map<std::pair<MatShape, int>, double> gwork;
+    for (auto& ch : chunks) gwork[{ch.sh, ch.lvl}] += work(ch);
+    std::vector<std::pair<double, std::pair<MatShape, int>>> gorder;
+    for (auto& kv : gwork) gorder.push_back({kv.second, kv.first});
+    std::stable_sort(gorder.begin(), gorder.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    std::map<std::pair<MatShape, int>, int> gstream;
     double load[2] = {0, 0};
-    for (size_t i : order) {
+    for (auto& g : gorder) {
         const int sidx = load[1] < load[0] ? 1 : 0;  // the less loaded stream
-        load[sidx] += work(chunks[i]);
+        load[sidx] += g.first;
+        gstream[g.second] = sidx;
+    }
+    std::vector<size_t> order(chunks.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+        return gwork[{chunks[x].sh, chunks[x].lvl}] > gwork[{chunks[y].sh, chunks[y].lvl}];
+    });
+    for (size_t i : order) {
+        const int sidx = gstream[{chunks[i].sh, chunks[i].lvl}];
         if (sidx == 0) {
             run(chunks[i], false, nullptr);
             continue;

@@ -77,6 +77,10 @@ void* Pool::alloc_locked(size_t bytes) {
     } else if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         trim_locked();
+        if (sibling) {  // the other cache's free blocks too (hipFree waits for the device)
+            std::lock_guard<std::mutex> lk2(sibling->m);
+            sibling->trim_locked();
+        }
         if (hipMalloc(&p, bytes) != hipSuccess) {
             (void)hipGetLastError();
             p = nullptr;
@@ -1263,6 +1267,8 @@ he_status he_ctx_create(const he_params* prm, const he_device* dev, he_ctx** out
             hip_check(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "stream");
             c->own_stream = true;
         }
+        c->pool.sibling = &c->pool_side;
+        c->pool_side.sibling = &c->pool;
         // the side stream (default priority) and its fork/join events
         hip_check(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "side stream");
         hip_check(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "fork event");

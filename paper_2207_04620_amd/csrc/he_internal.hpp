@@ -44,6 +44,7 @@ struct Pool {
     size_t held = 0, cached = 0;  // device bytes held (in use + cached), of them cached
     size_t limit = 0;             // cap on held bytes (0: none); beyond it alloc is HE_ENOMEM
     size_t peak = 0;              // largest in-use byte count (held - cached) since the last reset
+    Pool* sibling = nullptr;  // the context's other cache: its free blocks go back too when memory runs out
     void* (*dev_alloc)(size_t, void*) = nullptr;
     void (*dev_free)(void*, void*) = nullptr;
     void* user = nullptr;
