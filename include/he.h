@@ -243,10 +243,10 @@ typedef struct {
 he_status he_tuning_get(const he_ctx *ctx, he_tuning *out);
 he_status he_tuning_set(he_ctx *ctx, const he_tuning *t);
 /* Autotuner: times he_matmul_batch of 'batch' h x h pairs at 'level' on the device under each
- * candidate (pair_batch 1, 2, 4, 8; max_group = batch, and batch / 2 when batch >= 16; then
- * overlap off against on for the best of those; the best of two timed runs each after a
- * warm-up), applies the fastest to the context (a later candidate must be 1 % faster to displace
- * an earlier one) and caches it per (N, limbs, alpha, schedule, h, level, batch, device) in the
+ * candidate (the context's current setting first, then pair_batch 1, 2, 4, 8 with max_group =
+ * batch, and batch / 2 when batch >= 16; then overlap on for the best of those; the best of two
+ * timed runs each after a warm-up), applies the fastest to the context (a later candidate must
+ * be 1 % faster to displace an earlier one) and caches it per (N, limbs, alpha, schedule, h, level, batch, device) in the
  * process and, when cache_path is set, in that text file (a line already there is used without
  * timing).  report: optional JSON of the candidates' times and the
  * choice, truncated to report_n bytes.  HE_ESHAPE / HE_ELEVEL as for he_matmul.  Synchronizes. */

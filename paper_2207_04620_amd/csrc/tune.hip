@@ -172,9 +172,13 @@ he_status he_autotune(he_ctx* ctx, uint32_t h, uint32_t level, uint32_t batch, c
                     best.overlap = (uint32_t)ov;
                 }
             };
+            // the context's own setting first: another candidate must beat it by 1 % to replace it
+            const int pb0 = restore.pb, mg0 = std::min(restore.mg, (int)batch);
+            candidate(pb0, mg0, 0);
             const int groups[2] = {(int)batch, (int)batch / 2};
             for (int gi = 0; gi < (batch >= 16 ? 2 : 1); ++gi)
-                for (int pb : {1, 2, 4, 8}) candidate(pb, groups[gi], 0);
+                for (int pb : {1, 2, 4, 8})
+                    if (pb != pb0 || groups[gi] != mg0) candidate(pb, groups[gi], 0);
             candidate((int)best.pair_batch, (int)best.max_group, 1);
             rep += "]";
             (void)hipEventDestroy(e0);
