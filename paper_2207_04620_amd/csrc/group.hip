@@ -835,7 +835,7 @@ bool Ctx::matmul_step(MatmulJob& J, int k_chunk) {
                         cur = g_pairs_ip(J.A0, J.liftA->p, pair_group(k), ms);
                     }
                     const int k1 = k + cur.P;
-                    if (overlap && side && stream != side && k1 < kend) {
+                    if (overlap && k1 < kend && ensure_side() && stream != side) {
                         std::vector<MaskPair> pr = pair_group(k1);  // masks on the context stream
                         hip_check(hipEventRecord(ev_fork, stream), "fork side stream");
                         hip_check(hipStreamWaitEvent(side, ev_fork, 0), "fork side stream");
@@ -1254,7 +1254,7 @@ std::vector<CtPtr> Ctx::matmul_batch(const std::vector<const CtData*>& A, const 
         else
             for (size_t t = 0; t < J.result.size(); ++t) out[ch.idx[t]] = J.result[t];
     };
-    if (groups.size() < 2 || !concurrent_groups || !side) {
+    if (groups.size() < 2 || !concurrent_groups || !ensure_side()) {
         for (auto& ch : chunks) run(ch, false, nullptr);
         return out;
     }

@@ -1269,10 +1269,7 @@ he_status he_ctx_create(const he_params* prm, const he_device* dev, he_ctx** out
         }
         c->pool.sibling = &c->pool_side;
         c->pool_side.sibling = &c->pool;
-        // the side stream (default priority) and its fork/join events
-        hip_check(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "side stream");
-        hip_check(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "fork event");
-        hip_check(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "join event");
+
         std::vector<uint32_t> qb(prm->q_bits, prm->q_bits + prm->n_q), pb(prm->p_bits, prm->p_bits + prm->n_p);
         gen_primes(c->log_n, qb, c->mods);
         gen_primes(c->log_n, pb, c->mods);

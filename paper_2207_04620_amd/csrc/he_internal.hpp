@@ -188,6 +188,26 @@ struct Ctx {
     // after the join, so the allocation cache stays ordered by the context stream)
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // the side stream (default priority) and its events, made on first use: a context that
+    // never overlaps work holds no second stream (hardware queues are few per process)
+    bool ensure_side() {
+        if (side) return true;
+        hipStream_t s2 = nullptr;
+        hipEvent_t e1 = nullptr, e2 = nullptr;
+        if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&e1, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&e2, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            if (s2) (void)hipStreamDestroy(s2);
+            if (e1) (void)hipEventDestroy(e1);
+            if (e2) (void)hipEventDestroy(e2);
+            return false;  // the work then runs on the context stream alone
+        }
+        side = s2;
+        ev_fork = e1;
+        ev_join = e2;
+        return true;
+    }
     ~Ctx() {
         if (side) (void)hipStreamSynchronize(side);
         if (side) (void)hipStreamDestroy(side);
