@@ -394,6 +394,26 @@ def shapes_leg(he, I, prm, sched, stream, batch):
     return out
 
 
+def hbm_probe(torch, ctx, words=1 << 27, reps=20):
+    """What a plain streaming kernel moves through HBM on this device (he_stream_probe: 16-byte
+    accesses, 1 GiB per stream): read only, copy (one read and one write stream) and two read
+    streams with one write stream (the ModDown row pass's mix), in GB/s of bytes moved"""
+    a = torch.empty(words, dtype=torch.int64, device="cuda")
+    b = torch.empty(words, dtype=torch.int64, device="cuda")
+    c = torch.empty(words, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    out = {}
+    for name, pattern, streams in (("read", 0, 1), ("copy", 1, 2), ("two_reads_one_write", 2, 3)):
+        ms = ctx.stream_probe(pattern, a, b if pattern == 2 else None, c, reps)
+        out[f"{name}_GB/s"] = round(streams * 8 * words / (ms * 1e-3) / 1e9, 1)
+    out["bytes_per_stream"] = 8 * words
+    out["note"] = ("he_stream_probe: 16-byte accesses, four per lane in flight, mean of 20 launches after one; "
+                   "the row pass reads two streams and writes one")
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -413,6 +433,7 @@ def main():
     ap.add_argument("--c4", type=int, default=128, help="ciphertexts of the N=2^16 ReLU + h=32 leg (0: skip)")
     ap.add_argument("--serve-rings", type=int, default=2000, help="requests of the cross-ring serving leg (0: skip)")
     ap.add_argument("--no-shapes", action="store_true", help="skip the packed / rectangular / transpose leg")
+    ap.add_argument("--no-probe", action="store_true", help="skip the streaming-bandwidth probe")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / batched capacity")
     ap.add_argument("--serve-min-batch", type=int, default=8)
@@ -618,6 +639,14 @@ def main():
                      "avg_launch_us": round(avg_ms * 1e3, 2), "launches": d["launches"],
                      "share_of_gpu_time": round(prof_all[dom]["ms"] / total_ms, 3),
                      "gpu_busy": round(total_ms / (prof_elapsed * 1e3), 3)})
+    probe = None
+    if not args.no_probe:
+        probe = hbm_probe(torch, ctx)
+        log(f"hbm probe: {probe}")
+        if roofline["bound"] == "hbm":
+            best = max(probe["copy_GB/s"], probe["two_reads_one_write_GB/s"])
+            roofline["frac_of_achievable"] = round(achieved / best, 4)
+            roofline["achievable_GB/s"] = best
     prof = prof_all
     ntt_ms = sum(prof[k]["ms"] for k in NTT_KERNELS)
     ntt_ops = sum(prof[k]["ops"] for k in NTT_KERNELS)
@@ -655,6 +684,7 @@ def main():
                            "note": "butterfly_valu_frac: the butterflies' VALU instructions (28 per 64-bit integer "
                                    "butterfly of a 60-bit prime, 8 per FP64 butterfly of a prime below 2^46) over "
                                    "the VALU rate of 39.32 T lane-instructions/s"},
+        "hbm_probe": probe,
         "step_traffic": {"algorithmic_GB": round(step_bytes / 1e9, 2),
                          "per_product_GB": round(step_bytes / args.batch / 1e9, 3),
                          "hbm_frac": round(step_bytes / (step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),

@@ -345,6 +345,17 @@ he_status he_profile_report(he_ctx *ctx, char *buf, size_t n);
  * runtime rejects is HE_EDEVICE from the call that issued it. */
 he_status he_debug_fail_launch(uint64_t n);
 
+/* Streaming-bandwidth probe (a measurement aid; no operation of the method uses it): after one
+ * untimed launch, 'reps' launches of one access mix over caller device buffers, timed with HIP
+ * events on the context stream (the call synchronizes); *ms_per_rep is the mean time of one.
+ * pattern 0 reads n_words words of a and writes 2^20 words of partial sums to c (c must hold
+ * them; their sum equals the sum of a's words mod 2^64): 8 n_words bytes from HBM.
+ * pattern 1: c = a (16 n_words bytes); pattern 2: c = a + b word-wise mod 2^64 (24 n_words
+ * bytes; the mix of the ModDown row pass: two read streams, one write stream).  Buffers are
+ * 16-byte aligned device memory of n_words words (even); HE_EINVAL otherwise. */
+he_status he_stream_probe(he_ctx *ctx, uint32_t pattern, const uint64_t *a, const uint64_t *b, uint64_t *c,
+                          uint64_t n_words, uint32_t reps, double *ms_per_rep);
+
 const char *he_status_string(he_status s);
 
 #ifdef __cplusplus

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhe.so")
-SOURCES = ["kernels.hip", "he_host.hip", "group.hip", "serve.hip", "tune.hip", "graph.hip"]
+SOURCES = ["kernels.hip", "he_host.hip", "group.hip", "serve.hip", "tune.hip", "graph.hip", "probe.hip"]
 
 # Packed FP32 instructions are disabled for all device code: the kernels compute in 64-bit
 # integers and FP64 only, and the flag keeps the compiler from ever emitting packed FP32.

@@ -141,6 +141,8 @@ SIGNATURES = {
     "he_pool_limit": (C.c_int, [C.c_void_p, C.c_uint64]),
     "he_pack_beta": (C.c_int, [C.c_size_t, C.c_size_t, C.c_void_p, C.POINTER(C.c_double)]),
     "he_pool_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.c_int]),
+    "he_stream_probe": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
+                                  C.c_uint32, C.POINTER(C.c_double)]),
 }
 
 
@@ -488,6 +490,15 @@ class Context:
         n_limbs = dev_tensor.shape[0]
         mi = (C.c_uint32 * n_limbs)(*[int(x) for x in mod_idx])
         _chk(lib().he_ntt(self.ptr, C.c_void_p(dev_tensor.data_ptr()), n_limbs, mi, int(inverse)), "he_ntt")
+
+    def stream_probe(self, pattern, a, b, c, reps):
+        """he_stream_probe over 64-bit torch tensors on the GPU (a, c and, for pattern 2, b of
+        equal word counts; pattern 0 writes 2^20 partial-sum words to c): mean ms per launch"""
+        ms = C.c_double()
+        bp = C.c_void_p(b.data_ptr()) if b is not None else None
+        _chk(lib().he_stream_probe(self.ptr, int(pattern), C.c_void_p(a.data_ptr()), bp, C.c_void_p(c.data_ptr()),
+                                   a.numel(), int(reps), C.byref(ms)), "he_stream_probe")
+        return ms.value
 
 
 class Graph:
