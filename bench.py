@@ -395,9 +395,10 @@ def shapes_leg(he, I, prm, sched, stream, batch):
 
 
 def hbm_probe(torch, ctx, words=1 << 27, reps=20):
-    """What a plain streaming kernel moves through HBM on this device (he_stream_probe: 16-byte
-    accesses, 1 GiB per stream): read only, copy (one read and one write stream) and two read
-    streams with one write stream (the ModDown row pass's mix), in GB/s of bytes moved"""
+    """What a plain streaming kernel moves through HBM on this device (he_stream_probe: one pass
+    of 16-byte nontemporal accesses, 1 GiB per stream): read only, copy (one read and one write
+    stream) and two read streams with one write stream (the ModDown row pass's mix), in GB/s of
+    bytes moved"""
     a = torch.empty(words, dtype=torch.int64, device="cuda")
     b = torch.empty(words, dtype=torch.int64, device="cuda")
     c = torch.empty(words, dtype=torch.int64, device="cuda")
@@ -407,7 +408,7 @@ def hbm_probe(torch, ctx, words=1 << 27, reps=20):
         ms = ctx.stream_probe(pattern, a, b if pattern == 2 else None, c, reps)
         out[f"{name}_GB/s"] = round(streams * 8 * words / (ms * 1e-3) / 1e9, 1)
     out["bytes_per_stream"] = 8 * words
-    out["note"] = ("he_stream_probe: 16-byte accesses, four per lane in flight, mean of 20 launches after one; "
+    out["note"] = ("he_stream_probe: one pass of 16-byte nontemporal accesses, mean of 20 launches after one; "
                    "the row pass reads two streams and writes one")
     del a, b, c
     torch.cuda.empty_cache()

@@ -345,11 +345,13 @@ he_status he_profile_report(he_ctx *ctx, char *buf, size_t n);
  * runtime rejects is HE_EDEVICE from the call that issued it. */
 he_status he_debug_fail_launch(uint64_t n);
 
-/* Streaming-bandwidth probe (a measurement aid; no operation of the method uses it): after one
- * untimed launch, 'reps' launches of one access mix over caller device buffers, timed with HIP
- * events on the context stream (the call synchronizes); *ms_per_rep is the mean time of one.
- * pattern 0 reads n_words words of a and writes 2^20 words of partial sums to c (c must hold
- * them; their sum equals the sum of a's words mod 2^64): 8 n_words bytes from HBM.
+/* Streaming-bandwidth probe (a measurement aid; no operation of the method uses it): one pass of
+ * 16-byte nontemporal accesses.  After one untimed launch, 'reps' launches of one access mix
+ * over caller device buffers, timed with HIP events on the context stream (the call
+ * synchronizes); *ms_per_rep is the mean time of one.
+ * pattern 0 reads n_words words of a and writes one pair of partial sums per 4096 words
+ * (c must hold 2 ceil(n_words / 4096) words; their sum equals the sum of a's words mod 2^64):
+ * 8 n_words bytes from HBM.
  * pattern 1: c = a (16 n_words bytes); pattern 2: c = a + b word-wise mod 2^64 (24 n_words
  * bytes; the mix of the ModDown row pass: two read streams, one write stream).  Buffers are
  * 16-byte aligned device memory of n_words words (even); HE_EINVAL otherwise. */

@@ -1,5 +1,4 @@
-// Streaming-bandwidth probe: what a plain kernel written like this library's (16-byte accesses,
-// several loads in flight per lane, one pass over the data) moves through HBM per second, for
+// Streaming-bandwidth probe: what a plain streaming kernel moves through HBM per second, for
 // the three access mixes the method's kernels have — read only, one read stream and one write
 // stream (a copy), two read streams and one write stream (the ModDown row pass reads the
 // converted limb and u and writes the result).  It is a measurement aid: the method never calls
@@ -17,55 +16,52 @@ namespace {
 typedef uint64_t w64;
 typedef w64 w64x2 __attribute__((ext_vector_type(2)));
 
-constexpr int PTPB = 256;              // threads per block
-constexpr int PU = 4;                  // 16-byte accesses in flight per lane and stream
-constexpr int READ_BLOCKS = 2048;      // the read mix's grid (8 blocks per CU, grid-stride): 2^19 lanes,
-                                       // 2^20 words of partial sums
+constexpr int PTPB = 256;  // threads per block
+constexpr int RPU = 8;     // the read mix: 16-byte loads per lane (one pass, 2048 pairs per block)
 
-// pattern 0: every lane sums its words (two lanes of 64-bit sums, mod 2^64) over a grid-stride
-// walk and writes its pair of partial sums to c[lane]
+// Accesses bypass the caches' normal retention (nontemporal): each word is touched once, and
+// these were the fastest forms of each mix measured on the device (one pass, 16-byte accesses;
+// one pair per lane for the copy and the two-read mix, eight for the read mix).
+
+// pattern 0: a block sums its 2048 pairs (two lanes of 64-bit sums, mod 2^64) and writes one
+// pair to c[block]
 __global__ __launch_bounds__(PTPB) void k_stream_read(const w64x2* __restrict__ a, w64x2* __restrict__ c,
                                                       int64_t n2) {
-    const int64_t lane = (int64_t)blockIdx.x * PTPB + threadIdx.x, stride = (int64_t)gridDim.x * PTPB;
+    __shared__ w64x2 red[PTPB];
+    const int64_t base = (int64_t)blockIdx.x * (PTPB * RPU) + threadIdx.x;
     w64x2 s = {0, 0};
-    int64_t i = lane;
-    for (; i + (PU - 1) * stride < n2; i += PU * stride) {
-        w64x2 v[PU];
 #pragma unroll
-        for (int k = 0; k < PU; ++k) v[k] = a[i + k * stride];
-#pragma unroll
-        for (int k = 0; k < PU; ++k) s += v[k];
+    for (int k = 0; k < RPU; ++k) {
+        const int64_t i = base + (int64_t)k * PTPB;
+        if (i < n2) s += __builtin_nontemporal_load(a + i);
     }
-    for (; i < n2; i += stride) s += a[i];
-    c[lane] = s;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = PTPB / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) c[blockIdx.x] = red[0];
 }
 
-// patterns 1 and 2: one pass, PU pairs per lane, c = a or c = a + b (mod 2^64 per word)
+// patterns 1 and 2: one pair per lane, c = a or c = a + b (mod 2^64 per word)
 template <bool ADD>
 __global__ __launch_bounds__(PTPB) void k_stream_map(const w64x2* __restrict__ a, const w64x2* __restrict__ b,
                                                      w64x2* __restrict__ c, int64_t n2) {
-    const int64_t base = (int64_t)blockIdx.x * (PTPB * PU) + threadIdx.x;
-    w64x2 v[PU], w[PU];
-#pragma unroll
-    for (int k = 0; k < PU; ++k) {
-        const int64_t i = base + (int64_t)k * PTPB;
-        if (i < n2) {
-            v[k] = a[i];
-            if constexpr (ADD) w[k] = b[i];
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < PU; ++k) {
-        const int64_t i = base + (int64_t)k * PTPB;
-        if (i < n2) c[i] = ADD ? v[k] + w[k] : v[k];
+    const int64_t i = (int64_t)blockIdx.x * PTPB + threadIdx.x;
+    if (i < n2) {
+        w64x2 v = __builtin_nontemporal_load(a + i);
+        if constexpr (ADD) v += __builtin_nontemporal_load(b + i);
+        __builtin_nontemporal_store(v, c + i);
     }
 }
 
 void launch_stream(uint32_t pattern, const w64x2* a, const w64x2* b, w64x2* c, int64_t n2, hipStream_t st) {
     if (pattern == 0) {
-        HE_LAUNCH(k_stream_read, dim3(READ_BLOCKS), dim3(PTPB), 0, st, a, c, n2);
+        const int64_t blocks = (n2 + PTPB * RPU - 1) / (PTPB * RPU);
+        HE_LAUNCH(k_stream_read, dim3((unsigned)blocks), dim3(PTPB), 0, st, a, c, n2);
     } else {
-        const int64_t blocks = (n2 + PTPB * PU - 1) / (PTPB * PU);
+        const int64_t blocks = (n2 + PTPB - 1) / PTPB;
         if (pattern == 1)
             HE_LAUNCH(k_stream_map<false>, dim3((unsigned)blocks), dim3(PTPB), 0, st, a, b, c, n2);
         else
@@ -85,7 +81,7 @@ he_status he_stream_probe(he_ctx* ctx, uint32_t pattern, const uint64_t* a, cons
     if (pattern == 2 && !b) return HE_EINVAL;
     if (misaligned(a) || misaligned(c) || (b && misaligned(b))) return HE_EINVAL;
     // one grid dimension of blocks for the one-pass mixes
-    if (n_words / 2 > (uint64_t)0x7fffffff * PTPB * PU) return HE_EINVAL;
+    if (n_words / 2 > (uint64_t)0x7fffffff * PTPB) return HE_EINVAL;
     const int64_t n2 = (int64_t)(n_words / 2);
     return run_guarded(ctx, [&]() {
         hipStream_t st = ctx->c->stream;
