@@ -123,8 +123,44 @@ std::shared_ptr<DBuf> Ctx::g_lift(const Grp& a, int poly) {
     J.cstride = lcs;
     J.nct = B;
     J.n = 0;
+    // every digit's conversion in one fused launch (one grid over all targets: the digits' few
+    // blocks each would leave the device part idle at their ends)
+    const bool merged = fused && beta <= HE_MAXDIG && beta * ne - nl <= HE_MAXT;
+    ConvDesc M;
+    memset(&M, 0, sizeof M);
+    if (merged) {
+        M.src = coef.p;
+        M.src_cstride = (int64_t)nl * N;
+        M.dst = lift->p;
+        M.dst_cstride = lcs;
+        M.nct = B;
+        M.npoly = 1;
+        M.tab = d_mu_tab->p;
+        M.tab_ld = ne;
+        M.prescaled = 1;
+        M.ndig = beta;
+    }
     for (int j = 0; j < beta; ++j) {
         const ModUpInfo& inf = infos[j];
+        if (merged) {
+            M.dns[j] = inf.hi - inf.lo;
+            M.dsrc[j] = (int64_t)inf.lo * N;
+            M.dtab[j] = (int64_t)inf.off;
+            M.ns = std::max(M.ns, inf.hi - inf.lo);
+            for (int t = 0; t < ne; ++t) {
+                if (t >= inf.lo && t < inf.hi) continue;
+                M.doff[M.nt] = (uint16_t)(j * ne + t);
+                M.dmod[M.nt] = (uint8_t)ext_mod(level, t);
+                M.tcol[M.nt] = (uint16_t)t;
+                M.tdig[M.nt] = (uint8_t)j;
+                ++M.nt;
+                if (J.n >= HE_MAXJ) throw HeError(HE_EUNSUPPORTED);
+                J.off[J.n] = (uint16_t)(j * ne + t);
+                J.mod[J.n] = (uint8_t)ext_mod(level, t);
+                ++J.n;
+            }
+            continue;
+        }
         ConvDesc D;
         memset(&D, 0, sizeof D);
         D.src = coef.p + (size_t)inf.lo * N;
@@ -158,6 +194,7 @@ std::shared_ptr<DBuf> Ctx::g_lift(const Grp& a, int poly) {
         if (fused) launch_conv_cols(T, D, stream);
         else launch_baseconv(T, D, stream);
     }
+    if (merged) launch_conv_cols(T, M, stream);
     launch_ntt(T, J, false, stream, nullptr, 0, !fused);
     // the digits' own limbs stay where they are: the inner product reads them from the
     // polynomial (which outlives the lift wherever a lift is used)

@@ -1194,17 +1194,23 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
     const bool fp = fp64_limb(m.q, L1, N2);
     double* sd = reinterpret_cast<double*>(s);
     constexpr bool BAL = NS > 5;  // the balanced split keeps six to eight products in int64
+    // a digit with fewer sources than NS: its missing terms get a zero constant and re-read its
+    // last source, so every lane runs the same loads and the sum is unchanged
+    const int dg = D.ndig ? D.tdig[t] : 0;
+    const int ns = D.ndig ? D.dns[dg] : NS;
+    const u64* tab = D.ndig ? D.tab + D.dtab[dg] : D.tab;
     Split30 tw[NS];
 #pragma unroll
-    for (int i = 0; i < NS; ++i) tw[i] = split30(D.tab[((int64_t)i * D.tab_ld + D.tcol[t]) * 2]);
-    const u64* src = D.src + c * D.src_cstride + p * D.src_pstride;
+    for (int i = 0; i < NS; ++i)
+        tw[i] = i < ns ? split30(tab[((int64_t)i * D.tab_ld + D.tcol[t]) * 2]) : Split30{0, 0};
+    const u64* src = D.src + (D.ndig ? D.dsrc[dg] : 0) + c * D.src_cstride + p * D.src_pstride;
     const int col0 = x * C;
     for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB) {
         const int64_t slot = (int64_t)(e >> logC) * N2 + col0 + (e & (C - 1));
         AccS a0 = {0, 0, 0}, a1 = {0, 0, 0};
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
-            const u64x2 y = ld2(src + (int64_t)i * N + slot);
+            const u64x2 y = ld2(src + (int64_t)(i < ns ? i : ns - 1) * N + slot);
             int32_t lo, hi;
             split30s<BAL>((int64_t)y.x, lo, hi);
             macs(a0, lo, hi, tw[i]);
@@ -1424,15 +1430,28 @@ void launch_baseconv(const DevTables& T, const ConvDesc& D, hipStream_t st) {
 bool conv_cols_fits(const DevTables& T, int ns) { return T.n1_log >= 1 && ns >= 1 && ns <= HE_MAXSRC; }
 
 void launch_conv_cols(const DevTables& T, const ConvDesc& D, hipStream_t st) {
-    if (!conv_cols_fits(T, D.ns) || !D.prescaled) throw std::runtime_error("conv_cols: unsupported shape");
-    if (misaligned16(D.src) || misaligned16(D.dst) || ((D.src_pstride | D.dst_pstride | D.src_cstride |
-                                                         D.dst_cstride) & 1))
+    if (!conv_cols_fits(T, D.ns) || !D.prescaled || D.nt < 1 || D.nt > HE_MAXT || D.ndig < 0 ||
+        D.ndig > HE_MAXDIG)
+        throw std::runtime_error("conv_cols: unsupported shape");
+    bool odd = (D.src_pstride | D.dst_pstride | D.src_cstride | D.dst_cstride) & 1;
+    double src_limbs = D.ns;  // source limbs read per (poly, ciphertext)
+    if (D.ndig) {
+        src_limbs = 0;
+        for (int d = 0; d < D.ndig; ++d) {
+            if (D.dns[d] < 1 || D.dns[d] > D.ns) throw std::runtime_error("conv_cols: unsupported shape");
+            odd = odd || (D.dsrc[d] & 1);
+            src_limbs += D.dns[d];
+        }
+        for (int t = 0; t < D.nt; ++t)
+            if (D.tdig[t] >= D.ndig) throw std::runtime_error("conv_cols: unsupported shape");
+    }
+    if (misaligned16(D.src) || misaligned16(D.dst) || odd)
         throw std::runtime_error("conv_cols operand not 16-byte aligned");
     const int N = 1 << T.log_n;
     const double units = (double)D.nt * D.npoly * D.nct;
     double fpu = 0;
     for (int t = 0; t < D.nt; ++t) fpu += (double)((T.fp64_mods >> D.dmod[t]) & 1) * D.npoly * D.nct;
-    ProfScope prof_(PK_CONV_COLS, ((double)D.ns * D.npoly * D.nct + units) * 8.0 * N, st,
+    ProfScope prof_(PK_CONV_COLS, (src_limbs * D.npoly * D.nct + units) * 8.0 * N, st,
                     units * (N / 2) * T.n1_log, fpu * (N / 2) * T.n1_log);
     dim3 grid((N / NTT_E) * D.npoly * D.nct * D.nt);
     switch (D.ns) {

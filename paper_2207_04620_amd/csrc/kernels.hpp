@@ -14,6 +14,7 @@
 #define HE_MAXJ 192   // limbs in one job list
 #define HE_MAXSRC 8   // source limbs of one base conversion (digit width / K)
 #define HE_MAXT 64    // target limbs of one base conversion / ext limbs
+#define HE_MAXDIG 8   // digits of one merged ModUp conversion (fused conversion only)
 
 // A list of limbs: limb k of copy c lives at base + c * cstride + off[k] * N and is
 // reduced modulo the prime with index mod[k].
@@ -102,6 +103,14 @@ struct ConvDesc {
     uint16_t doff[HE_MAXT];
     uint16_t tcol[HE_MAXT];  // table column of target t
     uint8_t dmod[HE_MAXT];
+    // The digits of one ModUp in one fused launch (ndig > 0): target t belongs to digit tdig[t],
+    // whose ns_d = dns[d] sources start dsrc[d] words after src and whose table starts dtab[d]
+    // words after tab; ns is the largest ns_d.  ndig = 0: one digit, no offsets.
+    int ndig;
+    int dns[HE_MAXDIG];
+    int64_t dsrc[HE_MAXDIG];
+    int64_t dtab[HE_MAXDIG];
+    uint8_t tdig[HE_MAXT];
 };
 
 struct SampleArgs {
