@@ -1172,7 +1172,9 @@ __global__ __launch_bounds__(TPB) void k_ntt_inv_cols(DevTables T, Jobs J, const
 // it; the row pass follows as usual.  Workgroups are handed to
 // the 8 XCDs round-robin, so the blocks of all targets of one source block are numbered to
 // run back to back on one XCD, where the source words stay in that XCD's L2.
-template <int NS>
+// MD: the digits of one ModUp in one launch (targets carry their digit; a block reads its own
+// digit's sources); without it the single-digit form keeps its loads free of the digit logic
+template <int NS, bool MD>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k_conv_cols(DevTables T, ConvDesc D) {
     __shared__ u64 s[NTT_E];
     const int N = 1 << T.log_n, L1 = T.n1_log, N2 = N >> L1;
@@ -1196,14 +1198,14 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(8))) void k
     constexpr bool BAL = NS > 5;  // the balanced split keeps six to eight products in int64
     // a digit with fewer sources than NS: its missing terms get a zero constant and re-read its
     // last source, so every lane runs the same loads and the sum is unchanged
-    const int dg = D.ndig ? D.tdig[t] : 0;
-    const int ns = D.ndig ? D.dns[dg] : NS;
-    const u64* tab = D.ndig ? D.tab + D.dtab[dg] : D.tab;
+    const int dg = MD ? D.tdig[t] : 0;
+    const int ns = MD ? D.dns[dg] : NS;
+    const u64* tab = MD ? D.tab + D.dtab[dg] : D.tab;
     Split30 tw[NS];
 #pragma unroll
     for (int i = 0; i < NS; ++i)
         tw[i] = i < ns ? split30(tab[((int64_t)i * D.tab_ld + D.tcol[t]) * 2]) : Split30{0, 0};
-    const u64* src = D.src + (D.ndig ? D.dsrc[dg] : 0) + c * D.src_cstride + p * D.src_pstride;
+    const u64* src = D.src + (MD ? D.dsrc[dg] : 0) + c * D.src_cstride + p * D.src_pstride;
     const int col0 = x * C;
     for (int e = 2 * threadIdx.x; e < NTT_E; e += 2 * TPB) {
         const int64_t slot = (int64_t)(e >> logC) * N2 + col0 + (e & (C - 1));
@@ -1427,6 +1429,20 @@ void launch_baseconv(const DevTables& T, const ConvDesc& D, hipStream_t st) {
     }
 }
 
+template <bool MD>
+static void launch_conv_cols_ns(int ns, dim3 grid, hipStream_t st, const DevTables& T, const ConvDesc& D) {
+    switch (ns) {
+        case 1: HE_LAUNCH((k_conv_cols<1, MD>), grid, dim3(TPB), 0, st, T, D); break;
+        case 2: HE_LAUNCH((k_conv_cols<2, MD>), grid, dim3(TPB), 0, st, T, D); break;
+        case 3: HE_LAUNCH((k_conv_cols<3, MD>), grid, dim3(TPB), 0, st, T, D); break;
+        case 4: HE_LAUNCH((k_conv_cols<4, MD>), grid, dim3(TPB), 0, st, T, D); break;
+        case 5: HE_LAUNCH((k_conv_cols<5, MD>), grid, dim3(TPB), 0, st, T, D); break;
+        case 6: HE_LAUNCH((k_conv_cols<6, MD>), grid, dim3(TPB), 0, st, T, D); break;
+        case 7: HE_LAUNCH((k_conv_cols<7, MD>), grid, dim3(TPB), 0, st, T, D); break;
+        default: HE_LAUNCH((k_conv_cols<8, MD>), grid, dim3(TPB), 0, st, T, D); break;
+    }
+}
+
 bool conv_cols_fits(const DevTables& T, int ns) { return T.n1_log >= 1 && ns >= 1 && ns <= HE_MAXSRC; }
 
 void launch_conv_cols(const DevTables& T, const ConvDesc& D, hipStream_t st) {
@@ -1454,16 +1470,10 @@ void launch_conv_cols(const DevTables& T, const ConvDesc& D, hipStream_t st) {
     ProfScope prof_(PK_CONV_COLS, (src_limbs * D.npoly * D.nct + units) * 8.0 * N, st,
                     units * (N / 2) * T.n1_log, fpu * (N / 2) * T.n1_log);
     dim3 grid((N / NTT_E) * D.npoly * D.nct * D.nt);
-    switch (D.ns) {
-        case 1: HE_LAUNCH(k_conv_cols<1>, grid, dim3(TPB), 0, st, T, D); break;
-        case 2: HE_LAUNCH(k_conv_cols<2>, grid, dim3(TPB), 0, st, T, D); break;
-        case 3: HE_LAUNCH(k_conv_cols<3>, grid, dim3(TPB), 0, st, T, D); break;
-        case 4: HE_LAUNCH(k_conv_cols<4>, grid, dim3(TPB), 0, st, T, D); break;
-        case 5: HE_LAUNCH(k_conv_cols<5>, grid, dim3(TPB), 0, st, T, D); break;
-        case 6: HE_LAUNCH(k_conv_cols<6>, grid, dim3(TPB), 0, st, T, D); break;
-        case 7: HE_LAUNCH(k_conv_cols<7>, grid, dim3(TPB), 0, st, T, D); break;
-        default: HE_LAUNCH(k_conv_cols<8>, grid, dim3(TPB), 0, st, T, D); break;
-    }
+    if (D.ndig)
+        launch_conv_cols_ns<true>(D.ns, grid, st, T, D);
+    else
+        launch_conv_cols_ns<false>(D.ns, grid, st, T, D);
 }
 
 // ------------------------------------------------------------------ ChaCha20 samplers
