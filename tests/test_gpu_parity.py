@@ -179,6 +179,25 @@ def test_matmul_parity_small(small, h):
     assert np.abs(small.g.decrypt(gm, h * h).reshape(h, h) - A @ B).max() < 1e-3
 
 
+def test_modup_conversion_launch_forms(he):
+    """one digit per prime (8 digits): at the top level the 8 digits' 72 targets exceed one
+    merged ModUp conversion launch, so each digit converts in its own launch; after the first
+    rescales the digits fit one launch.  A product through both forms, single and as a batch of
+    two, equals the oracle on every residue"""
+    prm = I.small(log_n=12, n_q=8, alpha=1, q_bits=40, p_bits=50)
+    p = Pair(he, prm, h_list=[4])
+    A, B = I.matrix_pair(77, 4)
+    ga, gb = p.g.encrypt(A.ravel(), nonce=40), p.g.encrypt(B.ravel(), nonce=41)
+    oa, ob = p.o.encrypt(A.ravel(), nonce=40), p.o.encrypt(B.ravel(), nonce=41)
+    om = p.o.matmul(oa, ob, 4)
+    p.same(p.g.matmul(ga, gb, 4), om)
+    A2, B2 = I.matrix_pair(78, 4)
+    ga2, gb2 = p.g.encrypt(A2.ravel(), nonce=42), p.g.encrypt(B2.ravel(), nonce=43)
+    res = p.g.matmul_batch([ga, ga2], [gb, gb2], [4, 4])
+    p.same(res[0], om)
+    assert np.abs(p.g.decrypt(res[1], 16).reshape(4, 4) - A2 @ B2).max() < 1e-3
+
+
 def test_matmul_relin_once_parity(he):
     prm = I.small(log_n=12, n_q=6, alpha=2, q_bits=40, p_bits=50)
     p = Pair(he, prm, h_list=[8], schedule=1)
