@@ -494,6 +494,11 @@ class Context:
     def stream_probe(self, pattern, a, b, c, reps):
         """he_stream_probe over 64-bit torch tensors on the GPU (a, c and, for pattern 2, b of
         equal word counts; pattern 0 writes 2^20 partial-sum words to c): mean ms per launch"""
+        for t in (a, b, c):
+            if t is not None and (t.element_size() != 8 or not t.is_contiguous()):
+                raise ValueError("stream_probe: contiguous tensors of 64-bit words")
+        if b is not None and b.numel() != a.numel():
+            raise ValueError("stream_probe: a and b of different sizes")
         ms = C.c_double()
         bp = C.c_void_p(b.data_ptr()) if b is not None else None
         _chk(lib().he_stream_probe(self.ptr, int(pattern), C.c_void_p(a.data_ptr()), bp, C.c_void_p(c.data_ptr()),
