@@ -499,6 +499,9 @@ class Context:
                 raise ValueError("stream_probe: contiguous tensors of 64-bit words")
         if b is not None and b.numel() != a.numel():
             raise ValueError("stream_probe: a and b of different sizes")
+        need = 2 * ((a.numel() + 4095) // 4096) if pattern == 0 else a.numel()
+        if c.numel() < need:
+            raise ValueError(f"stream_probe: c holds {c.numel()} words, the pattern writes {need}")
         ms = C.c_double()
         bp = C.c_void_p(b.data_ptr()) if b is not None else None
         _chk(lib().he_stream_probe(self.ptr, int(pattern), C.c_void_p(a.data_ptr()), bp, C.c_void_p(c.data_ptr()),
